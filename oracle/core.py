@@ -1,0 +1,212 @@
+"""ctypes front-end of the C oracle (test infrastructure only).
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark use
+this module.  It compiles ``oracle.c`` with gcc on demand (``build()``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "liboracle.so")
+SRC = os.path.join(HERE, "oracle.c")
+
+OR_CELL = 1
+OR_FACE = 2
+OR_ALL = 3
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle into ``oracle/liboracle.so`` (gcc, OpenMP, FP64)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+               "-D_GNU_SOURCE", "-ffp-contract=off", SRC, "-o", LIB + ".tmp", "-lm"]
+        subprocess.check_call(cmd, cwd=HERE)
+        os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+class _Prob(C.Structure):
+    _fields_ = [("k", C.c_int), ("g", C.c_int), ("n_cells", C.c_long),
+                ("nodes", C.c_void_p), ("nbr", C.c_void_p),
+                ("alpha", C.c_void_p), ("beta", C.c_void_p), ("P", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(LIB)
+        dp = C.POINTER(C.c_double)
+        pp = C.POINTER(_Prob)
+        L.or_gauss_legendre.argtypes = [C.c_int, dp, dp]
+        L.or_gauss_lobatto.argtypes = [C.c_int, dp, dp]
+        L.or_lagrange.argtypes = [C.c_int, dp, C.c_double, dp, dp]
+        L.or_mesh_check.argtypes = [pp]
+        L.or_mesh_check.restype = C.c_int
+        for name in ("or_dof_coords", "or_cell_volumes", "or_face_sigma"):
+            getattr(L, name).argtypes = [pp, dp]
+        L.or_quad_data.argtypes = [pp, dp, dp]
+        L.or_load_vector.argtypes = [pp, dp, dp]
+        L.or_apply.argtypes = [pp, C.c_int, dp, dp]
+        L.or_assemble_dense.argtypes = [pp, C.c_int, dp]
+        L.or_bj_cell_data.argtypes = [pp, C.c_long, dp, dp, dp, dp]
+        L.or_bj_sep_block.argtypes = [pp, C.c_long, dp]
+        L.or_bj_sep_apply.argtypes = [pp, dp, dp]
+        L.or_bj_sep_apply.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+# ---------------------------------------------------------------------------
+# 1-D rules
+# ---------------------------------------------------------------------------
+
+def gauss_legendre(n: int):
+    x = np.zeros(n); w = np.zeros(n)
+    lib().or_gauss_legendre(n, _dp(x), _dp(w))
+    return x, w
+
+
+def gauss_lobatto(n: int):
+    x = np.zeros(n); w = np.zeros(n)
+    lib().or_gauss_lobatto(n, _dp(x), _dp(w))
+    return x, w
+
+
+def lagrange(nodes: np.ndarray, t: float):
+    nodes = np.ascontiguousarray(nodes, dtype=np.float64)
+    n = nodes.size
+    v = np.zeros(n); d = np.zeros(n)
+    lib().or_lagrange(n, _dp(nodes), float(t), _dp(v), _dp(d))
+    return v, d
+
+
+# ---------------------------------------------------------------------------
+# problem
+# ---------------------------------------------------------------------------
+
+class Problem:
+    """A mesh, a degree and (optionally) coefficient fields, as the oracle sees
+    them.  Arrays are kept alive here; ``alpha``/``beta`` are DG nodal fields
+    ``[n_cells*(k+1)^3]``."""
+
+    def __init__(self, mesh, k: int, alpha=None, beta=None, P: float = 2.0):
+        self.mesh = mesh
+        self.k = int(k)
+        self.g = int(mesh.g)
+        self.n = self.k + 1
+        self.nd = self.n ** 3
+        self.n_cells = mesh.n_cells
+        self.n_dofs = self.n_cells * self.nd
+        self.nodes = np.ascontiguousarray(mesh.nodes, dtype=np.float64)
+        self.nbr = np.ascontiguousarray(mesh.nbr, dtype=np.int64)
+        self.P = float(P)
+        self.alpha = None
+        self.beta = None
+        if alpha is not None:
+            self.set_coefficients(alpha, beta)
+
+    def set_coefficients(self, alpha, beta):
+        self.alpha = np.ascontiguousarray(alpha, dtype=np.float64)
+        self.beta = np.ascontiguousarray(beta, dtype=np.float64)
+        assert self.alpha.shape == (self.n_dofs,) and self.beta.shape == (self.n_dofs,)
+
+    def set_coefficient_functions(self, fa, fb):
+        x, y, z = self.dof_coords()
+        self.set_coefficients(fa(x, y, z), fb(x, y, z))
+
+    def _s(self):
+        zero = None
+        s = _Prob(self.k, self.g, self.n_cells,
+                  self.nodes.ctypes.data, self.nbr.ctypes.data,
+                  self.alpha.ctypes.data if self.alpha is not None else zero,
+                  self.beta.ctypes.data if self.beta is not None else zero,
+                  self.P)
+        return C.byref(s)
+
+    # geometry ------------------------------------------------------------
+    def mesh_check(self) -> int:
+        return lib().or_mesh_check(self._s())
+
+    def dof_coords(self):
+        xyz = np.zeros(3 * self.n_dofs)
+        lib().or_dof_coords(self._s(), _dp(xyz))
+        return xyz.reshape(3, self.n_dofs)
+
+    def quad_data(self):
+        xyz = np.zeros(3 * self.n_dofs)
+        w = np.zeros(self.n_dofs)
+        lib().or_quad_data(self._s(), _dp(xyz), _dp(w))
+        return xyz.reshape(3, self.n_dofs), w
+
+    def load_vector(self, f):
+        """b_i = int f phi_i by the cell GL rule; f is a function of (x,y,z)."""
+        xyz, _ = self.quad_data()
+        fq = np.ascontiguousarray(f(xyz[0], xyz[1], xyz[2]), dtype=np.float64)
+        b = np.zeros(self.n_dofs)
+        lib().or_load_vector(self._s(), _dp(fq), _dp(b))
+        return b
+
+    def cell_volumes(self):
+        v = np.zeros(self.n_cells)
+        lib().or_cell_volumes(self._s(), _dp(v))
+        return v
+
+    def face_sigma(self):
+        s = np.zeros(3 * self.n_cells)
+        lib().or_face_sigma(self._s(), _dp(s))
+        return s.reshape(self.n_cells, 3)
+
+    # operator ------------------------------------------------------------
+    def apply(self, x, flags: int = OR_ALL):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.zeros(self.n_dofs)
+        lib().or_apply(self._s(), int(flags), _dp(x), _dp(y))
+        return y
+
+    def assemble_dense(self, flags: int = OR_ALL):
+        A = np.zeros((self.n_dofs, self.n_dofs))
+        lib().or_assemble_dense(self._s(), int(flags), _dp(A))
+        return A
+
+    def matrix_by_unit_vectors(self, flags: int = OR_ALL):
+        """Columns A e_j, one operator application per unit vector."""
+        A = np.zeros((self.n_dofs, self.n_dofs))
+        e = np.zeros(self.n_dofs)
+        for j in range(self.n_dofs):
+            e[j] = 1.0
+            A[:, j] = self.apply(e, flags)
+            e[j] = 0.0
+        return A
+
+    # block Jacobi ----------------------------------------------------------
+    def bj_cell_data(self, c: int):
+        ell = np.zeros(3); ab = np.zeros(1); bb = np.zeros(1); sig = np.zeros(6)
+        lib().or_bj_cell_data(self._s(), int(c), _dp(ell), _dp(ab), _dp(bb), _dp(sig))
+        return ell, float(ab[0]), float(bb[0]), sig.reshape(3, 2)
+
+    def bj_sep_block(self, c: int):
+        A = np.zeros(self.nd * self.nd)
+        lib().or_bj_sep_block(self._s(), int(c), _dp(A))
+        return A.reshape(self.nd, self.nd)
+
+    def bj_apply(self, r):
+        r = np.ascontiguousarray(r, dtype=np.float64)
+        z = np.zeros(self.n_dofs)
+        bad = lib().or_bj_sep_apply(self._s(), _dp(r), _dp(z))
+        if bad:
+            raise FloatingPointError("separable block not positive definite")
+        return z

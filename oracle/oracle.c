@@ -1,0 +1,790 @@
+/*
+ * Reference ("oracle") implementation of the DG Helmholtz-type pressure
+ * operator -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow, FP64 C.  It evaluates the quadrature-defined bilinear form
+ * directly: at every quadrature point it evaluates all basis functions by the
+ * Lagrange product formula, with no sum factorisation, blocking or fusion.
+ * Only the test-suite, the smoke check and the CPU-baseline leg of the
+ * benchmark may load it; the product path never does.  It shares no code with
+ * the HIP library.
+ *
+ * What is computed (paper section 2, the Helmholtz equation for the pressure,
+ * linearised with frozen coefficients, and section 3.1, the matrix S~ whose
+ * volume terms are a mass term plus a dt-scaled enthalpy-weighted stiffness):
+ *
+ *   a(u,v) = sum_K sum_q w_q detJ_q [alpha_q u v + beta_q grad u . grad v]
+ *          + sum_F sum_q ds_q [ -1/2 (b- dn u- + b+ dn u+) [v]
+ *                               -1/2 (b- dn v- + b+ dn v+) [u]
+ *                               + sigma_F 1/2 (b- + b+) [u][v] ]
+ *
+ * on conforming hexahedral meshes mapped by a tensor-product Lagrange map of
+ * degree g through equispaced reference nodes;  the DG space is the
+ * tensor-product Lagrange basis on (k+1) Gauss-Lobatto points (section 2);
+ * quadrature is (k+1)-point Gauss-Legendre per direction, the rule of the
+ * fast block-diagonal evaluation (section 3.3);  [w] = w- - w+, n is the unit
+ * normal of the minus cell (the cell whose +d face it is), ds and n are taken
+ * from the minus side for both sides, the plus-side point has the same
+ * tangential reference coordinates;
+ *   sigma_F = P (k+1)^2 max(|F|/|K-|, |F|/|K+|);
+ * boundary faces (neighbour -1) contribute nothing (natural Neumann).
+ *
+ * The separable cell-block preconditioner Ahat_K (the tensor-product
+ * structure used for the fast inverse of block-diagonal operators, section
+ * 3.3) is built here by explicit Kronecker sums and solved densely.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "oracle.h"
+
+#define MAXN 10          /* max (k+1) and (g+1) */
+
+/* ------------------------------------------------------------------------ */
+/* 1-D rules on [0,1]                                                        */
+/* ------------------------------------------------------------------------ */
+
+/* Legendre P_n(x) and its derivative on [-1,1] by the three-term recurrence. */
+static void legendre(int n, double x, double *p, double *dp)
+{
+    double p0 = 1.0, p1 = x;
+    if (n == 0) { *p = 1.0; *dp = 0.0; return; }
+    for (int m = 2; m <= n; ++m) {
+        double p2 = ((2.0 * m - 1.0) * x * p1 - (m - 1.0) * p0) / m;
+        p0 = p1; p1 = p2;
+    }
+    *p = p1;
+    /* (x^2 - 1) P_n' = n (x P_n - P_{n-1}) */
+    if (fabs(x) < 1.0)
+        *dp = n * (x * p1 - p0) / (x * x - 1.0);
+    else
+        *dp = 0.5 * n * (n + 1.0) * (x > 0 ? 1.0 : ((n % 2) ? 1.0 : -1.0));
+}
+
+/* n-point Gauss-Legendre: roots of P_n by Newton from Chebyshev guesses. */
+void or_gauss_legendre(int n, double *x, double *w)
+{
+    for (int i = 0; i < n; ++i) {
+        double t = -cos(M_PI * (i + 0.75) / (n + 0.5));
+        for (int it = 0; it < 100; ++it) {
+            double p, dp;
+            legendre(n, t, &p, &dp);
+            double dt = p / dp;
+            t -= dt;
+            if (fabs(dt) < 1e-16) break;
+        }
+        double p, dp;
+        legendre(n, t, &p, &dp);
+        x[i] = 0.5 * (t + 1.0);
+        w[i] = 0.5 * 2.0 / ((1.0 - t * t) * dp * dp);
+    }
+}
+
+/* n-point Gauss-Lobatto: the endpoints and the roots of P'_{n-1}.
+ * Newton on q(x) = P'_{n-1}(x) using q' = (2x q - m(m+1) P_m)/(1-x^2), m = n-1. */
+void or_gauss_lobatto(int n, double *x, double *w)
+{
+    int m = n - 1;
+    x[0] = 0.0; x[n - 1] = 1.0;
+    w[0] = w[n - 1] = 0.5 * 2.0 / (n * (n - 1.0));
+    for (int i = 1; i < n - 1; ++i) {
+        double t = -cos(M_PI * i / m);
+        for (int it = 0; it < 100; ++it) {
+            double p, dp;
+            legendre(m, t, &p, &dp);
+            double ddp = (2.0 * t * dp - m * (m + 1.0) * p) / (1.0 - t * t);
+            double dt = dp / ddp;
+            t -= dt;
+            if (fabs(dt) < 1e-16) break;
+        }
+        double p, dp;
+        legendre(m, t, &p, &dp);
+        x[i] = 0.5 * (t + 1.0);
+        w[i] = 0.5 * 2.0 / (n * (n - 1.0) * p * p);
+    }
+}
+
+/* Lagrange basis through nodes[0..n-1]: values and derivatives at t,
+ * straight from the product formula. */
+void or_lagrange(int n, const double *nodes, double t, double *val, double *der)
+{
+    for (int i = 0; i < n; ++i) {
+        double v = 1.0;
+        for (int m = 0; m < n; ++m)
+            if (m != i) v *= (t - nodes[m]) / (nodes[i] - nodes[m]);
+        val[i] = v;
+        double d = 0.0;
+        for (int m = 0; m < n; ++m) {
+            if (m == i) continue;
+            double prod = 1.0 / (nodes[i] - nodes[m]);
+            for (int l = 0; l < n; ++l)
+                if (l != i && l != m) prod *= (t - nodes[l]) / (nodes[i] - nodes[l]);
+            d += prod;
+        }
+        der[i] = d;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* reference data                                                            */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int n, nd;               /* k+1, (k+1)^3 */
+    int ng, ngn;             /* g+1, (g+1)^3 */
+    double xq[MAXN], wq[MAXN];   /* GL on [0,1] */
+    double xl[MAXN], wl[MAXN];   /* GLL on [0,1] (dof nodes) */
+    double xe[MAXN];             /* equispaced geometry nodes */
+} ref_t;
+
+static void ref_init(ref_t *r, int k, int g)
+{
+    r->n = k + 1; r->nd = r->n * r->n * r->n;
+    r->ng = g + 1; r->ngn = r->ng * r->ng * r->ng;
+    or_gauss_legendre(r->n, r->xq, r->wq);
+    or_gauss_lobatto(r->n, r->xl, r->wl);
+    for (int a = 0; a <= g; ++a) r->xe[a] = (double)a / g;
+}
+
+/* all nd basis functions and reference gradients at reference point xi */
+static void basis_at(const ref_t *r, const double xi[3], double *phi, double (*dphi)[3])
+{
+    double v[3][MAXN], d[3][MAXN];
+    for (int c = 0; c < 3; ++c) or_lagrange(r->n, r->xl, xi[c], v[c], d[c]);
+    int n = r->n;
+    for (int l = 0; l < n; ++l)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                int a = i + n * (j + n * l);
+                phi[a] = v[0][i] * v[1][j] * v[2][l];
+                dphi[a][0] = d[0][i] * v[1][j] * v[2][l];
+                dphi[a][1] = v[0][i] * d[1][j] * v[2][l];
+                dphi[a][2] = v[0][i] * v[1][j] * d[2][l];
+            }
+}
+
+/* physical position and Jacobian J[r][d] = d x_r / d xi_d of one cell */
+static void geom_at(const ref_t *r, const double *X, const double xi[3],
+                    double x[3], double J[3][3])
+{
+    double v[3][MAXN], d[3][MAXN];
+    for (int c = 0; c < 3; ++c) or_lagrange(r->ng, r->xe, xi[c], v[c], d[c]);
+    int ng = r->ng;
+    for (int a = 0; a < 3; ++a) { x[a] = 0.0; J[a][0] = J[a][1] = J[a][2] = 0.0; }
+    for (int c = 0; c < ng; ++c)
+        for (int b = 0; b < ng; ++b)
+            for (int a = 0; a < ng; ++a) {
+                const double *P = X + 3 * (a + ng * (b + ng * c));
+                double s = v[0][a] * v[1][b] * v[2][c];
+                double s0 = d[0][a] * v[1][b] * v[2][c];
+                double s1 = v[0][a] * d[1][b] * v[2][c];
+                double s2 = v[0][a] * v[1][b] * d[2][c];
+                for (int q = 0; q < 3; ++q) {
+                    x[q] += s * P[q];
+                    J[q][0] += s0 * P[q];
+                    J[q][1] += s1 * P[q];
+                    J[q][2] += s2 * P[q];
+                }
+            }
+}
+
+static double det3(double J[3][3])
+{
+    return J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1])
+         - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0])
+         + J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+}
+
+/* inverse transpose K = J^{-T} (so that grad = K * grad_ref) */
+static void inv_transpose(double J[3][3], double det, double K[3][3])
+{
+    double C[3][3];   /* cofactor matrix */
+    C[0][0] =  (J[1][1] * J[2][2] - J[1][2] * J[2][1]);
+    C[0][1] = -(J[1][0] * J[2][2] - J[1][2] * J[2][0]);
+    C[0][2] =  (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    C[1][0] = -(J[0][1] * J[2][2] - J[0][2] * J[2][1]);
+    C[1][1] =  (J[0][0] * J[2][2] - J[0][2] * J[2][0]);
+    C[1][2] = -(J[0][0] * J[2][1] - J[0][1] * J[2][0]);
+    C[2][0] =  (J[0][1] * J[1][2] - J[0][2] * J[1][1]);
+    C[2][1] = -(J[0][0] * J[1][2] - J[0][2] * J[1][0]);
+    C[2][2] =  (J[0][0] * J[1][1] - J[0][1] * J[1][0]);
+    /* J^{-1} = C^T / det  =>  J^{-T} = C / det */
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) K[a][b] = C[a][b] / det;
+}
+
+static void matvec3(double K[3][3], const double v[3], double out[3])
+{
+    for (int a = 0; a < 3; ++a) out[a] = K[a][0] * v[0] + K[a][1] * v[1] + K[a][2] * v[2];
+}
+
+static const double *cell_nodes(const or_prob *p, const ref_t *r, long c)
+{
+    return p->nodes + (size_t)c * r->ngn * 3;
+}
+
+/* cell volume |K| = sum_q w_q detJ_q */
+static double cell_volume(const or_prob *p, const ref_t *r, long c)
+{
+    int n = r->n;
+    double vol = 0.0;
+    for (int l = 0; l < n; ++l)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                double xi[3] = {r->xq[i], r->xq[j], r->xq[l]}, x[3], J[3][3];
+                geom_at(r, cell_nodes(p, r, c), xi, x, J);
+                vol += r->wq[i] * r->wq[j] * r->wq[l] * det3(J);
+            }
+    return vol;
+}
+
+/* reference point on the (+d or -d) face of a cell, tangential GL (a,b) */
+static void face_point(const ref_t *r, int d, int plus, int a, int b, double xi[3])
+{
+    int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+    xi[d] = plus ? 1.0 : 0.0;
+    xi[t1] = r->xq[a];
+    xi[t2] = r->xq[b];
+}
+
+/* minus-side normal and surface element at one face point of the +d face */
+static void face_normal(const ref_t *r, const double *Xm, int d, int a, int b,
+                        double nrm[3], double *ds)
+{
+    double xi[3], x[3], J[3][3], K[3][3];
+    face_point(r, d, 1, a, b, xi);
+    geom_at(r, Xm, xi, x, J);
+    double det = det3(J);
+    inv_transpose(J, det, K);
+    double e[3] = {0, 0, 0}, m[3];
+    e[d] = 1.0;
+    matvec3(K, e, m);
+    double len = sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
+    for (int q = 0; q < 3; ++q) nrm[q] = m[q] / len;
+    *ds = r->wq[a] * r->wq[b] * det * len;
+}
+
+/* |F| of the +d face of cell c (minus side) */
+static double face_area(const or_prob *p, const ref_t *r, long c, int d)
+{
+    double area = 0.0, nrm[3], ds;
+    for (int b = 0; b < r->n; ++b)
+        for (int a = 0; a < r->n; ++a) {
+            face_normal(r, cell_nodes(p, r, c), d, a, b, nrm, &ds);
+            area += ds;
+        }
+    return area;
+}
+
+/* penalty of the +d face of cell c (c is the minus cell), -1 if boundary */
+static double face_sigma(const or_prob *p, const ref_t *r, long c, int d)
+{
+    long nb = p->nbr[6 * c + 2 * d + 1];
+    if (nb < 0) return -1.0;
+    double area = face_area(p, r, c, d);
+    double vm = cell_volume(p, r, c), vp = cell_volume(p, r, nb);
+    double s = area / vm > area / vp ? area / vm : area / vp;
+    return p->P * (double)(r->n * r->n) * s;
+}
+
+void or_face_sigma(const or_prob *p, double *sigma)
+{
+    ref_t r; ref_init(&r, p->k, p->g);
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < p->n_cells; ++c)
+        for (int d = 0; d < 3; ++d) sigma[3 * c + d] = face_sigma(p, &r, c, d);
+}
+
+void or_cell_volumes(const or_prob *p, double *vol)
+{
+    ref_t r; ref_init(&r, p->k, p->g);
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < p->n_cells; ++c) vol[c] = cell_volume(p, &r, c);
+}
+
+/* ------------------------------------------------------------------------ */
+/* mesh check                                                                */
+/* ------------------------------------------------------------------------ */
+
+int or_mesh_check(const or_prob *p)
+{
+    ref_t r; ref_init(&r, p->k, p->g);
+    int bad = 0;
+    for (long c = 0; c < p->n_cells; ++c) {
+        for (int f = 0; f < 6; ++f) {
+            long nb = p->nbr[6 * c + f];
+            if (nb < -1 || nb >= p->n_cells) return 2;
+            if (nb >= 0 && p->nbr[6 * nb + (f ^ 1)] != c) return 2;
+        }
+    }
+#pragma omp parallel for schedule(static) reduction(|:bad)
+    for (long c = 0; c < p->n_cells; ++c) {
+        int n = r.n;
+        for (int l = 0; l < n; ++l)
+            for (int j = 0; j < n; ++j)
+                for (int i = 0; i < n; ++i) {
+                    double xi[3] = {r.xq[i], r.xq[j], r.xq[l]}, x[3], J[3][3];
+                    geom_at(&r, cell_nodes(p, &r, c), xi, x, J);
+                    if (!(det3(J) > 0.0)) bad |= 1;
+                }
+    }
+    return bad;
+}
+
+/* ------------------------------------------------------------------------ */
+/* coordinates and load vectors                                              */
+/* ------------------------------------------------------------------------ */
+
+void or_dof_coords(const or_prob *p, double *xyz)
+{
+    ref_t r; ref_init(&r, p->k, p->g);
+    long ndofs = p->n_cells * r.nd;
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < p->n_cells; ++c) {
+        int n = r.n;
+        for (int l = 0; l < n; ++l)
+            for (int j = 0; j < n; ++j)
+                for (int i = 0; i < n; ++i) {
+                    double xi[3] = {r.xl[i], r.xl[j], r.xl[l]}, x[3], J[3][3];
+                    geom_at(&r, cell_nodes(p, &r, c), xi, x, J);
+                    long dof = c * r.nd + i + n * (j + n * l);
+                    for (int q = 0; q < 3; ++q) xyz[q * ndofs + dof] = x[q];
+                }
+    }
+}
+
+void or_quad_data(const or_prob *p, double *xyz, double *wdet)
+{
+    ref_t r; ref_init(&r, p->k, p->g);
+    long nq = p->n_cells * r.nd;
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < p->n_cells; ++c) {
+        int n = r.n;
+        for (int l = 0; l < n; ++l)
+            for (int j = 0; j < n; ++j)
+                for (int i = 0; i < n; ++i) {
+                    double xi[3] = {r.xq[i], r.xq[j], r.xq[l]}, x[3], J[3][3];
+                    geom_at(&r, cell_nodes(p, &r, c), xi, x, J);
+                    long q = c * r.nd + i + n * (j + n * l);
+                    for (int a = 0; a < 3; ++a) xyz[a * nq + q] = x[a];
+                    wdet[q] = r.wq[i] * r.wq[j] * r.wq[l] * det3(J);
+                }
+    }
+}
+
+/* b_i = sum_q w_q detJ_q f(x_q) phi_i(x_q), with f given at the GL points */
+void or_load_vector(const or_prob *p, const double *fq, double *b)
+{
+    ref_t r; ref_init(&r, p->k, p->g);
+#pragma omp parallel
+    {
+        double *phi = malloc(sizeof(double) * r.nd);
+        double (*dphi)[3] = malloc(sizeof(double) * 3 * r.nd);
+#pragma omp for schedule(static)
+        for (long c = 0; c < p->n_cells; ++c) {
+            int n = r.n;
+            double *bc = b + c * r.nd;
+            for (int a = 0; a < r.nd; ++a) bc[a] = 0.0;
+            for (int l = 0; l < n; ++l)
+                for (int j = 0; j < n; ++j)
+                    for (int i = 0; i < n; ++i) {
+                        double xi[3] = {r.xq[i], r.xq[j], r.xq[l]}, x[3], J[3][3];
+                        geom_at(&r, cell_nodes(p, &r, c), xi, x, J);
+                        double wd = r.wq[i] * r.wq[j] * r.wq[l] * det3(J);
+                        basis_at(&r, xi, phi, dphi);
+                        double fv = fq[c * r.nd + i + n * (j + n * l)];
+                        for (int a = 0; a < r.nd; ++a) bc[a] += wd * fv * phi[a];
+                    }
+        }
+        free(phi); free(dphi);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* operator action                                                           */
+/* ------------------------------------------------------------------------ */
+
+/* value of a DG field (nodal coefficients f of cell c) at reference point */
+static double field_at(const double *phi, const double *fc, int nd)
+{
+    double s = 0.0;
+    for (int a = 0; a < nd; ++a) s += phi[a] * fc[a];
+    return s;
+}
+
+typedef struct {
+    double *phi;            /* [nd] */
+    double (*dphi)[3];      /* [nd][3] */
+} scratch_t;
+
+/* y = A x: each cell accumulates a(x, phi_i) for its own test functions. */
+void or_apply(const or_prob *p, int flags, const double *xv, double *yv)
+{
+    ref_t r; ref_init(&r, p->k, p->g);
+    const int nd = r.nd, n = r.n;
+#pragma omp parallel
+    {
+        double *phi = malloc(sizeof(double) * nd), *phiB = malloc(sizeof(double) * nd);
+        double (*dphi)[3] = malloc(sizeof(double) * 3 * nd);
+        double (*dphiB)[3] = malloc(sizeof(double) * 3 * nd);
+#pragma omp for schedule(dynamic, 4)
+        for (long c = 0; c < p->n_cells; ++c) {
+            double *yc = yv + c * nd;
+            const double *xc = xv + c * nd;
+            for (int a = 0; a < nd; ++a) yc[a] = 0.0;
+            const double *X = cell_nodes(p, &r, c);
+            /* ---- cell integral ---- */
+            if (flags & OR_CELL) {
+                for (int l = 0; l < n; ++l)
+                    for (int j = 0; j < n; ++j)
+                        for (int i = 0; i < n; ++i) {
+                            double xi[3] = {r.xq[i], r.xq[j], r.xq[l]}, x[3], J[3][3], K[3][3];
+                            geom_at(&r, X, xi, x, J);
+                            double det = det3(J);
+                            inv_transpose(J, det, K);
+                            double w = r.wq[i] * r.wq[j] * r.wq[l] * det;
+                            basis_at(&r, xi, phi, dphi);
+                            double al = field_at(phi, p->alpha + c * nd, nd);
+                            double be = field_at(phi, p->beta + c * nd, nd);
+                            double u = 0.0, gr[3] = {0, 0, 0};
+                            for (int a = 0; a < nd; ++a) {
+                                u += phi[a] * xc[a];
+                                for (int q = 0; q < 3; ++q) gr[q] += dphi[a][q] * xc[a];
+                            }
+                            double gu[3];
+                            matvec3(K, gr, gu);
+                            for (int a = 0; a < nd; ++a) {
+                                double gv[3];
+                                matvec3(K, dphi[a], gv);
+                                yc[a] += w * (al * u * phi[a]
+                                              + be * (gu[0] * gv[0] + gu[1] * gv[1] + gu[2] * gv[2]));
+                            }
+                        }
+            }
+            /* ---- face integrals, test functions of cell c only ---- */
+            if (flags & OR_FACE) {
+                for (int d = 0; d < 3; ++d)
+                    for (int side = 0; side < 2; ++side) {
+                        /* side 1: the +d face of c (c is the minus cell);
+                           side 0: the -d face of c (c is the plus cell) */
+                        long nb = p->nbr[6 * c + 2 * d + side];
+                        if (nb < 0) continue;
+                        long km = side ? c : nb, kp = side ? nb : c;
+                        double sigma = face_sigma(p, &r, km, d);
+                        const double *Xm = cell_nodes(p, &r, km), *Xp = cell_nodes(p, &r, kp);
+                        const double *xm = xv + km * nd, *xp = xv + kp * nd;
+                        for (int b = 0; b < n; ++b)
+                            for (int a = 0; a < n; ++a) {
+                                double nrm[3], ds;
+                                face_normal(&r, Xm, d, a, b, nrm, &ds);
+                                double xim[3], xip[3], pos[3], Jm[3][3], Jp[3][3], Km[3][3], Kp[3][3];
+                                face_point(&r, d, 1, a, b, xim);
+                                face_point(&r, d, 0, a, b, xip);
+                                geom_at(&r, Xm, xim, pos, Jm);
+                                geom_at(&r, Xp, xip, pos, Jp);
+                                inv_transpose(Jm, det3(Jm), Km);
+                                inv_transpose(Jp, det3(Jp), Kp);
+                                /* minus side */
+                                basis_at(&r, xim, phi, dphi);
+                                /* plus side */
+                                basis_at(&r, xip, phiB, dphiB);
+                                double bm = field_at(phi, p->beta + km * nd, nd);
+                                double bp = field_at(phiB, p->beta + kp * nd, nd);
+                                double um = 0, up = 0, gm[3] = {0, 0, 0}, gp[3] = {0, 0, 0};
+                                for (int e = 0; e < nd; ++e) {
+                                    um += phi[e] * xm[e];
+                                    up += phiB[e] * xp[e];
+                                    for (int q = 0; q < 3; ++q) {
+                                        gm[q] += dphi[e][q] * xm[e];
+                                        gp[q] += dphiB[e][q] * xp[e];
+                                    }
+                                }
+                                double Gm[3], Gp[3];
+                                matvec3(Km, gm, Gm);
+                                matvec3(Kp, gp, Gp);
+                                double dnm = nrm[0] * Gm[0] + nrm[1] * Gm[1] + nrm[2] * Gm[2];
+                                double dnp = nrm[0] * Gp[0] + nrm[1] * Gp[1] + nrm[2] * Gp[2];
+                                double flux = bm * dnm + bp * dnp;
+                                double jump = um - up;
+                                double pen = sigma * 0.5 * (bm + bp);
+                                /* own test functions */
+                                const double *tphi = side ? phi : phiB;
+                                double (*tdphi)[3] = side ? dphi : dphiB;
+                                double (*Kown)[3] = side ? Km : Kp;
+                                double bown = side ? bm : bp;
+                                double sgn = side ? 1.0 : -1.0;
+                                for (int e = 0; e < nd; ++e) {
+                                    double gv[3];
+                                    matvec3(Kown, tdphi[e], gv);
+                                    double dnv = nrm[0] * gv[0] + nrm[1] * gv[1] + nrm[2] * gv[2];
+                                    double jv = sgn * tphi[e];
+                                    yc[e] += ds * (-0.5 * flux * jv - 0.5 * bown * dnv * jump
+                                                   + pen * jump * jv);
+                                }
+                            }
+                    }
+            }
+        }
+        free(phi); free(phiB); free(dphi); free(dphiB);
+    }
+}
+
+
+/* values of a DG field at the cell GL points, uq[c*nd + q] */
+void or_eval_quad(const or_prob *p, const double *u, double *uq)
+{
+    ref_t r; ref_init(&r, p->k, p->g);
+#pragma omp parallel
+    {
+        double *phi = malloc(sizeof(double) * r.nd);
+        double (*dphi)[3] = malloc(sizeof(double) * 3 * r.nd);
+#pragma omp for schedule(static)
+        for (long c = 0; c < p->n_cells; ++c) {
+            int n = r.n;
+            for (int l = 0; l < n; ++l)
+                for (int j = 0; j < n; ++j)
+                    for (int i = 0; i < n; ++i) {
+                        double xi[3] = {r.xq[i], r.xq[j], r.xq[l]};
+                        basis_at(&r, xi, phi, dphi);
+                        uq[c * r.nd + i + n * (j + n * l)] = field_at(phi, u + c * r.nd, r.nd);
+                    }
+        }
+        free(phi); free(dphi);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* dense assembly (a second, independent route: explicit matrix entries)    */
+/* ------------------------------------------------------------------------ */
+
+void or_assemble_dense(const or_prob *p, int flags, double *A)
+{
+    ref_t r; ref_init(&r, p->k, p->g);
+    const int nd = r.nd, n = r.n;
+    const long N = p->n_cells * nd;
+    memset(A, 0, sizeof(double) * (size_t)N * N);
+    double *phi = malloc(sizeof(double) * nd), *phi2 = malloc(sizeof(double) * nd);
+    double (*dphi)[3] = malloc(sizeof(double) * 3 * nd);
+    double (*dphi2)[3] = malloc(sizeof(double) * 3 * nd);
+    double (*gphys)[3] = malloc(sizeof(double) * 3 * nd);
+    double (*gphys2)[3] = malloc(sizeof(double) * 3 * nd);
+    /* element matrices */
+    if (flags & OR_CELL) {
+        for (long c = 0; c < p->n_cells; ++c) {
+            const double *X = cell_nodes(p, &r, c);
+            for (int l = 0; l < n; ++l)
+                for (int j = 0; j < n; ++j)
+                    for (int i = 0; i < n; ++i) {
+                        double xi[3] = {r.xq[i], r.xq[j], r.xq[l]}, x[3], J[3][3], K[3][3];
+                        geom_at(&r, X, xi, x, J);
+                        double det = det3(J);
+                        inv_transpose(J, det, K);
+                        double w = r.wq[i] * r.wq[j] * r.wq[l] * det;
+                        basis_at(&r, xi, phi, dphi);
+                        double al = 0, be = 0;
+                        for (int a = 0; a < nd; ++a) {
+                            al += phi[a] * p->alpha[c * nd + a];
+                            be += phi[a] * p->beta[c * nd + a];
+                            matvec3(K, dphi[a], gphys[a]);
+                        }
+                        for (int ti = 0; ti < nd; ++ti)
+                            for (int tj = 0; tj < nd; ++tj) {
+                                double s = al * phi[ti] * phi[tj]
+                                    + be * (gphys[ti][0] * gphys[tj][0] + gphys[ti][1] * gphys[tj][1]
+                                            + gphys[ti][2] * gphys[tj][2]);
+                                A[(size_t)(c * nd + ti) * N + c * nd + tj] += w * s;
+                            }
+                    }
+        }
+    }
+    /* interior faces, each once, all four blocks */
+    if (flags & OR_FACE) {
+        for (long km = 0; km < p->n_cells; ++km)
+            for (int d = 0; d < 3; ++d) {
+                long kp = p->nbr[6 * km + 2 * d + 1];
+                if (kp < 0) continue;
+                double sigma = face_sigma(p, &r, km, d);
+                for (int b = 0; b < n; ++b)
+                    for (int a = 0; a < n; ++a) {
+                        double nrm[3], ds, xim[3], xip[3], pos[3], Jm[3][3], Jp[3][3], Km[3][3], Kp[3][3];
+                        face_normal(&r, cell_nodes(p, &r, km), d, a, b, nrm, &ds);
+                        face_point(&r, d, 1, a, b, xim);
+                        face_point(&r, d, 0, a, b, xip);
+                        geom_at(&r, cell_nodes(p, &r, km), xim, pos, Jm);
+                        geom_at(&r, cell_nodes(p, &r, kp), xip, pos, Jp);
+                        inv_transpose(Jm, det3(Jm), Km);
+                        inv_transpose(Jp, det3(Jp), Kp);
+                        basis_at(&r, xim, phi, dphi);
+                        basis_at(&r, xip, phi2, dphi2);
+                        double bm = 0, bp = 0;
+                        for (int e = 0; e < nd; ++e) {
+                            bm += phi[e] * p->beta[km * nd + e];
+                            bp += phi2[e] * p->beta[kp * nd + e];
+                            matvec3(Km, dphi[e], gphys[e]);
+                            matvec3(Kp, dphi2[e], gphys2[e]);
+                        }
+                        double pen = sigma * 0.5 * (bm + bp);
+                        /* side s in {0: minus, 1: plus}: value, normal derivative, beta, sign */
+                        for (int st = 0; st < 2; ++st)        /* test side */
+                            for (int su = 0; su < 2; ++su) {  /* trial side */
+                                long ct = st ? kp : km, cu = su ? kp : km;
+                                const double *vt = st ? phi2 : phi, *vu = su ? phi2 : phi;
+                                double (*gt)[3] = st ? gphys2 : gphys;
+                                double (*gu)[3] = su ? gphys2 : gphys;
+                                double bt = st ? bp : bm, bu = su ? bp : bm;
+                                double zt = st ? -1.0 : 1.0, zu = su ? -1.0 : 1.0;
+                                for (int ti = 0; ti < nd; ++ti) {
+                                    double dnt = nrm[0] * gt[ti][0] + nrm[1] * gt[ti][1] + nrm[2] * gt[ti][2];
+                                    for (int tj = 0; tj < nd; ++tj) {
+                                        double dnu = nrm[0] * gu[tj][0] + nrm[1] * gu[tj][1] + nrm[2] * gu[tj][2];
+                                        double s = -0.5 * bu * dnu * zt * vt[ti]
+                                                   - 0.5 * bt * dnt * zu * vu[tj]
+                                                   + pen * zu * vu[tj] * zt * vt[ti];
+                                        A[(size_t)(ct * nd + ti) * N + cu * nd + tj] += ds * s;
+                                    }
+                                }
+                            }
+                    }
+            }
+    }
+    free(phi); free(phi2); free(dphi); free(dphi2); free(gphys); free(gphys2);
+}
+
+/* ------------------------------------------------------------------------ */
+/* separable cell-block preconditioner                                      */
+/* ------------------------------------------------------------------------ */
+
+/* per-cell data of the separable block: lengths l_d (mean over GL points of
+ * the column norms |J e_d|), volume-weighted means of alpha and beta, and the
+ * penalties at the two ends of each direction (-1 where the end is a
+ * boundary). */
+void or_bj_cell_data(const or_prob *p, long c, double ell[3], double *abar,
+                     double *bbar, double sig[3][2])
+{
+    ref_t r; ref_init(&r, p->k, p->g);
+    int n = r.n, nd = r.nd;
+    double *phi = malloc(sizeof(double) * nd);
+    double (*dphi)[3] = malloc(sizeof(double) * 3 * nd);
+    double vol = 0, sa = 0, sb = 0;
+    ell[0] = ell[1] = ell[2] = 0.0;
+    for (int l = 0; l < n; ++l)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                double xi[3] = {r.xq[i], r.xq[j], r.xq[l]}, x[3], J[3][3];
+                geom_at(&r, cell_nodes(p, &r, c), xi, x, J);
+                double w = r.wq[i] * r.wq[j] * r.wq[l] * det3(J);
+                basis_at(&r, xi, phi, dphi);
+                vol += w;
+                sa += w * field_at(phi, p->alpha + c * nd, nd);
+                sb += w * field_at(phi, p->beta + c * nd, nd);
+                for (int d = 0; d < 3; ++d)
+                    ell[d] += sqrt(J[0][d] * J[0][d] + J[1][d] * J[1][d] + J[2][d] * J[2][d]);
+            }
+    for (int d = 0; d < 3; ++d) {
+        ell[d] /= nd;
+        long lo = p->nbr[6 * c + 2 * d];
+        sig[d][0] = lo >= 0 ? face_sigma(p, &r, lo, d) : -1.0;
+        sig[d][1] = face_sigma(p, &r, c, d);
+    }
+    *abar = sa / vol;
+    *bbar = sb / vol;
+    free(phi); free(dphi);
+}
+
+/* 1-D reference mass and SIP blocks on [0,1] for one direction of a cell */
+static void one_d_blocks(const ref_t *r, double ell, const double sig[2],
+                         double M[MAXN][MAXN], double L[MAXN][MAXN])
+{
+    int n = r->n;
+    double v[MAXN], d[MAXN], ve[2][MAXN], de[2][MAXN];
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) M[i][j] = L[i][j] = 0.0;
+    for (int q = 0; q < n; ++q) {
+        or_lagrange(n, r->xl, r->xq[q], v, d);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                M[i][j] += r->wq[q] * v[i] * v[j];
+                L[i][j] += r->wq[q] * d[i] * d[j];
+            }
+    }
+    or_lagrange(n, r->xl, 0.0, ve[0], de[0]);
+    or_lagrange(n, r->xl, 1.0, ve[1], de[1]);
+    for (int e = 0; e < 2; ++e) {
+        if (sig[e] < 0) continue;
+        double nh = e ? 1.0 : -1.0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j)
+                L[i][j] += -0.5 * nh * (de[e][i] * ve[e][j] + ve[e][i] * de[e][j])
+                           + sig[e] * ell * ve[e][i] * ve[e][j];
+    }
+}
+
+/* dense Ahat_K = abar lx ly lz M(x)M(x)M + bbar [ (ly lz/lx) M(x)M(x)Lx + ... ],
+ * the x factor acting on the fastest local index */
+void or_bj_sep_block(const or_prob *p, long c, double *Ab)
+{
+    ref_t r; ref_init(&r, p->k, p->g);
+    int n = r.n, nd = r.nd;
+    double ell[3], abar, bbar, sig[3][2];
+    or_bj_cell_data(p, c, ell, &abar, &bbar, sig);
+    double M[3][MAXN][MAXN], L[3][MAXN][MAXN];
+    for (int d = 0; d < 3; ++d) one_d_blocks(&r, ell[d], sig[d], M[d], L[d]);
+    double cm = abar * ell[0] * ell[1] * ell[2];
+    double cx = bbar * ell[1] * ell[2] / ell[0];
+    double cy = bbar * ell[0] * ell[2] / ell[1];
+    double cz = bbar * ell[0] * ell[1] / ell[2];
+    for (int l = 0; l < n; ++l) for (int j = 0; j < n; ++j) for (int i = 0; i < n; ++i)
+        for (int l2 = 0; l2 < n; ++l2) for (int j2 = 0; j2 < n; ++j2) for (int i2 = 0; i2 < n; ++i2) {
+            int row = i + n * (j + n * l), col = i2 + n * (j2 + n * l2);
+            double mx = M[0][i][i2], my = M[1][j][j2], mz = M[2][l][l2];
+            Ab[row * nd + col] = cm * mx * my * mz + cx * L[0][i][i2] * my * mz
+                               + cy * mx * L[1][j][j2] * mz + cz * mx * my * L[2][l][l2];
+        }
+}
+
+/* in-place Cholesky solve of a dense SPD system (row-major A, overwritten) */
+static int chol_solve(int nd, double *A, double *x)
+{
+    for (int j = 0; j < nd; ++j) {
+        double s = A[j * nd + j];
+        for (int m = 0; m < j; ++m) s -= A[j * nd + m] * A[j * nd + m];
+        if (!(s > 0.0)) return 1;
+        double ljj = sqrt(s);
+        A[j * nd + j] = ljj;
+        for (int i = j + 1; i < nd; ++i) {
+            double t = A[i * nd + j];
+            for (int m = 0; m < j; ++m) t -= A[i * nd + m] * A[j * nd + m];
+            A[i * nd + j] = t / ljj;
+        }
+    }
+    for (int i = 0; i < nd; ++i) {
+        double t = x[i];
+        for (int m = 0; m < i; ++m) t -= A[i * nd + m] * x[m];
+        x[i] = t / A[i * nd + i];
+    }
+    for (int i = nd - 1; i >= 0; --i) {
+        double t = x[i];
+        for (int m = i + 1; m < nd; ++m) t -= A[m * nd + i] * x[m];
+        x[i] = t / A[i * nd + i];
+    }
+    return 0;
+}
+
+int or_bj_sep_apply(const or_prob *p, const double *rv, double *zv)
+{
+    int nd = (p->k + 1) * (p->k + 1) * (p->k + 1);
+    int bad = 0;
+#pragma omp parallel reduction(|:bad)
+    {
+        double *Ab = malloc(sizeof(double) * nd * nd);
+#pragma omp for schedule(dynamic, 4)
+        for (long c = 0; c < p->n_cells; ++c) {
+            or_bj_sep_block(p, c, Ab);
+            for (int a = 0; a < nd; ++a) zv[c * nd + a] = rv[c * nd + a];
+            bad |= chol_solve(nd, Ab, zv + c * nd);
+        }
+        free(Ab);
+    }
+    return bad;
+}

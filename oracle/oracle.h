@@ -1,0 +1,39 @@
+/* Oracle (test infrastructure only): plain FP64 reference of the DG
+ * Helmholtz-type pressure operator and its separable cell-block
+ * preconditioner.  Not part of the product library. */
+#ifndef HELM_ORACLE_H
+#define HELM_ORACLE_H
+
+#define OR_CELL 1
+#define OR_FACE 2
+
+typedef struct {
+    int k;                 /* polynomial degree of the DG space */
+    int g;                 /* degree of the geometry map */
+    long n_cells;
+    const double *nodes;   /* [n_cells][(g+1)^3][3], equispaced reference nodes */
+    const long *nbr;       /* [n_cells][6]: -x,+x,-y,+y,-z,+z; -1 = boundary */
+    const double *alpha;   /* [n_cells*(k+1)^3] DG nodal field */
+    const double *beta;    /* [n_cells*(k+1)^3] DG nodal field */
+    double P;              /* penalty factor */
+} or_prob;
+
+void or_gauss_legendre(int n, double *x, double *w);
+void or_gauss_lobatto(int n, double *x, double *w);
+void or_lagrange(int n, const double *nodes, double t, double *val, double *der);
+
+int  or_mesh_check(const or_prob *p);
+void or_dof_coords(const or_prob *p, double *xyz);
+void or_quad_data(const or_prob *p, double *xyz, double *wdet);
+void or_load_vector(const or_prob *p, const double *fq, double *b);
+void or_cell_volumes(const or_prob *p, double *vol);
+void or_face_sigma(const or_prob *p, double *sigma);
+void or_eval_quad(const or_prob *p, const double *u, double *uq);
+void or_apply(const or_prob *p, int flags, const double *x, double *y);
+void or_assemble_dense(const or_prob *p, int flags, double *A);
+void or_bj_cell_data(const or_prob *p, long c, double ell[3], double *abar,
+                     double *bbar, double sig[3][2]);
+void or_bj_sep_block(const or_prob *p, long c, double *Ab);
+int  or_bj_sep_apply(const or_prob *p, const double *r, double *z);
+
+#endif
