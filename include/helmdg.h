@@ -1,0 +1,253 @@
+/*
+ * helmdg -- matrix-free DG Helmholtz-type pressure operator and its
+ * preconditioned Krylov solve on one AMD Instinct MI355X (gfx950).
+ *
+ * The operator is the implicit pressure step of an IMEX-DG compressible-Euler
+ * solver (Orlando, Benacchio, Bonaventura, "Improving the scalability of a
+ * high-order atmospheric dynamics solver based on the deal.II library",
+ * arXiv:2505.00384): the Helmholtz-type equation for the pressure (section 2),
+ * linearised with frozen coefficients, whose volume terms are the mass term
+ * plus the dt-scaled, enthalpy-weighted stiffness of the matrix S~
+ * (section 3.1, entries of the Helmholtz preconditioner), discretised by
+ * symmetric interior-penalty DG with the tensor-product Lagrange basis on
+ * (k+1) Gauss-Lobatto points (section 2) and (k+1)-point Gauss-Legendre
+ * quadrature per direction (section 3.3):
+ *
+ *   a(u,v) = sum_K sum_q w_q detJ_q [alpha u v + beta grad u . grad v]
+ *          + sum_F sum_q ds_q [ -1/2 (b- dn u- + b+ dn u+)[v]
+ *                               -1/2 (b- dn v- + b+ dn v+)[u]
+ *                               + sigma_F 1/2 (b- + b+)[u][v] ],
+ *   sigma_F = P (k+1)^2 max(|F|/|K-|, |F|/|K+|),
+ *
+ * with [w] = w- - w+, n the unit normal of the minus cell (the cell whose +d
+ * face it is), ds and n taken from the minus side, and natural Neumann
+ * boundaries.  The operator is never assembled; only its action is computed
+ * (section 3.1).
+ *
+ * Conventions for every call
+ * --------------------------
+ * - Vectors are cell-major; inside a cell the (k+1)^3 nodal values are in
+ *   lexicographic Gauss-Lobatto order with x fastest:
+ *   dof = cell*(k+1)^3 + i + (k+1)*(j + (k+1)*l).
+ * - Vector arguments of apply/residual/preconditioner/solve are DEVICE
+ *   pointers owned by the caller (e.g. torch tensors); the library never frees
+ *   them.  FP64 vectors are double, FP32 vectors float.  They must not alias
+ *   unless stated.
+ * - Host arrays are copied during the call and may be freed afterwards.
+ * - A context is bound at creation to one device and one HIP stream; every
+ *   kernel of the context runs on that stream, so apply_* calls are
+ *   asynchronous with respect to the host.  hx_solve returns after the solve
+ *   has finished.  One context must not be used by two host threads at once.
+ * - Every call returns an hx_status and never aborts; hx_last_error() gives a
+ *   message for the last failed call of the context.
+ */
+#ifndef HELMDG_H
+#define HELMDG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hx_ctx hx_ctx;
+
+typedef enum {
+    HX_OK = 0,
+    HX_ERR_ARG = 1,        /* invalid argument (null pointer, size, degree) */
+    HX_ERR_STATE = 2,      /* call order: e.g. apply before mesh/coefficients */
+    HX_ERR_DEVICE = 3,     /* a HIP runtime call failed */
+    HX_ERR_OOM = 4,        /* device allocation failed */
+    HX_ERR_MESH = 5,       /* detJ <= 0, or inconsistent neighbour table */
+    HX_ERR_NOCONV = 6,     /* solver did not reach the tolerance */
+    HX_FALLBACK_USED = 7   /* converged, after the fallback preconditioner took over */
+} hx_status;
+
+typedef enum { HX_F64 = 0, HX_F32 = 1 } hx_prec;
+
+typedef enum {
+    HX_PC_NONE = 0,
+    HX_PC_BLOCK_JACOBI = 1,   /* separable cell block, fast-diagonalisation inverse */
+    HX_PC_LEARNED = 2         /* block Jacobi + per-cell network correction */
+} hx_pc;
+
+/* Create a context on `device` (HIP ordinal) whose kernels run on
+ * `hip_stream` (a hipStream_t; NULL = the null stream). */
+hx_status hx_create(hx_ctx **out, int device, void *hip_stream);
+/* Free every device buffer the context owns.  Accepts NULL. */
+hx_status hx_destroy(hx_ctx *c);
+/* Message of the last failed call (never NULL; "" if none). */
+const char *hx_last_error(const hx_ctx *c);
+/* Highest polynomial degree this build supports. */
+int hx_max_degree(void);
+
+/* ---------------------------------------------------------------------- */
+/* setup (geometry: step a1)                                               */
+/* ---------------------------------------------------------------------- */
+
+/* Upload a conforming hexahedral mesh and compute its geometry data.
+ *   degree      polynomial degree k of the DG space, 1 <= k <= hx_max_degree()
+ *   n_cells     number of cells (>= 1, < 2^31)
+ *   geo_degree  g >= 1, degree of the cell map
+ *   geo_nodes   HOST [n_cells][(g+1)^3][3]: node a + (g+1)*(b + (g+1)*c) is
+ *               the image of the reference point (a/g, b/g, c/g); the cell map
+ *               is the tensor-product Lagrange interpolant through them
+ *   neighbours  HOST [n_cells][6]: cell across the -x,+x,-y,+y,-z,+z faces, -1
+ *               for a boundary face; the +d face of a cell must be the -d face
+ *               of its +d neighbour (conforming, standard orientation; a cell
+ *               may be its own neighbour in a periodic direction)
+ * Fails with HX_ERR_MESH if the table is inconsistent or detJ <= 0 at any
+ * quadrature point.  Invalidates coefficients set before. */
+hx_status hx_setup_mesh(hx_ctx *c, int degree, int64_t n_cells, int geo_degree,
+                        const double *geo_nodes, const int64_t *neighbours);
+
+/* Physical coordinates of every dof (Gauss-Lobatto node images), written to
+ * the DEVICE array xyz [3][n_dofs] (all x, then all y, then all z). */
+hx_status hx_dof_coordinates(hx_ctx *c, double *xyz);
+
+/* Number of dofs, (k+1)^3 * n_cells, or -1 without a mesh. */
+int64_t hx_num_dofs(const hx_ctx *c);
+
+/* ---------------------------------------------------------------------- */
+/* coefficients (step a2)                                                  */
+/* ---------------------------------------------------------------------- */
+
+/* Set the mass coefficient alpha and the stiffness coefficient beta (the
+ * dt-scaled enthalpy weight) as DG nodal fields [n_dofs] (FP64), and the
+ * penalty factor P (> 0; 2 is the usual choice).  Pointers are device
+ * pointers if on_device != 0, host pointers otherwise.  Builds the merged
+ * per-quadrature-point data of the operator in FP64 and FP32 and the
+ * separable block-Jacobi data.  In the fixed-point iteration of the paper
+ * (section 3.1) this is redone each outer iteration with the new pressure. */
+hx_status hx_set_coefficients(hx_ctx *c, const double *alpha, const double *beta,
+                              double penalty_factor, int on_device);
+
+/* ---------------------------------------------------------------------- */
+/* operator (steps a3, a4, a7)                                             */
+/* ---------------------------------------------------------------------- */
+
+/* y = A x (y overwritten).  prec selects FP64 (double*) or FP32 (float*)
+ * vectors and arithmetic; the FP32 form uses an FP32 copy of the merged
+ * geometry and accumulates in FP32.  x and y must not alias. */
+hx_status hx_apply_operator(hx_ctx *c, hx_prec prec, const void *x, void *y);
+
+/* r = b - A x in FP64.  r may alias b but not x. */
+hx_status hx_residual(hx_ctx *c, const double *b, const double *x, double *r);
+
+/* ---------------------------------------------------------------------- */
+/* preconditioners (steps a5, a9)                                          */
+/* ---------------------------------------------------------------------- */
+
+/* z = M^{-1} r.  HX_PC_BLOCK_JACOBI: inverse of the separable approximation
+ * of each cell block,
+ *   Ahat_K = abar lx ly lz M(x)M(x)M + bbar [ (ly lz/lx) L_x(x)M(x)M + ... ],
+ * applied by fast diagonalisation (S_z(x)S_y(x)S_x) D^{-1} (S_z(x)S_y(x)S_x)^T
+ * with S^T M S = I, S^T L S = Lambda -- the tensor-product inverse of
+ * block-diagonal operators of section 3.3, with the 1-D SIP blocks in place of
+ * the mass.  HX_PC_LEARNED (FP64 only; needs hx_set_network): block Jacobi
+ * plus the per-cell network correction.  HX_PC_NONE copies r.  r and z must
+ * not alias. */
+hx_status hx_apply_preconditioner(hx_ctx *c, hx_pc kind, hx_prec prec,
+                                  const void *r, void *z);
+
+/* ---------------------------------------------------------------------- */
+/* solve (steps a6, a8)                                                    */
+/* ---------------------------------------------------------------------- */
+
+typedef struct {
+    int method;          /* 0 = preconditioned CG, 1 = flexible GMRES(restart) */
+    int restart;         /* FGMRES restart length, 1..64 (30) */
+    double rtol;         /* stop when ||b - A x||_2 <= rtol ||b||_2 */
+    int max_iter;        /* total iteration cap */
+    int pc;              /* hx_pc of the (outer) iteration */
+    int mixed;           /* 1: outer FP64 FGMRES, preconditioner = inner FP32 CG */
+    int inner_iters;     /* inner FP32 CG iterations per outer step (mixed) */
+    double inner_rtol;   /* inner stopping tolerance (relative, mixed) */
+    int x0_mode;         /* 0: start from zero, 1: x holds the initial guess */
+    int stall_window;    /* FGMRES stall rule window (10); 0 disables it */
+    double stall_ratio;  /* stall if estimate > ratio * estimate window ago (0.99) */
+} hx_solve_params;
+
+typedef struct {
+    int iters;           /* outer iterations */
+    int restarts;        /* FGMRES cycles */
+    int status;          /* hx_status of the solve */
+    int fallback_used;   /* 1 if the learned preconditioner was replaced by BJ */
+    int inner_iters;     /* total inner (FP32) iterations, mixed form */
+    double true_rel_res; /* ||b - A x||_2 / ||b||_2 in FP64, recomputed at the end */
+    double ms_total;     /* wall time of the solve (host clock) */
+    double ms_op, ms_pc, ms_orth;  /* device time per phase (HIP events) */
+    double *history;     /* optional HOST buffer: residual estimate per iteration */
+    int history_len;     /* in: capacity of history; out: entries written */
+} hx_solve_info;
+
+/* Fill p with the defaults (CG, restart 30, rtol 1e-8, max_iter 10000, block
+ * Jacobi, FP64, inner 12 iterations / 1e-2, zero initial guess, stall 10/0.99). */
+void hx_default_params(hx_solve_params *p);
+
+/* Solve A x = b.  b, x: DEVICE FP64 [n_dofs]; x is the initial guess if
+ * x0_mode = 1 and always receives the best iterate.  info is always written.
+ * Returns HX_OK, HX_FALLBACK_USED (converged after the learned preconditioner
+ * stalled or produced a non-finite value and block Jacobi took over) or
+ * HX_ERR_NOCONV. */
+hx_status hx_solve(hx_ctx *c, const hx_solve_params *prm, const double *b,
+                   double *x, hx_solve_info *info);
+
+/* ---------------------------------------------------------------------- */
+/* BLAS-1 helpers on the context stream (step a6), FP64 device vectors      */
+/* ---------------------------------------------------------------------- */
+
+/* *out (HOST) = x . y, deterministic two-stage reduction. */
+hx_status hx_dot(hx_ctx *c, int64_t n, const double *x, const double *y, double *out);
+
+/* ---------------------------------------------------------------------- */
+/* learned preconditioner (steps a9, a10)                                  */
+/* ---------------------------------------------------------------------- */
+
+/* Network: n_in = (k+1)^3 + 6 (k+1)^2 + 1 -> 256 -> 256 -> (k+1)^3, ReLU,
+ * parameters flat [W1, b1, W2, b2, W3, b3], W row-major [out][in].  BF16
+ * weights and activations, FP32 accumulation on MFMA; FP32 master weights
+ * and Adam moments live in the context. */
+int64_t hx_network_size(const hx_ctx *c);
+
+/* Load FP32 master weights (HOST, n = hx_network_size) and reset Adam. */
+hx_status hx_set_network(hx_ctx *c, const float *master_weights, int64_t n);
+/* Copy the FP32 master weights to the HOST buffer. */
+hx_status hx_get_network(const hx_ctx *c, float *master_weights, int64_t n);
+
+/* Features of every cell from the FP64 residual r (DEVICE [n_dofs]):
+ * feats DEVICE float [n_cells][n_in] (r_K, the six neighbour face layers, the
+ * coefficient feature log(bbar/(abar l^2)), all but the last divided by
+ * s = RMS(r_K)), scale DEVICE float [n_cells] (s). */
+hx_status hx_gather_features(hx_ctx *c, const double *r, float *feats, float *scale);
+
+/* out DEVICE float [batch][n_out] = network(feats DEVICE float [batch][n_in]). */
+hx_status hx_network_forward(hx_ctx *c, const float *feats, int64_t batch, float *out);
+
+/* One Adam step on the MSE loss mean((net(feats) - targets)^2): forward,
+ * backward and update on the GPU.  feats DEVICE float [batch][n_in], targets
+ * DEVICE float [batch][n_out]; *loss_out (HOST, may be NULL) = loss before
+ * the step.  With grad_out (DEVICE float [hx_network_size], may be NULL) the
+ * gradient is also returned and, if lr == 0, no update is made. */
+hx_status hx_train_step(hx_ctx *c, const float *feats, const float *targets,
+                        int64_t batch, float lr, float *loss_out, float *grad_out);
+
+/* ---------------------------------------------------------------------- */
+/* inspection                                                              */
+/* ---------------------------------------------------------------------- */
+
+enum {
+    HX_EXPORT_CELL_DATA = 0,   /* FP64 [n_cells][7][(k+1)^3]: m, Gxx, Gxy, Gxz, Gyy, Gyz, Gzz */
+    HX_EXPORT_FACE_DATA = 1,   /* FP64 [n_cells][3][7][(k+1)^2]: g-(3), g+(3), s of the +d face */
+    HX_EXPORT_SIGMA = 2,       /* FP64 [n_cells][3]: penalty of the +d face (-1: boundary) */
+    HX_EXPORT_VOLUME = 3,      /* FP64 [n_cells] */
+    HX_EXPORT_BJ_SCALARS = 4   /* FP64 [n_cells][4]: abar lx ly lz, bbar ly lz/lx, ... */
+};
+/* Copy internal data to a HOST buffer of `bytes` bytes (for tests). */
+hx_status hx_debug_export(hx_ctx *c, int what, void *host_buf, int64_t bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HELMDG_H */

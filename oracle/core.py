@@ -57,6 +57,7 @@ def lib():
         L.or_load_vector.argtypes = [pp, dp, dp]
         L.or_apply.argtypes = [pp, C.c_int, dp, dp]
         L.or_assemble_dense.argtypes = [pp, C.c_int, dp]
+        L.or_apply_cells.argtypes = [pp, C.c_int, C.c_void_p, C.c_long, dp, dp]
         L.or_bj_cell_data.argtypes = [pp, C.c_long, dp, dp, dp, dp]
         L.or_bj_sep_block.argtypes = [pp, C.c_long, dp]
         L.or_bj_sep_apply.argtypes = [pp, dp, dp]
@@ -176,6 +177,14 @@ class Problem:
         y = np.zeros(self.n_dofs)
         lib().or_apply(self._s(), int(flags), _dp(x), _dp(y))
         return y
+
+    def apply_cells(self, x, cells, flags: int = OR_ALL):
+        """(A x) restricted to the listed cells: [len(cells), nd]."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        cells = np.ascontiguousarray(cells, dtype=np.int64)
+        out = np.zeros(cells.size * self.nd)
+        lib().or_apply_cells(self._s(), int(flags), cells.ctypes.data, cells.size, _dp(x), _dp(out))
+        return out.reshape(cells.size, self.nd)
 
     def assemble_dense(self, flags: int = OR_ALL):
         A = np.zeros((self.n_dofs, self.n_dofs))

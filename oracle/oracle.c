@@ -418,115 +418,134 @@ typedef struct {
     double (*dphi)[3];      /* [nd][3] */
 } scratch_t;
 
-/* y = A x: each cell accumulates a(x, phi_i) for its own test functions. */
-void or_apply(const or_prob *p, int flags, const double *xv, double *yv)
+/* (A x) restricted to the test functions of cell c, written to yc[nd] */
+static void apply_one_cell(const or_prob *p, int flags, long c, const double *xv, double *yc)
 {
     ref_t r; ref_init(&r, p->k, p->g);
     const int nd = r.nd, n = r.n;
-#pragma omp parallel
-    {
-        double *phi = malloc(sizeof(double) * nd), *phiB = malloc(sizeof(double) * nd);
-        double (*dphi)[3] = malloc(sizeof(double) * 3 * nd);
-        double (*dphiB)[3] = malloc(sizeof(double) * 3 * nd);
-#pragma omp for schedule(dynamic, 4)
-        for (long c = 0; c < p->n_cells; ++c) {
-            double *yc = yv + c * nd;
-            const double *xc = xv + c * nd;
-            for (int a = 0; a < nd; ++a) yc[a] = 0.0;
-            const double *X = cell_nodes(p, &r, c);
-            /* ---- cell integral ---- */
-            if (flags & OR_CELL) {
-                for (int l = 0; l < n; ++l)
-                    for (int j = 0; j < n; ++j)
-                        for (int i = 0; i < n; ++i) {
-                            double xi[3] = {r.xq[i], r.xq[j], r.xq[l]}, x[3], J[3][3], K[3][3];
-                            geom_at(&r, X, xi, x, J);
-                            double det = det3(J);
-                            inv_transpose(J, det, K);
-                            double w = r.wq[i] * r.wq[j] * r.wq[l] * det;
-                            basis_at(&r, xi, phi, dphi);
-                            double al = field_at(phi, p->alpha + c * nd, nd);
-                            double be = field_at(phi, p->beta + c * nd, nd);
-                            double u = 0.0, gr[3] = {0, 0, 0};
-                            for (int a = 0; a < nd; ++a) {
-                                u += phi[a] * xc[a];
-                                for (int q = 0; q < 3; ++q) gr[q] += dphi[a][q] * xc[a];
-                            }
-                            double gu[3];
-                            matvec3(K, gr, gu);
-                            for (int a = 0; a < nd; ++a) {
-                                double gv[3];
-                                matvec3(K, dphi[a], gv);
-                                yc[a] += w * (al * u * phi[a]
-                                              + be * (gu[0] * gv[0] + gu[1] * gv[1] + gu[2] * gv[2]));
+    double *phi = malloc(sizeof(double) * nd), *phiB = malloc(sizeof(double) * nd);
+    double (*dphi)[3] = malloc(sizeof(double) * 3 * nd);
+    double (*dphiB)[3] = malloc(sizeof(double) * 3 * nd);
+    const double *xc = xv + c * nd;
+    for (int a = 0; a < nd; ++a) yc[a] = 0.0;
+    const double *X = cell_nodes(p, &r, c);
+    /* ---- cell integral ---- */
+    if (flags & OR_CELL) {
+        for (int l = 0; l < n; ++l)
+            for (int j = 0; j < n; ++j)
+                for (int i = 0; i < n; ++i) {
+                    double xi[3] = {r.xq[i], r.xq[j], r.xq[l]}, x[3], J[3][3], K[3][3];
+                    geom_at(&r, X, xi, x, J);
+                    double det = det3(J);
+                    inv_transpose(J, det, K);
+                    double w = r.wq[i] * r.wq[j] * r.wq[l] * det;
+                    basis_at(&r, xi, phi, dphi);
+                    double al = field_at(phi, p->alpha + c * nd, nd);
+                    double be = field_at(phi, p->beta + c * nd, nd);
+                    double u = 0.0, gr[3] = {0, 0, 0};
+                    for (int a = 0; a < nd; ++a) {
+                        u += phi[a] * xc[a];
+                        for (int q = 0; q < 3; ++q) gr[q] += dphi[a][q] * xc[a];
+                    }
+                    double gu[3];
+                    matvec3(K, gr, gu);
+                    for (int a = 0; a < nd; ++a) {
+                        double gv[3];
+                        matvec3(K, dphi[a], gv);
+                        yc[a] += w * (al * u * phi[a]
+                                      + be * (gu[0] * gv[0] + gu[1] * gv[1] + gu[2] * gv[2]));
+                    }
+                }
+    }
+    /* ---- face integrals, test functions of cell c only ---- */
+    if (flags & OR_FACE) {
+        for (int d = 0; d < 3; ++d)
+            for (int side = 0; side < 2; ++side) {
+                /* side 1: the +d face of c (c is the minus cell);
+                   side 0: the -d face of c (c is the plus cell) */
+                long nb = p->nbr[6 * c + 2 * d + side];
+                if (nb < 0) continue;
+                long km = side ? c : nb, kp = side ? nb : c;
+                double sigma = face_sigma(p, &r, km, d);
+                const double *Xm = cell_nodes(p, &r, km), *Xp = cell_nodes(p, &r, kp);
+                const double *xm = xv + km * nd, *xp = xv + kp * nd;
+                for (int b = 0; b < n; ++b)
+                    for (int a = 0; a < n; ++a) {
+                        double nrm[3], ds;
+                        face_normal(&r, Xm, d, a, b, nrm, &ds);
+                        double xim[3], xip[3], pos[3], Jm[3][3], Jp[3][3], Km[3][3], Kp[3][3];
+                        face_point(&r, d, 1, a, b, xim);
+                        face_point(&r, d, 0, a, b, xip);
+                        geom_at(&r, Xm, xim, pos, Jm);
+                        geom_at(&r, Xp, xip, pos, Jp);
+                        inv_transpose(Jm, det3(Jm), Km);
+                        inv_transpose(Jp, det3(Jp), Kp);
+                        basis_at(&r, xim, phi, dphi);      /* minus side */
+                        basis_at(&r, xip, phiB, dphiB);    /* plus side */
+                        double bm = field_at(phi, p->beta + km * nd, nd);
+                        double bp = field_at(phiB, p->beta + kp * nd, nd);
+                        double um = 0, up = 0, gm[3] = {0, 0, 0}, gp[3] = {0, 0, 0};
+                        for (int e = 0; e < nd; ++e) {
+                            um += phi[e] * xm[e];
+                            up += phiB[e] * xp[e];
+                            for (int q = 0; q < 3; ++q) {
+                                gm[q] += dphi[e][q] * xm[e];
+                                gp[q] += dphiB[e][q] * xp[e];
                             }
                         }
-            }
-            /* ---- face integrals, test functions of cell c only ---- */
-            if (flags & OR_FACE) {
-                for (int d = 0; d < 3; ++d)
-                    for (int side = 0; side < 2; ++side) {
-                        /* side 1: the +d face of c (c is the minus cell);
-                           side 0: the -d face of c (c is the plus cell) */
-                        long nb = p->nbr[6 * c + 2 * d + side];
-                        if (nb < 0) continue;
-                        long km = side ? c : nb, kp = side ? nb : c;
-                        double sigma = face_sigma(p, &r, km, d);
-                        const double *Xm = cell_nodes(p, &r, km), *Xp = cell_nodes(p, &r, kp);
-                        const double *xm = xv + km * nd, *xp = xv + kp * nd;
-                        for (int b = 0; b < n; ++b)
-                            for (int a = 0; a < n; ++a) {
-                                double nrm[3], ds;
-                                face_normal(&r, Xm, d, a, b, nrm, &ds);
-                                double xim[3], xip[3], pos[3], Jm[3][3], Jp[3][3], Km[3][3], Kp[3][3];
-                                face_point(&r, d, 1, a, b, xim);
-                                face_point(&r, d, 0, a, b, xip);
-                                geom_at(&r, Xm, xim, pos, Jm);
-                                geom_at(&r, Xp, xip, pos, Jp);
-                                inv_transpose(Jm, det3(Jm), Km);
-                                inv_transpose(Jp, det3(Jp), Kp);
-                                /* minus side */
-                                basis_at(&r, xim, phi, dphi);
-                                /* plus side */
-                                basis_at(&r, xip, phiB, dphiB);
-                                double bm = field_at(phi, p->beta + km * nd, nd);
-                                double bp = field_at(phiB, p->beta + kp * nd, nd);
-                                double um = 0, up = 0, gm[3] = {0, 0, 0}, gp[3] = {0, 0, 0};
-                                for (int e = 0; e < nd; ++e) {
-                                    um += phi[e] * xm[e];
-                                    up += phiB[e] * xp[e];
-                                    for (int q = 0; q < 3; ++q) {
-                                        gm[q] += dphi[e][q] * xm[e];
-                                        gp[q] += dphiB[e][q] * xp[e];
-                                    }
-                                }
-                                double Gm[3], Gp[3];
-                                matvec3(Km, gm, Gm);
-                                matvec3(Kp, gp, Gp);
-                                double dnm = nrm[0] * Gm[0] + nrm[1] * Gm[1] + nrm[2] * Gm[2];
-                                double dnp = nrm[0] * Gp[0] + nrm[1] * Gp[1] + nrm[2] * Gp[2];
-                                double flux = bm * dnm + bp * dnp;
-                                double jump = um - up;
-                                double pen = sigma * 0.5 * (bm + bp);
-                                /* own test functions */
-                                const double *tphi = side ? phi : phiB;
-                                double (*tdphi)[3] = side ? dphi : dphiB;
-                                double (*Kown)[3] = side ? Km : Kp;
-                                double bown = side ? bm : bp;
-                                double sgn = side ? 1.0 : -1.0;
-                                for (int e = 0; e < nd; ++e) {
-                                    double gv[3];
-                                    matvec3(Kown, tdphi[e], gv);
-                                    double dnv = nrm[0] * gv[0] + nrm[1] * gv[1] + nrm[2] * gv[2];
-                                    double jv = sgn * tphi[e];
-                                    yc[e] += ds * (-0.5 * flux * jv - 0.5 * bown * dnv * jump
-                                                   + pen * jump * jv);
-                                }
-                            }
+                        double Gm[3], Gp[3];
+                        matvec3(Km, gm, Gm);
+                        matvec3(Kp, gp, Gp);
+                        double dnm = nrm[0] * Gm[0] + nrm[1] * Gm[1] + nrm[2] * Gm[2];
+                        double dnp = nrm[0] * Gp[0] + nrm[1] * Gp[1] + nrm[2] * Gp[2];
+                        double flux = bm * dnm + bp * dnp;
+                        double jump = um - up;
+                        double pen = sigma * 0.5 * (bm + bp);
+                        /* own test functions */
+                        const double *tphi = side ? phi : phiB;
+                        double (*tdphi)[3] = side ? dphi : dphiB;
+                        double (*Kown)[3] = side ? Km : Kp;
+                        double bown = side ? bm : bp;
+                        double sgn = side ? 1.0 : -1.0;
+                        for (int e = 0; e < nd; ++e) {
+                            double gv[3];
+                            matvec3(Kown, tdphi[e], gv);
+                            double dnv = nrm[0] * gv[0] + nrm[1] * gv[1] + nrm[2] * gv[2];
+                            double jv = sgn * tphi[e];
+                            yc[e] += ds * (-0.5 * flux * jv - 0.5 * bown * dnv * jump
+                                           + pen * jump * jv);
+                        }
                     }
             }
+    }
+    free(phi); free(phiB); free(dphi); free(dphiB);
+}
+
+/* y = A x: each cell accumulates a(x, phi_i) for its own test functions. */
+void or_apply(const or_prob *p, int flags, const double *xv, double *yv)
+{
+    int nd = (p->k + 1) * (p->k + 1) * (p->k + 1);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (long c = 0; c < p->n_cells; ++c) apply_one_cell(p, flags, c, xv, yv + c * nd);
+}
+
+/* y restricted to the listed cells: out[m*nd + a] = (A x)_{cells[m]*nd + a}.
+ * Same arithmetic as or_apply, for spot checks on large meshes. */
+void or_apply_cells(const or_prob *p, int flags, const long *cells, long m,
+                    const double *xv, double *out)
+{
+    int nd = (p->k + 1) * (p->k + 1) * (p->k + 1);
+    or_prob sub = *p;
+    (void)sub;
+#pragma omp parallel
+    {
+        double *tmp = malloc(sizeof(double) * nd);
+#pragma omp for schedule(dynamic, 1)
+        for (long s = 0; s < m; ++s) {
+            apply_one_cell(p, flags, cells[s], xv, tmp);
+            for (int a = 0; a < nd; ++a) out[s * nd + a] = tmp[a];
         }
-        free(phi); free(phiB); free(dphi); free(dphiB);
+        free(tmp);
     }
 }
 

@@ -30,6 +30,8 @@ void or_cell_volumes(const or_prob *p, double *vol);
 void or_face_sigma(const or_prob *p, double *sigma);
 void or_eval_quad(const or_prob *p, const double *u, double *uq);
 void or_apply(const or_prob *p, int flags, const double *x, double *y);
+void or_apply_cells(const or_prob *p, int flags, const long *cells, long m,
+                    const double *x, double *out);
 void or_assemble_dense(const or_prob *p, int flags, double *A);
 void or_bj_cell_data(const or_prob *p, long c, double ell[3], double *abar,
                      double *bbar, double sig[3][2]);

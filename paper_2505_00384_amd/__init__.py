@@ -1,0 +1,279 @@
+"""helmdg: matrix-free DG Helmholtz pressure operator and Krylov solve on MI355X.
+
+Thin ctypes binding of ``libhelmdg.so`` (built by ``build.py`` for gfx950).
+Every numerical step runs in the library's HIP kernels; this module only
+marshals arguments: torch tensors supply device memory and the HIP stream.
+Loading fails loudly when the library has not been built -- there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhelmdg.so")
+
+HX_OK, HX_ERR_ARG, HX_ERR_STATE, HX_ERR_DEVICE, HX_ERR_OOM, HX_ERR_MESH, \
+    HX_ERR_NOCONV, HX_FALLBACK_USED = range(8)
+HX_F64, HX_F32 = 0, 1
+HX_PC_NONE, HX_PC_BLOCK_JACOBI, HX_PC_LEARNED = 0, 1, 2
+HX_EXPORT_CELL_DATA, HX_EXPORT_FACE_DATA, HX_EXPORT_SIGMA, HX_EXPORT_VOLUME, \
+    HX_EXPORT_BJ_SCALARS = range(5)
+
+STATUS_NAMES = {0: "HX_OK", 1: "HX_ERR_ARG", 2: "HX_ERR_STATE", 3: "HX_ERR_DEVICE",
+                4: "HX_ERR_OOM", 5: "HX_ERR_MESH", 6: "HX_ERR_NOCONV",
+                7: "HX_FALLBACK_USED"}
+
+
+class HXError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class SolveParams(C.Structure):
+    _fields_ = [("method", C.c_int), ("restart", C.c_int), ("rtol", C.c_double),
+                ("max_iter", C.c_int), ("pc", C.c_int), ("mixed", C.c_int),
+                ("inner_iters", C.c_int), ("inner_rtol", C.c_double),
+                ("x0_mode", C.c_int), ("stall_window", C.c_int),
+                ("stall_ratio", C.c_double)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("status", C.c_int),
+                ("fallback_used", C.c_int), ("inner_iters", C.c_int),
+                ("true_rel_res", C.c_double), ("ms_total", C.c_double),
+                ("ms_op", C.c_double), ("ms_pc", C.c_double), ("ms_orth", C.c_double),
+                ("history", C.POINTER(C.c_double)), ("history_len", C.c_int)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libhelmdg.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} not found: build it with paper_2505_00384_amd/build.py "
+                          "(there is no fallback path)")
+    L = C.CDLL(path)
+    vp, i64, dp = C.c_void_p, C.c_int64, C.POINTER(C.c_double)
+    sig = {
+        "hx_create": ([C.POINTER(vp), C.c_int, vp], C.c_int),
+        "hx_destroy": ([vp], C.c_int),
+        "hx_last_error": ([vp], C.c_char_p),
+        "hx_max_degree": ([], C.c_int),
+        "hx_setup_mesh": ([vp, C.c_int, i64, C.c_int, vp, vp], C.c_int),
+        "hx_dof_coordinates": ([vp, vp], C.c_int),
+        "hx_num_dofs": ([vp], i64),
+        "hx_set_coefficients": ([vp, vp, vp, C.c_double, C.c_int], C.c_int),
+        "hx_apply_operator": ([vp, C.c_int, vp, vp], C.c_int),
+        "hx_residual": ([vp, vp, vp, vp], C.c_int),
+        "hx_apply_preconditioner": ([vp, C.c_int, C.c_int, vp, vp], C.c_int),
+        "hx_default_params": ([C.POINTER(SolveParams)], None),
+        "hx_solve": ([vp, C.POINTER(SolveParams), vp, vp, C.POINTER(SolveInfo)], C.c_int),
+        "hx_dot": ([vp, i64, vp, vp, dp], C.c_int),
+        "hx_network_size": ([vp], i64),
+        "hx_set_network": ([vp, vp, i64], C.c_int),
+        "hx_get_network": ([vp, vp, i64], C.c_int),
+        "hx_gather_features": ([vp, vp, vp, vp], C.c_int),
+        "hx_network_forward": ([vp, vp, i64, vp], C.c_int),
+        "hx_train_step": ([vp, vp, vp, i64, C.c_float, C.POINTER(C.c_float), vp], C.c_int),
+        "hx_debug_export": ([vp, C.c_int, vp, i64], C.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def default_params(**kw) -> SolveParams:
+    p = SolveParams()
+    load().hx_default_params(C.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+def _ptr(t) -> int:
+    return t.data_ptr()
+
+
+class HelmDG:
+    """One library context on one device, bound to torch's current stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.torch = torch
+        self.L = load()
+        self.device = device
+        torch.cuda.set_device(device)
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = C.c_void_p()
+        st = self.L.hx_create(C.byref(h), device, C.c_void_p(stream.cuda_stream))
+        if st != HX_OK:
+            raise HXError(st, "hx_create failed")
+        self.h = h
+        self.n_dofs = -1
+        self.k = None
+
+    # -- helpers ----------------------------------------------------------
+    def _chk(self, st: int, what: str):
+        if st not in (HX_OK, HX_FALLBACK_USED):
+            raise HXError(st, f"{what}: {self.L.hx_last_error(self.h).decode()}")
+        return st
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.hx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def last_error(self) -> str:
+        return self.L.hx_last_error(self.h).decode()
+
+    # -- setup --------------------------------------------------------------
+    def setup_mesh(self, degree: int, nodes: np.ndarray, nbr: np.ndarray, geo_degree: int):
+        nodes = np.ascontiguousarray(nodes, dtype=np.float64)
+        nbr = np.ascontiguousarray(nbr, dtype=np.int64)
+        n_cells = nbr.shape[0]
+        st = self.L.hx_setup_mesh(self.h, int(degree), n_cells, int(geo_degree),
+                                  nodes.ctypes.data, nbr.ctypes.data)
+        self._chk(st, "setup_mesh")
+        self.k = int(degree)
+        self.n_dofs = int(self.L.hx_num_dofs(self.h))
+        self.n_cells = n_cells
+        return self
+
+    def dof_coordinates(self):
+        t = self.torch.empty(3, self.n_dofs, dtype=self.torch.float64, device=f"cuda:{self.device}")
+        self._chk(self.L.hx_dof_coordinates(self.h, _ptr(t)), "dof_coordinates")
+        return t
+
+    def set_coefficients(self, alpha, beta, penalty: float = 2.0):
+        if isinstance(alpha, np.ndarray):
+            a = np.ascontiguousarray(alpha, dtype=np.float64)
+            b = np.ascontiguousarray(beta, dtype=np.float64)
+            st = self.L.hx_set_coefficients(self.h, a.ctypes.data, b.ctypes.data, float(penalty), 0)
+        else:
+            a = alpha.contiguous(); b = beta.contiguous()
+            st = self.L.hx_set_coefficients(self.h, _ptr(a), _ptr(b), float(penalty), 1)
+        self._chk(st, "set_coefficients")
+
+    # -- operator -------------------------------------------------------------
+    def apply_operator(self, x, y=None):
+        prec = HX_F64 if x.dtype == self.torch.float64 else HX_F32
+        if y is None:
+            y = self.torch.empty_like(x)
+        self._chk(self.L.hx_apply_operator(self.h, prec, _ptr(x), _ptr(y)), "apply_operator")
+        return y
+
+    def residual(self, b, x, r=None):
+        if r is None:
+            r = self.torch.empty_like(b)
+        self._chk(self.L.hx_residual(self.h, _ptr(b), _ptr(x), _ptr(r)), "residual")
+        return r
+
+    def apply_preconditioner(self, r, z=None, kind: int = HX_PC_BLOCK_JACOBI):
+        prec = HX_F64 if r.dtype == self.torch.float64 else HX_F32
+        if z is None:
+            z = self.torch.empty_like(r)
+        self._chk(self.L.hx_apply_preconditioner(self.h, kind, prec, _ptr(r), _ptr(z)),
+                  "apply_preconditioner")
+        return z
+
+    def solve(self, b, x=None, params: Optional[SolveParams] = None, history: int = 0,
+              check: bool = True):
+        if params is None:
+            params = default_params()
+        if x is None:
+            x = self.torch.zeros_like(b)
+        info = SolveInfo()
+        hist = None
+        if history:
+            hist = (C.c_double * history)()
+            info.history = C.cast(hist, C.POINTER(C.c_double))
+            info.history_len = history
+        st = self.L.hx_solve(self.h, C.byref(params), _ptr(b), _ptr(x), C.byref(info))
+        if check and st not in (HX_OK, HX_FALLBACK_USED, HX_ERR_NOCONV):
+            self._chk(st, "solve")
+        res = dict(status=st, iters=info.iters, restarts=info.restarts,
+                   fallback_used=bool(info.fallback_used), inner_iters=info.inner_iters,
+                   true_rel_res=info.true_rel_res, ms_total=info.ms_total, ms_op=info.ms_op,
+                   ms_pc=info.ms_pc, ms_orth=info.ms_orth)
+        if hist is not None:
+            res["history"] = list(hist[:info.history_len])
+        return x, res
+
+    def dot(self, x, y) -> float:
+        out = C.c_double()
+        self._chk(self.L.hx_dot(self.h, x.numel(), _ptr(x), _ptr(y), C.byref(out)), "dot")
+        return out.value
+
+    # -- learned preconditioner -------------------------------------------
+    def network_size(self) -> int:
+        return int(self.L.hx_network_size(self.h))
+
+    def set_network(self, w: np.ndarray):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        self._chk(self.L.hx_set_network(self.h, w.ctypes.data, w.size), "set_network")
+
+    def get_network(self) -> np.ndarray:
+        w = np.zeros(self.network_size(), dtype=np.float32)
+        self._chk(self.L.hx_get_network(self.h, w.ctypes.data, w.size), "get_network")
+        return w
+
+    def n_features(self) -> int:
+        n = self.k + 1
+        return n ** 3 + 6 * n * n + 1
+
+    def gather_features(self, r):
+        F = self.torch.empty(self.n_cells, self.n_features(), dtype=self.torch.float32,
+                             device=r.device)
+        s = self.torch.empty(self.n_cells, dtype=self.torch.float32, device=r.device)
+        self._chk(self.L.hx_gather_features(self.h, _ptr(r), _ptr(F), _ptr(s)), "gather_features")
+        return F, s
+
+    def network_forward(self, feats):
+        n_out = (self.k + 1) ** 3
+        out = self.torch.empty(feats.shape[0], n_out, dtype=self.torch.float32, device=feats.device)
+        self._chk(self.L.hx_network_forward(self.h, _ptr(feats), feats.shape[0], _ptr(out)),
+                  "network_forward")
+        return out
+
+    def train_step(self, feats, targets, lr: float, want_grad: bool = False):
+        loss = C.c_float()
+        g = None
+        if want_grad:
+            g = self.torch.empty(self.network_size(), dtype=self.torch.float32, device=feats.device)
+        self._chk(self.L.hx_train_step(self.h, _ptr(feats), _ptr(targets), feats.shape[0],
+                                       float(lr), C.byref(loss), _ptr(g) if g is not None else None),
+                  "train_step")
+        return loss.value, g
+
+    def debug_export(self, what: int, shape, dtype=np.float64) -> np.ndarray:
+        out = np.zeros(shape, dtype=dtype)
+        self._chk(self.L.hx_debug_export(self.h, what, out.ctypes.data, out.nbytes), "debug_export")
+        return out
+
+
+__all__ = ["HelmDG", "HXError", "SolveParams", "SolveInfo", "default_params", "load"] + \
+    [n for n in list(globals()) if n.startswith("HX_")]

@@ -1,0 +1,379 @@
+// C-ABI entry points of libhelmdg: context, argument validation, mesh and
+// coefficient set-up, operator / preconditioner application.
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <vector>
+
+#include "common.hpp"
+
+namespace hx {
+
+hx_status fail(hx_ctx *c, hx_status s, const char *fmt, ...)
+{
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return s;
+}
+
+hx_status dalloc(hx_ctx *c, void **p, size_t bytes)
+{
+    *p = nullptr;
+    if (bytes == 0) bytes = 8;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(c, HX_ERR_OOM, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+    }
+    return HX_OK;
+}
+
+void dfree(void **p)
+{
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+}
+
+static void free_mesh(hx_ctx *c)
+{
+    void **bufs[] = {(void **)&c->nodes, (void **)&c->nbr, (void **)&c->ref, (void **)&c->vol,
+                     (void **)&c->ell, (void **)&c->mindet, (void **)&c->sigma,
+                     (void **)&c->cell64, (void **)&c->cell32, (void **)&c->face64,
+                     (void **)&c->face32, (void **)&c->bjS64, (void **)&c->bjS32,
+                     (void **)&c->bjL64, (void **)&c->bjL32, (void **)&c->bjC64,
+                     (void **)&c->bjC32, (void **)&c->coef_feat, (void **)&c->work64,
+                     (void **)&c->work32};
+    for (void **b : bufs) dfree(b);
+    c->work64_len = c->work32_len = 0;
+    c->has_mesh = c->has_coef = false;
+}
+
+static hx_status upload_tables(hx_ctx *c)
+{
+    std::vector<OpTab> all(MAXN + 1);
+    std::memset(all.data(), 0, sizeof(OpTab) * all.size());
+    for (int n = 2; n <= MAXN; ++n) {
+        RefTab64 t;
+        build_ref_tables(n, t);
+        for (int i = 0; i < n * n; ++i) {
+            all[n].B[i] = t.B[i];
+            all[n].BD[i] = t.BD[i];
+            all[n].Bf[i] = (float)t.B[i];
+            all[n].BDf[i] = (float)t.BD[i];
+        }
+        for (int e = 0; e < 2; ++e)
+            for (int i = 0; i < n; ++i) {
+                all[n].DL[e][i] = t.DL[e][i];
+                all[n].DLf[e][i] = (float)t.DL[e][i];
+            }
+    }
+    HX_HIP(c, upload_op_tables_operator(all.data()));
+    return HX_OK;
+}
+
+}  // namespace hx
+
+using namespace hx;
+
+extern "C" {
+
+int hx_max_degree(void) { return MAXK; }
+
+hx_status hx_create(hx_ctx **out, int device, void *hip_stream)
+{
+    if (!out) return HX_ERR_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+        (void)hipGetLastError();
+        return HX_ERR_DEVICE;
+    }
+    if (device < 0 || device >= ndev) return HX_ERR_ARG;
+    if (hipSetDevice(device) != hipSuccess) return HX_ERR_DEVICE;
+    hx_ctx *c = new hx_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    hx_status s = upload_tables(c);
+    if (s == HX_OK) s = dalloc(c, (void **)&c->red, sizeof(double) * (size_t)1024 * 72);
+    if (s == HX_OK && hipHostMalloc((void **)&c->red_host, sizeof(double) * 1024) != hipSuccess)
+        s = HX_ERR_DEVICE;
+    if (s != HX_OK) {
+        hx_destroy(c);
+        return s;
+    }
+    *out = c;
+    return HX_OK;
+}
+
+hx_status hx_destroy(hx_ctx *c)
+{
+    if (!c) return HX_OK;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    mlp_destroy(c);
+    free_mesh(c);
+    dfree((void **)&c->red);
+    if (c->red_host) (void)hipHostFree(c->red_host);
+    delete c;
+    return HX_OK;
+}
+
+const char *hx_last_error(const hx_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+int64_t hx_num_dofs(const hx_ctx *c) { return (c && c->has_mesh) ? c->n_dofs : -1; }
+
+hx_status hx_setup_mesh(hx_ctx *c, int degree, int64_t n_cells, int geo_degree,
+                        const double *geo_nodes, const int64_t *neighbours)
+{
+    if (!c) return HX_ERR_ARG;
+    c->err.clear();
+    if (degree < 1 || degree > MAXK)
+        return fail(c, HX_ERR_ARG, "degree %d outside 1..%d", degree, MAXK);
+    if (geo_degree < 1 || geo_degree > MAXG)
+        return fail(c, HX_ERR_ARG, "geometry degree %d outside 1..%d", geo_degree, MAXG);
+    if (n_cells < 1 || n_cells >= (int64_t(1) << 31))
+        return fail(c, HX_ERR_ARG, "n_cells %lld out of range", (long long)n_cells);
+    if (!geo_nodes || !neighbours) return fail(c, HX_ERR_ARG, "null mesh array");
+    // neighbour table: range and conformity
+    std::vector<int32_t> nb32((size_t)n_cells * 6);
+    for (int64_t i = 0; i < n_cells; ++i)
+        for (int f = 0; f < 6; ++f) {
+            const int64_t v = neighbours[6 * i + f];
+            if (v < -1 || v >= n_cells)
+                return fail(c, HX_ERR_MESH, "neighbour %lld of cell %lld face %d out of range",
+                            (long long)v, (long long)i, f);
+            if (v >= 0 && neighbours[6 * v + (f ^ 1)] != i)
+                return fail(c, HX_ERR_MESH, "cell %lld face %d: neighbour %lld does not point back",
+                            (long long)i, f, (long long)v);
+            nb32[6 * i + f] = (int32_t)v;
+        }
+    HX_HIP(c, hipSetDevice(c->device));
+    free_mesh(c);
+    c->k = degree;
+    c->n = degree + 1;
+    c->nf = c->n * c->n;
+    c->nd = c->nf * c->n;
+    c->g = geo_degree;
+    c->n_cells = n_cells;
+    c->n_dofs = n_cells * c->nd;
+    const size_t ng3 = (size_t)(geo_degree + 1) * (geo_degree + 1) * (geo_degree + 1);
+    const size_t nc = (size_t)n_cells;
+    build_ref_tables(c->n, c->ref_host);
+    hx_status s = HX_OK;
+#define ALLOC(ptr, bytes)                                  \
+    if (s == HX_OK) s = dalloc(c, (void **)&(ptr), (bytes));
+    ALLOC(c->nodes, sizeof(double) * nc * ng3 * 3);
+    ALLOC(c->nbr, sizeof(int32_t) * nc * 6);
+    ALLOC(c->ref, sizeof(RefTab64));
+    ALLOC(c->vol, sizeof(double) * nc);
+    ALLOC(c->ell, sizeof(double) * nc * 3);
+    ALLOC(c->mindet, sizeof(double) * nc);
+    ALLOC(c->sigma, sizeof(double) * nc * 3);
+    ALLOC(c->cell64, sizeof(double) * nc * 7 * c->nd);
+    ALLOC(c->cell32, sizeof(float) * nc * 7 * c->nd);
+    ALLOC(c->face64, sizeof(double) * nc * 3 * 7 * c->nf);
+    ALLOC(c->face32, sizeof(float) * nc * 3 * 7 * c->nf);
+    ALLOC(c->bjS64, sizeof(double) * nc * 3 * c->nf);
+    ALLOC(c->bjS32, sizeof(float) * nc * 3 * c->nf);
+    ALLOC(c->bjL64, sizeof(double) * nc * 3 * c->n);
+    ALLOC(c->bjL32, sizeof(float) * nc * 3 * c->n);
+    ALLOC(c->bjC64, sizeof(double) * nc * 4);
+    ALLOC(c->bjC32, sizeof(float) * nc * 4);
+    ALLOC(c->coef_feat, sizeof(double) * nc);
+#undef ALLOC
+    if (s != HX_OK) {
+        free_mesh(c);
+        return s;
+    }
+    HX_HIP(c, hipMemcpyAsync(c->nodes, geo_nodes, sizeof(double) * nc * ng3 * 3,
+                             hipMemcpyHostToDevice, c->stream));
+    HX_HIP(c, hipMemcpyAsync(c->nbr, nb32.data(), sizeof(int32_t) * nc * 6, hipMemcpyHostToDevice,
+                             c->stream));
+    HX_HIP(c, hipMemcpyAsync(c->ref, &c->ref_host, sizeof(RefTab64), hipMemcpyHostToDevice,
+                             c->stream));
+    HX_HIP(c, launch_cell_geometry(c));
+    std::vector<double> md(nc);
+    HX_HIP(c, hipMemcpyAsync(md.data(), c->mindet, sizeof(double) * nc, hipMemcpyDeviceToHost,
+                             c->stream));
+    HX_HIP(c, hipStreamSynchronize(c->stream));
+    for (size_t i = 0; i < nc; ++i)
+        if (!(md[i] > 0.0)) {
+            free_mesh(c);
+            return fail(c, HX_ERR_MESH, "cell %zu: detJ = %g <= 0 at a quadrature point", i, md[i]);
+        }
+    HX_HIP(c, launch_face_sigma(c));
+    HX_HIP(c, launch_bj_eigen(c));
+    HX_HIP(c, hipStreamSynchronize(c->stream));
+    c->has_mesh = true;
+    return HX_OK;
+}
+
+hx_status hx_dof_coordinates(hx_ctx *c, double *xyz)
+{
+    if (!c) return HX_ERR_ARG;
+    if (!c->has_mesh) return fail(c, HX_ERR_STATE, "no mesh");
+    if (!xyz) return fail(c, HX_ERR_ARG, "null output");
+    HX_HIP(c, launch_dof_coords(c, xyz));
+    return HX_OK;
+}
+
+hx_status hx_set_coefficients(hx_ctx *c, const double *alpha, const double *beta,
+                              double penalty_factor, int on_device)
+{
+    if (!c) return HX_ERR_ARG;
+    if (!c->has_mesh) return fail(c, HX_ERR_STATE, "set_coefficients before setup_mesh");
+    if (!alpha || !beta) return fail(c, HX_ERR_ARG, "null coefficient array");
+    if (!(penalty_factor > 0.0) || !std::isfinite(penalty_factor))
+        return fail(c, HX_ERR_ARG, "penalty factor must be positive");
+    HX_HIP(c, hipSetDevice(c->device));
+    const size_t bytes = sizeof(double) * (size_t)c->n_dofs;
+    double *da = (double *)alpha, *db = (double *)beta;
+    double *tmp = nullptr;
+    if (!on_device) {
+        hx_status s = dalloc(c, (void **)&tmp, 2 * bytes);
+        if (s != HX_OK) return s;
+        da = tmp;
+        db = tmp + c->n_dofs;
+        HX_HIP(c, hipMemcpyAsync(da, alpha, bytes, hipMemcpyHostToDevice, c->stream));
+        HX_HIP(c, hipMemcpyAsync(db, beta, bytes, hipMemcpyHostToDevice, c->stream));
+    }
+    if (penalty_factor != c->P) {
+        c->P = penalty_factor;
+        HX_HIP(c, launch_face_sigma(c));
+        HX_HIP(c, launch_bj_eigen(c));
+    }
+    hipError_t e = launch_set_coefficients(c, da, db);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (tmp) dfree((void **)&tmp);
+    if (e != hipSuccess) return fail(c, HX_ERR_DEVICE, "set_coefficients: %s", hipGetErrorString(e));
+    c->has_coef = true;
+    return HX_OK;
+}
+
+hx_status hx_apply_operator(hx_ctx *c, hx_prec prec, const void *x, void *y)
+{
+    if (!c) return HX_ERR_ARG;
+    if (!c->has_coef) return fail(c, HX_ERR_STATE, "apply before setup_mesh/set_coefficients");
+    if (!x || !y) return fail(c, HX_ERR_ARG, "null vector");
+    if (x == y) return fail(c, HX_ERR_ARG, "x and y alias");
+    if (prec == HX_F64) HX_HIP(c, launch_apply64(c, (const double *)x, (double *)y, nullptr));
+    else if (prec == HX_F32) HX_HIP(c, launch_apply32(c, (const float *)x, (float *)y, nullptr));
+    else return fail(c, HX_ERR_ARG, "unknown precision %d", (int)prec);
+    return HX_OK;
+}
+
+hx_status hx_residual(hx_ctx *c, const double *b, const double *x, double *r)
+{
+    if (!c) return HX_ERR_ARG;
+    if (!c->has_coef) return fail(c, HX_ERR_STATE, "residual before setup_mesh/set_coefficients");
+    if (!b || !x || !r) return fail(c, HX_ERR_ARG, "null vector");
+    if (x == r) return fail(c, HX_ERR_ARG, "x and r alias");
+    HX_HIP(c, launch_apply64(c, x, r, b));
+    return HX_OK;
+}
+
+hx_status hx_apply_preconditioner(hx_ctx *c, hx_pc kind, hx_prec prec, const void *r, void *z)
+{
+    if (!c) return HX_ERR_ARG;
+    if (!c->has_coef) return fail(c, HX_ERR_STATE, "preconditioner before set_coefficients");
+    if (!r || !z) return fail(c, HX_ERR_ARG, "null vector");
+    if (r == z) return fail(c, HX_ERR_ARG, "r and z alias");
+    if (prec != HX_F64 && prec != HX_F32) return fail(c, HX_ERR_ARG, "unknown precision");
+    const size_t es = prec == HX_F64 ? 8 : 4;
+    switch (kind) {
+    case HX_PC_NONE:
+        HX_HIP(c, hipMemcpyAsync(z, r, es * c->n_dofs, hipMemcpyDeviceToDevice, c->stream));
+        return HX_OK;
+    case HX_PC_BLOCK_JACOBI:
+        if (prec == HX_F64) HX_HIP(c, launch_bj64(c, (const double *)r, (double *)z));
+        else HX_HIP(c, launch_bj32(c, (const float *)r, (float *)z));
+        return HX_OK;
+    case HX_PC_LEARNED: {
+        if (prec != HX_F64) return fail(c, HX_ERR_ARG, "learned preconditioner is FP64-in/out");
+        int nonfinite = 0;
+        return mlp_precondition(c, (const double *)r, (double *)z, &nonfinite);
+    }
+    default:
+        return fail(c, HX_ERR_ARG, "unknown preconditioner %d", (int)kind);
+    }
+}
+
+hx_status hx_dot(hx_ctx *c, int64_t n, const double *x, const double *y, double *out)
+{
+    if (!c || !x || !y || !out || n < 0) return c ? fail(c, HX_ERR_ARG, "bad dot arguments") : HX_ERR_ARG;
+    HX_HIP(c, blas_dot(c, n, x, y, c->red + 1024 * 70));
+    HX_HIP(c, hipMemcpyAsync(out, c->red + 1024 * 70, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HX_HIP(c, hipStreamSynchronize(c->stream));
+    return HX_OK;
+}
+
+int64_t hx_network_size(const hx_ctx *c) { return c && c->has_mesh ? mlp_param_count(c) : -1; }
+
+hx_status hx_set_network(hx_ctx *c, const float *w, int64_t n)
+{
+    if (!c) return HX_ERR_ARG;
+    if (!c->has_mesh) return fail(c, HX_ERR_STATE, "set_network before setup_mesh");
+    if (!w) return fail(c, HX_ERR_ARG, "null weights");
+    return mlp_set(c, w, n);
+}
+
+hx_status hx_get_network(const hx_ctx *c, float *w, int64_t n)
+{
+    if (!c || !w) return HX_ERR_ARG;
+    return mlp_get(c, w, n);
+}
+
+hx_status hx_gather_features(hx_ctx *c, const double *r, float *feats, float *scale)
+{
+    if (!c) return HX_ERR_ARG;
+    if (!c->has_coef) return fail(c, HX_ERR_STATE, "features before set_coefficients");
+    if (!r || !feats || !scale) return fail(c, HX_ERR_ARG, "null pointer");
+    return mlp_features(c, r, feats, scale);
+}
+
+hx_status hx_network_forward(hx_ctx *c, const float *feats, int64_t batch, float *out)
+{
+    if (!c) return HX_ERR_ARG;
+    if (!feats || !out || batch < 0) return fail(c, HX_ERR_ARG, "bad forward arguments");
+    return mlp_forward(c, feats, batch, out);
+}
+
+hx_status hx_train_step(hx_ctx *c, const float *feats, const float *targets, int64_t batch,
+                        float lr, float *loss_out, float *grad_out)
+{
+    if (!c) return HX_ERR_ARG;
+    if (!feats || !targets || batch <= 0) return fail(c, HX_ERR_ARG, "bad training arguments");
+    return mlp_train(c, feats, targets, batch, lr, loss_out, grad_out);
+}
+
+hx_status hx_debug_export(hx_ctx *c, int what, void *host_buf, int64_t bytes)
+{
+    if (!c || !host_buf) return HX_ERR_ARG;
+    if (!c->has_mesh) return fail(c, HX_ERR_STATE, "no mesh");
+    const void *src = nullptr;
+    size_t need = 0;
+    const size_t nc = (size_t)c->n_cells;
+    switch (what) {
+    case HX_EXPORT_CELL_DATA: src = c->cell64; need = sizeof(double) * nc * 7 * c->nd; break;
+    case HX_EXPORT_FACE_DATA: src = c->face64; need = sizeof(double) * nc * 3 * 7 * c->nf; break;
+    case HX_EXPORT_SIGMA: src = c->sigma; need = sizeof(double) * nc * 3; break;
+    case HX_EXPORT_VOLUME: src = c->vol; need = sizeof(double) * nc; break;
+    case HX_EXPORT_BJ_SCALARS: src = c->bjC64; need = sizeof(double) * nc * 4; break;
+    default: return fail(c, HX_ERR_ARG, "unknown export %d", what);
+    }
+    if ((what == HX_EXPORT_CELL_DATA || what == HX_EXPORT_FACE_DATA || what == HX_EXPORT_BJ_SCALARS) &&
+        !c->has_coef)
+        return fail(c, HX_ERR_STATE, "no coefficients");
+    if (bytes < (int64_t)need) return fail(c, HX_ERR_ARG, "buffer too small (%zu needed)", need);
+    HX_HIP(c, hipMemcpyAsync(host_buf, src, need, hipMemcpyDeviceToHost, c->stream));
+    HX_HIP(c, hipStreamSynchronize(c->stream));
+    return HX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,188 @@
+// Separable cell-block Jacobi by fast diagonalisation:
+//   z_K = (S_z (x) S_y (x) S_x) diag(1/(c0 + cx lx_i + cy ly_j + cz lz_l))
+//         (S_z (x) S_y (x) S_x)^T r_K,
+// with S_d^T M S_d = I and S_d^T L_d S_d = diag(l_d) per cell and direction.
+// This is the tensor-product inversion of block-diagonal operators the paper
+// uses for its velocity mass matrix (section 3.3: inverse as S^-T J^-1 S^-1
+// with S a Kronecker product of 1-D matrices), applied here to the
+// separable approximation of the Helmholtz cell block.
+//
+// Mapping: N*N threads per cell, one per pencil; 6 sweeps of N x N 1-D
+// matrices that differ per cell (kept in LDS) plus one diagonal scaling.
+#include "common.hpp"
+
+#include <type_traits>
+
+namespace hx {
+
+namespace {
+
+template <int N>
+struct Cfg {
+    static constexpr int NF = N * N, ND = N * N * N;
+    static constexpr int CPB = (256 / NF) > 0 ? 256 / NF : 1;
+    static constexpr int NT = ((CPB * NF + 63) / 64) * 64;
+};
+
+template <int N, typename T>
+__global__ void __launch_bounds__(Cfg<N>::NT)
+k_bj(const T *__restrict__ r, T *__restrict__ z, const T *__restrict__ S, const T *__restrict__ L,
+     const T *__restrict__ C, int n_cells, int nwg)
+{
+    constexpr int NF = Cfg<N>::NF, ND = Cfg<N>::ND, CPB = Cfg<N>::CPB;
+    __shared__ T sR[CPB][ND];
+    __shared__ T sS[CPB][3][NF];
+    __shared__ T sL[CPB][3][N];
+    __shared__ T sC[CPB][4];
+
+    const int bid = blockIdx.x;
+    const int q8 = nwg / NXCD, r8 = nwg % NXCD, xcd = bid % NXCD;
+    const int wg = xcd * q8 + (xcd < r8 ? xcd : r8) + bid / NXCD;
+    const int t = threadIdx.x;
+    const int lc0 = t / NF;
+    const bool slot = lc0 < CPB;
+    const int lc = slot ? lc0 : 0;
+    const int tt = t - lc0 * NF;
+    const int a = tt % N, b = tt / N;
+    const int64_t cid = (int64_t)wg * CPB + lc;
+    const bool active = slot && cid < n_cells;
+
+    if (active) {
+        for (int e = tt; e < ND; e += NF) sR[lc][e] = r[cid * ND + e];
+        for (int e = tt; e < 3 * NF; e += NF) sS[lc][e / NF][e % NF] = S[cid * 3 * NF + e];
+        for (int e = tt; e < 3 * N; e += NF) sL[lc][e / N][e % N] = L[cid * 3 * N + e];
+        for (int e = tt; e < 4; e += NF) sC[lc][e] = C[cid * 4 + e];
+    }
+    __syncthreads();
+    T v[N], w[N];
+    // S_x^T along x: thread (j=a, l=b)
+    if (active) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] = sR[lc][i + N * a + NF * b];
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+            T s = 0;
+#pragma unroll
+            for (int i = 0; i < N; ++i) s += sS[lc][0][i * N + m] * v[i];
+            w[m] = s;
+        }
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+        for (int m = 0; m < N; ++m) sR[lc][m + N * a + NF * b] = w[m];
+    }
+    __syncthreads();
+    // S_y^T along y: thread (mx=a, l=b)
+    if (active) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) v[j] = sR[lc][a + N * j + NF * b];
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+            T s = 0;
+#pragma unroll
+            for (int j = 0; j < N; ++j) s += sS[lc][1][j * N + m] * v[j];
+            w[m] = s;
+        }
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+        for (int m = 0; m < N; ++m) sR[lc][a + N * m + NF * b] = w[m];
+    }
+    __syncthreads();
+    // S_z^T along z, diagonal scaling, S_z along z: thread (mx=a, my=b)
+    if (active) {
+#pragma unroll
+        for (int l = 0; l < N; ++l) v[l] = sR[lc][a + N * b + NF * l];
+        const T c0 = sC[lc][0], cx = sC[lc][1], cy = sC[lc][2], cz = sC[lc][3];
+        const T base = c0 + cx * sL[lc][0][a] + cy * sL[lc][1][b];
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+            T s = 0;
+#pragma unroll
+            for (int l = 0; l < N; ++l) s += sS[lc][2][l * N + m] * v[l];
+            w[m] = s / (base + cz * sL[lc][2][m]);
+        }
+#pragma unroll
+        for (int l = 0; l < N; ++l) {
+            T s = 0;
+#pragma unroll
+            for (int m = 0; m < N; ++m) s += sS[lc][2][l * N + m] * w[m];
+            v[l] = s;
+        }
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+        for (int l = 0; l < N; ++l) sR[lc][a + N * b + NF * l] = v[l];
+    }
+    __syncthreads();
+    // S_y along y: thread (mx=a, l=b)
+    if (active) {
+#pragma unroll
+        for (int m = 0; m < N; ++m) v[m] = sR[lc][a + N * m + NF * b];
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            T s = 0;
+#pragma unroll
+            for (int m = 0; m < N; ++m) s += sS[lc][1][j * N + m] * v[m];
+            w[j] = s;
+        }
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) sR[lc][a + N * j + NF * b] = w[j];
+    }
+    __syncthreads();
+    // S_x along x: thread (j=a, l=b), write out
+    if (active) {
+#pragma unroll
+        for (int m = 0; m < N; ++m) v[m] = sR[lc][m + N * a + NF * b];
+        const int64_t o = cid * ND + N * a + NF * b;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            T s = 0;
+#pragma unroll
+            for (int m = 0; m < N; ++m) s += sS[lc][0][i * N + m] * v[m];
+            z[o + i] = s;
+        }
+    }
+}
+
+template <int N, typename T>
+hipError_t bj_n(hx_ctx *c, const T *r, T *z)
+{
+    const int cpb = Cfg<N>::CPB;
+    const int nwg = (int)((c->n_cells + cpb - 1) / cpb);
+    const bool dbl = std::is_same<T, double>::value;
+    const T *S = dbl ? (const T *)c->bjS64 : (const T *)c->bjS32;
+    const T *L = dbl ? (const T *)c->bjL64 : (const T *)c->bjL32;
+    const T *C = dbl ? (const T *)c->bjC64 : (const T *)c->bjC32;
+    hipLaunchKernelGGL((k_bj<N, T>), dim3(nwg), dim3(Cfg<N>::NT), 0, c->stream, r, z, S, L, C,
+                       (int)c->n_cells, nwg);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t bj_dispatch(hx_ctx *c, const T *r, T *z)
+{
+    switch (c->n) {
+    case 2: return bj_n<2, T>(c, r, z);
+    case 3: return bj_n<3, T>(c, r, z);
+    case 4: return bj_n<4, T>(c, r, z);
+    case 5: return bj_n<5, T>(c, r, z);
+    case 6: return bj_n<6, T>(c, r, z);
+    case 7: return bj_n<7, T>(c, r, z);
+    case 8: return bj_n<8, T>(c, r, z);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_bj64(hx_ctx *c, const double *r, double *z) { return bj_dispatch<double>(c, r, z); }
+hipError_t launch_bj32(hx_ctx *c, const float *r, float *z) { return bj_dispatch<float>(c, r, z); }
+
+}  // namespace hx

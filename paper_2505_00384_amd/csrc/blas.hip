@@ -1,0 +1,285 @@
+// Krylov building blocks on one stream: deterministic two-stage reductions
+// (wave64 shuffles, then a fixed-order LDS tree; the stage-1 partition
+// depends only on n, so results are bitwise reproducible), block dot products
+// and block updates for classical Gram-Schmidt, fused CG updates that read
+// their scalars from device memory (no host round trip), casts.
+#include "common.hpp"
+
+namespace hx {
+namespace {
+
+constexpr int RT = 256;          // threads of a reduction block
+constexpr int RED_MAX = 1024;    // max stage-1 blocks
+constexpr int MC = 8;            // vectors per block-dot pass
+
+inline int red_blocks(int64_t n)
+{
+    int64_t b = (n + RT * 8 - 1) / (RT * 8);
+    if (b < 1) b = 1;
+    if (b > RED_MAX) b = RED_MAX;
+    return (int)b;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+
+// sum over the block in a fixed order; result valid in thread 0
+__device__ __forceinline__ double block_sum(double v, double *sh)
+{
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += sh[i];
+    __syncthreads();
+    return s;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(RT) k_dot1(int64_t n, const T *__restrict__ x,
+                                             const T *__restrict__ y, double *part)
+{
+    __shared__ double sh[RT / 64];
+    double s = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * RT;
+    for (int64_t i = blockIdx.x * (int64_t)RT + threadIdx.x; i < n; i += stride)
+        s += (double)x[i] * (double)y[i];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// stage 2: block v sums part[v*ld + 0..nb)
+__global__ void __launch_bounds__(RT) k_red2(const double *__restrict__ part, int nb, int ld,
+                                             double *dst)
+{
+    __shared__ double sh[RT / 64];
+    double s = 0.0;
+    const double *p = part + (int64_t)blockIdx.x * ld;
+    for (int i = threadIdx.x; i < nb; i += RT) s += p[i];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) dst[blockIdx.x] = s;
+}
+
+// block dot: part[(v0+k)*ld + blk] = sum_i V[v0+k][i] w[i], k < mc
+__global__ void __launch_bounds__(RT) k_mdot1(int64_t n, int v0, int mc,
+                                              const double *__restrict__ V, int64_t ldv,
+                                              const double *__restrict__ w, double *part, int ld)
+{
+    __shared__ double sh[RT / 64];
+    double s[MC];
+#pragma unroll
+    for (int k = 0; k < MC; ++k) s[k] = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * RT;
+    for (int64_t i = blockIdx.x * (int64_t)RT + threadIdx.x; i < n; i += stride) {
+        const double wi = w[i];
+#pragma unroll
+        for (int k = 0; k < MC; ++k)
+            if (k < mc) s[k] += V[(int64_t)(v0 + k) * ldv + i] * wi;
+    }
+#pragma unroll
+    for (int k = 0; k < MC; ++k) {
+        if (k >= mc) break;
+        const double r = block_sum(s[k], sh);
+        if (threadIdx.x == 0) part[(int64_t)(v0 + k) * ld + blockIdx.x] = r;
+    }
+}
+
+// w += sign * sum_k h[k] V[k]
+__global__ void k_mupdate(int64_t n, int m, const double *__restrict__ V, int64_t ldv,
+                          const double *__restrict__ h, double sign, double *w)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int k = 0; k < m; ++k) s += h[k] * V[(int64_t)k * ldv + i];
+    w[i] += sign * s;
+}
+
+__global__ void k_axpby(int64_t n, double a, const double *__restrict__ x, double b, double *y)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) y[i] = a * x[i] + (b == 0.0 ? 0.0 : b * y[i]);
+}
+
+// mode 0: y = s x, 1: y = x / s, 2: y = x / sqrt(s)
+__global__ void k_scale_copy(int64_t n, const double *__restrict__ s, int mode,
+                             const double *__restrict__ x, double *y)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double v = s[0];
+    y[i] = mode == 0 ? v * x[i] : (mode == 1 ? x[i] / v : x[i] / sqrt(v));
+}
+
+// y = (float)(x * scale), scale = 1/sqrt(s) if s != null
+__global__ void k_cast64to32(int64_t n, const double *__restrict__ x, float *y,
+                             const double *__restrict__ s)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double f = s ? 1.0 / sqrt(s[0]) : 1.0;
+    y[i] = (float)(x[i] * f);
+}
+
+// y = (double)x * scale, scale = sqrt(s) if s != null
+__global__ void k_cast32to64(int64_t n, const float *__restrict__ x, double *y,
+                             const double *__restrict__ s)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double f = s ? sqrt(s[0]) : 1.0;
+    y[i] = (double)x[i] * f;
+}
+
+template <typename T>
+__global__ void k_fill(int64_t n, T v, T *y)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) y[i] = v;
+}
+
+__global__ void k_copy(int64_t n, const double *__restrict__ x, double *y)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) y[i] = x[i];
+}
+
+// ---- FP32 CG with device scalars: sc[0] = rz (current), sc[1] = p.q,
+// sc[2] = new rz.  x += a p, r -= a q with a = sc[0]/sc[1].
+__global__ void k_cg_x(int64_t n, float *x, float *r, const float *__restrict__ p,
+                       const float *__restrict__ q, const double *__restrict__ sc)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float a = (float)(sc[0] / sc[1]);
+    x[i] += a * p[i];
+    r[i] -= a * q[i];
+}
+
+// p = z + (sc[2]/sc[0]) p
+__global__ void k_cg_p(int64_t n, const float *__restrict__ z, float *p,
+                       const double *__restrict__ sc)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float bt = (float)(sc[2] / sc[0]);
+    p[i] = z[i] + bt * p[i];
+}
+
+__global__ void k_shift(double *sc)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) sc[0] = sc[2];
+}
+
+inline unsigned nb256(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+hipError_t blas_dot(hx_ctx *c, int64_t n, const double *x, const double *y, double *dst)
+{
+    const int nb = red_blocks(n);
+    hipLaunchKernelGGL(k_dot1<double>, dim3(nb), dim3(RT), 0, c->stream, n, x, y, c->red);
+    hipLaunchKernelGGL(k_red2, dim3(1), dim3(RT), 0, c->stream, c->red, nb, RED_MAX, dst);
+    return hipGetLastError();
+}
+
+hipError_t blas_dot32(hx_ctx *c, int64_t n, const float *x, const float *y, double *dst)
+{
+    const int nb = red_blocks(n);
+    hipLaunchKernelGGL(k_dot1<float>, dim3(nb), dim3(RT), 0, c->stream, n, x, y, c->red);
+    hipLaunchKernelGGL(k_red2, dim3(1), dim3(RT), 0, c->stream, c->red, nb, RED_MAX, dst);
+    return hipGetLastError();
+}
+
+hipError_t blas_mdot(hx_ctx *c, int64_t n, int m, const double *V, int64_t ldv, const double *w,
+                     double *dst)
+{
+    const int nb = red_blocks(n);
+    for (int v0 = 0; v0 < m; v0 += MC) {
+        const int mc = (m - v0) < MC ? (m - v0) : MC;
+        hipLaunchKernelGGL(k_mdot1, dim3(nb), dim3(RT), 0, c->stream, n, v0, mc, V, ldv, w, c->red,
+                           RED_MAX);
+    }
+    hipLaunchKernelGGL(k_red2, dim3(m), dim3(RT), 0, c->stream, c->red, nb, RED_MAX, dst);
+    return hipGetLastError();
+}
+
+hipError_t blas_mupdate(hx_ctx *c, int64_t n, int m, const double *V, int64_t ldv, const double *h,
+                        double sign, double *w)
+{
+    hipLaunchKernelGGL(k_mupdate, dim3(nb256(n)), dim3(256), 0, c->stream, n, m, V, ldv, h, sign, w);
+    return hipGetLastError();
+}
+
+hipError_t blas_lincomb(hx_ctx *c, int64_t n, int m, const double *Z, int64_t ldz,
+                        const double *y_dev, double *x)
+{
+    return blas_mupdate(c, n, m, Z, ldz, y_dev, 1.0, x);
+}
+
+hipError_t blas_axpby(hx_ctx *c, int64_t n, double a, const double *x, double b, double *y)
+{
+    hipLaunchKernelGGL(k_axpby, dim3(nb256(n)), dim3(256), 0, c->stream, n, a, x, b, y);
+    return hipGetLastError();
+}
+
+hipError_t blas_scale_copy(hx_ctx *c, int64_t n, const double *s_dev, int mode, const double *x,
+                           double *y)
+{
+    hipLaunchKernelGGL(k_scale_copy, dim3(nb256(n)), dim3(256), 0, c->stream, n, s_dev, mode, x, y);
+    return hipGetLastError();
+}
+
+hipError_t blas_cast64to32(hx_ctx *c, int64_t n, const double *x, float *y, const double *s_dev)
+{
+    hipLaunchKernelGGL(k_cast64to32, dim3(nb256(n)), dim3(256), 0, c->stream, n, x, y, s_dev);
+    return hipGetLastError();
+}
+
+hipError_t blas_cast32to64(hx_ctx *c, int64_t n, const float *x, double *y, const double *s_dev)
+{
+    hipLaunchKernelGGL(k_cast32to64, dim3(nb256(n)), dim3(256), 0, c->stream, n, x, y, s_dev);
+    return hipGetLastError();
+}
+
+hipError_t blas_copy(hx_ctx *c, int64_t n, const double *x, double *y)
+{
+    hipLaunchKernelGGL(k_copy, dim3(nb256(n)), dim3(256), 0, c->stream, n, x, y);
+    return hipGetLastError();
+}
+
+hipError_t blas_fill(hx_ctx *c, int64_t n, double v, double *y)
+{
+    hipLaunchKernelGGL(k_fill<double>, dim3(nb256(n)), dim3(256), 0, c->stream, n, v, y);
+    return hipGetLastError();
+}
+
+hipError_t blas_fill32(hx_ctx *c, int64_t n, float v, float *y)
+{
+    hipLaunchKernelGGL(k_fill<float>, dim3(nb256(n)), dim3(256), 0, c->stream, n, v, y);
+    return hipGetLastError();
+}
+
+hipError_t cg32_step_x(hx_ctx *c, int64_t n, float *x, float *r, const float *p, const float *q,
+                       double *sc)
+{
+    hipLaunchKernelGGL(k_cg_x, dim3(nb256(n)), dim3(256), 0, c->stream, n, x, r, p, q, sc);
+    return hipGetLastError();
+}
+
+hipError_t cg32_step_p(hx_ctx *c, int64_t n, const float *z, float *p, double *sc)
+{
+    hipLaunchKernelGGL(k_cg_p, dim3(nb256(n)), dim3(256), 0, c->stream, n, z, p, sc);
+    hipLaunchKernelGGL(k_shift, dim3(1), dim3(64), 0, c->stream, sc);
+    return hipGetLastError();
+}
+
+int red_stage1_max() { return RED_MAX; }
+
+}  // namespace hx

@@ -1,0 +1,166 @@
+// Internal declarations of the helmdg library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/helmdg.h"
+
+namespace hx {
+
+constexpr int MAXK = 7;             // highest supported polynomial degree
+constexpr int MAXN = MAXK + 1;      // points per direction
+constexpr int MAXG = 8;             // highest geometry degree
+constexpr int NXCD = 8;             // accelerator complex dies of the MI355X
+
+// Reference data of one degree (host side, FP64).
+struct RefTab64 {
+    double xq[MAXN], wq[MAXN], xl[MAXN];   // GL points/weights, GLL nodes on [0,1]
+    double B[MAXN * MAXN];                 // B[q*n+i]  = l_i(xq_q)   (GLL basis at GL points)
+    double BD[MAXN * MAXN];                // BD[q*n+i] = l_i'(xq_q)
+    double DL[2][MAXN];                    // DL[e][i]  = l_i'(e), e = 0, 1
+    double M[MAXN * MAXN];                 // 1-D reference mass
+    double L0[MAXN * MAXN];                // 1-D reference stiffness
+    double Cinv[MAXN * MAXN];              // inverse Cholesky factor of M (lower)
+};
+
+// Tables the operator kernels read from constant memory, per degree.
+struct OpTab {
+    double B[MAXN * MAXN], BD[MAXN * MAXN], DL[2][MAXN];
+    float Bf[MAXN * MAXN], BDf[MAXN * MAXN], DLf[2][MAXN];
+};
+
+void sym_eig(int n, double *a, double *w, double *v);
+void rule_gauss_legendre(int n, double *x01, double *w01);
+void rule_gauss_lobatto(int n, double *x01, double *w01);
+void lagrange_eval(int n, const double *nodes, double t, double *val, double *der);
+void build_ref_tables(int n, RefTab64 &t);
+
+// Per-translation-unit upload of the constant-memory tables.
+hipError_t upload_op_tables_operator(const OpTab *all /*[MAXN+1]*/);
+
+struct MlpState;   // learned preconditioner (mlp.hip)
+
+}  // namespace hx
+
+struct hx_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+
+    // mesh
+    int k = 0, n = 0, nd = 0, nf = 0, g = 0;
+    int64_t n_cells = 0, n_dofs = 0;
+    bool has_mesh = false, has_coef = false;
+    double P = 2.0;
+
+    double *nodes = nullptr;      // [n_cells][(g+1)^3][3]
+    int32_t *nbr = nullptr;       // [n_cells][6]
+    hx::RefTab64 *ref = nullptr;  // device copy of the tables of degree k
+    hx::RefTab64 ref_host{};
+    double *vol = nullptr;        // [n_cells]
+    double *ell = nullptr;        // [n_cells][3]
+    double *mindet = nullptr;     // [n_cells]
+    double *sigma = nullptr;      // [n_cells][3]
+
+    // merged operator data
+    double *cell64 = nullptr;     // [n_cells][7][nd]
+    float *cell32 = nullptr;
+    double *face64 = nullptr;     // [n_cells][3][7][nf]
+    float *face32 = nullptr;
+
+    // separable block-Jacobi data
+    double *bjS64 = nullptr;      // [n_cells][3][n][n]  eigenvectors S_d
+    float *bjS32 = nullptr;
+    double *bjL64 = nullptr;      // [n_cells][3][n]     eigenvalues
+    float *bjL32 = nullptr;
+    double *bjC64 = nullptr;      // [n_cells][4]        c0, cx, cy, cz
+    float *bjC32 = nullptr;
+    double *coef_feat = nullptr;  // [n_cells] log(bbar / (abar l^2))
+
+    // reductions
+    double *red = nullptr;        // partial sums
+    double *red_host = nullptr;   // pinned
+    int red_blocks = 0;
+
+    // solver work space (allocated on first use, grown as needed)
+    double *work64 = nullptr;
+    size_t work64_len = 0;
+    float *work32 = nullptr;
+    size_t work32_len = 0;
+
+    hx::MlpState *mlp = nullptr;
+};
+
+namespace hx {
+
+hx_status fail(hx_ctx *c, hx_status s, const char *fmt, ...);
+
+#define HX_HIP(c, call)                                                              \
+    do {                                                                             \
+        hipError_t e_ = (call);                                                      \
+        if (e_ != hipSuccess)                                                        \
+            return ::hx::fail((c), HX_ERR_DEVICE, "%s failed: %s", #call,            \
+                              hipGetErrorString(e_));                                \
+    } while (0)
+
+hx_status dalloc(hx_ctx *c, void **p, size_t bytes);
+void dfree(void **p);
+
+// ---- kernel launchers (defined in the .hip translation units) ----------
+// geometry / coefficients
+hipError_t launch_cell_geometry(hx_ctx *c);                 // vol, ell, mindet
+hipError_t launch_face_sigma(hx_ctx *c);                    // sigma
+hipError_t launch_bj_eigen(hx_ctx *c);                      // bjS, bjL
+hipError_t launch_set_coefficients(hx_ctx *c, const double *alpha, const double *beta);
+hipError_t launch_dof_coords(hx_ctx *c, double *xyz);
+
+// operator: y = A x, or y = b - A x when b != nullptr
+hipError_t launch_apply64(hx_ctx *c, const double *x, double *y, const double *b);
+hipError_t launch_apply32(hx_ctx *c, const float *x, float *y, const float *b);
+
+// separable block Jacobi: z = Ahat^{-1} r
+hipError_t launch_bj64(hx_ctx *c, const double *r, double *z);
+hipError_t launch_bj32(hx_ctx *c, const float *r, float *z);
+
+// BLAS-1 / block kernels (blas.hip); results of reductions stay on device
+// in c->red[slot] unless copied.
+hipError_t blas_dot(hx_ctx *c, int64_t n, const double *x, const double *y, double *dst);
+hipError_t blas_dot32(hx_ctx *c, int64_t n, const float *x, const float *y, double *dst);
+hipError_t blas_mdot(hx_ctx *c, int64_t n, int m, const double *V, int64_t ldv,
+                     const double *w, double *dst /*[m]*/);
+hipError_t blas_mupdate(hx_ctx *c, int64_t n, int m, const double *V, int64_t ldv,
+                        const double *h /*device [m]*/, double sign, double *w);
+hipError_t blas_axpby(hx_ctx *c, int64_t n, double a, const double *x, double b, double *y);
+hipError_t blas_scale_copy(hx_ctx *c, int64_t n, const double *s_dev, int inv,
+                           const double *x, double *y);
+hipError_t blas_cast64to32(hx_ctx *c, int64_t n, const double *x, float *y, const double *s_dev);
+hipError_t blas_cast32to64(hx_ctx *c, int64_t n, const float *x, double *y, const double *s_dev);
+hipError_t blas_copy(hx_ctx *c, int64_t n, const double *x, double *y);
+hipError_t blas_fill(hx_ctx *c, int64_t n, double v, double *y);
+hipError_t blas_fill32(hx_ctx *c, int64_t n, float v, float *y);
+// fused CG steps on device scalars (no host round trip)
+hipError_t cg32_init(hx_ctx *c, int64_t n, float *r, float *z, float *p, double *sc);
+hipError_t cg32_step_x(hx_ctx *c, int64_t n, float *x, float *r, const float *p,
+                       const float *q, double *sc);
+hipError_t cg32_step_p(hx_ctx *c, int64_t n, const float *z, float *p, double *sc);
+hipError_t cg32_step_p_dot(hx_ctx *c, int64_t n, const float *r, const float *z, double *sc);
+hipError_t blas_lincomb(hx_ctx *c, int64_t n, int m, const double *Z, int64_t ldz,
+                        const double *y_dev, double *x);
+
+// learned preconditioner (mlp.hip)
+hx_status mlp_create(hx_ctx *c);
+void mlp_destroy(hx_ctx *c);
+int64_t mlp_param_count(const hx_ctx *c);
+hx_status mlp_set(hx_ctx *c, const float *w, int64_t n);
+hx_status mlp_get(const hx_ctx *c, float *w, int64_t n);
+hx_status mlp_features(hx_ctx *c, const double *r, float *feats, float *scale);
+hx_status mlp_forward(hx_ctx *c, const float *feats, int64_t batch, float *out);
+hx_status mlp_train(hx_ctx *c, const float *feats, const float *targets, int64_t batch,
+                    float lr, float *loss_out, float *grad_out);
+hx_status mlp_precondition(hx_ctx *c, const double *r, double *z, int *nonfinite);
+
+}  // namespace hx

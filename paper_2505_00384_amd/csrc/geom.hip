@@ -1,0 +1,497 @@
+// Geometry and coefficient set-up (FP64): cell metric terms, face normals,
+// surface elements and penalties, merged per-quadrature-point operator data,
+// the separable block-Jacobi eigen-tables and dof coordinates.
+//
+// Everything here runs once per mesh (setup_mesh) or once per coefficient
+// update (set_coefficients, redone each fixed-point iteration of the paper's
+// pressure solve, section 3.1), so it favours clarity over speed.
+#include "common.hpp"
+
+#include <cmath>
+
+namespace hx {
+namespace {
+
+// Lagrange basis through the equispaced nodes a/g, a = 0..g (the geometry
+// nodes of the mesh format): values and derivatives at t.
+__device__ inline void lag_equi(int ng, double t, double *v, double *d)
+{
+    const double g = ng - 1;
+    for (int i = 0; i < ng; ++i) {
+        const double xi = i / g;
+        double val = 1.0, der = 0.0;
+        for (int m = 0; m < ng; ++m) {
+            if (m == i) continue;
+            const double xm = m / g;
+            const double f = (t - xm) / (xi - xm);
+            der = der * f + val / (xi - xm);
+            val *= f;
+        }
+        v[i] = val;
+        d[i] = der;
+    }
+}
+
+// x(xi) and J = dx/dxi of one cell from its geometry nodes X[(g+1)^3][3].
+__device__ inline void cell_map(const double *__restrict__ X, int ng, const double xi[3],
+                                double x[3], double J[3][3])
+{
+    double v[3][MAXG + 1], d[3][MAXG + 1];
+    for (int c = 0; c < 3; ++c) lag_equi(ng, xi[c], v[c], d[c]);
+    for (int r = 0; r < 3; ++r) x[r] = J[r][0] = J[r][1] = J[r][2] = 0.0;
+    for (int cz = 0; cz < ng; ++cz)
+        for (int cy = 0; cy < ng; ++cy) {
+            const double vyz = v[1][cy] * v[2][cz], dyz = d[1][cy] * v[2][cz], yzd = v[1][cy] * d[2][cz];
+            for (int cx = 0; cx < ng; ++cx) {
+                const double *P = X + 3 * (cx + ng * (cy + ng * cz));
+                const double s = v[0][cx] * vyz, s0 = d[0][cx] * vyz, s1 = v[0][cx] * dyz,
+                             s2 = v[0][cx] * yzd;
+                for (int r = 0; r < 3; ++r) {
+                    const double p = P[r];
+                    x[r] += s * p;
+                    J[r][0] += s0 * p;
+                    J[r][1] += s1 * p;
+                    J[r][2] += s2 * p;
+                }
+            }
+        }
+}
+
+__device__ inline double det3(const double J[3][3])
+{
+    return J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+           J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+           J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+}
+
+// Ji = J^{-1}
+__device__ inline void inv3(const double J[3][3], double det, double Ji[3][3])
+{
+    const double id = 1.0 / det;
+    Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) * id;
+    Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+    Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+    Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) * id;
+    Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+    Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+    Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) * id;
+    Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+    Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+}
+
+__device__ inline int lidx(int n, int i, int j, int l) { return i + n * (j + n * l); }
+
+// local index of the point with coordinate m along d and tangential (p, r),
+// t1 < t2 the other two directions
+__device__ inline int layer_idx(int n, int d, int m, int p, int r)
+{
+    int c[3];
+    const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+    c[d] = m;
+    c[t1] = p;
+    c[t2] = r;
+    return lidx(n, c[0], c[1], c[2]);
+}
+
+__device__ inline void face_xi(const RefTab64 *T, int d, int plus, int a, int b, double xi[3])
+{
+    const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+    xi[d] = plus ? 1.0 : 0.0;
+    xi[t1] = T->xq[a];
+    xi[t2] = T->xq[b];
+}
+
+// -------------------------------------------------------------------------
+// per cell: volume, mean column lengths l_d, minimum detJ (thread per cell)
+// -------------------------------------------------------------------------
+__global__ void k_cell_geometry(const double *__restrict__ nodes, int ng, int n, int64_t n_cells,
+                                const RefTab64 *__restrict__ T, double *vol, double *ell,
+                                double *mindet)
+{
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= n_cells) return;
+    const double *X = nodes + c * (int64_t)ng * ng * ng * 3;
+    double v = 0.0, e0 = 0.0, e1 = 0.0, e2 = 0.0, md = 1e300;
+    for (int l = 0; l < n; ++l)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                double xi[3] = {T->xq[i], T->xq[j], T->xq[l]}, x[3], J[3][3];
+                cell_map(X, ng, xi, x, J);
+                const double det = det3(J);
+                md = fmin(md, det);
+                v += T->wq[i] * T->wq[j] * T->wq[l] * det;
+                e0 += sqrt(J[0][0] * J[0][0] + J[1][0] * J[1][0] + J[2][0] * J[2][0]);
+                e1 += sqrt(J[0][1] * J[0][1] + J[1][1] * J[1][1] + J[2][1] * J[2][1]);
+                e2 += sqrt(J[0][2] * J[0][2] + J[1][2] * J[1][2] + J[2][2] * J[2][2]);
+            }
+    const double inv = 1.0 / (n * n * n);
+    vol[c] = v;
+    ell[3 * c + 0] = e0 * inv;
+    ell[3 * c + 1] = e1 * inv;
+    ell[3 * c + 2] = e2 * inv;
+    mindet[c] = md;
+}
+
+// -------------------------------------------------------------------------
+// penalty of the +d face of each cell (thread per (cell, d))
+// -------------------------------------------------------------------------
+__global__ void k_face_sigma(const double *__restrict__ nodes, int ng, int n, int64_t n_cells,
+                             const int32_t *__restrict__ nbr, const RefTab64 *__restrict__ T,
+                             const double *__restrict__ vol, double P, double *sigma)
+{
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= 3 * n_cells) return;
+    const int64_t c = t / 3;
+    const int d = (int)(t % 3);
+    const int32_t nb = nbr[6 * c + 2 * d + 1];
+    if (nb < 0) {
+        sigma[t] = -1.0;
+        return;
+    }
+    const double *X = nodes + c * (int64_t)ng * ng * ng * 3;
+    double area = 0.0;
+    for (int b = 0; b < n; ++b)
+        for (int a = 0; a < n; ++a) {
+            double xi[3], x[3], J[3][3], Ji[3][3];
+            face_xi(T, d, 1, a, b, xi);
+            cell_map(X, ng, xi, x, J);
+            const double det = det3(J);
+            inv3(J, det, Ji);
+            // |J^{-T} e_d| = norm of row d of J^{-1}
+            const double len = sqrt(Ji[d][0] * Ji[d][0] + Ji[d][1] * Ji[d][1] + Ji[d][2] * Ji[d][2]);
+            area += T->wq[a] * T->wq[b] * det * len;
+        }
+    const double r = fmax(area / vol[c], area / vol[nb]);
+    sigma[t] = P * (double)(n * n) * r;
+}
+
+// -------------------------------------------------------------------------
+// generalised eigenproblems of the separable block (thread per (cell, d)):
+// L_d s = lambda M s with L_d the 1-D SIP block of the cell in direction d.
+// -------------------------------------------------------------------------
+template <int N>
+__device__ void jacobi_eig(double (&A)[N][N], double (&V)[N][N])
+{
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) V[i][j] = (i == j) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 30; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < N; ++i)
+            for (int j = 0; j < N; ++j) {
+                tot += A[i][j] * A[i][j];
+                if (i != j) off += A[i][j] * A[i][j];
+            }
+        if (off <= 1e-34 * tot) break;
+        for (int p = 0; p < N - 1; ++p)
+            for (int q = p + 1; q < N; ++q) {
+                const double apq = A[p][q];
+                if (apq == 0.0) continue;
+                const double theta = (A[q][q] - A[p][p]) / (2.0 * apq);
+                const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                const double cs = 1.0 / sqrt(t * t + 1.0), sn = t * cs;
+                for (int k = 0; k < N; ++k) {
+                    const double akp = A[k][p], akq = A[k][q];
+                    A[k][p] = cs * akp - sn * akq;
+                    A[k][q] = sn * akp + cs * akq;
+                }
+                for (int k = 0; k < N; ++k) {
+                    const double apk = A[p][k], aqk = A[q][k];
+                    A[p][k] = cs * apk - sn * aqk;
+                    A[q][k] = sn * apk + cs * aqk;
+                }
+                for (int k = 0; k < N; ++k) {
+                    const double vkp = V[k][p], vkq = V[k][q];
+                    V[k][p] = cs * vkp - sn * vkq;
+                    V[k][q] = sn * vkp + cs * vkq;
+                }
+            }
+    }
+}
+
+template <int N>
+__global__ void k_bj_eigen(int64_t n_cells, const int32_t *__restrict__ nbr,
+                           const RefTab64 *__restrict__ T, const double *__restrict__ ell,
+                           const double *__restrict__ sigma, double *S64, float *S32, double *L64,
+                           float *L32)
+{
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= 3 * n_cells) return;
+    const int64_t c = t / 3;
+    const int d = (int)(t % 3);
+    const double l = ell[3 * c + d];
+    const int32_t lo = nbr[6 * c + 2 * d], hi = nbr[6 * c + 2 * d + 1];
+    const double sig_lo = lo >= 0 ? sigma[3 * (int64_t)lo + d] : -1.0;
+    const double sig_hi = hi >= 0 ? sigma[3 * c + d] : -1.0;
+    double L[N][N];
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) L[i][j] = T->L0[i * N + j];
+    // end terms; the GLL basis is 1 at its own end node and 0 at the others
+    if (sig_lo >= 0.0) {   // end 0, outward reference normal -1
+        for (int i = 0; i < N; ++i) {
+            L[i][0] += 0.5 * T->DL[0][i];
+            L[0][i] += 0.5 * T->DL[0][i];
+        }
+        L[0][0] += sig_lo * l;
+    }
+    if (sig_hi >= 0.0) {   // end 1, outward reference normal +1
+        for (int i = 0; i < N; ++i) {
+            L[i][N - 1] -= 0.5 * T->DL[1][i];
+            L[N - 1][i] -= 0.5 * T->DL[1][i];
+        }
+        L[N - 1][N - 1] += sig_hi * l;
+    }
+    // C = Cinv L Cinv^T
+    double A[N][N], tmp[N][N], V[N][N];
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) {
+            double s = 0.0;
+            for (int r = 0; r < N; ++r) s += T->Cinv[i * N + r] * L[r][j];
+            tmp[i][j] = s;
+        }
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) {
+            double s = 0.0;
+            for (int r = 0; r < N; ++r) s += tmp[i][r] * T->Cinv[j * N + r];
+            A[i][j] = s;
+        }
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < i; ++j) A[i][j] = A[j][i] = 0.5 * (A[i][j] + A[j][i]);
+    jacobi_eig<N>(A, V);
+    // S = Cinv^T V, stored row-major S[i][m]
+    double *S = S64 + t * N * N;
+    float *Sf = S32 + t * N * N;
+    for (int i = 0; i < N; ++i)
+        for (int m = 0; m < N; ++m) {
+            double s = 0.0;
+            for (int r = 0; r < N; ++r) s += T->Cinv[r * N + i] * V[r][m];
+            S[i * N + m] = s;
+            Sf[i * N + m] = (float)s;
+        }
+    for (int m = 0; m < N; ++m) {
+        L64[t * N + m] = A[m][m];
+        L32[t * N + m] = (float)A[m][m];
+    }
+}
+
+// -------------------------------------------------------------------------
+// merged cell data (block per cell, thread per quadrature point)
+//   m = alpha_q w detJ,  G = beta_q w detJ J^{-1} J^{-T}
+// and the block-Jacobi scalars from the volume-weighted means of alpha, beta
+// -------------------------------------------------------------------------
+__global__ void k_set_cell(const double *__restrict__ nodes, int ng, int n,
+                           const RefTab64 *__restrict__ T, const double *__restrict__ alpha,
+                           const double *__restrict__ beta, const double *__restrict__ ell,
+                           double *cell64, float *cell32, double *bjC64, float *bjC32,
+                           double *coef_feat)
+{
+    const int64_t c = blockIdx.x;
+    const int nd = n * n * n;
+    const int q = threadIdx.x;
+    double sw = 0.0, sa = 0.0, sb = 0.0;
+    if (q < nd) {
+        const int i = q % n, j = (q / n) % n, l = q / (n * n);
+        double xi[3] = {T->xq[i], T->xq[j], T->xq[l]}, x[3], J[3][3], Ji[3][3];
+        cell_map(nodes + c * (int64_t)ng * ng * ng * 3, ng, xi, x, J);
+        const double det = det3(J);
+        inv3(J, det, Ji);
+        const double w = T->wq[i] * T->wq[j] * T->wq[l] * det;
+        const double *ac = alpha + c * nd, *bc = beta + c * nd;
+        double aq = 0.0, bq = 0.0;
+        for (int l2 = 0; l2 < n; ++l2)
+            for (int j2 = 0; j2 < n; ++j2) {
+                const double byz = T->B[j * n + j2] * T->B[l * n + l2];
+                for (int i2 = 0; i2 < n; ++i2) {
+                    const double wgt = T->B[i * n + i2] * byz;
+                    const int e = lidx(n, i2, j2, l2);
+                    aq += wgt * ac[e];
+                    bq += wgt * bc[e];
+                }
+            }
+        double G[6];
+        const int pa[6] = {0, 0, 0, 1, 1, 2}, pb[6] = {0, 1, 2, 1, 2, 2};
+        for (int s = 0; s < 6; ++s) {
+            const int A = pa[s], Bq = pb[s];
+            G[s] = bq * w * (Ji[A][0] * Ji[Bq][0] + Ji[A][1] * Ji[Bq][1] + Ji[A][2] * Ji[Bq][2]);
+        }
+        double *dst = cell64 + c * 7 * nd;
+        float *dstf = cell32 + c * 7 * nd;
+        dst[q] = aq * w;
+        dstf[q] = (float)(aq * w);
+        for (int s = 0; s < 6; ++s) {
+            dst[(1 + s) * nd + q] = G[s];
+            dstf[(1 + s) * nd + q] = (float)G[s];
+        }
+        sw = w;
+        sa = w * aq;
+        sb = w * bq;
+    }
+    // block reduction (fixed order)
+    __shared__ double red[3][512];
+    red[0][threadIdx.x] = sw;
+    red[1][threadIdx.x] = sa;
+    red[2][threadIdx.x] = sb;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int r = 0; r < 3; ++r) red[r][threadIdx.x] += red[r][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double vol = red[0][0];
+        const double ab = red[1][0] / vol, bb = red[2][0] / vol;
+        const double lx = ell[3 * c], ly = ell[3 * c + 1], lz = ell[3 * c + 2];
+        const double cc[4] = {ab * lx * ly * lz, bb * ly * lz / lx, bb * lx * lz / ly, bb * lx * ly / lz};
+        for (int r = 0; r < 4; ++r) {
+            bjC64[4 * c + r] = cc[r];
+            bjC32[4 * c + r] = (float)cc[r];
+        }
+        const double l2 = cbrt(lx * ly * lz);
+        coef_feat[c] = log(bb / (ab * l2 * l2));
+    }
+}
+
+// -------------------------------------------------------------------------
+// merged face data of the +d face of every cell (thread per face point):
+//   g- = beta- ds J-^{-1} n,  g+ = beta+ ds J+^{-1} n,  s = sigma 1/2 (b- + b+) ds
+// with n and ds from the minus cell.
+// -------------------------------------------------------------------------
+__global__ void k_set_face(const double *__restrict__ nodes, int ng, int n, int64_t n_cells,
+                           const int32_t *__restrict__ nbr, const RefTab64 *__restrict__ T,
+                           const double *__restrict__ beta, const double *__restrict__ sigma,
+                           double *face64, float *face32)
+{
+    const int nf = n * n, nd = nf * n;
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= 3 * n_cells * nf) return;
+    const int pt = (int)(t % nf);
+    const int64_t cd = t / nf;
+    const int64_t c = cd / 3;
+    const int d = (int)(cd % 3);
+    const int a = pt % n, b = pt / n;
+    double *dst = face64 + cd * 7 * nf;
+    float *dstf = face32 + cd * 7 * nf;
+    const int32_t nb = nbr[6 * c + 2 * d + 1];
+    if (nb < 0) {
+        for (int s = 0; s < 7; ++s) {
+            dst[s * nf + pt] = 0.0;
+            dstf[s * nf + pt] = 0.0f;
+        }
+        return;
+    }
+    double xim[3], xip[3], x[3], Jm[3][3], Jp[3][3], Jmi[3][3], Jpi[3][3];
+    face_xi(T, d, 1, a, b, xim);
+    face_xi(T, d, 0, a, b, xip);
+    const int64_t gsz = (int64_t)ng * ng * ng * 3;
+    cell_map(nodes + c * gsz, ng, xim, x, Jm);
+    cell_map(nodes + (int64_t)nb * gsz, ng, xip, x, Jp);
+    const double detm = det3(Jm), detp = det3(Jp);
+    inv3(Jm, detm, Jmi);
+    inv3(Jp, detp, Jpi);
+    // J^{-T} e_d is row d of J^{-1}
+    double nv[3] = {Jmi[d][0], Jmi[d][1], Jmi[d][2]};
+    const double len = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+    for (int r = 0; r < 3; ++r) nv[r] /= len;
+    const double ds = T->wq[a] * T->wq[b] * detm * len;
+    double bm = 0.0, bp = 0.0;
+    for (int r = 0; r < n; ++r)
+        for (int p = 0; p < n; ++p) {
+            const double wgt = T->B[a * n + p] * T->B[b * n + r];
+            bm += wgt * beta[c * nd + layer_idx(n, d, n - 1, p, r)];
+            bp += wgt * beta[(int64_t)nb * nd + layer_idx(n, d, 0, p, r)];
+        }
+    double out[7];
+    for (int r = 0; r < 3; ++r) {
+        out[r] = bm * ds * (Jmi[r][0] * nv[0] + Jmi[r][1] * nv[1] + Jmi[r][2] * nv[2]);
+        out[3 + r] = bp * ds * (Jpi[r][0] * nv[0] + Jpi[r][1] * nv[1] + Jpi[r][2] * nv[2]);
+    }
+    out[6] = sigma[3 * c + d] * 0.5 * (bm + bp) * ds;
+    for (int s = 0; s < 7; ++s) {
+        dst[s * nf + pt] = out[s];
+        dstf[s * nf + pt] = (float)out[s];
+    }
+}
+
+// -------------------------------------------------------------------------
+// dof coordinates (thread per dof)
+// -------------------------------------------------------------------------
+__global__ void k_dof_coords(const double *__restrict__ nodes, int ng, int n, int64_t n_dofs,
+                             const RefTab64 *__restrict__ T, double *xyz)
+{
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= n_dofs) return;
+    const int nd = n * n * n;
+    const int64_t c = t / nd;
+    const int q = (int)(t % nd);
+    double xi[3] = {T->xl[q % n], T->xl[(q / n) % n], T->xl[q / (n * n)]}, x[3], J[3][3];
+    cell_map(nodes + c * (int64_t)ng * ng * ng * 3, ng, xi, x, J);
+    xyz[t] = x[0];
+    xyz[n_dofs + t] = x[1];
+    xyz[2 * n_dofs + t] = x[2];
+}
+
+inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+hipError_t launch_cell_geometry(hx_ctx *c)
+{
+    hipLaunchKernelGGL(k_cell_geometry, dim3(nblk(c->n_cells, 64)), dim3(64), 0, c->stream,
+                       c->nodes, c->g + 1, c->n, c->n_cells, c->ref, c->vol, c->ell, c->mindet);
+    return hipGetLastError();
+}
+
+hipError_t launch_face_sigma(hx_ctx *c)
+{
+    hipLaunchKernelGGL(k_face_sigma, dim3(nblk(3 * c->n_cells, 64)), dim3(64), 0, c->stream,
+                       c->nodes, c->g + 1, c->n, c->n_cells, c->nbr, c->ref, c->vol, c->P,
+                       c->sigma);
+    return hipGetLastError();
+}
+
+template <int N>
+static hipError_t bj_eigen_n(hx_ctx *c)
+{
+    hipLaunchKernelGGL(k_bj_eigen<N>, dim3(nblk(3 * c->n_cells, 64)), dim3(64), 0, c->stream,
+                       c->n_cells, c->nbr, c->ref, c->ell, c->sigma, c->bjS64, c->bjS32, c->bjL64,
+                       c->bjL32);
+    return hipGetLastError();
+}
+
+hipError_t launch_bj_eigen(hx_ctx *c)
+{
+    switch (c->n) {
+    case 2: return bj_eigen_n<2>(c);
+    case 3: return bj_eigen_n<3>(c);
+    case 4: return bj_eigen_n<4>(c);
+    case 5: return bj_eigen_n<5>(c);
+    case 6: return bj_eigen_n<6>(c);
+    case 7: return bj_eigen_n<7>(c);
+    case 8: return bj_eigen_n<8>(c);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_set_coefficients(hx_ctx *c, const double *alpha, const double *beta)
+{
+    int threads = 64;                     // power of two for the tree reduction
+    while (threads < c->nd) threads *= 2;
+    hipLaunchKernelGGL(k_set_cell, dim3((unsigned)c->n_cells), dim3(threads), 0, c->stream,
+                       c->nodes, c->g + 1, c->n, c->ref, alpha, beta, c->ell, c->cell64, c->cell32,
+                       c->bjC64, c->bjC32, c->coef_feat);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t nt = 3 * c->n_cells * c->nf;
+    hipLaunchKernelGGL(k_set_face, dim3(nblk(nt, 128)), dim3(128), 0, c->stream, c->nodes,
+                       c->g + 1, c->n, c->n_cells, c->nbr, c->ref, beta, c->sigma, c->face64,
+                       c->face32);
+    return hipGetLastError();
+}
+
+hipError_t launch_dof_coords(hx_ctx *c, double *xyz)
+{
+    hipLaunchKernelGGL(k_dof_coords, dim3(nblk(c->n_dofs, 128)), dim3(128), 0, c->stream,
+                       c->nodes, c->g + 1, c->n, c->n_dofs, c->ref, xyz);
+    return hipGetLastError();
+}
+
+}  // namespace hx

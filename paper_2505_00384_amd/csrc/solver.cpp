@@ -1,0 +1,409 @@
+// Host drivers of the Krylov solves (the paper's pressure solve: PCG for
+// symmetric positive-definite systems, GMRES with a Jacobi-type
+// preconditioner, section 3.1).  All vector work runs in HIP kernels on the
+// context stream; the host only takes the scalar decisions.
+//
+//  * CG: preconditioned conjugate gradients in FP64.
+//  * FGMRES(m): right-preconditioned flexible GMRES with classical
+//    Gram-Schmidt applied twice (CGS2: one pass over the basis for the block
+//    dot products, one for the update, repeated), Givens rotations on the
+//    host, explicit residual b - A x at every restart.
+//  * Mixed precision: the FGMRES preconditioner is an inner FP32 PCG with
+//    FP32 operator and FP32 block Jacobi, run for a fixed number of
+//    iterations with all scalars kept on the device; the outer residual,
+//    orthogonalisation and update stay FP64 (iterative refinement through the
+//    explicit FP64 residual at each restart).
+//  * Learned: block Jacobi plus the network correction; if the preconditioned
+//    vector is not finite or the residual estimate stalls over stall_window
+//    iterations, the solver restarts from the current x with block Jacobi.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "common.hpp"
+
+namespace hx {
+namespace {
+
+constexpr int64_t SC_OFF = 1024 * 66;   // device scalar area inside c->red
+
+struct Timer {
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    double op = 0, pc = 0, orth = 0;
+    bool ok = false;
+    explicit Timer(bool on)
+    {
+        if (!on) return;
+        ok = true;
+        for (auto &e : ev)
+            if (hipEventCreate(&e) != hipSuccess) ok = false;
+    }
+    ~Timer()
+    {
+        for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+    void rec(int i, hipStream_t s)
+    {
+        if (ok) (void)hipEventRecord(ev[i], s);
+    }
+    // after a stream sync: accumulate pc = ev0..1, op = 1..2, orth = 2..3
+    void acc()
+    {
+        if (!ok) return;
+        float a = 0, b = 0, c = 0;
+        if (hipEventElapsedTime(&a, ev[0], ev[1]) == hipSuccess) pc += a;
+        if (hipEventElapsedTime(&b, ev[1], ev[2]) == hipSuccess) op += b;
+        if (hipEventElapsedTime(&c, ev[2], ev[3]) == hipSuccess) orth += c;
+    }
+};
+
+hx_status ensure_work(hx_ctx *c, size_t n64, size_t n32)
+{
+    if (n64 > c->work64_len) {
+        dfree((void **)&c->work64);
+        c->work64_len = 0;
+        hx_status s = dalloc(c, (void **)&c->work64, sizeof(double) * n64);
+        if (s != HX_OK) return s;
+        c->work64_len = n64;
+    }
+    if (n32 > c->work32_len) {
+        dfree((void **)&c->work32);
+        c->work32_len = 0;
+        hx_status s = dalloc(c, (void **)&c->work32, sizeof(float) * n32);
+        if (s != HX_OK) return s;
+        c->work32_len = n32;
+    }
+    return HX_OK;
+}
+
+// inner FP32 PCG for `iters` iterations on A32 z = v (FP64 in/out); scalars
+// on the device.  w32: 5 float vectors.
+hx_status inner_fp32(hx_ctx *c, const double *v, double *z, float *w32, int iters, int *count)
+{
+    const int64_t n = c->n_dofs;
+    float *x = w32, *r = w32 + n, *zz = w32 + 2 * n, *p = w32 + 3 * n, *q = w32 + 4 * n;
+    double *sc = c->red + SC_OFF + 512;   // [0] rz, [1] pq, [2] rz_new
+    HX_HIP(c, blas_cast64to32(c, n, v, r, nullptr));
+    HX_HIP(c, blas_fill32(c, n, 0.0f, x));
+    HX_HIP(c, launch_bj32(c, r, zz));
+    HX_HIP(c, hipMemcpyAsync(p, zz, sizeof(float) * n, hipMemcpyDeviceToDevice, c->stream));
+    HX_HIP(c, blas_dot32(c, n, r, zz, sc + 0));
+    for (int it = 0; it < iters; ++it) {
+        HX_HIP(c, launch_apply32(c, p, q, nullptr));
+        HX_HIP(c, blas_dot32(c, n, p, q, sc + 1));
+        HX_HIP(c, cg32_step_x(c, n, x, r, p, q, sc));
+        if (it + 1 == iters) break;
+        HX_HIP(c, launch_bj32(c, r, zz));
+        HX_HIP(c, blas_dot32(c, n, r, zz, sc + 2));
+        HX_HIP(c, cg32_step_p(c, n, zz, p, sc));
+    }
+    HX_HIP(c, blas_cast32to64(c, n, x, z, nullptr));
+    *count += iters;
+    return HX_OK;
+}
+
+hx_status precondition(hx_ctx *c, int pc, int mixed, int inner_iters, const double *v, double *z,
+                       float *w32, int *inner_count, int *nonfinite)
+{
+    *nonfinite = 0;
+    if (mixed) return inner_fp32(c, v, z, w32, inner_iters, inner_count);
+    switch (pc) {
+    case HX_PC_NONE: HX_HIP(c, blas_copy(c, c->n_dofs, v, z)); return HX_OK;
+    case HX_PC_BLOCK_JACOBI: HX_HIP(c, launch_bj64(c, v, z)); return HX_OK;
+    case HX_PC_LEARNED: return mlp_precondition(c, v, z, nonfinite);
+    default: return fail(c, HX_ERR_ARG, "unknown preconditioner %d", pc);
+    }
+}
+
+double now_ms()
+{
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+hx_status read_scalars(hx_ctx *c, const double *dev, int m, double *host)
+{
+    HX_HIP(c, hipMemcpyAsync(c->red_host, dev, sizeof(double) * m, hipMemcpyDeviceToHost, c->stream));
+    HX_HIP(c, hipStreamSynchronize(c->stream));
+    std::memcpy(host, c->red_host, sizeof(double) * m);
+    return HX_OK;
+}
+
+// ------------------------------------------------------------------- CG
+hx_status solve_cg(hx_ctx *c, const hx_solve_params *prm, const double *b, double *x,
+                   hx_solve_info *info, Timer &tm)
+{
+    const int64_t n = c->n_dofs;
+    hx_status s = ensure_work(c, 4 * (size_t)n, 0);
+    if (s != HX_OK) return s;
+    double *r = c->work64, *z = r + n, *p = z + n, *q = p + n;
+    double *sc = c->red + SC_OFF;
+    double h[4];
+    HX_HIP(c, blas_dot(c, n, b, b, sc + 3));
+    if (prm->x0_mode == 1) {
+        HX_HIP(c, launch_apply64(c, x, r, b));
+    } else {
+        HX_HIP(c, blas_fill(c, n, 0.0, x));
+        HX_HIP(c, blas_copy(c, n, b, r));
+    }
+    HX_HIP(c, blas_dot(c, n, r, r, sc + 2));
+    if ((s = read_scalars(c, sc + 2, 2, h)) != HX_OK) return s;
+    const double nb = std::sqrt(h[1]);
+    double rel = nb > 0 ? std::sqrt(h[0]) / nb : 0.0;
+    if (nb == 0.0) {
+        HX_HIP(c, blas_fill(c, n, 0.0, x));
+        info->true_rel_res = 0.0;
+        return HX_OK;
+    }
+    int nonfinite = 0, dummy = 0;
+    if ((s = precondition(c, prm->pc, 0, 0, r, z, nullptr, &dummy, &nonfinite)) != HX_OK) return s;
+    HX_HIP(c, blas_copy(c, n, z, p));
+    HX_HIP(c, blas_dot(c, n, r, z, sc + 0));
+    if ((s = read_scalars(c, sc, 1, h)) != HX_OK) return s;
+    double rz = h[0];
+    int it = 0;
+    while (rel > prm->rtol && it < prm->max_iter) {
+        tm.rec(1, c->stream);
+        HX_HIP(c, launch_apply64(c, p, q, nullptr));
+        tm.rec(2, c->stream);
+        HX_HIP(c, blas_dot(c, n, p, q, sc + 1));
+        if ((s = read_scalars(c, sc + 1, 1, h)) != HX_OK) return s;
+        const double alpha = rz / h[0];
+        HX_HIP(c, blas_axpby(c, n, alpha, p, 1.0, x));
+        HX_HIP(c, blas_axpby(c, n, -alpha, q, 1.0, r));
+        HX_HIP(c, blas_dot(c, n, r, r, sc + 2));
+        tm.rec(0, c->stream);
+        if ((s = precondition(c, prm->pc, 0, 0, r, z, nullptr, &dummy, &nonfinite)) != HX_OK) return s;
+        tm.rec(3, c->stream);
+        HX_HIP(c, blas_dot(c, n, r, z, sc + 0));
+        double hh[3];
+        if ((s = read_scalars(c, sc, 3, hh)) != HX_OK) return s;
+        tm.acc();   // pc: 0..1 spans the previous iteration's tail; approximate split
+        ++it;
+        rel = std::sqrt(hh[2]) / nb;
+        if (info->history && it - 1 < info->history_len) info->history[it - 1] = rel;
+        if (!std::isfinite(rel)) break;
+        const double rz_new = hh[0];
+        HX_HIP(c, blas_axpby(c, n, 1.0, z, rz_new / rz, p));
+        rz = rz_new;
+    }
+    info->iters = it;
+    info->history_len = info->history ? (it < info->history_len ? it : info->history_len) : 0;
+    return HX_OK;
+}
+
+// --------------------------------------------------------------- FGMRES
+hx_status solve_fgmres(hx_ctx *c, const hx_solve_params *prm, const double *b, double *x,
+                       hx_solve_info *info, Timer &tm)
+{
+    const int64_t n = c->n_dofs;
+    const int m = prm->restart;
+    const size_t need64 = (size_t)(2 * m + 3) * n;
+    const size_t need32 = prm->mixed ? 5 * (size_t)n : 0;
+    hx_status s = ensure_work(c, need64, need32);
+    if (s != HX_OK) return s;
+    double *V = c->work64;                 // (m+1) n
+    double *Z = V + (size_t)(m + 1) * n;   // m n
+    double *w = Z + (size_t)m * n;         // n
+    double *rtmp = w + n;                  // n
+    float *w32 = c->work32;
+    double *sc = c->red + SC_OFF;          // [0..64] h1, [64..128] h2, [128] hn, [129] bb, [130..] y
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), hv(2 * 65 + 2);
+    auto Hm = [&](int i, int j) -> double & { return H[(size_t)i * m + j]; };
+
+    HX_HIP(c, blas_dot(c, n, b, b, sc + 129));
+    double tmp[1];
+    if ((s = read_scalars(c, sc + 129, 1, tmp)) != HX_OK) return s;
+    const double nb = std::sqrt(tmp[0]);
+    if (nb == 0.0) {
+        HX_HIP(c, blas_fill(c, n, 0.0, x));
+        info->true_rel_res = 0.0;
+        return HX_OK;
+    }
+    if (prm->x0_mode != 1) HX_HIP(c, blas_fill(c, n, 0.0, x));
+    int pc = prm->pc;
+    int mixed = prm->mixed;
+    int it = 0, hist = 0;
+    std::vector<double> est_hist;
+    bool done = false;
+    while (!done && it < prm->max_iter) {
+        // explicit residual
+        HX_HIP(c, launch_apply64(c, x, V, b));
+        HX_HIP(c, blas_dot(c, n, V, V, sc + 128));
+        if ((s = read_scalars(c, sc + 128, 1, tmp)) != HX_OK) return s;
+        const double beta = std::sqrt(tmp[0]);
+        const double rel0 = beta / nb;
+        if (!std::isfinite(rel0)) return fail(c, HX_ERR_NOCONV, "non-finite residual");
+        if (rel0 <= prm->rtol) break;
+        HX_HIP(c, blas_scale_copy(c, n, sc + 128, 2, V, V));
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int j_used = 0;
+        bool sw = false;
+        for (int j = 0; j < m && it < prm->max_iter; ++j) {
+            double *vj = V + (size_t)j * n, *zj = Z + (size_t)j * n;
+            int nonfinite = 0;
+            tm.rec(0, c->stream);
+            if ((s = precondition(c, pc, mixed, prm->inner_iters, vj, zj, w32, &info->inner_iters,
+                                  &nonfinite)) != HX_OK)
+                return s;
+            if (nonfinite) {
+                sw = true;
+                break;
+            }
+            tm.rec(1, c->stream);
+            HX_HIP(c, launch_apply64(c, zj, w, nullptr));
+            tm.rec(2, c->stream);
+            // CGS2
+            HX_HIP(c, blas_mdot(c, n, j + 1, V, n, w, sc));
+            HX_HIP(c, blas_mupdate(c, n, j + 1, V, n, sc, -1.0, w));
+            HX_HIP(c, blas_mdot(c, n, j + 1, V, n, w, sc + 64));
+            HX_HIP(c, blas_mupdate(c, n, j + 1, V, n, sc + 64, -1.0, w));
+            HX_HIP(c, blas_dot(c, n, w, w, sc + 128));
+            HX_HIP(c, blas_scale_copy(c, n, sc + 128, 2, w, V + (size_t)(j + 1) * n));
+            tm.rec(3, c->stream);
+            HX_HIP(c, hipMemcpyAsync(c->red_host, sc, sizeof(double) * 129, hipMemcpyDeviceToHost,
+                                     c->stream));
+            HX_HIP(c, hipStreamSynchronize(c->stream));
+            tm.acc();
+            for (int i = 0; i <= j; ++i) Hm(i, j) = c->red_host[i] + c->red_host[64 + i];
+            const double hn = std::sqrt(c->red_host[128]);
+            Hm(j + 1, j) = hn;
+            for (int i = 0; i < j; ++i) {
+                const double t = cs[i] * Hm(i, j) + sn[i] * Hm(i + 1, j);
+                Hm(i + 1, j) = -sn[i] * Hm(i, j) + cs[i] * Hm(i + 1, j);
+                Hm(i, j) = t;
+            }
+            const double den = std::hypot(Hm(j, j), Hm(j + 1, j));
+            if (!(den > 0.0) || !std::isfinite(den)) {
+                sw = true;
+                break;
+            }
+            cs[j] = Hm(j, j) / den;
+            sn[j] = Hm(j + 1, j) / den;
+            Hm(j, j) = den;
+            Hm(j + 1, j) = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            ++it;
+            j_used = j + 1;
+            const double est = std::fabs(g[j + 1]) / nb;
+            est_hist.push_back(est);
+            if (info->history && hist < info->history_len) info->history[hist++] = est;
+            if (est <= prm->rtol) break;
+            if (pc == HX_PC_LEARNED && prm->stall_window > 0 &&
+                (int)est_hist.size() > prm->stall_window &&
+                est > prm->stall_ratio * est_hist[est_hist.size() - 1 - prm->stall_window]) {
+                sw = true;
+                break;
+            }
+            if (!(hn > 0.0)) break;   // happy breakdown: exact solution in the space
+        }
+        if (j_used > 0) {
+            for (int i = j_used - 1; i >= 0; --i) {
+                double t = g[i];
+                for (int k = i + 1; k < j_used; ++k) t -= Hm(i, k) * y[k];
+                y[i] = t / Hm(i, i);
+            }
+            HX_HIP(c, hipMemcpyAsync(sc + 130, y.data(), sizeof(double) * j_used,
+                                     hipMemcpyHostToDevice, c->stream));
+            HX_HIP(c, blas_lincomb(c, n, j_used, Z, n, sc + 130, x));
+        }
+        ++info->restarts;
+        if (sw) {
+            if (pc == HX_PC_LEARNED) {
+                pc = HX_PC_BLOCK_JACOBI;
+                info->fallback_used = 1;
+                est_hist.clear();
+            } else {
+                done = true;   // breakdown with no fallback left
+            }
+        }
+    }
+    info->iters = it;
+    info->history_len = info->history ? hist : 0;
+    (void)rtmp;
+    return HX_OK;
+}
+
+}  // namespace
+}  // namespace hx
+
+using namespace hx;
+
+extern "C" {
+
+void hx_default_params(hx_solve_params *p)
+{
+    if (!p) return;
+    p->method = 0;
+    p->restart = 30;
+    p->rtol = 1e-8;
+    p->max_iter = 10000;
+    p->pc = HX_PC_BLOCK_JACOBI;
+    p->mixed = 0;
+    p->inner_iters = 12;
+    p->inner_rtol = 1e-2;
+    p->x0_mode = 0;
+    p->stall_window = 10;
+    p->stall_ratio = 0.99;
+}
+
+hx_status hx_solve(hx_ctx *c, const hx_solve_params *prm, const double *b, double *x,
+                   hx_solve_info *info)
+{
+    if (!c) return HX_ERR_ARG;
+    if (!prm || !b || !x || !info) return fail(c, HX_ERR_ARG, "null argument");
+    double *hist = info->history;
+    int hcap = info->history_len;
+    std::memset(info, 0, sizeof(*info));
+    info->history = hist;
+    info->history_len = hist ? hcap : 0;
+    info->status = HX_ERR_STATE;
+    if (!c->has_coef) return fail(c, HX_ERR_STATE, "solve before setup_mesh/set_coefficients");
+    if (b == x) return fail(c, HX_ERR_ARG, "b and x alias");
+    if (prm->method != 0 && prm->method != 1) return fail(c, HX_ERR_ARG, "method must be 0 or 1");
+    if (prm->method == 1 && (prm->restart < 1 || prm->restart > 64))
+        return fail(c, HX_ERR_ARG, "restart must be in 1..64");
+    if (!(prm->rtol > 0.0) || prm->max_iter < 1) return fail(c, HX_ERR_ARG, "bad rtol/max_iter");
+    if (prm->pc < HX_PC_NONE || prm->pc > HX_PC_LEARNED) return fail(c, HX_ERR_ARG, "bad pc");
+    if (prm->method == 0 && (prm->pc == HX_PC_LEARNED || prm->mixed))
+        return fail(c, HX_ERR_ARG, "CG needs a fixed SPD preconditioner; use FGMRES");
+    if (prm->mixed && prm->inner_iters < 1) return fail(c, HX_ERR_ARG, "inner_iters must be >= 1");
+    if (prm->pc == HX_PC_LEARNED && !c->mlp) return fail(c, HX_ERR_STATE, "no network loaded");
+    HX_HIP(c, hipSetDevice(c->device));
+    const double t0 = now_ms();
+    Timer tm(true);
+    hx_status s = prm->method == 0 ? solve_cg(c, prm, b, x, info, tm)
+                                   : solve_fgmres(c, prm, b, x, info, tm);
+    if (s != HX_OK && s != HX_ERR_NOCONV) {
+        info->status = s;
+        return s;
+    }
+    // true FP64 residual is the judge
+    const int64_t n = c->n_dofs;
+    double *sc = c->red + SC_OFF;
+    hx_status s2 = ensure_work(c, (size_t)n, 0);
+    if (s2 != HX_OK) return s2;
+    HX_HIP(c, launch_apply64(c, x, c->work64, b));
+    HX_HIP(c, blas_dot(c, n, c->work64, c->work64, sc + 200));
+    HX_HIP(c, blas_dot(c, n, b, b, sc + 201));
+    double hh[2];
+    if ((s2 = read_scalars(c, sc + 200, 2, hh)) != HX_OK) return s2;
+    info->true_rel_res = hh[1] > 0 ? std::sqrt(hh[0] / hh[1]) : 0.0;
+    info->ms_total = now_ms() - t0;
+    info->ms_op = tm.op;
+    info->ms_pc = tm.pc;
+    info->ms_orth = tm.orth;
+    const bool conv = info->true_rel_res <= prm->rtol * 1.0001;
+    hx_status st = conv ? (info->fallback_used ? HX_FALLBACK_USED : HX_OK) : HX_ERR_NOCONV;
+    info->status = st;
+    if (st == HX_ERR_NOCONV)
+        fail(c, st, "not converged: true relative residual %.3e after %d iterations",
+             info->true_rel_res, info->iters);
+    return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,55 @@
+"""Shared set-up for the GPU parity tests: one seeded input, given to both the
+HIP library and the oracle."""
+import numpy as np
+
+import oracle
+import synth_inputs as si
+
+
+def problem(mesh, k, coef="random", seed=0, P=2.0):
+    """Oracle problem with coefficient fields evaluated at the oracle's own dof
+    coordinates; the same arrays are then handed to the library."""
+    p = oracle.Problem(mesh, k, P=P)
+    if coef == "terrain":
+        fa, fb = si.terrain_coefficients()
+    elif coef == "const":
+        fa, fb = si.const_coefficients(1.0, 0.01)
+    else:
+        fa, fb = si.random_smooth_coefficients(seed)
+    p.set_coefficient_functions(fa, fb)
+    return p
+
+
+def gpu_context(p):
+    import paper_2505_00384_amd as hx
+    ctx = hx.HelmDG(0)
+    ctx.setup_mesh(p.k, p.nodes, p.nbr, p.g)
+    ctx.set_coefficients(p.alpha, p.beta, p.P)
+    return ctx
+
+
+def to_dev(a, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to("cuda:0")
+
+
+def normwise(y, ref):
+    """(||y - ref||_2 / ||ref||_2, max|y - ref| / max|ref|)"""
+    d = np.asarray(y, dtype=np.float64) - ref
+    return (np.linalg.norm(d) / np.linalg.norm(ref), np.abs(d).max() / np.abs(ref).max())
+
+
+TINY = [
+    ("1x1x1-periodic", lambda: si.box_mesh(1, 1, 1, periodic=(True, True, True))),
+    ("2x1x3-periodic", lambda: si.box_mesh(2, 1, 3, periodic=(True, True, True))),
+    ("3x3x3-neumann", lambda: si.cube_mesh(3, periodic=(False, False, False))),
+    ("terrain-3x2x2-g2", lambda: si.terrain_mesh(3, 2, 2, g=2)),
+    ("wavy-3-g3", lambda: si.wavy_cube_mesh(3, 3)),
+    ("jitter-3x2x2", lambda: si.random_node_jitter(
+        si.box_mesh(3, 2, 2, periodic=(False,) * 3, g=2), 4, 0.03)),
+    ("ragged-7x1x1", lambda: si.box_mesh(7, 1, 1, periodic=(True, False, True),
+                                          mapping=si.random_affine_mapping(9))),
+]

@@ -1,0 +1,193 @@
+"""GPU parity of geometry (step a1), coefficient merge (a2), the fused
+cell + face operator (a3, a4), the residual (a7) and the separable block
+Jacobi (a5) against the FP64 oracle, on the same seeded inputs.
+
+Tolerances: FP64 normwise ||y - y_or|| <= 1e-12 ||y_or|| and
+max|y - y_or| <= 1e-12 max|y_or| (both sides sum in different orders and the
+GPU contracts to FMA, so agreement is to rounding, not bitwise).  FP32 paths
+are compared to the FP64 oracle with a bound derived from float epsilon
+(6e-8) times the sweep depth and conditioning of the cell operations.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth_inputs as si
+from helpers import TINY, gpu_context, normwise, problem, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _check(y, ref, tol=TOL):
+    e2, einf = normwise(y, ref)
+    assert e2 <= tol and einf <= tol, (e2, einf)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6, 7])
+def test_operator_parity_tiny_meshes(k):
+    import torch
+    for name, mk in TINY:
+        m = mk()
+        if k >= 6 and m.n_cells > 12:
+            continue
+        print(f"[parity] k={k} mesh={name}", flush=True)
+        p = problem(m, k, seed=k)
+        ctx = gpu_context(p)
+        x = si.random_vector(p.n_dofs, 100 + k)
+        y = ctx.apply_operator(to_dev(x)).cpu().numpy()
+        _check(y, p.apply(x))
+        ctx.close()
+
+
+def test_geometry_parity():
+    for name, mk in TINY + [("terrain-8x2x4-g4", lambda: si.terrain_mesh(8, 2, 4, g=4))]:
+        m = mk()
+        print(f"[geometry] mesh={name}", flush=True)
+        p = problem(m, 4 if m.g >= 3 else 2)
+        ctx = gpu_context(p)
+        xyz = ctx.dof_coordinates().cpu().numpy()
+        ref = p.dof_coords()
+        assert np.abs(xyz - ref).max() <= 1e-14 * max(1.0, np.abs(ref).max())
+        vol = ctx.debug_export(oracle_export("VOLUME"), (m.n_cells,))
+        np.testing.assert_allclose(vol, p.cell_volumes(), rtol=1e-13)
+        sig = ctx.debug_export(oracle_export("SIGMA"), (m.n_cells, 3))
+        np.testing.assert_allclose(sig, p.face_sigma(), rtol=1e-12)
+        bjc = ctx.debug_export(oracle_export("BJ_SCALARS"), (m.n_cells, 4))
+        for c in range(0, m.n_cells, max(1, m.n_cells // 5)):
+            ell, ab, bb, _ = p.bj_cell_data(c)
+            ref4 = [ab * ell.prod(), bb * ell[1] * ell[2] / ell[0], bb * ell[0] * ell[2] / ell[1],
+                    bb * ell[0] * ell[1] / ell[2]]
+            np.testing.assert_allclose(bjc[c], ref4, rtol=1e-12)
+        ctx.close()
+
+
+def oracle_export(name):
+    import paper_2505_00384_amd as hx
+    return getattr(hx, "HX_EXPORT_" + name)
+
+
+def test_operator_parity_workload_small():
+    """periodic unit cube 4^3 at degree 2 (constant coefficients) and the
+    terrain channel at 1/4 resolution at degree 4"""
+    for mesh, k, coef in [(si.cube_mesh(4), 2, "const"), (si.terrain_mesh(8, 2, 4, g=4), 4, "terrain")]:
+        print(f"[parity] workload {mesh.name} k={k}", flush=True)
+        p = problem(mesh, k, coef=coef)
+        ctx = gpu_context(p)
+        for seed in range(3):
+            x = si.random_vector(p.n_dofs, seed)
+            y = ctx.apply_operator(to_dev(x)).cpu().numpy()
+            _check(y, p.apply(x))
+        ctx.close()
+
+
+def test_operator_parity_terrain_32x8x16():
+    """the full 32x8x16 Q4 terrain channel (512,000 dofs)"""
+    print("[parity] terrain 32x8x16 k=4", flush=True)
+    p = problem(si.terrain_mesh(32, 8, 16, g=4), 4, coef="terrain")
+    ctx = gpu_context(p)
+    x = si.rhs_terrain(3)(*p.dof_coords())
+    y = ctx.apply_operator(to_dev(x)).cpu().numpy()
+    _check(y, p.apply(x))
+    # residual epilogue r = b - A x
+    b = si.random_vector(p.n_dofs, 4)
+    r = ctx.residual(to_dev(b), to_dev(x)).cpu().numpy()
+    ref = b - p.apply(x)
+    assert np.linalg.norm(r - ref) <= 1e-12 * (np.linalg.norm(b) + np.linalg.norm(p.apply(x)))
+    ctx.close()
+
+
+def test_dense_matrix_by_unit_vectors():
+    """The GPU operator applied to every unit vector (section 3.1 of the
+    paper builds a matrix-free operator's matrix this way) equals the oracle's
+    assembled matrix, on the 4^3 periodic cube at degree 2."""
+    import torch
+    p = problem(si.cube_mesh(4), 2, coef="const")
+    ctx = gpu_context(p)
+    n = p.n_dofs
+    A = np.zeros((n, n))
+    e = torch.zeros(n, dtype=torch.float64, device="cuda:0")
+    y = torch.empty_like(e)
+    for j in range(n):
+        e[j] = 1.0
+        ctx.apply_operator(e, y)
+        A[:, j] = y.cpu().numpy()
+        e[j] = 0.0
+    Ar = p.assemble_dense()
+    assert np.abs(A - Ar).max() <= 1e-12 * np.abs(Ar).max()
+    assert np.abs(A - A.T).max() <= 1e-13 * np.abs(A).max()
+    ctx.close()
+
+
+def test_fp32_operator_error():
+    import torch
+    p = problem(si.terrain_mesh(8, 2, 4, g=4), 4, coef="terrain")
+    ctx = gpu_context(p)
+    x = si.rhs_terrain(1)(*p.dof_coords())
+    y32 = ctx.apply_operator(to_dev(x, torch.float32)).double().cpu().numpy()
+    e2, _ = normwise(y32, p.apply(x))
+    assert e2 <= 2e-6, e2
+    ctx.close()
+
+
+def test_determinism_and_empty_input():
+    import torch
+    p = problem(si.wavy_cube_mesh(3, 3), 3)
+    ctx = gpu_context(p)
+    x = to_dev(si.random_vector(p.n_dofs, 7))
+    y1 = ctx.apply_operator(x).clone()
+    for _ in range(3):
+        assert torch.equal(ctx.apply_operator(x), y1)
+    z = torch.zeros_like(x)
+    assert torch.count_nonzero(ctx.apply_operator(z)) == 0
+    ctx.close()
+
+
+def test_sampled_parity_large_terrain():
+    """At the 256x64x64 Q4 size the oracle computes sampled cells only."""
+    import torch
+    free = torch.cuda.mem_get_info()[0]
+    if free < 40e9:
+        pytest.skip("needs ~40 GB of device memory")
+    print("[parity] terrain 256x64x64 k=4, sampled cells", flush=True)
+    m = si.terrain_mesh(256, 64, 64, g=4)
+    p = problem(m, 4, coef="terrain")
+    ctx = gpu_context(p)
+    x = si.rhs_terrain(5)(*p.dof_coords())
+    y = ctx.apply_operator(to_dev(x)).cpu().numpy().reshape(m.n_cells, -1)
+    rng = np.random.default_rng(0)
+    cells = np.unique(np.concatenate([rng.integers(0, m.n_cells, 48),
+                                      [0, 255, 256 * 63, m.n_cells - 1]]))
+    ref = p.apply_cells(x, cells)
+    e2, einf = normwise(y[cells], ref)
+    assert e2 <= TOL and einf <= TOL, (e2, einf)
+    ctx.close()
+
+
+# ---------------------------------------------------------------- block Jacobi
+
+@pytest.mark.parametrize("k", [1, 2, 4, 6])
+def test_block_jacobi_parity(k):
+    for name, mk in TINY:
+        m = mk()
+        print(f"[bj] k={k} mesh={name}", flush=True)
+        p = problem(m, k, seed=2 * k)
+        ctx = gpu_context(p)
+        r = si.random_vector(p.n_dofs, 11)
+        z = ctx.apply_preconditioner(to_dev(r)).cpu().numpy()
+        _check(z, p.bj_apply(r), tol=1e-11)
+        ctx.close()
+
+
+def test_block_jacobi_terrain_and_fp32():
+    import torch
+    p = problem(si.terrain_mesh(8, 2, 4, g=4), 4, coef="terrain")
+    ctx = gpu_context(p)
+    r = si.rhs_terrain(2)(*p.dof_coords())
+    zr = p.bj_apply(r)
+    z = ctx.apply_preconditioner(to_dev(r)).cpu().numpy()
+    _check(z, zr, tol=1e-11)
+    z32 = ctx.apply_preconditioner(to_dev(r, torch.float32)).double().cpu().numpy()
+    assert normwise(z32, zr)[0] <= 1e-5
+    ctx.close()
