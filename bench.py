@@ -1,0 +1,248 @@
+"""Benchmark of the DG Helmholtz pressure operator and solve on one MI355X.
+
+Timed step: one application of the fused cell + face operator (y = A x, FP64)
+on the terrain-following channel with 256 x 64 x 64 Q4 cells (131,072,000
+dofs), inputs resident in HBM.  ``value`` is GDoF/s = n_dofs / (time per
+application).  The JSON line also carries
+
+* ``roofline``: algorithmic bytes per application (105.6 B/dof: x and y,
+  7 merged cell values and 3 x 7 x 25 / 125 merged face values per dof, FP64)
+  over the event-timed kernel duration, against the 8 TB/s HBM peak, and the
+  HBM traffic measured by rocprofv3 counters (from the committed profile, null
+  if the kernel source changed since);
+* ``solve``: time to a 1e-8 relative true residual for plain FP64, mixed
+  precision and (when a trained network is available) learned forms;
+* ``cpu_baseline``: the FP64 oracle timed on the host cores on a sample of the
+  same workload.
+
+Usage: python bench.py [--gpus 1] [--steps 50] [--warmup 5]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+ALG_BYTES_PER_DOF_F64 = 16.0 + 56.0 + 33.6     # x + y, cell data, face data
+HBM_PEAK_GBS = 8000.0
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "op_apply_f64_terrain256x64x64_k4_traffic.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_2505_00384_amd", "csrc", "operator.hip")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def read_traffic(n_dofs: int):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel source."""
+    if not os.path.exists(PROFILE_TRAFFIC):
+        return None
+    kv = {}
+    for line in open(PROFILE_TRAFFIC):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("operator_source_sha256_16") != kernel_hash():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def setup(ctx_cls, mesh, k, torch, dev):
+    from synth_inputs import terrain_coefficients
+    ctx = ctx_cls(0)
+    t0 = time.time()
+    ctx.setup_mesh(k, mesh.nodes, mesh.nbr, mesh.g)
+    xyz = ctx.dof_coordinates()
+    fa, fb = terrain_coefficients()
+    ctx.set_coefficients(field_on_device(fa, xyz, torch), field_on_device(fb, xyz, torch), 2.0)
+    torch.cuda.synchronize()
+    return ctx, xyz, time.time() - t0
+
+
+def rhs_on_device(xyz, seed, torch):
+    from synth_inputs import rhs_terrain
+    return field_on_device(rhs_terrain(seed), xyz, torch)
+
+
+def field_on_device(f, xyz, torch):
+    """Evaluate an analytic input field (numpy function of x, y, z) at the
+    library's dof coordinates, in chunks on the host, and upload it."""
+    x = xyz.cpu().numpy()
+    out = np.empty(x.shape[1])
+    step = 1 << 24
+    for s in range(0, x.shape[1], step):
+        out[s:s + step] = f(x[0, s:s + step], x[1, s:s + step], x[2, s:s + step])
+    return torch.from_numpy(out).to(xyz.device)
+
+
+def time_matvec(ctx, x, y, steps, warmup, torch):
+    for _ in range(warmup):
+        ctx.apply_operator(x, y)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        ctx.apply_operator(x, y)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps        # ms per application
+
+
+def solve_suite(hx, ctx, b, torch, forms, label):
+    out = {}
+    for name, params in forms:
+        x = torch.zeros_like(b)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        x, info = ctx.solve(b, x, params)
+        torch.cuda.synchronize()
+        wall = (time.time() - t0) * 1e3
+        out[name] = dict(ms=round(wall, 3), iters=info["iters"], inner_iters=info["inner_iters"],
+                         true_rel_res=info["true_rel_res"], status=hx.STATUS_NAMES[info["status"]],
+                         ms_op=round(info["ms_op"], 3), ms_pc=round(info["ms_pc"], 3),
+                         ms_orth=round(info["ms_orth"], 3))
+        log(f"{label} {name}: {out[name]}")
+    return out
+
+
+def cpu_baseline(layers: int):
+    """Oracle matvec on the bottom `layers` cell layers of the 256x64x64 terrain
+    channel (same cells, same fields), all host cores."""
+    import oracle
+    import synth_inputs as si
+    T = si.TERRAIN
+    hz = T["Lz"] / 64
+    m = si.box_mesh(256, 64, layers, lo=(-T["Lx"] / 2, 0.0, 0.0),
+                    hi=(T["Lx"] / 2, T["Ly"], layers * hz), periodic=(True, True, False), g=4,
+                    mapping=si.terrain_mapping)
+    p = oracle.Problem(m, 4)
+    p.set_coefficient_functions(*si.terrain_coefficients())
+    x = si.rhs_terrain(0)(*p.dof_coords())
+    t0 = time.time()
+    p.apply(x)
+    dt = time.time() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=p.n_dofs / dt / 1e9, unit="GDoF/s", cores=cores, kind="oracle",
+                sample=f"FP64 oracle matvec on the bottom {layers} cell layers of the 256x64x64 "
+                       f"Q4 terrain channel ({m.n_cells} cells, {p.n_dofs} dofs), {dt:.2f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--nx", type=int, default=256)
+    ap.add_argument("--ny", type=int, default=64)
+    ap.add_argument("--nz", type=int, default=64)
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-layers", type=int, default=2)
+    ap.add_argument("--fp32", action="store_true", help="also time the FP32 operator")
+    ap.add_argument("--copy-calibrate", action="store_true",
+                    help="also run a plain device copy of the x vector (for counter scaling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
+              "decomposition is a design, not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2505_00384_amd as hx
+    import synth_inputs as si
+
+    dev = torch.device("cuda:0")
+    k = 4
+    log(f"building mesh {args.nx}x{args.ny}x{args.nz}")
+    mesh = si.terrain_mesh(args.nx, args.ny, args.nz, g=4)
+    ctx, xyz, t_setup = setup(hx.HelmDG, mesh, k, torch, dev)
+    n = ctx.n_dofs
+    log(f"setup {t_setup:.2f} s, {n} dofs")
+    del mesh
+    x = rhs_on_device(xyz, 0, torch)
+    del xyz
+    y = torch.empty_like(x)
+    ms = time_matvec(ctx, x, y, args.steps, args.warmup, torch)
+    gdofs = n / (ms * 1e-3) / 1e9
+    achieved = ALG_BYTES_PER_DOF_F64 * n / (ms * 1e-3) / 1e9
+    log(f"FP64 matvec {ms:.4f} ms, {gdofs:.2f} GDoF/s, {achieved:.0f} GB/s algorithmic")
+    extra = {}
+    if args.fp32:
+        x32 = x.float()
+        y32 = torch.empty_like(x32)
+        ms32 = time_matvec(ctx, x32, y32, args.steps, args.warmup, torch)
+        extra["fp32_matvec"] = dict(ms=round(ms32, 4), gdofs=round(n / (ms32 * 1e-3) / 1e9, 3),
+                                    alg_GBs=round(ALG_BYTES_PER_DOF_F64 / 2 * n / (ms32 * 1e-3) / 1e9, 1))
+        log(f"FP32 matvec {ms32:.4f} ms")
+        del x32, y32
+    if args.copy_calibrate:
+        # a plain copy of known size: reads and writes 8 n bytes each
+        y.copy_(x)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {8 * n} bytes read, {8 * n} bytes written")
+    traffic = read_traffic(n)
+    roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic)
+
+    solve = {}
+    if not args.no_solve:
+        b = x
+        forms = [
+            ("fp64_fgmres_bj", hx.default_params(method=1, restart=30, rtol=1e-8, pc=hx.HX_PC_BLOCK_JACOBI)),
+            ("mixed_fp32_inner", hx.default_params(method=1, restart=10, rtol=1e-8, mixed=1, inner_iters=12)),
+        ]
+        del y
+        solve["terrain256x64x64"] = solve_suite(hx, ctx, b, torch, forms, "C3")
+        ctx.close()
+        del b, x
+        torch.cuda.empty_cache()
+        m2 = si.terrain_mesh(32, 8, 16, g=4)
+        ctx2, xyz2, _ = setup(hx.HelmDG, m2, k, torch, dev)
+        b2 = rhs_on_device(xyz2, 0, torch)
+        forms2 = forms + [("fp64_cg_bj", hx.default_params(method=0, rtol=1e-8, pc=hx.HX_PC_BLOCK_JACOBI))]
+        solve["terrain32x8x16"] = solve_suite(hx, ctx2, b2, torch, forms2, "C2")
+        ctx2.close()
+    else:
+        ctx.close()
+
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline(args.cpu_layers)
+        log(f"cpu baseline {cpu}")
+
+    rec = {
+        "metric": "Helmholtz matvec GDoF/s (% HBM peak); time-to-1e-8 solve: FP64 vs mixed/learned",
+        "value": round(gdofs, 3), "unit": "GDoF/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"terrain-following channel {args.nx}x{args.ny}x{args.nz} cells, DG Q4, "
+                               "isothermal background coefficients, SIP penalty 2",
+                   "n_dofs": n, "degree": k, "geometry_degree": 4},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "solve": solve,
+        **extra,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

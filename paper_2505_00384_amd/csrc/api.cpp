@@ -41,7 +41,7 @@ void dfree(void **p)
 
 static void free_mesh(hx_ctx *c)
 {
-    void **bufs[] = {(void **)&c->nodes, (void **)&c->nbr, (void **)&c->ref, (void **)&c->vol,
+    void **bufs[] = {(void **)&c->nodes, (void **)&c->nbr, (void **)&c->order, (void **)&c->ref, (void **)&c->vol,
                      (void **)&c->ell, (void **)&c->mindet, (void **)&c->sigma,
                      (void **)&c->cell64, (void **)&c->cell32, (void **)&c->face64,
                      (void **)&c->face32, (void **)&c->bjS64, (void **)&c->bjS32,
@@ -170,6 +170,7 @@ hx_status hx_setup_mesh(hx_ctx *c, int degree, int64_t n_cells, int geo_degree,
     if (s == HX_OK) s = dalloc(c, (void **)&(ptr), (bytes));
     ALLOC(c->nodes, sizeof(double) * nc * ng3 * 3);
     ALLOC(c->nbr, sizeof(int32_t) * nc * 6);
+    ALLOC(c->order, sizeof(int32_t) * nc);
     ALLOC(c->ref, sizeof(RefTab64));
     ALLOC(c->vol, sizeof(double) * nc);
     ALLOC(c->ell, sizeof(double) * nc * 3);
@@ -194,6 +195,10 @@ hx_status hx_setup_mesh(hx_ctx *c, int degree, int64_t n_cells, int geo_degree,
     HX_HIP(c, hipMemcpyAsync(c->nodes, geo_nodes, sizeof(double) * nc * ng3 * 3,
                              hipMemcpyHostToDevice, c->stream));
     HX_HIP(c, hipMemcpyAsync(c->nbr, nb32.data(), sizeof(int32_t) * nc * 6, hipMemcpyHostToDevice,
+                             c->stream));
+    std::vector<int32_t> order(nc);
+    build_traversal(nb32.data(), n_cells, order.data());
+    HX_HIP(c, hipMemcpyAsync(c->order, order.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice,
                              c->stream));
     HX_HIP(c, hipMemcpyAsync(c->ref, &c->ref_host, sizeof(RefTab64), hipMemcpyHostToDevice,
                              c->stream));

@@ -59,6 +59,7 @@ struct hx_ctx {
 
     double *nodes = nullptr;      // [n_cells][(g+1)^3][3]
     int32_t *nbr = nullptr;       // [n_cells][6]
+    int32_t *order = nullptr;     // [n_cells] traversal order of the operator kernel
     hx::RefTab64 *ref = nullptr;  // device copy of the tables of degree k
     hx::RefTab64 ref_host{};
     double *vol = nullptr;        // [n_cells]
@@ -108,6 +109,7 @@ hx_status fail(hx_ctx *c, hx_status s, const char *fmt, ...);
     } while (0)
 
 hx_status dalloc(hx_ctx *c, void **p, size_t bytes);
+void build_traversal(const int32_t *nbr, int64_t n_cells, int32_t *order);
 void dfree(void **p);
 
 // ---- kernel launchers (defined in the .hip translation units) ----------

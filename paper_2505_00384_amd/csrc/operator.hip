@@ -4,21 +4,29 @@
 // stiffness; section 3.3, tensor-product evaluation with (k+1) Gauss points).
 //
 // Layout and mapping on gfx950
-//  * a workgroup handles CPB cells; each cell is served by N*N threads, one per
-//    "pencil" of N values along one direction; the direction changes between
-//    the sum-factorisation sweeps by staging the cell's values in LDS.
-//  * the 1-D tables (GLL->GL interpolation B, derivative BD, end derivatives DL)
-//    sit in constant memory; every loop over them is unrolled at compile time,
-//    so their entries are wave-uniform scalar operands.
-//  * cell data [cell][7][N^3] (m, G symmetric) and face data
-//    [cell][3][7][N^2] (g-, g+, s of the +d face) are streamed once, coalesced.
-//  * faces are evaluated cell-centrically: a cell computes, for each of its 6
-//    faces, its own and its neighbour's value / reference-gradient traces at the
-//    N^2 face Gauss points and accumulates the flux terms of its own test
-//    functions only, so every output value is written by exactly one thread
-//    (no atomics; results are bitwise reproducible).
-//  * workgroups are remapped so that each XCD walks a contiguous range of
-//    cells, which keeps the neighbours a cell reads in that XCD's L2.
+//  * a workgroup is one wave64; it serves CPW cells with LPC lanes each
+//    (N = 5: 2 cells x 32 lanes), so every barrier is a single-wave barrier.
+//  * cell integrals: lane (a, b) owns a pencil of N values; the sweeps
+//    (GLL -> Gauss interpolation B, derivative BD, and their transposes) run in
+//    registers, and the pencil direction changes through LDS;
+//  * face integrals: lane (f, r) owns row r of face f (6 faces x N rows).  It
+//    reads the own normal slab from LDS and the neighbour's slab straight from
+//    global memory into registers, forms layer values and normal derivatives,
+//    interpolates along the first tangential direction in registers, and after
+//    one LDS transpose lane (f, q1) finishes the second direction, the
+//    pointwise flux terms at the Gauss points and the transposed sweep; a
+//    second transpose returns to rows for the last transposed sweep.  The
+//    pencil owners then add the six faces' layer and normal-derivative
+//    contributions to their own output values.  Each output value is written
+//    by exactly one lane (no atomics; bitwise reproducible).
+//  * the 1-D tables sit in constant memory, loops over them are unrolled, so
+//    their entries are wave-uniform scalar operands.
+//  * cell data [cell][7][N^3] is streamed once with non-temporal loads; x and
+//    the face data [cell][3][7][N^2] are read by neighbours too and stay
+//    cacheable.
+//  * cells are visited in the order of a host-built permutation: tiles of
+//    columns swept layer by layer, in one contiguous range per XCD, so the
+//    neighbours a cell reads were touched recently by the same XCD's L2.
 #include "common.hpp"
 
 #include <type_traits>
@@ -53,11 +61,21 @@ __device__ __forceinline__ T tE(int e, int i)
     else return c_op[N].DLf[e][i];
 }
 
+constexpr int pow2_at_least(int v)
+{
+    int p = 1;
+    while (p < v) p *= 2;
+    return p;
+}
+
 template <int N>
 struct Cfg {
     static constexpr int NF = N * N, ND = N * N * N;
-    static constexpr int CPB = (256 / NF) > 0 ? 256 / NF : 1;
-    static constexpr int NT = ((CPB * NF + 63) / 64) * 64;
+    static constexpr int LPC = pow2_at_least(NF > 6 * N ? NF : 6 * N) > 64
+                                   ? 64 : pow2_at_least(NF > 6 * N ? NF : 6 * N);
+    static constexpr int CPW = 64 / LPC;                       // cells per wave
+    static constexpr int GS = (36 * NF > 3 * ND) ? 36 * NF : 3 * ND;  // work area per cell
+    static_assert(NF <= 64 && 6 * N <= 64, "one wave per cell at most");
 };
 
 // local index with coordinate m along direction d and (p, r) along the two
@@ -68,65 +86,84 @@ __device__ __forceinline__ int lix(int d, int m, int p, int r)
     return d == 0 ? m + N * (p + N * r) : (d == 1 ? p + N * (m + N * r) : p + N * (r + N * m));
 }
 
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T *p)
+{
+    return __builtin_nontemporal_load(p);
+}
+
 template <int N, typename T>
-__global__ void __launch_bounds__(Cfg<N>::NT)
+__global__ void __launch_bounds__(64)
 k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
         const T *__restrict__ cell, const T *__restrict__ face, const int32_t *__restrict__ nbr,
-        int n_cells, int nwg)
+        const int32_t *__restrict__ order, int n_cells, int nwg)
 {
-    constexpr int NF = Cfg<N>::NF, ND = Cfg<N>::ND, CPB = Cfg<N>::CPB;
-    __shared__ T sU[CPB][ND];
-    __shared__ T sV[CPB][ND];
-    __shared__ T sW[3][CPB][ND];
-    __shared__ T sF[CPB][10][NF];
+    constexpr int NF = Cfg<N>::NF, ND = Cfg<N>::ND, LPC = Cfg<N>::LPC, CPW = Cfg<N>::CPW,
+                  GS = Cfg<N>::GS;
+    __shared__ T sU[CPW][ND];
+    __shared__ T sG[CPW][GS];
 
-    // contiguous cell ranges per XCD (workgroups are dealt round-robin to XCDs)
+    // contiguous ranges of the traversal per XCD (workgroups are dealt
+    // round-robin to the XCDs)
     const int bid = blockIdx.x;
     const int q8 = nwg / NXCD, r8 = nwg % NXCD, xcd = bid % NXCD;
     const int wg = xcd * q8 + (xcd < r8 ? xcd : r8) + bid / NXCD;
 
-    const int t = threadIdx.x;
-    const int lc0 = t / NF;
-    const bool slot = lc0 < CPB;
-    const int lc = slot ? lc0 : 0;
-    const int tt = t - lc0 * NF;
-    const int a = tt % N, b = tt / N;
-    const int64_t cid = (int64_t)wg * CPB + lc;
-    const bool active = slot && cid < n_cells;
+    const int lane = threadIdx.x;
+    const int cs = lane / LPC;             // cell slot in the wave
+    const int ln = lane - cs * LPC;        // lane within the cell
+    const int slot = wg * CPW + cs;
+    const bool valid = slot < n_cells;
+    const int64_t cid = valid ? order[slot] : 0;
+    T *G = &sG[cs][0];
+    T *U = &sU[cs][0];
 
-    if (active)
-        for (int e = tt; e < ND; e += NF) sU[lc][e] = x[cid * ND + e];
+    // ---- cell lanes: (a, b), pencil owners
+    const bool cl = valid && ln < NF;
+    const int a = ln % N, b = (ln / N) % N;
+    // ---- face lanes: (f, r), row owners
+    const bool fl0 = valid && ln < 6 * N;
+    const int f = fl0 ? ln / N : 0, rr = ln % N;
+    const int d = f >> 1, s = f & 1;
+    const int32_t nb = fl0 ? nbr[cid * 6 + f] : -1;
+    const bool fl = nb >= 0;
+
+    if (valid)
+        for (int e = ln; e < ND; e += LPC) sU[cs][e] = x[cid * ND + e];
+
+    // quadrature-point data of this lane's z pencil, streamed once
+    const T *cp = cell + cid * 7 * ND + a + N * b;
     __syncthreads();
 
     T Y[N];
-    // ------------------------------------------------------------ cell part
-    {
-        // x: thread (j=a, l=b) -> B u and BD u along x
-        if (active) {
-            T r[N];
+    // =========================================================== cell part
+    // x sweep: lane (j=a, l=b): B u and BD u along x
+    if (cl) {
+        T r[N];
 #pragma unroll
-            for (int i = 0; i < N; ++i) r[i] = sU[lc][i + N * a + NF * b];
+        for (int i = 0; i < N; ++i) r[i] = U[i + N * a + NF * b];
 #pragma unroll
-            for (int q = 0; q < N; ++q) {
-                T s0 = 0, s1 = 0;
+        for (int q = 0; q < N; ++q) {
+            T s0 = 0, s1 = 0;
 #pragma unroll
-                for (int i = 0; i < N; ++i) {
-                    s0 += tB<T, N>(q, i) * r[i];
-                    s1 += tD<T, N>(q, i) * r[i];
-                }
-                sW[0][lc][q + N * a + NF * b] = s0;
-                sW[1][lc][q + N * a + NF * b] = s1;
+            for (int i = 0; i < N; ++i) {
+                s0 += tB<T, N>(q, i) * r[i];
+                s1 += tD<T, N>(q, i) * r[i];
             }
+            G[q + N * a + NF * b] = s0;
+            G[ND + q + N * a + NF * b] = s1;
         }
-        __syncthreads();
-        // y: thread (qx=a, l=b)
+    }
+    __syncthreads();
+    // y sweep: lane (qx=a, l=b)
+    {
         T c0[N], c1[N], c2[N];
-        if (active) {
+        if (cl) {
             T p0[N], p1[N];
 #pragma unroll
             for (int j = 0; j < N; ++j) {
-                p0[j] = sW[0][lc][a + N * j + NF * b];
-                p1[j] = sW[1][lc][a + N * j + NF * b];
+                p0[j] = G[a + N * j + NF * b];
+                p1[j] = G[ND + a + N * j + NF * b];
             }
 #pragma unroll
             for (int q = 0; q < N; ++q) {
@@ -141,28 +178,28 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
             }
         }
         __syncthreads();
-        if (active) {
+        if (cl) {
 #pragma unroll
             for (int q = 0; q < N; ++q) {
-                sW[0][lc][a + N * q + NF * b] = c0[q];   // u (interpolated in x, y)
-                sW[1][lc][a + N * q + NF * b] = c1[q];   // d/deta
-                sW[2][lc][a + N * q + NF * b] = c2[q];   // d/dxi
+                G[a + N * q + NF * b] = c0[q];            // u
+                G[ND + a + N * q + NF * b] = c1[q];       // d/deta
+                G[2 * ND + a + N * q + NF * b] = c2[q];   // d/dxi
             }
         }
-        __syncthreads();
-        // z: thread (qx=a, qy=b): values and reference gradient at the points,
-        // quadrature-point operation, then the transposed z sweep
+    }
+    __syncthreads();
+    // z sweep, quadrature-point operation and transposed z sweep: lane (qx=a, qy=b)
+    {
         T t0[N], t1[N], t2[N];
-        if (active) {
+        if (cl) {
             T p0[N], p1[N], p2[N];
 #pragma unroll
             for (int l = 0; l < N; ++l) {
-                p0[l] = sW[0][lc][a + N * b + NF * l];
-                p1[l] = sW[1][lc][a + N * b + NF * l];
-                p2[l] = sW[2][lc][a + N * b + NF * l];
+                p0[l] = G[a + N * b + NF * l];
+                p1[l] = G[ND + a + N * b + NF * l];
+                p2[l] = G[2 * ND + a + N * b + NF * l];
+                t0[l] = t1[l] = t2[l] = 0;
             }
-            T v[N], fx[N], fy[N], fz[N];
-            const T *cd = cell + cid * 7 * ND + a + N * b;
 #pragma unroll
             for (int q = 0; q < N; ++q) {
                 T u = 0, dz = 0, dy = 0, dx = 0;
@@ -173,45 +210,43 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
                     dy += tB<T, N>(q, l) * p1[l];
                     dx += tB<T, N>(q, l) * p2[l];
                 }
-                const int o = NF * q;
-                const T m = cd[o], gxx = cd[ND + o], gxy = cd[2 * ND + o], gxz = cd[3 * ND + o],
-                        gyy = cd[4 * ND + o], gyz = cd[5 * ND + o], gzz = cd[6 * ND + o];
-                v[q] = m * u;
-                fx[q] = gxx * dx + gxy * dy + gxz * dz;
-                fy[q] = gxy * dx + gyy * dy + gyz * dz;
-                fz[q] = gxz * dx + gyz * dy + gzz * dz;
-            }
+                const T *cq = cp + NF * q;
+                const T m = ld_stream(cq), gxx = ld_stream(cq + ND), gxy = ld_stream(cq + 2 * ND),
+                        gxz = ld_stream(cq + 3 * ND), gyy = ld_stream(cq + 4 * ND),
+                        gyz = ld_stream(cq + 5 * ND), gzz = ld_stream(cq + 6 * ND);
+                const T v = m * u;
+                const T fx = gxx * dx + gxy * dy + gxz * dz;
+                const T fy = gxy * dx + gyy * dy + gyz * dz;
+                const T fz = gxz * dx + gyz * dy + gzz * dz;
 #pragma unroll
-            for (int l = 0; l < N; ++l) {
-                T s0 = 0, s1 = 0, s2 = 0;
-#pragma unroll
-                for (int q = 0; q < N; ++q) {
-                    s0 += tB<T, N>(q, l) * v[q] + tD<T, N>(q, l) * fz[q];
-                    s1 += tB<T, N>(q, l) * fy[q];
-                    s2 += tB<T, N>(q, l) * fx[q];
+                for (int l = 0; l < N; ++l) {
+                    t0[l] += tB<T, N>(q, l) * v + tD<T, N>(q, l) * fz;
+                    t1[l] += tB<T, N>(q, l) * fy;
+                    t2[l] += tB<T, N>(q, l) * fx;
                 }
-                t0[l] = s0; t1[l] = s1; t2[l] = s2;
             }
         }
         __syncthreads();
-        if (active) {
+        if (cl) {
 #pragma unroll
             for (int l = 0; l < N; ++l) {
-                sW[0][lc][a + N * b + NF * l] = t0[l];
-                sW[1][lc][a + N * b + NF * l] = t1[l];
-                sW[2][lc][a + N * b + NF * l] = t2[l];
+                G[a + N * b + NF * l] = t0[l];
+                G[ND + a + N * b + NF * l] = t1[l];
+                G[2 * ND + a + N * b + NF * l] = t2[l];
             }
         }
-        __syncthreads();
-        // y transposed: thread (qx=a, l=b)
+    }
+    __syncthreads();
+    // transposed y sweep: lane (qx=a, l=b)
+    {
         T s0v[N], s1v[N];
-        if (active) {
+        if (cl) {
             T p0[N], p1[N], p2[N];
 #pragma unroll
             for (int q = 0; q < N; ++q) {
-                p0[q] = sW[0][lc][a + N * q + NF * b];
-                p1[q] = sW[1][lc][a + N * q + NF * b];
-                p2[q] = sW[2][lc][a + N * q + NF * b];
+                p0[q] = G[a + N * q + NF * b];
+                p1[q] = G[ND + a + N * q + NF * b];
+                p2[q] = G[2 * ND + a + N * q + NF * b];
             }
 #pragma unroll
             for (int j = 0; j < N; ++j) {
@@ -225,183 +260,244 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
             }
         }
         __syncthreads();
-        if (active) {
+        if (cl) {
 #pragma unroll
             for (int j = 0; j < N; ++j) {
-                sW[0][lc][a + N * j + NF * b] = s0v[j];
-                sW[1][lc][a + N * j + NF * b] = s1v[j];
-            }
-        }
-        __syncthreads();
-        // x transposed: thread (j=a, l=b) owns the output pencil Y
-        if (active) {
-            T p0[N], p1[N];
-#pragma unroll
-            for (int q = 0; q < N; ++q) {
-                p0[q] = sW[0][lc][q + N * a + NF * b];
-                p1[q] = sW[1][lc][q + N * a + NF * b];
-            }
-#pragma unroll
-            for (int i = 0; i < N; ++i) {
-                T s = 0;
-#pragma unroll
-                for (int q = 0; q < N; ++q) s += tB<T, N>(q, i) * p0[q] + tD<T, N>(q, i) * p1[q];
-                Y[i] = s;
-            }
-        }
-        __syncthreads();
-        // sW[0] becomes the accumulator of the y- and z-face terms
-        if (active) {
-#pragma unroll
-            for (int i = 0; i < N; ++i) sW[0][lc][i + N * a + NF * b] = 0;
-        }
-    }
-
-    // ------------------------------------------------------------ faces
-    T *YF = &sW[0][lc][0];
-#pragma unroll 1
-    for (int d = 0; d < 3; ++d) {
-#pragma unroll 1
-        for (int s = 0; s < 2; ++s) {
-            const int32_t nb = active ? nbr[cid * 6 + 2 * d + s] : -1;
-            const bool fact = nb >= 0;
-            const int eo = s, en = 1 - s;               // own / neighbour end along d
-            __syncthreads();                            // previous face done with sV, sF, YF
-            if (fact)
-                for (int e = tt; e < ND; e += NF) sV[lc][e] = x[(int64_t)nb * ND + e];
-            __syncthreads();
-            // T1: thread (p=a, r=b): layer values and normal derivatives
-            if (fact) {
-                T lo = 0, dno = 0, ln = 0, dnn = 0;
-#pragma unroll
-                for (int m = 0; m < N; ++m) {
-                    const int id = lix<N>(d, m, a, b);
-                    const T uo = sU[lc][id], un = sV[lc][id];
-                    dno += tE<T, N>(eo, m) * uo;
-                    dnn += tE<T, N>(en, m) * un;
-                    if (m == (eo ? N - 1 : 0)) lo = uo;
-                    if (m == (en ? N - 1 : 0)) ln = un;
-                }
-                sF[lc][0][a + N * b] = lo;
-                sF[lc][1][a + N * b] = dno;
-                sF[lc][2][a + N * b] = ln;
-                sF[lc][3][a + N * b] = dnn;
-            }
-            __syncthreads();
-            // T2: thread (q1=a, r=b): interpolate along the first tangential direction
-            if (fact) {
-                T g[6] = {0, 0, 0, 0, 0, 0};
-#pragma unroll
-                for (int p = 0; p < N; ++p) {
-                    const T f0o = sF[lc][0][p + N * b], f1o = sF[lc][1][p + N * b];
-                    const T f0n = sF[lc][2][p + N * b], f1n = sF[lc][3][p + N * b];
-                    const T bb = tB<T, N>(a, p), bd = tD<T, N>(a, p);
-                    g[0] += bb * f0o; g[1] += bd * f0o; g[2] += bb * f1o;
-                    g[3] += bb * f0n; g[4] += bd * f0n; g[5] += bb * f1n;
-                }
-#pragma unroll
-                for (int k = 0; k < 6; ++k) sF[lc][4 + k][a + N * b] = g[k];
-            }
-            __syncthreads();
-            // T3: thread (q1=a, q2=b): traces at the face point, flux terms
-            if (fact) {
-                T vo = 0, t2o = 0, t1o = 0, dno = 0, vn = 0, t2n = 0, t1n = 0, dnn = 0;
-#pragma unroll
-                for (int r = 0; r < N; ++r) {
-                    const T bb = tB<T, N>(b, r), bd = tD<T, N>(b, r);
-                    const T g0o = sF[lc][4][a + N * r], g1o = sF[lc][5][a + N * r], g2o = sF[lc][6][a + N * r];
-                    const T g0n = sF[lc][7][a + N * r], g1n = sF[lc][8][a + N * r], g2n = sF[lc][9][a + N * r];
-                    vo += bb * g0o; t2o += bd * g0o; t1o += bb * g1o; dno += bb * g2o;
-                    vn += bb * g0n; t2n += bd * g0n; t1n += bb * g1n; dnn += bb * g2n;
-                }
-                const int64_t fid = s ? cid : (int64_t)nb;
-                const T *fd = face + (fid * 3 + d) * 7 * NF + a + N * b;
-                const T gm0 = fd[0], gm1 = fd[NF], gm2 = fd[2 * NF];
-                const T gp0 = fd[3 * NF], gp1 = fd[4 * NF], gp2 = fd[5 * NF];
-                const T pen = fd[6 * NF];
-                // reference gradients in (xi, eta, zeta) order
-                T go[3], gn[3];
-                const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-                go[d] = dno; go[t1] = t1o; go[t2] = t2o;
-                gn[d] = dnn; gn[t1] = t1n; gn[t2] = t2n;
-                const T fo = s ? (gm0 * go[0] + gm1 * go[1] + gm2 * go[2])
-                               : (gp0 * go[0] + gp1 * go[1] + gp2 * go[2]);
-                const T fn = s ? (gp0 * gn[0] + gp1 * gn[1] + gp2 * gn[2])
-                               : (gm0 * gn[0] + gm1 * gn[1] + gm2 * gn[2]);
-                const T flux = fo + fn;
-                const T jump = s ? (vo - vn) : (vn - vo);
-                const T sg = s ? T(1) : T(-1);
-                const T cv = sg * (T(-0.5) * flux + pen * jump);
-                const T hj = T(-0.5) * jump;
-                T cg[3];
-                cg[0] = hj * (s ? gm0 : gp0);
-                cg[1] = hj * (s ? gm1 : gp1);
-                cg[2] = hj * (s ? gm2 : gp2);
-                sF[lc][0][a + N * b] = cv;
-                sF[lc][1][a + N * b] = cg[t2];
-                sF[lc][2][a + N * b] = cg[t1];
-                sF[lc][3][a + N * b] = cg[d];
-            }
-            __syncthreads();
-            // R2: thread (q1=a, r=b): transpose along the second tangential direction
-            if (fact) {
-                T h0 = 0, h1 = 0, h2 = 0;
-#pragma unroll
-                for (int q = 0; q < N; ++q) {
-                    const T bb = tB<T, N>(q, b), bd = tD<T, N>(q, b);
-                    h0 += bb * sF[lc][0][a + N * q] + bd * sF[lc][1][a + N * q];
-                    h1 += bb * sF[lc][2][a + N * q];
-                    h2 += bb * sF[lc][3][a + N * q];
-                }
-                sF[lc][4][a + N * b] = h0;
-                sF[lc][5][a + N * b] = h1;
-                sF[lc][6][a + N * b] = h2;
-            }
-            __syncthreads();
-            // R1 + R0: thread (p=a, r=b): transpose along the first tangential
-            // direction, then spread onto the own normal pencil
-            if (fact) {
-                T f0 = 0, f1 = 0;
-#pragma unroll
-                for (int q = 0; q < N; ++q) {
-                    const T bb = tB<T, N>(q, a), bd = tD<T, N>(q, a);
-                    f0 += bb * sF[lc][4][q + N * b] + bd * sF[lc][5][q + N * b];
-                    f1 += bb * sF[lc][6][q + N * b];
-                }
-                if (d == 0) {
-#pragma unroll
-                    for (int m = 0; m < N; ++m)
-                        Y[m] += tE<T, N>(eo, m) * f1 + ((m == (eo ? N - 1 : 0)) ? f0 : T(0));
-                } else {
-#pragma unroll
-                    for (int m = 0; m < N; ++m) {
-                        const int id = lix<N>(d, m, a, b);
-                        YF[id] += tE<T, N>(eo, m) * f1 + ((m == (eo ? N - 1 : 0)) ? f0 : T(0));
-                    }
-                }
+                G[a + N * j + NF * b] = s0v[j];
+                G[ND + a + N * j + NF * b] = s1v[j];
             }
         }
     }
     __syncthreads();
-    if (active) {
-        const int64_t o = cid * ND + N * a + NF * b;
+    // transposed x sweep: lane (j=a, l=b) keeps its output pencil in Y
+    if (cl) {
+        T p0[N], p1[N];
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            p0[q] = G[q + N * a + NF * b];
+            p1[q] = G[ND + q + N * a + NF * b];
+        }
 #pragma unroll
         for (int i = 0; i < N; ++i) {
-            const T val = Y[i] + YF[i + N * a + NF * b];
-            y[o + i] = bvec ? bvec[o + i] - val : val;
+            T sacc = 0;
+#pragma unroll
+            for (int q = 0; q < N; ++q) sacc += tB<T, N>(q, i) * p0[q] + tD<T, N>(q, i) * p1[q];
+            Y[i] = sacc;
         }
+    }
+    __syncthreads();
+
+    // =========================================================== face part
+    // step 1, lane (f, r): layers and normal derivatives of both sides on row
+    // r, then interpolation along the first tangential direction
+    if (fl) {
+        const int eo = s, en = 1 - s;
+        const int mo = eo ? N - 1 : 0, mn = en ? N - 1 : 0;
+        const T *xn = x + (int64_t)nb * ND;
+        T Lo[N], No[N], Ln[N], Nn[N];
+#pragma unroll
+        for (int p = 0; p < N; ++p) {
+            T so = 0, sn = 0;
+#pragma unroll
+            for (int m = 0; m < N; ++m) {
+                const int id = lix<N>(d, m, p, rr);
+                so += tE<T, N>(eo, m) * U[id];
+                sn += tE<T, N>(en, m) * xn[id];
+            }
+            No[p] = so;
+            Nn[p] = sn;
+            Lo[p] = U[lix<N>(d, mo, p, rr)];
+            Ln[p] = xn[lix<N>(d, mn, p, rr)];
+        }
+        T *gw = G + f * 6 * NF + rr * N;
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            T g0 = 0, g1 = 0, g2 = 0, g3 = 0, g4 = 0, g5 = 0;
+#pragma unroll
+            for (int p = 0; p < N; ++p) {
+                const T bb = tB<T, N>(q, p), bd = tD<T, N>(q, p);
+                g0 += bb * Lo[p]; g1 += bd * Lo[p]; g2 += bb * No[p];
+                g3 += bb * Ln[p]; g4 += bd * Ln[p]; g5 += bb * Nn[p];
+            }
+            gw[0 * NF + q] = g0; gw[1 * NF + q] = g1; gw[2 * NF + q] = g2;
+            gw[3 * NF + q] = g3; gw[4 * NF + q] = g4; gw[5 * NF + q] = g5;
+        }
+    }
+    __syncthreads();
+    // the own values are no longer needed: the output pencils wait in sU
+    if (cl) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) sU[cs][i + N * a + NF * b] = Y[i];
+    }
+    // step 2, lane (f, q1): second tangential direction, flux terms at the
+    // Gauss points, transposed sweep back along it.  The neighbour side is
+    // evaluated first (its flux and value per point), then the own side.
+    {
+        T A0[N], A1[N], A2[N];
+        const int q1 = rr;
+        if (fl) {
+            const int64_t fid = s ? cid : (int64_t)nb;
+            const T *fd = face + (fid * 3 + d) * 7 * NF + q1;
+            const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+            const T *gr = G + f * 6 * NF + q1;
+            // g of the neighbour side: g+ if the own cell is the minus cell
+            const int gn_off = s ? 3 : 0, go_off = s ? 0 : 3;
+            T fnb[N], vnb[N];
+            {
+                T h0[N], h1[N], h2[N];
+#pragma unroll
+                for (int r = 0; r < N; ++r) {
+                    h0[r] = gr[3 * NF + r * N];
+                    h1[r] = gr[4 * NF + r * N];
+                    h2[r] = gr[5 * NF + r * N];
+                }
+#pragma unroll
+                for (int q2 = 0; q2 < N; ++q2) {
+                    T vn = 0, t2n = 0, t1n = 0, dnn = 0;
+#pragma unroll
+                    for (int r = 0; r < N; ++r) {
+                        const T bb = tB<T, N>(q2, r), bd = tD<T, N>(q2, r);
+                        vn += bb * h0[r]; t2n += bd * h0[r]; t1n += bb * h1[r]; dnn += bb * h2[r];
+                    }
+                    const T *fq = fd + N * q2 + gn_off * NF;
+                    T gn[3];
+                    gn[d] = dnn; gn[t1] = t1n; gn[t2] = t2n;
+                    fnb[q2] = fq[0] * gn[0] + fq[NF] * gn[1] + fq[2 * NF] * gn[2];
+                    vnb[q2] = vn;
+                }
+            }
+            T h0[N], h1[N], h2[N];
+#pragma unroll
+            for (int r = 0; r < N; ++r) {
+                h0[r] = gr[r * N];
+                h1[r] = gr[NF + r * N];
+                h2[r] = gr[2 * NF + r * N];
+                A0[r] = A1[r] = A2[r] = 0;
+            }
+#pragma unroll
+            for (int q2 = 0; q2 < N; ++q2) {
+                T vo = 0, t2o = 0, t1o = 0, dno = 0;
+#pragma unroll
+                for (int r = 0; r < N; ++r) {
+                    const T bb = tB<T, N>(q2, r), bd = tD<T, N>(q2, r);
+                    vo += bb * h0[r]; t2o += bd * h0[r]; t1o += bb * h1[r]; dno += bb * h2[r];
+                }
+                const T *fq = fd + N * q2 + go_off * NF;
+                const T g0 = fq[0], g1 = fq[NF], g2 = fq[2 * NF];
+                const T pen = fd[6 * NF + N * q2];
+                T go[3];
+                go[d] = dno; go[t1] = t1o; go[t2] = t2o;
+                const T flux = g0 * go[0] + g1 * go[1] + g2 * go[2] + fnb[q2];
+                const T jump = s ? (vo - vnb[q2]) : (vnb[q2] - vo);
+                const T sg = s ? T(1) : T(-1);
+                const T cv = sg * (T(-0.5) * flux + pen * jump);
+                const T hj = T(-0.5) * jump;
+                T cg[3] = {hj * g0, hj * g1, hj * g2};
+                const T ct2 = cg[t2], ct1 = cg[t1], cn = cg[d];
+#pragma unroll
+                for (int r = 0; r < N; ++r) {
+                    const T bb = tB<T, N>(q2, r), bd = tD<T, N>(q2, r);
+                    A0[r] += bb * cv + bd * ct2;
+                    A1[r] += bb * ct1;
+                    A2[r] += bb * cn;
+                }
+            }
+        }
+        __syncthreads();
+        if (fl) {
+            T *gw = G + f * 3 * NF + q1;
+#pragma unroll
+            for (int r = 0; r < N; ++r) {
+                gw[r * N] = A0[r];
+                gw[NF + r * N] = A1[r];
+                gw[2 * NF + r * N] = A2[r];
+            }
+        }
+    }
+    __syncthreads();
+    // step 3, lane (f, r): transposed sweep along the first tangential
+    // direction; the layer (F0) and normal-derivative (F1) weights of row r
+    if (fl0) {
+        T *out = G + 18 * NF + f * 2 * NF + rr * N;
+        if (fl) {
+            const T *gr = G + f * 3 * NF + rr * N;
+            T h0[N], h1[N], h2[N];
+#pragma unroll
+            for (int q = 0; q < N; ++q) {
+                h0[q] = gr[q];
+                h1[q] = gr[NF + q];
+                h2[q] = gr[2 * NF + q];
+            }
+#pragma unroll
+            for (int p = 0; p < N; ++p) {
+                T f0 = 0, f1 = 0;
+#pragma unroll
+                for (int q = 0; q < N; ++q) {
+                    f0 += tB<T, N>(q, p) * h0[q] + tD<T, N>(q, p) * h1[q];
+                    f1 += tB<T, N>(q, p) * h2[q];
+                }
+                out[p] = f0;
+                out[NF + p] = f1;
+            }
+        } else {
+#pragma unroll
+            for (int p = 0; p < N; ++p) out[p] = out[NF + p] = 0;
+        }
+    }
+    __syncthreads();
+    // pencil owners (j=a, l=b) add the six faces' contributions
+    if (cl) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) Y[i] = sU[cs][i + N * a + NF * b];
+        const T *F = G + 18 * NF;
+        // x faces: normal coordinate i, (p, r) = (j, l)
+#pragma unroll
+        for (int sx = 0; sx < 2; ++sx) {
+            const T f0 = F[(0 + sx) * 2 * NF + b * N + a], f1 = F[(0 + sx) * 2 * NF + NF + b * N + a];
+#pragma unroll
+            for (int i = 0; i < N; ++i)
+                Y[i] += tE<T, N>(sx, i) * f1 + ((i == (sx ? N - 1 : 0)) ? f0 : T(0));
+        }
+        // y faces: normal coordinate j = a, (p, r) = (i, l)
+#pragma unroll
+        for (int sy = 0; sy < 2; ++sy) {
+            const T *F0 = F + (2 + sy) * 2 * NF + b * N, *F1 = F0 + NF;
+            T e1 = 0;
+            // DL[sy][a] with a lane-dependent index: unrolled select
+#pragma unroll
+            for (int m = 0; m < N; ++m)
+                if (m == a) e1 = tE<T, N>(sy, m);
+            const bool on = a == (sy ? N - 1 : 0);
+#pragma unroll
+            for (int i = 0; i < N; ++i) Y[i] += e1 * F1[i] + (on ? F0[i] : T(0));
+        }
+        // z faces: normal coordinate l = b, (p, r) = (i, j)
+#pragma unroll
+        for (int sz = 0; sz < 2; ++sz) {
+            const T *F0 = F + (4 + sz) * 2 * NF + a * N, *F1 = F0 + NF;
+            T e1 = 0;
+#pragma unroll
+            for (int m = 0; m < N; ++m)
+                if (m == b) e1 = tE<T, N>(sz, m);
+            const bool on = b == (sz ? N - 1 : 0);
+#pragma unroll
+            for (int i = 0; i < N; ++i) Y[i] += e1 * F1[i] + (on ? F0[i] : T(0));
+        }
+        const int64_t o = cid * ND + N * a + NF * b;
+#pragma unroll
+        for (int i = 0; i < N; ++i) y[o + i] = bvec ? bvec[o + i] - Y[i] : Y[i];
     }
 }
 
 template <int N, typename T>
 hipError_t apply_n(hx_ctx *c, const T *x, T *y, const T *b)
 {
-    const int cpb = Cfg<N>::CPB;
-    const int nwg = (int)((c->n_cells + cpb - 1) / cpb);
+    const int cpw = Cfg<N>::CPW;
+    const int nwg = (int)((c->n_cells + cpw - 1) / cpw);
     const T *cell = std::is_same<T, double>::value ? (const T *)c->cell64 : (const T *)c->cell32;
     const T *face = std::is_same<T, double>::value ? (const T *)c->face64 : (const T *)c->face32;
-    hipLaunchKernelGGL((k_apply<N, T>), dim3(nwg), dim3(Cfg<N>::NT), 0, c->stream, x, y, b, cell,
-                       face, c->nbr, (int)c->n_cells, nwg);
+    hipLaunchKernelGGL((k_apply<N, T>), dim3(nwg), dim3(64), 0, c->stream, x, y, b, cell, face,
+                       c->nbr, c->order, (int)c->n_cells, nwg);
     return hipGetLastError();
 }
 

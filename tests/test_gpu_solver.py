@@ -1,0 +1,177 @@
+"""GPU Krylov solves (steps a6, a7, a8) against the oracle and the paper's
+definitions: the true FP64 residual is the judge.  Solutions are compared to
+the oracle's 1e-13 solve within kappa_est * rtol; iteration counts are not
+unique (CGS2 on the GPU vs modified Gram-Schmidt in the oracle)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth_inputs as si
+from helpers import gpu_context, normwise, problem, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _hx():
+    import paper_2505_00384_amd as hx
+    return hx
+
+
+def test_cg_periodic_cube_matches_dense_solve():
+    hx = _hx()
+    p = problem(si.cube_mesh(4), 2, coef="const")
+    A = p.assemble_dense()
+    kappa = np.linalg.cond(A)
+    for seed in range(3):
+        print(f"[solve] cg cube4 k=2 seed={seed}", flush=True)
+        b = si.rhs_cube(seed)(*p.dof_coords())
+        xs = np.linalg.solve(A, b)
+        ctx = gpu_context(p)
+        x, info = ctx.solve(to_dev(b), params=hx.default_params(method=0, rtol=1e-10))
+        assert info["status"] == hx.HX_OK and info["true_rel_res"] <= 1e-10
+        err = np.linalg.norm(x.cpu().numpy() - xs) / np.linalg.norm(xs)
+        assert err <= kappa * 1e-10, (err, kappa)
+        ctx.close()
+
+
+def test_block_jacobi_reduces_cg_iterations():
+    hx = _hx()
+    p = problem(si.terrain_mesh(8, 2, 4, g=4), 4, coef="terrain")
+    ctx = gpu_context(p)
+    b = to_dev(si.rhs_terrain(1)(*p.dof_coords()))
+    _, i_bj = ctx.solve(b, params=hx.default_params(method=0, rtol=1e-8, pc=hx.HX_PC_BLOCK_JACOBI))
+    _, i_no = ctx.solve(b, params=hx.default_params(method=0, rtol=1e-8, pc=hx.HX_PC_NONE,
+                                                     max_iter=20000))
+    assert i_bj["status"] == hx.HX_OK and i_no["status"] == hx.HX_OK
+    assert i_bj["iters"] < i_no["iters"]
+    ctx.close()
+
+
+@pytest.fixture(scope="module")
+def terrain_small():
+    p = problem(si.terrain_mesh(8, 2, 4, g=4), 4, coef="terrain")
+    b = si.rhs_terrain(7)(*p.dof_coords())
+    xs, info = oracle.solvers.cg(p.apply, b, precond=p.bj_apply, rtol=1e-13, max_iter=5000)
+    assert info.converged
+    return p, b, xs
+
+
+def test_fgmres_fp64_vs_oracle(terrain_small):
+    hx = _hx()
+    p, b, xs = terrain_small
+    ctx = gpu_context(p)
+    for restart in (5, 30):
+        print(f"[solve] fgmres restart={restart}", flush=True)
+        x, info = ctx.solve(to_dev(b), params=hx.default_params(method=1, restart=restart, rtol=1e-8),
+                            history=200)
+        assert info["status"] == hx.HX_OK and info["true_rel_res"] <= 1e-8
+        # estimates decrease monotonically within FGMRES
+        h = info["history"]
+        assert all(h[i + 1] <= h[i] * (1 + 1e-12) for i in range(len(h) - 1) if i + 1 < len(h))
+        err = np.linalg.norm(x.cpu().numpy() - xs) / np.linalg.norm(xs)
+        assert err <= 1e-6, err
+    ctx.close()
+
+
+def test_mixed_precision_solution_error(terrain_small):
+    hx = _hx()
+    p, b, xs = terrain_small
+    ctx = gpu_context(p)
+    x, info = ctx.solve(to_dev(b), params=hx.default_params(method=1, restart=10, rtol=1e-8,
+                                                             mixed=1, inner_iters=12))
+    assert info["status"] == hx.HX_OK and info["true_rel_res"] <= 1e-8
+    assert info["inner_iters"] >= 12
+    err = np.linalg.norm(x.cpu().numpy() - xs) / np.linalg.norm(xs)
+    assert err <= 1e-7, err
+    ctx.close()
+
+
+def test_initial_guess_zero_rhs_and_errors(terrain_small):
+    hx = _hx()
+    import torch
+    p, b, xs = terrain_small
+    ctx = gpu_context(p)
+    # exact initial guess: converged before the first iteration
+    x0 = to_dev(xs)
+    x, info = ctx.solve(to_dev(b), x=x0.clone(), params=hx.default_params(method=1, x0_mode=1))
+    assert info["iters"] == 0 and info["true_rel_res"] <= 1e-8
+    # zero right-hand side gives x = 0
+    z = torch.zeros(p.n_dofs, dtype=torch.float64, device="cuda:0")
+    x, info = ctx.solve(z, x=torch.ones_like(z), params=hx.default_params(method=1))
+    assert info["status"] == hx.HX_OK and torch.count_nonzero(x) == 0
+    # iteration cap: not converged, but info and the best x are written
+    x, info = ctx.solve(to_dev(b), params=hx.default_params(method=1, max_iter=2), check=False)
+    assert info["status"] == hx.HX_ERR_NOCONV and info["iters"] == 2
+    assert 1e-8 < info["true_rel_res"] < 1.0
+    # argument errors
+    with pytest.raises(hx.HXError) as e:
+        ctx.solve(to_dev(b), params=hx.default_params(method=1, restart=0))
+    assert e.value.status == hx.HX_ERR_ARG
+    with pytest.raises(hx.HXError) as e:
+        ctx.solve(to_dev(b), params=hx.default_params(method=0, pc=hx.HX_PC_LEARNED))
+    assert e.value.status == hx.HX_ERR_ARG
+    ctx.close()
+
+
+def test_call_order_and_mesh_errors():
+    hx = _hx()
+    import torch
+    ctx = hx.HelmDG(0)
+    v = torch.zeros(8, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(hx.HXError) as e:
+        ctx.apply_operator(v)
+    assert e.value.status == hx.HX_ERR_STATE
+    m = si.cube_mesh(2)
+    bad = m.nbr.copy(); bad[0, 1] = 5                     # does not point back
+    with pytest.raises(hx.HXError) as e:
+        ctx.setup_mesh(1, m.nodes, bad, 1)
+    assert e.value.status == hx.HX_ERR_MESH
+    inv = m.nodes.copy(); inv[3, :, 0] *= -1.0            # mirrored cell: detJ < 0
+    with pytest.raises(hx.HXError) as e:
+        ctx.setup_mesh(1, inv, m.nbr, 1)
+    assert e.value.status == hx.HX_ERR_MESH
+    with pytest.raises(hx.HXError) as e:
+        ctx.setup_mesh(99, m.nodes, m.nbr, 1)
+    assert e.value.status == hx.HX_ERR_ARG
+    ctx.setup_mesh(1, m.nodes, m.nbr, 1)
+    with pytest.raises(hx.HXError) as e:
+        ctx.solve(torch.zeros(ctx.n_dofs, dtype=torch.float64, device="cuda:0"))
+    assert e.value.status == hx.HX_ERR_STATE
+    ctx.close()
+
+
+def test_dot_deterministic():
+    import torch
+    p = problem(si.cube_mesh(2), 1)
+    ctx = gpu_context(p)
+    for n in (1, 1000, 3_000_001):
+        a = si.random_vector(n, 1); b = si.random_vector(n, 2)
+        ta, tb = to_dev(a), to_dev(b)
+        d1 = ctx.dot(ta, tb)
+        assert abs(d1 - float(a @ b)) <= 1e-12 * np.abs(a).dot(np.abs(b))
+        assert all(ctx.dot(ta, tb) == d1 for _ in range(3))
+    ctx.close()
+
+
+def test_terrain_32x8x16_forms_agree():
+    """The 32x8x16 Q4 channel: FP64 FGMRES(30)+BJ, FP64 CG+BJ and the mixed
+    form all reach 1e-8; their solutions agree within the solve tolerance
+    times a conditioning allowance."""
+    hx = _hx()
+    print("[solve] terrain 32x8x16", flush=True)
+    p = problem(si.terrain_mesh(32, 8, 16, g=4), 4, coef="terrain")
+    ctx = gpu_context(p)
+    b = to_dev(si.rhs_terrain(0)(*p.dof_coords()))
+    xr, ir = ctx.solve(b, params=hx.default_params(method=0, rtol=1e-12))
+    assert ir["status"] == hx.HX_OK
+    ref = xr.cpu().numpy()
+    for name, prm in [("fgmres", hx.default_params(method=1, restart=30, rtol=1e-8)),
+                      ("cg", hx.default_params(method=0, rtol=1e-8)),
+                      ("mixed", hx.default_params(method=1, restart=10, rtol=1e-8, mixed=1,
+                                                  inner_iters=12))]:
+        x, info = ctx.solve(b, params=prm)
+        print(f"[solve] {name}: {info}", flush=True)
+        assert info["status"] == hx.HX_OK and info["true_rel_res"] <= 1e-8
+        err = np.linalg.norm(x.cpu().numpy() - ref) / np.linalg.norm(ref)
+        assert err <= 1e-6, (name, err)
+    ctx.close()
