@@ -217,8 +217,44 @@ def main():
         ctx2, xyz2, _ = setup(hx.HelmDG, m2, k, torch, dev)
         b2 = rhs_on_device(xyz2, 0, torch)
         forms2 = forms + [("fp64_cg_bj", hx.default_params(method=0, rtol=1e-8, pc=hx.HX_PC_BLOCK_JACOBI))]
+        # learned form: network trained on the periodic unit cube (Q4), then used here
+        from paper_2505_00384_amd import learned
+        t0 = time.time()
+        F, T = learned.generate_pairs(100000, seed=0, log=log)
+        ctx2.set_network(learned.init_weights(ctx2, seed=0))
+        learned.train(ctx2, F, T, steps=3000, batch=2048, lr=1e-3, log=log, log_every=1000)
+        t_train = time.time() - t0
+        del F, T
+        forms2.append(("learned_fgmres", hx.default_params(method=1, restart=30, rtol=1e-8,
+                                                           pc=hx.HX_PC_LEARNED)))
         solve["terrain32x8x16"] = solve_suite(hx, ctx2, b2, torch, forms2, "C2")
+        solve["learned_training_s"] = round(t_train, 2)
+        w = ctx2.get_network()
         ctx2.close()
+        # the periodic unit cube: degree 2 CG + block Jacobi to 1e-10, and the
+        # learned form at degree 4 on the same mesh
+        m1 = si.cube_mesh(4)
+        c1 = hx.HelmDG(0)
+        c1.setup_mesh(2, m1.nodes, m1.nbr, 1)
+        x1 = c1.dof_coordinates()
+        ones = torch.ones(c1.n_dofs, dtype=torch.float64, device=dev)
+        c1.set_coefficients(ones, 0.01 * ones, 2.0)
+        b1 = field_on_device(si.rhs_cube(0), x1, torch)
+        solve["cube4_q2"] = solve_suite(hx, c1, b1, torch, [
+            ("fp64_cg_bj_1e-10", hx.default_params(method=0, rtol=1e-10))], "C1")
+        c1.close()
+        c5 = hx.HelmDG(0)
+        c5.setup_mesh(4, m1.nodes, m1.nbr, 1)
+        x5 = c5.dof_coordinates()
+        ones = torch.ones(c5.n_dofs, dtype=torch.float64, device=dev)
+        c5.set_coefficients(ones, 0.01 * ones, 2.0)
+        c5.set_network(w)
+        b5 = field_on_device(si.rhs_cube(101), x5, torch)
+        solve["cube4_q4"] = solve_suite(hx, c5, b5, torch, [
+            ("fp64_fgmres_bj", hx.default_params(method=1, restart=30, rtol=1e-8)),
+            ("learned_fgmres", hx.default_params(method=1, restart=30, rtol=1e-8, pc=hx.HX_PC_LEARNED))],
+            "C5")
+        c5.close()
     else:
         ctx.close()
 

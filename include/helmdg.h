@@ -131,7 +131,7 @@ hx_status hx_set_coefficients(hx_ctx *c, const double *alpha, const double *beta
  * geometry and accumulates in FP32.  x and y must not alias. */
 hx_status hx_apply_operator(hx_ctx *c, hx_prec prec, const void *x, void *y);
 
-/* r = b - A x in FP64.  r may alias b but not x. */
+/* r = b - A x in FP64.  r must not alias b or x. */
 hx_status hx_residual(hx_ctx *c, const double *b, const double *x, double *r);
 
 /* ---------------------------------------------------------------------- */
@@ -145,7 +145,8 @@ hx_status hx_residual(hx_ctx *c, const double *b, const double *x, double *r);
  * with S^T M S = I, S^T L S = Lambda -- the tensor-product inverse of
  * block-diagonal operators of section 3.3, with the 1-D SIP blocks in place of
  * the mass.  HX_PC_LEARNED (FP64 only; needs hx_set_network): block Jacobi
- * plus the per-cell network correction.  HX_PC_NONE copies r.  r and z must
+ * plus the per-cell network correction w_K net(features(r))_K, with w_K the
+ * RMS of the block-Jacobi output on cell K.  HX_PC_NONE copies r.  r and z must
  * not alias. */
 hx_status hx_apply_preconditioner(hx_ctx *c, hx_pc kind, hx_prec prec,
                                   const void *r, void *z);
@@ -176,7 +177,9 @@ typedef struct {
     int inner_iters;     /* total inner (FP32) iterations, mixed form */
     double true_rel_res; /* ||b - A x||_2 / ||b||_2 in FP64, recomputed at the end */
     double ms_total;     /* wall time of the solve (host clock) */
-    double ms_op, ms_pc, ms_orth;  /* device time per phase (HIP events) */
+    double ms_op, ms_pc, ms_orth;  /* device time per phase (HIP events): operator,
+                                      preconditioner, orthogonalisation (FGMRES) or
+                                      vector updates and dot products (CG) */
     double *history;     /* optional HOST buffer: residual estimate per iteration */
     int history_len;     /* in: capacity of history; out: entries written */
 } hx_solve_info;
@@ -220,6 +223,15 @@ hx_status hx_get_network(const hx_ctx *c, float *master_weights, int64_t n);
  * coefficient feature log(bbar/(abar l^2)), all but the last divided by
  * s = RMS(r_K)), scale DEVICE float [n_cells] (s). */
 hx_status hx_gather_features(hx_ctx *c, const double *r, float *feats, float *scale);
+
+/* Training pair of every cell from an iterate x_j of a solve of A x = b whose
+ * converged solution is x_star (all DEVICE FP64 [n_dofs]): with r = b - A x_j
+ * and e = x_star - x_j, feats = features(r) as in hx_gather_features and
+ * targets DEVICE float [n_cells][n_out] = (e_K - BJ(r)_K) / w_K, w_K = RMS(BJ(r)_K):
+ * the part of the error that block Jacobi misses, in the network's output
+ * scaling. */
+hx_status hx_training_pair(hx_ctx *c, const double *b, const double *x_star, const double *x_j,
+                           float *feats, float *targets);
 
 /* out DEVICE float [batch][n_out] = network(feats DEVICE float [batch][n_in]). */
 hx_status hx_network_forward(hx_ctx *c, const float *feats, int64_t batch, float *out);

@@ -14,8 +14,8 @@ Features of a cell K (all divided by s = RMS(r_K); zero when s = 0):
     Gauss-Lobatto nodes of the shared face (lexicographic in the two
     tangential directions, lower direction fastest; zeros on a boundary),
     log(beta_bar / (alpha_bar * ell^2)) with ell = (lx ly lz)^(1/3) ]
-The correction is s * MLP(features); the preconditioner adds it to the
-cell-block Jacobi result.
+The preconditioner is z = BJ(r) + w_K MLP(features)_K per cell, with w_K the
+RMS of the block-Jacobi output BJ(r)_K.
 """
 from __future__ import annotations
 
@@ -134,3 +134,15 @@ def features(r: np.ndarray, nbr: np.ndarray, n: int, coef: np.ndarray):
                 F[c, nd + f * n * n: nd + (f + 1) * n * n] = face_layer(R[nb], n, f) * inv[c]
     F[:, -1] = np.where(s > 0, coef, 0.0)
     return F, s
+
+
+def precondition(p, params, r, coef):
+    """z = BJ(r) + w_K net(features(r))_K with w_K = RMS(BJ(r)_K); p is an
+    oracle Problem (its separable block Jacobi), coef the per-cell coefficient
+    feature."""
+    z = p.bj_apply(r)
+    F, _ = features(r, p.nbr, p.n, coef)
+    out, _ = forward(params, F, bf16=True)
+    Z = z.reshape(p.n_cells, -1)
+    w = np.sqrt(np.mean(Z * Z, axis=1))
+    return (Z + w[:, None] * out).ravel()

@@ -85,6 +85,7 @@ def load(path: str = LIB_PATH):
         "hx_get_network": ([vp, vp, i64], C.c_int),
         "hx_gather_features": ([vp, vp, vp, vp], C.c_int),
         "hx_network_forward": ([vp, vp, i64, vp], C.c_int),
+        "hx_training_pair": ([vp, vp, vp, vp, vp, vp], C.c_int),
         "hx_train_step": ([vp, vp, vp, i64, C.c_float, C.POINTER(C.c_float), vp], C.c_int),
         "hx_debug_export": ([vp, C.c_int, vp, i64], C.c_int),
     }
@@ -252,6 +253,16 @@ class HelmDG:
         self._chk(self.L.hx_gather_features(self.h, _ptr(r), _ptr(F), _ptr(s)), "gather_features")
         return F, s
 
+    def training_pair(self, b, x_star, x_j):
+        """Per-cell features and residual-learning targets from a solver iterate."""
+        F = self.torch.empty(self.n_cells, self.n_features(), dtype=self.torch.float32,
+                             device=b.device)
+        T = self.torch.empty(self.n_cells, (self.k + 1) ** 3, dtype=self.torch.float32,
+                             device=b.device)
+        self._chk(self.L.hx_training_pair(self.h, _ptr(b), _ptr(x_star), _ptr(x_j), _ptr(F), _ptr(T)),
+                  "training_pair")
+        return F, T
+
     def network_forward(self, feats):
         n_out = (self.k + 1) ** 3
         out = self.torch.empty(feats.shape[0], n_out, dtype=self.torch.float32, device=feats.device)
@@ -259,15 +270,17 @@ class HelmDG:
                   "network_forward")
         return out
 
-    def train_step(self, feats, targets, lr: float, want_grad: bool = False):
+    def train_step(self, feats, targets, lr: float, want_grad: bool = False,
+                   want_loss: bool = True):
         loss = C.c_float()
         g = None
         if want_grad:
             g = self.torch.empty(self.network_size(), dtype=self.torch.float32, device=feats.device)
         self._chk(self.L.hx_train_step(self.h, _ptr(feats), _ptr(targets), feats.shape[0],
-                                       float(lr), C.byref(loss), _ptr(g) if g is not None else None),
+                                       float(lr), C.byref(loss) if want_loss else None,
+                                       _ptr(g) if g is not None else None),
                   "train_step")
-        return loss.value, g
+        return (loss.value if want_loss else None), g
 
     def debug_export(self, what: int, shape, dtype=np.float64) -> np.ndarray:
         out = np.zeros(shape, dtype=dtype)

@@ -278,7 +278,7 @@ hx_status hx_residual(hx_ctx *c, const double *b, const double *x, double *r)
     if (!c) return HX_ERR_ARG;
     if (!c->has_coef) return fail(c, HX_ERR_STATE, "residual before setup_mesh/set_coefficients");
     if (!b || !x || !r) return fail(c, HX_ERR_ARG, "null vector");
-    if (x == r) return fail(c, HX_ERR_ARG, "x and r alias");
+    if (x == r || b == r) return fail(c, HX_ERR_ARG, "r aliases x or b");
     HX_HIP(c, launch_apply64(c, x, r, b));
     return HX_OK;
 }
@@ -340,6 +340,16 @@ hx_status hx_gather_features(hx_ctx *c, const double *r, float *feats, float *sc
     if (!c->has_coef) return fail(c, HX_ERR_STATE, "features before set_coefficients");
     if (!r || !feats || !scale) return fail(c, HX_ERR_ARG, "null pointer");
     return mlp_features(c, r, feats, scale);
+}
+
+hx_status hx_training_pair(hx_ctx *c, const double *b, const double *x_star, const double *x_j,
+                           float *feats, float *targets)
+{
+    if (!c) return HX_ERR_ARG;
+    if (!c->has_coef) return fail(c, HX_ERR_STATE, "training pair before set_coefficients");
+    if (!b || !x_star || !x_j || !feats || !targets) return fail(c, HX_ERR_ARG, "null pointer");
+    if (x_j == b) return fail(c, HX_ERR_ARG, "x_j and b alias");
+    return mlp_training_pair(c, b, x_star, x_j, feats, targets);
 }
 
 hx_status hx_network_forward(hx_ctx *c, const float *feats, int64_t batch, float *out)

@@ -164,5 +164,7 @@ hx_status mlp_forward(hx_ctx *c, const float *feats, int64_t batch, float *out);
 hx_status mlp_train(hx_ctx *c, const float *feats, const float *targets, int64_t batch,
                     float lr, float *loss_out, float *grad_out);
 hx_status mlp_precondition(hx_ctx *c, const double *r, double *z, int *nonfinite);
+hx_status mlp_training_pair(hx_ctx *c, const double *b, const double *xs, const double *xj,
+                            float *feats, float *targets);
 
 }  // namespace hx

@@ -1,30 +1,619 @@
-// Learned per-cell preconditioner (network kernels).
+// Learned per-cell preconditioner: feature gather, BF16 MFMA network
+// forward/backward, Adam, and the correction added to block Jacobi.
+//
+// Network n_in -> 256 -> 256 -> n_out with ReLU, n_in = N^3 + 6 N^2 + 1,
+// n_out = N^3.  Parameters flat [W1, b1, W2, b2, W3, b3], W row-major
+// [out][in]; FP32 master weights and Adam moments, BF16 working copies.
+// Every product runs on the gfx950 matrix cores (v_mfma_f32_16x16x16_bf16,
+// FP32 accumulation); activations entering a product are BF16 (round to
+// nearest even), biases, losses and gradients of the biases are FP32.
+//
+// Features of cell K (divided by s = RMS(r_K), zero when s = 0): r_K in local
+// order, then for each face -x,+x,-y,+y,-z,+z the neighbour's residual on its
+// N^2 Gauss-Lobatto nodes of the shared face (tangential lexicographic order,
+// lower direction fastest; zero on a boundary), then log(bbar/(abar l^2)).
+// The correction added to block Jacobi is w_K net(features)_K with w_K the RMS
+// of the block-Jacobi output on the cell, so the network works in O(1) units.
 #include "common.hpp"
+
+#include <cmath>
+#include <vector>
 
 namespace hx {
 
+namespace {
+
+constexpr int HID = 256;
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x7FFFFFu)) return 0x7FC0;   // NaN
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// ---------------------------------------------------------------------------
+// C(m, n) = sum_k A(m, k) B(n, k) (+ bias[n]) (ReLU), A(m,k) = A[m*sam + k*sak],
+// B(n,k) = B[n*sbn + k*sbk], BF16 operands, FP32 accumulation on MFMA.
+// 64 x 64 output tile per workgroup of 4 waves, 32 x 32 per wave.
+// ---------------------------------------------------------------------------
+constexpr int TM = 64, TN = 64, TK = 32;
+
+__global__ void __launch_bounds__(256)
+k_gemm(int M, int N, int K, const uint16_t *__restrict__ A, int64_t sam, int64_t sak,
+       const uint16_t *__restrict__ B, int64_t sbn, int64_t sbk, const float *__restrict__ bias,
+       int relu, float *C32, int64_t ldc32, uint16_t *C16, int64_t ldc16)
+{
+    __shared__ uint16_t sA[TM][TK + 4];
+    __shared__ uint16_t sB[TN][TK + 4];
+    const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN;
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += TK) {
+        // stage the tiles (zero outside the matrices)
+        for (int e = t; e < TM * TK; e += 256) {
+            const int r = e / TK, kk = e % TK;
+            const int m = m0 + r, k = k0 + kk;
+            sA[r][kk] = (m < M && k < K) ? A[(int64_t)m * sam + (int64_t)k * sak] : (uint16_t)0;
+            const int n = n0 + r;
+            sB[r][kk] = (n < N && k < K) ? B[(int64_t)n * sbn + (int64_t)k * sbk] : (uint16_t)0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < TK; ks += 16) {
+            // operand layout of the 16x16x16 MFMA: lane l holds
+            //   A[row = l % 16][k = 4 (l / 16) .. +3],  B[k = 4 (l / 16) .. +3][col = l % 16]
+            const int rr = lane & 15, kq = (lane >> 4) * 4;
+            bf16x4 fa[2], fb[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    fa[i][q] = (short)sA[wm + 16 * i + rr][ks + kq + q];
+                    fb[i][q] = (short)sB[wn + 16 * i + rr][ks + kq + q];
+                }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fa[i], fb[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // result layout: lane l holds C[row = 4 (l / 16) + q][col = l % 16], q = 0..3
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + q;
+                const int n = n0 + wn + 16 * j + (lane & 15);
+                if (m < M && n < N) {
+                    float v = acc[i][j][q] + (bias ? bias[n] : 0.f);
+                    if (relu) v = v > 0.f ? v : 0.f;
+                    if (C32) C32[(int64_t)m * ldc32 + n] = v;
+                    if (C16) C16[(int64_t)m * ldc16 + n] = f2bf(v);
+                }
+            }
+}
+
+hipError_t gemm(hipStream_t st, int M, int N, int K, const uint16_t *A, int64_t sam, int64_t sak,
+                const uint16_t *B, int64_t sbn, int64_t sbk, const float *bias, int relu, float *C32,
+                int64_t ldc32, uint16_t *C16, int64_t ldc16)
+{
+    if (M <= 0 || N <= 0) return hipSuccess;
+    dim3 grid((M + TM - 1) / TM, (N + TN - 1) / TN);
+    hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, st, M, N, K, A, sam, sak, B, sbn, sbk, bias, relu,
+                       C32, ldc32, C16, ldc16);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// elementwise / reduction kernels
+// ---------------------------------------------------------------------------
+__global__ void k_weights_to_bf16(int64_t n, const float *__restrict__ w, int rows, int cols,
+                                  int ld, uint16_t *out)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= (int64_t)rows * ld) return;
+    const int r = (int)(i / ld), c = (int)(i % ld);
+    out[i] = c < cols ? f2bf(w[(int64_t)r * cols + c]) : (uint16_t)0;
+    (void)n;
+}
+
+// fp32 [B][n_in] -> bf16 [B][ld]
+__global__ void k_pack(int64_t Bn, int n_in, int ld, const float *__restrict__ x, uint16_t *out)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= Bn * ld) return;
+    const int64_t r = i / ld;
+    const int c = (int)(i % ld);
+    out[i] = c < n_in ? f2bf(x[r * n_in + c]) : (uint16_t)0;
+}
+
+// features: block per cell
+__global__ void __launch_bounds__(128)
+k_features(int n, int64_t n_cells, const double *__restrict__ r, const int32_t *__restrict__ nbr,
+           const double *__restrict__ coef, float *feats, int64_t ldf, uint16_t *fb, int64_t ldb,
+           float *scale)
+{
+    const int64_t c = blockIdx.x;
+    const int nd = n * n * n, nf = n * n;
+    const int n_in = nd + 6 * nf + 1;
+    __shared__ double red[128];
+    double ss = 0.0;
+    for (int e = threadIdx.x; e < nd; e += 128) {
+        const double v = r[c * nd + e];
+        ss += v * v;
+    }
+    red[threadIdx.x] = ss;
+    __syncthreads();
+    for (int s = 64; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    const double sK = sqrt(red[0] / nd);
+    const double inv = sK > 0.0 ? 1.0 / sK : 0.0;
+    for (int e = threadIdx.x; e < n_in; e += 128) {
+        double v = 0.0;
+        if (e < nd) {
+            v = r[c * nd + e] * inv;
+        } else if (e < nd + 6 * nf) {
+            const int f = (e - nd) / nf, t = (e - nd) % nf;
+            const int32_t nb = nbr[c * 6 + f];
+            if (nb >= 0) {
+                const int d = f >> 1, plus = f & 1;
+                const int m = plus ? 0 : n - 1;     // the neighbour's layer touching the face
+                const int p = t % n, q = t / n;      // tangential, lower direction fastest
+                int ijk[3];
+                const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+                ijk[d] = m;
+                ijk[t1] = p;
+                ijk[t2] = q;
+                v = r[(int64_t)nb * nd + ijk[0] + n * (ijk[1] + n * ijk[2])] * inv;
+            }
+        } else {
+            v = sK > 0.0 ? coef[c] : 0.0;
+        }
+        const float fv = (float)v;
+        if (feats) feats[c * ldf + e] = fv;
+        if (fb) fb[c * ldb + e] = f2bf(fv);
+    }
+    if (fb)
+        for (int e = n_in + threadIdx.x; e < ldb; e += 128) fb[c * ldb + e] = 0;
+    if (threadIdx.x == 0) scale[c] = (float)sK;
+}
+
+// d_o = 2 (o - t) / (B n_out) (fp32 and bf16); partial sums of (o - t)^2
+__global__ void __launch_bounds__(256)
+k_loss_grad(int64_t total, float inv_count, const float *__restrict__ o, const float *__restrict__ tg,
+            float *d, uint16_t *db, double *part)
+{
+    __shared__ double sh[256];
+    double s = 0.0;
+    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
+        const float e = o[i] - tg[i];
+        s += (double)e * e;
+        const float g = 2.f * e * inv_count;
+        d[i] = g;
+        db[i] = f2bf(g);
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void __launch_bounds__(256) k_sum_parts(int nb, const double *part, double scale, float *out)
+{
+    __shared__ double sh[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nb; i += 256) s += part[i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = (float)(sh[0] * scale);
+}
+
+// d[b][j] *= (h[b][j] > 0) in place (fp32), bf16 copy
+__global__ void k_relu_back(int64_t total, const float *__restrict__ h, float *d, uint16_t *db)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const float g = h[i] > 0.f ? d[i] : 0.f;
+    d[i] = g;
+    db[i] = f2bf(g);
+}
+
+// column sums out[j] = sum_b d[b][j] (fixed order), block per column
+__global__ void __launch_bounds__(256) k_colsum(int64_t Bn, int ncol, const float *__restrict__ d, float *out)
+{
+    __shared__ double sh[256];
+    const int j = blockIdx.x;
+    double s = 0.0;
+    for (int64_t b = threadIdx.x; b < Bn; b += 256) s += d[b * ncol + j];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[j] = (float)sh[0];
+}
+
+__global__ void k_adam(int64_t n, float *w, const float *__restrict__ g, float *m, float *v, float lr,
+                       float b1, float b2, float eps, float c1, float c2)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// per cell w_K = RMS(z_K) of the block-Jacobi output; z_K += w_K * o_K
+__global__ void __launch_bounds__(128)
+k_add_correction(int nd, const float *__restrict__ o, double *z)
+{
+    const int64_t c = blockIdx.x;
+    __shared__ double red[128];
+    double ss = 0.0;
+    for (int e = threadIdx.x; e < nd; e += 128) {
+        const double v = z[c * nd + e];
+        ss += v * v;
+    }
+    red[threadIdx.x] = ss;
+    __syncthreads();
+    for (int k = 64; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    const double w = sqrt(red[0] / nd);
+    for (int e = threadIdx.x; e < nd; e += 128) z[c * nd + e] += w * (double)o[c * nd + e];
+}
+
+// targets[c][i] = (e[c][i] - z[c][i]) / w_c with e = xs - xj, w_c = RMS(z_c)
+// (0 when w_c = 0)
+__global__ void __launch_bounds__(128)
+k_targets(int nd, const double *__restrict__ xs, const double *__restrict__ xj,
+          const double *__restrict__ z, float *tg)
+{
+    const int64_t c = blockIdx.x;
+    __shared__ double red[128];
+    double ss = 0.0;
+    for (int e = threadIdx.x; e < nd; e += 128) {
+        const double v = z[c * nd + e];
+        ss += v * v;
+    }
+    red[threadIdx.x] = ss;
+    __syncthreads();
+    for (int k = 64; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    const double w = sqrt(red[0] / nd);
+    const double inv = w > 0.0 ? 1.0 / w : 0.0;
+    for (int e = threadIdx.x; e < nd; e += 128) {
+        const int64_t i = c * nd + e;
+        tg[i] = (float)((xs[i] - xj[i] - z[i]) * inv);
+    }
+}
+
+inline unsigned nb256(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
 struct MlpState {
-    int dummy;
+    int n_in = 0, ldx = 0, n_out = 0;
+    int64_t P = 0;
+    int64_t off_w1 = 0, off_b1 = 0, off_w2 = 0, off_b2 = 0, off_w3 = 0, off_b3 = 0;
+    float *w = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
+    uint16_t *w1b = nullptr, *w2b = nullptr, *w3b = nullptr;
+    int64_t t = 0;
+    int64_t cap = 0;
+    uint16_t *xb = nullptr, *h1b = nullptr, *h2b = nullptr, *dob = nullptr, *dh1b = nullptr,
+             *dh2b = nullptr;
+    float *h1 = nullptr, *h2 = nullptr, *o = nullptr, *d_o = nullptr, *dh1 = nullptr,
+          *dh2 = nullptr, *scale = nullptr, *loss = nullptr;
+    double *part = nullptr, *zt = nullptr;
+    float *loss_host = nullptr;
 };
 
-hx_status mlp_create(hx_ctx *c) { return fail(c, HX_ERR_STATE, "network not available"); }
-void mlp_destroy(hx_ctx *c) { (void)c; }
+static void free_batch(MlpState *s)
+{
+    void **b[] = {(void **)&s->xb, (void **)&s->h1b, (void **)&s->h2b, (void **)&s->dob,
+                  (void **)&s->dh1b, (void **)&s->dh2b, (void **)&s->h1, (void **)&s->h2,
+                  (void **)&s->o, (void **)&s->d_o, (void **)&s->dh1, (void **)&s->dh2,
+                  (void **)&s->scale};
+    for (void **p : b) dfree(p);
+    s->cap = 0;
+}
+
+static hx_status ensure_batch(hx_ctx *c, int64_t B)
+{
+    MlpState *s = c->mlp;
+    if (B <= s->cap) return HX_OK;
+    free_batch(s);
+    hx_status st = HX_OK;
+#define A(p, bytes) \
+    if (st == HX_OK) st = dalloc(c, (void **)&(p), (bytes));
+    A(s->xb, 2 * (size_t)B * s->ldx);
+    A(s->h1b, 2 * (size_t)B * HID);
+    A(s->h2b, 2 * (size_t)B * HID);
+    A(s->dob, 2 * (size_t)B * s->n_out);
+    A(s->dh1b, 2 * (size_t)B * HID);
+    A(s->dh2b, 2 * (size_t)B * HID);
+    A(s->h1, 4 * (size_t)B * HID);
+    A(s->h2, 4 * (size_t)B * HID);
+    A(s->o, 4 * (size_t)B * s->n_out);
+    A(s->d_o, 4 * (size_t)B * s->n_out);
+    A(s->dh1, 4 * (size_t)B * HID);
+    A(s->dh2, 4 * (size_t)B * HID);
+    A(s->scale, 4 * (size_t)B);
+#undef A
+    if (st != HX_OK) {
+        free_batch(s);
+        return st;
+    }
+    s->cap = B;
+    return HX_OK;
+}
+
 int64_t mlp_param_count(const hx_ctx *c)
 {
-    const int64_t ni = c->nd + 6 * c->nf + 1, h = 256, no = c->nd;
-    return h * ni + h + h * h + h + no * h + no;
+    const int64_t ni = c->nd + 6 * c->nf + 1, no = c->nd;
+    return HID * ni + HID + HID * HID + HID + no * HID + no;
 }
-hx_status mlp_set(hx_ctx *c, const float *, int64_t) { return fail(c, HX_ERR_STATE, "network not available"); }
-hx_status mlp_get(const hx_ctx *c, float *, int64_t) { (void)c; return HX_ERR_STATE; }
-hx_status mlp_features(hx_ctx *c, const double *, float *, float *) { return fail(c, HX_ERR_STATE, "network not available"); }
-hx_status mlp_forward(hx_ctx *c, const float *, int64_t, float *) { return fail(c, HX_ERR_STATE, "network not available"); }
-hx_status mlp_train(hx_ctx *c, const float *, const float *, int64_t, float, float *, float *)
+
+hx_status mlp_create(hx_ctx *c)
 {
-    return fail(c, HX_ERR_STATE, "network not available");
+    if (c->mlp) return HX_OK;
+    MlpState *s = new MlpState();
+    c->mlp = s;
+    s->n_in = c->nd + 6 * c->nf + 1;
+    s->ldx = ((s->n_in + 31) / 32) * 32;
+    s->n_out = c->nd;
+    s->P = mlp_param_count(c);
+    s->off_w1 = 0;
+    s->off_b1 = s->off_w1 + (int64_t)HID * s->n_in;
+    s->off_w2 = s->off_b1 + HID;
+    s->off_b2 = s->off_w2 + (int64_t)HID * HID;
+    s->off_w3 = s->off_b2 + HID;
+    s->off_b3 = s->off_w3 + (int64_t)s->n_out * HID;
+    hx_status st = HX_OK;
+#define A(p, bytes) \
+    if (st == HX_OK) st = dalloc(c, (void **)&(p), (bytes));
+    A(s->w, 4 * (size_t)s->P);
+    A(s->m, 4 * (size_t)s->P);
+    A(s->v, 4 * (size_t)s->P);
+    A(s->grad, 4 * (size_t)s->P);
+    A(s->w1b, 2 * (size_t)HID * s->ldx);
+    A(s->w2b, 2 * (size_t)HID * HID);
+    A(s->w3b, 2 * (size_t)s->n_out * HID);
+    A(s->part, 8 * 1024);
+    A(s->loss, 16);
+#undef A
+    if (st == HX_OK && hipHostMalloc((void **)&s->loss_host, 16) != hipSuccess) st = HX_ERR_DEVICE;
+    if (st != HX_OK) {
+        mlp_destroy(c);
+        return st;
+    }
+    return HX_OK;
 }
-hx_status mlp_precondition(hx_ctx *c, const double *, double *, int *)
+
+void mlp_destroy(hx_ctx *c)
 {
-    return fail(c, HX_ERR_STATE, "network not available");
+    MlpState *s = c->mlp;
+    if (!s) return;
+    free_batch(s);
+    void **b[] = {(void **)&s->w, (void **)&s->m, (void **)&s->v, (void **)&s->grad,
+                  (void **)&s->w1b, (void **)&s->w2b, (void **)&s->w3b, (void **)&s->part,
+                  (void **)&s->loss, (void **)&s->zt};
+    for (void **p : b) dfree(p);
+    if (s->loss_host) (void)hipHostFree(s->loss_host);
+    delete s;
+    c->mlp = nullptr;
+}
+
+static hipError_t refresh_bf16(hx_ctx *c)
+{
+    MlpState *s = c->mlp;
+    hipLaunchKernelGGL(k_weights_to_bf16, dim3(nb256((int64_t)HID * s->ldx)), dim3(256), 0, c->stream,
+                       s->P, s->w + s->off_w1, HID, s->n_in, s->ldx, s->w1b);
+    hipLaunchKernelGGL(k_weights_to_bf16, dim3(nb256((int64_t)HID * HID)), dim3(256), 0, c->stream,
+                       s->P, s->w + s->off_w2, HID, HID, HID, s->w2b);
+    hipLaunchKernelGGL(k_weights_to_bf16, dim3(nb256((int64_t)s->n_out * HID)), dim3(256), 0,
+                       c->stream, s->P, s->w + s->off_w3, s->n_out, HID, HID, s->w3b);
+    return hipGetLastError();
+}
+
+hx_status mlp_set(hx_ctx *c, const float *w, int64_t n)
+{
+    if (n != mlp_param_count(c))
+        return fail(c, HX_ERR_ARG, "network has %lld parameters, got %lld",
+                    (long long)mlp_param_count(c), (long long)n);
+    hx_status st = mlp_create(c);
+    if (st != HX_OK) return st;
+    MlpState *s = c->mlp;
+    HX_HIP(c, hipMemcpyAsync(s->w, w, 4 * (size_t)n, hipMemcpyHostToDevice, c->stream));
+    HX_HIP(c, hipMemsetAsync(s->m, 0, 4 * (size_t)n, c->stream));
+    HX_HIP(c, hipMemsetAsync(s->v, 0, 4 * (size_t)n, c->stream));
+    s->t = 0;
+    HX_HIP(c, refresh_bf16(c));
+    HX_HIP(c, hipStreamSynchronize(c->stream));
+    return HX_OK;
+}
+
+hx_status mlp_get(const hx_ctx *cc, float *w, int64_t n)
+{
+    hx_ctx *c = const_cast<hx_ctx *>(cc);
+    if (!c->mlp) return fail(c, HX_ERR_STATE, "no network loaded");
+    if (n != c->mlp->P) return fail(c, HX_ERR_ARG, "size mismatch");
+    HX_HIP(c, hipMemcpyAsync(w, c->mlp->w, 4 * (size_t)n, hipMemcpyDeviceToHost, c->stream));
+    HX_HIP(c, hipStreamSynchronize(c->stream));
+    return HX_OK;
+}
+
+hx_status mlp_features(hx_ctx *c, const double *r, float *feats, float *scale)
+{
+    const int n_in = c->nd + 6 * c->nf + 1;
+    hipLaunchKernelGGL(k_features, dim3((unsigned)c->n_cells), dim3(128), 0, c->stream, c->n,
+                       c->n_cells, r, c->nbr, c->coef_feat, feats, (int64_t)n_in, (uint16_t *)nullptr,
+                       (int64_t)0, scale);
+    HX_HIP(c, hipGetLastError());
+    return HX_OK;
+}
+
+// forward on the packed batch s->xb (B rows); h1/h2 fp32 + bf16, o fp32
+static hipError_t forward_packed(hx_ctx *c, int64_t B)
+{
+    MlpState *s = c->mlp;
+    hipError_t e;
+    e = gemm(c->stream, (int)B, HID, s->ldx, s->xb, s->ldx, 1, s->w1b, s->ldx, 1, s->w + s->off_b1, 1,
+             s->h1, HID, s->h1b, HID);
+    if (e != hipSuccess) return e;
+    e = gemm(c->stream, (int)B, HID, HID, s->h1b, HID, 1, s->w2b, HID, 1, s->w + s->off_b2, 1, s->h2,
+             HID, s->h2b, HID);
+    if (e != hipSuccess) return e;
+    return gemm(c->stream, (int)B, s->n_out, HID, s->h2b, HID, 1, s->w3b, HID, 1, s->w + s->off_b3, 0,
+                s->o, s->n_out, nullptr, 0);
+}
+
+hx_status mlp_forward(hx_ctx *c, const float *feats, int64_t B, float *out)
+{
+    if (!c->mlp) return fail(c, HX_ERR_STATE, "no network loaded");
+    MlpState *s = c->mlp;
+    hx_status st = ensure_batch(c, B);
+    if (st != HX_OK) return st;
+    hipLaunchKernelGGL(k_pack, dim3(nb256(B * s->ldx)), dim3(256), 0, c->stream, B, s->n_in, s->ldx,
+                       feats, s->xb);
+    HX_HIP(c, hipGetLastError());
+    HX_HIP(c, forward_packed(c, B));
+    HX_HIP(c, hipMemcpyAsync(out, s->o, 4 * (size_t)B * s->n_out, hipMemcpyDeviceToDevice, c->stream));
+    return HX_OK;
+}
+
+hx_status mlp_train(hx_ctx *c, const float *feats, const float *targets, int64_t B, float lr,
+                    float *loss_out, float *grad_out)
+{
+    if (!c->mlp) return fail(c, HX_ERR_STATE, "no network loaded");
+    MlpState *s = c->mlp;
+    hx_status st = ensure_batch(c, B);
+    if (st != HX_OK) return st;
+    const hipStream_t q = c->stream;
+    hipLaunchKernelGGL(k_pack, dim3(nb256(B * s->ldx)), dim3(256), 0, q, B, s->n_in, s->ldx, feats,
+                       s->xb);
+    HX_HIP(c, forward_packed(c, B));
+    const int64_t tot = B * s->n_out;
+    const int nbk = (int)std::min<int64_t>(1024, (tot + 255) / 256);
+    hipLaunchKernelGGL(k_loss_grad, dim3(nbk), dim3(256), 0, q, tot, 1.0f / (float)tot, s->o, targets,
+                       s->d_o, s->dob, s->part);
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, q, nbk, s->part, 1.0 / (double)tot, s->loss);
+    HX_HIP(c, hipGetLastError());
+    float *g = s->grad;
+    // layer 3: dW3[o][h] = sum_b dO[b][o] H2[b][h]; db3 = colsum(dO); dH2 = dO W3
+    HX_HIP(c, gemm(q, s->n_out, HID, (int)B, s->dob, 1, s->n_out, s->h2b, 1, HID, nullptr, 0,
+                   g + s->off_w3, HID, nullptr, 0));
+    hipLaunchKernelGGL(k_colsum, dim3(s->n_out), dim3(256), 0, q, B, s->n_out, s->d_o, g + s->off_b3);
+    HX_HIP(c, gemm(q, (int)B, HID, s->n_out, s->dob, s->n_out, 1, s->w3b, 1, HID, nullptr, 0, s->dh2,
+                   HID, nullptr, 0));
+    hipLaunchKernelGGL(k_relu_back, dim3(nb256(B * HID)), dim3(256), 0, q, B * HID, s->h2, s->dh2, s->dh2b);
+    // layer 2
+    HX_HIP(c, gemm(q, HID, HID, (int)B, s->dh2b, 1, HID, s->h1b, 1, HID, nullptr, 0, g + s->off_w2,
+                   HID, nullptr, 0));
+    hipLaunchKernelGGL(k_colsum, dim3(HID), dim3(256), 0, q, B, HID, s->dh2, g + s->off_b2);
+    HX_HIP(c, gemm(q, (int)B, HID, HID, s->dh2b, HID, 1, s->w2b, 1, HID, nullptr, 0, s->dh1, HID,
+                   nullptr, 0));
+    hipLaunchKernelGGL(k_relu_back, dim3(nb256(B * HID)), dim3(256), 0, q, B * HID, s->h1, s->dh1, s->dh1b);
+    // layer 1: dW1[h][i] = sum_b dH1[b][h] X[b][i] (only the n_in real columns)
+    HX_HIP(c, gemm(q, HID, s->n_in, (int)B, s->dh1b, 1, HID, s->xb, 1, s->ldx, nullptr, 0,
+                   g + s->off_w1, s->n_in, nullptr, 0));
+    hipLaunchKernelGGL(k_colsum, dim3(HID), dim3(256), 0, q, B, HID, s->dh1, g + s->off_b1);
+    HX_HIP(c, hipGetLastError());
+    if (grad_out)
+        HX_HIP(c, hipMemcpyAsync(grad_out, g, 4 * (size_t)s->P, hipMemcpyDeviceToDevice, q));
+    if (lr != 0.0f) {
+        s->t += 1;
+        const float b1 = 0.9f, b2 = 0.999f;
+        const float c1 = 1.f - powf(b1, (float)s->t), c2 = 1.f - powf(b2, (float)s->t);
+        hipLaunchKernelGGL(k_adam, dim3(nb256(s->P)), dim3(256), 0, q, s->P, s->w, g, s->m, s->v, lr,
+                           b1, b2, 1e-8f, c1, c2);
+        HX_HIP(c, refresh_bf16(c));
+    }
+    if (loss_out) {
+        HX_HIP(c, hipMemcpyAsync(s->loss_host, s->loss, 4, hipMemcpyDeviceToHost, q));
+        HX_HIP(c, hipStreamSynchronize(q));
+        *loss_out = s->loss_host[0];
+    }
+    return HX_OK;
+}
+
+// one training pair per cell from a solver iterate xj of A x = b with solution xs:
+// r = b - A xj, features(r), targets = (xs - xj - BJ(r)) / RMS(BJ(r)) per cell
+hx_status mlp_training_pair(hx_ctx *c, const double *b, const double *xs, const double *xj,
+                            float *feats, float *targets)
+{
+    MlpState *s = c->mlp;
+    if (!s) {
+        hx_status st = mlp_create(c);
+        if (st != HX_OK) return st;
+        s = c->mlp;
+    }
+    if (!s->zt) {
+        hx_status st = dalloc(c, (void **)&s->zt, 2 * sizeof(double) * (size_t)c->n_dofs);
+        if (st != HX_OK) return st;
+    }
+    hx_status st = ensure_batch(c, c->n_cells);
+    if (st != HX_OK) return st;
+    double *r = s->zt, *z = s->zt + c->n_dofs;
+    HX_HIP(c, launch_apply64(c, xj, r, b));
+    HX_HIP(c, launch_bj64(c, r, z));
+    HX_HIP(c, (mlp_features(c, r, feats, s->scale) == HX_OK) ? hipSuccess : hipErrorUnknown);
+    hipLaunchKernelGGL(k_targets, dim3((unsigned)c->n_cells), dim3(128), 0, c->stream, c->nd, xs, xj,
+                       z, targets);
+    HX_HIP(c, hipGetLastError());
+    return HX_OK;
+}
+
+// z = BJ(r) + w_K net(features(r))_K, w_K = RMS(BJ(r)_K)
+hx_status mlp_precondition(hx_ctx *c, const double *r, double *z, int *nonfinite)
+{
+    *nonfinite = 0;
+    if (!c->mlp) return fail(c, HX_ERR_STATE, "no network loaded");
+    MlpState *s = c->mlp;
+    hx_status st = ensure_batch(c, c->n_cells);
+    if (st != HX_OK) return st;
+    hipLaunchKernelGGL(k_features, dim3((unsigned)c->n_cells), dim3(128), 0, c->stream, c->n,
+                       c->n_cells, r, c->nbr, c->coef_feat, (float *)nullptr, (int64_t)0, s->xb,
+                       (int64_t)s->ldx, s->scale);
+    HX_HIP(c, hipGetLastError());
+    HX_HIP(c, forward_packed(c, c->n_cells));
+    HX_HIP(c, launch_bj64(c, r, z));
+    hipLaunchKernelGGL(k_add_correction, dim3((unsigned)c->n_cells), dim3(128), 0, c->stream, c->nd,
+                       s->o, z);
+    HX_HIP(c, hipGetLastError());
+    return HX_OK;
 }
 
 }  // namespace hx

@@ -48,14 +48,28 @@ struct Timer {
     {
         if (ok) (void)hipEventRecord(ev[i], s);
     }
-    // after a stream sync: accumulate pc = ev0..1, op = 1..2, orth = 2..3
+    float span(int i, int j)
+    {
+        float t = 0;
+        return hipEventElapsedTime(&t, ev[i], ev[j]) == hipSuccess ? t : 0.0f;
+    }
+    // after a stream sync (FGMRES order ev0 < ev1 < ev2 < ev3):
+    // pc = ev0..1, op = ev1..2, orth = ev2..3
     void acc()
     {
         if (!ok) return;
-        float a = 0, b = 0, c = 0;
-        if (hipEventElapsedTime(&a, ev[0], ev[1]) == hipSuccess) pc += a;
-        if (hipEventElapsedTime(&b, ev[1], ev[2]) == hipSuccess) op += b;
-        if (hipEventElapsedTime(&c, ev[2], ev[3]) == hipSuccess) orth += c;
+        pc += span(0, 1);
+        op += span(1, 2);
+        orth += span(2, 3);
+    }
+    // CG order ev1 < ev2 < ev0 < ev3: op = ev1..2, vector updates = ev2..0,
+    // pc = ev0..3
+    void acc_cg()
+    {
+        if (!ok) return;
+        op += span(1, 2);
+        orth += span(2, 0);
+        pc += span(0, 3);
     }
 };
 
@@ -180,7 +194,7 @@ hx_status solve_cg(hx_ctx *c, const hx_solve_params *prm, const double *b, doubl
         HX_HIP(c, blas_dot(c, n, r, z, sc + 0));
         double hh[3];
         if ((s = read_scalars(c, sc, 3, hh)) != HX_OK) return s;
-        tm.acc();   // pc: 0..1 spans the previous iteration's tail; approximate split
+        tm.acc_cg();
         ++it;
         rel = std::sqrt(hh[2]) / nb;
         if (info->history && it - 1 < info->history_len) info->history[it - 1] = rel;
