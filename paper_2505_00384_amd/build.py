@@ -23,15 +23,29 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
           "-Wno-unused-command-line-argument"]
 
 
+GEN = "gen_tables.cpp"
+
+
 def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC)
-                  if f.endswith((".hip", ".cpp")))
+                  if f.endswith((".hip", ".cpp")) and f != GEN)
+
+
+def generate_tables():
+    """Compile and run the table generator (host only) into _build/optables.inc."""
+    exe = os.path.join(BUILD, "gen_tables")
+    cmd = [HIPCC, "-O2", "-std=c++17", "-I" + CSRC, os.path.join(CSRC, GEN),
+           os.path.join(CSRC, "rules.cpp"), "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"table generator failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    subprocess.check_call([exe, os.path.join(BUILD, "optables.inc")])
 
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     lang = ["-x", "hip"] if src.endswith(".hip") else []
-    cmd = [HIPCC, *COMMON, *lang, "-c", src, "-o", obj]
+    cmd = [HIPCC, *COMMON, "-I" + BUILD, *lang, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
@@ -40,6 +54,7 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
+    generate_tables()
     srcs = sources()
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))

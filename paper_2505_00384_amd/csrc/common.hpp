@@ -70,7 +70,7 @@ struct hx_ctx {
     // merged operator data
     double *cell64 = nullptr;     // [n_cells][7][nd]
     float *cell32 = nullptr;
-    double *face64 = nullptr;     // [n_cells][3][7][nf]
+    double *face64 = nullptr;     // [n_cells][3][7][N (1st tangential)][N (2nd)]
     float *face32 = nullptr;
 
     // separable block-Jacobi data

@@ -351,7 +351,8 @@ __global__ void k_set_cell(const double *__restrict__ nodes, int ng, int n,
 }
 
 // -------------------------------------------------------------------------
-// merged face data of the +d face of every cell (thread per face point):
+// merged face data of the +d face of every cell (thread per face point),
+// [cell][d][component][a][b] with a, b the first and second tangential index:
 //   g- = beta- ds J-^{-1} n,  g+ = beta+ ds J+^{-1} n,  s = sigma 1/2 (b- + b+) ds
 // with n and ds from the minus cell.
 // -------------------------------------------------------------------------
@@ -367,7 +368,9 @@ __global__ void k_set_face(const double *__restrict__ nodes, int ng, int n, int6
     const int64_t cd = t / nf;
     const int64_t c = cd / 3;
     const int d = (int)(cd % 3);
-    const int a = pt % n, b = pt / n;
+    // point (a, b): a along the first, b along the second tangential
+    // direction, stored at b + n a
+    const int b = pt % n, a = pt / n;
     double *dst = face64 + cd * 7 * nf;
     float *dstf = face32 + cd * 7 * nf;
     const int32_t nb = nbr[6 * c + 2 * d + 1];

@@ -9,20 +9,23 @@
 //  * cell integrals: lane (a, b) owns a pencil of N values; the sweeps
 //    (GLL -> Gauss interpolation B, derivative BD, and their transposes) run in
 //    registers, and the pencil direction changes through LDS;
-//  * face integrals: lane (f, r) owns row r of face f (6 faces x N rows).  It
-//    reads the own normal slab from LDS and the neighbour's slab straight from
-//    global memory into registers, forms layer values and normal derivatives,
-//    interpolates along the first tangential direction in registers, and after
-//    one LDS transpose lane (f, q1) finishes the second direction, the
-//    pointwise flux terms at the Gauss points and the transposed sweep; a
-//    second transpose returns to rows for the last transposed sweep.  The
+//  * face integrals: lane (f, p) owns column p of face f (6 faces x N
+//    columns).  It reads the neighbour's normal lines straight from global
+//    memory into registers at the start (in the same round trip as the own
+//    values; the N lanes of a face read neighbouring addresses) and the own
+//    ones from LDS, forms layer values and normal derivatives and interpolates
+//    along the second tangential direction in registers; after one LDS
+//    transpose lane (f, q2) finishes the first direction, the pointwise flux
+//    terms at the Gauss points (face data laid out [comp][q1][q2], so these
+//    loads are contiguous across lanes too) and the transposed sweep; a second
+//    transpose returns to columns for the last transposed sweep.  The
 //    pencil owners then add the six faces' layer and normal-derivative
 //    contributions to their own output values.  Each output value is written
 //    by exactly one lane (no atomics; bitwise reproducible).
 //  * the 1-D tables sit in constant memory, loops over them are unrolled, so
 //    their entries are wave-uniform scalar operands.
 //  * cell data [cell][7][N^3] is streamed once with non-temporal loads; x and
-//    the face data [cell][3][7][N^2] are read by neighbours too and stay
+//    the face data [cell][3][7][N][N] are read by neighbours too and stay
 //    cacheable.
 //  * cells are visited in the order of a host-built permutation: tiles of
 //    columns swept layer by layer, in one contiguous range per XCD, so the
@@ -42,23 +45,31 @@ hipError_t upload_op_tables_operator(const OpTab *all)
 
 namespace {
 
+// compile-time copies of the same tables (generated at build time from the
+// library's rules): with every loop unrolled the compiler materialises the
+// entries with scalar moves instead of constant-memory loads
+template <int N> struct KB;
+template <int N> struct KBD;
+template <int N> struct KDL;
+#include "optables.inc"
+
 template <typename T, int N>
 __device__ __forceinline__ T tB(int q, int i)
 {
-    if constexpr (std::is_same<T, double>::value) return c_op[N].B[q * N + i];
-    else return c_op[N].Bf[q * N + i];
+    if constexpr (std::is_same<T, double>::value) return KB<N>::d[q * N + i];
+    else return KB<N>::f[q * N + i];
 }
 template <typename T, int N>
 __device__ __forceinline__ T tD(int q, int i)
 {
-    if constexpr (std::is_same<T, double>::value) return c_op[N].BD[q * N + i];
-    else return c_op[N].BDf[q * N + i];
+    if constexpr (std::is_same<T, double>::value) return KBD<N>::d[q * N + i];
+    else return KBD<N>::f[q * N + i];
 }
 template <typename T, int N>
 __device__ __forceinline__ T tE(int e, int i)
 {
-    if constexpr (std::is_same<T, double>::value) return c_op[N].DL[e][i];
-    else return c_op[N].DLf[e][i];
+    if constexpr (std::is_same<T, double>::value) return KDL<N>::d[e * N + i];
+    else return KDL<N>::f[e * N + i];
 }
 
 constexpr int pow2_at_least(int v)
@@ -121,7 +132,7 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
     // ---- cell lanes: (a, b), pencil owners
     const bool cl = valid && ln < NF;
     const int a = ln % N, b = (ln / N) % N;
-    // ---- face lanes: (f, r), row owners
+    // ---- face lanes: (f, p), column owners
     const bool fl0 = valid && ln < 6 * N;
     const int f = fl0 ? ln / N : 0, rr = ln % N;
     const int d = f >> 1, s = f & 1;
@@ -130,6 +141,23 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
 
     if (valid)
         for (int e = ln; e < ND; e += LPC) sU[cs][e] = x[cid * ND + e];
+
+    // the neighbour's layer values and normal derivatives on column p of face
+    // f, loaded with the own values so that both arrive in one memory round
+    // trip; the N lanes of a face read neighbouring addresses in each load
+    T Ln[N], Nn[N];
+    if (fl) {
+        const int en = 1 - s, mn = en ? N - 1 : 0;
+        const T *xn = x + (int64_t)nb * ND;
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            T sn = 0;
+#pragma unroll
+            for (int m = 0; m < N; ++m) sn += tE<T, N>(en, m) * xn[lix<N>(d, m, rr, r)];
+            Nn[r] = sn;
+            Ln[r] = xn[lix<N>(d, mn, rr, r)];
+        }
+    }
 
     // quadrature-point data of this lane's z pencil, streamed once
     const T *cp = cell + cid * 7 * ND + a + N * b;
@@ -288,39 +316,32 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
     __syncthreads();
 
     // =========================================================== face part
-    // step 1, lane (f, r): layers and normal derivatives of both sides on row
-    // r, then interpolation along the first tangential direction
+    // step 1, lane (f, p): own layer and normal derivative on column p (the
+    // neighbour's were formed at the start), then interpolation of both sides
+    // along the second tangential direction
     if (fl) {
-        const int eo = s, en = 1 - s;
-        const int mo = eo ? N - 1 : 0, mn = en ? N - 1 : 0;
-        const T *xn = x + (int64_t)nb * ND;
-        T Lo[N], No[N], Ln[N], Nn[N];
+        const int eo = s, mo = eo ? N - 1 : 0;
+        T Lo[N], No[N];
 #pragma unroll
-        for (int p = 0; p < N; ++p) {
-            T so = 0, sn = 0;
+        for (int r = 0; r < N; ++r) {
+            T so = 0;
 #pragma unroll
-            for (int m = 0; m < N; ++m) {
-                const int id = lix<N>(d, m, p, rr);
-                so += tE<T, N>(eo, m) * U[id];
-                sn += tE<T, N>(en, m) * xn[id];
-            }
-            No[p] = so;
-            Nn[p] = sn;
-            Lo[p] = U[lix<N>(d, mo, p, rr)];
-            Ln[p] = xn[lix<N>(d, mn, p, rr)];
+            for (int m = 0; m < N; ++m) so += tE<T, N>(eo, m) * U[lix<N>(d, m, rr, r)];
+            No[r] = so;
+            Lo[r] = U[lix<N>(d, mo, rr, r)];
         }
-        T *gw = G + f * 6 * NF + rr * N;
+        T *gw = G + f * 6 * NF + rr;
 #pragma unroll
         for (int q = 0; q < N; ++q) {
             T g0 = 0, g1 = 0, g2 = 0, g3 = 0, g4 = 0, g5 = 0;
 #pragma unroll
-            for (int p = 0; p < N; ++p) {
-                const T bb = tB<T, N>(q, p), bd = tD<T, N>(q, p);
-                g0 += bb * Lo[p]; g1 += bd * Lo[p]; g2 += bb * No[p];
-                g3 += bb * Ln[p]; g4 += bd * Ln[p]; g5 += bb * Nn[p];
+            for (int r = 0; r < N; ++r) {
+                const T bb = tB<T, N>(q, r), bd = tD<T, N>(q, r);
+                g0 += bb * Lo[r]; g1 += bd * Lo[r]; g2 += bb * No[r];
+                g3 += bb * Ln[r]; g4 += bd * Ln[r]; g5 += bb * Nn[r];
             }
-            gw[0 * NF + q] = g0; gw[1 * NF + q] = g1; gw[2 * NF + q] = g2;
-            gw[3 * NF + q] = g3; gw[4 * NF + q] = g4; gw[5 * NF + q] = g5;
+            gw[0 * NF + q * N] = g0; gw[1 * NF + q * N] = g1; gw[2 * NF + q * N] = g2;
+            gw[3 * NF + q * N] = g3; gw[4 * NF + q * N] = g4; gw[5 * NF + q * N] = g5;
         }
     }
     __syncthreads();
@@ -329,119 +350,119 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
 #pragma unroll
         for (int i = 0; i < N; ++i) sU[cs][i + N * a + NF * b] = Y[i];
     }
-    // step 2, lane (f, q1): second tangential direction, flux terms at the
+    // step 2, lane (f, q2): first tangential direction, flux terms at the
     // Gauss points, transposed sweep back along it.  The neighbour side is
     // evaluated first (its flux and value per point), then the own side.
     {
         T A0[N], A1[N], A2[N];
-        const int q1 = rr;
+        const int q2 = rr;
         if (fl) {
             const int64_t fid = s ? cid : (int64_t)nb;
-            const T *fd = face + (fid * 3 + d) * 7 * NF + q1;
+            const T *fd = face + (fid * 3 + d) * 7 * NF + q2;   // [comp][q1][q2]
             const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-            const T *gr = G + f * 6 * NF + q1;
+            const T *gr = G + f * 6 * NF + q2 * N;
             // g of the neighbour side: g+ if the own cell is the minus cell
             const int gn_off = s ? 3 : 0, go_off = s ? 0 : 3;
             T fnb[N], vnb[N];
             {
                 T h0[N], h1[N], h2[N];
 #pragma unroll
-                for (int r = 0; r < N; ++r) {
-                    h0[r] = gr[3 * NF + r * N];
-                    h1[r] = gr[4 * NF + r * N];
-                    h2[r] = gr[5 * NF + r * N];
+                for (int p = 0; p < N; ++p) {
+                    h0[p] = gr[3 * NF + p];
+                    h1[p] = gr[4 * NF + p];
+                    h2[p] = gr[5 * NF + p];
                 }
 #pragma unroll
-                for (int q2 = 0; q2 < N; ++q2) {
-                    T vn = 0, t2n = 0, t1n = 0, dnn = 0;
+                for (int q1 = 0; q1 < N; ++q1) {
+                    T vn = 0, t1n = 0, t2n = 0, dnn = 0;
 #pragma unroll
-                    for (int r = 0; r < N; ++r) {
-                        const T bb = tB<T, N>(q2, r), bd = tD<T, N>(q2, r);
-                        vn += bb * h0[r]; t2n += bd * h0[r]; t1n += bb * h1[r]; dnn += bb * h2[r];
+                    for (int p = 0; p < N; ++p) {
+                        const T bb = tB<T, N>(q1, p), bd = tD<T, N>(q1, p);
+                        vn += bb * h0[p]; t1n += bd * h0[p]; t2n += bb * h1[p]; dnn += bb * h2[p];
                     }
-                    const T *fq = fd + N * q2 + gn_off * NF;
+                    const T *fq = fd + N * q1 + gn_off * NF;
                     T gn[3];
                     gn[d] = dnn; gn[t1] = t1n; gn[t2] = t2n;
-                    fnb[q2] = fq[0] * gn[0] + fq[NF] * gn[1] + fq[2 * NF] * gn[2];
-                    vnb[q2] = vn;
+                    fnb[q1] = fq[0] * gn[0] + fq[NF] * gn[1] + fq[2 * NF] * gn[2];
+                    vnb[q1] = vn;
                 }
             }
             T h0[N], h1[N], h2[N];
 #pragma unroll
-            for (int r = 0; r < N; ++r) {
-                h0[r] = gr[r * N];
-                h1[r] = gr[NF + r * N];
-                h2[r] = gr[2 * NF + r * N];
-                A0[r] = A1[r] = A2[r] = 0;
+            for (int p = 0; p < N; ++p) {
+                h0[p] = gr[p];
+                h1[p] = gr[NF + p];
+                h2[p] = gr[2 * NF + p];
+                A0[p] = A1[p] = A2[p] = 0;
             }
 #pragma unroll
-            for (int q2 = 0; q2 < N; ++q2) {
-                T vo = 0, t2o = 0, t1o = 0, dno = 0;
+            for (int q1 = 0; q1 < N; ++q1) {
+                T vo = 0, t1o = 0, t2o = 0, dno = 0;
 #pragma unroll
-                for (int r = 0; r < N; ++r) {
-                    const T bb = tB<T, N>(q2, r), bd = tD<T, N>(q2, r);
-                    vo += bb * h0[r]; t2o += bd * h0[r]; t1o += bb * h1[r]; dno += bb * h2[r];
+                for (int p = 0; p < N; ++p) {
+                    const T bb = tB<T, N>(q1, p), bd = tD<T, N>(q1, p);
+                    vo += bb * h0[p]; t1o += bd * h0[p]; t2o += bb * h1[p]; dno += bb * h2[p];
                 }
-                const T *fq = fd + N * q2 + go_off * NF;
+                const T *fq = fd + N * q1 + go_off * NF;
                 const T g0 = fq[0], g1 = fq[NF], g2 = fq[2 * NF];
-                const T pen = fd[6 * NF + N * q2];
+                const T pen = fd[6 * NF + N * q1];
                 T go[3];
                 go[d] = dno; go[t1] = t1o; go[t2] = t2o;
-                const T flux = g0 * go[0] + g1 * go[1] + g2 * go[2] + fnb[q2];
-                const T jump = s ? (vo - vnb[q2]) : (vnb[q2] - vo);
+                const T flux = g0 * go[0] + g1 * go[1] + g2 * go[2] + fnb[q1];
+                const T jump = s ? (vo - vnb[q1]) : (vnb[q1] - vo);
                 const T sg = s ? T(1) : T(-1);
                 const T cv = sg * (T(-0.5) * flux + pen * jump);
                 const T hj = T(-0.5) * jump;
                 T cg[3] = {hj * g0, hj * g1, hj * g2};
-                const T ct2 = cg[t2], ct1 = cg[t1], cn = cg[d];
+                const T ct1 = cg[t1], ct2 = cg[t2], cn = cg[d];
 #pragma unroll
-                for (int r = 0; r < N; ++r) {
-                    const T bb = tB<T, N>(q2, r), bd = tD<T, N>(q2, r);
-                    A0[r] += bb * cv + bd * ct2;
-                    A1[r] += bb * ct1;
-                    A2[r] += bb * cn;
+                for (int p = 0; p < N; ++p) {
+                    const T bb = tB<T, N>(q1, p), bd = tD<T, N>(q1, p);
+                    A0[p] += bb * cv + bd * ct1;
+                    A1[p] += bb * ct2;
+                    A2[p] += bb * cn;
                 }
             }
         }
         __syncthreads();
         if (fl) {
-            T *gw = G + f * 3 * NF + q1;
+            T *gw = G + f * 3 * NF + q2 * N;
 #pragma unroll
-            for (int r = 0; r < N; ++r) {
-                gw[r * N] = A0[r];
-                gw[NF + r * N] = A1[r];
-                gw[2 * NF + r * N] = A2[r];
+            for (int p = 0; p < N; ++p) {
+                gw[p] = A0[p];
+                gw[NF + p] = A1[p];
+                gw[2 * NF + p] = A2[p];
             }
         }
     }
     __syncthreads();
-    // step 3, lane (f, r): transposed sweep along the first tangential
-    // direction; the layer (F0) and normal-derivative (F1) weights of row r
+    // step 3, lane (f, p): transposed sweep along the second tangential
+    // direction; the layer (F0) and normal-derivative (F1) weights of column p
     if (fl0) {
-        T *out = G + 18 * NF + f * 2 * NF + rr * N;
+        T *out = G + 18 * NF + f * 2 * NF + rr;      // [field][r][p]
         if (fl) {
-            const T *gr = G + f * 3 * NF + rr * N;
+            const T *gr = G + f * 3 * NF + rr;
             T h0[N], h1[N], h2[N];
 #pragma unroll
             for (int q = 0; q < N; ++q) {
-                h0[q] = gr[q];
-                h1[q] = gr[NF + q];
-                h2[q] = gr[2 * NF + q];
+                h0[q] = gr[q * N];
+                h1[q] = gr[NF + q * N];
+                h2[q] = gr[2 * NF + q * N];
             }
 #pragma unroll
-            for (int p = 0; p < N; ++p) {
+            for (int r = 0; r < N; ++r) {
                 T f0 = 0, f1 = 0;
 #pragma unroll
                 for (int q = 0; q < N; ++q) {
-                    f0 += tB<T, N>(q, p) * h0[q] + tD<T, N>(q, p) * h1[q];
-                    f1 += tB<T, N>(q, p) * h2[q];
+                    f0 += tB<T, N>(q, r) * h0[q] + tD<T, N>(q, r) * h1[q];
+                    f1 += tB<T, N>(q, r) * h2[q];
                 }
-                out[p] = f0;
-                out[NF + p] = f1;
+                out[r * N] = f0;
+                out[NF + r * N] = f1;
             }
         } else {
 #pragma unroll
-            for (int p = 0; p < N; ++p) out[p] = out[NF + p] = 0;
+            for (int r = 0; r < N; ++r) out[r * N] = out[NF + r * N] = 0;
         }
     }
     __syncthreads();
