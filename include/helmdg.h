@@ -250,8 +250,9 @@ hx_status hx_train_step(hx_ctx *c, const float *feats, const float *targets,
 
 enum {
     HX_EXPORT_CELL_DATA = 0,   /* FP64 [n_cells][7][(k+1)^3]: m, Gxx, Gxy, Gxz, Gyy, Gyz, Gzz */
-    HX_EXPORT_FACE_DATA = 1,   /* FP64 [n_cells][3][7][(k+1)][(k+1)]: g-(3), g+(3), s of the +d face,
-                                  points [first][second tangential direction] */
+    HX_EXPORT_FACE_DATA = 1,   /* FP64 [n_cells][3][7][(k+1)][(k+1)]: g-(3), g+(3), s of the +d face;
+                                  g components in the order normal direction d, first, second
+                                  tangential direction; points [first][second tangential] */
     HX_EXPORT_SIGMA = 2,       /* FP64 [n_cells][3]: penalty of the +d face (-1: boundary) */
     HX_EXPORT_VOLUME = 3,      /* FP64 [n_cells] */
     HX_EXPORT_BJ_SCALARS = 4   /* FP64 [n_cells][4]: abar lx ly lz, bbar ly lz/lx, ... */

@@ -41,7 +41,7 @@ void dfree(void **p)
 
 static void free_mesh(hx_ctx *c)
 {
-    void **bufs[] = {(void **)&c->nodes, (void **)&c->nbr, (void **)&c->order, (void **)&c->ref, (void **)&c->vol,
+    void **bufs[] = {(void **)&c->nodes, (void **)&c->nbr, (void **)&c->visit, (void **)&c->ref, (void **)&c->vol,
                      (void **)&c->ell, (void **)&c->mindet, (void **)&c->sigma,
                      (void **)&c->cell64, (void **)&c->cell32, (void **)&c->face64,
                      (void **)&c->face32, (void **)&c->bjS64, (void **)&c->bjS32,
@@ -170,7 +170,7 @@ hx_status hx_setup_mesh(hx_ctx *c, int degree, int64_t n_cells, int geo_degree,
     if (s == HX_OK) s = dalloc(c, (void **)&(ptr), (bytes));
     ALLOC(c->nodes, sizeof(double) * nc * ng3 * 3);
     ALLOC(c->nbr, sizeof(int32_t) * nc * 6);
-    ALLOC(c->order, sizeof(int32_t) * nc);
+    ALLOC(c->visit, sizeof(int32_t) * nc * 8);
     ALLOC(c->ref, sizeof(RefTab64));
     ALLOC(c->vol, sizeof(double) * nc);
     ALLOC(c->ell, sizeof(double) * nc * 3);
@@ -196,10 +196,20 @@ hx_status hx_setup_mesh(hx_ctx *c, int degree, int64_t n_cells, int geo_degree,
                              hipMemcpyHostToDevice, c->stream));
     HX_HIP(c, hipMemcpyAsync(c->nbr, nb32.data(), sizeof(int32_t) * nc * 6, hipMemcpyHostToDevice,
                              c->stream));
-    std::vector<int32_t> order(nc);
-    build_traversal(nb32.data(), n_cells, order.data());
-    HX_HIP(c, hipMemcpyAsync(c->order, order.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice,
-                             c->stream));
+    {
+        // traversal records of the operator kernel: {cell, neighbours, 0}
+        std::vector<int32_t> order(nc), visit(nc * 8);
+        build_traversal(nb32.data(), n_cells, order.data());
+        for (size_t o = 0; o < nc; ++o) {
+            const int32_t cell = order[o];
+            visit[8 * o] = cell;
+            for (int f = 0; f < 6; ++f) visit[8 * o + 1 + f] = nb32[6 * (size_t)cell + f];
+            visit[8 * o + 7] = 0;
+        }
+        HX_HIP(c, hipMemcpyAsync(c->visit, visit.data(), sizeof(int32_t) * nc * 8,
+                                 hipMemcpyHostToDevice, c->stream));
+        HX_HIP(c, hipStreamSynchronize(c->stream));
+    }
     HX_HIP(c, hipMemcpyAsync(c->ref, &c->ref_host, sizeof(RefTab64), hipMemcpyHostToDevice,
                              c->stream));
     HX_HIP(c, launch_cell_geometry(c));

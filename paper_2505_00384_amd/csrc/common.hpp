@@ -59,7 +59,7 @@ struct hx_ctx {
 
     double *nodes = nullptr;      // [n_cells][(g+1)^3][3]
     int32_t *nbr = nullptr;       // [n_cells][6]
-    int32_t *order = nullptr;     // [n_cells] traversal order of the operator kernel
+    int32_t *visit = nullptr;     // [n_cells][8] operator traversal: {cell, 6 neighbours, 0}
     hx::RefTab64 *ref = nullptr;  // device copy of the tables of degree k
     hx::RefTab64 ref_host{};
     double *vol = nullptr;        // [n_cells]

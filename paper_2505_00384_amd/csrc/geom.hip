@@ -354,7 +354,9 @@ __global__ void k_set_cell(const double *__restrict__ nodes, int ng, int n,
 // merged face data of the +d face of every cell (thread per face point),
 // [cell][d][component][a][b] with a, b the first and second tangential index:
 //   g- = beta- ds J-^{-1} n,  g+ = beta+ ds J+^{-1} n,  s = sigma 1/2 (b- + b+) ds
-// with n and ds from the minus cell.
+// with n and ds from the minus cell; the three components of g are stored in
+// the order (d, first tangential, second tangential) so that the operator
+// pairs them with its reference derivatives without a per-lane selection.
 // -------------------------------------------------------------------------
 __global__ void k_set_face(const double *__restrict__ nodes, int ng, int n, int64_t n_cells,
                            const int32_t *__restrict__ nbr, const RefTab64 *__restrict__ T,
@@ -402,10 +404,14 @@ __global__ void k_set_face(const double *__restrict__ nodes, int ng, int n, int6
             bm += wgt * beta[c * nd + layer_idx(n, d, n - 1, p, r)];
             bp += wgt * beta[(int64_t)nb * nd + layer_idx(n, d, 0, p, r)];
         }
+    // components in the face's own order: normal reference direction d, then
+    // the first and second tangential one
+    const int dir[3] = {d, d == 0 ? 1 : 0, d == 2 ? 1 : 2};
     double out[7];
-    for (int r = 0; r < 3; ++r) {
-        out[r] = bm * ds * (Jmi[r][0] * nv[0] + Jmi[r][1] * nv[1] + Jmi[r][2] * nv[2]);
-        out[3 + r] = bp * ds * (Jpi[r][0] * nv[0] + Jpi[r][1] * nv[1] + Jpi[r][2] * nv[2]);
+    for (int k = 0; k < 3; ++k) {
+        const int r = dir[k];
+        out[k] = bm * ds * (Jmi[r][0] * nv[0] + Jmi[r][1] * nv[1] + Jmi[r][2] * nv[2]);
+        out[3 + k] = bp * ds * (Jpi[r][0] * nv[0] + Jpi[r][1] * nv[1] + Jpi[r][2] * nv[2]);
     }
     out[6] = sigma[3 * c + d] * 0.5 * (bm + bp) * ds;
     for (int s = 0; s < 7; ++s) {

@@ -18,7 +18,10 @@
 //    transpose lane (f, q2) finishes the first direction, the pointwise flux
 //    terms at the Gauss points (face data laid out [comp][q1][q2], so these
 //    loads are contiguous across lanes too) and the transposed sweep; a second
-//    transpose returns to columns for the last transposed sweep.  The
+//    transpose returns to columns for the last transposed sweep.  The two
+//    sides pass through the same three fields of LDS one after the other, and
+//    the transposed sweeps write over what they read, so a face needs 3 N^2
+//    values of LDS.  The
 //    pencil owners then add the six faces' layer and normal-derivative
 //    contributions to their own output values.  Each output value is written
 //    by exactly one lane (no atomics; bitwise reproducible).
@@ -27,7 +30,8 @@
 //  * cell data [cell][7][N^3] is streamed once with non-temporal loads; x and
 //    the face data [cell][3][7][N][N] are read by neighbours too and stay
 //    cacheable.
-//  * cells are visited in the order of a host-built permutation: tiles of
+//  * cells are visited in the order of a host-built permutation (one 32-byte
+//    record per slot holds the cell and its six neighbours): tiles of
 //    columns swept layer by layer, in one contiguous range per XCD, so the
 //    neighbours a cell reads were touched recently by the same XCD's L2.
 #include "common.hpp"
@@ -85,17 +89,17 @@ struct Cfg {
     static constexpr int LPC = pow2_at_least(NF > 6 * N ? NF : 6 * N) > 64
                                    ? 64 : pow2_at_least(NF > 6 * N ? NF : 6 * N);
     static constexpr int CPW = 64 / LPC;                       // cells per wave
-    static constexpr int GS = (36 * NF > 3 * ND) ? 36 * NF : 3 * ND;  // work area per cell
+    static constexpr int GS = (18 * NF > 3 * ND) ? 18 * NF : 3 * ND;  // work area per cell
     static_assert(NF <= 64 && 6 * N <= 64, "one wave per cell at most");
 };
 
-// local index with coordinate m along direction d and (p, r) along the two
-// other directions in increasing order
-template <int N>
-__device__ __forceinline__ int lix(int d, int m, int p, int r)
-{
-    return d == 0 ? m + N * (p + N * r) : (d == 1 ? p + N * (m + N * r) : p + N * (r + N * m));
-}
+// waves per SIMD the register budget is sized for (measured: a larger
+// budget beats the occupancy the LDS use would allow)
+template <int N, typename T>
+struct Occ {
+    static constexpr int W = sizeof(T) == 8 ? (N <= 4 ? 4 : (N <= 6 ? 3 : 2))
+                                            : (N <= 5 ? 4 : (N <= 7 ? 3 : 2));
+};
 
 template <typename T>
 __device__ __forceinline__ T ld_stream(const T *p)
@@ -104,10 +108,10 @@ __device__ __forceinline__ T ld_stream(const T *p)
 }
 
 template <int N, typename T>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(Occ<N, T>::W, Occ<N, T>::W)))
 k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
-        const T *__restrict__ cell, const T *__restrict__ face, const int32_t *__restrict__ nbr,
-        const int32_t *__restrict__ order, int n_cells, int nwg)
+        const T *__restrict__ cell, const T *__restrict__ face, const int32_t *__restrict__ visit,
+        int n_cells, int nwg)
 {
     constexpr int NF = Cfg<N>::NF, ND = Cfg<N>::ND, LPC = Cfg<N>::LPC, CPW = Cfg<N>::CPW,
                   GS = Cfg<N>::GS;
@@ -125,7 +129,10 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
     const int ln = lane - cs * LPC;        // lane within the cell
     const int slot = wg * CPW + cs;
     const bool valid = slot < n_cells;
-    const int64_t cid = valid ? order[slot] : 0;
+    // the slot's record {cell, neighbours -x,+x,-y,+y,-z,+z}: one 32-byte
+    // line gives every index this wave needs
+    const int32_t *rec = visit + (int64_t)(valid ? slot : 0) * 8;
+    const int64_t cid = valid ? rec[0] : 0;
     T *G = &sG[cs][0];
     T *U = &sU[cs][0];
 
@@ -136,27 +143,49 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
     const bool fl0 = valid && ln < 6 * N;
     const int f = fl0 ? ln / N : 0, rr = ln % N;
     const int d = f >> 1, s = f & 1;
-    const int32_t nb = fl0 ? nbr[cid * 6 + f] : -1;
+    const int32_t nb = fl0 ? rec[1 + f] : -1;
     const bool fl = nb >= 0;
+    // strides of the normal index m, the column index p and the row index r
+    // of the face's direction in a cell's lexicographic numbering
+    const int sm = d == 0 ? 1 : (d == 1 ? N : NF);
+    const int sp = d == 0 ? N : 1;
+    const int sr = d == 2 ? N : NF;
 
-    if (valid)
-        for (int e = ln; e < ND; e += LPC) sU[cs][e] = x[cid * ND + e];
+    // own values: all loads first, then the LDS stores
+    constexpr int XL = (ND + LPC - 1) / LPC;
+    T xv[XL];
+#pragma unroll
+    for (int k = 0; k < XL; ++k) {
+        const int e = ln + k * LPC;
+        xv[k] = (valid && e < ND) ? x[cid * ND + e] : T(0);
+    }
 
-    // the neighbour's layer values and normal derivatives on column p of face
-    // f, loaded with the own values so that both arrive in one memory round
-    // trip; the N lanes of a face read neighbouring addresses in each load
+    // The neighbour's layer values and normal derivatives on column p of
+    // face f, loaded with the own values so that both arrive in one memory
+    // round trip; the N lanes of a face read neighbouring addresses.  The
+    // normal line is walked from the shared face inwards, so both sides use
+    // the derivative weights of the lower end: for symmetric nodes the
+    // weights at the upper end are those of the lower end mirrored and
+    // negated.
     T Ln[N], Nn[N];
     if (fl) {
-        const int en = 1 - s, mn = en ? N - 1 : 0;
-        const T *xn = x + (int64_t)nb * ND;
+        // the neighbour touches with its upper layer when s = 0
+        const int m0 = s ? 0 : (N - 1) * sm, dm = s ? sm : -sm;
+        const T sgn = s ? T(1) : T(-1);
+        const T *xn = x + (int64_t)nb * ND + rr * sp + m0;
 #pragma unroll
         for (int r = 0; r < N; ++r) {
             T sn = 0;
 #pragma unroll
-            for (int m = 0; m < N; ++m) sn += tE<T, N>(en, m) * xn[lix<N>(d, m, rr, r)];
-            Nn[r] = sn;
-            Ln[r] = xn[lix<N>(d, mn, rr, r)];
+            for (int m = 0; m < N; ++m) sn += tE<T, N>(0, m) * xn[r * sr + m * dm];
+            Nn[r] = sgn * sn;
+            Ln[r] = xn[r * sr];
         }
+    }
+#pragma unroll
+    for (int k = 0; k < XL; ++k) {
+        const int e = ln + k * LPC;
+        if (valid && e < ND) U[e] = xv[k];
     }
 
     // quadrature-point data of this lane's z pencil, streamed once
@@ -316,33 +345,81 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
     __syncthreads();
 
     // =========================================================== face part
-    // step 1, lane (f, p): own layer and normal derivative on column p (the
-    // neighbour's were formed at the start), then interpolation of both sides
-    // along the second tangential direction
+    // The work area of a face holds three N x N fields at a time, laid out
+    // [field][q2 or r][p].  Layer values and normal derivatives of a side are
+    // interpolated along the second tangential direction by the column lanes
+    // (f, p) (step 1), then along the first one by the row lanes (f, q2)
+    // (step 2).  The neighbour side goes first and leaves its flux and value
+    // at the row's Gauss points in registers; the own side then forms the
+    // pointwise terms, sweeps back along the first direction in place (step
+    // 3) and the column lanes finish the transposed sweep in place (step 4).
+    const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+    T *gf = G + f * 3 * NF;
+    // step 1 of one side: fields B L, BD L, B Nd along the second direction
+    auto interp_t2 = [&](const T (&L)[N], const T (&Nd)[N]) {
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            T g0 = 0, g1 = 0, g2 = 0;
+#pragma unroll
+            for (int r = 0; r < N; ++r) {
+                g0 += tB<T, N>(q, r) * L[r];
+                g1 += tD<T, N>(q, r) * L[r];
+                g2 += tB<T, N>(q, r) * Nd[r];
+            }
+            gf[q * N + rr] = g0;
+            gf[NF + q * N + rr] = g1;
+            gf[2 * NF + q * N + rr] = g2;
+        }
+    };
+    // face data of this row: [comp][q1][q2], components g-(3), g+(3), s
+    const int64_t fid = s ? cid : (int64_t)nb;
+    const T *fd = face + (fid * 3 + d) * 7 * NF + rr;
+    // g of the neighbour side: g+ if the own cell is the minus cell
+    const int gn_off = s ? 3 : 0, go_off = s ? 0 : 3;
+
+    if (fl) interp_t2(Ln, Nn);
+    __syncthreads();
+    // step 2, neighbour side, lane (f, q2): flux and value at (q1, q2)
+    T fnb[N], vnb[N];
     if (fl) {
-        const int eo = s, mo = eo ? N - 1 : 0;
+        T h0[N], h1[N], h2[N];
+#pragma unroll
+        for (int p = 0; p < N; ++p) {
+            h0[p] = gf[rr * N + p];
+            h1[p] = gf[NF + rr * N + p];
+            h2[p] = gf[2 * NF + rr * N + p];
+        }
+#pragma unroll
+        for (int q1 = 0; q1 < N; ++q1) {
+            T vn = 0, t1n = 0, t2n = 0, dnn = 0;
+#pragma unroll
+            for (int p = 0; p < N; ++p) {
+                const T bb = tB<T, N>(q1, p), bd = tD<T, N>(q1, p);
+                vn += bb * h0[p]; t1n += bd * h0[p]; t2n += bb * h1[p]; dnn += bb * h2[p];
+            }
+            const T *fq = fd + N * q1 + gn_off * NF;
+            fnb[q1] = fq[0] * dnn + fq[NF] * t1n + fq[2 * NF] * t2n;
+            vnb[q1] = vn;
+        }
+    }
+    __syncthreads();
+    // step 1, own side, lane (f, p): layer and normal derivative from the
+    // values in LDS
+    if (fl) {
+        // the own cell touches with its upper layer when s = 1
+        const int m0 = s ? (N - 1) * sm : 0, dm = s ? -sm : sm;
+        const T sgn = s ? T(-1) : T(1);
+        const T *uo = U + rr * sp + m0;
         T Lo[N], No[N];
 #pragma unroll
         for (int r = 0; r < N; ++r) {
             T so = 0;
 #pragma unroll
-            for (int m = 0; m < N; ++m) so += tE<T, N>(eo, m) * U[lix<N>(d, m, rr, r)];
-            No[r] = so;
-            Lo[r] = U[lix<N>(d, mo, rr, r)];
+            for (int m = 0; m < N; ++m) so += tE<T, N>(0, m) * uo[r * sr + m * dm];
+            No[r] = sgn * so;
+            Lo[r] = uo[r * sr];
         }
-        T *gw = G + f * 6 * NF + rr;
-#pragma unroll
-        for (int q = 0; q < N; ++q) {
-            T g0 = 0, g1 = 0, g2 = 0, g3 = 0, g4 = 0, g5 = 0;
-#pragma unroll
-            for (int r = 0; r < N; ++r) {
-                const T bb = tB<T, N>(q, r), bd = tD<T, N>(q, r);
-                g0 += bb * Lo[r]; g1 += bd * Lo[r]; g2 += bb * No[r];
-                g3 += bb * Ln[r]; g4 += bd * Ln[r]; g5 += bb * Nn[r];
-            }
-            gw[0 * NF + q * N] = g0; gw[1 * NF + q * N] = g1; gw[2 * NF + q * N] = g2;
-            gw[3 * NF + q * N] = g3; gw[4 * NF + q * N] = g4; gw[5 * NF + q * N] = g5;
-        }
+        interp_t2(Lo, No);
     }
     __syncthreads();
     // the own values are no longer needed: the output pencils wait in sU
@@ -350,104 +427,61 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
 #pragma unroll
         for (int i = 0; i < N; ++i) sU[cs][i + N * a + NF * b] = Y[i];
     }
-    // step 2, lane (f, q2): first tangential direction, flux terms at the
-    // Gauss points, transposed sweep back along it.  The neighbour side is
-    // evaluated first (its flux and value per point), then the own side.
-    {
-        T A0[N], A1[N], A2[N];
-        const int q2 = rr;
-        if (fl) {
-            const int64_t fid = s ? cid : (int64_t)nb;
-            const T *fd = face + (fid * 3 + d) * 7 * NF + q2;   // [comp][q1][q2]
-            const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-            const T *gr = G + f * 6 * NF + q2 * N;
-            // g of the neighbour side: g+ if the own cell is the minus cell
-            const int gn_off = s ? 3 : 0, go_off = s ? 0 : 3;
-            T fnb[N], vnb[N];
-            {
-                T h0[N], h1[N], h2[N];
+    // steps 2 and 3, own side, lane (f, q2): pointwise terms and the
+    // transposed sweep along the first direction, written over the row read
+    if (fl) {
+        T h0[N], h1[N], h2[N], A0[N], A1[N], A2[N];
 #pragma unroll
-                for (int p = 0; p < N; ++p) {
-                    h0[p] = gr[3 * NF + p];
-                    h1[p] = gr[4 * NF + p];
-                    h2[p] = gr[5 * NF + p];
-                }
+        for (int p = 0; p < N; ++p) {
+            h0[p] = gf[rr * N + p];
+            h1[p] = gf[NF + rr * N + p];
+            h2[p] = gf[2 * NF + rr * N + p];
+            A0[p] = A1[p] = A2[p] = 0;
+        }
 #pragma unroll
-                for (int q1 = 0; q1 < N; ++q1) {
-                    T vn = 0, t1n = 0, t2n = 0, dnn = 0;
-#pragma unroll
-                    for (int p = 0; p < N; ++p) {
-                        const T bb = tB<T, N>(q1, p), bd = tD<T, N>(q1, p);
-                        vn += bb * h0[p]; t1n += bd * h0[p]; t2n += bb * h1[p]; dnn += bb * h2[p];
-                    }
-                    const T *fq = fd + N * q1 + gn_off * NF;
-                    T gn[3];
-                    gn[d] = dnn; gn[t1] = t1n; gn[t2] = t2n;
-                    fnb[q1] = fq[0] * gn[0] + fq[NF] * gn[1] + fq[2 * NF] * gn[2];
-                    vnb[q1] = vn;
-                }
-            }
-            T h0[N], h1[N], h2[N];
+        for (int q1 = 0; q1 < N; ++q1) {
+            T vo = 0, t1o = 0, t2o = 0, dno = 0;
 #pragma unroll
             for (int p = 0; p < N; ++p) {
-                h0[p] = gr[p];
-                h1[p] = gr[NF + p];
-                h2[p] = gr[2 * NF + p];
-                A0[p] = A1[p] = A2[p] = 0;
+                const T bb = tB<T, N>(q1, p), bd = tD<T, N>(q1, p);
+                vo += bb * h0[p]; t1o += bd * h0[p]; t2o += bb * h1[p]; dno += bb * h2[p];
             }
+            const T *fq = fd + N * q1 + go_off * NF;
+            const T g0 = fq[0], g1 = fq[NF], g2 = fq[2 * NF];
+            const T pen = fd[6 * NF + N * q1];
+            const T flux = g0 * dno + g1 * t1o + g2 * t2o + fnb[q1];
+            const T jump = s ? (vo - vnb[q1]) : (vnb[q1] - vo);
+            const T sg = s ? T(1) : T(-1);
+            const T cv = sg * (T(-0.5) * flux + pen * jump);
+            const T hj = T(-0.5) * jump;
+            const T cn = hj * g0, ct1 = hj * g1, ct2 = hj * g2;
 #pragma unroll
-            for (int q1 = 0; q1 < N; ++q1) {
-                T vo = 0, t1o = 0, t2o = 0, dno = 0;
-#pragma unroll
-                for (int p = 0; p < N; ++p) {
-                    const T bb = tB<T, N>(q1, p), bd = tD<T, N>(q1, p);
-                    vo += bb * h0[p]; t1o += bd * h0[p]; t2o += bb * h1[p]; dno += bb * h2[p];
-                }
-                const T *fq = fd + N * q1 + go_off * NF;
-                const T g0 = fq[0], g1 = fq[NF], g2 = fq[2 * NF];
-                const T pen = fd[6 * NF + N * q1];
-                T go[3];
-                go[d] = dno; go[t1] = t1o; go[t2] = t2o;
-                const T flux = g0 * go[0] + g1 * go[1] + g2 * go[2] + fnb[q1];
-                const T jump = s ? (vo - vnb[q1]) : (vnb[q1] - vo);
-                const T sg = s ? T(1) : T(-1);
-                const T cv = sg * (T(-0.5) * flux + pen * jump);
-                const T hj = T(-0.5) * jump;
-                T cg[3] = {hj * g0, hj * g1, hj * g2};
-                const T ct1 = cg[t1], ct2 = cg[t2], cn = cg[d];
-#pragma unroll
-                for (int p = 0; p < N; ++p) {
-                    const T bb = tB<T, N>(q1, p), bd = tD<T, N>(q1, p);
-                    A0[p] += bb * cv + bd * ct1;
-                    A1[p] += bb * ct2;
-                    A2[p] += bb * cn;
-                }
+            for (int p = 0; p < N; ++p) {
+                const T bb = tB<T, N>(q1, p), bd = tD<T, N>(q1, p);
+                A0[p] += bb * cv + bd * ct1;
+                A1[p] += bb * ct2;
+                A2[p] += bb * cn;
             }
         }
-        __syncthreads();
-        if (fl) {
-            T *gw = G + f * 3 * NF + q2 * N;
 #pragma unroll
-            for (int p = 0; p < N; ++p) {
-                gw[p] = A0[p];
-                gw[NF + p] = A1[p];
-                gw[2 * NF + p] = A2[p];
-            }
+        for (int p = 0; p < N; ++p) {
+            gf[rr * N + p] = A0[p];
+            gf[NF + rr * N + p] = A1[p];
+            gf[2 * NF + rr * N + p] = A2[p];
         }
     }
     __syncthreads();
-    // step 3, lane (f, p): transposed sweep along the second tangential
-    // direction; the layer (F0) and normal-derivative (F1) weights of column p
+    // step 4, lane (f, p): transposed sweep along the second direction, in
+    // place: layer weights (F0) and normal-derivative weights (F1) of column p
+    // in fields 0 and 1, [field][r][p]
     if (fl0) {
-        T *out = G + 18 * NF + f * 2 * NF + rr;      // [field][r][p]
         if (fl) {
-            const T *gr = G + f * 3 * NF + rr;
             T h0[N], h1[N], h2[N];
 #pragma unroll
             for (int q = 0; q < N; ++q) {
-                h0[q] = gr[q * N];
-                h1[q] = gr[NF + q * N];
-                h2[q] = gr[2 * NF + q * N];
+                h0[q] = gf[q * N + rr];
+                h1[q] = gf[NF + q * N + rr];
+                h2[q] = gf[2 * NF + q * N + rr];
             }
 #pragma unroll
             for (int r = 0; r < N; ++r) {
@@ -457,12 +491,12 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
                     f0 += tB<T, N>(q, r) * h0[q] + tD<T, N>(q, r) * h1[q];
                     f1 += tB<T, N>(q, r) * h2[q];
                 }
-                out[r * N] = f0;
-                out[NF + r * N] = f1;
+                gf[r * N + rr] = f0;
+                gf[NF + r * N + rr] = f1;
             }
         } else {
 #pragma unroll
-            for (int r = 0; r < N; ++r) out[r * N] = out[NF + r * N] = 0;
+            for (int r = 0; r < N; ++r) gf[r * N + rr] = gf[NF + r * N + rr] = 0;
         }
     }
     __syncthreads();
@@ -470,11 +504,11 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
     if (cl) {
 #pragma unroll
         for (int i = 0; i < N; ++i) Y[i] = sU[cs][i + N * a + NF * b];
-        const T *F = G + 18 * NF;
+        const T *F = G;
         // x faces: normal coordinate i, (p, r) = (j, l)
 #pragma unroll
         for (int sx = 0; sx < 2; ++sx) {
-            const T f0 = F[(0 + sx) * 2 * NF + b * N + a], f1 = F[(0 + sx) * 2 * NF + NF + b * N + a];
+            const T f0 = F[(0 + sx) * 3 * NF + b * N + a], f1 = F[(0 + sx) * 3 * NF + NF + b * N + a];
 #pragma unroll
             for (int i = 0; i < N; ++i)
                 Y[i] += tE<T, N>(sx, i) * f1 + ((i == (sx ? N - 1 : 0)) ? f0 : T(0));
@@ -482,7 +516,7 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
         // y faces: normal coordinate j = a, (p, r) = (i, l)
 #pragma unroll
         for (int sy = 0; sy < 2; ++sy) {
-            const T *F0 = F + (2 + sy) * 2 * NF + b * N, *F1 = F0 + NF;
+            const T *F0 = F + (2 + sy) * 3 * NF + b * N, *F1 = F0 + NF;
             T e1 = 0;
             // DL[sy][a] with a lane-dependent index: unrolled select
 #pragma unroll
@@ -495,7 +529,7 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
         // z faces: normal coordinate l = b, (p, r) = (i, j)
 #pragma unroll
         for (int sz = 0; sz < 2; ++sz) {
-            const T *F0 = F + (4 + sz) * 2 * NF + a * N, *F1 = F0 + NF;
+            const T *F0 = F + (4 + sz) * 3 * NF + a * N, *F1 = F0 + NF;
             T e1 = 0;
 #pragma unroll
             for (int m = 0; m < N; ++m)
@@ -518,7 +552,7 @@ hipError_t apply_n(hx_ctx *c, const T *x, T *y, const T *b)
     const T *cell = std::is_same<T, double>::value ? (const T *)c->cell64 : (const T *)c->cell32;
     const T *face = std::is_same<T, double>::value ? (const T *)c->face64 : (const T *)c->face32;
     hipLaunchKernelGGL((k_apply<N, T>), dim3(nwg), dim3(64), 0, c->stream, x, y, b, cell, face,
-                       c->nbr, c->order, (int)c->n_cells, nwg);
+                       c->visit, (int)c->n_cells, nwg);
     return hipGetLastError();
 }
 
