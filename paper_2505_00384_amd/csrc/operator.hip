@@ -76,6 +76,104 @@ __device__ __forceinline__ T tE(int e, int i)
     else return KDL<N>::f[e * N + i];
 }
 
+// ---------------------------------------------------------------------------
+// Even-odd evaluation of the 1-D contractions.  Gauss points and GLL nodes lie
+// symmetric about the centre, so B(N-1-q, N-1-i) = B(q, i) and
+// BD(N-1-q, N-1-i) = -BD(q, i), and the same holds for the transposes.  With
+// a pencil split into e_i = u_i + u_{N-1-i}, o_i = u_i - u_{N-1-i} (i < N/2)
+// and the middle value (N odd), rows r and N-1-r of a contraction come out as
+// the sum and difference of two partial sums over N/2 terms each, which
+// removes about a quarter of the multiply-adds for N = 5.
+
+// entry (r, c) of B (W = 0) or BD (W = 1), or of its transpose (TR)
+template <int N, int W, bool TR>
+__device__ __forceinline__ double tab(int r, int c)
+{
+    const int q = TR ? c : r, i = TR ? r : c;
+    return W ? KBD<N>::d[q * N + i] : KB<N>::d[q * N + i];
+}
+
+// split of a pencil into its even and odd parts
+template <typename T, int N>
+struct EvenOdd {
+    static constexpr int H = N / 2;
+    T e[H], o[H], m;
+    __device__ __forceinline__ explicit EvenOdd(const T (&u)[N])
+    {
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+            e[i] = u[i] + u[N - 1 - i];
+            o[i] = u[i] - u[N - 1 - i];
+        }
+        m = (N & 1) ? u[H] : T(0);
+    }
+};
+
+// output pencil as mirror-even (P) and mirror-odd (Q) partial sums of its
+// first (N+1)/2 rows: y_r = P_r + Q_r, y_{N-1-r} = P_r - Q_r
+template <typename T, int N>
+struct Rows {
+    static constexpr int H = N / 2, R = (N + 1) / 2;
+    T P[R], Q[R];
+    __device__ __forceinline__ Rows()
+    {
+#pragma unroll
+        for (int r = 0; r < R; ++r) P[r] = Q[r] = T(0);
+    }
+    // add M x with M = B or BD (W) or a transpose (TR); for a symmetric M the
+    // even part of x feeds P and the odd part Q, for an antisymmetric M the
+    // other way round; in the middle row (N odd) the part that vanishes by
+    // symmetry is skipped
+    template <int W, bool TR>
+    __device__ __forceinline__ void add(const EvenOdd<T, N> &x)
+    {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const bool mid = (N & 1) && r == H;
+            T &pe = W ? Q[r] : P[r];   // receives the even part
+            T &po = W ? P[r] : Q[r];   // receives the odd part
+            if (!(W && mid)) {
+                if (N & 1) pe += T(tab<N, W, TR>(r, H)) * x.m;
+#pragma unroll
+                for (int i = 0; i < H; ++i)
+                    pe += T(0.5 * (tab<N, W, TR>(r, i) + tab<N, W, TR>(r, N - 1 - i))) * x.e[i];
+            }
+            if (!(!W && mid)) {
+#pragma unroll
+                for (int i = 0; i < H; ++i)
+                    po += T(0.5 * (tab<N, W, TR>(r, i) - tab<N, W, TR>(r, N - 1 - i))) * x.o[i];
+            }
+        }
+    }
+    __device__ __forceinline__ void out(T (&y)[N]) const
+    {
+#pragma unroll
+        for (int r = 0; r < H; ++r) {
+            y[r] = P[r] + Q[r];
+            y[N - 1 - r] = P[r] - Q[r];
+        }
+        if (N & 1) y[H] = P[H];
+    }
+};
+
+// y = B u (W = 0) or BD u (W = 1) along a pencil; transposed with TR
+template <typename T, int N, int W, bool TR>
+__device__ __forceinline__ void contract(const EvenOdd<T, N> &x, T (&y)[N])
+{
+    Rows<T, N> acc;
+    acc.template add<W, TR>(x);
+    acc.out(y);
+}
+// y = B^T u + BD^T v
+template <typename T, int N>
+__device__ __forceinline__ void contract_t2(const T (&u)[N], const T (&v)[N], T (&y)[N])
+{
+    Rows<T, N> acc;
+    acc.template add<0, true>(EvenOdd<T, N>(u));
+    acc.template add<1, true>(EvenOdd<T, N>(v));
+    acc.out(y);
+}
+
 constexpr int pow2_at_least(int v)
 {
     int p = 1;
@@ -97,8 +195,10 @@ struct Cfg {
 // budget beats the occupancy the LDS use would allow)
 template <int N, typename T>
 struct Occ {
-    static constexpr int W = sizeof(T) == 8 ? (N <= 4 ? 4 : (N <= 6 ? 3 : 2))
-                                            : (N <= 5 ? 4 : (N <= 7 ? 3 : 2));
+    static constexpr int W = sizeof(T) == 8 ? (N <= 3 ? 4 : (N <= 5 ? 3 : 2))
+                                            : (N <= 4 ? 4 : (N <= 6 ? 3 : 2));
+    // request the quadrature-point data before the y sweep (register cost 7 N)
+    static constexpr bool PREFETCH_CELL = N <= 5;
 };
 
 template <typename T>
@@ -196,22 +296,28 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
     // =========================================================== cell part
     // x sweep: lane (j=a, l=b): B u and BD u along x
     if (cl) {
-        T r[N];
+        T r[N], s0[N], s1[N];
 #pragma unroll
         for (int i = 0; i < N; ++i) r[i] = U[i + N * a + NF * b];
+        const EvenOdd<T, N> xr(r);
+        contract<T, N, 0, false>(xr, s0);
+        contract<T, N, 1, false>(xr, s1);
 #pragma unroll
         for (int q = 0; q < N; ++q) {
-            T s0 = 0, s1 = 0;
-#pragma unroll
-            for (int i = 0; i < N; ++i) {
-                s0 += tB<T, N>(q, i) * r[i];
-                s1 += tD<T, N>(q, i) * r[i];
-            }
-            G[q + N * a + NF * b] = s0;
-            G[ND + q + N * a + NF * b] = s1;
+            G[q + N * a + NF * b] = s0[q];
+            G[ND + q + N * a + NF * b] = s1[q];
         }
     }
     __syncthreads();
+    // quadrature-point data, requested before the y sweep so that the
+    // stream is in flight while it runs
+    T cdat[7][N];
+    if (Occ<N, T>::PREFETCH_CELL && cl) {
+#pragma unroll
+        for (int q = 0; q < N; ++q)
+#pragma unroll
+            for (int k = 0; k < 7; ++k) cdat[k][q] = ld_stream(cp + NF * q + k * ND);
+    }
     // y sweep: lane (qx=a, l=b)
     {
         T c0[N], c1[N], c2[N];
@@ -222,17 +328,10 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
                 p0[j] = G[a + N * j + NF * b];
                 p1[j] = G[ND + a + N * j + NF * b];
             }
-#pragma unroll
-            for (int q = 0; q < N; ++q) {
-                T s0 = 0, s1 = 0, s2 = 0;
-#pragma unroll
-                for (int j = 0; j < N; ++j) {
-                    s0 += tB<T, N>(q, j) * p0[j];
-                    s1 += tD<T, N>(q, j) * p0[j];
-                    s2 += tB<T, N>(q, j) * p1[j];
-                }
-                c0[q] = s0; c1[q] = s1; c2[q] = s2;
-            }
+            const EvenOdd<T, N> x0(p0), x1(p1);
+            contract<T, N, 0, false>(x0, c0);
+            contract<T, N, 1, false>(x0, c1);
+            contract<T, N, 0, false>(x1, c2);
         }
         __syncthreads();
         if (cl) {
@@ -255,33 +354,33 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
                 p0[l] = G[a + N * b + NF * l];
                 p1[l] = G[ND + a + N * b + NF * l];
                 p2[l] = G[2 * ND + a + N * b + NF * l];
-                t0[l] = t1[l] = t2[l] = 0;
             }
+            T uq[N], dzq[N], dyq[N], dxq[N];
+            {
+                const EvenOdd<T, N> x0(p0);
+                contract<T, N, 0, false>(x0, uq);
+                contract<T, N, 1, false>(x0, dzq);
+                contract<T, N, 0, false>(EvenOdd<T, N>(p1), dyq);
+                contract<T, N, 0, false>(EvenOdd<T, N>(p2), dxq);
+            }
+            T vq[N], fxq[N], fyq[N], fzq[N];
 #pragma unroll
             for (int q = 0; q < N; ++q) {
-                T u = 0, dz = 0, dy = 0, dx = 0;
+                const T u = uq[q], dz = dzq[q], dy = dyq[q], dx = dxq[q];
+                T cq[7];
 #pragma unroll
-                for (int l = 0; l < N; ++l) {
-                    u += tB<T, N>(q, l) * p0[l];
-                    dz += tD<T, N>(q, l) * p0[l];
-                    dy += tB<T, N>(q, l) * p1[l];
-                    dx += tB<T, N>(q, l) * p2[l];
-                }
-                const T *cq = cp + NF * q;
-                const T m = ld_stream(cq), gxx = ld_stream(cq + ND), gxy = ld_stream(cq + 2 * ND),
-                        gxz = ld_stream(cq + 3 * ND), gyy = ld_stream(cq + 4 * ND),
-                        gyz = ld_stream(cq + 5 * ND), gzz = ld_stream(cq + 6 * ND);
-                const T v = m * u;
-                const T fx = gxx * dx + gxy * dy + gxz * dz;
-                const T fy = gxy * dx + gyy * dy + gyz * dz;
-                const T fz = gxz * dx + gyz * dy + gzz * dz;
-#pragma unroll
-                for (int l = 0; l < N; ++l) {
-                    t0[l] += tB<T, N>(q, l) * v + tD<T, N>(q, l) * fz;
-                    t1[l] += tB<T, N>(q, l) * fy;
-                    t2[l] += tB<T, N>(q, l) * fx;
-                }
+                for (int k = 0; k < 7; ++k)
+                    cq[k] = Occ<N, T>::PREFETCH_CELL ? cdat[k][q] : ld_stream(cp + NF * q + k * ND);
+                const T m = cq[0], gxx = cq[1], gxy = cq[2], gxz = cq[3], gyy = cq[4], gyz = cq[5],
+                        gzz = cq[6];
+                vq[q] = m * u;
+                fxq[q] = gxx * dx + gxy * dy + gxz * dz;
+                fyq[q] = gxy * dx + gyy * dy + gyz * dz;
+                fzq[q] = gxz * dx + gyz * dy + gzz * dz;
             }
+            contract_t2<T, N>(vq, fzq, t0);
+            contract<T, N, 0, true>(EvenOdd<T, N>(fyq), t1);
+            contract<T, N, 0, true>(EvenOdd<T, N>(fxq), t2);
         }
         __syncthreads();
         if (cl) {
@@ -305,16 +404,8 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
                 p1[q] = G[ND + a + N * q + NF * b];
                 p2[q] = G[2 * ND + a + N * q + NF * b];
             }
-#pragma unroll
-            for (int j = 0; j < N; ++j) {
-                T s0 = 0, s1 = 0;
-#pragma unroll
-                for (int q = 0; q < N; ++q) {
-                    s0 += tB<T, N>(q, j) * p0[q] + tD<T, N>(q, j) * p1[q];
-                    s1 += tB<T, N>(q, j) * p2[q];
-                }
-                s0v[j] = s0; s1v[j] = s1;
-            }
+            contract_t2<T, N>(p0, p1, s0v);
+            contract<T, N, 0, true>(EvenOdd<T, N>(p2), s1v);
         }
         __syncthreads();
         if (cl) {
@@ -334,13 +425,7 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
             p0[q] = G[q + N * a + NF * b];
             p1[q] = G[ND + q + N * a + NF * b];
         }
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-            T sacc = 0;
-#pragma unroll
-            for (int q = 0; q < N; ++q) sacc += tB<T, N>(q, i) * p0[q] + tD<T, N>(q, i) * p1[q];
-            Y[i] = sacc;
-        }
+        contract_t2<T, N>(p0, p1, Y);
     }
     __syncthreads();
 
@@ -357,18 +442,16 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
     T *gf = G + f * 3 * NF;
     // step 1 of one side: fields B L, BD L, B Nd along the second direction
     auto interp_t2 = [&](const T (&L)[N], const T (&Nd)[N]) {
+        T g0[N], g1[N], g2[N];
+        const EvenOdd<T, N> xl(L);
+        contract<T, N, 0, false>(xl, g0);
+        contract<T, N, 1, false>(xl, g1);
+        contract<T, N, 0, false>(EvenOdd<T, N>(Nd), g2);
 #pragma unroll
         for (int q = 0; q < N; ++q) {
-            T g0 = 0, g1 = 0, g2 = 0;
-#pragma unroll
-            for (int r = 0; r < N; ++r) {
-                g0 += tB<T, N>(q, r) * L[r];
-                g1 += tD<T, N>(q, r) * L[r];
-                g2 += tB<T, N>(q, r) * Nd[r];
-            }
-            gf[q * N + rr] = g0;
-            gf[NF + q * N + rr] = g1;
-            gf[2 * NF + q * N + rr] = g2;
+            gf[q * N + rr] = g0[q];
+            gf[NF + q * N + rr] = g1[q];
+            gf[2 * NF + q * N + rr] = g2[q];
         }
     };
     // face data of this row: [comp][q1][q2], components g-(3), g+(3), s
@@ -377,6 +460,20 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
     // g of the neighbour side: g+ if the own cell is the minus cell
     const int gn_off = s ? 3 : 0, go_off = s ? 0 : 3;
 
+    // face data of this row, all requested at once: g of the neighbour side,
+    // g of the own side and the penalty factor at the row's N points
+    T gnb[3][N], gow[3][N], pn[N];
+    if (fl) {
+#pragma unroll
+        for (int q1 = 0; q1 < N; ++q1) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                gnb[k][q1] = fd[(gn_off + k) * NF + N * q1];
+                gow[k][q1] = fd[(go_off + k) * NF + N * q1];
+            }
+            pn[q1] = fd[6 * NF + N * q1];
+        }
+    }
     if (fl) interp_t2(Ln, Nn);
     __syncthreads();
     // step 2, neighbour side, lane (f, q2): flux and value at (q1, q2)
@@ -389,18 +486,17 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
             h1[p] = gf[NF + rr * N + p];
             h2[p] = gf[2 * NF + rr * N + p];
         }
-#pragma unroll
-        for (int q1 = 0; q1 < N; ++q1) {
-            T vn = 0, t1n = 0, t2n = 0, dnn = 0;
-#pragma unroll
-            for (int p = 0; p < N; ++p) {
-                const T bb = tB<T, N>(q1, p), bd = tD<T, N>(q1, p);
-                vn += bb * h0[p]; t1n += bd * h0[p]; t2n += bb * h1[p]; dnn += bb * h2[p];
-            }
-            const T *fq = fd + N * q1 + gn_off * NF;
-            fnb[q1] = fq[0] * dnn + fq[NF] * t1n + fq[2 * NF] * t2n;
-            vnb[q1] = vn;
+        T t1n[N], t2n[N], dnn[N];
+        {
+            const EvenOdd<T, N> x0(h0);
+            contract<T, N, 0, false>(x0, vnb);
+            contract<T, N, 1, false>(x0, t1n);
+            contract<T, N, 0, false>(EvenOdd<T, N>(h1), t2n);
+            contract<T, N, 0, false>(EvenOdd<T, N>(h2), dnn);
         }
+#pragma unroll
+        for (int q1 = 0; q1 < N; ++q1)
+            fnb[q1] = gnb[0][q1] * dnn[q1] + gnb[1][q1] * t1n[q1] + gnb[2][q1] * t2n[q1];
     }
     __syncthreads();
     // step 1, own side, lane (f, p): layer and normal derivative from the
@@ -436,33 +532,34 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
             h0[p] = gf[rr * N + p];
             h1[p] = gf[NF + rr * N + p];
             h2[p] = gf[2 * NF + rr * N + p];
-            A0[p] = A1[p] = A2[p] = 0;
         }
+        T voq[N], t1q[N], t2q[N], dnq[N];
+        {
+            const EvenOdd<T, N> x0(h0);
+            contract<T, N, 0, false>(x0, voq);
+            contract<T, N, 1, false>(x0, t1q);
+            contract<T, N, 0, false>(EvenOdd<T, N>(h1), t2q);
+            contract<T, N, 0, false>(EvenOdd<T, N>(h2), dnq);
+        }
+        T cvq[N], ct1q[N], ct2q[N], cnq[N];
 #pragma unroll
         for (int q1 = 0; q1 < N; ++q1) {
-            T vo = 0, t1o = 0, t2o = 0, dno = 0;
-#pragma unroll
-            for (int p = 0; p < N; ++p) {
-                const T bb = tB<T, N>(q1, p), bd = tD<T, N>(q1, p);
-                vo += bb * h0[p]; t1o += bd * h0[p]; t2o += bb * h1[p]; dno += bb * h2[p];
-            }
-            const T *fq = fd + N * q1 + go_off * NF;
-            const T g0 = fq[0], g1 = fq[NF], g2 = fq[2 * NF];
-            const T pen = fd[6 * NF + N * q1];
+            const T vo = voq[q1], t1o = t1q[q1], t2o = t2q[q1], dno = dnq[q1];
+            const T g0 = gow[0][q1], g1 = gow[1][q1], g2 = gow[2][q1];
+            const T pen = pn[q1];
             const T flux = g0 * dno + g1 * t1o + g2 * t2o + fnb[q1];
             const T jump = s ? (vo - vnb[q1]) : (vnb[q1] - vo);
             const T sg = s ? T(1) : T(-1);
             const T cv = sg * (T(-0.5) * flux + pen * jump);
             const T hj = T(-0.5) * jump;
-            const T cn = hj * g0, ct1 = hj * g1, ct2 = hj * g2;
-#pragma unroll
-            for (int p = 0; p < N; ++p) {
-                const T bb = tB<T, N>(q1, p), bd = tD<T, N>(q1, p);
-                A0[p] += bb * cv + bd * ct1;
-                A1[p] += bb * ct2;
-                A2[p] += bb * cn;
-            }
+            cvq[q1] = cv;
+            cnq[q1] = hj * g0;
+            ct1q[q1] = hj * g1;
+            ct2q[q1] = hj * g2;
         }
+        contract_t2<T, N>(cvq, ct1q, A0);
+        contract<T, N, 0, true>(EvenOdd<T, N>(ct2q), A1);
+        contract<T, N, 0, true>(EvenOdd<T, N>(cnq), A2);
 #pragma unroll
         for (int p = 0; p < N; ++p) {
             gf[rr * N + p] = A0[p];
@@ -483,16 +580,13 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
                 h1[q] = gf[NF + q * N + rr];
                 h2[q] = gf[2 * NF + q * N + rr];
             }
+            T f0[N], f1[N];
+            contract_t2<T, N>(h0, h1, f0);
+            contract<T, N, 0, true>(EvenOdd<T, N>(h2), f1);
 #pragma unroll
             for (int r = 0; r < N; ++r) {
-                T f0 = 0, f1 = 0;
-#pragma unroll
-                for (int q = 0; q < N; ++q) {
-                    f0 += tB<T, N>(q, r) * h0[q] + tD<T, N>(q, r) * h1[q];
-                    f1 += tB<T, N>(q, r) * h2[q];
-                }
-                gf[r * N + rr] = f0;
-                gf[NF + r * N + rr] = f1;
+                gf[r * N + rr] = f0[r];
+                gf[NF + r * N + rr] = f1[r];
             }
         } else {
 #pragma unroll
