@@ -157,7 +157,7 @@ hx_status hx_apply_preconditioner(hx_ctx *c, hx_pc kind, hx_prec prec,
 
 typedef struct {
     int method;          /* 0 = preconditioned CG, 1 = flexible GMRES(restart) */
-    int restart;         /* FGMRES restart length, 1..64 (30) */
+    int restart;         /* FGMRES restart length, 1..63 (30) */
     double rtol;         /* stop when ||b - A x||_2 <= rtol ||b||_2 */
     int max_iter;        /* total iteration cap */
     int pc;              /* hx_pc of the (outer) iteration */
@@ -167,6 +167,10 @@ typedef struct {
     int x0_mode;         /* 0: start from zero, 1: x holds the initial guess */
     int stall_window;    /* FGMRES stall rule window (10); 0 disables it */
     double stall_ratio;  /* stall if estimate > ratio * estimate window ago (0.99) */
+    int orth;            /* FGMRES orthogonalisation, both classical Gram-Schmidt twice:
+                            0 = two block-dot/update pairs per step (four passes over
+                            the basis), 1 = second pass delayed by one step and fused
+                            with the next step's (two passes; default) */
 } hx_solve_params;
 
 typedef struct {

@@ -41,7 +41,7 @@ class SolveParams(C.Structure):
                 ("max_iter", C.c_int), ("pc", C.c_int), ("mixed", C.c_int),
                 ("inner_iters", C.c_int), ("inner_rtol", C.c_double),
                 ("x0_mode", C.c_int), ("stall_window", C.c_int),
-                ("stall_ratio", C.c_double)]
+                ("stall_ratio", C.c_double), ("orth", C.c_int)]
 
 
 class SolveInfo(C.Structure):

@@ -90,6 +90,114 @@ __global__ void __launch_bounds__(RT) k_mdot1(int64_t n, int v0, int mc,
     }
 }
 
+// two-sided block dot over the vector chunk blockIdx.y:
+// part[(k)*ld + blk] = sum_i V[k][i] a[i], part[(mtot + k)*ld + blk] = sum_i V[k][i] b[i]
+__global__ void __launch_bounds__(RT) k_mdot2(int64_t n, int mtot, const double *__restrict__ V,
+                                              int64_t ldv, const double *__restrict__ a,
+                                              const double *__restrict__ b, double *part, int ld)
+{
+    __shared__ double sh[RT / 64];
+    const int v0 = blockIdx.y * MC;
+    const int mc = (mtot - v0) < MC ? (mtot - v0) : MC;
+    double sa[MC], sb[MC];
+#pragma unroll
+    for (int k = 0; k < MC; ++k) sa[k] = sb[k] = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * RT;
+    for (int64_t i = blockIdx.x * (int64_t)RT + threadIdx.x; i < n; i += stride) {
+        const double ai = a[i], bi = b[i];
+#pragma unroll
+        for (int k = 0; k < MC; ++k)
+            if (k < mc) {
+                const double v = V[(int64_t)(v0 + k) * ldv + i];
+                sa[k] += v * ai;
+                sb[k] += v * bi;
+            }
+    }
+#pragma unroll
+    for (int k = 0; k < MC; ++k) {
+        if (k >= mc) break;
+        const double ra = block_sum(sa[k], sh);
+        const double rb = block_sum(sb[k], sh);
+        if (threadIdx.x == 0) {
+            part[(int64_t)(v0 + k) * ld + blockIdx.x] = ra;
+            part[(int64_t)(mtot + v0 + k) * ld + blockIdx.x] = rb;
+        }
+    }
+}
+
+// Scalars of one delayed-reorthogonalisation step (see solver.cpp), one
+// thread, fixed summation order.  sc[0..j): c = V_{j-1}^T t, sc[j]: t.t,
+// sc[64..64+j): h = V_{j-1}^T w, sc[64+j]: t.w.  Writes sc[DC_CW + k] =
+// h_k - c_k hj/rho, and sc[DC_S + 0..4] = 1/rho, hj/rho, rho, hj, flag (1 if
+// t lies in the span of V_{j-1} to working precision).
+constexpr int DC_CW = 300, DC_S = 364;
+__global__ void k_dcgs_coef(int j, double *sc)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double cc = 0.0, ch = 0.0;
+    for (int k = 0; k < j; ++k) {
+        cc += sc[k] * sc[k];
+        ch += sc[k] * sc[64 + k];
+    }
+    const double r2 = sc[j] - cc;
+    double flag = 0.0, rho;
+    if (r2 > 0.0 && r2 >= 1e-12 * sc[j]) {
+        rho = sqrt(r2);
+    } else {
+        flag = 1.0;
+        rho = sc[j] > 0.0 ? sqrt(sc[j]) : 1.0;
+    }
+    const double hj = (sc[64 + j] - ch) / rho;
+    for (int k = 0; k < j; ++k) sc[DC_CW + k] = sc[64 + k] - sc[k] * (hj / rho);
+    sc[DC_S + 0] = 1.0 / rho;
+    sc[DC_S + 1] = hj / rho;
+    sc[DC_S + 2] = rho;
+    sc[DC_S + 3] = hj;
+    sc[DC_S + 4] = flag;
+}
+
+// Fused update of one delayed step: with t = V[j] (tentative vector),
+//   V[j] <- (t - V_{j-1} c) / rho,  w <- w - V_{j-1} cw - t hj/rho,
+// and part[blk] = partial sums of the new |w|^2.  Reads V_{j-1} once.
+__global__ void __launch_bounds__(RT) k_dcgs_update(int64_t n, int j, double *V, int64_t ldv,
+                                                    const double *__restrict__ sc, double *w,
+                                                    double *part)
+{
+    __shared__ double sh[RT / 64];
+    __shared__ double cs[64], cws[64];
+    for (int k = threadIdx.x; k < j; k += RT) {
+        cs[k] = sc[k];
+        cws[k] = sc[DC_CW + k];
+    }
+    __syncthreads();
+    const double irho = sc[DC_S + 0], hr = sc[DC_S + 1];
+    double nu = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * RT;
+    double *t = V + (int64_t)j * ldv;
+    for (int64_t i = blockIdx.x * (int64_t)RT + threadIdx.x; i < n; i += stride) {
+        double sv = 0.0, sw = 0.0;
+        int k = 0;
+        for (; k + 4 <= j; k += 4) {
+            const double v0 = V[(int64_t)k * ldv + i], v1 = V[(int64_t)(k + 1) * ldv + i],
+                         v2 = V[(int64_t)(k + 2) * ldv + i], v3 = V[(int64_t)(k + 3) * ldv + i];
+            sv += v0 * cs[k] + v1 * cs[k + 1] + v2 * cs[k + 2] + v3 * cs[k + 3];
+            sw += v0 * cws[k] + v1 * cws[k + 1] + v2 * cws[k + 2] + v3 * cws[k + 3];
+        }
+        for (; k < j; ++k) {
+            const double v = V[(int64_t)k * ldv + i];
+            sv += v * cs[k];
+            sw += v * cws[k];
+        }
+        const double ti = t[i];
+        t[i] = (ti - sv) * irho;
+        const double wn = w[i] - sw - ti * hr;
+        w[i] = wn;
+        nu += wn * wn;
+    }
+    nu = block_sum(nu, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = nu;
+}
+
 // w += sign * sum_k h[k] V[k]
 __global__ void k_mupdate(int64_t n, int m, const double *__restrict__ V, int64_t ldv,
                           const double *__restrict__ h, double sign, double *w)
@@ -207,6 +315,38 @@ hipError_t blas_mdot(hx_ctx *c, int64_t n, int m, const double *V, int64_t ldv, 
                            RED_MAX);
     }
     hipLaunchKernelGGL(k_red2, dim3(m), dim3(RT), 0, c->stream, c->red, nb, RED_MAX, dst);
+    return hipGetLastError();
+}
+
+// dst_a[k] = V[k].a, dst_b[k] = V[k].b for k < m (m <= 64)
+hipError_t blas_mdot2(hx_ctx *c, int64_t n, int m, const double *V, int64_t ldv, const double *a,
+                      const double *b, double *dst_a, double *dst_b)
+{
+    // two rows of partial sums per vector: 128 rows of 512 fit below the
+    // device scalar area
+    int nb = red_blocks(n);
+    if (nb > RED_MAX / 2) nb = RED_MAX / 2;
+    const int nch = (m + MC - 1) / MC;
+    hipLaunchKernelGGL(k_mdot2, dim3(nb, nch), dim3(RT), 0, c->stream, n, m, V, ldv, a, b, c->red,
+                       RED_MAX / 2);
+    hipLaunchKernelGGL(k_red2, dim3(m), dim3(RT), 0, c->stream, c->red, nb, RED_MAX / 2, dst_a);
+    hipLaunchKernelGGL(k_red2, dim3(m), dim3(RT), 0, c->stream, c->red + (int64_t)m * (RED_MAX / 2),
+                       nb, RED_MAX / 2, dst_b);
+    return hipGetLastError();
+}
+
+// one delayed-reorthogonalisation step after blas_mdot2 filled sc (see
+// k_dcgs_coef): finalises V[j], projects w, stores |w|^2 in sc[128] and the
+// tentative next vector w/|w| in V[j+1]
+hipError_t blas_dcgs_step(hx_ctx *c, int64_t n, int j, double *V, int64_t ldv, double *w,
+                          double *sc)
+{
+    hipLaunchKernelGGL(k_dcgs_coef, dim3(1), dim3(64), 0, c->stream, j, sc);
+    const int nb = red_blocks(n);
+    hipLaunchKernelGGL(k_dcgs_update, dim3(nb), dim3(RT), 0, c->stream, n, j, V, ldv, sc, w, c->red);
+    hipLaunchKernelGGL(k_red2, dim3(1), dim3(RT), 0, c->stream, c->red, nb, RED_MAX, sc + 128);
+    hipLaunchKernelGGL(k_scale_copy, dim3(nb256(n)), dim3(256), 0, c->stream, n, sc + 128, 2, w,
+                       V + (int64_t)(j + 1) * ldv);
     return hipGetLastError();
 }
 

@@ -134,6 +134,11 @@ hipError_t blas_dot(hx_ctx *c, int64_t n, const double *x, const double *y, doub
 hipError_t blas_dot32(hx_ctx *c, int64_t n, const float *x, const float *y, double *dst);
 hipError_t blas_mdot(hx_ctx *c, int64_t n, int m, const double *V, int64_t ldv,
                      const double *w, double *dst /*[m]*/);
+hipError_t blas_mdot2(hx_ctx *c, int64_t n, int m, const double *V, int64_t ldv, const double *a,
+                      const double *b, double *dst_a, double *dst_b);
+hipError_t blas_dcgs_step(hx_ctx *c, int64_t n, int j, double *V, int64_t ldv, double *w,
+                          double *sc);
+constexpr int DCGS_S = 364;   // device scalars of blas_dcgs_step: 1/rho, hj/rho, rho, hj, flag
 hipError_t blas_mupdate(hx_ctx *c, int64_t n, int m, const double *V, int64_t ldv,
                         const double *h /*device [m]*/, double sign, double *w);
 hipError_t blas_axpby(hx_ctx *c, int64_t n, double a, const double *x, double b, double *y);

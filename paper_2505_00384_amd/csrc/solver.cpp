@@ -5,9 +5,10 @@
 //
 //  * CG: preconditioned conjugate gradients in FP64.
 //  * FGMRES(m): right-preconditioned flexible GMRES with classical
-//    Gram-Schmidt applied twice (CGS2: one pass over the basis for the block
-//    dot products, one for the update, repeated), Givens rotations on the
-//    host, explicit residual b - A x at every restart.
+//    Gram-Schmidt applied twice (CGS2), either as two block-dot/update pairs
+//    per step or with the second pass delayed and fused into the next step
+//    (two passes over the basis per step instead of four), Givens rotations
+//    on the host, explicit residual b - A x at every restart.
 //  * Mixed precision: the FGMRES preconditioner is an inner FP32 PCG with
 //    FP32 operator and FP32 block Jacobi, run for a fixed number of
 //    iterations with all scalars kept on the device; the outer residual,
@@ -209,6 +210,71 @@ hx_status solve_cg(hx_ctx *c, const hx_solve_params *prm, const double *b, doubl
 }
 
 // --------------------------------------------------------------- FGMRES
+// Givens bookkeeping of one FGMRES cycle on the host: raw (unrotated)
+// Hessenberg columns, rotations, rotated right-hand side g.
+struct Hess {
+    int m;
+    std::vector<double> raw, R, cs, sn, g;
+    explicit Hess(int m_) : m(m_), raw((size_t)(m_ + 1) * m_), R((size_t)(m_ + 1) * m_), cs(m_),
+                            sn(m_), g(m_ + 1) {}
+    double &h(int i, int j) { return raw[(size_t)i * m + j]; }
+    double &r(int i, int j) { return R[(size_t)i * m + j]; }
+    void reset(double beta)
+    {
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+    }
+    // rotate column j (entries 0..j+1 of raw) into R; false on breakdown
+    bool rotate(int j)
+    {
+        for (int i = 0; i <= j + 1; ++i) r(i, j) = h(i, j);
+        for (int i = 0; i < j; ++i) {
+            const double t = cs[i] * r(i, j) + sn[i] * r(i + 1, j);
+            r(i + 1, j) = -sn[i] * r(i, j) + cs[i] * r(i + 1, j);
+            r(i, j) = t;
+        }
+        const double den = std::hypot(r(j, j), r(j + 1, j));
+        if (!(den > 0.0) || !std::isfinite(den)) return false;
+        cs[j] = r(j, j) / den;
+        sn[j] = r(j + 1, j) / den;
+        r(j, j) = den;
+        r(j + 1, j) = 0.0;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        return true;
+    }
+    // |g_{j+1}| that rotate(j) would give, without changing the state
+    double peek(int j)
+    {
+        std::vector<double> col(j + 2);
+        for (int i = 0; i <= j + 1; ++i) col[i] = h(i, j);
+        for (int i = 0; i < j; ++i) {
+            const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+            col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+            col[i] = t;
+        }
+        const double a = col[j], b = col[j + 1];
+        const double den = std::hypot(a, b);
+        if (!(den > 0.0) || !std::isfinite(den)) return INFINITY;
+        return std::fabs(b / den * g[j]);
+    }
+};
+
+// FGMRES(m), right preconditioned: A Z_k = V_{k+1} Hbar_k with orthonormal V
+// and free Z (the preconditioner may change between steps).  Two ways of
+// orthogonalising w = A z_j against V:
+//  orth = 0: CGS2, two passes of block dot + update over V (four reads of V);
+//  orth = 1: CGS2 with the second pass delayed by one step and fused with the
+//    next step's pass: step j receives the once-orthogonalised, normalised
+//    vector t_j, applies the preconditioner and A to it, and one block dot of
+//    [V_{j-1}, t_j] against [t_j, w] gives both the reorthogonalisation
+//    coefficients c of t_j and the projections of w.  One fused update then
+//    finalises v_j = (t_j - V_{j-1} c)/rho and projects w (two reads of V).
+//    Since t_j = rho v_j + V_{j-1} c, column j-1 of H gains nu_{j-1} c and
+//    H(j, j-1) = nu_{j-1} rho one step late; a cycle ends with one extra
+//    block dot that finalises its last column.  Convergence is tested on the
+//    provisional column (the correction is of the order of the loss of
+//    orthogonality) and confirmed after finalising it.
 hx_status solve_fgmres(hx_ctx *c, const hx_solve_params *prm, const double *b, double *x,
                        hx_solve_info *info, Timer &tm)
 {
@@ -221,11 +287,13 @@ hx_status solve_fgmres(hx_ctx *c, const hx_solve_params *prm, const double *b, d
     double *V = c->work64;                 // (m+1) n
     double *Z = V + (size_t)(m + 1) * n;   // m n
     double *w = Z + (size_t)m * n;         // n
-    double *rtmp = w + n;                  // n
     float *w32 = c->work32;
-    double *sc = c->red + SC_OFF;          // [0..64] h1, [64..128] h2, [128] hn, [129] bb, [130..] y
-    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), hv(2 * 65 + 2);
-    auto Hm = [&](int i, int j) -> double & { return H[(size_t)i * m + j]; };
+    // device scalars: [0..64] dots with the first vector, [64..128] with the
+    // second, [128] |w|^2, [129] |b|^2, [130..194] y, [300..370] delayed step
+    double *sc = c->red + SC_OFF;
+    Hess H(m);
+    std::vector<double> y(m);
+    const bool delayed = prm->orth == 1;
 
     HX_HIP(c, blas_dot(c, n, b, b, sc + 129));
     double tmp[1];
@@ -242,6 +310,37 @@ hx_status solve_fgmres(hx_ctx *c, const hx_solve_params *prm, const double *b, d
     int it = 0, hist = 0;
     std::vector<double> est_hist;
     bool done = false;
+    // finalised residual estimate after column j: history, stall rule
+    auto record = [&](int j) -> double {
+        const double est = std::fabs(H.g[j + 1]) / nb;
+        est_hist.push_back(est);
+        if (info->history && hist < info->history_len) info->history[hist++] = est;
+        return est;
+    };
+    auto stalled = [&]() {
+        return pc == HX_PC_LEARNED && prm->stall_window > 0 &&
+               (int)est_hist.size() > prm->stall_window &&
+               est_hist.back() > prm->stall_ratio * est_hist[est_hist.size() - 1 - prm->stall_window];
+    };
+    // delayed form: reorthogonalise the tentative vector V[j+1] against
+    // V[0..j] and finalise column j (H(0..j, j) += nu c, H(j+1, j) = nu rho)
+    double nu_prev = 0.0;
+    auto finalise = [&](int j) -> hx_status {
+        tm.rec(2, c->stream);
+        HX_HIP(c, blas_mdot(c, n, j + 2, V, n, V + (size_t)(j + 1) * n, sc));
+        tm.rec(3, c->stream);
+        HX_HIP(c, hipMemcpyAsync(c->red_host, sc, sizeof(double) * (j + 2), hipMemcpyDeviceToHost,
+                                 c->stream));
+        HX_HIP(c, hipStreamSynchronize(c->stream));
+        tm.orth += tm.span(2, 3);
+        double cc = 0.0;
+        for (int i = 0; i <= j; ++i) cc += c->red_host[i] * c->red_host[i];
+        const double r2 = c->red_host[j + 1] - cc;
+        for (int i = 0; i <= j; ++i) H.h(i, j) += nu_prev * c->red_host[i];
+        H.h(j + 1, j) = r2 > 0.0 ? nu_prev * std::sqrt(r2) : 0.0;
+        return HX_OK;
+    };
+
     while (!done && it < prm->max_iter) {
         // explicit residual
         HX_HIP(c, launch_apply64(c, x, V, b));
@@ -252,10 +351,9 @@ hx_status solve_fgmres(hx_ctx *c, const hx_solve_params *prm, const double *b, d
         if (!std::isfinite(rel0)) return fail(c, HX_ERR_NOCONV, "non-finite residual");
         if (rel0 <= prm->rtol) break;
         HX_HIP(c, blas_scale_copy(c, n, sc + 128, 2, V, V));
-        std::fill(g.begin(), g.end(), 0.0);
-        g[0] = beta;
+        H.reset(beta);
         int j_used = 0;
-        bool sw = false;
+        bool sw = false, stop = false;
         for (int j = 0; j < m && it < prm->max_iter; ++j) {
             double *vj = V + (size_t)j * n, *zj = Z + (size_t)j * n;
             int nonfinite = 0;
@@ -270,56 +368,118 @@ hx_status solve_fgmres(hx_ctx *c, const hx_solve_params *prm, const double *b, d
             tm.rec(1, c->stream);
             HX_HIP(c, launch_apply64(c, zj, w, nullptr));
             tm.rec(2, c->stream);
-            // CGS2
-            HX_HIP(c, blas_mdot(c, n, j + 1, V, n, w, sc));
-            HX_HIP(c, blas_mupdate(c, n, j + 1, V, n, sc, -1.0, w));
-            HX_HIP(c, blas_mdot(c, n, j + 1, V, n, w, sc + 64));
-            HX_HIP(c, blas_mupdate(c, n, j + 1, V, n, sc + 64, -1.0, w));
-            HX_HIP(c, blas_dot(c, n, w, w, sc + 128));
-            HX_HIP(c, blas_scale_copy(c, n, sc + 128, 2, w, V + (size_t)(j + 1) * n));
+            if (!delayed) {
+                // CGS2
+                HX_HIP(c, blas_mdot(c, n, j + 1, V, n, w, sc));
+                HX_HIP(c, blas_mupdate(c, n, j + 1, V, n, sc, -1.0, w));
+                HX_HIP(c, blas_mdot(c, n, j + 1, V, n, w, sc + 64));
+                HX_HIP(c, blas_mupdate(c, n, j + 1, V, n, sc + 64, -1.0, w));
+                HX_HIP(c, blas_dot(c, n, w, w, sc + 128));
+                HX_HIP(c, blas_scale_copy(c, n, sc + 128, 2, w, V + (size_t)(j + 1) * n));
+                tm.rec(3, c->stream);
+                HX_HIP(c, hipMemcpyAsync(c->red_host, sc, sizeof(double) * 129,
+                                         hipMemcpyDeviceToHost, c->stream));
+                HX_HIP(c, hipStreamSynchronize(c->stream));
+                tm.acc();
+                for (int i = 0; i <= j; ++i) H.h(i, j) = c->red_host[i] + c->red_host[64 + i];
+                const double hn = std::sqrt(c->red_host[128]);
+                H.h(j + 1, j) = hn;
+                ++it;
+                if (!H.rotate(j)) {
+                    sw = true;
+                    break;
+                }
+                j_used = j + 1;
+                if (record(j) <= prm->rtol) break;
+                if (stalled()) {
+                    sw = true;
+                    break;
+                }
+                if (!(hn > 0.0)) break;   // happy breakdown: exact solution in the space
+                continue;
+            }
+            // delayed CGS2: V[j] holds t_j
+            HX_HIP(c, blas_mdot2(c, n, j + 1, V, n, vj, w, sc, sc + 64));
+            HX_HIP(c, blas_dcgs_step(c, n, j, V, n, w, sc));
             tm.rec(3, c->stream);
-            HX_HIP(c, hipMemcpyAsync(c->red_host, sc, sizeof(double) * 129, hipMemcpyDeviceToHost,
-                                     c->stream));
+            HX_HIP(c, hipMemcpyAsync(c->red_host, sc, sizeof(double) * (DCGS_S + 5),
+                                     hipMemcpyDeviceToHost, c->stream));
             HX_HIP(c, hipStreamSynchronize(c->stream));
             tm.acc();
-            for (int i = 0; i <= j; ++i) Hm(i, j) = c->red_host[i] + c->red_host[64 + i];
-            const double hn = std::sqrt(c->red_host[128]);
-            Hm(j + 1, j) = hn;
-            for (int i = 0; i < j; ++i) {
-                const double t = cs[i] * Hm(i, j) + sn[i] * Hm(i + 1, j);
-                Hm(i + 1, j) = -sn[i] * Hm(i, j) + cs[i] * Hm(i + 1, j);
-                Hm(i, j) = t;
-            }
-            const double den = std::hypot(Hm(j, j), Hm(j + 1, j));
-            if (!(den > 0.0) || !std::isfinite(den)) {
-                sw = true;
-                break;
-            }
-            cs[j] = Hm(j, j) / den;
-            sn[j] = Hm(j + 1, j) / den;
-            Hm(j, j) = den;
-            Hm(j + 1, j) = 0.0;
-            g[j + 1] = -sn[j] * g[j];
-            g[j] = cs[j] * g[j];
+            const double *hs = c->red_host;
+            const double rho = hs[DCGS_S + 2], hj = hs[DCGS_S + 3], flag = hs[DCGS_S + 4];
+            const double nu = std::sqrt(hs[128]);
             ++it;
-            j_used = j + 1;
-            const double est = std::fabs(g[j + 1]) / nb;
-            est_hist.push_back(est);
-            if (info->history && hist < info->history_len) info->history[hist++] = est;
-            if (est <= prm->rtol) break;
-            if (pc == HX_PC_LEARNED && prm->stall_window > 0 &&
-                (int)est_hist.size() > prm->stall_window &&
-                est > prm->stall_ratio * est_hist[est_hist.size() - 1 - prm->stall_window]) {
+            if (j > 0) {
+                // finalise column j-1 with the coefficients of t_j
+                for (int i = 0; i < j; ++i) H.h(i, j - 1) += nu_prev * hs[i];
+                H.h(j, j - 1) = flag != 0.0 ? 0.0 : nu_prev * rho;
+                if (!H.rotate(j - 1)) {
+                    sw = true;
+                    break;
+                }
+                j_used = j;
+                if (record(j - 1) <= prm->rtol) break;
+                if (stalled()) {
+                    sw = true;
+                    break;
+                }
+                if (flag != 0.0) break;   // t_j in span(V): exact solution in the space
+            } else if (flag != 0.0) {
+                sw = true;   // the residual direction itself degenerated
+                break;
+            }
+            if (!std::isfinite(nu) || !std::isfinite(hj)) {
                 sw = true;
                 break;
             }
-            if (!(hn > 0.0)) break;   // happy breakdown: exact solution in the space
+            // provisional column j
+            for (int i = 0; i < j; ++i) H.h(i, j) = hs[64 + i];
+            H.h(j, j) = hj;
+            H.h(j + 1, j) = nu;
+            nu_prev = nu;
+            const bool last = j + 1 == m || it >= prm->max_iter;
+            if (!(nu > 0.0)) {
+                // happy breakdown: the column is final as it stands
+                if (!H.rotate(j)) {
+                    sw = true;
+                    break;
+                }
+                j_used = j + 1;
+                record(j);
+                stop = true;
+                break;
+            }
+            if (last || H.peek(j) / nb <= prm->rtol) {
+                if ((s = finalise(j)) != HX_OK) return s;
+                if (!H.rotate(j)) {
+                    sw = true;
+                    break;
+                }
+                j_used = j + 1;
+                if (record(j) <= prm->rtol || last) break;
+                if (stalled()) {
+                    sw = true;
+                    break;
+                }
+                // not converged after all: the next step recomputes the same
+                // coefficients and adds them to the now-final column, so undo
+                for (int i = 0; i <= j; ++i) H.h(i, j) = i < j ? hs[64 + i] : hj;
+                H.h(j + 1, j) = nu;
+                // roll the rotation back
+                H.g[j] = H.cs[j] * H.g[j] - H.sn[j] * H.g[j + 1];
+                H.g[j + 1] = 0.0;
+                est_hist.pop_back();
+                if (info->history && hist > 0) --hist;
+                j_used = j;
+            }
         }
+        (void)stop;
         if (j_used > 0) {
             for (int i = j_used - 1; i >= 0; --i) {
-                double t = g[i];
-                for (int k = i + 1; k < j_used; ++k) t -= Hm(i, k) * y[k];
-                y[i] = t / Hm(i, i);
+                double t = H.g[i];
+                for (int k = i + 1; k < j_used; ++k) t -= H.r(i, k) * y[k];
+                y[i] = t / H.r(i, i);
             }
             HX_HIP(c, hipMemcpyAsync(sc + 130, y.data(), sizeof(double) * j_used,
                                      hipMemcpyHostToDevice, c->stream));
@@ -338,7 +498,6 @@ hx_status solve_fgmres(hx_ctx *c, const hx_solve_params *prm, const double *b, d
     }
     info->iters = it;
     info->history_len = info->history ? hist : 0;
-    (void)rtmp;
     return HX_OK;
 }
 
@@ -363,6 +522,7 @@ void hx_default_params(hx_solve_params *p)
     p->x0_mode = 0;
     p->stall_window = 10;
     p->stall_ratio = 0.99;
+    p->orth = 1;
 }
 
 hx_status hx_solve(hx_ctx *c, const hx_solve_params *prm, const double *b, double *x,
@@ -379,8 +539,9 @@ hx_status hx_solve(hx_ctx *c, const hx_solve_params *prm, const double *b, doubl
     if (!c->has_coef) return fail(c, HX_ERR_STATE, "solve before setup_mesh/set_coefficients");
     if (b == x) return fail(c, HX_ERR_ARG, "b and x alias");
     if (prm->method != 0 && prm->method != 1) return fail(c, HX_ERR_ARG, "method must be 0 or 1");
-    if (prm->method == 1 && (prm->restart < 1 || prm->restart > 64))
-        return fail(c, HX_ERR_ARG, "restart must be in 1..64");
+    if (prm->method == 1 && (prm->restart < 1 || prm->restart > 63))
+        return fail(c, HX_ERR_ARG, "restart must be in 1..63");
+    if (prm->orth != 0 && prm->orth != 1) return fail(c, HX_ERR_ARG, "orth must be 0 or 1");
     if (!(prm->rtol > 0.0) || prm->max_iter < 1) return fail(c, HX_ERR_ARG, "bad rtol/max_iter");
     if (prm->pc < HX_PC_NONE || prm->pc > HX_PC_LEARNED) return fail(c, HX_ERR_ARG, "bad pc");
     if (prm->method == 0 && (prm->pc == HX_PC_LEARNED || prm->mixed))

@@ -73,6 +73,32 @@ def test_fgmres_fp64_vs_oracle(terrain_small):
     ctx.close()
 
 
+def test_delayed_reorthogonalisation_matches_cgs2(terrain_small):
+    """FGMRES with the second Gram-Schmidt pass delayed and fused (orth=1)
+    against two plain passes per step (orth=0): both are CGS2, so the
+    residual estimates agree to rounding, the iteration counts match, and both
+    meet the true-residual bar; across a restart too (restart 7)."""
+    hx = _hx()
+    p, b, xs = terrain_small
+    ctx = gpu_context(p)
+    for restart in (7, 30):
+        out = {}
+        for orth in (0, 1):
+            x, info = ctx.solve(to_dev(b), params=hx.default_params(method=1, restart=restart,
+                                                                    rtol=1e-10, orth=orth),
+                                history=400)
+            assert info["status"] == hx.HX_OK and info["true_rel_res"] <= 1e-10, (orth, info)
+            out[orth] = (x.cpu().numpy(), info)
+        (x0, i0), (x1, i1) = out[0], out[1]
+        print(f"[solve] restart={restart}: CGS2 {i0['iters']} it, delayed {i1['iters']} it", flush=True)
+        assert abs(i0["iters"] - i1["iters"]) <= 1
+        h0, h1 = np.array(i0["history"]), np.array(i1["history"])
+        k = min(len(h0), len(h1))
+        assert np.allclose(h0[:k], h1[:k], rtol=1e-6, atol=1e-14)
+        assert np.linalg.norm(x1 - x0) <= 1e-8 * np.linalg.norm(x0)
+    ctx.close()
+
+
 def test_mixed_precision_solution_error(terrain_small):
     hx = _hx()
     p, b, xs = terrain_small
