@@ -57,6 +57,7 @@ def lib():
         L.or_load_vector.argtypes = [pp, dp, dp]
         L.or_apply.argtypes = [pp, C.c_int, dp, dp]
         L.or_assemble_dense.argtypes = [pp, C.c_int, dp]
+        L.or_cell_diagonal.argtypes = [pp, C.c_int, dp]
         L.or_apply_cells.argtypes = [pp, C.c_int, C.c_void_p, C.c_long, dp, dp]
         L.or_bj_cell_data.argtypes = [pp, C.c_long, dp, dp, dp, dp]
         L.or_bj_sep_block.argtypes = [pp, C.c_long, dp]
@@ -200,6 +201,15 @@ class Problem:
             A[:, j] = self.apply(e, flags)
             e[j] = 0.0
         return A
+
+    # the paper's diagonal preconditioners ---------------------------------
+    def cell_diagonal(self, stiff: bool = True):
+        """Diagonal of the volume part of the form (mass plus stiffness, or the
+        mass alone): the matrices whose inverses are the paper's Helmholtz and
+        internal-energy preconditioners (section 3.1)."""
+        d = np.zeros(self.n_dofs)
+        lib().or_cell_diagonal(self._s(), int(bool(stiff)), _dp(d))
+        return d
 
     # block Jacobi ----------------------------------------------------------
     def bj_cell_data(self, c: int):

@@ -521,6 +521,49 @@ static void apply_one_cell(const or_prob *p, int flags, long c, const double *xv
     free(phi); free(phiB); free(dphi); free(dphiB);
 }
 
+/* Diagonal of the volume part of the form (section 3.1: the paper's
+ * "Helmholtz preconditioner" is the inverse of the diagonal of S~, whose
+ * entries are volume integrals only; its "internal-energy" variant keeps the
+ * mass term alone):
+ *   d_i = sum_q w_q detJ_q [alpha_q phi_i^2 + beta_q |J^-T grad phi_i|^2]
+ * with the stiffness term only if `stiff` is nonzero. */
+void or_cell_diagonal(const or_prob *p, int stiff, double *diag)
+{
+    const int nd = (p->k + 1) * (p->k + 1) * (p->k + 1);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (long c = 0; c < p->n_cells; ++c) {
+        ref_t r; ref_init(&r, p->k, p->g);
+        const int n = r.n;
+        double *phi = malloc(sizeof(double) * nd);
+        double (*dphi)[3] = malloc(sizeof(double) * 3 * nd);
+        double *dc = diag + c * nd;
+        for (int a = 0; a < nd; ++a) dc[a] = 0.0;
+        const double *X = cell_nodes(p, &r, c);
+        for (int l = 0; l < n; ++l)
+            for (int j = 0; j < n; ++j)
+                for (int i = 0; i < n; ++i) {
+                    double xi[3] = {r.xq[i], r.xq[j], r.xq[l]}, x[3], J[3][3], K[3][3];
+                    geom_at(&r, X, xi, x, J);
+                    double det = det3(J);
+                    inv_transpose(J, det, K);
+                    double w = r.wq[i] * r.wq[j] * r.wq[l] * det;
+                    basis_at(&r, xi, phi, dphi);
+                    double al = field_at(phi, p->alpha + c * nd, nd);
+                    double be = field_at(phi, p->beta + c * nd, nd);
+                    for (int a = 0; a < nd; ++a) {
+                        double v = al * phi[a] * phi[a];
+                        if (stiff) {
+                            double gv[3];
+                            matvec3(K, dphi[a], gv);
+                            v += be * (gv[0] * gv[0] + gv[1] * gv[1] + gv[2] * gv[2]);
+                        }
+                        dc[a] += w * v;
+                    }
+                }
+        free(phi); free(dphi);
+    }
+}
+
 /* y = A x: each cell accumulates a(x, phi_i) for its own test functions. */
 void or_apply(const or_prob *p, int flags, const double *xv, double *yv)
 {

@@ -33,6 +33,7 @@ void or_apply(const or_prob *p, int flags, const double *x, double *y);
 void or_apply_cells(const or_prob *p, int flags, const long *cells, long m,
                     const double *x, double *out);
 void or_assemble_dense(const or_prob *p, int flags, double *A);
+void or_cell_diagonal(const or_prob *p, int stiff, double *diag);
 void or_bj_cell_data(const or_prob *p, long c, double ell[3], double *abar,
                      double *bbar, double sig[3][2]);
 void or_bj_sep_block(const or_prob *p, long c, double *Ab);
