@@ -10,8 +10,9 @@ application).  The JSON line also carries
   over the event-timed kernel duration, against the 8 TB/s HBM peak, and the
   HBM traffic measured by rocprofv3 counters (from the committed profile, null
   if the kernel source changed since);
-* ``solve``: time to a 1e-8 relative true residual for plain FP64, mixed
-  precision and (when a trained network is available) learned forms;
+* ``solve``: time to a 1e-8 relative true residual for plain FP64 (FGMRES and
+  CG with block Jacobi, CG with the paper's Helmholtz and internal-energy
+  diagonal preconditioners), mixed precision and learned forms;
 * ``cpu_baseline``: the FP64 oracle timed on the host cores on a sample of the
   same workload.
 
@@ -208,15 +209,27 @@ def main():
             ("fp64_fgmres_bj", hx.default_params(method=1, restart=30, rtol=1e-8, pc=hx.HX_PC_BLOCK_JACOBI)),
             ("mixed_fp32_inner", hx.default_params(method=1, restart=10, rtol=1e-8, mixed=1, inner_iters=12)),
         ]
+        # SPD operator: CG with block Jacobi and with the paper's Helmholtz
+        # (volume-diagonal) preconditioner
+        cg_forms = [
+            ("fp64_cg_bj", hx.default_params(method=0, rtol=1e-8, pc=hx.HX_PC_BLOCK_JACOBI)),
+            ("fp64_cg_helmholtz_diag", hx.default_params(method=0, rtol=1e-8, max_iter=20000,
+                                                         pc=hx.HX_PC_HELMHOLTZ_DIAG)),
+        ]
         del y
-        solve["terrain256x64x64"] = solve_suite(hx, ctx, b, torch, forms, "C3")
+        solve["terrain256x64x64"] = solve_suite(hx, ctx, b, torch, forms + cg_forms, "C3")
         ctx.close()
         del b, x
         torch.cuda.empty_cache()
         m2 = si.terrain_mesh(32, 8, 16, g=4)
         ctx2, xyz2, _ = setup(hx.HelmDG, m2, k, torch, dev)
         b2 = rhs_on_device(xyz2, 0, torch)
-        forms2 = forms + [("fp64_cg_bj", hx.default_params(method=0, rtol=1e-8, pc=hx.HX_PC_BLOCK_JACOBI))]
+        forms2 = forms + cg_forms + [
+            ("fp64_cg_mass_diag", hx.default_params(method=0, rtol=1e-8, max_iter=20000,
+                                                    pc=hx.HX_PC_MASS_DIAG)),
+            ("fp64_fgmres_helmholtz_diag", hx.default_params(method=1, restart=30, rtol=1e-8,
+                                                             max_iter=20000,
+                                                             pc=hx.HX_PC_HELMHOLTZ_DIAG))]
         # learned form: network trained on the periodic unit cube (Q4), then used here
         from paper_2505_00384_amd import learned
         t0 = time.time()

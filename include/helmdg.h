@@ -68,7 +68,9 @@ typedef enum { HX_F64 = 0, HX_F32 = 1 } hx_prec;
 typedef enum {
     HX_PC_NONE = 0,
     HX_PC_BLOCK_JACOBI = 1,   /* separable cell block, fast-diagonalisation inverse */
-    HX_PC_LEARNED = 2         /* block Jacobi + per-cell network correction */
+    HX_PC_LEARNED = 2,        /* block Jacobi + per-cell network correction */
+    HX_PC_HELMHOLTZ_DIAG = 3, /* inverse diagonal of the volume terms (mass + stiffness) */
+    HX_PC_MASS_DIAG = 4       /* inverse diagonal of the mass term alone */
 } hx_pc;
 
 /* Create a context on `device` (HIP ordinal) whose kernels run on
@@ -146,8 +148,13 @@ hx_status hx_residual(hx_ctx *c, const double *b, const double *x, double *r);
  * block-diagonal operators of section 3.3, with the 1-D SIP blocks in place of
  * the mass.  HX_PC_LEARNED (FP64 only; needs hx_set_network): block Jacobi
  * plus the per-cell network correction w_K net(features(r))_K, with w_K the
- * RMS of the block-Jacobi output on cell K.  HX_PC_NONE copies r.  r and z must
- * not alias. */
+ * RMS of the block-Jacobi output on cell K.  HX_PC_HELMHOLTZ_DIAG: the
+ * paper's "Helmholtz preconditioner" (section 3.1), the inverse of the
+ * diagonal of the volume terms of the form,
+ *   d_i = sum_q w_q detJ_q [alpha_q phi_i^2 + beta_q |J^-T grad phi_i|^2],
+ * face terms left out; HX_PC_MASS_DIAG: its "internal-energy" variant, the
+ * inverse of the mass diagonal alone.  Both diagonals are formed by
+ * hx_set_coefficients.  HX_PC_NONE copies r.  r and z must not alias. */
 hx_status hx_apply_preconditioner(hx_ctx *c, hx_pc kind, hx_prec prec,
                                   const void *r, void *z);
 
@@ -259,7 +266,9 @@ enum {
                                   tangential direction; points [first][second tangential] */
     HX_EXPORT_SIGMA = 2,       /* FP64 [n_cells][3]: penalty of the +d face (-1: boundary) */
     HX_EXPORT_VOLUME = 3,      /* FP64 [n_cells] */
-    HX_EXPORT_BJ_SCALARS = 4   /* FP64 [n_cells][4]: abar lx ly lz, bbar ly lz/lx, ... */
+    HX_EXPORT_BJ_SCALARS = 4,  /* FP64 [n_cells][4]: abar lx ly lz, bbar ly lz/lx, ... */
+    HX_EXPORT_INV_DIAG = 5     /* FP64 [2][n_dofs]: inverse volume diagonals, mass + stiffness
+                                  (HX_PC_HELMHOLTZ_DIAG) then mass alone (HX_PC_MASS_DIAG) */
 };
 /* Copy internal data to a HOST buffer of `bytes` bytes (for tests). */
 hx_status hx_debug_export(hx_ctx *c, int what, void *host_buf, int64_t bytes);

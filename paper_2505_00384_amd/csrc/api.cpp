@@ -44,7 +44,8 @@ static void free_mesh(hx_ctx *c)
     void **bufs[] = {(void **)&c->nodes, (void **)&c->nbr, (void **)&c->visit, (void **)&c->ref, (void **)&c->vol,
                      (void **)&c->ell, (void **)&c->mindet, (void **)&c->sigma,
                      (void **)&c->cell64, (void **)&c->cell32, (void **)&c->face64,
-                     (void **)&c->face32, (void **)&c->bjS64, (void **)&c->bjS32,
+                     (void **)&c->face32, (void **)&c->dg64, (void **)&c->dg32,
+                     (void **)&c->bjS64, (void **)&c->bjS32,
                      (void **)&c->bjL64, (void **)&c->bjL32, (void **)&c->bjC64,
                      (void **)&c->bjC32, (void **)&c->coef_feat, (void **)&c->work64,
                      (void **)&c->work32};
@@ -180,6 +181,8 @@ hx_status hx_setup_mesh(hx_ctx *c, int degree, int64_t n_cells, int geo_degree,
     ALLOC(c->cell32, sizeof(float) * nc * 7 * c->nd);
     ALLOC(c->face64, sizeof(double) * nc * 3 * 7 * c->nf);
     ALLOC(c->face32, sizeof(float) * nc * 3 * 7 * c->nf);
+    ALLOC(c->dg64, sizeof(double) * 2 * nc * c->nd);
+    ALLOC(c->dg32, sizeof(float) * 2 * nc * c->nd);
     ALLOC(c->bjS64, sizeof(double) * nc * 3 * c->nf);
     ALLOC(c->bjS32, sizeof(float) * nc * 3 * c->nf);
     ALLOC(c->bjL64, sizeof(double) * nc * 3 * c->n);
@@ -309,6 +312,13 @@ hx_status hx_apply_preconditioner(hx_ctx *c, hx_pc kind, hx_prec prec, const voi
         if (prec == HX_F64) HX_HIP(c, launch_bj64(c, (const double *)r, (double *)z));
         else HX_HIP(c, launch_bj32(c, (const float *)r, (float *)z));
         return HX_OK;
+    case HX_PC_HELMHOLTZ_DIAG:
+    case HX_PC_MASS_DIAG: {
+        const int which = kind == HX_PC_HELMHOLTZ_DIAG ? 0 : 1;
+        if (prec == HX_F64) HX_HIP(c, launch_diag64(c, which, (const double *)r, (double *)z));
+        else HX_HIP(c, launch_diag32(c, which, (const float *)r, (float *)z));
+        return HX_OK;
+    }
     case HX_PC_LEARNED: {
         if (prec != HX_F64) return fail(c, HX_ERR_ARG, "learned preconditioner is FP64-in/out");
         int nonfinite = 0;
@@ -390,9 +400,11 @@ hx_status hx_debug_export(hx_ctx *c, int what, void *host_buf, int64_t bytes)
     case HX_EXPORT_SIGMA: src = c->sigma; need = sizeof(double) * nc * 3; break;
     case HX_EXPORT_VOLUME: src = c->vol; need = sizeof(double) * nc; break;
     case HX_EXPORT_BJ_SCALARS: src = c->bjC64; need = sizeof(double) * nc * 4; break;
+    case HX_EXPORT_INV_DIAG: src = c->dg64; need = sizeof(double) * 2 * nc * c->nd; break;
     default: return fail(c, HX_ERR_ARG, "unknown export %d", what);
     }
-    if ((what == HX_EXPORT_CELL_DATA || what == HX_EXPORT_FACE_DATA || what == HX_EXPORT_BJ_SCALARS) &&
+    if ((what == HX_EXPORT_CELL_DATA || what == HX_EXPORT_FACE_DATA || what == HX_EXPORT_BJ_SCALARS ||
+         what == HX_EXPORT_INV_DIAG) &&
         !c->has_coef)
         return fail(c, HX_ERR_STATE, "no coefficients");
     if (bytes < (int64_t)need) return fail(c, HX_ERR_ARG, "buffer too small (%zu needed)", need);

@@ -185,4 +185,30 @@ hipError_t bj_dispatch(hx_ctx *c, const T *r, T *z)
 hipError_t launch_bj64(hx_ctx *c, const double *r, double *z) { return bj_dispatch<double>(c, r, z); }
 hipError_t launch_bj32(hx_ctx *c, const float *r, float *z) { return bj_dispatch<float>(c, r, z); }
 
+namespace {
+// z = D^{-1} r with a stored inverse diagonal
+template <typename T>
+__global__ void k_diag(int64_t n, const T *__restrict__ dinv, const T *__restrict__ r, T *z)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) z[i] = dinv[i] * r[i];
+}
+}  // namespace
+
+hipError_t launch_diag64(hx_ctx *c, int which, const double *r, double *z)
+{
+    const int64_t n = c->n_dofs;
+    hipLaunchKernelGGL(k_diag<double>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, n,
+                       c->dg64 + (int64_t)which * n, r, z);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag32(hx_ctx *c, int which, const float *r, float *z)
+{
+    const int64_t n = c->n_dofs;
+    hipLaunchKernelGGL(k_diag<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, n,
+                       c->dg32 + (int64_t)which * n, r, z);
+    return hipGetLastError();
+}
+
 }  // namespace hx

@@ -493,6 +493,61 @@ hipError_t launch_set_coefficients(hx_ctx *c, const double *alpha, const double 
     hipLaunchKernelGGL(k_set_face, dim3(nblk(nt, 128)), dim3(128), 0, c->stream, c->nodes,
                        c->g + 1, c->n, c->n_cells, c->nbr, c->ref, beta, c->sigma, c->face64,
                        c->face32);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_cell_diag(c);
+}
+
+// -------------------------------------------------------------------------
+// Volume diagonals from the merged cell data (block per cell, thread per
+// dof i = (a, b, l)):
+//   d_i = sum_q [ m_q phi_i(q)^2 + grad phi_i(q)^T G_q grad phi_i(q) ],
+// phi_i(q) = B(qx,a) B(qy,b) B(qz,l), reference gradient from BD.  Stored as
+// inverses: dg[0] of mass plus stiffness (the paper's Helmholtz
+// preconditioner, section 3.1), dg[1] of the mass alone (its internal-energy
+// variant).
+// -------------------------------------------------------------------------
+__global__ void k_cell_diag(int n, int64_t n_cells, const RefTab64 *__restrict__ T,
+                            const double *__restrict__ cell, double *dg64, float *dg32)
+{
+    extern __shared__ double scd[];          // [7][nd]
+    const int nd = n * n * n;
+    const int64_t c = blockIdx.x;
+    const double *cd = cell + c * 7 * nd;
+    for (int e = threadIdx.x; e < 7 * nd; e += blockDim.x) scd[e] = cd[e];
+    __syncthreads();
+    const int i = threadIdx.x;
+    if (i >= nd) return;
+    const int a = i % n, b = (i / n) % n, l = i / (n * n);
+    double dm = 0.0, ds = 0.0;
+    for (int qz = 0; qz < n; ++qz)
+        for (int qy = 0; qy < n; ++qy)
+            for (int qx = 0; qx < n; ++qx) {
+                const int q = qx + n * (qy + n * qz);
+                const double bx = T->B[qx * n + a], by = T->B[qy * n + b], bz = T->B[qz * n + l];
+                const double g0 = T->BD[qx * n + a] * by * bz, g1 = bx * T->BD[qy * n + b] * bz,
+                             g2 = bx * by * T->BD[qz * n + l];
+                const double ph = bx * by * bz;
+                const double *G = scd + q;
+                dm += G[0] * ph * ph;
+                ds += G[nd] * g0 * g0 + G[4 * nd] * g1 * g1 + G[6 * nd] * g2 * g2 +
+                      2.0 * (G[2 * nd] * g0 * g1 + G[3 * nd] * g0 * g2 + G[5 * nd] * g1 * g2);
+            }
+    const int64_t o = c * nd + i, nt = n_cells * nd;
+    const double ih = 1.0 / (dm + ds), im = 1.0 / dm;
+    dg64[o] = ih;
+    dg64[nt + o] = im;
+    dg32[o] = (float)ih;
+    dg32[nt + o] = (float)im;
+}
+
+hipError_t launch_cell_diag(hx_ctx *c)
+{
+    int threads = 64;
+    while (threads < c->nd) threads *= 2;
+    hipLaunchKernelGGL(k_cell_diag, dim3((unsigned)c->n_cells), dim3(threads),
+                       sizeof(double) * 7 * c->nd, c->stream, c->n, c->n_cells, c->ref, c->cell64,
+                       c->dg64, c->dg32);
     return hipGetLastError();
 }
 

@@ -128,6 +128,8 @@ hx_status precondition(hx_ctx *c, int pc, int mixed, int inner_iters, const doub
     case HX_PC_NONE: HX_HIP(c, blas_copy(c, c->n_dofs, v, z)); return HX_OK;
     case HX_PC_BLOCK_JACOBI: HX_HIP(c, launch_bj64(c, v, z)); return HX_OK;
     case HX_PC_LEARNED: return mlp_precondition(c, v, z, nonfinite);
+    case HX_PC_HELMHOLTZ_DIAG: HX_HIP(c, launch_diag64(c, 0, v, z)); return HX_OK;
+    case HX_PC_MASS_DIAG: HX_HIP(c, launch_diag64(c, 1, v, z)); return HX_OK;
     default: return fail(c, HX_ERR_ARG, "unknown preconditioner %d", pc);
     }
 }
@@ -543,7 +545,7 @@ hx_status hx_solve(hx_ctx *c, const hx_solve_params *prm, const double *b, doubl
         return fail(c, HX_ERR_ARG, "restart must be in 1..63");
     if (prm->orth != 0 && prm->orth != 1) return fail(c, HX_ERR_ARG, "orth must be 0 or 1");
     if (!(prm->rtol > 0.0) || prm->max_iter < 1) return fail(c, HX_ERR_ARG, "bad rtol/max_iter");
-    if (prm->pc < HX_PC_NONE || prm->pc > HX_PC_LEARNED) return fail(c, HX_ERR_ARG, "bad pc");
+    if (prm->pc < HX_PC_NONE || prm->pc > HX_PC_MASS_DIAG) return fail(c, HX_ERR_ARG, "bad pc");
     if (prm->method == 0 && (prm->pc == HX_PC_LEARNED || prm->mixed))
         return fail(c, HX_ERR_ARG, "CG needs a fixed SPD preconditioner; use FGMRES");
     if (prm->mixed && prm->inner_iters < 1) return fail(c, HX_ERR_ARG, "inner_iters must be >= 1");
