@@ -207,7 +207,7 @@ def main():
         b = x
         forms = [
             ("fp64_fgmres_bj", hx.default_params(method=1, restart=30, rtol=1e-8, pc=hx.HX_PC_BLOCK_JACOBI)),
-            ("mixed_fp32_inner", hx.default_params(method=1, restart=10, rtol=1e-8, mixed=1, inner_iters=12)),
+            ("mixed_fp32_inner", hx.default_params(method=1, restart=10, rtol=1e-8, mixed=1, inner_iters=32)),
         ]
         # SPD operator: CG with block Jacobi and with the paper's Helmholtz
         # (volume-diagonal) preconditioner

@@ -169,7 +169,7 @@ typedef struct {
     int max_iter;        /* total iteration cap */
     int pc;              /* hx_pc of the (outer) iteration */
     int mixed;           /* 1: outer FP64 FGMRES, preconditioner = inner FP32 CG */
-    int inner_iters;     /* inner FP32 CG iterations per outer step (mixed) */
+    int inner_iters;     /* inner FP32 CG iterations per outer step (mixed; 32) */
     double inner_rtol;   /* inner stopping tolerance (relative, mixed) */
     int x0_mode;         /* 0: start from zero, 1: x holds the initial guess */
     int stall_window;    /* FGMRES stall rule window (10); 0 disables it */

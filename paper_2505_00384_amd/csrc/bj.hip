@@ -9,6 +9,9 @@
 //
 // Mapping: N*N threads per cell, one per pencil; 6 sweeps of N x N 1-D
 // matrices that differ per cell (kept in LDS) plus one diagonal scaling.
+// A fused form also performs the conjugate-gradient updates of x and r
+// before the solve and sums r.z and r.r per block, so one CG step touches
+// each vector once.
 #include "common.hpp"
 
 #include <type_traits>
@@ -24,11 +27,43 @@ struct Cfg {
     static constexpr int NT = ((CPB * NF + 63) / 64) * 64;
 };
 
-template <int N, typename T>
-__global__ void __launch_bounds__(Cfg<N>::NT)
-k_bj(const T *__restrict__ r, T *__restrict__ z, const T *__restrict__ S, const T *__restrict__ L,
-     const T *__restrict__ C, int n_cells, int nwg)
+// deterministic block sum of two values (result valid in thread 0)
+template <int NT>
+__device__ __forceinline__ void block_sum2(double &u, double &v, double *sh)
 {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        u += __shfl_down(u, o, 64);
+        v += __shfl_down(v, o, 64);
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) {
+        sh[2 * wv] = u;
+        sh[2 * wv + 1] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        u = v = 0.0;
+        for (int i = 0; i < NT / 64; ++i) {
+            u += sh[2 * i];
+            v += sh[2 * i + 1];
+        }
+    }
+}
+
+// FUSE: one conjugate-gradient step around the preconditioner, with the
+// step length a = sc[0] / sc[1] (r.z over p.q) read from device memory:
+//   x += a p,  r -= a q,  z = M^{-1} r,
+// and per-block partial sums of r.z and r.r written to part[blk] and
+// part[ld + blk].  Without FUSE, plain z = M^{-1} r.
+template <int N, typename T, bool FUSE>
+__global__ void __launch_bounds__(Cfg<N>::NT)
+k_bj(const T *__restrict__ rin, T *__restrict__ z, const T *__restrict__ S, const T *__restrict__ L,
+     const T *__restrict__ C, int n_cells, int nwg, T *x, T *rw, const T *__restrict__ p,
+     const T *__restrict__ q, const double *__restrict__ sc, double *part, int ld)
+{
+    const T *r = FUSE ? rw : rin;
     constexpr int NF = Cfg<N>::NF, ND = Cfg<N>::ND, CPB = Cfg<N>::CPB;
     __shared__ T sR[CPB][ND];
     __shared__ T sS[CPB][3][NF];
@@ -47,18 +82,32 @@ k_bj(const T *__restrict__ r, T *__restrict__ z, const T *__restrict__ S, const 
     const int64_t cid = (int64_t)wg * CPB + lc;
     const bool active = slot && cid < n_cells;
 
-    if (active) {
+    double acc_rr = 0.0, acc_rz = 0.0;
+    if (FUSE && active) {
+        const T al = (T)(sc[0] / sc[1]);
+        for (int e = tt; e < ND; e += NF) {
+            const int64_t gi = cid * ND + e;
+            const T rv = rw[gi] - al * q[gi];
+            x[gi] += al * p[gi];
+            rw[gi] = rv;
+            sR[lc][e] = rv;
+            acc_rr += (double)rv * (double)rv;
+        }
+    } else if (active) {
         for (int e = tt; e < ND; e += NF) sR[lc][e] = r[cid * ND + e];
+    }
+    if (active) {
         for (int e = tt; e < 3 * NF; e += NF) sS[lc][e / NF][e % NF] = S[cid * 3 * NF + e];
         for (int e = tt; e < 3 * N; e += NF) sL[lc][e / N][e % N] = L[cid * 3 * N + e];
         for (int e = tt; e < 4; e += NF) sC[lc][e] = C[cid * 4 + e];
     }
     __syncthreads();
-    T v[N], w[N];
-    // S_x^T along x: thread (j=a, l=b)
+    T v[N], w[N], rp[N];
+    // S_x^T along x: thread (j=a, l=b); rp keeps the residual pencil, whose
+    // positions are those of the output pencil written at the end
     if (active) {
 #pragma unroll
-        for (int i = 0; i < N; ++i) v[i] = sR[lc][i + N * a + NF * b];
+        for (int i = 0; i < N; ++i) v[i] = rp[i] = sR[lc][i + N * a + NF * b];
 #pragma unroll
         for (int m = 0; m < N; ++m) {
             T s = 0;
@@ -147,12 +196,29 @@ k_bj(const T *__restrict__ r, T *__restrict__ z, const T *__restrict__ S, const 
 #pragma unroll
             for (int m = 0; m < N; ++m) s += sS[lc][0][i * N + m] * v[m];
             z[o + i] = s;
+            acc_rz += (double)rp[i] * (double)s;
+        }
+    }
+    if (FUSE) {
+        __shared__ double sh2[2 * (Cfg<N>::NT / 64)];
+        block_sum2<Cfg<N>::NT>(acc_rz, acc_rr, sh2);
+        if (threadIdx.x == 0) {
+            part[bid] = acc_rz;
+            part[ld + bid] = acc_rr;
         }
     }
 }
 
+// CG step arguments of the fused form (null for a plain application)
+template <typename T>
+struct CgArgs {
+    T *x = nullptr, *r = nullptr;
+    const T *p = nullptr, *q = nullptr;
+    const double *sc = nullptr;
+};
+
 template <int N, typename T>
-hipError_t bj_n(hx_ctx *c, const T *r, T *z)
+hipError_t bj_n(hx_ctx *c, const T *r, T *z, const CgArgs<T> *cg, int *nblk)
 {
     const int cpb = Cfg<N>::CPB;
     const int nwg = (int)((c->n_cells + cpb - 1) / cpb);
@@ -160,22 +226,31 @@ hipError_t bj_n(hx_ctx *c, const T *r, T *z)
     const T *S = dbl ? (const T *)c->bjS64 : (const T *)c->bjS32;
     const T *L = dbl ? (const T *)c->bjL64 : (const T *)c->bjL32;
     const T *C = dbl ? (const T *)c->bjC64 : (const T *)c->bjC32;
-    hipLaunchKernelGGL((k_bj<N, T>), dim3(nwg), dim3(Cfg<N>::NT), 0, c->stream, r, z, S, L, C,
-                       (int)c->n_cells, nwg);
+    if (nblk) *nblk = nwg;
+    if (cg)
+        hipLaunchKernelGGL((k_bj<N, T, true>), dim3(nwg), dim3(Cfg<N>::NT), 0, c->stream, r, z, S,
+                           L, C, (int)c->n_cells, nwg, cg->x, cg->r, cg->p, cg->q, cg->sc,
+                           c->cgpart, (int)c->n_cells + 1);
+    else
+        hipLaunchKernelGGL((k_bj<N, T, false>), dim3(nwg), dim3(Cfg<N>::NT), 0, c->stream, r, z, S,
+                           L, C, (int)c->n_cells, nwg, (T *)nullptr, (T *)nullptr,
+                           (const T *)nullptr, (const T *)nullptr, (const double *)nullptr,
+                           (double *)nullptr, 0);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t bj_dispatch(hx_ctx *c, const T *r, T *z)
+hipError_t bj_dispatch(hx_ctx *c, const T *r, T *z, const CgArgs<T> *cg = nullptr,
+                       int *nblk = nullptr)
 {
     switch (c->n) {
-    case 2: return bj_n<2, T>(c, r, z);
-    case 3: return bj_n<3, T>(c, r, z);
-    case 4: return bj_n<4, T>(c, r, z);
-    case 5: return bj_n<5, T>(c, r, z);
-    case 6: return bj_n<6, T>(c, r, z);
-    case 7: return bj_n<7, T>(c, r, z);
-    case 8: return bj_n<8, T>(c, r, z);
+    case 2: return bj_n<2, T>(c, r, z, cg, nblk);
+    case 3: return bj_n<3, T>(c, r, z, cg, nblk);
+    case 4: return bj_n<4, T>(c, r, z, cg, nblk);
+    case 5: return bj_n<5, T>(c, r, z, cg, nblk);
+    case 6: return bj_n<6, T>(c, r, z, cg, nblk);
+    case 7: return bj_n<7, T>(c, r, z, cg, nblk);
+    case 8: return bj_n<8, T>(c, r, z, cg, nblk);
     default: return hipErrorInvalidValue;
     }
 }
@@ -184,6 +259,22 @@ hipError_t bj_dispatch(hx_ctx *c, const T *r, T *z)
 
 hipError_t launch_bj64(hx_ctx *c, const double *r, double *z) { return bj_dispatch<double>(c, r, z); }
 hipError_t launch_bj32(hx_ctx *c, const float *r, float *z) { return bj_dispatch<float>(c, r, z); }
+
+hipError_t launch_cg_bj64(hx_ctx *c, double *x, double *r, const double *p, const double *q,
+                          double *z, const double *sc, int *nblk)
+{
+    CgArgs<double> a;
+    a.x = x; a.r = r; a.p = p; a.q = q; a.sc = sc;
+    return bj_dispatch<double>(c, r, z, &a, nblk);
+}
+
+hipError_t launch_cg_bj32(hx_ctx *c, float *x, float *r, const float *p, const float *q, float *z,
+                          const double *sc, int *nblk)
+{
+    CgArgs<float> a;
+    a.x = x; a.r = r; a.p = p; a.q = q; a.sc = sc;
+    return bj_dispatch<float>(c, r, z, &a, nblk);
+}
 
 namespace {
 // z = D^{-1} r with a stored inverse diagonal

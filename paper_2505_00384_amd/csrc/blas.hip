@@ -285,6 +285,47 @@ __global__ void k_shift(double *sc)
     if (threadIdx.x == 0 && blockIdx.x == 0) sc[0] = sc[2];
 }
 
+// ---- fused CG steps, FP64 or FP32 vectors, scalars on the device:
+// sc[0] = r.z (current), sc[1] = p.q, sc[2] = new r.z, sc[3] = new r.r.
+// x += a p, r -= a q with a = sc[0] / sc[1], z = dinv r (or z = r), and the
+// per-block partial sums of r.z and r.r in part[blk], part[ld + blk].
+template <typename T>
+__global__ void __launch_bounds__(RT) k_cg_elem(int64_t n, T *x, T *r, const T *__restrict__ p,
+                                                const T *__restrict__ q, T *z,
+                                                const T *__restrict__ dinv,
+                                                const double *__restrict__ sc, double *part, int ld)
+{
+    __shared__ double sh[RT / 64];
+    const T al = (T)(sc[0] / sc[1]);
+    double rz = 0.0, rr = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * RT;
+    for (int64_t i = blockIdx.x * (int64_t)RT + threadIdx.x; i < n; i += stride) {
+        const T rv = r[i] - al * q[i];
+        x[i] += al * p[i];
+        r[i] = rv;
+        const T zv = dinv ? dinv[i] * rv : rv;
+        z[i] = zv;
+        rz += (double)rv * (double)zv;
+        rr += (double)rv * (double)rv;
+    }
+    rz = block_sum(rz, sh);
+    rr = block_sum(rr, sh);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = rz;
+        part[ld + blockIdx.x] = rr;
+    }
+}
+
+// p = z + (sc[2] / sc[0]) p
+template <typename T>
+__global__ void k_cg_pt(int64_t n, const T *__restrict__ z, T *p, const double *__restrict__ sc)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const T bt = (T)(sc[2] / sc[0]);
+    p[i] = z[i] + bt * p[i];
+}
+
 inline unsigned nb256(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
@@ -421,5 +462,64 @@ hipError_t cg32_step_p(hx_ctx *c, int64_t n, const float *z, float *p, double *s
 }
 
 int red_stage1_max() { return RED_MAX; }
+
+// One fused CG step around the preconditioner pc (none, block Jacobi or a
+// diagonal kind): x += a p, r -= a q, z = M^{-1} r, sc[2] = r.z, sc[3] = r.r.
+template <typename T>
+hipError_t cg_step_pc(hx_ctx *c, int pc, T *x, T *r, const T *p, const T *q, T *z, double *sc)
+{
+    const int64_t n = c->n_dofs;
+    const int ld = (int)c->n_cells + 1;
+    const bool dbl = sizeof(T) == 8;
+    int nb = 0;
+    hipError_t e;
+    if (pc == HX_PC_BLOCK_JACOBI) {
+        e = dbl ? launch_cg_bj64(c, (double *)x, (double *)r, (const double *)p, (const double *)q,
+                                 (double *)z, sc, &nb)
+                : launch_cg_bj32(c, (float *)x, (float *)r, (const float *)p, (const float *)q,
+                                 (float *)z, sc, &nb);
+    } else {
+        const T *dinv = nullptr;
+        if (pc == HX_PC_HELMHOLTZ_DIAG || pc == HX_PC_MASS_DIAG) {
+            const int w = pc == HX_PC_HELMHOLTZ_DIAG ? 0 : 1;
+            dinv = dbl ? (const T *)(c->dg64 + (int64_t)w * n) : (const T *)(c->dg32 + (int64_t)w * n);
+        }
+        nb = red_blocks(n);
+        hipLaunchKernelGGL(k_cg_elem<T>, dim3(nb), dim3(RT), 0, c->stream, n, x, r, p, q, z, dinv,
+                           sc, c->cgpart, ld);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_red2, dim3(2), dim3(RT), 0, c->stream, c->cgpart, nb, ld, sc + 2);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t cg_step_p(hx_ctx *c, const T *z, T *p, double *sc)
+{
+    const int64_t n = c->n_dofs;
+    hipLaunchKernelGGL(k_cg_pt<T>, dim3(nb256(n)), dim3(256), 0, c->stream, n, z, p, sc);
+    hipLaunchKernelGGL(k_shift, dim3(1), dim3(64), 0, c->stream, sc);
+    return hipGetLastError();
+}
+
+hipError_t cg_step_pc64(hx_ctx *c, int pc, double *x, double *r, const double *p, const double *q,
+                        double *z, double *sc)
+{
+    return cg_step_pc<double>(c, pc, x, r, p, q, z, sc);
+}
+hipError_t cg_step_pc32(hx_ctx *c, int pc, float *x, float *r, const float *p, const float *q,
+                        float *z, double *sc)
+{
+    return cg_step_pc<float>(c, pc, x, r, p, q, z, sc);
+}
+hipError_t cg_step_p64(hx_ctx *c, const double *z, double *p, double *sc)
+{
+    return cg_step_p<double>(c, z, p, sc);
+}
+hipError_t cg_step_p32(hx_ctx *c, const float *z, float *p, double *sc)
+{
+    return cg_step_p<float>(c, z, p, sc);
+}
 
 }  // namespace hx

@@ -74,6 +74,7 @@ struct hx_ctx {
     float *face32 = nullptr;
     double *dg64 = nullptr;       // [2][n_dofs] inverse volume diagonals: mass + stiffness, mass
     float *dg32 = nullptr;
+    double *cgpart = nullptr;     // [2][n_cells + 1] per-block partial sums of the fused CG steps
 
     // separable block-Jacobi data
     double *bjS64 = nullptr;      // [n_cells][3][n][n]  eigenvectors S_d
@@ -159,6 +160,17 @@ hipError_t cg32_init(hx_ctx *c, int64_t n, float *r, float *z, float *p, double 
 hipError_t cg32_step_x(hx_ctx *c, int64_t n, float *x, float *r, const float *p,
                        const float *q, double *sc);
 hipError_t cg32_step_p(hx_ctx *c, int64_t n, const float *z, float *p, double *sc);
+// fused CG steps (scalars in sc[0..3], see blas.hip)
+hipError_t launch_cg_bj64(hx_ctx *c, double *x, double *r, const double *p, const double *q,
+                          double *z, const double *sc, int *nblk);
+hipError_t launch_cg_bj32(hx_ctx *c, float *x, float *r, const float *p, const float *q, float *z,
+                          const double *sc, int *nblk);
+hipError_t cg_step_pc64(hx_ctx *c, int pc, double *x, double *r, const double *p, const double *q,
+                        double *z, double *sc);
+hipError_t cg_step_pc32(hx_ctx *c, int pc, float *x, float *r, const float *p, const float *q,
+                        float *z, double *sc);
+hipError_t cg_step_p64(hx_ctx *c, const double *z, double *p, double *sc);
+hipError_t cg_step_p32(hx_ctx *c, const float *z, float *p, double *sc);
 hipError_t cg32_step_p_dot(hx_ctx *c, int64_t n, const float *r, const float *z, double *sc);
 hipError_t blas_lincomb(hx_ctx *c, int64_t n, int m, const double *Z, int64_t ldz,
                         const double *y_dev, double *x);

@@ -191,11 +191,12 @@ struct Cfg {
     static_assert(NF <= 64 && 6 * N <= 64, "one wave per cell at most");
 };
 
-// waves per SIMD the register budget is sized for (measured: a larger
-// budget beats the occupancy the LDS use would allow)
+// waves per SIMD the register budget is sized for (measured at N = 5 FP64:
+// 2 waves with 160 registers is as fast as 3 and much faster than 4, which
+// spills; the memory pipeline, not occupancy, sets the pace)
 template <int N, typename T>
 struct Occ {
-    static constexpr int W = sizeof(T) == 8 ? (N <= 3 ? 4 : (N <= 5 ? 3 : 2))
+    static constexpr int W = sizeof(T) == 8 ? (N <= 3 ? 4 : (N <= 4 ? 3 : 2))
                                             : (N <= 4 ? 4 : (N <= 6 ? 3 : 2));
     // request the quadrature-point data before the y sweep (register cost 7 N)
     static constexpr bool PREFETCH_CELL = N <= 5;

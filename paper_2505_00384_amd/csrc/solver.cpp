@@ -63,8 +63,8 @@ struct Timer {
         op += span(1, 2);
         orth += span(2, 3);
     }
-    // CG order ev1 < ev2 < ev0 < ev3: op = ev1..2, vector updates = ev2..0,
-    // pc = ev0..3
+    // CG order ev1 < ev2 < ev0 < ev3: op = ev1..2, p.q = ev2..0, fused
+    // updates and preconditioner = ev0..3
     void acc_cg()
     {
         if (!ok) return;
@@ -94,12 +94,13 @@ hx_status ensure_work(hx_ctx *c, size_t n64, size_t n32)
 }
 
 // inner FP32 PCG for `iters` iterations on A32 z = v (FP64 in/out); scalars
-// on the device.  w32: 5 float vectors.
+// on the device, each step fused around the FP32 block Jacobi (one pass over
+// x, r, p, q and z).  w32: 5 float vectors.
 hx_status inner_fp32(hx_ctx *c, const double *v, double *z, float *w32, int iters, int *count)
 {
     const int64_t n = c->n_dofs;
     float *x = w32, *r = w32 + n, *zz = w32 + 2 * n, *p = w32 + 3 * n, *q = w32 + 4 * n;
-    double *sc = c->red + SC_OFF + 512;   // [0] rz, [1] pq, [2] rz_new
+    double *sc = c->red + SC_OFF + 512;   // [0] rz, [1] pq, [2] rz_new, [3] rr
     HX_HIP(c, blas_cast64to32(c, n, v, r, nullptr));
     HX_HIP(c, blas_fill32(c, n, 0.0f, x));
     HX_HIP(c, launch_bj32(c, r, zz));
@@ -108,11 +109,12 @@ hx_status inner_fp32(hx_ctx *c, const double *v, double *z, float *w32, int iter
     for (int it = 0; it < iters; ++it) {
         HX_HIP(c, launch_apply32(c, p, q, nullptr));
         HX_HIP(c, blas_dot32(c, n, p, q, sc + 1));
-        HX_HIP(c, cg32_step_x(c, n, x, r, p, q, sc));
-        if (it + 1 == iters) break;
-        HX_HIP(c, launch_bj32(c, r, zz));
-        HX_HIP(c, blas_dot32(c, n, r, zz, sc + 2));
-        HX_HIP(c, cg32_step_p(c, n, zz, p, sc));
+        if (it + 1 == iters) {
+            HX_HIP(c, cg32_step_x(c, n, x, r, p, q, sc));
+            break;
+        }
+        HX_HIP(c, cg_step_pc32(c, HX_PC_BLOCK_JACOBI, x, r, p, q, zz, sc));
+        HX_HIP(c, cg_step_p32(c, zz, p, sc));
     }
     HX_HIP(c, blas_cast32to64(c, n, x, z, nullptr));
     *count += iters;
@@ -149,6 +151,11 @@ hx_status read_scalars(hx_ctx *c, const double *dev, int m, double *host)
 }
 
 // ------------------------------------------------------------------- CG
+// Preconditioned CG with its scalars on the device: per step one operator
+// application, one dot product p.q, one fused kernel (x and r updates,
+// preconditioner, r.z and r.r) and the update of p.  The host reads |r|^2
+// of step k while step k+1 runs, so the stream never waits for the host; the
+// solve stops one step after the test first passes.
 hx_status solve_cg(hx_ctx *c, const hx_solve_params *prm, const double *b, double *x,
                    hx_solve_info *info, Timer &tm)
 {
@@ -156,17 +163,17 @@ hx_status solve_cg(hx_ctx *c, const hx_solve_params *prm, const double *b, doubl
     hx_status s = ensure_work(c, 4 * (size_t)n, 0);
     if (s != HX_OK) return s;
     double *r = c->work64, *z = r + n, *p = z + n, *q = p + n;
-    double *sc = c->red + SC_OFF;
-    double h[4];
-    HX_HIP(c, blas_dot(c, n, b, b, sc + 3));
+    double *sc = c->red + SC_OFF;          // [0] rz, [1] pq, [2] rz_new, [3] rr, [4] bb
+    double h[2];
+    HX_HIP(c, blas_dot(c, n, b, b, sc + 4));
     if (prm->x0_mode == 1) {
         HX_HIP(c, launch_apply64(c, x, r, b));
     } else {
         HX_HIP(c, blas_fill(c, n, 0.0, x));
         HX_HIP(c, blas_copy(c, n, b, r));
     }
-    HX_HIP(c, blas_dot(c, n, r, r, sc + 2));
-    if ((s = read_scalars(c, sc + 2, 2, h)) != HX_OK) return s;
+    HX_HIP(c, blas_dot(c, n, r, r, sc + 3));
+    if ((s = read_scalars(c, sc + 3, 2, h)) != HX_OK) return s;
     const double nb = std::sqrt(h[1]);
     double rel = nb > 0 ? std::sqrt(h[0]) / nb : 0.0;
     if (nb == 0.0) {
@@ -178,34 +185,65 @@ hx_status solve_cg(hx_ctx *c, const hx_solve_params *prm, const double *b, doubl
     if ((s = precondition(c, prm->pc, 0, 0, r, z, nullptr, &dummy, &nonfinite)) != HX_OK) return s;
     HX_HIP(c, blas_copy(c, n, z, p));
     HX_HIP(c, blas_dot(c, n, r, z, sc + 0));
-    if ((s = read_scalars(c, sc, 1, h)) != HX_OK) return s;
-    double rz = h[0];
-    int it = 0;
-    while (rel > prm->rtol && it < prm->max_iter) {
-        tm.rec(1, c->stream);
-        HX_HIP(c, launch_apply64(c, p, q, nullptr));
-        tm.rec(2, c->stream);
-        HX_HIP(c, blas_dot(c, n, p, q, sc + 1));
-        if ((s = read_scalars(c, sc + 1, 1, h)) != HX_OK) return s;
-        const double alpha = rz / h[0];
-        HX_HIP(c, blas_axpby(c, n, alpha, p, 1.0, x));
-        HX_HIP(c, blas_axpby(c, n, -alpha, q, 1.0, r));
-        HX_HIP(c, blas_dot(c, n, r, r, sc + 2));
-        tm.rec(0, c->stream);
-        if ((s = precondition(c, prm->pc, 0, 0, r, z, nullptr, &dummy, &nonfinite)) != HX_OK) return s;
-        tm.rec(3, c->stream);
-        HX_HIP(c, blas_dot(c, n, r, z, sc + 0));
-        double hh[3];
-        if ((s = read_scalars(c, sc, 3, hh)) != HX_OK) return s;
-        tm.acc_cg();
-        ++it;
-        rel = std::sqrt(hh[2]) / nb;
-        if (info->history && it - 1 < info->history_len) info->history[it - 1] = rel;
-        if (!std::isfinite(rel)) break;
-        const double rz_new = hh[0];
-        HX_HIP(c, blas_axpby(c, n, 1.0, z, rz_new / rz, p));
-        rz = rz_new;
+    if (rel <= prm->rtol || prm->max_iter < 1) {
+        info->iters = 0;
+        info->history_len = 0;
+        return HX_OK;
     }
+    // two steps in flight: slot k % 2 of the pinned buffer, events and timers
+    hipEvent_t done[2] = {nullptr, nullptr};
+    for (auto &e : done)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+            return fail(c, HX_ERR_DEVICE, "hipEventCreate failed");
+    Timer tb(true);
+    Timer *tms[2] = {&tm, &tb};
+    double *hr = c->red_host + 1000;
+    auto cleanup = [&]() {
+        for (auto &e : done)
+            if (e) (void)hipEventDestroy(e);
+    };
+    int it = 0, checked = 0;
+    bool stop = false;
+    hx_status err = HX_OK;
+    // rel of step k, once its copy has landed
+    auto check = [&](int k) -> bool {
+        if (hipEventSynchronize(done[k % 2]) != hipSuccess) {
+            err = fail(c, HX_ERR_DEVICE, "CG: event wait failed");
+            return true;
+        }
+        tms[k % 2]->acc_cg();
+        const double rk = std::sqrt(hr[k % 2]) / nb;
+        if (info->history && k < info->history_len) info->history[k] = rk;
+        checked = k + 1;
+        return !(rk > prm->rtol) || !std::isfinite(rk);
+    };
+    while (it < prm->max_iter && !stop) {
+        Timer &t = *tms[it % 2];
+        t.rec(1, c->stream);
+        if (hipSuccess != launch_apply64(c, p, q, nullptr)) { err = fail(c, HX_ERR_DEVICE, "CG: apply"); break; }
+        t.rec(2, c->stream);
+        if (hipSuccess != blas_dot(c, n, p, q, sc + 1)) { err = fail(c, HX_ERR_DEVICE, "CG: dot"); break; }
+        t.rec(0, c->stream);
+        if (hipSuccess != cg_step_pc64(c, prm->pc, x, r, p, q, z, sc)) { err = fail(c, HX_ERR_DEVICE, "CG: step"); break; }
+        t.rec(3, c->stream);
+        if (hipSuccess != cg_step_p64(c, z, p, sc)) { err = fail(c, HX_ERR_DEVICE, "CG: p update"); break; }
+        if (hipSuccess != hipMemcpyAsync(hr + it % 2, sc + 3, sizeof(double), hipMemcpyDeviceToHost,
+                                         c->stream) ||
+            hipSuccess != hipEventRecord(done[it % 2], c->stream)) {
+            err = fail(c, HX_ERR_DEVICE, "CG: copy");
+            break;
+        }
+        ++it;
+        // test the previous step while this one runs
+        if (it >= 2 && check(it - 2)) stop = true;
+    }
+    // the steps still in flight
+    while (err == HX_OK && checked < it) check(checked);
+    cleanup();
+    tm.op += tb.op;
+    tm.pc += tb.pc;
+    tm.orth += tb.orth;
+    if (err != HX_OK) return err;
     info->iters = it;
     info->history_len = info->history ? (it < info->history_len ? it : info->history_len) : 0;
     return HX_OK;
@@ -519,7 +557,7 @@ void hx_default_params(hx_solve_params *p)
     p->max_iter = 10000;
     p->pc = HX_PC_BLOCK_JACOBI;
     p->mixed = 0;
-    p->inner_iters = 12;
+    p->inner_iters = 32;
     p->inner_rtol = 1e-2;
     p->x0_mode = 0;
     p->stall_window = 10;
