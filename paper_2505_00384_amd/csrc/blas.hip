@@ -463,6 +463,31 @@ hipError_t cg32_step_p(hx_ctx *c, int64_t n, const float *z, float *p, double *s
 
 int red_stage1_max() { return RED_MAX; }
 
+namespace {
+// out[blk] = sum of part[blk*chunk .. min(n, (blk+1)*chunk))
+__global__ void __launch_bounds__(RT) k_chunk_sum(const double *__restrict__ part, int64_t n,
+                                                  int64_t chunk, double *out)
+{
+    __shared__ double sh[RT / 64];
+    const int64_t lo = blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
+    double s = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += RT) s += part[i];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+}  // namespace
+
+hipError_t reduce_parts(hx_ctx *c, const double *part, int64_t n, double *dst)
+{
+    const int64_t chunk = 4096;
+    int64_t nb = (n + chunk - 1) / chunk;
+    if (nb < 1) nb = 1;
+    if (nb > RED_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_chunk_sum, dim3((unsigned)nb), dim3(RT), 0, c->stream, part, n, chunk, c->red);
+    hipLaunchKernelGGL(k_red2, dim3(1), dim3(RT), 0, c->stream, c->red, (int)nb, RED_MAX, dst);
+    return hipGetLastError();
+}
+
 // One fused CG step around the preconditioner pc (none, block Jacobi or a
 // diagonal kind): x += a p, r -= a q, z = M^{-1} r, sc[2] = r.z, sc[3] = r.r.
 template <typename T>

@@ -129,6 +129,11 @@ hipError_t launch_diag32(hx_ctx *c, int which, const float *r, float *z);
 // operator: y = A x, or y = b - A x when b != nullptr
 hipError_t launch_apply64(hx_ctx *c, const double *x, double *y, const double *b);
 hipError_t launch_apply32(hx_ctx *c, const float *x, float *y, const float *b);
+// y = A x and dst = x.(A x) in FP64 (CG's p.q), summed in a fixed order
+hipError_t launch_apply64_dot(hx_ctx *c, const double *x, double *y, double *dst);
+hipError_t launch_apply32_dot(hx_ctx *c, const float *x, float *y, double *dst);
+// dst = sum of part[0..n) in a fixed order (two stages)
+hipError_t reduce_parts(hx_ctx *c, const double *part, int64_t n, double *dst);
 
 // separable block Jacobi: z = Ahat^{-1} r
 hipError_t launch_bj64(hx_ctx *c, const double *r, double *z);

@@ -208,11 +208,11 @@ __device__ __forceinline__ T ld_stream(const T *p)
     return __builtin_nontemporal_load(p);
 }
 
-template <int N, typename T>
+template <int N, typename T, bool DOT>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(Occ<N, T>::W, Occ<N, T>::W)))
 k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
         const T *__restrict__ cell, const T *__restrict__ face, const int32_t *__restrict__ visit,
-        int n_cells, int nwg)
+        int n_cells, int nwg, double *__restrict__ dpart)
 {
     constexpr int NF = Cfg<N>::NF, ND = Cfg<N>::ND, LPC = Cfg<N>::LPC, CPW = Cfg<N>::CPW,
                   GS = Cfg<N>::GS;
@@ -295,11 +295,16 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
 
     T Y[N];
     // =========================================================== cell part
-    // x sweep: lane (j=a, l=b): B u and BD u along x
+    // x sweep: lane (j=a, l=b): B u and BD u along x; the lane's own input
+    // pencil is kept when the caller wants x.(A x)
+    T xp[N];
     if (cl) {
         T r[N], s0[N], s1[N];
 #pragma unroll
-        for (int i = 0; i < N; ++i) r[i] = U[i + N * a + NF * b];
+        for (int i = 0; i < N; ++i) {
+            r[i] = U[i + N * a + NF * b];
+            if (DOT) xp[i] = r[i];
+        }
         const EvenOdd<T, N> xr(r);
         contract<T, N, 0, false>(xr, s0);
         contract<T, N, 1, false>(xr, s1);
@@ -637,31 +642,48 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
 #pragma unroll
         for (int i = 0; i < N; ++i) y[o + i] = bvec ? bvec[o + i] - Y[i] : Y[i];
     }
+    // x.(A x) of the wave's cells (fixed-order wave sum), for CG's p.q
+    if (DOT) {
+        double acc = 0.0;
+        if (cl) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) acc += (double)xp[i] * (double)Y[i];
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+        if (lane == 0) dpart[bid] = acc;
+    }
 }
 
 template <int N, typename T>
-hipError_t apply_n(hx_ctx *c, const T *x, T *y, const T *b)
+hipError_t apply_n(hx_ctx *c, const T *x, T *y, const T *b, double *dpart, int *nwg_out)
 {
     const int cpw = Cfg<N>::CPW;
     const int nwg = (int)((c->n_cells + cpw - 1) / cpw);
     const T *cell = std::is_same<T, double>::value ? (const T *)c->cell64 : (const T *)c->cell32;
     const T *face = std::is_same<T, double>::value ? (const T *)c->face64 : (const T *)c->face32;
-    hipLaunchKernelGGL((k_apply<N, T>), dim3(nwg), dim3(64), 0, c->stream, x, y, b, cell, face,
-                       c->visit, (int)c->n_cells, nwg);
+    if (nwg_out) *nwg_out = nwg;
+    if (dpart)
+        hipLaunchKernelGGL((k_apply<N, T, true>), dim3(nwg), dim3(64), 0, c->stream, x, y, b, cell,
+                           face, c->visit, (int)c->n_cells, nwg, dpart);
+    else
+        hipLaunchKernelGGL((k_apply<N, T, false>), dim3(nwg), dim3(64), 0, c->stream, x, y, b, cell,
+                           face, c->visit, (int)c->n_cells, nwg, dpart);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t apply_dispatch(hx_ctx *c, const T *x, T *y, const T *b)
+hipError_t apply_dispatch(hx_ctx *c, const T *x, T *y, const T *b, double *dpart = nullptr,
+                          int *nwg = nullptr)
 {
     switch (c->n) {
-    case 2: return apply_n<2, T>(c, x, y, b);
-    case 3: return apply_n<3, T>(c, x, y, b);
-    case 4: return apply_n<4, T>(c, x, y, b);
-    case 5: return apply_n<5, T>(c, x, y, b);
-    case 6: return apply_n<6, T>(c, x, y, b);
-    case 7: return apply_n<7, T>(c, x, y, b);
-    case 8: return apply_n<8, T>(c, x, y, b);
+    case 2: return apply_n<2, T>(c, x, y, b, dpart, nwg);
+    case 3: return apply_n<3, T>(c, x, y, b, dpart, nwg);
+    case 4: return apply_n<4, T>(c, x, y, b, dpart, nwg);
+    case 5: return apply_n<5, T>(c, x, y, b, dpart, nwg);
+    case 6: return apply_n<6, T>(c, x, y, b, dpart, nwg);
+    case 7: return apply_n<7, T>(c, x, y, b, dpart, nwg);
+    case 8: return apply_n<8, T>(c, x, y, b, dpart, nwg);
     default: return hipErrorInvalidValue;
     }
 }
@@ -676,6 +698,21 @@ hipError_t launch_apply64(hx_ctx *c, const double *x, double *y, const double *b
 hipError_t launch_apply32(hx_ctx *c, const float *x, float *y, const float *b)
 {
     return apply_dispatch<float>(c, x, y, b);
+}
+
+// y = A x and dst = x.y (summed in a fixed order)
+hipError_t launch_apply64_dot(hx_ctx *c, const double *x, double *y, double *dst)
+{
+    int nwg = 0;
+    hipError_t e = apply_dispatch<double>(c, x, y, nullptr, c->cgpart, &nwg);
+    return e != hipSuccess ? e : reduce_parts(c, c->cgpart, nwg, dst);
+}
+
+hipError_t launch_apply32_dot(hx_ctx *c, const float *x, float *y, double *dst)
+{
+    int nwg = 0;
+    hipError_t e = apply_dispatch<float>(c, x, y, nullptr, c->cgpart, &nwg);
+    return e != hipSuccess ? e : reduce_parts(c, c->cgpart, nwg, dst);
 }
 
 }  // namespace hx

@@ -107,8 +107,7 @@ hx_status inner_fp32(hx_ctx *c, const double *v, double *z, float *w32, int iter
     HX_HIP(c, hipMemcpyAsync(p, zz, sizeof(float) * n, hipMemcpyDeviceToDevice, c->stream));
     HX_HIP(c, blas_dot32(c, n, r, zz, sc + 0));
     for (int it = 0; it < iters; ++it) {
-        HX_HIP(c, launch_apply32(c, p, q, nullptr));
-        HX_HIP(c, blas_dot32(c, n, p, q, sc + 1));
+        HX_HIP(c, launch_apply32_dot(c, p, q, sc + 1));
         if (it + 1 == iters) {
             HX_HIP(c, cg32_step_x(c, n, x, r, p, q, sc));
             break;
@@ -152,7 +151,7 @@ hx_status read_scalars(hx_ctx *c, const double *dev, int m, double *host)
 
 // ------------------------------------------------------------------- CG
 // Preconditioned CG with its scalars on the device: per step one operator
-// application, one dot product p.q, one fused kernel (x and r updates,
+// application that also sums p.q, one fused kernel (x and r updates,
 // preconditioner, r.z and r.r) and the update of p.  The host reads |r|^2
 // of step k while step k+1 runs, so the stream never waits for the host; the
 // solve stops one step after the test first passes.
@@ -220,9 +219,8 @@ hx_status solve_cg(hx_ctx *c, const hx_solve_params *prm, const double *b, doubl
     while (it < prm->max_iter && !stop) {
         Timer &t = *tms[it % 2];
         t.rec(1, c->stream);
-        if (hipSuccess != launch_apply64(c, p, q, nullptr)) { err = fail(c, HX_ERR_DEVICE, "CG: apply"); break; }
+        if (hipSuccess != launch_apply64_dot(c, p, q, sc + 1)) { err = fail(c, HX_ERR_DEVICE, "CG: apply"); break; }
         t.rec(2, c->stream);
-        if (hipSuccess != blas_dot(c, n, p, q, sc + 1)) { err = fail(c, HX_ERR_DEVICE, "CG: dot"); break; }
         t.rec(0, c->stream);
         if (hipSuccess != cg_step_pc64(c, prm->pc, x, r, p, q, z, sc)) { err = fail(c, HX_ERR_DEVICE, "CG: step"); break; }
         t.rec(3, c->stream);
