@@ -54,29 +54,6 @@ static void free_mesh(hx_ctx *c)
     c->has_mesh = c->has_coef = false;
 }
 
-static hx_status upload_tables(hx_ctx *c)
-{
-    std::vector<OpTab> all(MAXN + 1);
-    std::memset(all.data(), 0, sizeof(OpTab) * all.size());
-    for (int n = 2; n <= MAXN; ++n) {
-        RefTab64 t;
-        build_ref_tables(n, t);
-        for (int i = 0; i < n * n; ++i) {
-            all[n].B[i] = t.B[i];
-            all[n].BD[i] = t.BD[i];
-            all[n].Bf[i] = (float)t.B[i];
-            all[n].BDf[i] = (float)t.BD[i];
-        }
-        for (int e = 0; e < 2; ++e)
-            for (int i = 0; i < n; ++i) {
-                all[n].DL[e][i] = t.DL[e][i];
-                all[n].DLf[e][i] = (float)t.DL[e][i];
-            }
-    }
-    HX_HIP(c, upload_op_tables_operator(all.data()));
-    return HX_OK;
-}
-
 }  // namespace hx
 
 using namespace hx;
@@ -99,8 +76,7 @@ hx_status hx_create(hx_ctx **out, int device, void *hip_stream)
     hx_ctx *c = new hx_ctx();
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
-    hx_status s = upload_tables(c);
-    if (s == HX_OK) s = dalloc(c, (void **)&c->red, sizeof(double) * (size_t)1024 * 72);
+    hx_status s = dalloc(c, (void **)&c->red, sizeof(double) * (size_t)1024 * 72);
     if (s == HX_OK && hipHostMalloc((void **)&c->red_host, sizeof(double) * 1024) != hipSuccess)
         s = HX_ERR_DEVICE;
     if (s != HX_OK) {

@@ -27,20 +27,11 @@ struct RefTab64 {
     double Cinv[MAXN * MAXN];              // inverse Cholesky factor of M (lower)
 };
 
-// Tables the operator kernels read from constant memory, per degree.
-struct OpTab {
-    double B[MAXN * MAXN], BD[MAXN * MAXN], DL[2][MAXN];
-    float Bf[MAXN * MAXN], BDf[MAXN * MAXN], DLf[2][MAXN];
-};
-
 void sym_eig(int n, double *a, double *w, double *v);
 void rule_gauss_legendre(int n, double *x01, double *w01);
 void rule_gauss_lobatto(int n, double *x01, double *w01);
 void lagrange_eval(int n, const double *nodes, double t, double *val, double *der);
 void build_ref_tables(int n, RefTab64 &t);
-
-// Per-translation-unit upload of the constant-memory tables.
-hipError_t upload_op_tables_operator(const OpTab *all /*[MAXN+1]*/);
 
 struct MlpState;   // learned preconditioner (mlp.hip)
 

@@ -25,8 +25,8 @@
 //    pencil owners then add the six faces' layer and normal-derivative
 //    contributions to their own output values.  Each output value is written
 //    by exactly one lane (no atomics; bitwise reproducible).
-//  * the 1-D tables sit in constant memory, loops over them are unrolled, so
-//    their entries are wave-uniform scalar operands.
+//  * the 1-D tables are compile-time constants and loops over them are
+//    unrolled, so their entries are wave-uniform scalar operands.
 //  * cell data [cell][7][N^3] is streamed once with non-temporal loads; x and
 //    the face data [cell][3][7][N][N] are read by neighbours too and stay
 //    cacheable.
@@ -40,35 +40,16 @@
 
 namespace hx {
 
-__constant__ OpTab c_op[MAXN + 1];
-
-hipError_t upload_op_tables_operator(const OpTab *all)
-{
-    return hipMemcpyToSymbol(HIP_SYMBOL(c_op), all, sizeof(OpTab) * (MAXN + 1));
-}
-
 namespace {
 
-// compile-time copies of the same tables (generated at build time from the
+// compile-time copies of the 1-D tables (generated at build time from the
 // library's rules): with every loop unrolled the compiler materialises the
-// entries with scalar moves instead of constant-memory loads
+// entries as scalar operands instead of loading them
 template <int N> struct KB;
 template <int N> struct KBD;
 template <int N> struct KDL;
 #include "optables.inc"
 
-template <typename T, int N>
-__device__ __forceinline__ T tB(int q, int i)
-{
-    if constexpr (std::is_same<T, double>::value) return KB<N>::d[q * N + i];
-    else return KB<N>::f[q * N + i];
-}
-template <typename T, int N>
-__device__ __forceinline__ T tD(int q, int i)
-{
-    if constexpr (std::is_same<T, double>::value) return KBD<N>::d[q * N + i];
-    else return KBD<N>::f[q * N + i];
-}
 template <typename T, int N>
 __device__ __forceinline__ T tE(int e, int i)
 {

@@ -1,7 +1,8 @@
 // Host-side 1-D reference data of the library: Gauss-Legendre and
 // Gauss-Lobatto rules by the Golub-Welsch eigenvalue method, Lagrange
-// bases in barycentric form, and the per-degree tables the kernels read
-// from constant memory.
+// bases in barycentric form, and the per-degree tables of the set-up and
+// block-Jacobi kernels (the operator's copies are generated from the same
+// rules at build time).
 //
 // Dof nodes are the (k+1) Gauss-Lobatto points (section 2 of the paper);
 // quadrature is (k+1)-point Gauss-Legendre (section 3.3).
