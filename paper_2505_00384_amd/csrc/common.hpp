@@ -61,6 +61,8 @@ struct hx_ctx {
     // merged operator data
     double *cell64 = nullptr;     // [n_cells][7][nd]
     float *cell32 = nullptr;
+    double *cellgeo = nullptr;    // [n_cells][7][nd] geometric factors of the cell data
+    double *facegeo = nullptr;    // [n_cells][3][7][nf] geometric factors of the face data
     double *face64 = nullptr;     // [n_cells][3][7][N (1st tangential)][N (2nd)]
     float *face32 = nullptr;
     double *dg64 = nullptr;       // [2][n_dofs] inverse volume diagonals: mass + stiffness, mass
@@ -113,6 +115,7 @@ hipError_t launch_face_sigma(hx_ctx *c);                    // sigma
 hipError_t launch_bj_eigen(hx_ctx *c);                      // bjS, bjL
 hipError_t launch_set_coefficients(hx_ctx *c, const double *alpha, const double *beta);
 hipError_t launch_dof_coords(hx_ctx *c, double *xyz);
+hipError_t launch_geofac(hx_ctx *c);
 hipError_t launch_cell_diag(hx_ctx *c);
 hipError_t launch_diag64(hx_ctx *c, int which, const double *r, double *z);
 hipError_t launch_diag32(hx_ctx *c, int which, const float *r, float *z);

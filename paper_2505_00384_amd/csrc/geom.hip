@@ -274,15 +274,90 @@ __global__ void k_bj_eigen(int64_t n_cells, const int32_t *__restrict__ nbr,
 }
 
 // -------------------------------------------------------------------------
-// merged cell data (block per cell, thread per quadrature point)
-//   m = alpha_q w detJ,  G = beta_q w detJ J^{-1} J^{-T}
-// and the block-Jacobi scalars from the volume-weighted means of alpha, beta
+// Geometric factors, once per mesh (block per cell / thread per face point).
+// Cell quadrature point q:   cg[0] = w detJ,
+//                            cg[1..6] = w detJ (J^-1 J^-T)_{xx,xy,xz,yy,yz,zz}.
+// Point (a, b) of the +d face of a cell (a, b along the first and second
+// tangential direction, stored at b + n a):
+//                            fg[0..2] = ds J-^{-1} n,  fg[3..5] = ds J+^{-1} n
+// (components in the face's own order: normal direction d, first, second
+// tangential), fg[6] = ds / 2, with n and ds from the minus cell; zero on
+// boundary faces.  Coefficients multiply these in k_set_cell / k_set_face.
 // -------------------------------------------------------------------------
-__global__ void k_set_cell(const double *__restrict__ nodes, int ng, int n,
-                           const RefTab64 *__restrict__ T, const double *__restrict__ alpha,
+__global__ void k_cell_geofac(const double *__restrict__ nodes, int ng, int n, int64_t n_cells,
+                              const RefTab64 *__restrict__ T, double *cellgeo)
+{
+    const int nd = n * n * n;
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= n_cells * nd) return;
+    const int64_t c = t / nd;
+    const int q = (int)(t % nd);
+    const int i = q % n, j = (q / n) % n, l = q / (n * n);
+    double xi[3] = {T->xq[i], T->xq[j], T->xq[l]}, x[3], J[3][3], Ji[3][3];
+    cell_map(nodes + c * (int64_t)ng * ng * ng * 3, ng, xi, x, J);
+    const double det = det3(J);
+    inv3(J, det, Ji);
+    const double w = T->wq[i] * T->wq[j] * T->wq[l] * det;
+    double *dst = cellgeo + c * 7 * nd + q;
+    dst[0] = w;
+    const int pa[6] = {0, 0, 0, 1, 1, 2}, pb[6] = {0, 1, 2, 1, 2, 2};
+    for (int s = 0; s < 6; ++s) {
+        const int A = pa[s], Bq = pb[s];
+        dst[(1 + s) * nd] = w * (Ji[A][0] * Ji[Bq][0] + Ji[A][1] * Ji[Bq][1] + Ji[A][2] * Ji[Bq][2]);
+    }
+}
+
+__global__ void k_face_geofac(const double *__restrict__ nodes, int ng, int n, int64_t n_cells,
+                              const int32_t *__restrict__ nbr, const RefTab64 *__restrict__ T,
+                              double *facegeo)
+{
+    const int nf = n * n;
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= 3 * n_cells * nf) return;
+    const int pt = (int)(t % nf);
+    const int64_t cd = t / nf;
+    const int64_t c = cd / 3;
+    const int d = (int)(cd % 3);
+    const int b = pt % n, a = pt / n;
+    double *dst = facegeo + cd * 7 * nf + pt;
+    const int32_t nb = nbr[6 * c + 2 * d + 1];
+    if (nb < 0) {
+        for (int s = 0; s < 7; ++s) dst[s * nf] = 0.0;
+        return;
+    }
+    double xim[3], xip[3], x[3], Jm[3][3], Jp[3][3], Jmi[3][3], Jpi[3][3];
+    face_xi(T, d, 1, a, b, xim);
+    face_xi(T, d, 0, a, b, xip);
+    const int64_t gsz = (int64_t)ng * ng * ng * 3;
+    cell_map(nodes + c * gsz, ng, xim, x, Jm);
+    cell_map(nodes + (int64_t)nb * gsz, ng, xip, x, Jp);
+    const double detm = det3(Jm), detp = det3(Jp);
+    inv3(Jm, detm, Jmi);
+    inv3(Jp, detp, Jpi);
+    // J^{-T} e_d is row d of J^{-1}
+    double nv[3] = {Jmi[d][0], Jmi[d][1], Jmi[d][2]};
+    const double len = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+    for (int r = 0; r < 3; ++r) nv[r] /= len;
+    const double ds = T->wq[a] * T->wq[b] * detm * len;
+    const int dir[3] = {d, d == 0 ? 1 : 0, d == 2 ? 1 : 2};
+    for (int k = 0; k < 3; ++k) {
+        const int r = dir[k];
+        dst[k * nf] = ds * (Jmi[r][0] * nv[0] + Jmi[r][1] * nv[1] + Jmi[r][2] * nv[2]);
+        dst[(3 + k) * nf] = ds * (Jpi[r][0] * nv[0] + Jpi[r][1] * nv[1] + Jpi[r][2] * nv[2]);
+    }
+    dst[6 * nf] = 0.5 * ds;
+}
+
+// -------------------------------------------------------------------------
+// merged cell data from the coefficients (block per cell, thread per point):
+//   m = alpha_q w detJ,  G = beta_q w detJ J^-1 J^-T  (alpha_q, beta_q: the
+// nodal fields at the Gauss point), plus the cell means of the separable
+// block (volume-weighted alpha, beta) and the network's coefficient feature
+// -------------------------------------------------------------------------
+__global__ void k_set_cell(int n, const RefTab64 *__restrict__ T, const double *__restrict__ alpha,
                            const double *__restrict__ beta, const double *__restrict__ ell,
-                           double *cell64, float *cell32, double *bjC64, float *bjC32,
-                           double *coef_feat)
+                           const double *__restrict__ cellgeo, double *cell64, float *cell32,
+                           double *bjC64, float *bjC32, double *coef_feat)
 {
     const int64_t c = blockIdx.x;
     const int nd = n * n * n;
@@ -290,11 +365,6 @@ __global__ void k_set_cell(const double *__restrict__ nodes, int ng, int n,
     double sw = 0.0, sa = 0.0, sb = 0.0;
     if (q < nd) {
         const int i = q % n, j = (q / n) % n, l = q / (n * n);
-        double xi[3] = {T->xq[i], T->xq[j], T->xq[l]}, x[3], J[3][3], Ji[3][3];
-        cell_map(nodes + c * (int64_t)ng * ng * ng * 3, ng, xi, x, J);
-        const double det = det3(J);
-        inv3(J, det, Ji);
-        const double w = T->wq[i] * T->wq[j] * T->wq[l] * det;
         const double *ac = alpha + c * nd, *bc = beta + c * nd;
         double aq = 0.0, bq = 0.0;
         for (int l2 = 0; l2 < n; ++l2)
@@ -307,19 +377,16 @@ __global__ void k_set_cell(const double *__restrict__ nodes, int ng, int n,
                     bq += wgt * bc[e];
                 }
             }
-        double G[6];
-        const int pa[6] = {0, 0, 0, 1, 1, 2}, pb[6] = {0, 1, 2, 1, 2, 2};
-        for (int s = 0; s < 6; ++s) {
-            const int A = pa[s], Bq = pb[s];
-            G[s] = bq * w * (Ji[A][0] * Ji[Bq][0] + Ji[A][1] * Ji[Bq][1] + Ji[A][2] * Ji[Bq][2]);
-        }
-        double *dst = cell64 + c * 7 * nd;
-        float *dstf = cell32 + c * 7 * nd;
-        dst[q] = aq * w;
-        dstf[q] = (float)(aq * w);
-        for (int s = 0; s < 6; ++s) {
-            dst[(1 + s) * nd + q] = G[s];
-            dstf[(1 + s) * nd + q] = (float)G[s];
+        const double *g = cellgeo + c * 7 * nd + q;
+        double *dst = cell64 + c * 7 * nd + q;
+        float *dstf = cell32 + c * 7 * nd + q;
+        const double w = g[0];
+        dst[0] = aq * w;
+        dstf[0] = (float)(aq * w);
+        for (int s = 1; s < 7; ++s) {
+            const double v = bq * g[s * nd];
+            dst[s * nd] = v;
+            dstf[s * nd] = (float)v;
         }
         sw = w;
         sa = w * aq;
@@ -358,9 +425,9 @@ __global__ void k_set_cell(const double *__restrict__ nodes, int ng, int n,
 // the order (d, first tangential, second tangential) so that the operator
 // pairs them with its reference derivatives without a per-lane selection.
 // -------------------------------------------------------------------------
-__global__ void k_set_face(const double *__restrict__ nodes, int ng, int n, int64_t n_cells,
-                           const int32_t *__restrict__ nbr, const RefTab64 *__restrict__ T,
-                           const double *__restrict__ beta, const double *__restrict__ sigma,
+__global__ void k_set_face(int n, int64_t n_cells, const int32_t *__restrict__ nbr,
+                           const RefTab64 *__restrict__ T, const double *__restrict__ beta,
+                           const double *__restrict__ sigma, const double *__restrict__ facegeo,
                            double *face64, float *face32)
 {
     const int nf = n * n, nd = nf * n;
@@ -370,33 +437,18 @@ __global__ void k_set_face(const double *__restrict__ nodes, int ng, int n, int6
     const int64_t cd = t / nf;
     const int64_t c = cd / 3;
     const int d = (int)(cd % 3);
-    // point (a, b): a along the first, b along the second tangential
-    // direction, stored at b + n a
     const int b = pt % n, a = pt / n;
-    double *dst = face64 + cd * 7 * nf;
-    float *dstf = face32 + cd * 7 * nf;
+    double *dst = face64 + cd * 7 * nf + pt;
+    float *dstf = face32 + cd * 7 * nf + pt;
+    const double *g = facegeo + cd * 7 * nf + pt;
     const int32_t nb = nbr[6 * c + 2 * d + 1];
     if (nb < 0) {
         for (int s = 0; s < 7; ++s) {
-            dst[s * nf + pt] = 0.0;
-            dstf[s * nf + pt] = 0.0f;
+            dst[s * nf] = 0.0;
+            dstf[s * nf] = 0.0f;
         }
         return;
     }
-    double xim[3], xip[3], x[3], Jm[3][3], Jp[3][3], Jmi[3][3], Jpi[3][3];
-    face_xi(T, d, 1, a, b, xim);
-    face_xi(T, d, 0, a, b, xip);
-    const int64_t gsz = (int64_t)ng * ng * ng * 3;
-    cell_map(nodes + c * gsz, ng, xim, x, Jm);
-    cell_map(nodes + (int64_t)nb * gsz, ng, xip, x, Jp);
-    const double detm = det3(Jm), detp = det3(Jp);
-    inv3(Jm, detm, Jmi);
-    inv3(Jp, detp, Jpi);
-    // J^{-T} e_d is row d of J^{-1}
-    double nv[3] = {Jmi[d][0], Jmi[d][1], Jmi[d][2]};
-    const double len = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
-    for (int r = 0; r < 3; ++r) nv[r] /= len;
-    const double ds = T->wq[a] * T->wq[b] * detm * len;
     double bm = 0.0, bp = 0.0;
     for (int r = 0; r < n; ++r)
         for (int p = 0; p < n; ++p) {
@@ -404,19 +456,15 @@ __global__ void k_set_face(const double *__restrict__ nodes, int ng, int n, int6
             bm += wgt * beta[c * nd + layer_idx(n, d, n - 1, p, r)];
             bp += wgt * beta[(int64_t)nb * nd + layer_idx(n, d, 0, p, r)];
         }
-    // components in the face's own order: normal reference direction d, then
-    // the first and second tangential one
-    const int dir[3] = {d, d == 0 ? 1 : 0, d == 2 ? 1 : 2};
     double out[7];
     for (int k = 0; k < 3; ++k) {
-        const int r = dir[k];
-        out[k] = bm * ds * (Jmi[r][0] * nv[0] + Jmi[r][1] * nv[1] + Jmi[r][2] * nv[2]);
-        out[3 + k] = bp * ds * (Jpi[r][0] * nv[0] + Jpi[r][1] * nv[1] + Jpi[r][2] * nv[2]);
+        out[k] = bm * g[k * nf];
+        out[3 + k] = bp * g[(3 + k) * nf];
     }
-    out[6] = sigma[3 * c + d] * 0.5 * (bm + bp) * ds;
+    out[6] = sigma[3 * c + d] * (bm + bp) * g[6 * nf];
     for (int s = 0; s < 7; ++s) {
-        dst[s * nf + pt] = out[s];
-        dstf[s * nf + pt] = (float)out[s];
+        dst[s * nf] = out[s];
+        dstf[s * nf] = (float)out[s];
     }
 }
 
@@ -480,19 +528,30 @@ hipError_t launch_bj_eigen(hx_ctx *c)
     }
 }
 
+hipError_t launch_geofac(hx_ctx *c)
+{
+    hipLaunchKernelGGL(k_cell_geofac, dim3(nblk(c->n_cells * c->nd, 128)), dim3(128), 0, c->stream,
+                       c->nodes, c->g + 1, c->n, c->n_cells, c->ref, c->cellgeo);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t nt = 3 * c->n_cells * c->nf;
+    hipLaunchKernelGGL(k_face_geofac, dim3(nblk(nt, 128)), dim3(128), 0, c->stream, c->nodes,
+                       c->g + 1, c->n, c->n_cells, c->nbr, c->ref, c->facegeo);
+    return hipGetLastError();
+}
+
 hipError_t launch_set_coefficients(hx_ctx *c, const double *alpha, const double *beta)
 {
     int threads = 64;                     // power of two for the tree reduction
     while (threads < c->nd) threads *= 2;
-    hipLaunchKernelGGL(k_set_cell, dim3((unsigned)c->n_cells), dim3(threads), 0, c->stream,
-                       c->nodes, c->g + 1, c->n, c->ref, alpha, beta, c->ell, c->cell64, c->cell32,
-                       c->bjC64, c->bjC32, c->coef_feat);
+    hipLaunchKernelGGL(k_set_cell, dim3((unsigned)c->n_cells), dim3(threads), 0, c->stream, c->n,
+                       c->ref, alpha, beta, c->ell, c->cellgeo, c->cell64, c->cell32, c->bjC64,
+                       c->bjC32, c->coef_feat);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t nt = 3 * c->n_cells * c->nf;
-    hipLaunchKernelGGL(k_set_face, dim3(nblk(nt, 128)), dim3(128), 0, c->stream, c->nodes,
-                       c->g + 1, c->n, c->n_cells, c->nbr, c->ref, beta, c->sigma, c->face64,
-                       c->face32);
+    hipLaunchKernelGGL(k_set_face, dim3(nblk(nt, 128)), dim3(128), 0, c->stream, c->n, c->n_cells,
+                       c->nbr, c->ref, beta, c->sigma, c->facegeo, c->face64, c->face32);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_cell_diag(c);
