@@ -558,42 +558,96 @@ hipError_t launch_set_coefficients(hx_ctx *c, const double *alpha, const double 
 }
 
 // -------------------------------------------------------------------------
-// Volume diagonals from the merged cell data (block per cell, thread per
-// dof i = (a, b, l)):
+// Volume diagonals from the merged cell data (block per cell):
 //   d_i = sum_q [ m_q phi_i(q)^2 + grad phi_i(q)^T G_q grad phi_i(q) ],
-// phi_i(q) = B(qx,a) B(qy,b) B(qz,l), reference gradient from BD.  Stored as
-// inverses: dg[0] of mass plus stiffness (the paper's Helmholtz
-// preconditioner, section 3.1), dg[1] of the mass alone (its internal-energy
-// variant).
+// phi_i(q) = B(qx,a) B(qy,b) B(qz,l), reference gradient from BD.  Every
+// term is a tensor contraction of one quadrature field with products of
+// 1-D tables, P0 = B B, P1 = B BD, P2 = BD BD, e.g. the Gxy term is
+// 2 sum_q Gxy P1(qx,a) P1(qy,b) P0(qz,l); the kernel contracts z, then y,
+// then x, merging terms that share their remaining tables (N^4 work per
+// sweep instead of N^6 per cell).  Stored as inverses: dg[0] of mass plus
+// stiffness (the paper's Helmholtz preconditioner, section 3.1), dg[1] of
+// the mass alone (its internal-energy variant).
 // -------------------------------------------------------------------------
+__device__ __forceinline__ double ptab(const RefTab64 *T, int n, int kind, int q, int a)
+{
+    const double bv = T->B[q * n + a], dv = T->BD[q * n + a];
+    return kind == 0 ? bv * bv : (kind == 1 ? bv * dv : dv * dv);
+}
+
 __global__ void k_cell_diag(int n, int64_t n_cells, const RefTab64 *__restrict__ T,
                             const double *__restrict__ cell, double *dg64, float *dg32)
 {
-    extern __shared__ double scd[];          // [7][nd]
+    extern __shared__ double sd[];           // F [7][nd], then A [7][nd]
     const int nd = n * n * n;
     const int64_t c = blockIdx.x;
     const double *cd = cell + c * 7 * nd;
-    for (int e = threadIdx.x; e < 7 * nd; e += blockDim.x) scd[e] = cd[e];
+    double *F = sd, *A = sd + 7 * nd;
+    for (int e = threadIdx.x; e < 7 * nd; e += blockDim.x) F[e] = cd[e];
     __syncthreads();
-    const int i = threadIdx.x;
-    if (i >= nd) return;
-    const int a = i % n, b = (i / n) % n, l = i / (n * n);
-    double dm = 0.0, ds = 0.0;
-    for (int qz = 0; qz < n; ++qz)
-        for (int qy = 0; qy < n; ++qy)
-            for (int qx = 0; qx < n; ++qx) {
-                const int q = qx + n * (qy + n * qz);
-                const double bx = T->B[qx * n + a], by = T->B[qy * n + b], bz = T->B[qz * n + l];
-                const double g0 = T->BD[qx * n + a] * by * bz, g1 = bx * T->BD[qy * n + b] * bz,
-                             g2 = bx * by * T->BD[qz * n + l];
-                const double ph = bx * by * bz;
-                const double *G = scd + q;
-                dm += G[0] * ph * ph;
-                ds += G[nd] * g0 * g0 + G[4 * nd] * g1 * g1 + G[6 * nd] * g2 * g2 +
-                      2.0 * (G[2 * nd] * g0 * g1 + G[3 * nd] * g0 * g2 + G[5 * nd] * g1 * g2);
-            }
-    const int64_t o = c * nd + i, nt = n_cells * nd;
-    const double ih = 1.0 / (dm + ds), im = 1.0 / dm;
+    const int t = threadIdx.x;
+    const bool on = t < nd;
+    const int i0 = t % n, i1 = (t / n) % n, i2 = t / (n * n);
+    // z: thread (qx, qy, l); fields m, Gxx, Gxy, Gxz, Gyy, Gyz, Gzz
+    if (on) {
+        double tm = 0, txx = 0, tyy = 0, tzz = 0, txy = 0, txz = 0, tyz = 0;
+        for (int qz = 0; qz < n; ++qz) {
+            const int q = i0 + n * (i1 + n * qz);
+            const double p0 = ptab(T, n, 0, qz, i2), p1 = ptab(T, n, 1, qz, i2),
+                         p2 = ptab(T, n, 2, qz, i2);
+            tm += p0 * F[q];
+            txx += p0 * F[nd + q];
+            txy += p0 * F[2 * nd + q];
+            txz += p1 * F[3 * nd + q];
+            tyy += p0 * F[4 * nd + q];
+            tyz += p1 * F[5 * nd + q];
+            tzz += p2 * F[6 * nd + q];
+        }
+        // groups by their remaining (x, y) tables:
+        // 0 mass (P0,P0), 1 m + Gzz (P0,P0), 2 Gxx (P2,P0), 3 Gyy (P0,P2),
+        // 4 2Gxy (P1,P1), 5 2Gxz (P1,P0), 6 2Gyz (P0,P1)
+        A[t] = tm;
+        A[nd + t] = tm + tzz;
+        A[2 * nd + t] = txx;
+        A[3 * nd + t] = tyy;
+        A[4 * nd + t] = 2.0 * txy;
+        A[5 * nd + t] = 2.0 * txz;
+        A[6 * nd + t] = 2.0 * tyz;
+    }
+    __syncthreads();
+    // y: thread (qx, b, l); results by their x table: mass P0, P0, P2, P1
+    double cm = 0, c0 = 0, c2 = 0, c1 = 0;
+    if (on) {
+        for (int qy = 0; qy < n; ++qy) {
+            const int q = i0 + n * (qy + n * i2);
+            const double p0 = ptab(T, n, 0, qy, i1), p1 = ptab(T, n, 1, qy, i1),
+                         p2 = ptab(T, n, 2, qy, i1);
+            cm += p0 * A[q];
+            c0 += p0 * A[nd + q] + p2 * A[3 * nd + q] + p1 * A[6 * nd + q];
+            c2 += p0 * A[2 * nd + q];
+            c1 += p1 * A[4 * nd + q] + p0 * A[5 * nd + q];
+        }
+    }
+    __syncthreads();
+    if (on) {
+        F[t] = cm;
+        F[nd + t] = c0;
+        F[2 * nd + t] = c2;
+        F[3 * nd + t] = c1;
+    }
+    __syncthreads();
+    // x: thread (a, b, l)
+    if (!on) return;
+    double dm = 0, dt = 0;
+    for (int qx = 0; qx < n; ++qx) {
+        const int q = qx + n * (i1 + n * i2);
+        const double p0 = ptab(T, n, 0, qx, i0), p1 = ptab(T, n, 1, qx, i0),
+                     p2 = ptab(T, n, 2, qx, i0);
+        dm += p0 * F[q];
+        dt += p0 * F[nd + q] + p2 * F[2 * nd + q] + p1 * F[3 * nd + q];
+    }
+    const int64_t o = c * nd + t, nt = n_cells * nd;
+    const double ih = 1.0 / dt, im = 1.0 / dm;
     dg64[o] = ih;
     dg64[nt + o] = im;
     dg32[o] = (float)ih;
@@ -605,7 +659,7 @@ hipError_t launch_cell_diag(hx_ctx *c)
     int threads = 64;
     while (threads < c->nd) threads *= 2;
     hipLaunchKernelGGL(k_cell_diag, dim3((unsigned)c->n_cells), dim3(threads),
-                       sizeof(double) * 7 * c->nd, c->stream, c->n, c->n_cells, c->ref, c->cell64,
+                       sizeof(double) * 14 * c->nd, c->stream, c->n, c->n_cells, c->ref, c->cell64,
                        c->dg64, c->dg32);
     return hipGetLastError();
 }
