@@ -167,7 +167,8 @@ typedef struct {
     int restart;         /* FGMRES restart length, 1..63 (30) */
     double rtol;         /* stop when ||b - A x||_2 <= rtol ||b||_2 */
     int max_iter;        /* total iteration cap */
-    int pc;              /* hx_pc of the (outer) iteration */
+    int pc;              /* hx_pc of the iteration; with mixed = 1, of the inner FP32 CG
+                            (HX_PC_LEARNED is not allowed there) */
     int mixed;           /* 1: outer FP64 FGMRES, preconditioner = inner FP32 CG */
     int inner_iters;     /* inner FP32 CG iterations per outer step (mixed; 32) */
     double inner_rtol;   /* inner stopping tolerance (relative, mixed) */

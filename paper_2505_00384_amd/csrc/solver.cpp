@@ -93,17 +93,25 @@ hx_status ensure_work(hx_ctx *c, size_t n64, size_t n32)
     return HX_OK;
 }
 
-// inner FP32 PCG for `iters` iterations on A32 z = v (FP64 in/out); scalars
-// on the device, each step fused around the FP32 block Jacobi (one pass over
-// x, r, p, q and z).  w32: 5 float vectors.
-hx_status inner_fp32(hx_ctx *c, const double *v, double *z, float *w32, int iters, int *count)
+// inner FP32 PCG for `iters` iterations on A32 z = v (FP64 in/out) with the
+// FP32 form of preconditioner pc (block Jacobi, a diagonal kind or none);
+// scalars on the device, each step fused around the preconditioner (one pass
+// over x, r, p, q and z).  w32: 5 float vectors.
+hx_status inner_fp32(hx_ctx *c, int pc, const double *v, double *z, float *w32, int iters,
+                     int *count)
 {
     const int64_t n = c->n_dofs;
     float *x = w32, *r = w32 + n, *zz = w32 + 2 * n, *p = w32 + 3 * n, *q = w32 + 4 * n;
     double *sc = c->red + SC_OFF + 512;   // [0] rz, [1] pq, [2] rz_new, [3] rr
     HX_HIP(c, blas_cast64to32(c, n, v, r, nullptr));
     HX_HIP(c, blas_fill32(c, n, 0.0f, x));
-    HX_HIP(c, launch_bj32(c, r, zz));
+    switch (pc) {
+    case HX_PC_BLOCK_JACOBI: HX_HIP(c, launch_bj32(c, r, zz)); break;
+    case HX_PC_HELMHOLTZ_DIAG: HX_HIP(c, launch_diag32(c, 0, r, zz)); break;
+    case HX_PC_MASS_DIAG: HX_HIP(c, launch_diag32(c, 1, r, zz)); break;
+    default:
+        HX_HIP(c, hipMemcpyAsync(zz, r, sizeof(float) * n, hipMemcpyDeviceToDevice, c->stream));
+    }
     HX_HIP(c, hipMemcpyAsync(p, zz, sizeof(float) * n, hipMemcpyDeviceToDevice, c->stream));
     HX_HIP(c, blas_dot32(c, n, r, zz, sc + 0));
     for (int it = 0; it < iters; ++it) {
@@ -112,7 +120,7 @@ hx_status inner_fp32(hx_ctx *c, const double *v, double *z, float *w32, int iter
             HX_HIP(c, cg32_step_x(c, n, x, r, p, q, sc));
             break;
         }
-        HX_HIP(c, cg_step_pc32(c, HX_PC_BLOCK_JACOBI, x, r, p, q, zz, sc));
+        HX_HIP(c, cg_step_pc32(c, pc, x, r, p, q, zz, sc));
         HX_HIP(c, cg_step_p32(c, zz, p, sc));
     }
     HX_HIP(c, blas_cast32to64(c, n, x, z, nullptr));
@@ -124,7 +132,7 @@ hx_status precondition(hx_ctx *c, int pc, int mixed, int inner_iters, const doub
                        float *w32, int *inner_count, int *nonfinite)
 {
     *nonfinite = 0;
-    if (mixed) return inner_fp32(c, v, z, w32, inner_iters, inner_count);
+    if (mixed) return inner_fp32(c, pc, v, z, w32, inner_iters, inner_count);
     switch (pc) {
     case HX_PC_NONE: HX_HIP(c, blas_copy(c, c->n_dofs, v, z)); return HX_OK;
     case HX_PC_BLOCK_JACOBI: HX_HIP(c, launch_bj64(c, v, z)); return HX_OK;
@@ -585,6 +593,8 @@ hx_status hx_solve(hx_ctx *c, const hx_solve_params *prm, const double *b, doubl
     if (prm->method == 0 && (prm->pc == HX_PC_LEARNED || prm->mixed))
         return fail(c, HX_ERR_ARG, "CG needs a fixed SPD preconditioner; use FGMRES");
     if (prm->mixed && prm->inner_iters < 1) return fail(c, HX_ERR_ARG, "inner_iters must be >= 1");
+    if (prm->mixed && prm->pc == HX_PC_LEARNED)
+        return fail(c, HX_ERR_ARG, "the learned preconditioner is FP64; it cannot precondition the inner FP32 solve");
     if (prm->pc == HX_PC_LEARNED && !c->mlp) return fail(c, HX_ERR_STATE, "no network loaded");
     HX_HIP(c, hipSetDevice(c->device));
     const double t0 = now_ms();

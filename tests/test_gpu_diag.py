@@ -74,3 +74,21 @@ def test_solves_with_diagonal_preconditioners():
     assert its[("helmholtz", 0)] < its[("mass", 0)]
     assert its[("bj", 0)] < its[("helmholtz", 0)]
     ctx.close()
+
+
+def test_mixed_solve_with_diagonal_inner_preconditioner():
+    """The inner FP32 CG of the mixed form takes the chosen kind; the learned
+    kind (FP64 only) is refused there."""
+    hx = _hx()
+    p = problem(si.terrain_mesh(8, 2, 4, g=4), 4, coef="terrain")
+    ctx = gpu_context(p)
+    b = to_dev(si.rhs_terrain(5)(*p.dof_coords()))
+    for kind in (hx.HX_PC_HELMHOLTZ_DIAG, hx.HX_PC_BLOCK_JACOBI):
+        x, info = ctx.solve(b, params=hx.default_params(method=1, restart=10, mixed=1, pc=kind,
+                                                         inner_iters=16, rtol=1e-8))
+        print(f"[diag] mixed inner pc={kind}: {info['iters']} outer, {info['inner_iters']} inner",
+              flush=True)
+        assert info["status"] == hx.HX_OK and info["true_rel_res"] <= 1e-8
+    with pytest.raises(hx.HXError):
+        ctx.solve(b, params=hx.default_params(method=1, mixed=1, pc=hx.HX_PC_LEARNED))
+    ctx.close()

@@ -99,6 +99,27 @@ def test_delayed_reorthogonalisation_matches_cgs2(terrain_small):
     ctx.close()
 
 
+def test_solves_are_bitwise_reproducible(terrain_small):
+    """Fixed-order reductions everywhere (dots, fused CG steps, the operator's
+    p.q, FGMRES block dots): repeating a solve gives the same bits and the
+    same iteration count, for CG (block Jacobi and the Helmholtz diagonal),
+    FGMRES in both orthogonalisation forms and the mixed form."""
+    import torch
+    hx = _hx()
+    p, b, _ = terrain_small
+    ctx = gpu_context(p)
+    bd = to_dev(b)
+    for kw in (dict(method=0), dict(method=0, pc=hx.HX_PC_HELMHOLTZ_DIAG, max_iter=5000),
+               dict(method=1, orth=0), dict(method=1, orth=1),
+               dict(method=1, restart=10, mixed=1, inner_iters=16)):
+        x1, i1 = ctx.solve(bd, params=hx.default_params(rtol=1e-9, **kw))
+        x2, i2 = ctx.solve(bd, params=hx.default_params(rtol=1e-9, **kw))
+        print(f"[solve] repeat {kw}: {i1['iters']} it", flush=True)
+        assert i1["status"] == hx.HX_OK and i1["iters"] == i2["iters"]
+        assert torch.equal(x1, x2), kw
+    ctx.close()
+
+
 def test_mixed_precision_solution_error(terrain_small):
     hx = _hx()
     p, b, xs = terrain_small
