@@ -4,8 +4,9 @@
 // Network n_in -> 256 -> 256 -> n_out with ReLU, n_in = N^3 + 6 N^2 + 1,
 // n_out = N^3.  Parameters flat [W1, b1, W2, b2, W3, b3], W row-major
 // [out][in]; FP32 master weights and Adam moments, BF16 working copies.
-// Every product runs on the gfx950 matrix cores (v_mfma_f32_16x16x16_bf16,
-// FP32 accumulation); activations entering a product are BF16 (round to
+// Every product runs on the gfx950 matrix cores (v_mfma_f32_16x16x32_bf16
+// for the K-contiguous forward products, v_mfma_f32_16x16x16_bf16 for the
+// strided ones of the backward pass; FP32 accumulation); activations entering a product are BF16 (round to
 // nearest even), biases, losses and gradients of the biases are FP32.
 //
 // Features of cell K (divided by s = RMS(r_K), zero when s = 0): r_K in local
@@ -109,11 +110,92 @@ k_gemm(int M, int N, int K, const uint16_t *__restrict__ A, int64_t sam, int64_t
             }
 }
 
+// ---------------------------------------------------------------------------
+// The same product when both operands are K-contiguous (A [M][K], B [N][K],
+// K a multiple of 32, rows 16-byte aligned) -- every forward product of the
+// network.  128 x 128 output tile per workgroup of 4 waves (64 x 64 each, a
+// 4 x 4 grid of 16 x 16 accumulators), 16-byte tile loads into padded LDS
+// rows, v_mfma_f32_16x16x32_bf16 (gfx950): lane l supplies A[row l % 16] and
+// B[col l % 16] at the same 8 consecutive k, 8 (l / 16) .. + 7, so the
+// product pairs matching k whatever order the unit sums them in.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int NM = 128, NN = 128, NK = 32, NPAD = 8;
+
+__global__ void __launch_bounds__(256)
+k_gemm_nt(int M, int N, int K, const uint16_t *__restrict__ A, int64_t lda,
+          const uint16_t *__restrict__ B, int64_t ldb, const float *__restrict__ bias, int relu,
+          float *C32, int64_t ldc32, uint16_t *C16, int64_t ldc16)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t sA[NM][NK + NPAD];
+    __shared__ __attribute__((aligned(16))) uint16_t sB[NN][NK + NPAD];
+    const int m0 = blockIdx.x * NM, n0 = blockIdx.y * NN;
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    const uint4 zero = {0u, 0u, 0u, 0u};
+    for (int k0 = 0; k0 < K; k0 += NK) {
+        // 128 rows x 32 k per operand = 512 chunks of 8 values, 2 per thread
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int ch = t + 256 * h, row = ch >> 2, kc = (ch & 3) * 8;
+            const int m = m0 + row, n = n0 + row;
+            const uint4 va = m < M ? *(const uint4 *)(A + (int64_t)m * lda + k0 + kc) : zero;
+            const uint4 vb = n < N ? *(const uint4 *)(B + (int64_t)n * ldb + k0 + kc) : zero;
+            *(uint4 *)&sA[row][kc] = va;
+            *(uint4 *)&sB[row][kc] = vb;
+        }
+        __syncthreads();
+        const int rr = lane & 15, kq = (lane >> 4) * 8;
+        bf16x8 fa[4], fb[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            fa[i] = __builtin_bit_cast(bf16x8, *(const uint4 *)&sA[wm + 16 * i + rr][kq]);
+            fb[i] = __builtin_bit_cast(bf16x8, *(const uint4 *)&sB[wn + 16 * i + rr][kq]);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
+    }
+    // result layout: lane l holds C[row = 4 (l / 16) + q][col = l % 16], q = 0..3
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int n = n0 + wn + 16 * j + (lane & 15);
+            const float bn = (bias && n < N) ? bias[n] : 0.f;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + q;
+                if (m < M && n < N) {
+                    float v = acc[i][j][q] + bn;
+                    if (relu) v = v > 0.f ? v : 0.f;
+                    if (C32) C32[(int64_t)m * ldc32 + n] = v;
+                    if (C16) C16[(int64_t)m * ldc16 + n] = f2bf(v);
+                }
+            }
+        }
+}
+
 hipError_t gemm(hipStream_t st, int M, int N, int K, const uint16_t *A, int64_t sam, int64_t sak,
                 const uint16_t *B, int64_t sbn, int64_t sbk, const float *bias, int relu, float *C32,
                 int64_t ldc32, uint16_t *C16, int64_t ldc16)
 {
     if (M <= 0 || N <= 0) return hipSuccess;
+    if (sak == 1 && sbk == 1 && K % NK == 0 && sam % 8 == 0 && sbn % 8 == 0 &&
+        ((uintptr_t)A & 15) == 0 && ((uintptr_t)B & 15) == 0) {
+        dim3 grid((M + NM - 1) / NM, (N + NN - 1) / NN);
+        hipLaunchKernelGGL(k_gemm_nt, grid, dim3(256), 0, st, M, N, K, A, sam, B, sbn, bias, relu,
+                           C32, ldc32, C16, ldc16);
+        return hipGetLastError();
+    }
     dim3 grid((M + TM - 1) / TM, (N + TN - 1) / TN);
     hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, st, M, N, K, A, sam, sak, B, sbn, sbk, bias, relu,
                        C32, ldc32, C16, ldc16);
@@ -485,16 +567,17 @@ hx_status mlp_features(hx_ctx *c, const double *r, float *feats, float *scale)
     return HX_OK;
 }
 
-// forward on the packed batch s->xb (B rows); h1/h2 fp32 + bf16, o fp32
-static hipError_t forward_packed(hx_ctx *c, int64_t B)
+// forward on the packed batch s->xb (B rows); h1/h2 bf16 (and fp32 for the
+// backward pass when training), o fp32
+static hipError_t forward_packed(hx_ctx *c, int64_t B, bool training)
 {
     MlpState *s = c->mlp;
     hipError_t e;
     e = gemm(c->stream, (int)B, HID, s->ldx, s->xb, s->ldx, 1, s->w1b, s->ldx, 1, s->w + s->off_b1, 1,
-             s->h1, HID, s->h1b, HID);
+             training ? s->h1 : nullptr, HID, s->h1b, HID);
     if (e != hipSuccess) return e;
-    e = gemm(c->stream, (int)B, HID, HID, s->h1b, HID, 1, s->w2b, HID, 1, s->w + s->off_b2, 1, s->h2,
-             HID, s->h2b, HID);
+    e = gemm(c->stream, (int)B, HID, HID, s->h1b, HID, 1, s->w2b, HID, 1, s->w + s->off_b2, 1,
+             training ? s->h2 : nullptr, HID, s->h2b, HID);
     if (e != hipSuccess) return e;
     return gemm(c->stream, (int)B, s->n_out, HID, s->h2b, HID, 1, s->w3b, HID, 1, s->w + s->off_b3, 0,
                 s->o, s->n_out, nullptr, 0);
@@ -509,7 +592,7 @@ hx_status mlp_forward(hx_ctx *c, const float *feats, int64_t B, float *out)
     hipLaunchKernelGGL(k_pack, dim3(nb256(B * s->ldx)), dim3(256), 0, c->stream, B, s->n_in, s->ldx,
                        feats, s->xb);
     HX_HIP(c, hipGetLastError());
-    HX_HIP(c, forward_packed(c, B));
+    HX_HIP(c, forward_packed(c, B, false));
     HX_HIP(c, hipMemcpyAsync(out, s->o, 4 * (size_t)B * s->n_out, hipMemcpyDeviceToDevice, c->stream));
     return HX_OK;
 }
@@ -524,7 +607,7 @@ hx_status mlp_train(hx_ctx *c, const float *feats, const float *targets, int64_t
     const hipStream_t q = c->stream;
     hipLaunchKernelGGL(k_pack, dim3(nb256(B * s->ldx)), dim3(256), 0, q, B, s->n_in, s->ldx, feats,
                        s->xb);
-    HX_HIP(c, forward_packed(c, B));
+    HX_HIP(c, forward_packed(c, B, true));
     const int64_t tot = B * s->n_out;
     const int nbk = (int)std::min<int64_t>(1024, (tot + 255) / 256);
     hipLaunchKernelGGL(k_loss_grad, dim3(nbk), dim3(256), 0, q, tot, 1.0f / (float)tot, s->o, targets,
@@ -608,7 +691,7 @@ hx_status mlp_precondition(hx_ctx *c, const double *r, double *z, int *nonfinite
                        c->n_cells, r, c->nbr, c->coef_feat, (float *)nullptr, (int64_t)0, s->xb,
                        (int64_t)s->ldx, s->scale);
     HX_HIP(c, hipGetLastError());
-    HX_HIP(c, forward_packed(c, c->n_cells));
+    HX_HIP(c, forward_packed(c, c->n_cells, false));
     HX_HIP(c, launch_bj64(c, r, z));
     hipLaunchKernelGGL(k_add_correction, dim3((unsigned)c->n_cells), dim3(128), 0, c->stream, c->nd,
                        s->o, z);
