@@ -32,7 +32,11 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-ALG_BYTES_PER_DOF_F64 = 16.0 + 56.0 + 33.6     # x + y, cell data, face data
+def alg_bytes_per_dof(k: int) -> float:
+    """FP64 bytes per dof one application must move: x and y (16), the merged
+    cell data (7 values per Gauss point = per dof, 56) and the merged face data
+    (3 faces x 7 values x (k+1)^2 points per cell, 168/(k+1)); 105.6 at k = 4."""
+    return 16.0 + 56.0 + 3 * 7 * 8.0 / (k + 1)
 HBM_PEAK_GBS = 8000.0
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "op_apply_f64_terrain256x64x64_k4_traffic.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2505_00384_amd", "csrc", "operator.hip")
@@ -167,6 +171,10 @@ def main():
     ap.add_argument("--ny", type=int, default=64)
     ap.add_argument("--nz", type=int, default=64)
     ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--solves", choices=["all", "large"], default="all",
+                    help="'large': only the solves on the timed mesh (for profiling)")
+    ap.add_argument("--degree", type=int, default=4,
+                    help="polynomial degree (default 4, the benchmark's)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-layers", type=int, default=2)
     ap.add_argument("--fp32", action="store_true", help="also time the FP32 operator")
@@ -183,7 +191,7 @@ def main():
     import synth_inputs as si
 
     dev = torch.device("cuda:0")
-    k = 4
+    k = args.degree
     log(f"building mesh {args.nx}x{args.ny}x{args.nz}")
     mesh = si.terrain_mesh(args.nx, args.ny, args.nz, g=4)
     setup_times = {}
@@ -196,7 +204,7 @@ def main():
     y = torch.empty_like(x)
     ms = time_matvec(ctx, x, y, args.steps, args.warmup, torch)
     gdofs = n / (ms * 1e-3) / 1e9
-    achieved = ALG_BYTES_PER_DOF_F64 * n / (ms * 1e-3) / 1e9
+    achieved = alg_bytes_per_dof(k) * n / (ms * 1e-3) / 1e9
     log(f"FP64 matvec {ms:.4f} ms, {gdofs:.2f} GDoF/s, {achieved:.0f} GB/s algorithmic")
     extra = {}
     if args.fp32:
@@ -204,7 +212,7 @@ def main():
         y32 = torch.empty_like(x32)
         ms32 = time_matvec(ctx, x32, y32, args.steps, args.warmup, torch)
         extra["fp32_matvec"] = dict(ms=round(ms32, 4), gdofs=round(n / (ms32 * 1e-3) / 1e9, 3),
-                                    alg_GBs=round(ALG_BYTES_PER_DOF_F64 / 2 * n / (ms32 * 1e-3) / 1e9, 1))
+                                    alg_GBs=round(alg_bytes_per_dof(k) / 2 * n / (ms32 * 1e-3) / 1e9, 1))
         log(f"FP32 matvec {ms32:.4f} ms")
         del x32, y32
     if args.copy_calibrate:
@@ -212,7 +220,7 @@ def main():
         y.copy_(x)
         torch.cuda.synchronize()
         log(f"copy calibration: {8 * n} bytes read, {8 * n} bytes written")
-    traffic = read_traffic(n)
+    traffic = read_traffic(n) if (k == 4 and (args.nx, args.ny, args.nz) == (256, 64, 64)) else None
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic)
 
@@ -231,8 +239,10 @@ def main():
                                                          pc=hx.HX_PC_HELMHOLTZ_DIAG)),
         ]
         del y
-        solve["terrain256x64x64"] = solve_suite(hx, ctx, b, torch, forms + cg_forms, "C3")
+        solve[f"terrain{args.nx}x{args.ny}x{args.nz}"] = solve_suite(hx, ctx, b, torch,
+                                                                     forms + cg_forms, "C3")
         ctx.close()
+    if not args.no_solve and args.solves == "all":
         del b, x
         torch.cuda.empty_cache()
         m2 = si.terrain_mesh(32, 8, 16, g=4)
@@ -296,7 +306,7 @@ def main():
         "value": round(gdofs, 3), "unit": "GDoF/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 5), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"terrain-following channel {args.nx}x{args.ny}x{args.nz} cells, DG Q4, "
+        "config": {"workload": f"terrain-following channel {args.nx}x{args.ny}x{args.nz} cells, DG Q{k}, "
                                "isothermal background coefficients, SIP penalty 2",
                    "n_dofs": n, "degree": k, "geometry_degree": 4},
         "roofline": roof,

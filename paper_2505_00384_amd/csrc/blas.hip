@@ -515,6 +515,11 @@ hipError_t cg_step_pc(hx_ctx *c, int pc, T *x, T *r, const T *p, const T *q, T *
         e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
+    if (nb > 8192) {
+        // one partial sum per block of the fused block-Jacobi kernel: two stages
+        e = reduce_parts(c, c->cgpart, nb, sc + 2);
+        return e != hipSuccess ? e : reduce_parts(c, c->cgpart + ld, nb, sc + 3);
+    }
     hipLaunchKernelGGL(k_red2, dim3(2), dim3(RT), 0, c->stream, c->cgpart, nb, ld, sc + 2);
     return hipGetLastError();
 }
