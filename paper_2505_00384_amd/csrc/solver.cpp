@@ -605,7 +605,7 @@ hx_status hx_solve(hx_ctx *c, const hx_solve_params *prm, const double *b, doubl
         info->status = s;
         return s;
     }
-    // true FP64 residual is the judge
+    // the true FP64 residual decides
     const int64_t n = c->n_dofs;
     double *sc = c->red + SC_OFF;
     hx_status s2 = ensure_work(c, (size_t)n, 0);

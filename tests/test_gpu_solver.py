@@ -1,5 +1,5 @@
 """GPU Krylov solves (steps a6, a7, a8) against the oracle and the paper's
-definitions: the true FP64 residual is the judge.  Solutions are compared to
+definitions: the true FP64 residual decides.  Solutions are compared to
 the oracle's 1e-13 solve within kappa_est * rtol; iteration counts are not
 unique (CGS2 on the GPU vs modified Gram-Schmidt in the oracle)."""
 import numpy as np
