@@ -176,7 +176,7 @@ def main():
     ap.add_argument("--degree", type=int, default=4,
                     help="polynomial degree (default 4, the benchmark's)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-layers", type=int, default=2)
+    ap.add_argument("--cpu-layers", type=int, default=6)
     ap.add_argument("--fp32", action="store_true", help="also time the FP32 operator")
     ap.add_argument("--copy-calibrate", action="store_true",
                     help="also run a plain device copy of the x vector (for counter scaling)")
