@@ -363,16 +363,22 @@ hipError_t blas_mdot(hx_ctx *c, int64_t n, int m, const double *V, int64_t ldv, 
 hipError_t blas_mdot2(hx_ctx *c, int64_t n, int m, const double *V, int64_t ldv, const double *a,
                       const double *b, double *dst_a, double *dst_b)
 {
-    // two rows of partial sums per vector: 128 rows of 512 fit below the
-    // device scalar area
+    // two rows of partial sums per vector (up to 128 rows of RED_MAX); the
+    // per-block buffer of the fused CG steps holds them when it is large enough
     int nb = red_blocks(n);
-    if (nb > RED_MAX / 2) nb = RED_MAX / 2;
+    double *part = c->red;
+    int ld = RED_MAX / 2;
+    if ((int64_t)2 * 64 * RED_MAX <= 2 * (c->n_cells + 1)) {
+        part = c->cgpart;
+        ld = RED_MAX;
+    } else if (nb > RED_MAX / 2) {
+        nb = RED_MAX / 2;
+    }
     const int nch = (m + MC - 1) / MC;
-    hipLaunchKernelGGL(k_mdot2, dim3(nb, nch), dim3(RT), 0, c->stream, n, m, V, ldv, a, b, c->red,
-                       RED_MAX / 2);
-    hipLaunchKernelGGL(k_red2, dim3(m), dim3(RT), 0, c->stream, c->red, nb, RED_MAX / 2, dst_a);
-    hipLaunchKernelGGL(k_red2, dim3(m), dim3(RT), 0, c->stream, c->red + (int64_t)m * (RED_MAX / 2),
-                       nb, RED_MAX / 2, dst_b);
+    hipLaunchKernelGGL(k_mdot2, dim3(nb, nch), dim3(RT), 0, c->stream, n, m, V, ldv, a, b, part, ld);
+    hipLaunchKernelGGL(k_red2, dim3(m), dim3(RT), 0, c->stream, part, nb, ld, dst_a);
+    hipLaunchKernelGGL(k_red2, dim3(m), dim3(RT), 0, c->stream, part + (int64_t)m * ld, nb, ld,
+                       dst_b);
     return hipGetLastError();
 }
 
