@@ -368,7 +368,12 @@ hipError_t blas_mdot2(hx_ctx *c, int64_t n, int m, const double *V, int64_t ldv,
     int nb = red_blocks(n);
     double *part = c->red;
     int ld = RED_MAX / 2;
-    if ((int64_t)2 * 64 * RED_MAX <= 2 * (c->n_cells + 1)) {
+    if ((int64_t)2 * 64 * 2 * RED_MAX <= 2 * (c->n_cells + 1)) {
+        part = c->cgpart;
+        ld = 2 * RED_MAX;
+        const int64_t want = (n + RT * 8 - 1) / (RT * 8);
+        nb = (int)(want < 2 * RED_MAX ? (want < 1 ? 1 : want) : 2 * RED_MAX);
+    } else if ((int64_t)2 * 64 * RED_MAX <= 2 * (c->n_cells + 1)) {
         part = c->cgpart;
         ld = RED_MAX;
     } else if (nb > RED_MAX / 2) {
@@ -389,9 +394,15 @@ hipError_t blas_dcgs_step(hx_ctx *c, int64_t n, int j, double *V, int64_t ldv, d
                           double *sc)
 {
     hipLaunchKernelGGL(k_dcgs_coef, dim3(1), dim3(64), 0, c->stream, j, sc);
-    const int nb = red_blocks(n);
-    hipLaunchKernelGGL(k_dcgs_update, dim3(nb), dim3(RT), 0, c->stream, n, j, V, ldv, sc, w, c->red);
-    hipLaunchKernelGGL(k_red2, dim3(1), dim3(RT), 0, c->stream, c->red, nb, RED_MAX, sc + 128);
+    int nb = red_blocks(n);
+    double *part = c->red;
+    if (2 * RED_MAX <= 2 * (c->n_cells + 1)) {
+        const int64_t want = (n + RT * 8 - 1) / (RT * 8);
+        nb = (int)(want < 2 * RED_MAX ? (want < 1 ? 1 : want) : 2 * RED_MAX);
+        part = c->cgpart;
+    }
+    hipLaunchKernelGGL(k_dcgs_update, dim3(nb), dim3(RT), 0, c->stream, n, j, V, ldv, sc, w, part);
+    hipLaunchKernelGGL(k_red2, dim3(1), dim3(RT), 0, c->stream, part, nb, RED_MAX, sc + 128);
     hipLaunchKernelGGL(k_scale_copy, dim3(nb256(n)), dim3(256), 0, c->stream, n, sc + 128, 2, w,
                        V + (int64_t)(j + 1) * ldv);
     return hipGetLastError();
