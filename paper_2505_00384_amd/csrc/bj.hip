@@ -185,20 +185,28 @@ k_bj(const T *__restrict__ rin, T *__restrict__ z, const T *__restrict__ S, cons
         for (int j = 0; j < N; ++j) sR[lc][a + N * j + NF * b] = w[j];
     }
     __syncthreads();
-    // S_x along x: thread (j=a, l=b), write out
+    // S_x along x: thread (j=a, l=b); the output goes back through LDS so
+    // that the stores are contiguous across threads
     if (active) {
 #pragma unroll
         for (int m = 0; m < N; ++m) v[m] = sR[lc][m + N * a + NF * b];
-        const int64_t o = cid * ND + N * a + NF * b;
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             T s = 0;
 #pragma unroll
             for (int m = 0; m < N; ++m) s += sS[lc][0][i * N + m] * v[m];
-            z[o + i] = s;
+            w[i] = s;
             acc_rz += (double)rp[i] * (double)s;
         }
     }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) sR[lc][i + N * a + NF * b] = w[i];
+    }
+    __syncthreads();
+    if (active)
+        for (int e = tt; e < ND; e += NF) z[cid * ND + e] = sR[lc][e];
     if (FUSE) {
         __shared__ double sh2[2 * (Cfg<N>::NT / 64)];
         block_sum2<Cfg<N>::NT>(acc_rz, acc_rr, sh2);
