@@ -58,6 +58,9 @@ def lib():
         L.or_apply.argtypes = [pp, C.c_int, dp, dp]
         L.or_assemble_dense.argtypes = [pp, C.c_int, dp]
         L.or_cell_diagonal.argtypes = [pp, C.c_int, dp]
+        L.or_mass_block.argtypes = [pp, C.c_long, dp]
+        L.or_mass_block_apply.argtypes = [pp, dp, dp]
+        L.or_mass_block_apply.restype = C.c_int
         L.or_apply_cells.argtypes = [pp, C.c_int, C.c_void_p, C.c_long, dp, dp]
         L.or_bj_cell_data.argtypes = [pp, C.c_long, dp, dp, dp, dp]
         L.or_bj_sep_block.argtypes = [pp, C.c_long, dp]
@@ -210,6 +213,20 @@ class Problem:
         d = np.zeros(self.n_dofs)
         lib().or_cell_diagonal(self._s(), int(bool(stiff)), _dp(d))
         return d
+
+    def mass_block(self, c: int):
+        """The alpha-weighted mass matrix of cell c (direct quadrature)."""
+        M = np.zeros(self.nd * self.nd)
+        lib().or_mass_block(self._s(), int(c), _dp(M))
+        return M.reshape(self.nd, self.nd)
+
+    def mass_block_apply(self, r):
+        """z = M^{-1} r with M the block-diagonal alpha-weighted mass matrix."""
+        r = np.ascontiguousarray(r, dtype=np.float64)
+        z = np.zeros(self.n_dofs)
+        if lib().or_mass_block_apply(self._s(), _dp(r), _dp(z)):
+            raise FloatingPointError("mass block not positive definite")
+        return z
 
     # block Jacobi ----------------------------------------------------------
     def bj_cell_data(self, c: int):

@@ -850,3 +850,51 @@ int or_bj_sep_apply(const or_prob *p, const double *rv, double *zv)
     }
     return bad;
 }
+
+/* ------------------------------------------------------------------------ */
+/* cell mass blocks (the block-diagonal matrix whose fast inverse section 3.3 */
+/* builds from 1-D factors)                                                  */
+/* ------------------------------------------------------------------------ */
+
+/* M_K[i][j] = sum_q w_q detJ_q alpha_q phi_i phi_j, by direct quadrature */
+void or_mass_block(const or_prob *p, long c, double *Mb)
+{
+    ref_t r; ref_init(&r, p->k, p->g);
+    const int nd = r.nd, n = r.n;
+    double *phi = malloc(sizeof(double) * nd);
+    double (*dphi)[3] = malloc(sizeof(double) * 3 * nd);
+    for (int a = 0; a < nd * nd; ++a) Mb[a] = 0.0;
+    const double *X = cell_nodes(p, &r, c);
+    for (int l = 0; l < n; ++l)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                double xi[3] = {r.xq[i], r.xq[j], r.xq[l]}, x[3], J[3][3];
+                geom_at(&r, X, xi, x, J);
+                double w = r.wq[i] * r.wq[j] * r.wq[l] * det3(J);
+                basis_at(&r, xi, phi, dphi);
+                double al = field_at(phi, p->alpha + c * nd, nd);
+                for (int a = 0; a < nd; ++a)
+                    for (int b = 0; b < nd; ++b) Mb[a * nd + b] += w * al * phi[a] * phi[b];
+            }
+    free(phi); free(dphi);
+}
+
+/* z = M_K^{-1} r on every cell (dense Cholesky); nonzero if a block is not
+ * positive definite */
+int or_mass_block_apply(const or_prob *p, const double *rv, double *zv)
+{
+    int nd = (p->k + 1) * (p->k + 1) * (p->k + 1);
+    int bad = 0;
+#pragma omp parallel reduction(|:bad)
+    {
+        double *Mb = malloc(sizeof(double) * nd * nd);
+#pragma omp for schedule(dynamic, 4)
+        for (long c = 0; c < p->n_cells; ++c) {
+            or_mass_block(p, c, Mb);
+            for (int a = 0; a < nd; ++a) zv[c * nd + a] = rv[c * nd + a];
+            bad |= chol_solve(nd, Mb, zv + c * nd);
+        }
+        free(Mb);
+    }
+    return bad;
+}

@@ -38,5 +38,7 @@ void or_bj_cell_data(const or_prob *p, long c, double ell[3], double *abar,
                      double *bbar, double sig[3][2]);
 void or_bj_sep_block(const or_prob *p, long c, double *Ab);
 int  or_bj_sep_apply(const or_prob *p, const double *r, double *z);
+void or_mass_block(const or_prob *p, long c, double *Mb);
+int  or_mass_block_apply(const or_prob *p, const double *r, double *z);
 
 #endif

@@ -75,3 +75,45 @@ def test_equals_unit_vector_matrix_of_cell_operator(mesh, k):
     dm = p.cell_diagonal(stiff=False)
     np.testing.assert_allclose(dm, np.diag(A0), rtol=1e-12, atol=1e-14 * np.abs(dm).max())
     assert (dm > 0).all() and (d > dm).all()
+
+
+# ---------------------------------------------------------------------------
+# cell mass blocks: the block-diagonal matrix section 3.3 inverts by its
+# tensor-product factors
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("k,nc", [(2, 2), (4, 1), (3, 2)])
+def test_mass_block_cartesian_closed_form(k, nc):
+    alpha, h = 1.3, 1.0 / nc
+    p = oracle.Problem(si.cube_mesh(nc), k)
+    p.set_coefficient_functions(*si.const_coefficients(alpha, 0.2))
+    n = k + 1
+    xq, wq, xl = _np_rules(n)
+    M1 = np.zeros((n, n))
+    for x, w in zip(xq, wq):
+        v, _ = _np_lagrange(xl, x)
+        M1 += w * np.outer(v, v)
+    ref = alpha * h ** 3 * np.kron(M1, np.kron(M1, M1))   # z slowest, x fastest
+    for c in range(p.n_cells):
+        np.testing.assert_allclose(p.mass_block(c), ref, rtol=1e-13, atol=1e-15 * np.abs(ref).max())
+    r = si.random_vector(p.n_dofs, 1)
+    z = p.mass_block_apply(r)
+    for c in range(p.n_cells):
+        s = slice(c * n ** 3, (c + 1) * n ** 3)
+        np.testing.assert_allclose(ref @ z[s], r[s], rtol=1e-10, atol=1e-12 * np.abs(r).max())
+
+
+def test_mass_block_is_the_cell_operator_block_without_stiffness():
+    msh = si.terrain_mesh(2, 1, 2, g=2)
+    fa, fb = si.terrain_coefficients()
+    p = oracle.Problem(msh, 2)
+    x, y, z = (lambda t: t)(p.dof_coords())
+    p.set_coefficients(fa(x, y, z), np.zeros(p.n_dofs))
+    A0 = p.matrix_by_unit_vectors(oracle.OR_CELL)
+    nd = p.nd
+    for c in range(p.n_cells):
+        s = slice(c * nd, (c + 1) * nd)
+        blk = A0[s, s]
+        np.testing.assert_allclose(p.mass_block(c), blk, rtol=1e-12, atol=1e-14 * np.abs(blk).max())
+        # nothing outside the cell's own block
+        assert np.abs(np.delete(A0[s], np.arange(c * nd, (c + 1) * nd), axis=1)).max() == 0.0
