@@ -70,7 +70,8 @@ typedef enum {
     HX_PC_BLOCK_JACOBI = 1,   /* separable cell block, fast-diagonalisation inverse */
     HX_PC_LEARNED = 2,        /* block Jacobi + per-cell network correction */
     HX_PC_HELMHOLTZ_DIAG = 3, /* inverse diagonal of the volume terms (mass + stiffness) */
-    HX_PC_MASS_DIAG = 4       /* inverse diagonal of the mass term alone */
+    HX_PC_MASS_DIAG = 4,      /* inverse diagonal of the mass term alone */
+    HX_PC_MASS_BLOCK = 5      /* exact inverse of the alpha-weighted cell mass blocks */
 } hx_pc;
 
 /* Create a context on `device` (HIP ordinal) whose kernels run on
@@ -154,7 +155,13 @@ hx_status hx_residual(hx_ctx *c, const double *b, const double *x, double *r);
  *   d_i = sum_q w_q detJ_q [alpha_q phi_i^2 + beta_q |J^-T grad phi_i|^2],
  * face terms left out; HX_PC_MASS_DIAG: its "internal-energy" variant, the
  * inverse of the mass diagonal alone.  Both diagonals are formed by
- * hx_set_coefficients.  HX_PC_NONE copies r.  r and z must not alias. */
+ * hx_set_coefficients.  HX_PC_MASS_BLOCK: the exact inverse of the
+ * block-diagonal mass matrix with entries sum_q w_q detJ_q alpha_q phi_i phi_j
+ * (curved cells and variable alpha included), by the tensor-product form of
+ * section 3.3, M_K^{-1} = B3^{-1} diag(1/(w detJ alpha)) B3^{-T} with B3 the
+ * square interpolation from the (k+1)^3 nodes to the (k+1)^3 Gauss points;
+ * it reads the first component of the merged cell data.  HX_PC_NONE copies
+ * r.  r and z must not alias. */
 hx_status hx_apply_preconditioner(hx_ctx *c, hx_pc kind, hx_prec prec,
                                   const void *r, void *z);
 

@@ -299,6 +299,10 @@ hx_status hx_apply_preconditioner(hx_ctx *c, hx_pc kind, hx_prec prec, const voi
         else HX_HIP(c, launch_diag32(c, which, (const float *)r, (float *)z));
         return HX_OK;
     }
+    case HX_PC_MASS_BLOCK:
+        if (prec == HX_F64) HX_HIP(c, launch_massinv64(c, (const double *)r, (double *)z));
+        else HX_HIP(c, launch_massinv32(c, (const float *)r, (float *)z));
+        return HX_OK;
     case HX_PC_LEARNED: {
         if (prec != HX_F64) return fail(c, HX_ERR_ARG, "learned preconditioner is FP64-in/out");
         int nonfinite = 0;

@@ -14,6 +14,7 @@
 // each vector once.
 #include "common.hpp"
 
+#include <cstddef>
 #include <type_traits>
 
 namespace hx {
@@ -53,7 +54,8 @@ __device__ __forceinline__ void block_sum2(double &u, double &v, double *sh)
 }
 
 // FUSE: one conjugate-gradient step around the preconditioner, with the
-// step length a = sc[0] / sc[1] (r.z over p.q) read from device memory:
+// step length a = sc[0] / sc[1] (r.z over p.q) read from device memory (0
+// when p.q is exactly 0: a step in flight after exact convergence):
 //   x += a p,  r -= a q,  z = M^{-1} r,
 // and per-block partial sums of r.z and r.r written to part[blk] and
 // part[ld + blk].  Without FUSE, plain z = M^{-1} r.
@@ -84,7 +86,7 @@ k_bj(const T *__restrict__ rin, T *__restrict__ z, const T *__restrict__ S, cons
 
     double acc_rr = 0.0, acc_rz = 0.0;
     if (FUSE && active) {
-        const T al = (T)(sc[0] / sc[1]);
+        const T al = (T)(sc[1] != 0.0 ? sc[0] / sc[1] : 0.0);
         for (int e = tt; e < ND; e += NF) {
             const int64_t gi = cid * ND + e;
             const T rv = rw[gi] - al * q[gi];
@@ -308,6 +310,232 @@ hipError_t launch_diag32(hx_ctx *c, int which, const float *r, float *z)
     hipLaunchKernelGGL(k_diag<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, n,
                        c->dg32 + (int64_t)which * n, r, z);
     return hipGetLastError();
+}
+
+namespace {
+// z = M^{-1} r for the alpha-weighted cell mass blocks
+//   M_K = B3^T diag(m_K) B3,  B3 = B (x) B (x) B,
+// B the square (k+1) x (k+1) interpolation from the nodes to the Gauss points
+// and m_K the quadrature weights times alpha |det J| (component 0 of the
+// merged cell data), so M_K^{-1} = B3^{-1} diag(1/m_K) B3^{-T}: the exact
+// inverse by tensor-product sweeps (section 3.3, the inverse of the mass
+// matrix as S^-T J^-1 S^-1 with S a Kronecker product of 1-D matrices), valid
+// for curved cells and variable alpha.  Same thread mapping as k_bj, with the
+// one 1-D matrix shared by all cells.
+// FUSE: the conjugate-gradient step around it, as in k_bj.
+template <int N, typename T, bool FUSE>
+__global__ void __launch_bounds__(Cfg<N>::NT)
+k_massinv(const T *__restrict__ rin, T *__restrict__ z, const T *__restrict__ cell,
+          const double *__restrict__ Binv, int n_cells, int nwg, T *x, T *rw,
+          const T *__restrict__ p, const T *__restrict__ q, const double *__restrict__ sc,
+          double *part, int ld)
+{
+    const T *r = FUSE ? rw : rin;
+    constexpr int NF = Cfg<N>::NF, ND = Cfg<N>::ND, CPB = Cfg<N>::CPB;
+    __shared__ T sR[CPB][ND];
+    __shared__ T sB[NF];                 // sB[i*N+q] = (B^{-1})_{iq}
+
+    const int bid = blockIdx.x;
+    const int q8 = nwg / NXCD, r8 = nwg % NXCD, xcd = bid % NXCD;
+    const int wg = xcd * q8 + (xcd < r8 ? xcd : r8) + bid / NXCD;
+    const int t = threadIdx.x;
+    const int lc0 = t / NF;
+    const bool slot = lc0 < CPB;
+    const int lc = slot ? lc0 : 0;
+    const int tt = t - lc0 * NF;
+    const int a = tt % N, b = tt / N;
+    const int64_t cid = (int64_t)wg * CPB + lc;
+    const bool active = slot && cid < n_cells;
+
+    for (int e = t; e < NF; e += blockDim.x) sB[e] = (T)Binv[e];
+    T mq[N], v[N], w[N], rp[N];
+    double acc_rr = 0.0, acc_rz = 0.0;
+    if (FUSE && active) {
+        const T al = (T)(sc[1] != 0.0 ? sc[0] / sc[1] : 0.0);
+        for (int e = tt; e < ND; e += NF) {
+            const int64_t gi = cid * ND + e;
+            const T rv = rw[gi] - al * q[gi];
+            x[gi] += al * p[gi];
+            rw[gi] = rv;
+            sR[lc][e] = rv;
+            acc_rr += (double)rv * (double)rv;
+        }
+    } else if (active) {
+        for (int e = tt; e < ND; e += NF) sR[lc][e] = r[cid * ND + e];
+    }
+    if (active) {
+#pragma unroll
+        for (int m = 0; m < N; ++m) mq[m] = cell[cid * 7 * ND + a + N * b + NF * m];
+    }
+    __syncthreads();
+    // B^{-T} along x: thread (j=a, l=b); rp keeps the residual pencil, at the
+    // positions of the output pencil written at the end
+    if (active) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] = rp[i] = sR[lc][i + N * a + NF * b];
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+            T s = 0;
+#pragma unroll
+            for (int i = 0; i < N; ++i) s += sB[i * N + m] * v[i];
+            w[m] = s;
+        }
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+        for (int m = 0; m < N; ++m) sR[lc][m + N * a + NF * b] = w[m];
+    }
+    __syncthreads();
+    // B^{-T} along y: thread (qx=a, l=b)
+    if (active) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) v[j] = sR[lc][a + N * j + NF * b];
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+            T s = 0;
+#pragma unroll
+            for (int j = 0; j < N; ++j) s += sB[j * N + m] * v[j];
+            w[m] = s;
+        }
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+        for (int m = 0; m < N; ++m) sR[lc][a + N * m + NF * b] = w[m];
+    }
+    __syncthreads();
+    // B^{-T} along z, 1/m at the Gauss points, B^{-1} along z: thread (qx=a, qy=b);
+    // the Gauss point (a, b, m) is entry a + N b + N^2 m of the cell data
+    if (active) {
+#pragma unroll
+        for (int l = 0; l < N; ++l) v[l] = sR[lc][a + N * b + NF * l];
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+            T s = 0;
+#pragma unroll
+            for (int l = 0; l < N; ++l) s += sB[l * N + m] * v[l];
+            w[m] = s / mq[m];
+        }
+#pragma unroll
+        for (int l = 0; l < N; ++l) {
+            T s = 0;
+#pragma unroll
+            for (int m = 0; m < N; ++m) s += sB[l * N + m] * w[m];
+            v[l] = s;
+        }
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+        for (int l = 0; l < N; ++l) sR[lc][a + N * b + NF * l] = v[l];
+    }
+    __syncthreads();
+    // B^{-1} along y: thread (qx=a, l=b)
+    if (active) {
+#pragma unroll
+        for (int m = 0; m < N; ++m) v[m] = sR[lc][a + N * m + NF * b];
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            T s = 0;
+#pragma unroll
+            for (int m = 0; m < N; ++m) s += sB[j * N + m] * v[m];
+            w[j] = s;
+        }
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) sR[lc][a + N * j + NF * b] = w[j];
+    }
+    __syncthreads();
+    // B^{-1} along x: thread (j=a, l=b), output through LDS for contiguous stores
+    if (active) {
+#pragma unroll
+        for (int m = 0; m < N; ++m) v[m] = sR[lc][m + N * a + NF * b];
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            T s = 0;
+#pragma unroll
+            for (int m = 0; m < N; ++m) s += sB[i * N + m] * v[m];
+            w[i] = s;
+            acc_rz += (double)rp[i] * (double)s;
+        }
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) sR[lc][i + N * a + NF * b] = w[i];
+    }
+    __syncthreads();
+    if (active)
+        for (int e = tt; e < ND; e += NF) z[cid * ND + e] = sR[lc][e];
+    if (FUSE) {
+        __shared__ double sh2[2 * (Cfg<N>::NT / 64)];
+        block_sum2<Cfg<N>::NT>(acc_rz, acc_rr, sh2);
+        if (threadIdx.x == 0) {
+            part[bid] = acc_rz;
+            part[ld + bid] = acc_rr;
+        }
+    }
+}
+
+template <int N, typename T>
+hipError_t massinv_n(hx_ctx *c, const T *r, T *z, const CgArgs<T> *cg, int *nblk)
+{
+    const int cpb = Cfg<N>::CPB;
+    const int nwg = (int)((c->n_cells + cpb - 1) / cpb);
+    const bool dbl = std::is_same<T, double>::value;
+    const T *cell = dbl ? (const T *)c->cell64 : (const T *)c->cell32;
+    const double *Binv = reinterpret_cast<const double *>(reinterpret_cast<const char *>(c->ref) +
+                                                          offsetof(RefTab64, Binv));
+    if (nblk) *nblk = nwg;
+    if (cg)
+        hipLaunchKernelGGL((k_massinv<N, T, true>), dim3(nwg), dim3(Cfg<N>::NT), 0, c->stream, r, z,
+                           cell, Binv, (int)c->n_cells, nwg, cg->x, cg->r, cg->p, cg->q, cg->sc,
+                           c->cgpart, (int)c->n_cells + 1);
+    else
+        hipLaunchKernelGGL((k_massinv<N, T, false>), dim3(nwg), dim3(Cfg<N>::NT), 0, c->stream, r,
+                           z, cell, Binv, (int)c->n_cells, nwg, (T *)nullptr, (T *)nullptr,
+                           (const T *)nullptr, (const T *)nullptr, (const double *)nullptr,
+                           (double *)nullptr, 0);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t massinv_dispatch(hx_ctx *c, const T *r, T *z, const CgArgs<T> *cg = nullptr,
+                            int *nblk = nullptr)
+{
+    switch (c->n) {
+    case 2: return massinv_n<2, T>(c, r, z, cg, nblk);
+    case 3: return massinv_n<3, T>(c, r, z, cg, nblk);
+    case 4: return massinv_n<4, T>(c, r, z, cg, nblk);
+    case 5: return massinv_n<5, T>(c, r, z, cg, nblk);
+    case 6: return massinv_n<6, T>(c, r, z, cg, nblk);
+    case 7: return massinv_n<7, T>(c, r, z, cg, nblk);
+    case 8: return massinv_n<8, T>(c, r, z, cg, nblk);
+    default: return hipErrorInvalidValue;
+    }
+}
+}  // namespace
+
+hipError_t launch_massinv64(hx_ctx *c, const double *r, double *z) { return massinv_dispatch<double>(c, r, z); }
+hipError_t launch_massinv32(hx_ctx *c, const float *r, float *z) { return massinv_dispatch<float>(c, r, z); }
+
+hipError_t launch_cg_massinv64(hx_ctx *c, double *x, double *r, const double *p, const double *q,
+                               double *z, const double *sc, int *nblk)
+{
+    CgArgs<double> a;
+    a.x = x; a.r = r; a.p = p; a.q = q; a.sc = sc;
+    return massinv_dispatch<double>(c, r, z, &a, nblk);
+}
+
+hipError_t launch_cg_massinv32(hx_ctx *c, float *x, float *r, const float *p, const float *q,
+                               float *z, const double *sc, int *nblk)
+{
+    CgArgs<float> a;
+    a.x = x; a.r = r; a.p = p; a.q = q; a.sc = sc;
+    return massinv_dispatch<float>(c, r, z, &a, nblk);
 }
 
 }  // namespace hx

@@ -265,7 +265,7 @@ __global__ void k_cg_x(int64_t n, float *x, float *r, const float *__restrict__ 
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const float a = (float)(sc[0] / sc[1]);
+    const float a = (float)(sc[1] != 0.0 ? sc[0] / sc[1] : 0.0);
     x[i] += a * p[i];
     r[i] -= a * q[i];
 }
@@ -276,7 +276,7 @@ __global__ void k_cg_p(int64_t n, const float *__restrict__ z, float *p,
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const float bt = (float)(sc[2] / sc[0]);
+    const float bt = (float)(sc[0] != 0.0 ? sc[2] / sc[0] : 0.0);
     p[i] = z[i] + bt * p[i];
 }
 
@@ -287,7 +287,8 @@ __global__ void k_shift(double *sc)
 
 // ---- fused CG steps, FP64 or FP32 vectors, scalars on the device:
 // sc[0] = r.z (current), sc[1] = p.q, sc[2] = new r.z, sc[3] = new r.r.
-// x += a p, r -= a q with a = sc[0] / sc[1], z = dinv r (or z = r), and the
+// x += a p, r -= a q with a = sc[0] / sc[1] (0 when p.q is exactly 0: the
+// step in flight after exact convergence), z = dinv r (or z = r), and the
 // per-block partial sums of r.z and r.r in part[blk], part[ld + blk].
 template <typename T>
 __global__ void __launch_bounds__(RT) k_cg_elem(int64_t n, T *x, T *r, const T *__restrict__ p,
@@ -296,7 +297,7 @@ __global__ void __launch_bounds__(RT) k_cg_elem(int64_t n, T *x, T *r, const T *
                                                 const double *__restrict__ sc, double *part, int ld)
 {
     __shared__ double sh[RT / 64];
-    const T al = (T)(sc[0] / sc[1]);
+    const T al = (T)(sc[1] != 0.0 ? sc[0] / sc[1] : 0.0);
     double rz = 0.0, rr = 0.0;
     const int64_t stride = (int64_t)gridDim.x * RT;
     for (int64_t i = blockIdx.x * (int64_t)RT + threadIdx.x; i < n; i += stride) {
@@ -322,7 +323,7 @@ __global__ void k_cg_pt(int64_t n, const T *__restrict__ z, T *p, const double *
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const T bt = (T)(sc[2] / sc[0]);
+    const T bt = (T)(sc[0] != 0.0 ? sc[2] / sc[0] : 0.0);
     p[i] = z[i] + bt * p[i];
 }
 
@@ -505,8 +506,8 @@ hipError_t reduce_parts(hx_ctx *c, const double *part, int64_t n, double *dst)
     return hipGetLastError();
 }
 
-// One fused CG step around the preconditioner pc (none, block Jacobi or a
-// diagonal kind): x += a p, r -= a q, z = M^{-1} r, sc[2] = r.z, sc[3] = r.r.
+// One fused CG step around the preconditioner pc (none, block Jacobi, the
+// cell mass blocks or a diagonal kind): x += a p, r -= a q, z = M^{-1} r, sc[2] = r.z, sc[3] = r.r.
 template <typename T>
 hipError_t cg_step_pc(hx_ctx *c, int pc, T *x, T *r, const T *p, const T *q, T *z, double *sc)
 {
@@ -520,6 +521,11 @@ hipError_t cg_step_pc(hx_ctx *c, int pc, T *x, T *r, const T *p, const T *q, T *
                                  (double *)z, sc, &nb)
                 : launch_cg_bj32(c, (float *)x, (float *)r, (const float *)p, (const float *)q,
                                  (float *)z, sc, &nb);
+    } else if (pc == HX_PC_MASS_BLOCK) {
+        e = dbl ? launch_cg_massinv64(c, (double *)x, (double *)r, (const double *)p,
+                                      (const double *)q, (double *)z, sc, &nb)
+                : launch_cg_massinv32(c, (float *)x, (float *)r, (const float *)p, (const float *)q,
+                                      (float *)z, sc, &nb);
     } else {
         const T *dinv = nullptr;
         if (pc == HX_PC_HELMHOLTZ_DIAG || pc == HX_PC_MASS_DIAG) {
@@ -533,7 +539,7 @@ hipError_t cg_step_pc(hx_ctx *c, int pc, T *x, T *r, const T *p, const T *q, T *
     }
     if (e != hipSuccess) return e;
     if (nb > 8192) {
-        // one partial sum per block of the fused block-Jacobi kernel: two stages
+        // one partial sum per block of the fused cell-block kernels: two stages
         e = reduce_parts(c, c->cgpart, nb, sc + 2);
         return e != hipSuccess ? e : reduce_parts(c, c->cgpart + ld, nb, sc + 3);
     }

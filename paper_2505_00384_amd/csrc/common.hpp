@@ -25,6 +25,7 @@ struct RefTab64 {
     double M[MAXN * MAXN];                 // 1-D reference mass
     double L0[MAXN * MAXN];                // 1-D reference stiffness
     double Cinv[MAXN * MAXN];              // inverse Cholesky factor of M (lower)
+    double Binv[MAXN * MAXN];              // Binv[i*n+q]: inverse of B (n points = n nodes)
 };
 
 void sym_eig(int n, double *a, double *w, double *v);
@@ -119,6 +120,14 @@ hipError_t launch_geofac(hx_ctx *c);
 hipError_t launch_cell_diag(hx_ctx *c);
 hipError_t launch_diag64(hx_ctx *c, int which, const double *r, double *z);
 hipError_t launch_diag32(hx_ctx *c, int which, const float *r, float *z);
+// z = M^{-1} r, M the block-diagonal alpha-weighted mass matrix (fast
+// tensor-product inverse)
+hipError_t launch_massinv64(hx_ctx *c, const double *r, double *z);
+hipError_t launch_massinv32(hx_ctx *c, const float *r, float *z);
+hipError_t launch_cg_massinv64(hx_ctx *c, double *x, double *r, const double *p, const double *q,
+                               double *z, const double *sc, int *nblk);
+hipError_t launch_cg_massinv32(hx_ctx *c, float *x, float *r, const float *p, const float *q,
+                               float *z, const double *sc, int *nblk);
 
 // operator: y = A x, or y = b - A x when b != nullptr
 hipError_t launch_apply64(hx_ctx *c, const double *x, double *y, const double *b);

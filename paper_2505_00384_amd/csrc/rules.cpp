@@ -6,6 +6,7 @@
 //
 // Dof nodes are the (k+1) Gauss-Lobatto points (section 2 of the paper);
 // quadrature is (k+1)-point Gauss-Legendre (section 3.3).
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -217,6 +218,27 @@ void build_ref_tables(int n, RefTab64 &t)
             for (int k = 0; k < i; ++k) r -= C[i * n + k] * t.Cinv[k * n + col];
             t.Cinv[i * n + col] = r / C[i * n + i];
         }
+    // Binv = B^{-1} (B maps nodal values to the n Gauss points, so it is
+    // square): Gauss-Jordan elimination with partial pivoting
+    double W[MAXN][2 * MAXN];
+    for (int q = 0; q < n; ++q)
+        for (int i = 0; i < 2 * n; ++i) W[q][i] = i < n ? t.B[q * n + i] : (i - n == q ? 1.0 : 0.0);
+    for (int col = 0; col < n; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < n; ++r)
+            if (std::fabs(W[r][col]) > std::fabs(W[piv][col])) piv = r;
+        if (piv != col)
+            for (int i = 0; i < 2 * n; ++i) std::swap(W[col][i], W[piv][i]);
+        const double d = W[col][col];
+        for (int i = 0; i < 2 * n; ++i) W[col][i] /= d;
+        for (int r = 0; r < n; ++r)
+            if (r != col) {
+                const double f = W[r][col];
+                for (int i = 0; i < 2 * n; ++i) W[r][i] -= f * W[col][i];
+            }
+    }
+    for (int i = 0; i < n; ++i)
+        for (int q = 0; q < n; ++q) t.Binv[i * n + q] = W[i][n + q];
 }
 
 }  // namespace hx

@@ -94,7 +94,8 @@ hx_status ensure_work(hx_ctx *c, size_t n64, size_t n32)
 }
 
 // inner FP32 PCG for `iters` iterations on A32 z = v (FP64 in/out) with the
-// FP32 form of preconditioner pc (block Jacobi, a diagonal kind or none);
+// FP32 form of preconditioner pc (block Jacobi, the cell mass blocks, a
+// diagonal kind or none);
 // scalars on the device, each step fused around the preconditioner (one pass
 // over x, r, p, q and z).  w32: 5 float vectors.
 hx_status inner_fp32(hx_ctx *c, int pc, const double *v, double *z, float *w32, int iters,
@@ -109,6 +110,7 @@ hx_status inner_fp32(hx_ctx *c, int pc, const double *v, double *z, float *w32, 
     case HX_PC_BLOCK_JACOBI: HX_HIP(c, launch_bj32(c, r, zz)); break;
     case HX_PC_HELMHOLTZ_DIAG: HX_HIP(c, launch_diag32(c, 0, r, zz)); break;
     case HX_PC_MASS_DIAG: HX_HIP(c, launch_diag32(c, 1, r, zz)); break;
+    case HX_PC_MASS_BLOCK: HX_HIP(c, launch_massinv32(c, r, zz)); break;
     default:
         HX_HIP(c, hipMemcpyAsync(zz, r, sizeof(float) * n, hipMemcpyDeviceToDevice, c->stream));
     }
@@ -139,6 +141,7 @@ hx_status precondition(hx_ctx *c, int pc, int mixed, int inner_iters, const doub
     case HX_PC_LEARNED: return mlp_precondition(c, v, z, nonfinite);
     case HX_PC_HELMHOLTZ_DIAG: HX_HIP(c, launch_diag64(c, 0, v, z)); return HX_OK;
     case HX_PC_MASS_DIAG: HX_HIP(c, launch_diag64(c, 1, v, z)); return HX_OK;
+    case HX_PC_MASS_BLOCK: HX_HIP(c, launch_massinv64(c, v, z)); return HX_OK;
     default: return fail(c, HX_ERR_ARG, "unknown preconditioner %d", pc);
     }
 }
@@ -589,7 +592,7 @@ hx_status hx_solve(hx_ctx *c, const hx_solve_params *prm, const double *b, doubl
         return fail(c, HX_ERR_ARG, "restart must be in 1..63");
     if (prm->orth != 0 && prm->orth != 1) return fail(c, HX_ERR_ARG, "orth must be 0 or 1");
     if (!(prm->rtol > 0.0) || prm->max_iter < 1) return fail(c, HX_ERR_ARG, "bad rtol/max_iter");
-    if (prm->pc < HX_PC_NONE || prm->pc > HX_PC_MASS_DIAG) return fail(c, HX_ERR_ARG, "bad pc");
+    if (prm->pc < HX_PC_NONE || prm->pc > HX_PC_MASS_BLOCK) return fail(c, HX_ERR_ARG, "bad pc");
     if (prm->method == 0 && (prm->pc == HX_PC_LEARNED || prm->mixed))
         return fail(c, HX_ERR_ARG, "CG needs a fixed SPD preconditioner; use FGMRES");
     if (prm->mixed && prm->inner_iters < 1) return fail(c, HX_ERR_ARG, "inner_iters must be >= 1");
