@@ -61,6 +61,8 @@ def lib():
         L.or_mass_block.argtypes = [pp, C.c_long, dp]
         L.or_mass_block_apply.argtypes = [pp, dp, dp]
         L.or_mass_block_apply.restype = C.c_int
+        L.or_grad_apply.argtypes = [pp, C.c_double, dp, dp]
+        L.or_div_apply.argtypes = [pp, C.c_double, dp, dp, dp]
         L.or_apply_cells.argtypes = [pp, C.c_int, C.c_void_p, C.c_long, dp, dp]
         L.or_bj_cell_data.argtypes = [pp, C.c_long, dp, dp, dp, dp]
         L.or_bj_sep_block.argtypes = [pp, C.c_long, dp]
@@ -228,6 +230,24 @@ class Problem:
             raise FloatingPointError("mass block not positive definite")
         return z
 
+    # velocity-pressure coupling -------------------------------------------
+    def grad_apply(self, p, tau: float = 1.0):
+        """B p (pressure gradient with central flux, own trace on boundary
+        faces), scaled by tau: [3, n_dofs]."""
+        p = np.ascontiguousarray(p, dtype=np.float64)
+        u3 = np.zeros(3 * self.n_dofs)
+        lib().or_grad_apply(self._s(), float(tau), _dp(p), _dp(u3))
+        return u3.reshape(3, self.n_dofs)
+
+    def div_apply(self, u3, hr, tau: float = 1.0):
+        """C u (divergence of hr u with central flux, no boundary flux),
+        scaled by tau; u3 is [3, n_dofs], hr a nodal field."""
+        u3 = np.ascontiguousarray(u3, dtype=np.float64).reshape(-1)
+        hr = np.ascontiguousarray(hr, dtype=np.float64)
+        q = np.zeros(self.n_dofs)
+        lib().or_div_apply(self._s(), float(tau), _dp(hr), _dp(u3), _dp(q))
+        return q
+
     # block Jacobi ----------------------------------------------------------
     def bj_cell_data(self, c: int):
         ell = np.zeros(3); ab = np.zeros(1); bb = np.zeros(1); sig = np.zeros(6)
@@ -246,3 +266,42 @@ class Problem:
         if bad:
             raise FloatingPointError("separable block not positive definite")
         return z
+
+
+class PressureSystem:
+    """The pressure system of one IMEX stage (section 2):
+        A U + B P = F,   C U + D P = G,
+        S P = D P - C A^-1 B P = G - C A^-1 F,
+    with A the rho-weighted velocity mass (one scalar block per component),
+    B the tau-scaled pressure gradient, C the tau-scaled divergence of
+    (h rho) u, D the internal-energy mass of an ideal gas, (1/(gamma-1)) M.
+    Composed from the oracle's own operators, in the paper's order."""
+
+    def __init__(self, mesh, k: int, rho, h, gamma: float, tau: float):
+        self.vel = Problem(mesh, k, alpha=rho, beta=np.zeros_like(rho))
+        n = self.vel.n_dofs
+        self.pmass = Problem(mesh, k, alpha=np.full(n, 1.0 / (gamma - 1.0)), beta=np.zeros(n))
+        self.hr = np.ascontiguousarray(np.asarray(h) * np.asarray(rho), dtype=np.float64)
+        self.tau = float(tau)
+        self.n_dofs = n
+
+    def a_inv(self, u3):
+        return np.stack([self.vel.mass_block_apply(u3[c]) for c in range(3)])
+
+    def grad(self, p):
+        return self.vel.grad_apply(p, self.tau)
+
+    def div(self, u3):
+        return self.vel.div_apply(u3, self.hr, self.tau)
+
+    def d_apply(self, p):
+        return self.pmass.apply(p, OR_CELL)
+
+    def apply(self, p):
+        return self.d_apply(p) - self.div(self.a_inv(self.grad(p)))
+
+    def rhs(self, F, G):
+        return np.asarray(G) - self.div(self.a_inv(np.asarray(F)))
+
+    def velocity(self, F, p):
+        return self.a_inv(np.asarray(F) - self.grad(p))

@@ -898,3 +898,185 @@ int or_mass_block_apply(const or_prob *p, const double *rv, double *zv)
     }
     return bad;
 }
+
+/* ------------------------------------------------------------------------ */
+/* velocity-pressure coupling of the IMEX stage (section 2: the discrete     */
+/* momentum and energy equations A U + B P = F, C U + D P = G, and the       */
+/* pressure system D P + C A^-1 (F - B P) = G).  The paper names these       */
+/* matrices without giving them; they are read here from the stage           */
+/* equations with central fluxes:                                            */
+/*   (B p)_{c,i} = tau [ -sum_K int_K p d_c phi_i                            */
+/*                       + sum_K int_dK p^ phi_i n_{K,c} ],                  */
+/*     p^ = {p} on interior faces, the own trace on boundary faces;          */
+/*   (C u)_i = tau [ -sum_K int_K hr u . grad Psi_i                          */
+/*                   + sum_F interior int_F {hr u . n} [Psi_i] ],            */
+/*     no flux through boundary faces;                                       */
+/* hr is the nodal field of h rho (enthalpy times density), tau = a_ll dt.   */
+/* Velocity vectors are component-major: u3[c * n_dofs + dof].               */
+/* ------------------------------------------------------------------------ */
+
+/* outward unit normal and surface element of a cell on its own (d, plus)
+ * face at tangential GL point (a, b), from the cell's own map */
+static void face_normal_own(const ref_t *r, const double *X, int d, int plus, int a, int b,
+                            double nrm[3], double *ds)
+{
+    double xi[3], x[3], J[3][3], K[3][3];
+    face_point(r, d, plus, a, b, xi);
+    geom_at(r, X, xi, x, J);
+    double det = det3(J);
+    inv_transpose(J, det, K);
+    double e[3] = {0, 0, 0}, m[3];
+    e[d] = 1.0;
+    matvec3(K, e, m);
+    double len = sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
+    double s = plus ? 1.0 : -1.0;
+    for (int q = 0; q < 3; ++q) nrm[q] = s * m[q] / len;
+    *ds = r->wq[a] * r->wq[b] * det * len;
+}
+
+/* (B p) on the test functions of cell c: yc[3][nd] */
+static void grad_one_cell(const or_prob *p, double tau, long c, const double *pv, double *yc)
+{
+    ref_t r; ref_init(&r, p->k, p->g);
+    const int nd = r.nd, n = r.n;
+    double *phi = malloc(sizeof(double) * nd), *phiB = malloc(sizeof(double) * nd);
+    double (*dphi)[3] = malloc(sizeof(double) * 3 * nd);
+    double (*dphiB)[3] = malloc(sizeof(double) * 3 * nd);
+    for (int a = 0; a < 3 * nd; ++a) yc[a] = 0.0;
+    const double *X = cell_nodes(p, &r, c);
+    /* cell term: -int_K p grad phi_i */
+    for (int l = 0; l < n; ++l)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                double xi[3] = {r.xq[i], r.xq[j], r.xq[l]}, x[3], J[3][3], K[3][3];
+                geom_at(&r, X, xi, x, J);
+                double det = det3(J);
+                inv_transpose(J, det, K);
+                double w = r.wq[i] * r.wq[j] * r.wq[l] * det;
+                basis_at(&r, xi, phi, dphi);
+                double pq = field_at(phi, pv + c * nd, nd);
+                for (int a = 0; a < nd; ++a) {
+                    double gv[3];
+                    matvec3(K, dphi[a], gv);
+                    for (int cc = 0; cc < 3; ++cc) yc[cc * nd + a] -= tau * w * pq * gv[cc];
+                }
+            }
+    /* face terms: int_dK p^ phi_i n_K */
+    for (int d = 0; d < 3; ++d)
+        for (int side = 0; side < 2; ++side) {
+            long nb = p->nbr[6 * c + 2 * d + side];
+            for (int b = 0; b < n; ++b)
+                for (int a = 0; a < n; ++a) {
+                    double nrm[3], ds, ph, xi[3];
+                    const double *tphi;
+                    if (nb < 0) {
+                        face_normal_own(&r, X, d, side, a, b, nrm, &ds);
+                        face_point(&r, d, side, a, b, xi);
+                        basis_at(&r, xi, phi, dphi);
+                        ph = field_at(phi, pv + c * nd, nd);
+                        tphi = phi;
+                    } else {
+                        long km = side ? c : nb, kp = side ? nb : c;
+                        double xim[3], xip[3];
+                        face_normal(&r, cell_nodes(p, &r, km), d, a, b, nrm, &ds);
+                        face_point(&r, d, 1, a, b, xim);
+                        face_point(&r, d, 0, a, b, xip);
+                        basis_at(&r, xim, phi, dphi);
+                        basis_at(&r, xip, phiB, dphiB);
+                        ph = 0.5 * (field_at(phi, pv + km * nd, nd) + field_at(phiB, pv + kp * nd, nd));
+                        tphi = side ? phi : phiB;
+                        if (!side)
+                            for (int q = 0; q < 3; ++q) nrm[q] = -nrm[q];   /* outward for c */
+                    }
+                    for (int e = 0; e < nd; ++e)
+                        for (int cc = 0; cc < 3; ++cc)
+                            yc[cc * nd + e] += tau * ds * ph * tphi[e] * nrm[cc];
+                }
+        }
+    free(phi); free(phiB); free(dphi); free(dphiB);
+}
+
+void or_grad_apply(const or_prob *p, double tau, const double *pv, double *u3)
+{
+    const int nd = (p->k + 1) * (p->k + 1) * (p->k + 1);
+    const long nt = p->n_cells * nd;
+#pragma omp parallel
+    {
+        double *tmp = malloc(sizeof(double) * 3 * nd);
+#pragma omp for schedule(dynamic, 4)
+        for (long c = 0; c < p->n_cells; ++c) {
+            grad_one_cell(p, tau, c, pv, tmp);
+            for (int cc = 0; cc < 3; ++cc)
+                for (int a = 0; a < nd; ++a) u3[cc * nt + c * nd + a] = tmp[cc * nd + a];
+        }
+        free(tmp);
+    }
+}
+
+/* (C u) on the test functions of cell c: yc[nd] */
+static void div_one_cell(const or_prob *p, double tau, const double *hr, long c,
+                         const double *u3, double *yc)
+{
+    ref_t r; ref_init(&r, p->k, p->g);
+    const int nd = r.nd, n = r.n;
+    const long nt = p->n_cells * nd;
+    double *phi = malloc(sizeof(double) * nd), *phiB = malloc(sizeof(double) * nd);
+    double (*dphi)[3] = malloc(sizeof(double) * 3 * nd);
+    double (*dphiB)[3] = malloc(sizeof(double) * 3 * nd);
+    for (int a = 0; a < nd; ++a) yc[a] = 0.0;
+    const double *X = cell_nodes(p, &r, c);
+    /* cell term: -int_K hr u . grad Psi_i */
+    for (int l = 0; l < n; ++l)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                double xi[3] = {r.xq[i], r.xq[j], r.xq[l]}, x[3], J[3][3], K[3][3];
+                geom_at(&r, X, xi, x, J);
+                double det = det3(J);
+                inv_transpose(J, det, K);
+                double w = r.wq[i] * r.wq[j] * r.wq[l] * det;
+                basis_at(&r, xi, phi, dphi);
+                double hq = field_at(phi, hr + c * nd, nd);
+                double uq[3];
+                for (int cc = 0; cc < 3; ++cc) uq[cc] = field_at(phi, u3 + cc * nt + c * nd, nd);
+                for (int a = 0; a < nd; ++a) {
+                    double gv[3];
+                    matvec3(K, dphi[a], gv);
+                    yc[a] -= tau * w * hq * (uq[0] * gv[0] + uq[1] * gv[1] + uq[2] * gv[2]);
+                }
+            }
+    /* interior faces: int_F {hr u . n} [Psi_i], n the minus-side normal */
+    for (int d = 0; d < 3; ++d)
+        for (int side = 0; side < 2; ++side) {
+            long nb = p->nbr[6 * c + 2 * d + side];
+            if (nb < 0) continue;
+            long km = side ? c : nb, kp = side ? nb : c;
+            for (int b = 0; b < n; ++b)
+                for (int a = 0; a < n; ++a) {
+                    double nrm[3], ds, xim[3], xip[3];
+                    face_normal(&r, cell_nodes(p, &r, km), d, a, b, nrm, &ds);
+                    face_point(&r, d, 1, a, b, xim);
+                    face_point(&r, d, 0, a, b, xip);
+                    basis_at(&r, xim, phi, dphi);
+                    basis_at(&r, xip, phiB, dphiB);
+                    double fm = 0.0, fp = 0.0;
+                    for (int cc = 0; cc < 3; ++cc) {
+                        fm += field_at(phi, u3 + cc * nt + km * nd, nd) * nrm[cc];
+                        fp += field_at(phiB, u3 + cc * nt + kp * nd, nd) * nrm[cc];
+                    }
+                    fm *= field_at(phi, hr + km * nd, nd);
+                    fp *= field_at(phiB, hr + kp * nd, nd);
+                    const double avg = 0.5 * (fm + fp);
+                    const double *tphi = side ? phi : phiB;
+                    const double sgn = side ? 1.0 : -1.0;
+                    for (int e = 0; e < nd; ++e) yc[e] += tau * ds * avg * sgn * tphi[e];
+                }
+        }
+    free(phi); free(phiB); free(dphi); free(dphiB);
+}
+
+void or_div_apply(const or_prob *p, double tau, const double *hr, const double *u3, double *qv)
+{
+    const int nd = (p->k + 1) * (p->k + 1) * (p->k + 1);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (long c = 0; c < p->n_cells; ++c) div_one_cell(p, tau, hr, c, u3, qv + c * nd);
+}

@@ -40,5 +40,7 @@ void or_bj_sep_block(const or_prob *p, long c, double *Ab);
 int  or_bj_sep_apply(const or_prob *p, const double *r, double *z);
 void or_mass_block(const or_prob *p, long c, double *Mb);
 int  or_mass_block_apply(const or_prob *p, const double *r, double *z);
+void or_grad_apply(const or_prob *p, double tau, const double *pv, double *u3);
+void or_div_apply(const or_prob *p, double tau, const double *hr, const double *u3, double *q);
 
 #endif
