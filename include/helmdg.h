@@ -186,6 +186,11 @@ typedef struct {
                             0 = two block-dot/update pairs per step (four passes over
                             the basis), 1 = second pass delayed by one step and fused
                             with the next step's (two passes; default) */
+    int system;          /* 0 = the Helmholtz-type operator A (default); 1 = the pressure
+                            system S = D - C A^-1 B of hx_set_pressure_system (FGMRES
+                            only: S is not symmetric); the preconditioners, the inner
+                            FP32 CG of the mixed form included, act with the
+                            Helmholtz-type operator set by hx_set_pressure_system */
 } hx_solve_params;
 
 typedef struct {
@@ -214,6 +219,52 @@ void hx_default_params(hx_solve_params *p);
  * HX_ERR_NOCONV. */
 hx_status hx_solve(hx_ctx *c, const hx_solve_params *prm, const double *b,
                    double *x, hx_solve_info *info);
+
+/* ---------------------------------------------------------------------- */
+/* pressure system of one IMEX stage                                        */
+/* ---------------------------------------------------------------------- */
+
+/* Section 2 writes the stage as the discrete momentum and energy equations
+ *   A U + B P = F,   C U + D P = G,
+ * and solves D P + C A^-1 (F - B P) = G for the pressure, i.e.
+ *   S P = (D - C A^-1 B) P = G - C A^-1 F.
+ * The paper does not give the matrices; from the stage equations with
+ * central fluxes (velocity: three DG fields of the pressure space,
+ * component-major [3][n_dofs]):
+ *   (B p)_{e,i} = tau [ -int_K p d_e phi_i + int_dK p^ phi_i n_e ],
+ *                 p^ = {p} inside, the own trace on boundary faces;
+ *   (C u)_i     = tau [ -int_K h rho u . grad Psi_i + int_dK {h rho u . n} Psi_i ],
+ *                 no flux through boundary faces;
+ *   A = rho-weighted velocity mass (one block per cell and component),
+ *   D = mass / (gamma - 1) (internal energy of an ideal gas),
+ * all with the (k+1)-point Gauss rules of the operator, so A^-1 is the exact
+ * tensor-product inverse of section 3.3.  tau = a_ll dt.
+ *
+ * Set-up: rho, h (specific enthalpy) nodal fields [n_dofs] (HOST, or DEVICE
+ * with on_device = 1), gamma > 1, tau > 0.  It also calls
+ * hx_set_coefficients with alpha = 1/(gamma - 1) and beta = tau^2 h: the
+ * Helmholtz-type operator whose volume diagonal is the paper's Helmholtz
+ * preconditioner (section 3.1) and which preconditions S.  Requires
+ * setup_mesh; may be called again with new fields (the fixed-point loop). */
+hx_status hx_set_pressure_system(hx_ctx *c, const double *rho, const double *h, double gamma,
+                                 double tau, double penalty_factor, int on_device);
+
+typedef enum {
+    HX_PS_GRAD = 0,       /* out[3][n] = B in[n] */
+    HX_PS_DIV = 1,        /* out[n] = C in[3][n] */
+    HX_PS_VMASS_INV = 2,  /* out[3][n] = A^-1 in[3][n] */
+    HX_PS_DMASS = 3,      /* out[n] = D in[n] */
+    HX_PS_SYSTEM = 4      /* out[n] = S in[n] */
+} hx_ps_part;
+
+/* Apply one part of the pressure system; in, out DEVICE FP64, distinct. */
+hx_status hx_apply_pressure_part(hx_ctx *c, int part, const double *in, double *out);
+
+/* rhs[n] = G - C A^-1 F (F DEVICE [3][n], G DEVICE [n]). */
+hx_status hx_pressure_rhs(hx_ctx *c, const double *F, const double *G, double *rhs);
+
+/* U[3][n] = A^-1 (F - B P): the velocity of the stage once P is known. */
+hx_status hx_pressure_velocity(hx_ctx *c, const double *F, const double *P, double *U);
 
 /* ---------------------------------------------------------------------- */
 /* BLAS-1 helpers on the context stream (step a6), FP64 device vectors      */

@@ -25,6 +25,7 @@ HX_F64, HX_F32 = 0, 1
  HX_PC_MASS_BLOCK) = range(6)
 HX_EXPORT_CELL_DATA, HX_EXPORT_FACE_DATA, HX_EXPORT_SIGMA, HX_EXPORT_VOLUME, \
     HX_EXPORT_BJ_SCALARS, HX_EXPORT_INV_DIAG = range(6)
+HX_PS_GRAD, HX_PS_DIV, HX_PS_VMASS_INV, HX_PS_DMASS, HX_PS_SYSTEM = range(5)
 
 STATUS_NAMES = {0: "HX_OK", 1: "HX_ERR_ARG", 2: "HX_ERR_STATE", 3: "HX_ERR_DEVICE",
                 4: "HX_ERR_OOM", 5: "HX_ERR_MESH", 6: "HX_ERR_NOCONV",
@@ -42,7 +43,7 @@ class SolveParams(C.Structure):
                 ("max_iter", C.c_int), ("pc", C.c_int), ("mixed", C.c_int),
                 ("inner_iters", C.c_int), ("inner_rtol", C.c_double),
                 ("x0_mode", C.c_int), ("stall_window", C.c_int),
-                ("stall_ratio", C.c_double), ("orth", C.c_int)]
+                ("stall_ratio", C.c_double), ("orth", C.c_int), ("system", C.c_int)]
 
 
 class SolveInfo(C.Structure):
@@ -89,6 +90,11 @@ def load(path: str = LIB_PATH):
         "hx_training_pair": ([vp, vp, vp, vp, vp, vp], C.c_int),
         "hx_train_step": ([vp, vp, vp, i64, C.c_float, C.POINTER(C.c_float), vp], C.c_int),
         "hx_debug_export": ([vp, C.c_int, vp, i64], C.c_int),
+        "hx_set_pressure_system": ([vp, vp, vp, C.c_double, C.c_double, C.c_double, C.c_int],
+                                   C.c_int),
+        "hx_apply_pressure_part": ([vp, C.c_int, vp, vp], C.c_int),
+        "hx_pressure_rhs": ([vp, vp, vp, vp], C.c_int),
+        "hx_pressure_velocity": ([vp, vp, vp, vp], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -179,6 +185,37 @@ class HelmDG:
             a = alpha.contiguous(); b = beta.contiguous()
             st = self.L.hx_set_coefficients(self.h, _ptr(a), _ptr(b), float(penalty), 1)
         self._chk(st, "set_coefficients")
+
+    # -- pressure system of an IMEX stage --------------------------------------
+    def set_pressure_system(self, rho, h, gamma: float, tau: float, penalty: float = 2.0):
+        if isinstance(rho, np.ndarray):
+            r = np.ascontiguousarray(rho, dtype=np.float64)
+            hh = np.ascontiguousarray(h, dtype=np.float64)
+            st = self.L.hx_set_pressure_system(self.h, r.ctypes.data, hh.ctypes.data, float(gamma),
+                                               float(tau), float(penalty), 0)
+        else:
+            r = rho.contiguous(); hh = h.contiguous()
+            st = self.L.hx_set_pressure_system(self.h, _ptr(r), _ptr(hh), float(gamma), float(tau),
+                                               float(penalty), 1)
+        self._chk(st, "set_pressure_system")
+
+    def apply_pressure_part(self, part: int, x):
+        n = self.n_dofs
+        shape = (3, n) if part in (HX_PS_GRAD, HX_PS_VMASS_INV) else (n,)
+        y = self.torch.empty(shape, dtype=self.torch.float64, device=x.device)
+        self._chk(self.L.hx_apply_pressure_part(self.h, int(part), _ptr(x), _ptr(y)),
+                  "apply_pressure_part")
+        return y
+
+    def pressure_rhs(self, F, G):
+        out = self.torch.empty_like(G)
+        self._chk(self.L.hx_pressure_rhs(self.h, _ptr(F), _ptr(G), _ptr(out)), "pressure_rhs")
+        return out
+
+    def pressure_velocity(self, F, P):
+        U = self.torch.empty_like(F)
+        self._chk(self.L.hx_pressure_velocity(self.h, _ptr(F), _ptr(P), _ptr(U)), "pressure_velocity")
+        return U
 
     # -- operator -------------------------------------------------------------
     def apply_operator(self, x, y=None):

@@ -48,10 +48,11 @@ static void free_mesh(hx_ctx *c)
                      (void **)&c->bjS64, (void **)&c->bjS32,
                      (void **)&c->bjL64, (void **)&c->bjL32, (void **)&c->bjC64,
                      (void **)&c->bjC32, (void **)&c->coef_feat, (void **)&c->work64,
-                     (void **)&c->work32};
+                     (void **)&c->work32, (void **)&c->psW, (void **)&c->psWC, (void **)&c->psMr,
+                     (void **)&c->psMd, (void **)&c->psFn, (void **)&c->psFh, (void **)&c->psWork};
     for (void **b : bufs) dfree(b);
     c->work64_len = c->work32_len = 0;
-    c->has_mesh = c->has_coef = false;
+    c->has_mesh = c->has_coef = c->has_press = false;
 }
 
 }  // namespace hx
@@ -251,6 +252,102 @@ hx_status hx_set_coefficients(hx_ctx *c, const double *alpha, const double *beta
     if (tmp) dfree((void **)&tmp);
     if (e != hipSuccess) return fail(c, HX_ERR_DEVICE, "set_coefficients: %s", hipGetErrorString(e));
     c->has_coef = true;
+    return HX_OK;
+}
+
+hx_status hx_set_pressure_system(hx_ctx *c, const double *rho, const double *h, double gamma,
+                                 double tau, double penalty_factor, int on_device)
+{
+    if (!c) return HX_ERR_ARG;
+    if (!c->has_mesh) return fail(c, HX_ERR_STATE, "set_pressure_system before setup_mesh");
+    if (!rho || !h) return fail(c, HX_ERR_ARG, "null field");
+    if (!(gamma > 1.0) || !std::isfinite(gamma)) return fail(c, HX_ERR_ARG, "gamma must exceed 1");
+    if (!(tau > 0.0) || !std::isfinite(tau)) return fail(c, HX_ERR_ARG, "tau must be positive");
+    if (!(penalty_factor > 0.0) || !std::isfinite(penalty_factor))
+        return fail(c, HX_ERR_ARG, "penalty factor must be positive");
+    HX_HIP(c, hipSetDevice(c->device));
+    const int64_t n = c->n_dofs, nc = c->n_cells;
+    hx_status s = HX_OK;
+    if (!c->psW) {
+        auto al = [&](double **p, size_t count) {
+            if (s == HX_OK) s = dalloc(c, (void **)p, sizeof(double) * count);
+        };
+        al(&c->psW, (size_t)nc * 9 * c->nd);
+        al(&c->psWC, (size_t)nc * 9 * c->nd);
+        al(&c->psMr, (size_t)n);
+        al(&c->psMd, (size_t)n);
+        al(&c->psFn, (size_t)nc * 18 * c->nf);
+        al(&c->psFh, (size_t)nc * 6 * c->nf);
+        al(&c->psWork, (size_t)7 * n);
+        if (s != HX_OK) return s;
+    }
+    // fields on the device: [rho, h, alpha, beta]
+    double *tmp = nullptr;
+    if ((s = dalloc(c, (void **)&tmp, sizeof(double) * 4 * n)) != HX_OK) return s;
+    double *dr = tmp, *dh = tmp + n, *al = tmp + 2 * n, *be = tmp + 3 * n;
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    hipError_t e = hipMemcpyAsync(dr, rho, sizeof(double) * n, kind, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(dh, h, sizeof(double) * n, kind, c->stream);
+    if (e == hipSuccess) e = launch_press_setup(c, dr, dh, gamma);
+    if (e == hipSuccess) e = blas_fill(c, n, 1.0 / (gamma - 1.0), al);
+    if (e == hipSuccess) e = blas_axpby(c, n, tau * tau, dh, 0.0, be);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        dfree((void **)&tmp);
+        return fail(c, HX_ERR_DEVICE, "set_pressure_system: %s", hipGetErrorString(e));
+    }
+    s = hx_set_coefficients(c, al, be, penalty_factor, 1);
+    dfree((void **)&tmp);
+    if (s != HX_OK) return s;
+    c->ps_tau = tau;
+    c->has_press = true;
+    return HX_OK;
+}
+
+hx_status hx_apply_pressure_part(hx_ctx *c, int part, const double *in, double *out)
+{
+    if (!c) return HX_ERR_ARG;
+    if (!c->has_press) return fail(c, HX_ERR_STATE, "pressure system not set");
+    if (!in || !out || in == out) return fail(c, HX_ERR_ARG, "null or aliasing vectors");
+    HX_HIP(c, hipSetDevice(c->device));
+    const int64_t n = c->n_dofs;
+    switch (part) {
+    case HX_PS_GRAD: HX_HIP(c, launch_grad(c, in, out)); return HX_OK;
+    case HX_PS_DIV: HX_HIP(c, launch_div(c, in, out)); return HX_OK;
+    case HX_PS_VMASS_INV:
+        for (int e = 0; e < 3; ++e) HX_HIP(c, launch_mass64(c, c->psMr, c->nd, 1, in + e * n, out + e * n));
+        return HX_OK;
+    case HX_PS_DMASS: HX_HIP(c, launch_mass64(c, c->psMd, c->nd, 0, in, out)); return HX_OK;
+    case HX_PS_SYSTEM: HX_HIP(c, press_apply64(c, in, out, nullptr)); return HX_OK;
+    default: return fail(c, HX_ERR_ARG, "unknown pressure-system part %d", part);
+    }
+}
+
+hx_status hx_pressure_rhs(hx_ctx *c, const double *F, const double *G, double *rhs)
+{
+    if (!c) return HX_ERR_ARG;
+    if (!c->has_press) return fail(c, HX_ERR_STATE, "pressure system not set");
+    if (!F || !G || !rhs || rhs == G) return fail(c, HX_ERR_ARG, "null or aliasing vectors");
+    HX_HIP(c, hipSetDevice(c->device));
+    const int64_t n = c->n_dofs;
+    double *v3 = c->psWork + 3 * n;
+    for (int e = 0; e < 3; ++e) HX_HIP(c, launch_mass64(c, c->psMr, c->nd, 1, F + e * n, v3 + e * n));
+    HX_HIP(c, launch_div(c, v3, rhs));
+    HX_HIP(c, blas_axpby(c, n, 1.0, G, -1.0, rhs));
+    return HX_OK;
+}
+
+hx_status hx_pressure_velocity(hx_ctx *c, const double *F, const double *P, double *U)
+{
+    if (!c) return HX_ERR_ARG;
+    if (!c->has_press) return fail(c, HX_ERR_STATE, "pressure system not set");
+    if (!F || !P || !U || U == F) return fail(c, HX_ERR_ARG, "null or aliasing vectors");
+    HX_HIP(c, hipSetDevice(c->device));
+    const int64_t n = c->n_dofs;
+    double *u3 = c->psWork;
+    HX_HIP(c, launch_grad(c, P, u3));
+    HX_HIP(c, blas_axpby(c, 3 * n, 1.0, F, -1.0, u3));
+    for (int e = 0; e < 3; ++e) HX_HIP(c, launch_mass64(c, c->psMr, c->nd, 1, u3 + e * n, U + e * n));
     return HX_OK;
 }
 

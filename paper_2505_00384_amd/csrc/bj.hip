@@ -322,18 +322,20 @@ namespace {
 // matrix as S^-T J^-1 S^-1 with S a Kronecker product of 1-D matrices), valid
 // for curved cells and variable alpha.  Same thread mapping as k_bj, with the
 // one 1-D matrix shared by all cells.
-// FUSE: the conjugate-gradient step around it, as in k_bj.
-template <int N, typename T, bool FUSE>
+// FUSE: the conjugate-gradient step around it, as in k_bj.  With INV false
+// the same sweeps apply M_K itself (B3^T diag(m_K) B3: the 1-D matrix is
+// B^T, the scaling a product).  The weights are wgt[cell * wstride + q].
+template <int N, typename T, bool FUSE, bool INV>
 __global__ void __launch_bounds__(Cfg<N>::NT)
-k_massinv(const T *__restrict__ rin, T *__restrict__ z, const T *__restrict__ cell,
-          const double *__restrict__ Binv, int n_cells, int nwg, T *x, T *rw,
+k_massinv(const T *__restrict__ rin, T *__restrict__ z, const T *__restrict__ wgt, int64_t wstride,
+          const double *__restrict__ Fm, int n_cells, int nwg, T *x, T *rw,
           const T *__restrict__ p, const T *__restrict__ q, const double *__restrict__ sc,
           double *part, int ld)
 {
     const T *r = FUSE ? rw : rin;
     constexpr int NF = Cfg<N>::NF, ND = Cfg<N>::ND, CPB = Cfg<N>::CPB;
     __shared__ T sR[CPB][ND];
-    __shared__ T sB[NF];                 // sB[i*N+q] = (B^{-1})_{iq}
+    __shared__ T sB[NF];                 // sB[i*N+q] = (B^{-1})_{iq}, or B_{qi}
 
     const int bid = blockIdx.x;
     const int q8 = nwg / NXCD, r8 = nwg % NXCD, xcd = bid % NXCD;
@@ -347,7 +349,7 @@ k_massinv(const T *__restrict__ rin, T *__restrict__ z, const T *__restrict__ ce
     const int64_t cid = (int64_t)wg * CPB + lc;
     const bool active = slot && cid < n_cells;
 
-    for (int e = t; e < NF; e += blockDim.x) sB[e] = (T)Binv[e];
+    for (int e = t; e < NF; e += blockDim.x) sB[e] = (T)(INV ? Fm[e] : Fm[(e % N) * N + e / N]);
     T mq[N], v[N], w[N], rp[N];
     double acc_rr = 0.0, acc_rz = 0.0;
     if (FUSE && active) {
@@ -365,7 +367,7 @@ k_massinv(const T *__restrict__ rin, T *__restrict__ z, const T *__restrict__ ce
     }
     if (active) {
 #pragma unroll
-        for (int m = 0; m < N; ++m) mq[m] = cell[cid * 7 * ND + a + N * b + NF * m];
+        for (int m = 0; m < N; ++m) mq[m] = wgt[cid * wstride + a + N * b + NF * m];
     }
     __syncthreads();
     // B^{-T} along x: thread (j=a, l=b); rp keeps the residual pencil, at the
@@ -415,7 +417,7 @@ k_massinv(const T *__restrict__ rin, T *__restrict__ z, const T *__restrict__ ce
             T s = 0;
 #pragma unroll
             for (int l = 0; l < N; ++l) s += sB[l * N + m] * v[l];
-            w[m] = s / mq[m];
+            w[m] = INV ? s / mq[m] : s * mq[m];
         }
 #pragma unroll
         for (int l = 0; l < N; ++l) {
@@ -481,39 +483,50 @@ k_massinv(const T *__restrict__ rin, T *__restrict__ z, const T *__restrict__ ce
 }
 
 template <int N, typename T>
-hipError_t massinv_n(hx_ctx *c, const T *r, T *z, const CgArgs<T> *cg, int *nblk)
+hipError_t massinv_n(hx_ctx *c, const T *wgt, int64_t wstride, bool inv, const T *r, T *z,
+                     const CgArgs<T> *cg, int *nblk)
 {
     const int cpb = Cfg<N>::CPB;
     const int nwg = (int)((c->n_cells + cpb - 1) / cpb);
-    const bool dbl = std::is_same<T, double>::value;
-    const T *cell = dbl ? (const T *)c->cell64 : (const T *)c->cell32;
-    const double *Binv = reinterpret_cast<const double *>(reinterpret_cast<const char *>(c->ref) +
-                                                          offsetof(RefTab64, Binv));
+    const char *ref = reinterpret_cast<const char *>(c->ref);
+    const double *Fm = reinterpret_cast<const double *>(ref + (inv ? offsetof(RefTab64, Binv)
+                                                                     : offsetof(RefTab64, B)));
     if (nblk) *nblk = nwg;
     if (cg)
-        hipLaunchKernelGGL((k_massinv<N, T, true>), dim3(nwg), dim3(Cfg<N>::NT), 0, c->stream, r, z,
-                           cell, Binv, (int)c->n_cells, nwg, cg->x, cg->r, cg->p, cg->q, cg->sc,
-                           c->cgpart, (int)c->n_cells + 1);
+        hipLaunchKernelGGL((k_massinv<N, T, true, true>), dim3(nwg), dim3(Cfg<N>::NT), 0, c->stream,
+                           r, z, wgt, wstride, Fm, (int)c->n_cells, nwg, cg->x, cg->r, cg->p, cg->q,
+                           cg->sc, c->cgpart, (int)c->n_cells + 1);
+    else if (inv)
+        hipLaunchKernelGGL((k_massinv<N, T, false, true>), dim3(nwg), dim3(Cfg<N>::NT), 0, c->stream,
+                           r, z, wgt, wstride, Fm, (int)c->n_cells, nwg, (T *)nullptr, (T *)nullptr,
+                           (const T *)nullptr, (const T *)nullptr, (const double *)nullptr,
+                           (double *)nullptr, 0);
     else
-        hipLaunchKernelGGL((k_massinv<N, T, false>), dim3(nwg), dim3(Cfg<N>::NT), 0, c->stream, r,
-                           z, cell, Binv, (int)c->n_cells, nwg, (T *)nullptr, (T *)nullptr,
+        hipLaunchKernelGGL((k_massinv<N, T, false, false>), dim3(nwg), dim3(Cfg<N>::NT), 0, c->stream,
+                           r, z, wgt, wstride, Fm, (int)c->n_cells, nwg, (T *)nullptr, (T *)nullptr,
                            (const T *)nullptr, (const T *)nullptr, (const double *)nullptr,
                            (double *)nullptr, 0);
     return hipGetLastError();
 }
 
+// the alpha-weighted mass of the Helmholtz operator: first cell-data component
 template <typename T>
 hipError_t massinv_dispatch(hx_ctx *c, const T *r, T *z, const CgArgs<T> *cg = nullptr,
-                            int *nblk = nullptr)
+                            int *nblk = nullptr, const T *wgt = nullptr, int64_t wstride = 0,
+                            bool inv = true)
 {
+    if (!wgt) {
+        wgt = std::is_same<T, double>::value ? (const T *)c->cell64 : (const T *)c->cell32;
+        wstride = 7 * (int64_t)c->nd;
+    }
     switch (c->n) {
-    case 2: return massinv_n<2, T>(c, r, z, cg, nblk);
-    case 3: return massinv_n<3, T>(c, r, z, cg, nblk);
-    case 4: return massinv_n<4, T>(c, r, z, cg, nblk);
-    case 5: return massinv_n<5, T>(c, r, z, cg, nblk);
-    case 6: return massinv_n<6, T>(c, r, z, cg, nblk);
-    case 7: return massinv_n<7, T>(c, r, z, cg, nblk);
-    case 8: return massinv_n<8, T>(c, r, z, cg, nblk);
+    case 2: return massinv_n<2, T>(c, wgt, wstride, inv, r, z, cg, nblk);
+    case 3: return massinv_n<3, T>(c, wgt, wstride, inv, r, z, cg, nblk);
+    case 4: return massinv_n<4, T>(c, wgt, wstride, inv, r, z, cg, nblk);
+    case 5: return massinv_n<5, T>(c, wgt, wstride, inv, r, z, cg, nblk);
+    case 6: return massinv_n<6, T>(c, wgt, wstride, inv, r, z, cg, nblk);
+    case 7: return massinv_n<7, T>(c, wgt, wstride, inv, r, z, cg, nblk);
+    case 8: return massinv_n<8, T>(c, wgt, wstride, inv, r, z, cg, nblk);
     default: return hipErrorInvalidValue;
     }
 }
@@ -521,6 +534,12 @@ hipError_t massinv_dispatch(hx_ctx *c, const T *r, T *z, const CgArgs<T> *cg = n
 
 hipError_t launch_massinv64(hx_ctx *c, const double *r, double *z) { return massinv_dispatch<double>(c, r, z); }
 hipError_t launch_massinv32(hx_ctx *c, const float *r, float *z) { return massinv_dispatch<float>(c, r, z); }
+
+hipError_t launch_mass64(hx_ctx *c, const double *wgt, int64_t wstride, int inv, const double *r,
+                         double *z)
+{
+    return massinv_dispatch<double>(c, r, z, nullptr, nullptr, wgt, wstride, inv != 0);
+}
 
 hipError_t launch_cg_massinv64(hx_ctx *c, double *x, double *r, const double *p, const double *q,
                                double *z, const double *sc, int *nblk)

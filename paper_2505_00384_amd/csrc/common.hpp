@@ -69,6 +69,16 @@ struct hx_ctx {
     double *dg64 = nullptr;       // [2][n_dofs] inverse volume diagonals: mass + stiffness, mass
     float *dg32 = nullptr;
     double *cgpart = nullptr;     // [2][n_cells + 1] per-block partial sums of the fused CG steps
+    // pressure system of the IMEX stage (A U + B P = F, C U + D P = G)
+    bool has_press = false;
+    double ps_tau = 0.0;
+    double *psW = nullptr;        // [n_cells][9][nd]  w detJ J^-1
+    double *psWC = nullptr;       // [n_cells][9][nd]  h rho w detJ J^-1
+    double *psMr = nullptr;       // [n_cells][nd]     rho w detJ (velocity mass)
+    double *psMd = nullptr;       // [n_cells][nd]     w detJ / (gamma - 1) (internal-energy mass)
+    double *psFn = nullptr;       // [n_cells][6][3][nf] outward ds n on the own faces
+    double *psFh = nullptr;       // [n_cells][6][nf]  h rho on the own faces
+    double *psWork = nullptr;     // [7][n_dofs]       velocity temporaries and C A^-1 B x
 
     // separable block-Jacobi data
     double *bjS64 = nullptr;      // [n_cells][3][n][n]  eigenvectors S_d
@@ -123,6 +133,16 @@ hipError_t launch_diag32(hx_ctx *c, int which, const float *r, float *z);
 // z = M^{-1} r, M the block-diagonal alpha-weighted mass matrix (fast
 // tensor-product inverse)
 hipError_t launch_massinv64(hx_ctx *c, const double *r, double *z);
+// z = M r (inv = 0) or M^{-1} r (inv = 1) for the block-diagonal mass matrix
+// with quadrature weights wgt[cell * wstride + q] (FP64)
+hipError_t launch_mass64(hx_ctx *c, const double *wgt, int64_t wstride, int inv, const double *r,
+                         double *z);
+// pressure system: set-up from nodal rho and h; B p (3 components),
+// C u, and y = S x or y = b - S x with S = D - C A^-1 B
+hipError_t launch_press_setup(hx_ctx *c, const double *rho, const double *h, double gamma);
+hipError_t launch_grad(hx_ctx *c, const double *p, double *u3);
+hipError_t launch_div(hx_ctx *c, const double *u3, double *q);
+hipError_t press_apply64(hx_ctx *c, const double *x, double *y, const double *b);
 hipError_t launch_massinv32(hx_ctx *c, const float *r, float *z);
 hipError_t launch_cg_massinv64(hx_ctx *c, double *x, double *r, const double *p, const double *q,
                                double *z, const double *sc, int *nblk);

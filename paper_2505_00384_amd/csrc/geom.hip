@@ -672,3 +672,102 @@ hipError_t launch_dof_coords(hx_ctx *c, double *xyz)
 }
 
 }  // namespace hx
+
+namespace hx {
+namespace {
+
+// -------------------------------------------------------------------------
+// Data of the pressure system of one IMEX stage (section 2: A U + B P = F,
+// C U + D P = G).  At cell Gauss point q of cell c:
+//   W[c][3d+e][q]  = w detJ (J^-1)_{de}   (so that (grad phi)_e = sum_d W ... / (w detJ))
+//   WC[c][3d+e][q] = hr_q W[c][3d+e][q]   (hr = h rho formed at the nodes, interpolated)
+//   mr[c][q] = rho_q w detJ,  md[c][q] = w detJ / (gamma - 1);
+// at Gauss point (a, b) of the cell's own face f = 2d + s:
+//   fn[c][f][e][a + N b] = ds n_e (outward),  fh[c][f][a + N b] = hr.
+// -------------------------------------------------------------------------
+__global__ void k_press_cell(const double *__restrict__ nodes, int ng, int n, int64_t n_cells,
+                             const RefTab64 *__restrict__ T, const double *__restrict__ rho,
+                             const double *__restrict__ h, double inv_gm1, double *W, double *WC,
+                             double *mr, double *md)
+{
+    const int nd = n * n * n;
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= n_cells * nd) return;
+    const int64_t c = t / nd;
+    const int q = (int)(t % nd);
+    const int i = q % n, j = (q / n) % n, l = q / (n * n);
+    double xi[3] = {T->xq[i], T->xq[j], T->xq[l]}, x[3], J[3][3], Ji[3][3];
+    cell_map(nodes + c * (int64_t)ng * ng * ng * 3, ng, xi, x, J);
+    const double det = det3(J);
+    inv3(J, det, Ji);
+    const double w = T->wq[i] * T->wq[j] * T->wq[l] * det;
+    double rq = 0.0, hq = 0.0;
+    const double *rc = rho + c * nd, *hc = h + c * nd;
+    for (int l2 = 0; l2 < n; ++l2)
+        for (int j2 = 0; j2 < n; ++j2) {
+            const double byz = T->B[j * n + j2] * T->B[l * n + l2];
+            for (int i2 = 0; i2 < n; ++i2) {
+                const double wgt = T->B[i * n + i2] * byz;
+                const int e = lidx(n, i2, j2, l2);
+                rq += wgt * rc[e];
+                hq += wgt * (hc[e] * rc[e]);
+            }
+        }
+    for (int d = 0; d < 3; ++d)
+        for (int e = 0; e < 3; ++e) {
+            const double v = w * Ji[d][e];
+            W[(c * 9 + 3 * d + e) * nd + q] = v;
+            WC[(c * 9 + 3 * d + e) * nd + q] = hq * v;
+        }
+    mr[c * nd + q] = rq * w;
+    md[c * nd + q] = w * inv_gm1;
+}
+
+__global__ void k_press_face(const double *__restrict__ nodes, int ng, int n, int64_t n_cells,
+                             const RefTab64 *__restrict__ T, const double *__restrict__ rho,
+                             const double *__restrict__ h, double *fn, double *fh)
+{
+    const int nf = n * n, nd = nf * n;
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= n_cells * 6 * nf) return;
+    const int pt = (int)(t % nf);
+    const int64_t cf = t / nf;
+    const int64_t c = cf / 6;
+    const int f = (int)(cf % 6), d = f >> 1, s = f & 1;
+    const int a = pt % n, b = pt / n;
+    double xi[3], x[3], J[3][3], Ji[3][3];
+    face_xi(T, d, s, a, b, xi);
+    cell_map(nodes + c * (int64_t)ng * ng * ng * 3, ng, xi, x, J);
+    const double det = det3(J);
+    inv3(J, det, Ji);
+    // ds n = +-w_a w_b detJ J^-T e_d (row d of J^-1), outward
+    const double sw = (s ? 1.0 : -1.0) * T->wq[a] * T->wq[b] * det;
+    for (int e = 0; e < 3; ++e) fn[(cf * 3 + e) * nf + pt] = sw * Ji[d][e];
+    // trace of hr: the face layer of GLL nodes interpolated to the point
+    const int m = s ? n - 1 : 0;
+    double hv = 0.0;
+    for (int e2 = 0; e2 < n; ++e2)
+        for (int e1 = 0; e1 < n; ++e1) {
+            const int64_t e = c * nd + layer_idx(n, d, m, e1, e2);
+            hv += T->B[a * n + e1] * T->B[b * n + e2] * (h[e] * rho[e]);
+        }
+    fh[cf * nf + pt] = hv;
+}
+
+}  // namespace
+
+hipError_t launch_press_setup(hx_ctx *c, const double *rho, const double *h, double gamma)
+{
+    const int64_t nt = c->n_cells * c->nd;
+    hipLaunchKernelGGL(k_press_cell, dim3(nblk(nt, 128)), dim3(128), 0, c->stream, c->nodes, c->g + 1,
+                       c->n, c->n_cells, c->ref, rho, h, 1.0 / (gamma - 1.0), c->psW, c->psWC,
+                       c->psMr, c->psMd);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t nf = c->n_cells * 6 * c->nf;
+    hipLaunchKernelGGL(k_press_face, dim3(nblk(nf, 128)), dim3(128), 0, c->stream, c->nodes, c->g + 1,
+                       c->n, c->n_cells, c->ref, rho, h, c->psFn, c->psFh);
+    return hipGetLastError();
+}
+
+}  // namespace hx

@@ -1,0 +1,415 @@
+// The pressure system of one IMEX stage (paper section 2: the discrete
+// momentum and energy equations A U + B P = F, C U + D P = G, and the system
+// D P + C A^-1 (F - B P) = G solved for the pressure).  The paper names the
+// matrices without giving them; with central fluxes they are
+//   (B p)_{e,i} = tau [ -int_K p d_e phi_i + int_dK p^ phi_i n_{K,e} ],
+//       p^ = {p} on interior faces, the own trace on boundary faces;
+//   (C u)_i     = tau [ -int_K hr u . grad Psi_i + int_dK {hr u . n_K} Psi_i ],
+//       interior faces only (no flux through the boundary);
+//   A = rho-weighted velocity mass (one scalar block per component),
+//   D = (1/(gamma - 1)) mass (internal energy of an ideal gas),
+// with hr = h rho and (k+1)-point Gauss rules on cells and faces, the rule of
+// the fast block-diagonal inverse (section 3.3), so A^-1 is exact by the
+// tensor-product sweeps of k_massinv.
+//
+// k_grad and k_div: NF threads per cell (pencil owners (a, b)), CPB cells
+// per block.  Cell terms by sum factorisation: values at the Gauss points by
+// three sweeps, the pointwise metric terms W = w detJ J^-1 (times hr for C),
+// and the transposed gradient (B^T / BD^T sweeps z, y, x).  Face terms: the
+// traces at the face Gauss points are N x N contractions of the face layers
+// (GLL nodes include the faces), the transposed contraction returns them to
+// the face-layer nodes, and the pencil owners add them.  Each output is
+// written by one thread: no atomics, bitwise reproducible.
+#include "common.hpp"
+
+namespace hx {
+namespace {
+
+template <int N>
+struct PCfg {
+    static constexpr int NF = N * N, ND = N * N * N;
+    static constexpr int CPB = (128 / NF) > 0 ? 128 / NF : 1;
+    static constexpr int NT = ((CPB * NF + 63) / 64) * 64;
+};
+
+// cell-local index of face-layer node (e1, e2) at normal coordinate m of
+// direction d; e1, e2 run along the tangential directions t1 < t2
+template <int N>
+__device__ __forceinline__ int lay(int d, int m, int e1, int e2)
+{
+    const int s1 = d == 0 ? N : 1, s2 = d == 2 ? N : N * N, sd = d == 0 ? 1 : (d == 1 ? N : N * N);
+    return m * sd + e1 * s1 + e2 * s2;
+}
+
+// value of a face layer at face Gauss point (a, b): sum B(a,e1) B(b,e2) v
+template <int N>
+__device__ __forceinline__ double trace_at(const double *sB, const double *v, int d, int m, int a,
+                                           int b)
+{
+    double s = 0.0;
+    for (int e2 = 0; e2 < N; ++e2) {
+        double r = 0.0;
+        for (int e1 = 0; e1 < N; ++e1) r += sB[a * N + e1] * v[lay<N>(d, m, e1, e2)];
+        s += sB[b * N + e2] * r;
+    }
+    return s;
+}
+
+// transposed contraction of a face field g[a + N b] to node (e1, e2)
+template <int N>
+__device__ __forceinline__ double trace_t(const double *sB, const double *g, int e1, int e2)
+{
+    double s = 0.0;
+    for (int b = 0; b < N; ++b) {
+        double r = 0.0;
+        for (int a = 0; a < N; ++a) r += sB[a * N + e1] * g[a + N * b];
+        s += sB[b * N + e2] * r;
+    }
+    return s;
+}
+
+// values of a cell field at the Gauss points along the lane's z pencil
+// (lane (a, b) = (qx, qy)); v is the field in LDS, F a scratch field
+template <int N>
+__device__ __forceinline__ void to_gauss(const double *sB, const double *v, double *F, bool act,
+                                         int a, int b, double (&out)[N])
+{
+    constexpr int NF = N * N;
+    double r[N], w[N];
+    if (act) {
+        for (int i = 0; i < N; ++i) r[i] = v[i + N * a + NF * b];
+        for (int q = 0; q < N; ++q) {
+            double s = 0.0;
+            for (int i = 0; i < N; ++i) s += sB[q * N + i] * r[i];
+            w[q] = s;
+        }
+        for (int q = 0; q < N; ++q) F[q + N * a + NF * b] = w[q];
+    }
+    __syncthreads();
+    if (act) {
+        for (int j = 0; j < N; ++j) r[j] = F[a + N * j + NF * b];
+        for (int q = 0; q < N; ++q) {
+            double s = 0.0;
+            for (int j = 0; j < N; ++j) s += sB[q * N + j] * r[j];
+            w[q] = s;
+        }
+    }
+    __syncthreads();
+    if (act)
+        for (int q = 0; q < N; ++q) F[a + N * q + NF * b] = w[q];
+    __syncthreads();
+    if (act) {
+        for (int l = 0; l < N; ++l) r[l] = F[a + N * b + NF * l];
+        for (int q = 0; q < N; ++q) {
+            double s = 0.0;
+            for (int l = 0; l < N; ++l) s += sB[q * N + l] * r[l];
+            out[q] = s;
+        }
+    }
+    __syncthreads();
+}
+
+// y = -tau sum_d G_d^T t_d, G_d the reference gradient component d at the
+// Gauss points; t_d given along the lane's z pencil; F0..F2 scratch fields;
+// the result is the lane's x pencil (lane (a, b) = (j, l))
+template <int N>
+__device__ __forceinline__ void grad_t(const double *sB, const double *sD, double *F0, double *F1,
+                                       double *F2, bool act, int a, int b, const double (&t0)[N],
+                                       const double (&t1)[N], const double (&t2)[N], double tau,
+                                       double (&y)[N])
+{
+    constexpr int NF = N * N;
+    if (act) {
+        for (int l = 0; l < N; ++l) {
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+            for (int q = 0; q < N; ++q) {
+                s0 += sB[q * N + l] * t0[q];
+                s1 += sB[q * N + l] * t1[q];
+                s2 += sD[q * N + l] * t2[q];
+            }
+            F0[a + N * b + NF * l] = s0;
+            F1[a + N * b + NF * l] = s1;
+            F2[a + N * b + NF * l] = s2;
+        }
+    }
+    __syncthreads();
+    double r0[N], r12[N];
+    if (act) {
+        double f0[N], f1[N], f2[N];
+        for (int q = 0; q < N; ++q) {
+            f0[q] = F0[a + N * q + NF * b];
+            f1[q] = F1[a + N * q + NF * b];
+            f2[q] = F2[a + N * q + NF * b];
+        }
+        for (int j = 0; j < N; ++j) {
+            double s0 = 0.0, s12 = 0.0;
+            for (int q = 0; q < N; ++q) {
+                s0 += sB[q * N + j] * f0[q];
+                s12 += sD[q * N + j] * f1[q] + sB[q * N + j] * f2[q];
+            }
+            r0[j] = s0;
+            r12[j] = s12;
+        }
+    }
+    __syncthreads();
+    if (act)
+        for (int j = 0; j < N; ++j) {
+            F0[a + N * j + NF * b] = r0[j];
+            F1[a + N * j + NF * b] = r12[j];
+        }
+    __syncthreads();
+    if (act) {
+        double g0[N], g1[N];
+        for (int q = 0; q < N; ++q) {
+            g0[q] = F0[q + N * a + NF * b];
+            g1[q] = F1[q + N * a + NF * b];
+        }
+        for (int i = 0; i < N; ++i) {
+            double s = 0.0;
+            for (int q = 0; q < N; ++q) s += sD[q * N + i] * g0[q] + sB[q * N + i] * g1[q];
+            y[i] = -tau * s;
+        }
+    }
+    __syncthreads();
+}
+
+// add face-layer contributions A[f][e1 + N e2] of the six faces to the x
+// pencil (i, j=a, l=b) of the lane
+template <int N>
+__device__ __forceinline__ void add_faces(const double *A, int a, int b, double (&y)[N])
+{
+    constexpr int NF = N * N;
+    // x faces: nodes (0 or N-1, a, b), (e1, e2) = (j, l)
+    y[0] += A[0 * NF + a + N * b];
+    y[N - 1] += A[1 * NF + a + N * b];
+    // y faces: j = a on the layer, (e1, e2) = (i, l)
+    if (a == 0)
+        for (int i = 0; i < N; ++i) y[i] += A[2 * NF + i + N * b];
+    if (a == N - 1)
+        for (int i = 0; i < N; ++i) y[i] += A[3 * NF + i + N * b];
+    // z faces: l = b on the layer, (e1, e2) = (i, j)
+    if (b == 0)
+        for (int i = 0; i < N; ++i) y[i] += A[4 * NF + i + N * a];
+    if (b == N - 1)
+        for (int i = 0; i < N; ++i) y[i] += A[5 * NF + i + N * a];
+}
+
+template <int N>
+__global__ void __launch_bounds__(PCfg<N>::NT)
+k_grad(const double *__restrict__ p, double *__restrict__ u3, int64_t nt,
+       const double *__restrict__ W, const double *__restrict__ fn, const int32_t *__restrict__ nbr,
+       const RefTab64 *__restrict__ T, double tau, int n_cells)
+{
+    constexpr int NF = PCfg<N>::NF, ND = PCfg<N>::ND, CPB = PCfg<N>::CPB;
+    __shared__ double sB[NF], sD[NF];
+    __shared__ double sP[CPB][ND];
+    __shared__ double sF[CPB][3][ND];
+    __shared__ double sG[CPB][3][NF];
+    __shared__ double sA[CPB][3][6 * NF];
+    const int t = threadIdx.x;
+    const int lc0 = t / NF;
+    const bool slot = lc0 < CPB;
+    const int lc = slot ? lc0 : 0;
+    const int tt = t - lc0 * NF;
+    const int a = tt % N, b = tt / N;
+    const int64_t cid = (int64_t)blockIdx.x * CPB + lc;
+    const bool act = slot && cid < n_cells;
+
+    for (int e = t; e < NF; e += blockDim.x) {
+        sB[e] = T->B[e];
+        sD[e] = T->BD[e];
+    }
+    if (act)
+        for (int e = tt; e < ND; e += NF) sP[lc][e] = p[cid * ND + e];
+    __syncthreads();
+    double pq[N];
+    to_gauss<N>(sB, sP[lc], sF[lc][0], act, a, b, pq);
+    double Y[3][N];
+#pragma unroll
+    for (int ec = 0; ec < 3; ++ec) {
+        double t0[N], t1[N], t2[N];
+        if (act) {
+            const double *Wc = W + cid * 9 * ND + a + N * b;
+            for (int q = 0; q < N; ++q) {
+                t0[q] = pq[q] * Wc[(0 + ec) * ND + NF * q];
+                t1[q] = pq[q] * Wc[(3 + ec) * ND + NF * q];
+                t2[q] = pq[q] * Wc[(6 + ec) * ND + NF * q];
+            }
+        }
+        grad_t<N>(sB, sD, sF[lc][0], sF[lc][1], sF[lc][2], act, a, b, t0, t1, t2, tau, Y[ec]);
+    }
+    // faces: tau ds n_e p^ at the Gauss points, back to the face-layer nodes
+    for (int f = 0; f < 6; ++f) {
+        const int d = f >> 1, s = f & 1;
+        if (act) {
+            const int32_t nb = nbr[6 * cid + f];
+            const double po = trace_at<N>(sB, sP[lc], d, s ? N - 1 : 0, a, b);
+            double ph = po;
+            if (nb >= 0) {
+                const double pn = trace_at<N>(sB, p + (int64_t)nb * ND, d, s ? 0 : N - 1, a, b);
+                ph = 0.5 * (po + pn);
+            }
+            const double *fnc = fn + (cid * 6 + f) * 3 * NF + tt;
+            for (int ec = 0; ec < 3; ++ec) sG[lc][ec][tt] = tau * ph * fnc[ec * NF];
+        }
+        __syncthreads();
+        if (act)
+            for (int ec = 0; ec < 3; ++ec) sA[lc][ec][f * NF + tt] = trace_t<N>(sB, sG[lc][ec], a, b);
+        __syncthreads();
+    }
+    if (act)
+#pragma unroll
+        for (int ec = 0; ec < 3; ++ec) {
+            add_faces<N>(sA[lc][ec], a, b, Y[ec]);
+            const int64_t o = ec * nt + cid * ND + N * a + NF * b;
+            for (int i = 0; i < N; ++i) u3[o + i] = Y[ec][i];
+        }
+}
+
+template <int N>
+__global__ void __launch_bounds__(PCfg<N>::NT)
+k_div(const double *__restrict__ u3, double *__restrict__ qv, int64_t nt,
+      const double *__restrict__ WC, const double *__restrict__ fn, const double *__restrict__ fh,
+      const int32_t *__restrict__ nbr, const RefTab64 *__restrict__ T, double tau, int n_cells)
+{
+    constexpr int NF = PCfg<N>::NF, ND = PCfg<N>::ND, CPB = PCfg<N>::CPB;
+    __shared__ double sB[NF], sD[NF];
+    __shared__ double sU[CPB][3][ND];
+    __shared__ double sF[CPB][3][ND];
+    __shared__ double sG[CPB][NF];
+    __shared__ double sA[CPB][6 * NF];
+    const int t = threadIdx.x;
+    const int lc0 = t / NF;
+    const bool slot = lc0 < CPB;
+    const int lc = slot ? lc0 : 0;
+    const int tt = t - lc0 * NF;
+    const int a = tt % N, b = tt / N;
+    const int64_t cid = (int64_t)blockIdx.x * CPB + lc;
+    const bool act = slot && cid < n_cells;
+
+    for (int e = t; e < NF; e += blockDim.x) {
+        sB[e] = T->B[e];
+        sD[e] = T->BD[e];
+    }
+    if (act)
+        for (int ec = 0; ec < 3; ++ec)
+            for (int e = tt; e < ND; e += NF) sU[lc][ec][e] = u3[ec * nt + cid * ND + e];
+    __syncthreads();
+    double uq[3][N];
+#pragma unroll
+    for (int ec = 0; ec < 3; ++ec) to_gauss<N>(sB, sU[lc][ec], sF[lc][0], act, a, b, uq[ec]);
+    double t0[N], t1[N], t2[N], Y[N];
+    if (act) {
+        const double *Wc = WC + cid * 9 * ND + a + N * b;
+        for (int q = 0; q < N; ++q) {
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+            for (int ec = 0; ec < 3; ++ec) {
+                s0 += Wc[(0 + ec) * ND + NF * q] * uq[ec][q];
+                s1 += Wc[(3 + ec) * ND + NF * q] * uq[ec][q];
+                s2 += Wc[(6 + ec) * ND + NF * q] * uq[ec][q];
+            }
+            t0[q] = s0;
+            t1[q] = s1;
+            t2[q] = s2;
+        }
+    }
+    grad_t<N>(sB, sD, sF[lc][0], sF[lc][1], sF[lc][2], act, a, b, t0, t1, t2, tau, Y);
+    // interior faces: tau ds {hr u . n_K} at the Gauss points, back to the nodes
+    for (int f = 0; f < 6; ++f) {
+        const int d = f >> 1, s = f & 1;
+        if (act) {
+            const int32_t nb = nbr[6 * cid + f];
+            double g = 0.0;
+            if (nb >= 0) {
+                const double *fnc = fn + (cid * 6 + f) * 3 * NF + tt;
+                double fo = 0.0, fnb = 0.0;
+                for (int ec = 0; ec < 3; ++ec) {
+                    const double uo = trace_at<N>(sB, sU[lc][ec], d, s ? N - 1 : 0, a, b);
+                    const double un = trace_at<N>(sB, u3 + ec * nt + (int64_t)nb * ND, d, s ? 0 : N - 1,
+                                                  a, b);
+                    fo += uo * fnc[ec * NF];
+                    fnb += un * fnc[ec * NF];
+                }
+                fo *= fh[(cid * 6 + f) * NF + tt];
+                fnb *= fh[((int64_t)nb * 6 + (f ^ 1)) * NF + tt];
+                g = tau * 0.5 * (fo + fnb);
+            }
+            sG[lc][tt] = g;
+        }
+        __syncthreads();
+        if (act) sA[lc][f * NF + tt] = trace_t<N>(sB, sG[lc], a, b);
+        __syncthreads();
+    }
+    if (act) {
+        add_faces<N>(sA[lc], a, b, Y);
+        const int64_t o = cid * ND + N * a + NF * b;
+        for (int i = 0; i < N; ++i) qv[o + i] = Y[i];
+    }
+}
+
+template <int N>
+hipError_t grad_n(hx_ctx *c, const double *p, double *u3)
+{
+    const int cpb = PCfg<N>::CPB;
+    const int nb = (int)((c->n_cells + cpb - 1) / cpb);
+    hipLaunchKernelGGL(k_grad<N>, dim3(nb), dim3(PCfg<N>::NT), 0, c->stream, p, u3, c->n_dofs,
+                       c->psW, c->psFn, c->nbr, c->ref, c->ps_tau, (int)c->n_cells);
+    return hipGetLastError();
+}
+
+template <int N>
+hipError_t div_n(hx_ctx *c, const double *u3, double *q)
+{
+    const int cpb = PCfg<N>::CPB;
+    const int nb = (int)((c->n_cells + cpb - 1) / cpb);
+    hipLaunchKernelGGL(k_div<N>, dim3(nb), dim3(PCfg<N>::NT), 0, c->stream, u3, q, c->n_dofs, c->psWC,
+                       c->psFn, c->psFh, c->nbr, c->ref, c->ps_tau, (int)c->n_cells);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_grad(hx_ctx *c, const double *p, double *u3)
+{
+    switch (c->n) {
+    case 2: return grad_n<2>(c, p, u3);
+    case 3: return grad_n<3>(c, p, u3);
+    case 4: return grad_n<4>(c, p, u3);
+    case 5: return grad_n<5>(c, p, u3);
+    case 6: return grad_n<6>(c, p, u3);
+    case 7: return grad_n<7>(c, p, u3);
+    case 8: return grad_n<8>(c, p, u3);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_div(hx_ctx *c, const double *u3, double *q)
+{
+    switch (c->n) {
+    case 2: return div_n<2>(c, u3, q);
+    case 3: return div_n<3>(c, u3, q);
+    case 4: return div_n<4>(c, u3, q);
+    case 5: return div_n<5>(c, u3, q);
+    case 6: return div_n<6>(c, u3, q);
+    case 7: return div_n<7>(c, u3, q);
+    case 8: return div_n<8>(c, u3, q);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// y = S x = D x - C A^-1 B x, or y = b - S x when b is given
+hipError_t press_apply64(hx_ctx *c, const double *x, double *y, const double *b)
+{
+    const int64_t n = c->n_dofs, nd = c->nd;
+    double *u3 = c->psWork, *v3 = u3 + 3 * n, *q = v3 + 3 * n;
+    hipError_t e = launch_grad(c, x, u3);
+    for (int ec = 0; ec < 3 && e == hipSuccess; ++ec)
+        e = launch_mass64(c, c->psMr, nd, 1, u3 + ec * n, v3 + ec * n);
+    if (e == hipSuccess) e = launch_div(c, v3, q);
+    if (e == hipSuccess) e = launch_mass64(c, c->psMd, nd, 0, x, y);
+    if (e == hipSuccess) e = blas_axpby(c, n, -1.0, q, 1.0, y);
+    if (e == hipSuccess && b) e = blas_axpby(c, n, 1.0, b, -1.0, y);
+    return e;
+}
+
+}  // namespace hx

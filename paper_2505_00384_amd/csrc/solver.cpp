@@ -324,6 +324,14 @@ struct Hess {
 //    block dot that finalises its last column.  Convergence is tested on the
 //    provisional column (the correction is of the order of the loss of
 //    orthogonality) and confirmed after finalising it.
+// y = M x or y = b - M x for the system being solved: the Helmholtz-type
+// operator, or the pressure system S = D - C A^-1 B
+static hipError_t sys_apply(hx_ctx *c, const hx_solve_params *prm, const double *x, double *y,
+                            const double *b)
+{
+    return prm->system == 1 ? press_apply64(c, x, y, b) : launch_apply64(c, x, y, b);
+}
+
 hx_status solve_fgmres(hx_ctx *c, const hx_solve_params *prm, const double *b, double *x,
                        hx_solve_info *info, Timer &tm)
 {
@@ -392,7 +400,7 @@ hx_status solve_fgmres(hx_ctx *c, const hx_solve_params *prm, const double *b, d
 
     while (!done && it < prm->max_iter) {
         // explicit residual
-        HX_HIP(c, launch_apply64(c, x, V, b));
+        HX_HIP(c, sys_apply(c, prm, x, V, b));
         HX_HIP(c, blas_dot(c, n, V, V, sc + 128));
         if ((s = read_scalars(c, sc + 128, 1, tmp)) != HX_OK) return s;
         const double beta = std::sqrt(tmp[0]);
@@ -415,7 +423,7 @@ hx_status solve_fgmres(hx_ctx *c, const hx_solve_params *prm, const double *b, d
                 break;
             }
             tm.rec(1, c->stream);
-            HX_HIP(c, launch_apply64(c, zj, w, nullptr));
+            HX_HIP(c, sys_apply(c, prm, zj, w, nullptr));
             tm.rec(2, c->stream);
             if (!delayed) {
                 // CGS2
@@ -572,6 +580,7 @@ void hx_default_params(hx_solve_params *p)
     p->stall_window = 10;
     p->stall_ratio = 0.99;
     p->orth = 1;
+    p->system = 0;
 }
 
 hx_status hx_solve(hx_ctx *c, const hx_solve_params *prm, const double *b, double *x,
@@ -599,6 +608,10 @@ hx_status hx_solve(hx_ctx *c, const hx_solve_params *prm, const double *b, doubl
     if (prm->mixed && prm->pc == HX_PC_LEARNED)
         return fail(c, HX_ERR_ARG, "the learned preconditioner is FP64; it cannot precondition the inner FP32 solve");
     if (prm->pc == HX_PC_LEARNED && !c->mlp) return fail(c, HX_ERR_STATE, "no network loaded");
+    if (prm->system != 0 && prm->system != 1) return fail(c, HX_ERR_ARG, "system must be 0 or 1");
+    if (prm->system == 1 && !c->has_press) return fail(c, HX_ERR_STATE, "pressure system not set");
+    if (prm->system == 1 && prm->method != 1)
+        return fail(c, HX_ERR_ARG, "the pressure system is not symmetric; use FGMRES");
     HX_HIP(c, hipSetDevice(c->device));
     const double t0 = now_ms();
     Timer tm(true);
@@ -613,7 +626,7 @@ hx_status hx_solve(hx_ctx *c, const hx_solve_params *prm, const double *b, doubl
     double *sc = c->red + SC_OFF;
     hx_status s2 = ensure_work(c, (size_t)n, 0);
     if (s2 != HX_OK) return s2;
-    HX_HIP(c, launch_apply64(c, x, c->work64, b));
+    HX_HIP(c, sys_apply(c, prm, x, c->work64, b));
     HX_HIP(c, blas_dot(c, n, c->work64, c->work64, sc + 200));
     HX_HIP(c, blas_dot(c, n, b, b, sc + 201));
     double hh[2];

@@ -228,6 +228,20 @@ def terrain_coefficients():
     return a, b
 
 
+def terrain_pressure_fields(gamma: float = 1.4):
+    """Fields of the pressure system on the isothermal background: density
+    ratio rho/rho0 = exp(-z/H) and the specific enthalpy of an isothermal
+    ideal gas, h = c^2/(gamma - 1) (constant), as functions of (x, y, z)."""
+    T = TERRAIN
+
+    def rho(x, y, z):
+        return np.exp(-np.asarray(z, dtype=np.float64) / T["H"])
+
+    def h(x, y, z):
+        return np.full_like(np.asarray(x, dtype=np.float64), T["c"] ** 2 / (gamma - 1.0))
+    return rho, h
+
+
 def random_smooth_coefficients(seed: int, lo=0.5, hi=2.0, scale=1.0):
     """Smooth positive fields: lo + (hi-lo) * (1 + sin(...)) / 2, random phases.
 
