@@ -266,6 +266,23 @@ hx_status hx_pressure_rhs(hx_ctx *c, const double *F, const double *G, double *r
 /* U[3][n] = A^-1 (F - B P): the velocity of the stage once P is known. */
 hx_status hx_pressure_velocity(hx_ctx *c, const double *F, const double *P, double *U);
 
+/* Fixed-point solve of the pressure system (section 2; the coefficients of
+ * the system and of its Helmholtz preconditioner are re-evaluated from the
+ * previous iterate, section 3.1).  For m = 0, 1, ...: h = gamma p_m /
+ * ((gamma - 1) rho) at the nodes (ideal gas), hx_set_pressure_system(rho, h),
+ * p_{m+1} = solution of S(h) p = G - C(h) A^-1 F by hx_solve with prm
+ * (system 1 and the previous iterate as initial guess are imposed); stop when
+ * ||p_{m+1} - p_m|| <= fp_tol ||p_{m+1}|| or after max_fp_iters iterations.
+ * rho [n], F [3][n], G [n], p [n] DEVICE FP64; p holds p_0 and receives the
+ * last iterate.  *fp_iters, *fp_change (HOST, may be NULL): iterations done and
+ * the last relative change; info: the last linear solve.  Returns HX_OK or
+ * HX_ERR_NOCONV (fixed point or linear solve not converged). */
+hx_status hx_solve_pressure_fixed_point(hx_ctx *c, const double *rho, const double *F,
+                                        const double *G, double *p, double gamma, double tau,
+                                        double penalty_factor, const hx_solve_params *prm,
+                                        int max_fp_iters, double fp_tol, int *fp_iters,
+                                        double *fp_change, hx_solve_info *info);
+
 /* ---------------------------------------------------------------------- */
 /* BLAS-1 helpers on the context stream (step a6), FP64 device vectors      */
 /* ---------------------------------------------------------------------- */

@@ -95,6 +95,10 @@ def load(path: str = LIB_PATH):
         "hx_apply_pressure_part": ([vp, C.c_int, vp, vp], C.c_int),
         "hx_pressure_rhs": ([vp, vp, vp, vp], C.c_int),
         "hx_pressure_velocity": ([vp, vp, vp, vp], C.c_int),
+        "hx_solve_pressure_fixed_point": ([vp, vp, vp, vp, vp, C.c_double, C.c_double, C.c_double,
+                                           C.POINTER(SolveParams), C.c_int, C.c_double,
+                                           C.POINTER(C.c_int), C.POINTER(C.c_double),
+                                           C.POINTER(SolveInfo)], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -216,6 +220,23 @@ class HelmDG:
         U = self.torch.empty_like(F)
         self._chk(self.L.hx_pressure_velocity(self.h, _ptr(F), _ptr(P), _ptr(U)), "pressure_velocity")
         return U
+
+    def solve_pressure_fixed_point(self, rho, F, G, p, gamma: float, tau: float,
+                                   params: Optional[SolveParams] = None, max_fp_iters: int = 20,
+                                   fp_tol: float = 1e-10, penalty: float = 2.0, check: bool = True):
+        """p (device, in/out): initial iterate, then the fixed point."""
+        if params is None:
+            params = default_params(method=1)
+        info = SolveInfo()
+        it = C.c_int(); ch = C.c_double()
+        st = self.L.hx_solve_pressure_fixed_point(
+            self.h, _ptr(rho), _ptr(F), _ptr(G), _ptr(p), float(gamma), float(tau), float(penalty),
+            C.byref(params), int(max_fp_iters), float(fp_tol), C.byref(it), C.byref(ch),
+            C.byref(info))
+        if check and st not in (HX_OK, HX_ERR_NOCONV):
+            self._chk(st, "solve_pressure_fixed_point")
+        return p, dict(status=st, fp_iters=it.value, fp_change=ch.value, iters=info.iters,
+                       true_rel_res=info.true_rel_res, ms_total=info.ms_total)
 
     # -- operator -------------------------------------------------------------
     def apply_operator(self, x, y=None):

@@ -143,6 +143,8 @@ hipError_t launch_press_setup(hx_ctx *c, const double *rho, const double *h, dou
 hipError_t launch_grad(hx_ctx *c, const double *p, double *u3);
 hipError_t launch_div(hx_ctx *c, const double *u3, double *q);
 hipError_t press_apply64(hx_ctx *c, const double *x, double *y, const double *b);
+// h = gamma p / ((gamma - 1) rho) at the nodes
+hipError_t launch_enthalpy(hx_ctx *c, const double *p, const double *rho, double gamma, double *h);
 hipError_t launch_massinv32(hx_ctx *c, const float *r, float *z);
 hipError_t launch_cg_massinv64(hx_ctx *c, double *x, double *r, const double *p, const double *q,
                                double *z, const double *sc, int *nblk);

@@ -367,7 +367,23 @@ hipError_t div_n(hx_ctx *c, const double *u3, double *q)
     return hipGetLastError();
 }
 
+// h = gamma p / ((gamma - 1) rho): specific enthalpy of an ideal gas
+__global__ void k_enthalpy(int64_t n, const double *__restrict__ p, const double *__restrict__ rho,
+                           double f, double *h)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) h[i] = f * p[i] / rho[i];
+}
+
 }  // namespace
+
+hipError_t launch_enthalpy(hx_ctx *c, const double *p, const double *rho, double gamma, double *h)
+{
+    const int64_t n = c->n_dofs;
+    hipLaunchKernelGGL(k_enthalpy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, n, p,
+                       rho, gamma / (gamma - 1.0), h);
+    return hipGetLastError();
+}
 
 hipError_t launch_grad(hx_ctx *c, const double *p, double *u3)
 {

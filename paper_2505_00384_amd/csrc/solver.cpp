@@ -645,4 +645,61 @@ hx_status hx_solve(hx_ctx *c, const hx_solve_params *prm, const double *b, doubl
     return st;
 }
 
+
+hx_status hx_solve_pressure_fixed_point(hx_ctx *c, const double *rho, const double *F,
+                                        const double *G, double *p, double gamma, double tau,
+                                        double penalty_factor, const hx_solve_params *prm,
+                                        int max_fp_iters, double fp_tol, int *fp_iters,
+                                        double *fp_change, hx_solve_info *info)
+{
+    if (!c) return HX_ERR_ARG;
+    if (!rho || !F || !G || !p || !prm || !info) return fail(c, HX_ERR_ARG, "null argument");
+    if (!c->has_mesh) return fail(c, HX_ERR_STATE, "fixed point before setup_mesh");
+    if (max_fp_iters < 1 || !(fp_tol > 0.0)) return fail(c, HX_ERR_ARG, "bad fixed-point limits");
+    if (prm->method != 1) return fail(c, HX_ERR_ARG, "the pressure system needs FGMRES");
+    HX_HIP(c, hipSetDevice(c->device));
+    const int64_t n = c->n_dofs;
+    double *tmp = nullptr;      // h, rhs, p_new
+    hx_status s = dalloc(c, (void **)&tmp, sizeof(double) * 3 * n);
+    if (s != HX_OK) return s;
+    double *h = tmp, *rhs = tmp + n, *pn = tmp + 2 * n;
+    double *sc = c->red + SC_OFF + 300;
+    hx_solve_params q = *prm;
+    q.system = 1;
+    q.x0_mode = 1;
+    int it = 0;
+    double change = 0.0;
+    bool conv = false, lin_ok = true;
+    for (it = 0; it < max_fp_iters && !conv; ++it) {
+        hipError_t e = launch_enthalpy(c, p, rho, gamma, h);
+        if (e != hipSuccess) { s = fail(c, HX_ERR_DEVICE, "enthalpy: %s", hipGetErrorString(e)); break; }
+        if ((s = hx_set_pressure_system(c, rho, h, gamma, tau, penalty_factor, 1)) != HX_OK) break;
+        if ((s = hx_pressure_rhs(c, F, G, rhs)) != HX_OK) break;
+        e = hipMemcpyAsync(pn, p, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream);
+        if (e != hipSuccess) { s = fail(c, HX_ERR_DEVICE, "copy: %s", hipGetErrorString(e)); break; }
+        s = hx_solve(c, &q, rhs, pn, info);
+        if (s != HX_OK && s != HX_FALLBACK_USED && s != HX_ERR_NOCONV) break;
+        lin_ok = s != HX_ERR_NOCONV;
+        s = HX_OK;
+        // change = ||p_new - p|| / ||p_new||; then p = p_new
+        e = blas_axpby(c, n, 1.0, pn, -1.0, p);
+        if (e == hipSuccess) e = blas_dot(c, n, p, p, sc);
+        if (e == hipSuccess) e = blas_dot(c, n, pn, pn, sc + 1);
+        if (e == hipSuccess) e = hipMemcpyAsync(p, pn, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream);
+        if (e != hipSuccess) { s = fail(c, HX_ERR_DEVICE, "update: %s", hipGetErrorString(e)); break; }
+        double hh[2];
+        if ((s = read_scalars(c, sc, 2, hh)) != HX_OK) break;
+        change = hh[1] > 0.0 ? std::sqrt(hh[0] / hh[1]) : std::sqrt(hh[0]);
+        conv = change <= fp_tol;
+    }
+    dfree((void **)&tmp);
+    if (fp_iters) *fp_iters = it;
+    if (fp_change) *fp_change = change;
+    if (s != HX_OK) return s;
+    if (!conv || !lin_ok)
+        return fail(c, HX_ERR_NOCONV, "fixed point: change %.3e after %d iterations%s", change, it,
+                    lin_ok ? "" : " (last linear solve not converged)");
+    return HX_OK;
+}
+
 }  // extern "C"

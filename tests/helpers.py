@@ -53,3 +53,39 @@ TINY = [
     ("ragged-7x1x1", lambda: si.box_mesh(7, 1, 1, periodic=(True, False, True),
                                           mapping=si.random_affine_mapping(9))),
 ]
+
+
+def oracle_fixed_point(mesh, k, rho, F, G, p0, gamma, tau, iters):
+    """The fixed point of the pressure system, step by step in the oracle:
+    h from the previous iterate (ideal gas, h = gamma p / ((gamma - 1) rho)),
+    rebuild the system, solve it tightly (FGMRES, inverse Helmholtz diagonal)."""
+    from oracle.core import PressureSystem
+    p = np.array(p0, dtype=np.float64)
+    for _ in range(iters):
+        h = gamma * p / ((gamma - 1.0) * rho)
+        ref = PressureSystem(mesh, k, rho, h, gamma, tau)
+        helm = oracle.Problem(mesh, k, alpha=np.full(p.size, 1.0 / (gamma - 1.0)),
+                              beta=tau ** 2 * h)
+        dinv = 1.0 / helm.cell_diagonal(stiff=True)
+        p, info = oracle.solvers.fgmres(ref.apply, ref.rhs(F, G), precond=lambda v: dinv * v,
+                                        restart=30, rtol=1e-13, max_iter=5000, x0=p)
+        assert info.converged
+    return p
+
+
+def constructed_pressure_state(mesh, k, gamma):
+    """A perturbed hydrostatic pressure p* on the terrain channel and data
+    (rho, F, G) for which p* is the fixed point: G = S(h(p*)) p* + C A^-1 F.
+    Returns rho, F, G, p_background, p_star, tau."""
+    from oracle.core import PressureSystem
+    p_or = oracle.Problem(mesh, k)
+    x, y, z = p_or.dof_coords()
+    T = si.TERRAIN
+    rho = np.exp(-z / T["H"])
+    p_bg = 1e5 * np.exp(-z / T["H"])
+    p_star = p_bg * (1.0 + 0.02 * np.sin(2 * np.pi * x / T["Lx"]) * np.cos(np.pi * z / T["Lz"]))
+    F = 10.0 * rho * np.stack([si.rhs_terrain(s)(x, y, z) for s in (41, 42, 43)])
+    tau = T["dt"]
+    ref = PressureSystem(mesh, k, rho, gamma * p_star / ((gamma - 1.0) * rho), gamma, tau)
+    G = ref.apply(p_star) + ref.div(ref.a_inv(F))
+    return rho, F, G, p_bg, p_star, tau

@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 import synth_inputs as si
-from helpers import TINY, to_dev
+from helpers import TINY, constructed_pressure_state, oracle_fixed_point, to_dev
 from oracle.core import PressureSystem
 
 pytestmark = pytest.mark.gpu
@@ -155,4 +155,35 @@ def test_pressure_system_errors():
     with pytest.raises(hx.HXError) as e:
         ctx.apply_pressure_part(7, v)
     assert e.value.status == hx.HX_ERR_ARG
+    ctx.close()
+
+
+def test_fixed_point_recovers_constructed_state():
+    """G is built so that a perturbed hydrostatic pressure p* is the fixed
+    point; the GPU loop started from the unperturbed background converges to
+    it, and its first two iterates equal the oracle's."""
+    hx = _hx()
+    m = si.terrain_mesh(4, 2, 3, g=4)
+    k = 4
+    p_or = oracle.Problem(m, k)
+    rho, F, G, p_bg, p_star, tau = constructed_pressure_state(m, k, GAMMA)
+    ctx = hx.HelmDG(0)
+    ctx.setup_mesh(k, p_or.nodes, p_or.nbr, p_or.g)
+    prm = hx.default_params(method=1, restart=30, rtol=1e-13, pc=hx.HX_PC_HELMHOLTZ_DIAG,
+                            max_iter=5000)
+    # two iterations against the oracle's two
+    pd = to_dev(p_bg)
+    pd, info = ctx.solve_pressure_fixed_point(to_dev(rho), to_dev(F), to_dev(G), pd, GAMMA, tau,
+                                              params=prm, max_fp_iters=2, fp_tol=1e-300,
+                                              check=False)
+    assert info["fp_iters"] == 2 and info["status"] == hx.HX_ERR_NOCONV
+    p2 = oracle_fixed_point(m, k, rho, F, G, p_bg, GAMMA, tau, 2)
+    assert np.linalg.norm(pd.cpu().numpy() - p2) <= 1e-10 * np.linalg.norm(p2)
+    # to convergence
+    pd = to_dev(p_bg)
+    pd, info = ctx.solve_pressure_fixed_point(to_dev(rho), to_dev(F), to_dev(G), pd, GAMMA, tau,
+                                              params=prm, max_fp_iters=30, fp_tol=1e-11)
+    print(f"[pressure] fixed point: {info}", flush=True)
+    assert info["status"] == hx.HX_OK and info["fp_iters"] < 30
+    assert np.linalg.norm(pd.cpu().numpy() - p_star) <= 1e-9 * np.linalg.norm(p_star)
     ctx.close()

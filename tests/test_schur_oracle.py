@@ -12,7 +12,9 @@ central fluxes.  Each pin comes from the mathematics, not from the oracle:
 * with a constant hr the pressure system is symmetric positive definite
   (S = D + c B^T A^-1 B), with a variable hr it is not symmetric;
 * consistency: on periodic cubes S applied to a smooth periodic p approaches
-  the load vector of p/(gamma-1) - tau^2 hr/rho lap p as the mesh is refined.
+  the load vector of p/(gamma-1) - tau^2 hr/rho lap p as the mesh is refined;
+* the fixed point (h re-evaluated from the previous iterate) converges to a
+  state p* built to be its fixed point.
 """
 import numpy as np
 import pytest
@@ -20,6 +22,7 @@ import pytest
 import oracle
 import synth_inputs as si
 from oracle.core import PressureSystem
+from helpers import constructed_pressure_state, oracle_fixed_point
 
 AFFINE = [
     ("cube3-periodic", lambda: si.cube_mesh(3)),
@@ -117,3 +120,11 @@ def test_pressure_system_consistency():
         ref = p.load_vector(lambda X, Y, Z: lam * f(X, Y, Z))
         errs.append(np.linalg.norm(Sp - ref) / np.linalg.norm(ref))
     assert errs[1] < 0.05 and errs[1] < errs[0] / 3, errs
+
+
+def test_fixed_point_converges_to_constructed_state():
+    m = si.terrain_mesh(4, 2, 3, g=4)
+    rho, F, G, p_bg, p_star, tau = constructed_pressure_state(m, 4, 1.4)
+    errs = [np.linalg.norm(oracle_fixed_point(m, 4, rho, F, G, p_bg, 1.4, tau, it) - p_star)
+            / np.linalg.norm(p_star) for it in (1, 5)]
+    assert errs[0] < 1e-2 and errs[1] < 1e-9, errs
