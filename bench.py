@@ -140,6 +140,79 @@ def solve_suite(hx, ctx, b, torch, forms, label):
     return out
 
 
+def time_call(fn, reps, torch):
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def pressure_suite(hx, ctx, torch, label, forms, reps=10, fixed_point=False):
+    """The pressure system of the IMEX stage (S = D - C A^-1 B) on the
+    isothermal background: timing of S and its parts, FGMRES solves of
+    S p = G - C A^-1 F, and (optionally) the fixed point from a state p*
+    built, with the library itself, to be its solution."""
+    import synth_inputs as si
+    gamma, T = 1.4, si.TERRAIN
+    xyz = ctx.dof_coordinates()
+    frho, fh = si.terrain_pressure_fields(gamma)
+    rho, h = field_on_device(frho, xyz, torch), field_on_device(fh, xyz, torch)
+    ctx.set_pressure_system(rho, h, gamma, T["dt"])
+    n = ctx.n_dofs
+    p = field_on_device(si.rhs_terrain(5), xyz, torch)
+    u3 = torch.stack([field_on_device(si.rhs_terrain(s), xyz, torch) for s in (6, 7, 8)])
+    out = {}
+    for name, part, arg in (("S", hx.HX_PS_SYSTEM, p), ("B", hx.HX_PS_GRAD, p),
+                            ("C", hx.HX_PS_DIV, u3), ("A_inv_3", hx.HX_PS_VMASS_INV, u3),
+                            ("D", hx.HX_PS_DMASS, p)):
+        out[f"ms_{name}"] = round(time_call(lambda: ctx.apply_pressure_part(part, arg), reps, torch), 3)
+    G = field_on_device(si.rhs_terrain(9), xyz, torch)
+    b = ctx.pressure_rhs(u3, G)
+    res = {}
+    for name, prm in forms:
+        x = torch.zeros_like(b)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        x, info = ctx.solve(b, x, prm)
+        torch.cuda.synchronize()
+        res[name] = dict(ms=round((time.time() - t0) * 1e3, 3), iters=info["iters"],
+                         inner_iters=info["inner_iters"], true_rel_res=info["true_rel_res"],
+                         status=hx.STATUS_NAMES[info["status"]])
+        log(f"{label} pressure {name}: {res[name]}")
+    out["solve"] = res
+    if fixed_point:
+        # p* = perturbed hydrostatic pressure; G chosen so that p* is the fixed point
+        z = xyz[2]
+        p_bg = 1e5 * torch.exp(-z / T["H"])
+        p_star = p_bg * (1.0 + 0.02 * torch.sin(2 * np.pi * xyz[0] / T["Lx"])
+                         * torch.cos(np.pi * z / T["Lz"]))
+        h_star = gamma * p_star / ((gamma - 1.0) * rho)
+        ctx.set_pressure_system(rho, h_star, gamma, T["dt"])
+        F = 10.0 * rho * u3
+        G = ctx.apply_pressure_part(hx.HX_PS_SYSTEM, p_star) + (G - ctx.pressure_rhs(F, G))
+        pf = p_bg.clone()
+        prm = hx.default_params(method=1, restart=30, rtol=1e-10, max_iter=5000,
+                                pc=hx.HX_PC_BLOCK_JACOBI)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        pf, info = ctx.solve_pressure_fixed_point(rho, F, G, pf, gamma, T["dt"], params=prm,
+                                                  max_fp_iters=30, fp_tol=1e-9)
+        torch.cuda.synchronize()
+        err = float(torch.linalg.norm(pf - p_star) / torch.linalg.norm(p_star))
+        out["fixed_point"] = dict(ms=round((time.time() - t0) * 1e3, 1), fp_iters=info["fp_iters"],
+                                  last_change=info["fp_change"], rel_error_vs_p_star=err,
+                                  status=hx.STATUS_NAMES[info["status"]])
+        log(f"{label} pressure fixed point: {out['fixed_point']}")
+    del xyz, rho, h, p, u3, G, b
+    return out
+
+
 def cpu_baseline(layers: int):
     """Oracle matvec on the bottom `layers` cell layers of the 256x64x64 terrain
     channel (same cells, same fields), all host cores."""
@@ -225,6 +298,7 @@ def main():
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic)
 
     solve = {}
+    pressure = {}
     if not args.no_solve:
         b = x
         forms = [
@@ -241,6 +315,12 @@ def main():
         del y
         solve[f"terrain{args.nx}x{args.ny}x{args.nz}"] = solve_suite(hx, ctx, b, torch,
                                                                      forms + cg_forms, "C3")
+        # the pressure system of the stage on the same mesh: FGMRES with the
+        # block Jacobi of the Helmholtz-type operator
+        pressure[f"terrain{args.nx}x{args.ny}x{args.nz}"] = pressure_suite(
+            hx, ctx, torch, "C3",
+            [("fgmres_bj", hx.default_params(method=1, system=1, restart=30, rtol=1e-8,
+                                             max_iter=5000, pc=hx.HX_PC_BLOCK_JACOBI))])
         ctx.close()
     if not args.no_solve and args.solves == "all":
         del b, x
@@ -267,6 +347,15 @@ def main():
         solve["terrain32x8x16"] = solve_suite(hx, ctx2, b2, torch, forms2, "C2")
         solve["learned_training_s"] = round(t_train, 2)
         w = ctx2.get_network()
+        pressure["terrain32x8x16"] = pressure_suite(hx, ctx2, torch, "C2", [
+            ("fgmres_helmholtz_diag", hx.default_params(method=1, system=1, restart=30, rtol=1e-8,
+                                                        max_iter=20000, pc=hx.HX_PC_HELMHOLTZ_DIAG)),
+            ("fgmres_mass_diag", hx.default_params(method=1, system=1, restart=30, rtol=1e-8,
+                                                   max_iter=20000, pc=hx.HX_PC_MASS_DIAG)),
+            ("fgmres_bj", hx.default_params(method=1, system=1, restart=30, rtol=1e-8,
+                                            max_iter=20000, pc=hx.HX_PC_BLOCK_JACOBI)),
+            ("fgmres_inner_cg", hx.default_params(method=1, system=1, restart=10, rtol=1e-8,
+                                                  mixed=1, inner_iters=32))], fixed_point=True)
         ctx2.close()
         # the periodic unit cube: degree 2 CG + block Jacobi to 1e-10, and the
         # learned form at degree 4 on the same mesh
@@ -312,6 +401,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "solve": solve,
+        "pressure_system": pressure,
         "setup": setup_times,
         **extra,
     }
