@@ -55,6 +55,19 @@ __device__ __forceinline__ double trace_at(const double *sB, const double *v, in
     return s;
 }
 
+// the same from a face layer already gathered as v[e1 + N e2]
+template <int N>
+__device__ __forceinline__ double trace_at2(const double *sB, const double *v, int a, int b)
+{
+    double s = 0.0;
+    for (int e2 = 0; e2 < N; ++e2) {
+        double r = 0.0;
+        for (int e1 = 0; e1 < N; ++e1) r += sB[a * N + e1] * v[e1 + N * e2];
+        s += sB[b * N + e2] * r;
+    }
+    return s;
+}
+
 // transposed contraction of a face field g[a + N b] to node (e1, e2)
 template <int N>
 __device__ __forceinline__ double trace_t(const double *sB, const double *g, int e1, int e2)
@@ -206,6 +219,7 @@ k_grad(const double *__restrict__ p, double *__restrict__ u3, int64_t nt,
     __shared__ double sF[CPB][3][ND];
     __shared__ double sG[CPB][3][NF];
     __shared__ double sA[CPB][3][6 * NF];
+    __shared__ double sL[CPB][NF];
     const int t = threadIdx.x;
     const int lc0 = t / NF;
     const bool slot = lc0 < CPB;
@@ -238,17 +252,17 @@ k_grad(const double *__restrict__ p, double *__restrict__ u3, int64_t nt,
         }
         grad_t<N>(sB, sD, sF[lc][0], sF[lc][1], sF[lc][2], act, a, b, t0, t1, t2, tau, Y[ec]);
     }
-    // faces: tau ds n_e p^ at the Gauss points, back to the face-layer nodes
+    // faces: tau ds n_e p^ at the Gauss points, back to the face-layer nodes;
+    // the neighbour's face layer is gathered into LDS first (one value per lane)
     for (int f = 0; f < 6; ++f) {
         const int d = f >> 1, s = f & 1;
+        const int32_t nb = act ? nbr[6 * cid + f] : -1;
+        if (nb >= 0) sL[lc][tt] = p[(int64_t)nb * ND + lay<N>(d, s ? 0 : N - 1, a, b)];
+        __syncthreads();
         if (act) {
-            const int32_t nb = nbr[6 * cid + f];
             const double po = trace_at<N>(sB, sP[lc], d, s ? N - 1 : 0, a, b);
             double ph = po;
-            if (nb >= 0) {
-                const double pn = trace_at<N>(sB, p + (int64_t)nb * ND, d, s ? 0 : N - 1, a, b);
-                ph = 0.5 * (po + pn);
-            }
+            if (nb >= 0) ph = 0.5 * (po + trace_at2<N>(sB, sL[lc], a, b));
             const double *fnc = fn + (cid * 6 + f) * 3 * NF + tt;
             for (int ec = 0; ec < 3; ++ec) sG[lc][ec][tt] = tau * ph * fnc[ec * NF];
         }
@@ -278,6 +292,7 @@ k_div(const double *__restrict__ u3, double *__restrict__ qv, int64_t nt,
     __shared__ double sF[CPB][3][ND];
     __shared__ double sG[CPB][NF];
     __shared__ double sA[CPB][6 * NF];
+    __shared__ double sL[CPB][3][NF];
     const int t = threadIdx.x;
     const int lc0 = t / NF;
     const bool slot = lc0 < CPB;
@@ -314,19 +329,24 @@ k_div(const double *__restrict__ u3, double *__restrict__ qv, int64_t nt,
         }
     }
     grad_t<N>(sB, sD, sF[lc][0], sF[lc][1], sF[lc][2], act, a, b, t0, t1, t2, tau, Y);
-    // interior faces: tau ds {hr u . n_K} at the Gauss points, back to the nodes
+    // interior faces: tau ds {hr u . n_K} at the Gauss points, back to the
+    // nodes; the neighbour's face layers are gathered into LDS first
     for (int f = 0; f < 6; ++f) {
         const int d = f >> 1, s = f & 1;
+        const int32_t nb = act ? nbr[6 * cid + f] : -1;
+        if (nb >= 0) {
+            const int64_t o = (int64_t)nb * ND + lay<N>(d, s ? 0 : N - 1, a, b);
+            for (int ec = 0; ec < 3; ++ec) sL[lc][ec][tt] = u3[ec * nt + o];
+        }
+        __syncthreads();
         if (act) {
-            const int32_t nb = nbr[6 * cid + f];
             double g = 0.0;
             if (nb >= 0) {
                 const double *fnc = fn + (cid * 6 + f) * 3 * NF + tt;
                 double fo = 0.0, fnb = 0.0;
                 for (int ec = 0; ec < 3; ++ec) {
                     const double uo = trace_at<N>(sB, sU[lc][ec], d, s ? N - 1 : 0, a, b);
-                    const double un = trace_at<N>(sB, u3 + ec * nt + (int64_t)nb * ND, d, s ? 0 : N - 1,
-                                                  a, b);
+                    const double un = trace_at2<N>(sB, sL[lc][ec], a, b);
                     fo += uo * fnc[ec * NF];
                     fnb += un * fnc[ec * NF];
                 }
