@@ -63,6 +63,8 @@ def lib():
         L.or_mass_block_apply.restype = C.c_int
         L.or_grad_apply.argtypes = [pp, C.c_double, dp, dp]
         L.or_div_apply.argtypes = [pp, C.c_double, dp, dp, dp]
+        L.or_grad_apply_cells.argtypes = [pp, C.c_double, C.c_void_p, C.c_long, dp, dp]
+        L.or_div_apply_cells.argtypes = [pp, C.c_double, dp, C.c_void_p, C.c_long, dp, dp]
         L.or_apply_cells.argtypes = [pp, C.c_int, C.c_void_p, C.c_long, dp, dp]
         L.or_bj_cell_data.argtypes = [pp, C.c_long, dp, dp, dp, dp]
         L.or_bj_sep_block.argtypes = [pp, C.c_long, dp]
@@ -248,6 +250,25 @@ class Problem:
         lib().or_div_apply(self._s(), float(tau), _dp(hr), _dp(u3), _dp(q))
         return q
 
+    def grad_cells(self, p, cells, tau: float = 1.0):
+        """B p on the listed cells only: [len(cells), 3, nd]."""
+        p = np.ascontiguousarray(p, dtype=np.float64)
+        cells = np.ascontiguousarray(cells, dtype=np.int64)
+        out = np.zeros(cells.size * 3 * self.nd)
+        lib().or_grad_apply_cells(self._s(), float(tau), cells.ctypes.data, cells.size, _dp(p), _dp(out))
+        return out.reshape(cells.size, 3, self.nd)
+
+    def div_cells(self, u3, hr, cells, tau: float = 1.0):
+        """C u on the listed cells only (u3 [3, n_dofs] needs valid values on
+        those cells and their face neighbours): [len(cells), nd]."""
+        u3 = np.ascontiguousarray(u3, dtype=np.float64).reshape(-1)
+        hr = np.ascontiguousarray(hr, dtype=np.float64)
+        cells = np.ascontiguousarray(cells, dtype=np.int64)
+        out = np.zeros(cells.size * self.nd)
+        lib().or_div_apply_cells(self._s(), float(tau), _dp(hr), cells.ctypes.data, cells.size,
+                                 _dp(u3), _dp(out))
+        return out.reshape(cells.size, self.nd)
+
     # block Jacobi ----------------------------------------------------------
     def bj_cell_data(self, c: int):
         ell = np.zeros(3); ab = np.zeros(1); bb = np.zeros(1); sig = np.zeros(6)
@@ -305,3 +326,21 @@ class PressureSystem:
 
     def velocity(self, F, p):
         return self.a_inv(np.asarray(F) - self.grad(p))
+
+    def apply_cells(self, p, cells):
+        """S p on the listed cells only, from the cells' two-layer stencil:
+        B p on the cells and their face neighbours, A^-1 per cell by a dense
+        solve of its mass block, C on the cells, D p on the cells."""
+        cells = np.asarray(cells, dtype=np.int64)
+        nbr = self.vel.nbr
+        stencil = np.unique(np.concatenate([cells, nbr[cells].ravel()]))
+        stencil = stencil[stencil >= 0]
+        nd, n = self.vel.nd, self.n_dofs
+        bp = self.vel.grad_cells(p, stencil, self.tau)          # [ms, 3, nd]
+        v3 = np.zeros((3, n))
+        for s, c in enumerate(stencil):
+            Mb = self.vel.mass_block(int(c))
+            v3[:, c * nd:(c + 1) * nd] = np.linalg.solve(Mb, bp[s].T).T
+        cq = self.vel.div_cells(v3, self.hr, cells, self.tau)   # [m, nd]
+        dq = self.pmass.apply_cells(p, cells, OR_CELL)
+        return dq - cq

@@ -1080,3 +1080,22 @@ void or_div_apply(const or_prob *p, double tau, const double *hr, const double *
 #pragma omp parallel for schedule(dynamic, 4)
     for (long c = 0; c < p->n_cells; ++c) div_one_cell(p, tau, hr, c, u3, qv + c * nd);
 }
+
+/* the same restricted to listed cells: out[s][3][nd] = (B p) on cells[s] */
+void or_grad_apply_cells(const or_prob *p, double tau, const long *cells, long m, const double *pv,
+                         double *out)
+{
+    const int nd = (p->k + 1) * (p->k + 1) * (p->k + 1);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long s = 0; s < m; ++s) grad_one_cell(p, tau, cells[s], pv, out + s * 3 * nd);
+}
+
+/* out[s][nd] = (C u) on cells[s]; u3 is read on the listed cells and their
+ * face neighbours only */
+void or_div_apply_cells(const or_prob *p, double tau, const double *hr, const long *cells, long m,
+                        const double *u3, double *out)
+{
+    const int nd = (p->k + 1) * (p->k + 1) * (p->k + 1);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long s = 0; s < m; ++s) div_one_cell(p, tau, hr, cells[s], u3, out + s * nd);
+}

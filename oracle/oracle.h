@@ -42,5 +42,9 @@ void or_mass_block(const or_prob *p, long c, double *Mb);
 int  or_mass_block_apply(const or_prob *p, const double *r, double *z);
 void or_grad_apply(const or_prob *p, double tau, const double *pv, double *u3);
 void or_div_apply(const or_prob *p, double tau, const double *hr, const double *u3, double *q);
+void or_grad_apply_cells(const or_prob *p, double tau, const long *cells, long m, const double *pv,
+                         double *out);
+void or_div_apply_cells(const or_prob *p, double tau, const double *hr, const long *cells, long m,
+                        const double *u3, double *out);
 
 #endif

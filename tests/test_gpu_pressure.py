@@ -187,3 +187,39 @@ def test_fixed_point_recovers_constructed_state():
     assert info["status"] == hx.HX_OK and info["fp_iters"] < 30
     assert np.linalg.norm(pd.cpu().numpy() - p_star) <= 1e-9 * np.linalg.norm(p_star)
     ctx.close()
+
+
+def test_sampled_parity_full_size_terrain():
+    """At the 256x64x64 Q4 size (the benchmarked configuration) the oracle
+    computes B, C and S on sampled cells only."""
+    import torch
+    hx = _hx()
+    free = torch.cuda.mem_get_info()[0]
+    if free < 100e9:
+        pytest.skip("needs ~100 GB of device memory")
+    print("[pressure] terrain 256x64x64 k=4, sampled cells", flush=True)
+    m = si.terrain_mesh(256, 64, 64, g=4)
+    p, ref, ctx = _setup("terrain-256x64x64-g4", lambda: m, 4)
+    n, nd = p.n_dofs, p.nd
+    pv = si.random_vector(n, 5)
+    u3 = si.random_vector(3 * n, 6).reshape(3, n)
+    area = p.cell_volumes().max() ** (2.0 / 3.0) / 25.0     # a face quadrature weight
+    rng = np.random.default_rng(0)
+    cells = np.unique(np.concatenate([rng.integers(0, m.n_cells, 24),
+                                      [0, 255, 256 * 63, m.n_cells - 1]]))
+    idx = (cells[:, None] * nd + np.arange(nd)[None, :]).ravel()
+    g = ctx.apply_pressure_part(hx.HX_PS_GRAD, to_dev(pv))
+    gs = g[:, torch.from_numpy(idx).to(g.device)].cpu().numpy().reshape(3, cells.size, nd)
+    del g
+    gr = ref.vel.grad_cells(pv, cells, ref.tau).transpose(1, 0, 2)
+    assert _close(gs, gr, 1e-12, ref.tau * np.abs(pv).max() * area), "B"
+    d = ctx.apply_pressure_part(hx.HX_PS_DIV, to_dev(u3))
+    ds = d[torch.from_numpy(idx).to(d.device)].cpu().numpy().reshape(cells.size, nd)
+    del d
+    assert _close(ds, ref.vel.div_cells(u3, ref.hr, cells, ref.tau), 1e-12,
+                  ref.tau * np.abs(ref.hr).max() * np.abs(u3).max() * area), "C"
+    s = ctx.apply_pressure_part(hx.HX_PS_SYSTEM, to_dev(pv))
+    ss = s[torch.from_numpy(idx).to(s.device)].cpu().numpy().reshape(cells.size, nd)
+    del s
+    assert _close(ss, ref.apply_cells(pv, cells), 1e-11), "S"
+    ctx.close()

@@ -128,3 +128,19 @@ def test_fixed_point_converges_to_constructed_state():
     errs = [np.linalg.norm(oracle_fixed_point(m, 4, rho, F, G, p_bg, 1.4, tau, it) - p_star)
             / np.linalg.norm(p_star) for it in (1, 5)]
     assert errs[0] < 1e-2 and errs[1] < 1e-9, errs
+
+
+def test_cell_restricted_system_equals_full():
+    """S p on sampled cells from their two-layer stencil (dense mass-block
+    solves) equals the full composition: the form the full-size GPU test
+    samples."""
+    m = si.terrain_mesh(4, 2, 3, g=4)
+    p = oracle.Problem(m, 4)
+    x, y, z = p.dof_coords()
+    fr, fh = si.terrain_pressure_fields()
+    sysm = PressureSystem(m, 4, fr(x, y, z), fh(x, y, z), 1.4, 1.0)
+    pv = si.random_vector(p.n_dofs, 3)
+    full = sysm.apply(pv).reshape(m.n_cells, -1)
+    cells = np.array([0, 5, 11, 23])
+    part = sysm.apply_cells(pv, cells)
+    assert np.abs(part - full[cells]).max() <= 1e-13 * np.abs(full).max()
