@@ -172,6 +172,9 @@ def pressure_suite(hx, ctx, torch, label, forms, reps=10, fixed_point=False):
                             ("C", hx.HX_PS_DIV, u3), ("A_inv_3", hx.HX_PS_VMASS_INV, u3),
                             ("D", hx.HX_PS_DMASS, p)):
         out[f"ms_{name}"] = round(time_call(lambda: ctx.apply_pressure_part(part, arg), reps, torch), 3)
+    # algorithmic bytes per dof of the two face-coupled kernels (FP64)
+    for name, bpd in (("B", 132.8), ("C", 142.4)):
+        out[f"{name}_alg_GBs"] = round(bpd * n / (out[f"ms_{name}"] * 1e-3) / 1e9, 1)
     G = field_on_device(si.rhs_terrain(9), xyz, torch)
     b = ctx.pressure_rhs(u3, G)
     res = {}

@@ -13,7 +13,9 @@
 // tensor-product sweeps of k_massinv.
 //
 // k_grad and k_div: NF threads per cell (pencil owners (a, b)), CPB cells
-// per block.  Cell terms by sum factorisation: values at the Gauss points by
+// per block (k_grad: one wave, so its LDS exchanges need no workgroup
+// barrier; k_div: two waves, measured faster with its larger LDS), cells taken in the operator's tile traversal with one contiguous range of
+// blocks per XCD, so neighbours' data are found in the same L2.  Cell terms by sum factorisation: values at the Gauss points by
 // three sweeps, the pointwise metric terms W = w detJ J^-1 (times hr for C),
 // and the transposed gradient (B^T / BD^T sweeps z, y, x).  Face terms: the
 // traces at the face Gauss points are N x N contractions of the face layers
@@ -25,12 +27,30 @@
 namespace hx {
 namespace {
 
+// compile-time 1-D tables (generated at build time from the library's rules,
+// the same values as the reference tables): in unrolled loops their entries
+// become instruction operands instead of memory reads
+template <int N> struct KB;
+template <int N> struct KBD;
+template <int N> struct KDL;
+#include "optables.inc"
+
 template <int N>
+__device__ __forceinline__ constexpr double tB(int q, int i) { return KB<N>::d[q * N + i]; }
+template <int N>
+__device__ __forceinline__ constexpr double tD(int q, int i) { return KBD<N>::d[q * N + i]; }
+
+// CPB cells of NF threads per block of at most TMAX threads (k_grad: one
+// wave; k_div, with three velocity components in LDS: two waves)
+template <int N, int TMAX>
 struct PCfg {
     static constexpr int NF = N * N, ND = N * N * N;
-    static constexpr int CPB = (128 / NF) > 0 ? 128 / NF : 1;
+    static constexpr int CPB = (TMAX / NF) > 0 ? TMAX / NF : 1;
     static constexpr int NT = ((CPB * NF + 63) / 64) * 64;
 };
+constexpr int GRAD_T = 64, DIV_T = 128;
+template <int N> constexpr int grad_nt() { return PCfg<N, GRAD_T>::NT; }
+template <int N> constexpr int div_nt() { return PCfg<N, DIV_T>::NT; }
 
 // cell-local index of face-layer node (e1, e2) at normal coordinate m of
 // direction d; e1, e2 run along the tangential directions t1 < t2
@@ -41,42 +61,66 @@ __device__ __forceinline__ int lay(int d, int m, int e1, int e2)
     return m * sd + e1 * s1 + e2 * s2;
 }
 
-// value of a face layer at face Gauss point (a, b): sum B(a,e1) B(b,e2) v
+// per-lane rows and columns of B for the face contractions of lane (a, b):
+// Ra[e] = B(a, e), Rb[e] = B(b, e), Ca[e] = B(e, a), Cb[e] = B(e, b)
 template <int N>
-__device__ __forceinline__ double trace_at(const double *sB, const double *v, int d, int m, int a,
-                                           int b)
+struct LaneB {
+    double Ra[N], Rb[N], Ca[N], Cb[N];
+    __device__ __forceinline__ LaneB(const double *sB, int a, int b)
+    {
+#pragma unroll
+        for (int e = 0; e < N; ++e) {
+            Ra[e] = sB[a * N + e];
+            Rb[e] = sB[b * N + e];
+            Ca[e] = sB[e * N + a];
+            Cb[e] = sB[e * N + b];
+        }
+    }
+};
+
+// value of a face layer at the lane's face Gauss point (a, b):
+// sum B(a,e1) B(b,e2) v(e1, e2), the layer at normal coordinate m of d
+template <int N>
+__device__ __forceinline__ double trace_at(const LaneB<N> &L, const double *v, int d, int m)
 {
     double s = 0.0;
+#pragma unroll
     for (int e2 = 0; e2 < N; ++e2) {
         double r = 0.0;
-        for (int e1 = 0; e1 < N; ++e1) r += sB[a * N + e1] * v[lay<N>(d, m, e1, e2)];
-        s += sB[b * N + e2] * r;
+#pragma unroll
+        for (int e1 = 0; e1 < N; ++e1) r += L.Ra[e1] * v[lay<N>(d, m, e1, e2)];
+        s += L.Rb[e2] * r;
     }
     return s;
 }
 
 // the same from a face layer already gathered as v[e1 + N e2]
 template <int N>
-__device__ __forceinline__ double trace_at2(const double *sB, const double *v, int a, int b)
+__device__ __forceinline__ double trace_at2(const LaneB<N> &L, const double *v)
 {
     double s = 0.0;
+#pragma unroll
     for (int e2 = 0; e2 < N; ++e2) {
         double r = 0.0;
-        for (int e1 = 0; e1 < N; ++e1) r += sB[a * N + e1] * v[e1 + N * e2];
-        s += sB[b * N + e2] * r;
+#pragma unroll
+        for (int e1 = 0; e1 < N; ++e1) r += L.Ra[e1] * v[e1 + N * e2];
+        s += L.Rb[e2] * r;
     }
     return s;
 }
 
-// transposed contraction of a face field g[a + N b] to node (e1, e2)
+// transposed contraction of a face field g[a' + N b'] to the lane's node
+// (e1, e2) = (a, b)
 template <int N>
-__device__ __forceinline__ double trace_t(const double *sB, const double *g, int e1, int e2)
+__device__ __forceinline__ double trace_t(const LaneB<N> &L, const double *g)
 {
     double s = 0.0;
+#pragma unroll
     for (int b = 0; b < N; ++b) {
         double r = 0.0;
-        for (int a = 0; a < N; ++a) r += sB[a * N + e1] * g[a + N * b];
-        s += sB[b * N + e2] * r;
+#pragma unroll
+        for (int a = 0; a < N; ++a) r += L.Ca[a] * g[a + N * b];
+        s += L.Cb[b] * r;
     }
     return s;
 }
@@ -84,38 +128,49 @@ __device__ __forceinline__ double trace_t(const double *sB, const double *g, int
 // values of a cell field at the Gauss points along the lane's z pencil
 // (lane (a, b) = (qx, qy)); v is the field in LDS, F a scratch field
 template <int N>
-__device__ __forceinline__ void to_gauss(const double *sB, const double *v, double *F, bool act,
-                                         int a, int b, double (&out)[N])
+__device__ __forceinline__ void to_gauss(const double *v, double *F, bool act, int a, int b,
+                                         double (&out)[N])
 {
     constexpr int NF = N * N;
     double r[N], w[N];
     if (act) {
+#pragma unroll
         for (int i = 0; i < N; ++i) r[i] = v[i + N * a + NF * b];
+#pragma unroll
         for (int q = 0; q < N; ++q) {
             double s = 0.0;
-            for (int i = 0; i < N; ++i) s += sB[q * N + i] * r[i];
+#pragma unroll
+            for (int i = 0; i < N; ++i) s += tB<N>(q, i) * r[i];
             w[q] = s;
         }
+#pragma unroll
         for (int q = 0; q < N; ++q) F[q + N * a + NF * b] = w[q];
     }
     __syncthreads();
     if (act) {
+#pragma unroll
         for (int j = 0; j < N; ++j) r[j] = F[a + N * j + NF * b];
+#pragma unroll
         for (int q = 0; q < N; ++q) {
             double s = 0.0;
-            for (int j = 0; j < N; ++j) s += sB[q * N + j] * r[j];
+#pragma unroll
+            for (int j = 0; j < N; ++j) s += tB<N>(q, j) * r[j];
             w[q] = s;
         }
     }
     __syncthreads();
     if (act)
+#pragma unroll
         for (int q = 0; q < N; ++q) F[a + N * q + NF * b] = w[q];
     __syncthreads();
     if (act) {
+#pragma unroll
         for (int l = 0; l < N; ++l) r[l] = F[a + N * b + NF * l];
+#pragma unroll
         for (int q = 0; q < N; ++q) {
             double s = 0.0;
-            for (int l = 0; l < N; ++l) s += sB[q * N + l] * r[l];
+#pragma unroll
+            for (int l = 0; l < N; ++l) s += tB<N>(q, l) * r[l];
             out[q] = s;
         }
     }
@@ -126,19 +181,20 @@ __device__ __forceinline__ void to_gauss(const double *sB, const double *v, doub
 // Gauss points; t_d given along the lane's z pencil; F0..F2 scratch fields;
 // the result is the lane's x pencil (lane (a, b) = (j, l))
 template <int N>
-__device__ __forceinline__ void grad_t(const double *sB, const double *sD, double *F0, double *F1,
-                                       double *F2, bool act, int a, int b, const double (&t0)[N],
-                                       const double (&t1)[N], const double (&t2)[N], double tau,
-                                       double (&y)[N])
+__device__ __forceinline__ void grad_t(double *F0, double *F1, double *F2, bool act, int a, int b,
+                                       const double (&t0)[N], const double (&t1)[N],
+                                       const double (&t2)[N], double tau, double (&y)[N])
 {
     constexpr int NF = N * N;
     if (act) {
+#pragma unroll
         for (int l = 0; l < N; ++l) {
             double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
             for (int q = 0; q < N; ++q) {
-                s0 += sB[q * N + l] * t0[q];
-                s1 += sB[q * N + l] * t1[q];
-                s2 += sD[q * N + l] * t2[q];
+                s0 += tB<N>(q, l) * t0[q];
+                s1 += tB<N>(q, l) * t1[q];
+                s2 += tD<N>(q, l) * t2[q];
             }
             F0[a + N * b + NF * l] = s0;
             F1[a + N * b + NF * l] = s1;
@@ -149,16 +205,19 @@ __device__ __forceinline__ void grad_t(const double *sB, const double *sD, doubl
     double r0[N], r12[N];
     if (act) {
         double f0[N], f1[N], f2[N];
+#pragma unroll
         for (int q = 0; q < N; ++q) {
             f0[q] = F0[a + N * q + NF * b];
             f1[q] = F1[a + N * q + NF * b];
             f2[q] = F2[a + N * q + NF * b];
         }
+#pragma unroll
         for (int j = 0; j < N; ++j) {
             double s0 = 0.0, s12 = 0.0;
+#pragma unroll
             for (int q = 0; q < N; ++q) {
-                s0 += sB[q * N + j] * f0[q];
-                s12 += sD[q * N + j] * f1[q] + sB[q * N + j] * f2[q];
+                s0 += tB<N>(q, j) * f0[q];
+                s12 += tD<N>(q, j) * f1[q] + tB<N>(q, j) * f2[q];
             }
             r0[j] = s0;
             r12[j] = s12;
@@ -166,6 +225,7 @@ __device__ __forceinline__ void grad_t(const double *sB, const double *sD, doubl
     }
     __syncthreads();
     if (act)
+#pragma unroll
         for (int j = 0; j < N; ++j) {
             F0[a + N * j + NF * b] = r0[j];
             F1[a + N * j + NF * b] = r12[j];
@@ -173,13 +233,16 @@ __device__ __forceinline__ void grad_t(const double *sB, const double *sD, doubl
     __syncthreads();
     if (act) {
         double g0[N], g1[N];
+#pragma unroll
         for (int q = 0; q < N; ++q) {
             g0[q] = F0[q + N * a + NF * b];
             g1[q] = F1[q + N * a + NF * b];
         }
+#pragma unroll
         for (int i = 0; i < N; ++i) {
             double s = 0.0;
-            for (int q = 0; q < N; ++q) s += sD[q * N + i] * g0[q] + sB[q * N + i] * g1[q];
+#pragma unroll
+            for (int q = 0; q < N; ++q) s += tD<N>(q, i) * g0[q] + tB<N>(q, i) * g1[q];
             y[i] = -tau * s;
         }
     }
@@ -208,13 +271,13 @@ __device__ __forceinline__ void add_faces(const double *A, int a, int b, double 
 }
 
 template <int N>
-__global__ void __launch_bounds__(PCfg<N>::NT)
+__global__ void __launch_bounds__(grad_nt<N>())
 k_grad(const double *__restrict__ p, double *__restrict__ u3, int64_t nt,
-       const double *__restrict__ W, const double *__restrict__ fn, const int32_t *__restrict__ nbr,
-       const RefTab64 *__restrict__ T, double tau, int n_cells)
+       const double *__restrict__ W, const double *__restrict__ fn, const int32_t *__restrict__ visit,
+       const RefTab64 *__restrict__ T, double tau, int n_cells, int nwg)
 {
-    constexpr int NF = PCfg<N>::NF, ND = PCfg<N>::ND, CPB = PCfg<N>::CPB;
-    __shared__ double sB[NF], sD[NF];
+    constexpr int NF = PCfg<N, GRAD_T>::NF, ND = PCfg<N, GRAD_T>::ND, CPB = PCfg<N, GRAD_T>::CPB;
+    __shared__ double sB[NF];
     __shared__ double sP[CPB][ND];
     __shared__ double sF[CPB][3][ND];
     __shared__ double sG[CPB][3][NF];
@@ -226,18 +289,23 @@ k_grad(const double *__restrict__ p, double *__restrict__ u3, int64_t nt,
     const int lc = slot ? lc0 : 0;
     const int tt = t - lc0 * NF;
     const int a = tt % N, b = tt / N;
-    const int64_t cid = (int64_t)blockIdx.x * CPB + lc;
-    const bool act = slot && cid < n_cells;
+    // the operator's traversal: slot records {cell, six neighbours} in tile
+    // order, one contiguous range of blocks per XCD
+    const int bid = blockIdx.x;
+    const int q8 = nwg / NXCD, r8 = nwg % NXCD, xcd = bid % NXCD;
+    const int wg = xcd * q8 + (xcd < r8 ? xcd : r8) + bid / NXCD;
+    const int64_t sl = (int64_t)wg * CPB + lc;
+    const bool act = slot && sl < n_cells;
+    const int32_t *rec = visit + (act ? sl : 0) * 8;
+    const int64_t cid = act ? rec[0] : 0;
 
-    for (int e = t; e < NF; e += blockDim.x) {
-        sB[e] = T->B[e];
-        sD[e] = T->BD[e];
-    }
+    for (int e = t; e < NF; e += blockDim.x) sB[e] = T->B[e];
     if (act)
         for (int e = tt; e < ND; e += NF) sP[lc][e] = p[cid * ND + e];
     __syncthreads();
+    const LaneB<N> LB(sB, a, b);
     double pq[N];
-    to_gauss<N>(sB, sP[lc], sF[lc][0], act, a, b, pq);
+    to_gauss<N>(sP[lc], sF[lc][0], act, a, b, pq);
     double Y[3][N];
 #pragma unroll
     for (int ec = 0; ec < 3; ++ec) {
@@ -250,25 +318,25 @@ k_grad(const double *__restrict__ p, double *__restrict__ u3, int64_t nt,
                 t2[q] = pq[q] * Wc[(6 + ec) * ND + NF * q];
             }
         }
-        grad_t<N>(sB, sD, sF[lc][0], sF[lc][1], sF[lc][2], act, a, b, t0, t1, t2, tau, Y[ec]);
+        grad_t<N>(sF[lc][0], sF[lc][1], sF[lc][2], act, a, b, t0, t1, t2, tau, Y[ec]);
     }
     // faces: tau ds n_e p^ at the Gauss points, back to the face-layer nodes;
     // the neighbour's face layer is gathered into LDS first (one value per lane)
     for (int f = 0; f < 6; ++f) {
         const int d = f >> 1, s = f & 1;
-        const int32_t nb = act ? nbr[6 * cid + f] : -1;
+        const int32_t nb = act ? rec[1 + f] : -1;
         if (nb >= 0) sL[lc][tt] = p[(int64_t)nb * ND + lay<N>(d, s ? 0 : N - 1, a, b)];
         __syncthreads();
         if (act) {
-            const double po = trace_at<N>(sB, sP[lc], d, s ? N - 1 : 0, a, b);
+            const double po = trace_at<N>(LB, sP[lc], d, s ? N - 1 : 0);
             double ph = po;
-            if (nb >= 0) ph = 0.5 * (po + trace_at2<N>(sB, sL[lc], a, b));
+            if (nb >= 0) ph = 0.5 * (po + trace_at2<N>(LB, sL[lc]));
             const double *fnc = fn + (cid * 6 + f) * 3 * NF + tt;
             for (int ec = 0; ec < 3; ++ec) sG[lc][ec][tt] = tau * ph * fnc[ec * NF];
         }
         __syncthreads();
         if (act)
-            for (int ec = 0; ec < 3; ++ec) sA[lc][ec][f * NF + tt] = trace_t<N>(sB, sG[lc][ec], a, b);
+            for (int ec = 0; ec < 3; ++ec) sA[lc][ec][f * NF + tt] = trace_t<N>(LB, sG[lc][ec]);
         __syncthreads();
     }
     if (act)
@@ -281,13 +349,13 @@ k_grad(const double *__restrict__ p, double *__restrict__ u3, int64_t nt,
 }
 
 template <int N>
-__global__ void __launch_bounds__(PCfg<N>::NT)
+__global__ void __launch_bounds__(div_nt<N>())
 k_div(const double *__restrict__ u3, double *__restrict__ qv, int64_t nt,
       const double *__restrict__ WC, const double *__restrict__ fn, const double *__restrict__ fh,
-      const int32_t *__restrict__ nbr, const RefTab64 *__restrict__ T, double tau, int n_cells)
+      const int32_t *__restrict__ visit, const RefTab64 *__restrict__ T, double tau, int n_cells, int nwg)
 {
-    constexpr int NF = PCfg<N>::NF, ND = PCfg<N>::ND, CPB = PCfg<N>::CPB;
-    __shared__ double sB[NF], sD[NF];
+    constexpr int NF = PCfg<N, DIV_T>::NF, ND = PCfg<N, DIV_T>::ND, CPB = PCfg<N, DIV_T>::CPB;
+    __shared__ double sB[NF];
     __shared__ double sU[CPB][3][ND];
     __shared__ double sF[CPB][3][ND];
     __shared__ double sG[CPB][NF];
@@ -299,20 +367,25 @@ k_div(const double *__restrict__ u3, double *__restrict__ qv, int64_t nt,
     const int lc = slot ? lc0 : 0;
     const int tt = t - lc0 * NF;
     const int a = tt % N, b = tt / N;
-    const int64_t cid = (int64_t)blockIdx.x * CPB + lc;
-    const bool act = slot && cid < n_cells;
+    // the operator's traversal: slot records {cell, six neighbours} in tile
+    // order, one contiguous range of blocks per XCD
+    const int bid = blockIdx.x;
+    const int q8 = nwg / NXCD, r8 = nwg % NXCD, xcd = bid % NXCD;
+    const int wg = xcd * q8 + (xcd < r8 ? xcd : r8) + bid / NXCD;
+    const int64_t sl = (int64_t)wg * CPB + lc;
+    const bool act = slot && sl < n_cells;
+    const int32_t *rec = visit + (act ? sl : 0) * 8;
+    const int64_t cid = act ? rec[0] : 0;
 
-    for (int e = t; e < NF; e += blockDim.x) {
-        sB[e] = T->B[e];
-        sD[e] = T->BD[e];
-    }
+    for (int e = t; e < NF; e += blockDim.x) sB[e] = T->B[e];
     if (act)
         for (int ec = 0; ec < 3; ++ec)
             for (int e = tt; e < ND; e += NF) sU[lc][ec][e] = u3[ec * nt + cid * ND + e];
     __syncthreads();
+    const LaneB<N> LB(sB, a, b);
     double uq[3][N];
 #pragma unroll
-    for (int ec = 0; ec < 3; ++ec) to_gauss<N>(sB, sU[lc][ec], sF[lc][0], act, a, b, uq[ec]);
+    for (int ec = 0; ec < 3; ++ec) to_gauss<N>(sU[lc][ec], sF[lc][0], act, a, b, uq[ec]);
     double t0[N], t1[N], t2[N], Y[N];
     if (act) {
         const double *Wc = WC + cid * 9 * ND + a + N * b;
@@ -328,12 +401,12 @@ k_div(const double *__restrict__ u3, double *__restrict__ qv, int64_t nt,
             t2[q] = s2;
         }
     }
-    grad_t<N>(sB, sD, sF[lc][0], sF[lc][1], sF[lc][2], act, a, b, t0, t1, t2, tau, Y);
+    grad_t<N>(sF[lc][0], sF[lc][1], sF[lc][2], act, a, b, t0, t1, t2, tau, Y);
     // interior faces: tau ds {hr u . n_K} at the Gauss points, back to the
     // nodes; the neighbour's face layers are gathered into LDS first
     for (int f = 0; f < 6; ++f) {
         const int d = f >> 1, s = f & 1;
-        const int32_t nb = act ? nbr[6 * cid + f] : -1;
+        const int32_t nb = act ? rec[1 + f] : -1;
         if (nb >= 0) {
             const int64_t o = (int64_t)nb * ND + lay<N>(d, s ? 0 : N - 1, a, b);
             for (int ec = 0; ec < 3; ++ec) sL[lc][ec][tt] = u3[ec * nt + o];
@@ -345,8 +418,8 @@ k_div(const double *__restrict__ u3, double *__restrict__ qv, int64_t nt,
                 const double *fnc = fn + (cid * 6 + f) * 3 * NF + tt;
                 double fo = 0.0, fnb = 0.0;
                 for (int ec = 0; ec < 3; ++ec) {
-                    const double uo = trace_at<N>(sB, sU[lc][ec], d, s ? N - 1 : 0, a, b);
-                    const double un = trace_at2<N>(sB, sL[lc][ec], a, b);
+                    const double uo = trace_at<N>(LB, sU[lc][ec], d, s ? N - 1 : 0);
+                    const double un = trace_at2<N>(LB, sL[lc][ec]);
                     fo += uo * fnc[ec * NF];
                     fnb += un * fnc[ec * NF];
                 }
@@ -357,7 +430,7 @@ k_div(const double *__restrict__ u3, double *__restrict__ qv, int64_t nt,
             sG[lc][tt] = g;
         }
         __syncthreads();
-        if (act) sA[lc][f * NF + tt] = trace_t<N>(sB, sG[lc], a, b);
+        if (act) sA[lc][f * NF + tt] = trace_t<N>(LB, sG[lc]);
         __syncthreads();
     }
     if (act) {
@@ -370,20 +443,20 @@ k_div(const double *__restrict__ u3, double *__restrict__ qv, int64_t nt,
 template <int N>
 hipError_t grad_n(hx_ctx *c, const double *p, double *u3)
 {
-    const int cpb = PCfg<N>::CPB;
+    const int cpb = PCfg<N, GRAD_T>::CPB;
     const int nb = (int)((c->n_cells + cpb - 1) / cpb);
-    hipLaunchKernelGGL(k_grad<N>, dim3(nb), dim3(PCfg<N>::NT), 0, c->stream, p, u3, c->n_dofs,
-                       c->psW, c->psFn, c->nbr, c->ref, c->ps_tau, (int)c->n_cells);
+    hipLaunchKernelGGL(k_grad<N>, dim3(nb), dim3(PCfg<N, GRAD_T>::NT), 0, c->stream, p, u3, c->n_dofs,
+                       c->psW, c->psFn, c->visit, c->ref, c->ps_tau, (int)c->n_cells, nb);
     return hipGetLastError();
 }
 
 template <int N>
 hipError_t div_n(hx_ctx *c, const double *u3, double *q)
 {
-    const int cpb = PCfg<N>::CPB;
+    const int cpb = PCfg<N, DIV_T>::CPB;
     const int nb = (int)((c->n_cells + cpb - 1) / cpb);
-    hipLaunchKernelGGL(k_div<N>, dim3(nb), dim3(PCfg<N>::NT), 0, c->stream, u3, q, c->n_dofs, c->psWC,
-                       c->psFn, c->psFh, c->nbr, c->ref, c->ps_tau, (int)c->n_cells);
+    hipLaunchKernelGGL(k_div<N>, dim3(nb), dim3(PCfg<N, DIV_T>::NT), 0, c->stream, u3, q, c->n_dofs, c->psWC,
+                       c->psFn, c->psFh, c->visit, c->ref, c->ps_tau, (int)c->n_cells, nb);
     return hipGetLastError();
 }
 
