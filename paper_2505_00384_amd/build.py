@@ -32,14 +32,16 @@ def sources():
 
 
 def generate_tables():
-    """Compile and run the table generator (host only) into _build/optables.inc."""
+    """Compile and run the table generator (host only) into _build/optables.inc
+    and _build/optables_binv.inc."""
     exe = os.path.join(BUILD, "gen_tables")
     cmd = [HIPCC, "-O2", "-std=c++17", "-I" + CSRC, os.path.join(CSRC, GEN),
            os.path.join(CSRC, "rules.cpp"), "-o", exe]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"table generator failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    subprocess.check_call([exe, os.path.join(BUILD, "optables.inc")])
+    subprocess.check_call([exe, os.path.join(BUILD, "optables.inc"),
+                           os.path.join(BUILD, "optables_binv.inc")])
 
 
 def _compile(src: str) -> str:

@@ -34,11 +34,16 @@ template <int N> struct KB;
 template <int N> struct KBD;
 template <int N> struct KDL;
 #include "optables.inc"
+template <int N> struct KBI;
+#include "optables_binv.inc"
 
 template <int N>
 __device__ __forceinline__ constexpr double tB(int q, int i) { return KB<N>::d[q * N + i]; }
 template <int N>
 __device__ __forceinline__ constexpr double tD(int q, int i) { return KBD<N>::d[q * N + i]; }
+// (B^-1)_{iq}: B maps nodes to Gauss points and is square
+template <int N>
+__device__ __forceinline__ constexpr double tBi(int i, int q) { return KBI<N>::d[i * N + q]; }
 
 // CPB cells of NF threads per block of at most TMAX threads (k_grad: one
 // wave; k_div, with three velocity components in LDS: two waves)
@@ -249,6 +254,165 @@ __device__ __forceinline__ void grad_t(double *F0, double *F1, double *F2, bool 
     __syncthreads();
 }
 
+// M^{-1} y for three fields at once, M = B3^T diag(m) B3 the cell mass block
+// with Gauss-point weights m (m[a + N b + N^2 q] for the lane's z pencil):
+// y holds the lane's x pencils (lane (a, b) = (j, l)) on entry and on exit;
+// F[0..2] are scratch fields
+template <int N>
+__device__ __forceinline__ void mass_inv3(double *F0, double *F1, double *F2, bool act, int a, int b,
+                                          const double *m, double (&y)[3][N])
+{
+    constexpr int NF = N * N;
+    double *F[3] = {F0, F1, F2};
+    // B^-T along x, in registers
+    if (act)
+#pragma unroll
+        for (int e = 0; e < 3; ++e)
+#pragma unroll
+            for (int q = 0; q < N; ++q) {
+                double s = 0.0;
+#pragma unroll
+                for (int i = 0; i < N; ++i) s += tBi<N>(i, q) * y[e][i];
+                F[e][q + N * a + NF * b] = s;
+            }
+    __syncthreads();
+    // B^-T along y: lane (qx=a, l=b)
+    double w[3][N];
+    if (act)
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            double v[N];
+#pragma unroll
+            for (int j = 0; j < N; ++j) v[j] = F[e][a + N * j + NF * b];
+#pragma unroll
+            for (int q = 0; q < N; ++q) {
+                double s = 0.0;
+#pragma unroll
+                for (int j = 0; j < N; ++j) s += tBi<N>(j, q) * v[j];
+                w[e][q] = s;
+            }
+        }
+    __syncthreads();
+    if (act)
+#pragma unroll
+        for (int e = 0; e < 3; ++e)
+#pragma unroll
+            for (int q = 0; q < N; ++q) F[e][a + N * q + NF * b] = w[e][q];
+    __syncthreads();
+    // B^-T along z, 1/m, B^-1 along z: lane (qx=a, qy=b)
+    if (act) {
+        double mi[N];
+#pragma unroll
+        for (int q = 0; q < N; ++q) mi[q] = 1.0 / m[NF * q];
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            double v[N], t[N];
+#pragma unroll
+            for (int l = 0; l < N; ++l) v[l] = F[e][a + N * b + NF * l];
+#pragma unroll
+            for (int q = 0; q < N; ++q) {
+                double s = 0.0;
+#pragma unroll
+                for (int l = 0; l < N; ++l) s += tBi<N>(l, q) * v[l];
+                t[q] = s * mi[q];
+            }
+#pragma unroll
+            for (int l = 0; l < N; ++l) {
+                double s = 0.0;
+#pragma unroll
+                for (int q = 0; q < N; ++q) s += tBi<N>(l, q) * t[q];
+                w[e][l] = s;
+            }
+        }
+    }
+    __syncthreads();
+    if (act)
+#pragma unroll
+        for (int e = 0; e < 3; ++e)
+#pragma unroll
+            for (int l = 0; l < N; ++l) F[e][a + N * b + NF * l] = w[e][l];
+    __syncthreads();
+    // B^-1 along y: lane (qx=a, l=b)
+    if (act)
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            double v[N];
+#pragma unroll
+            for (int q = 0; q < N; ++q) v[q] = F[e][a + N * q + NF * b];
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                double s = 0.0;
+#pragma unroll
+                for (int q = 0; q < N; ++q) s += tBi<N>(j, q) * v[q];
+                w[e][j] = s;
+            }
+        }
+    __syncthreads();
+    if (act)
+#pragma unroll
+        for (int e = 0; e < 3; ++e)
+#pragma unroll
+            for (int j = 0; j < N; ++j) F[e][a + N * j + NF * b] = w[e][j];
+    __syncthreads();
+    // B^-1 along x: lane (j=a, l=b), back into y
+    if (act)
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            double v[N];
+#pragma unroll
+            for (int q = 0; q < N; ++q) v[q] = F[e][q + N * a + NF * b];
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                double s = 0.0;
+#pragma unroll
+                for (int q = 0; q < N; ++q) s += tBi<N>(i, q) * v[q];
+                y[e][i] = s;
+            }
+        }
+    __syncthreads();
+}
+
+// y = B3^T t: transposed interpolation of Gauss-point values t (the lane's
+// z pencil) back to the nodes (the lane's x pencil); F a scratch field
+template <int N>
+__device__ __forceinline__ void interp_t(double *F, bool act, int a, int b, const double (&t)[N],
+                                         double (&y)[N])
+{
+    constexpr int NF = N * N;
+    if (act)
+#pragma unroll
+        for (int l = 0; l < N; ++l) {
+            double s = 0.0;
+#pragma unroll
+            for (int q = 0; q < N; ++q) s += tB<N>(q, l) * t[q];
+            F[a + N * b + NF * l] = s;
+        }
+    __syncthreads();
+    double r[N];
+    if (act)
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            double s = 0.0;
+#pragma unroll
+            for (int q = 0; q < N; ++q) s += tB<N>(q, j) * F[a + N * q + NF * b];
+            r[j] = s;
+        }
+    __syncthreads();
+    if (act)
+#pragma unroll
+        for (int j = 0; j < N; ++j) F[a + N * j + NF * b] = r[j];
+    __syncthreads();
+    if (act)
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            double s = 0.0;
+#pragma unroll
+            for (int q = 0; q < N; ++q) s += tB<N>(q, i) * F[q + N * a + NF * b];
+            y[i] = s;
+        }
+    __syncthreads();
+}
+
 // add face-layer contributions A[f][e1 + N e2] of the six faces to the x
 // pencil (i, j=a, l=b) of the lane
 template <int N>
@@ -270,11 +434,14 @@ __device__ __forceinline__ void add_faces(const double *A, int a, int b, double 
         for (int i = 0; i < N; ++i) y[i] += A[5 * NF + i + N * a];
 }
 
-template <int N>
+// MINV: the output is A^-1 B p (the rho-weighted mass inverse of each
+// component applied in the epilogue, weights mr), else B p
+template <int N, bool MINV>
 __global__ void __launch_bounds__(grad_nt<N>())
 k_grad(const double *__restrict__ p, double *__restrict__ u3, int64_t nt,
        const double *__restrict__ W, const double *__restrict__ fn, const int32_t *__restrict__ visit,
-       const RefTab64 *__restrict__ T, double tau, int n_cells, int nwg)
+       const RefTab64 *__restrict__ T, double tau, int n_cells, int nwg,
+       const double *__restrict__ mr)
 {
     constexpr int NF = PCfg<N, GRAD_T>::NF, ND = PCfg<N, GRAD_T>::ND, CPB = PCfg<N, GRAD_T>::CPB;
     __shared__ double sB[NF];
@@ -341,18 +508,25 @@ k_grad(const double *__restrict__ p, double *__restrict__ u3, int64_t nt,
     }
     if (act)
 #pragma unroll
+        for (int ec = 0; ec < 3; ++ec) add_faces<N>(sA[lc][ec], a, b, Y[ec]);
+    if (MINV)
+        mass_inv3<N>(sF[lc][0], sF[lc][1], sF[lc][2], act, a, b, mr + cid * ND + a + N * b, Y);
+    if (act)
+#pragma unroll
         for (int ec = 0; ec < 3; ++ec) {
-            add_faces<N>(sA[lc][ec], a, b, Y[ec]);
             const int64_t o = ec * nt + cid * ND + N * a + NF * b;
             for (int i = 0; i < N; ++i) u3[o + i] = Y[ec][i];
         }
 }
 
-template <int N>
+// DP: the output is D x - C u (or bv - (D x - C u) when bv is given), with
+// D the mass of Gauss-point weights md, else C u
+template <int N, bool DP>
 __global__ void __launch_bounds__(div_nt<N>())
 k_div(const double *__restrict__ u3, double *__restrict__ qv, int64_t nt,
       const double *__restrict__ WC, const double *__restrict__ fn, const double *__restrict__ fh,
-      const int32_t *__restrict__ visit, const RefTab64 *__restrict__ T, double tau, int n_cells, int nwg)
+      const int32_t *__restrict__ visit, const RefTab64 *__restrict__ T, double tau, int n_cells, int nwg,
+      const double *__restrict__ xv, const double *__restrict__ md, const double *__restrict__ bv)
 {
     constexpr int NF = PCfg<N, DIV_T>::NF, ND = PCfg<N, DIV_T>::ND, CPB = PCfg<N, DIV_T>::CPB;
     __shared__ double sB[NF];
@@ -433,31 +607,90 @@ k_div(const double *__restrict__ u3, double *__restrict__ qv, int64_t nt,
         if (act) sA[lc][f * NF + tt] = trace_t<N>(LB, sG[lc]);
         __syncthreads();
     }
+    if (act) add_faces<N>(sA[lc], a, b, Y);
+    if (DP) {
+        // D x: x at the Gauss points, times md, back to the nodes
+        if (act)
+            for (int e = tt; e < ND; e += NF) sF[lc][1][e] = xv[cid * ND + e];
+        __syncthreads();
+        double xq[N], dx[N];
+        to_gauss<N>(sF[lc][1], sF[lc][0], act, a, b, xq);
+        if (act)
+#pragma unroll
+            for (int q = 0; q < N; ++q) xq[q] *= md[cid * ND + a + N * b + NF * q];
+        interp_t<N>(sF[lc][0], act, a, b, xq, dx);
+        if (act)
+#pragma unroll
+            for (int i = 0; i < N; ++i) Y[i] = dx[i] - Y[i];
+    }
     if (act) {
-        add_faces<N>(sA[lc], a, b, Y);
         const int64_t o = cid * ND + N * a + NF * b;
-        for (int i = 0; i < N; ++i) qv[o + i] = Y[i];
+        if (DP && bv)
+            for (int i = 0; i < N; ++i) qv[o + i] = bv[o + i] - Y[i];
+        else
+            for (int i = 0; i < N; ++i) qv[o + i] = Y[i];
     }
 }
 
 template <int N>
-hipError_t grad_n(hx_ctx *c, const double *p, double *u3)
+hipError_t grad_n(hx_ctx *c, const double *p, double *u3, bool minv)
 {
     const int cpb = PCfg<N, GRAD_T>::CPB;
     const int nb = (int)((c->n_cells + cpb - 1) / cpb);
-    hipLaunchKernelGGL(k_grad<N>, dim3(nb), dim3(PCfg<N, GRAD_T>::NT), 0, c->stream, p, u3, c->n_dofs,
-                       c->psW, c->psFn, c->visit, c->ref, c->ps_tau, (int)c->n_cells, nb);
+    if (minv)
+        hipLaunchKernelGGL((k_grad<N, true>), dim3(nb), dim3(PCfg<N, GRAD_T>::NT), 0, c->stream, p, u3,
+                           c->n_dofs, c->psW, c->psFn, c->visit, c->ref, c->ps_tau, (int)c->n_cells,
+                           nb, c->psMr);
+    else
+        hipLaunchKernelGGL((k_grad<N, false>), dim3(nb), dim3(PCfg<N, GRAD_T>::NT), 0, c->stream, p,
+                           u3, c->n_dofs, c->psW, c->psFn, c->visit, c->ref, c->ps_tau,
+                           (int)c->n_cells, nb, (const double *)nullptr);
     return hipGetLastError();
 }
 
 template <int N>
-hipError_t div_n(hx_ctx *c, const double *u3, double *q)
+hipError_t div_n(hx_ctx *c, const double *u3, double *q, const double *x, const double *b)
 {
     const int cpb = PCfg<N, DIV_T>::CPB;
     const int nb = (int)((c->n_cells + cpb - 1) / cpb);
-    hipLaunchKernelGGL(k_div<N>, dim3(nb), dim3(PCfg<N, DIV_T>::NT), 0, c->stream, u3, q, c->n_dofs, c->psWC,
-                       c->psFn, c->psFh, c->visit, c->ref, c->ps_tau, (int)c->n_cells, nb);
+    if (x)
+        hipLaunchKernelGGL((k_div<N, true>), dim3(nb), dim3(PCfg<N, DIV_T>::NT), 0, c->stream, u3, q,
+                           c->n_dofs, c->psWC, c->psFn, c->psFh, c->visit, c->ref, c->ps_tau,
+                           (int)c->n_cells, nb, x, c->psMd, b);
+    else
+        hipLaunchKernelGGL((k_div<N, false>), dim3(nb), dim3(PCfg<N, DIV_T>::NT), 0, c->stream, u3, q,
+                           c->n_dofs, c->psWC, c->psFn, c->psFh, c->visit, c->ref, c->ps_tau,
+                           (int)c->n_cells, nb, (const double *)nullptr, (const double *)nullptr,
+                           (const double *)nullptr);
     return hipGetLastError();
+}
+
+hipError_t grad_dispatch(hx_ctx *c, const double *p, double *u3, bool minv)
+{
+    switch (c->n) {
+    case 2: return grad_n<2>(c, p, u3, minv);
+    case 3: return grad_n<3>(c, p, u3, minv);
+    case 4: return grad_n<4>(c, p, u3, minv);
+    case 5: return grad_n<5>(c, p, u3, minv);
+    case 6: return grad_n<6>(c, p, u3, minv);
+    case 7: return grad_n<7>(c, p, u3, minv);
+    case 8: return grad_n<8>(c, p, u3, minv);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t div_dispatch(hx_ctx *c, const double *u3, double *q, const double *x, const double *b)
+{
+    switch (c->n) {
+    case 2: return div_n<2>(c, u3, q, x, b);
+    case 3: return div_n<3>(c, u3, q, x, b);
+    case 4: return div_n<4>(c, u3, q, x, b);
+    case 5: return div_n<5>(c, u3, q, x, b);
+    case 6: return div_n<6>(c, u3, q, x, b);
+    case 7: return div_n<7>(c, u3, q, x, b);
+    case 8: return div_n<8>(c, u3, q, x, b);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 // h = gamma p / ((gamma - 1) rho): specific enthalpy of an ideal gas
@@ -478,47 +711,18 @@ hipError_t launch_enthalpy(hx_ctx *c, const double *p, const double *rho, double
     return hipGetLastError();
 }
 
-hipError_t launch_grad(hx_ctx *c, const double *p, double *u3)
-{
-    switch (c->n) {
-    case 2: return grad_n<2>(c, p, u3);
-    case 3: return grad_n<3>(c, p, u3);
-    case 4: return grad_n<4>(c, p, u3);
-    case 5: return grad_n<5>(c, p, u3);
-    case 6: return grad_n<6>(c, p, u3);
-    case 7: return grad_n<7>(c, p, u3);
-    case 8: return grad_n<8>(c, p, u3);
-    default: return hipErrorInvalidValue;
-    }
-}
+hipError_t launch_grad(hx_ctx *c, const double *p, double *u3) { return grad_dispatch(c, p, u3, false); }
 
-hipError_t launch_div(hx_ctx *c, const double *u3, double *q)
-{
-    switch (c->n) {
-    case 2: return div_n<2>(c, u3, q);
-    case 3: return div_n<3>(c, u3, q);
-    case 4: return div_n<4>(c, u3, q);
-    case 5: return div_n<5>(c, u3, q);
-    case 6: return div_n<6>(c, u3, q);
-    case 7: return div_n<7>(c, u3, q);
-    case 8: return div_n<8>(c, u3, q);
-    default: return hipErrorInvalidValue;
-    }
-}
+hipError_t launch_div(hx_ctx *c, const double *u3, double *q) { return div_dispatch(c, u3, q, nullptr, nullptr); }
 
-// y = S x = D x - C A^-1 B x, or y = b - S x when b is given
+// y = S x = D x - C A^-1 B x, or y = b - S x when b is given: two passes,
+// v = A^-1 B x (the mass inverse in the gradient's epilogue), then
+// D x - C v (the mass of x in the divergence's epilogue)
 hipError_t press_apply64(hx_ctx *c, const double *x, double *y, const double *b)
 {
-    const int64_t n = c->n_dofs, nd = c->nd;
-    double *u3 = c->psWork, *v3 = u3 + 3 * n, *q = v3 + 3 * n;
-    hipError_t e = launch_grad(c, x, u3);
-    for (int ec = 0; ec < 3 && e == hipSuccess; ++ec)
-        e = launch_mass64(c, c->psMr, nd, 1, u3 + ec * n, v3 + ec * n);
-    if (e == hipSuccess) e = launch_div(c, v3, q);
-    if (e == hipSuccess) e = launch_mass64(c, c->psMd, nd, 0, x, y);
-    if (e == hipSuccess) e = blas_axpby(c, n, -1.0, q, 1.0, y);
-    if (e == hipSuccess && b) e = blas_axpby(c, n, 1.0, b, -1.0, y);
-    return e;
+    double *v3 = c->psWork + 3 * c->n_dofs;
+    hipError_t e = grad_dispatch(c, x, v3, true);
+    return e != hipSuccess ? e : div_dispatch(c, v3, y, x, b);
 }
 
 }  // namespace hx
