@@ -62,6 +62,8 @@ def lib():
         L.or_mass_block_apply.argtypes = [pp, dp, dp]
         L.or_mass_block_apply.restype = C.c_int
         L.or_grad_apply.argtypes = [pp, C.c_double, dp, dp]
+        L.or_apply_q.argtypes = [pp, C.c_int, C.c_int, dp, dp]
+        L.or_apply_q_cells.argtypes = [pp, C.c_int, C.c_int, C.c_void_p, C.c_long, dp, dp]
         L.or_div_apply.argtypes = [pp, C.c_double, dp, dp, dp]
         L.or_grad_apply_cells.argtypes = [pp, C.c_double, C.c_void_p, C.c_long, dp, dp]
         L.or_div_apply_cells.argtypes = [pp, C.c_double, dp, C.c_void_p, C.c_long, dp, dp]
@@ -185,6 +187,22 @@ class Problem:
         y = np.zeros(self.n_dofs)
         lib().or_apply(self._s(), int(flags), _dp(x), _dp(y))
         return y
+
+    def apply_q(self, x, nq: int, flags: int = OR_ALL):
+        """A x with an nq-point Gauss rule per direction (nq = 2k+1:
+        consistent integration)."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.zeros(self.n_dofs)
+        lib().or_apply_q(self._s(), int(nq), int(flags), _dp(x), _dp(y))
+        return y
+
+    def apply_q_cells(self, x, cells, nq: int, flags: int = OR_ALL):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        cells = np.ascontiguousarray(cells, dtype=np.int64)
+        out = np.zeros(cells.size * self.nd)
+        lib().or_apply_q_cells(self._s(), int(nq), int(flags), cells.ctypes.data, cells.size,
+                               _dp(x), _dp(out))
+        return out.reshape(cells.size, self.nd)
 
     def apply_cells(self, x, cells, flags: int = OR_ALL):
         """(A x) restricted to the listed cells: [len(cells), nd]."""

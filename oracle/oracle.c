@@ -521,6 +521,141 @@ static void apply_one_cell(const or_prob *p, int flags, long c, const double *xv
     free(phi); free(phiB); free(dphi); free(dphiB);
 }
 
+/* ------------------------------------------------------------------------ */
+/* consistent integration (section 3.3: 2r+1 Gauss points per direction)     */
+/* ------------------------------------------------------------------------ */
+
+#define MAXQ 20
+
+/* (A x) on the test functions of cell c with an nq-point Gauss rule per
+ * direction on cells and faces; the same form as apply_one_cell, whose rule
+ * is the (k+1)-point one.  The penalty sigma_F keeps its geometric
+ * definition. */
+static void apply_one_cell_q(const or_prob *p, int nq, int flags, long c, const double *xv,
+                             double *yc)
+{
+    ref_t r; ref_init(&r, p->k, p->g);
+    const int nd = r.nd;
+    double xg[MAXQ], wg[MAXQ];
+    or_gauss_legendre(nq, xg, wg);
+    double *phi = malloc(sizeof(double) * nd), *phiB = malloc(sizeof(double) * nd);
+    double (*dphi)[3] = malloc(sizeof(double) * 3 * nd);
+    double (*dphiB)[3] = malloc(sizeof(double) * 3 * nd);
+    const double *xc = xv + c * nd;
+    for (int a = 0; a < nd; ++a) yc[a] = 0.0;
+    const double *X = cell_nodes(p, &r, c);
+    if (flags & OR_CELL) {
+        for (int l = 0; l < nq; ++l)
+            for (int j = 0; j < nq; ++j)
+                for (int i = 0; i < nq; ++i) {
+                    double xi[3] = {xg[i], xg[j], xg[l]}, x[3], J[3][3], K[3][3];
+                    geom_at(&r, X, xi, x, J);
+                    double det = det3(J);
+                    inv_transpose(J, det, K);
+                    double w = wg[i] * wg[j] * wg[l] * det;
+                    basis_at(&r, xi, phi, dphi);
+                    double al = field_at(phi, p->alpha + c * nd, nd);
+                    double be = field_at(phi, p->beta + c * nd, nd);
+                    double u = 0.0, gr[3] = {0, 0, 0};
+                    for (int a = 0; a < nd; ++a) {
+                        u += phi[a] * xc[a];
+                        for (int q = 0; q < 3; ++q) gr[q] += dphi[a][q] * xc[a];
+                    }
+                    double gu[3];
+                    matvec3(K, gr, gu);
+                    for (int a = 0; a < nd; ++a) {
+                        double gv[3];
+                        matvec3(K, dphi[a], gv);
+                        yc[a] += w * (al * u * phi[a]
+                                      + be * (gu[0] * gv[0] + gu[1] * gv[1] + gu[2] * gv[2]));
+                    }
+                }
+    }
+    if (flags & OR_FACE) {
+        for (int d = 0; d < 3; ++d)
+            for (int side = 0; side < 2; ++side) {
+                long nb = p->nbr[6 * c + 2 * d + side];
+                if (nb < 0) continue;
+                long km = side ? c : nb, kp = side ? nb : c;
+                double sigma = face_sigma(p, &r, km, d);
+                const double *Xm = cell_nodes(p, &r, km), *Xp = cell_nodes(p, &r, kp);
+                const double *xm = xv + km * nd, *xp = xv + kp * nd;
+                const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+                for (int b = 0; b < nq; ++b)
+                    for (int a = 0; a < nq; ++a) {
+                        double xim[3], xip[3], pos[3], Jm[3][3], Jp[3][3], Km[3][3], Kp[3][3];
+                        xim[d] = 1.0; xip[d] = 0.0;
+                        xim[t1] = xip[t1] = xg[a];
+                        xim[t2] = xip[t2] = xg[b];
+                        geom_at(&r, Xm, xim, pos, Jm);
+                        geom_at(&r, Xp, xip, pos, Jp);
+                        double detm = det3(Jm);
+                        inv_transpose(Jm, detm, Km);
+                        inv_transpose(Jp, det3(Jp), Kp);
+                        /* minus-side unit normal J^-T e_d / |.| and surface element */
+                        double e[3] = {0, 0, 0}, mv[3], nrm[3];
+                        e[d] = 1.0;
+                        matvec3(Km, e, mv);
+                        double len = sqrt(mv[0] * mv[0] + mv[1] * mv[1] + mv[2] * mv[2]);
+                        for (int q = 0; q < 3; ++q) nrm[q] = mv[q] / len;
+                        double ds = wg[a] * wg[b] * detm * len;
+                        basis_at(&r, xim, phi, dphi);
+                        basis_at(&r, xip, phiB, dphiB);
+                        double bm = field_at(phi, p->beta + km * nd, nd);
+                        double bp = field_at(phiB, p->beta + kp * nd, nd);
+                        double um = 0, up = 0, gm[3] = {0, 0, 0}, gp[3] = {0, 0, 0};
+                        for (int q2 = 0; q2 < nd; ++q2) {
+                            um += phi[q2] * xm[q2];
+                            up += phiB[q2] * xp[q2];
+                            for (int q = 0; q < 3; ++q) {
+                                gm[q] += dphi[q2][q] * xm[q2];
+                                gp[q] += dphiB[q2][q] * xp[q2];
+                            }
+                        }
+                        double Gm[3], Gp[3];
+                        matvec3(Km, gm, Gm);
+                        matvec3(Kp, gp, Gp);
+                        double dnm = nrm[0] * Gm[0] + nrm[1] * Gm[1] + nrm[2] * Gm[2];
+                        double dnp = nrm[0] * Gp[0] + nrm[1] * Gp[1] + nrm[2] * Gp[2];
+                        double flux = bm * dnm + bp * dnp;
+                        double jump = um - up;
+                        double pen = sigma * 0.5 * (bm + bp);
+                        const double *tphi = side ? phi : phiB;
+                        double (*tdphi)[3] = side ? dphi : dphiB;
+                        double (*Kown)[3] = side ? Km : Kp;
+                        double bown = side ? bm : bp;
+                        double sgn = side ? 1.0 : -1.0;
+                        for (int q2 = 0; q2 < nd; ++q2) {
+                            double gv[3];
+                            matvec3(Kown, tdphi[q2], gv);
+                            double dnv = nrm[0] * gv[0] + nrm[1] * gv[1] + nrm[2] * gv[2];
+                            double jv = sgn * tphi[q2];
+                            yc[q2] += ds * (-0.5 * flux * jv - 0.5 * bown * dnv * jump
+                                            + pen * jump * jv);
+                        }
+                    }
+            }
+    }
+    free(phi); free(phiB); free(dphi); free(dphiB);
+}
+
+/* y = A x with the nq-point rule (nq = 2k+1: consistent integration) */
+void or_apply_q(const or_prob *p, int nq, int flags, const double *xv, double *yv)
+{
+    int nd = (p->k + 1) * (p->k + 1) * (p->k + 1);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (long c = 0; c < p->n_cells; ++c) apply_one_cell_q(p, nq, flags, c, xv, yv + c * nd);
+}
+
+/* the same restricted to listed cells: out[s][nd] */
+void or_apply_q_cells(const or_prob *p, int nq, int flags, const long *cells, long m,
+                      const double *xv, double *out)
+{
+    int nd = (p->k + 1) * (p->k + 1) * (p->k + 1);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long s = 0; s < m; ++s) apply_one_cell_q(p, nq, flags, cells[s], xv, out + s * nd);
+}
+
 /* Diagonal of the volume part of the form (section 3.1: the paper's
  * "Helmholtz preconditioner" is the inverse of the diagonal of S~, whose
  * entries are volume integrals only; its "internal-energy" variant keeps the

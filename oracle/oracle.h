@@ -32,6 +32,9 @@ void or_eval_quad(const or_prob *p, const double *u, double *uq);
 void or_apply(const or_prob *p, int flags, const double *x, double *y);
 void or_apply_cells(const or_prob *p, int flags, const long *cells, long m,
                     const double *x, double *out);
+void or_apply_q(const or_prob *p, int nq, int flags, const double *x, double *y);
+void or_apply_q_cells(const or_prob *p, int nq, int flags, const long *cells, long m,
+                      const double *x, double *out);
 void or_assemble_dense(const or_prob *p, int flags, double *A);
 void or_cell_diagonal(const or_prob *p, int stiff, double *diag);
 void or_bj_cell_data(const or_prob *p, long c, double ell[3], double *abar,
