@@ -221,6 +221,23 @@ hx_status hx_solve(hx_ctx *c, const hx_solve_params *prm, const double *b,
                    double *x, hx_solve_info *info);
 
 /* ---------------------------------------------------------------------- */
+/* consistent integration                                                   */
+/* ---------------------------------------------------------------------- */
+
+/* Section 3.3 contrasts the fast evaluation with (r+1) Gauss points per
+ * direction (exact for mass matrices, aliasing for products of three
+ * polynomials such as variable-coefficient terms) with consistent
+ * integration by 2r+1 points.  hx_set_consistent builds the quadrature data
+ * of the same form (cell and face terms, penalty of hx_set_coefficients)
+ * with nq = 2k+1 points from nodal alpha, beta ([n_dofs], HOST, or DEVICE
+ * with on_device = 1): 7 nq^3 numbers per cell and 21 nq^2 per cell for the
+ * faces (for k = 4, 5.4x the data of the fast form).  Requires
+ * hx_set_coefficients (for the penalty).  hx_apply_consistent: y = A_q x,
+ * x, y DEVICE FP64 [n_dofs], distinct. */
+hx_status hx_set_consistent(hx_ctx *c, const double *alpha, const double *beta, int on_device);
+hx_status hx_apply_consistent(hx_ctx *c, const double *x, double *y);
+
+/* ---------------------------------------------------------------------- */
 /* pressure system of one IMEX stage                                        */
 /* ---------------------------------------------------------------------- */
 

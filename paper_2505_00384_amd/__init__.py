@@ -93,6 +93,8 @@ def load(path: str = LIB_PATH):
         "hx_set_pressure_system": ([vp, vp, vp, C.c_double, C.c_double, C.c_double, C.c_int],
                                    C.c_int),
         "hx_apply_pressure_part": ([vp, C.c_int, vp, vp], C.c_int),
+        "hx_set_consistent": ([vp, vp, vp, C.c_int], C.c_int),
+        "hx_apply_consistent": ([vp, vp, vp], C.c_int),
         "hx_pressure_rhs": ([vp, vp, vp, vp], C.c_int),
         "hx_pressure_velocity": ([vp, vp, vp, vp], C.c_int),
         "hx_solve_pressure_fixed_point": ([vp, vp, vp, vp, vp, C.c_double, C.c_double, C.c_double,
@@ -189,6 +191,23 @@ class HelmDG:
             a = alpha.contiguous(); b = beta.contiguous()
             st = self.L.hx_set_coefficients(self.h, _ptr(a), _ptr(b), float(penalty), 1)
         self._chk(st, "set_coefficients")
+
+    # -- consistent integration (2k+1 Gauss points) ----------------------------
+    def set_consistent(self, alpha, beta):
+        if isinstance(alpha, np.ndarray):
+            a = np.ascontiguousarray(alpha, dtype=np.float64)
+            b = np.ascontiguousarray(beta, dtype=np.float64)
+            st = self.L.hx_set_consistent(self.h, a.ctypes.data, b.ctypes.data, 0)
+        else:
+            a = alpha.contiguous(); b = beta.contiguous()
+            st = self.L.hx_set_consistent(self.h, _ptr(a), _ptr(b), 1)
+        self._chk(st, "set_consistent")
+
+    def apply_consistent(self, x, y=None):
+        if y is None:
+            y = self.torch.empty_like(x)
+        self._chk(self.L.hx_apply_consistent(self.h, _ptr(x), _ptr(y)), "apply_consistent")
+        return y
 
     # -- pressure system of an IMEX stage --------------------------------------
     def set_pressure_system(self, rho, h, gamma: float, tau: float, penalty: float = 2.0):

@@ -49,10 +49,11 @@ static void free_mesh(hx_ctx *c)
                      (void **)&c->bjL64, (void **)&c->bjL32, (void **)&c->bjC64,
                      (void **)&c->bjC32, (void **)&c->coef_feat, (void **)&c->work64,
                      (void **)&c->work32, (void **)&c->psW, (void **)&c->psWC, (void **)&c->psMr,
-                     (void **)&c->psMd, (void **)&c->psFn, (void **)&c->psFh, (void **)&c->psWork};
+                     (void **)&c->psMd, (void **)&c->psFn, (void **)&c->psFh, (void **)&c->psWork,
+                     (void **)&c->refq, (void **)&c->qcell, (void **)&c->qface};
     for (void **b : bufs) dfree(b);
     c->work64_len = c->work32_len = 0;
-    c->has_mesh = c->has_coef = c->has_press = false;
+    c->has_mesh = c->has_coef = c->has_press = c->has_q = false;
 }
 
 }  // namespace hx
@@ -301,6 +302,47 @@ hx_status hx_set_pressure_system(hx_ctx *c, const double *rho, const double *h, 
     if (s != HX_OK) return s;
     c->ps_tau = tau;
     c->has_press = true;
+    return HX_OK;
+}
+
+hx_status hx_set_consistent(hx_ctx *c, const double *alpha, const double *beta, int on_device)
+{
+    if (!c) return HX_ERR_ARG;
+    if (!c->has_coef) return fail(c, HX_ERR_STATE, "set_consistent before set_coefficients");
+    if (!alpha || !beta) return fail(c, HX_ERR_ARG, "null coefficient array");
+    HX_HIP(c, hipSetDevice(c->device));
+    const int64_t n = c->n_dofs, nc = c->n_cells;
+    const int nq = 2 * c->n - 1;
+    hx_status s = HX_OK;
+    if (!c->qcell) {
+        if ((s = dalloc(c, (void **)&c->refq, sizeof(RefTabQ))) != HX_OK) return s;
+        if ((s = dalloc(c, (void **)&c->qcell, sizeof(double) * nc * 7 * nq * nq * nq)) != HX_OK) return s;
+        if ((s = dalloc(c, (void **)&c->qface, sizeof(double) * nc * 3 * 7 * nq * nq)) != HX_OK) return s;
+    }
+    c->nq = nq;
+    RefTabQ tq;
+    build_q_tables(c->n, nq, tq);
+    double *tmp = nullptr;
+    if ((s = dalloc(c, (void **)&tmp, sizeof(double) * 2 * n)) != HX_OK) return s;
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    hipError_t e = hipMemcpyAsync(c->refq, &tq, sizeof(RefTabQ), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(tmp, alpha, sizeof(double) * n, kind, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(tmp + n, beta, sizeof(double) * n, kind, c->stream);
+    if (e == hipSuccess) e = launch_q_setup(c, tmp, tmp + n);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    dfree((void **)&tmp);
+    if (e != hipSuccess) return fail(c, HX_ERR_DEVICE, "set_consistent: %s", hipGetErrorString(e));
+    c->has_q = true;
+    return HX_OK;
+}
+
+hx_status hx_apply_consistent(hx_ctx *c, const double *x, double *y)
+{
+    if (!c) return HX_ERR_ARG;
+    if (!c->has_q) return fail(c, HX_ERR_STATE, "consistent integration not set up");
+    if (!x || !y || x == y) return fail(c, HX_ERR_ARG, "null or aliasing vectors");
+    HX_HIP(c, hipSetDevice(c->device));
+    HX_HIP(c, launch_apply_q(c, x, y));
     return HX_OK;
 }
 

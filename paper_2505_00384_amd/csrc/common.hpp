@@ -34,6 +34,17 @@ void rule_gauss_lobatto(int n, double *x01, double *w01);
 void lagrange_eval(int n, const double *nodes, double t, double *val, double *der);
 void build_ref_tables(int n, RefTab64 &t);
 
+// tables of an nq-point Gauss rule for the n-node GLL basis (consistent
+// integration uses nq = 2k+1 = 2n-1)
+constexpr int MAXQ = 2 * MAXK + 1;
+struct RefTabQ {
+    int nq = 0;
+    double xq[MAXQ], wq[MAXQ];           // GL on [0,1]
+    double B[MAXQ * MAXN];               // B[q*n+i]  = l_i(xq_q)
+    double BD[MAXQ * MAXN];              // BD[q*n+i] = l_i'(xq_q)
+};
+void build_q_tables(int n, int nq, RefTabQ &t);
+
 struct MlpState;   // learned preconditioner (mlp.hip)
 
 }  // namespace hx
@@ -79,6 +90,12 @@ struct hx_ctx {
     double *psFn = nullptr;       // [n_cells][6][3][nf] outward ds n on the own faces
     double *psFh = nullptr;       // [n_cells][6][nf]  h rho on the own faces
     double *psWork = nullptr;     // [7][n_dofs]       velocity temporaries and C A^-1 B x
+    // consistent integration: the operator with nq = 2k+1 Gauss points
+    bool has_q = false;
+    int nq = 0;
+    hx::RefTabQ *refq = nullptr;  // device tables
+    double *qcell = nullptr;      // [n_cells][7][nq^3]   m, Gxx, Gxy, Gxz, Gyy, Gyz, Gzz
+    double *qface = nullptr;      // [n_cells][3][7][nq^2] g-(3), g+(3), s of the +d face
 
     // separable block-Jacobi data
     double *bjS64 = nullptr;      // [n_cells][3][n][n]  eigenvectors S_d
@@ -143,6 +160,10 @@ hipError_t launch_press_setup(hx_ctx *c, const double *rho, const double *h, dou
 hipError_t launch_grad(hx_ctx *c, const double *p, double *u3);
 hipError_t launch_div(hx_ctx *c, const double *u3, double *q);
 hipError_t press_apply64(hx_ctx *c, const double *x, double *y, const double *b);
+// consistent integration: quadrature data from nodal alpha, beta (device), and
+// y = A_q x
+hipError_t launch_q_setup(hx_ctx *c, const double *alpha, const double *beta);
+hipError_t launch_apply_q(hx_ctx *c, const double *x, double *y);
 // h = gamma p / ((gamma - 1) rho) at the nodes
 hipError_t launch_enthalpy(hx_ctx *c, const double *p, const double *rho, double gamma, double *h);
 hipError_t launch_massinv32(hx_ctx *c, const float *r, float *z);

@@ -771,3 +771,120 @@ hipError_t launch_press_setup(hx_ctx *c, const double *rho, const double *h, dou
 }
 
 }  // namespace hx
+
+namespace hx {
+namespace {
+
+// -------------------------------------------------------------------------
+// Consistent integration (section 3.3: 2r+1 Gauss points per direction):
+// the merged cell and face data of the operator at the nq-point rule, the
+// same quantities as k_cell_geofac / k_set_cell and k_face_geofac /
+// k_set_face, with alpha and beta interpolated from the nodes to the points.
+// Cell point index qx + nq (qy + nq qz); face point a + nq b (a along t1).
+// -------------------------------------------------------------------------
+__global__ void k_q_cell(const double *__restrict__ nodes, int ng, int n, int64_t n_cells,
+                         const RefTabQ *__restrict__ Q, const double *__restrict__ alpha,
+                         const double *__restrict__ beta, double *qcell)
+{
+    const int nq = Q->nq, nq3 = nq * nq * nq, nd = n * n * n;
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= n_cells * nq3) return;
+    const int64_t c = t / nq3;
+    const int q = (int)(t % nq3);
+    const int i = q % nq, j = (q / nq) % nq, l = q / (nq * nq);
+    double xi[3] = {Q->xq[i], Q->xq[j], Q->xq[l]}, x[3], J[3][3], Ji[3][3];
+    cell_map(nodes + c * (int64_t)ng * ng * ng * 3, ng, xi, x, J);
+    const double det = det3(J);
+    inv3(J, det, Ji);
+    const double w = Q->wq[i] * Q->wq[j] * Q->wq[l] * det;
+    double aq = 0.0, bq = 0.0;
+    const double *ac = alpha + c * nd, *bc = beta + c * nd;
+    for (int l2 = 0; l2 < n; ++l2)
+        for (int j2 = 0; j2 < n; ++j2) {
+            const double byz = Q->B[j * n + j2] * Q->B[l * n + l2];
+            for (int i2 = 0; i2 < n; ++i2) {
+                const double wgt = Q->B[i * n + i2] * byz;
+                const int e = lidx(n, i2, j2, l2);
+                aq += wgt * ac[e];
+                bq += wgt * bc[e];
+            }
+        }
+    double *dst = qcell + c * 7 * nq3 + q;
+    dst[0] = aq * w;
+    const int pa[6] = {0, 0, 0, 1, 1, 2}, pb[6] = {0, 1, 2, 1, 2, 2};
+    for (int s = 0; s < 6; ++s) {
+        const int A = pa[s], Bq = pb[s];
+        dst[(1 + s) * nq3] =
+            bq * w * (Ji[A][0] * Ji[Bq][0] + Ji[A][1] * Ji[Bq][1] + Ji[A][2] * Ji[Bq][2]);
+    }
+}
+
+__global__ void k_q_face(const double *__restrict__ nodes, int ng, int n, int64_t n_cells,
+                         const int32_t *__restrict__ nbr, const RefTabQ *__restrict__ Q,
+                         const double *__restrict__ beta, const double *__restrict__ sigma,
+                         double *qface)
+{
+    const int nq = Q->nq, nq2 = nq * nq, nd = n * n * n;
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= 3 * n_cells * nq2) return;
+    const int pt = (int)(t % nq2);
+    const int64_t cd = t / nq2;
+    const int64_t c = cd / 3;
+    const int d = (int)(cd % 3);
+    const int a = pt % nq, b = pt / nq;
+    double *dst = qface + cd * 7 * nq2 + pt;
+    const int32_t nb = nbr[6 * c + 2 * d + 1];
+    if (nb < 0) {
+        for (int s = 0; s < 7; ++s) dst[s * nq2] = 0.0;
+        return;
+    }
+    const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+    double xim[3], xip[3], x[3], Jm[3][3], Jp[3][3], Jmi[3][3], Jpi[3][3];
+    xim[d] = 1.0;
+    xip[d] = 0.0;
+    xim[t1] = xip[t1] = Q->xq[a];
+    xim[t2] = xip[t2] = Q->xq[b];
+    const int64_t gsz = (int64_t)ng * ng * ng * 3;
+    cell_map(nodes + c * gsz, ng, xim, x, Jm);
+    cell_map(nodes + (int64_t)nb * gsz, ng, xip, x, Jp);
+    const double detm = det3(Jm), detp = det3(Jp);
+    inv3(Jm, detm, Jmi);
+    inv3(Jp, detp, Jpi);
+    double nv[3] = {Jmi[d][0], Jmi[d][1], Jmi[d][2]};
+    const double len = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+    for (int r = 0; r < 3; ++r) nv[r] /= len;
+    const double ds = Q->wq[a] * Q->wq[b] * detm * len;
+    // beta on both sides: the face layers interpolated to the point
+    double bm = 0.0, bp = 0.0;
+    for (int e2 = 0; e2 < n; ++e2)
+        for (int e1 = 0; e1 < n; ++e1) {
+            const double wgt = Q->B[a * n + e1] * Q->B[b * n + e2];
+            bm += wgt * beta[c * nd + layer_idx(n, d, n - 1, e1, e2)];
+            bp += wgt * beta[(int64_t)nb * nd + layer_idx(n, d, 0, e1, e2)];
+        }
+    const int dir[3] = {d, t1, t2};
+    for (int k = 0; k < 3; ++k) {
+        const int r = dir[k];
+        dst[k * nq2] = bm * ds * (Jmi[r][0] * nv[0] + Jmi[r][1] * nv[1] + Jmi[r][2] * nv[2]);
+        dst[(3 + k) * nq2] = bp * ds * (Jpi[r][0] * nv[0] + Jpi[r][1] * nv[1] + Jpi[r][2] * nv[2]);
+    }
+    dst[6 * nq2] = sigma[3 * c + d] * 0.5 * (bm + bp) * ds;
+}
+
+}  // namespace
+
+hipError_t launch_q_setup(hx_ctx *c, const double *alpha, const double *beta)
+{
+    const int nq = c->nq;
+    const int64_t nt = c->n_cells * nq * nq * nq;
+    hipLaunchKernelGGL(k_q_cell, dim3(nblk(nt, 128)), dim3(128), 0, c->stream, c->nodes, c->g + 1, c->n,
+                       c->n_cells, c->refq, alpha, beta, c->qcell);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t nf = 3 * c->n_cells * nq * nq;
+    hipLaunchKernelGGL(k_q_face, dim3(nblk(nf, 128)), dim3(128), 0, c->stream, c->nodes, c->g + 1, c->n,
+                       c->n_cells, c->nbr, c->refq, beta, c->sigma, c->qface);
+    return hipGetLastError();
+}
+
+}  // namespace hx

@@ -1,0 +1,303 @@
+// The operator with consistent integration (paper section 3.3: a Gauss rule
+// of 2r+1 points per direction, which integrates the products of three
+// polynomials of the variable-coefficient terms without aliasing, against
+// the r+1 points of the fast evaluation).  Same form as k_apply; the 1-D
+// interpolation B (nq x n) and its derivative BD are rectangular now, so the
+// sweeps change pencil lengths (n nodes <-> nq points).
+//
+// One cell per block.  Cell part: x sweep by lanes (j, l) (n^2), y sweep by
+// lanes (qx, l) (nq n), z sweep, quadrature-point operation and transposed z
+// sweep by lanes (qx, qy) (nq^2), transposed y and x sweeps back; fields in
+// LDS between the sweeps.  Face part, face by face: lanes (e1, e2) form the
+// own and the neighbour's face layer and normal-derivative column (the
+// derivative of the GLL basis at the face end), lanes (a, b) evaluate value,
+// tangential and normal derivatives at the nq^2 face points and the flux
+// terms, lanes (e1, e2) contract them back to layer weights, and the pencil
+// owners add them (layer weights to the face layer, derivative weights
+// along the normal lines).  One thread writes each output.
+#include "common.hpp"
+
+namespace hx {
+namespace {
+
+template <int N, int Q>
+struct QCfg {
+    static constexpr int ND = N * N * N, NF = N * N, Q2 = Q * Q, Q3 = Q * Q * Q;
+    static constexpr int QN = Q * N, QNN = Q * N * N, QQN = Q * Q * N;
+    static constexpr int NT = ((Q2 > QN ? Q2 : QN) + 63) / 64 * 64;
+};
+
+// threads per block for N nodes and 2N-1 points per direction
+template <int N>
+constexpr int q_nt() { return QCfg<N, 2 * N - 1>::NT; }
+
+template <int N>
+__device__ __forceinline__ int qlay(int d, int m, int e1, int e2)
+{
+    const int s1 = d == 0 ? N : 1, s2 = d == 2 ? N : N * N, sd = d == 0 ? 1 : (d == 1 ? N : N * N);
+    return m * sd + e1 * s1 + e2 * s2;
+}
+
+template <int N>
+__global__ void __launch_bounds__(q_nt<N>())
+k_apply_q(const double *__restrict__ x, double *__restrict__ y, const double *__restrict__ cell,
+          const double *__restrict__ face, const int32_t *__restrict__ nbr,
+          const RefTabQ *__restrict__ TQ, const RefTab64 *__restrict__ T, int n_cells)
+{
+    constexpr int Q = 2 * N - 1;
+    using C = QCfg<N, Q>;
+    constexpr int ND = C::ND, NF = C::NF, Q2 = C::Q2, Q3 = C::Q3, QNN = C::QNN, QQN = C::QQN;
+    __shared__ double sB[Q * N], sD[Q * N], sDL[2][N];
+    __shared__ double sX[ND];
+    __shared__ double U0[QNN], U1[QNN];
+    __shared__ double V0[QQN], V1[QQN], V2[QQN];
+    __shared__ double Lo[NF], Do[NF], Ln[NF], Dn[NF];
+    __shared__ double Pv[Q2], P1[Q2], P2[Q2], Pn[Q2];
+    __shared__ double FA[6][2][NF];
+    const int t = threadIdx.x;
+    const int64_t cid = blockIdx.x;
+    for (int e = t; e < Q * N; e += blockDim.x) {
+        sB[e] = TQ->B[e];
+        sD[e] = TQ->BD[e];
+    }
+    for (int e = t; e < 2 * N; e += blockDim.x) sDL[e / N][e % N] = T->DL[e / N][e % N];
+    for (int e = t; e < ND; e += blockDim.x) sX[e] = x[cid * ND + e];
+    __syncthreads();
+
+    // x sweep: lane (j, l): u and du/dxi at (qx, j, l), layout qx + Q (j + N l)
+    if (t < NF) {
+        const int j = t % N, l = t / N;
+        double v[N];
+        for (int i = 0; i < N; ++i) v[i] = sX[i + N * j + NF * l];
+        for (int q = 0; q < Q; ++q) {
+            double s0 = 0.0, s1 = 0.0;
+            for (int i = 0; i < N; ++i) {
+                s0 += sB[q * N + i] * v[i];
+                s1 += sD[q * N + i] * v[i];
+            }
+            U0[q + Q * (j + N * l)] = s0;
+            U1[q + Q * (j + N * l)] = s1;
+        }
+    }
+    __syncthreads();
+    // y sweep: lane (qx, l): u, d/deta (from u) and d/dxi (from U1) at
+    // (qx, qy, l), layout qx + Q (qy + Q l)
+    if (t < C::QN) {
+        const int qx = t % Q, l = t / Q;
+        double v0[N], v1[N];
+        for (int j = 0; j < N; ++j) {
+            v0[j] = U0[qx + Q * (j + N * l)];
+            v1[j] = U1[qx + Q * (j + N * l)];
+        }
+        for (int q = 0; q < Q; ++q) {
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+            for (int j = 0; j < N; ++j) {
+                s0 += sB[q * N + j] * v0[j];
+                s1 += sD[q * N + j] * v0[j];
+                s2 += sB[q * N + j] * v1[j];
+            }
+            V0[qx + Q * (q + Q * l)] = s0;
+            V1[qx + Q * (q + Q * l)] = s1;
+            V2[qx + Q * (q + Q * l)] = s2;
+        }
+    }
+    __syncthreads();
+    // z sweep, quadrature-point operation, transposed z sweep: lane (qx, qy)
+    double w0[N], w1[N], w2[N];
+    if (t < Q2) {
+        const int qx = t % Q, qy = t / Q;
+        double a0[N], a1[N], a2[N];
+        for (int l = 0; l < N; ++l) {
+            a0[l] = V0[qx + Q * (qy + Q * l)];
+            a1[l] = V1[qx + Q * (qy + Q * l)];
+            a2[l] = V2[qx + Q * (qy + Q * l)];
+        }
+        for (int l = 0; l < N; ++l) w0[l] = w1[l] = w2[l] = 0.0;
+        const double *cp = cell + cid * 7 * Q3 + qx + Q * qy;
+        for (int q = 0; q < Q; ++q) {
+            double u = 0.0, dz = 0.0, dy = 0.0, dx = 0.0;
+            for (int l = 0; l < N; ++l) {
+                u += sB[q * N + l] * a0[l];
+                dz += sD[q * N + l] * a0[l];
+                dy += sB[q * N + l] * a1[l];
+                dx += sB[q * N + l] * a2[l];
+            }
+            const double *cq = cp + Q2 * q;
+            const double m = cq[0], gxx = cq[Q3], gxy = cq[2 * Q3], gxz = cq[3 * Q3],
+                         gyy = cq[4 * Q3], gyz = cq[5 * Q3], gzz = cq[6 * Q3];
+            const double v = m * u;
+            const double fx = gxx * dx + gxy * dy + gxz * dz;
+            const double fy = gxy * dx + gyy * dy + gyz * dz;
+            const double fz = gxz * dx + gyz * dy + gzz * dz;
+            for (int l = 0; l < N; ++l) {
+                w0[l] += sB[q * N + l] * v + sD[q * N + l] * fz;
+                w1[l] += sB[q * N + l] * fy;
+                w2[l] += sB[q * N + l] * fx;
+            }
+        }
+    }
+    __syncthreads();
+    if (t < Q2) {
+        const int qx = t % Q, qy = t / Q;
+        for (int l = 0; l < N; ++l) {
+            V0[qx + Q * (qy + Q * l)] = w0[l];
+            V1[qx + Q * (qy + Q * l)] = w1[l];
+            V2[qx + Q * (qy + Q * l)] = w2[l];
+        }
+    }
+    __syncthreads();
+    // transposed y sweep: lane (qx, l) -> (qx, j, l): s0 = B^T w0 + BD^T w1,
+    // s1 = B^T w2
+    if (t < C::QN) {
+        const int qx = t % Q, l = t / Q;
+        double s0[N], s1[N];
+        for (int j = 0; j < N; ++j) s0[j] = s1[j] = 0.0;
+        for (int q = 0; q < Q; ++q) {
+            const double a0 = V0[qx + Q * (q + Q * l)], a1 = V1[qx + Q * (q + Q * l)],
+                         a2 = V2[qx + Q * (q + Q * l)];
+            for (int j = 0; j < N; ++j) {
+                s0[j] += sB[q * N + j] * a0 + sD[q * N + j] * a1;
+                s1[j] += sB[q * N + j] * a2;
+            }
+        }
+        for (int j = 0; j < N; ++j) {
+            U0[qx + Q * (j + N * l)] = s0[j];
+            U1[qx + Q * (j + N * l)] = s1[j];
+        }
+    }
+    __syncthreads();
+    // transposed x sweep: lane (j, l) keeps its output pencil
+    double Y[N];
+    if (t < NF) {
+        const int j = t % N, l = t / N;
+        for (int i = 0; i < N; ++i) Y[i] = 0.0;
+        for (int q = 0; q < Q; ++q) {
+            const double a0 = U0[q + Q * (j + N * l)], a1 = U1[q + Q * (j + N * l)];
+            for (int i = 0; i < N; ++i) Y[i] += sB[q * N + i] * a0 + sD[q * N + i] * a1;
+        }
+    }
+
+    // ---------------------------------------------------------------- faces
+    for (int f = 0; f < 6; ++f) {
+        const int d = f >> 1, s = f & 1;
+        const int32_t nb = nbr[6 * cid + f];
+        if (nb < 0) {
+            if (t < NF) FA[f][0][t] = FA[f][1][t] = 0.0;
+            continue;               // uniform across the block: no barrier skipped unevenly
+        }
+        // layers and normal-derivative columns, own and neighbour side
+        if (t < NF) {
+            const int e1 = t % N, e2 = t / N;
+            const int mo = s ? N - 1 : 0, mn = s ? 0 : N - 1;
+            const double *xn = x + (int64_t)nb * ND;
+            double dov = 0.0, dnv = 0.0;
+            for (int m = 0; m < N; ++m) {
+                dov += sDL[s][m] * sX[qlay<N>(d, m, e1, e2)];
+                dnv += sDL[1 - s][m] * xn[qlay<N>(d, m, e1, e2)];
+            }
+            Lo[t] = sX[qlay<N>(d, mo, e1, e2)];
+            Do[t] = dov;
+            Ln[t] = xn[qlay<N>(d, mn, e1, e2)];
+            Dn[t] = dnv;
+        }
+        __syncthreads();
+        // face points: values, tangential and normal derivatives, flux terms
+        if (t < Q2) {
+            const int a = t % Q, b = t / Q;
+            double vo = 0, t1o = 0, t2o = 0, dno = 0, vn = 0, t1n = 0, t2n = 0, dnn = 0;
+            for (int e2 = 0; e2 < N; ++e2) {
+                const double bb = sB[b * N + e2], db = sD[b * N + e2];
+                for (int e1 = 0; e1 < N; ++e1) {
+                    const double ba = sB[a * N + e1], da = sD[a * N + e1];
+                    const int k = e1 + N * e2;
+                    vo += ba * bb * Lo[k];
+                    t1o += da * bb * Lo[k];
+                    t2o += ba * db * Lo[k];
+                    dno += ba * bb * Do[k];
+                    vn += ba * bb * Ln[k];
+                    t1n += da * bb * Ln[k];
+                    t2n += ba * db * Ln[k];
+                    dnn += ba * bb * Dn[k];
+                }
+            }
+            const int64_t fid = s ? cid : (int64_t)nb;
+            const double *fd = face + (fid * 3 + d) * 7 * Q2 + t;
+            const int go = s ? 0 : 3, gn = s ? 3 : 0;
+            const double flux = fd[go * Q2] * dno + fd[(go + 1) * Q2] * t1o + fd[(go + 2) * Q2] * t2o +
+                                fd[gn * Q2] * dnn + fd[(gn + 1) * Q2] * t1n + fd[(gn + 2) * Q2] * t2n;
+            const double jump = s ? (vo - vn) : (vn - vo);
+            const double sg = s ? 1.0 : -1.0;
+            const double hj = -0.5 * jump;
+            Pv[t] = sg * (-0.5 * flux + fd[6 * Q2] * jump);
+            Pn[t] = hj * fd[go * Q2];
+            P1[t] = hj * fd[(go + 1) * Q2];
+            P2[t] = hj * fd[(go + 2) * Q2];
+        }
+        __syncthreads();
+        // back to layer weights (value test) and normal-derivative weights
+        if (t < NF) {
+            const int e1 = t % N, e2 = t / N;
+            double f0 = 0.0, f1 = 0.0;
+            for (int b = 0; b < Q; ++b) {
+                const double bb = sB[b * N + e2], db = sD[b * N + e2];
+                for (int a = 0; a < Q; ++a) {
+                    const double ba = sB[a * N + e1], da = sD[a * N + e1];
+                    const int k = a + Q * b;
+                    f0 += ba * bb * Pv[k] + da * bb * P1[k] + ba * db * P2[k];
+                    f1 += ba * bb * Pn[k];
+                }
+            }
+            FA[f][0][t] = f0;
+            FA[f][1][t] = f1;
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    // pencil owners (j, l) add the six faces
+    if (t < NF) {
+        const int j = t % N, l = t / N;
+        for (int s = 0; s < 2; ++s) {
+            const int layer = s ? N - 1 : 0;
+            // x faces: normal coordinate i, (e1, e2) = (j, l)
+            {
+                const double f0 = FA[s][0][j + N * l], f1 = FA[s][1][j + N * l];
+                for (int i = 0; i < N; ++i) Y[i] += sDL[s][i] * f1 + (i == layer ? f0 : 0.0);
+            }
+            // y faces: normal coordinate j, (e1, e2) = (i, l)
+            for (int i = 0; i < N; ++i)
+                Y[i] += sDL[s][j] * FA[2 + s][1][i + N * l] + (j == layer ? FA[2 + s][0][i + N * l] : 0.0);
+            // z faces: normal coordinate l, (e1, e2) = (i, j)
+            for (int i = 0; i < N; ++i)
+                Y[i] += sDL[s][l] * FA[4 + s][1][i + N * j] + (l == layer ? FA[4 + s][0][i + N * j] : 0.0);
+        }
+        for (int i = 0; i < N; ++i) y[cid * ND + i + N * j + NF * l] = Y[i];
+    }
+}
+
+template <int N>
+hipError_t apply_q_n(hx_ctx *c, const double *x, double *y)
+{
+    constexpr int Q = 2 * N - 1;
+    hipLaunchKernelGGL(k_apply_q<N>, dim3((unsigned)c->n_cells), dim3(QCfg<N, Q>::NT), 0,
+                       c->stream, x, y, c->qcell, c->qface, c->nbr, c->refq, c->ref, (int)c->n_cells);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_apply_q(hx_ctx *c, const double *x, double *y)
+{
+    if (c->nq != 2 * c->n - 1) return hipErrorInvalidValue;
+    switch (c->n) {
+    case 2: return apply_q_n<2>(c, x, y);
+    case 3: return apply_q_n<3>(c, x, y);
+    case 4: return apply_q_n<4>(c, x, y);
+    case 5: return apply_q_n<5>(c, x, y);
+    case 6: return apply_q_n<6>(c, x, y);
+    case 7: return apply_q_n<7>(c, x, y);
+    case 8: return apply_q_n<8>(c, x, y);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace hx

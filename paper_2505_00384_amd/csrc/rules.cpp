@@ -241,4 +241,19 @@ void build_ref_tables(int n, RefTab64 &t)
         for (int q = 0; q < n; ++q) t.Binv[i * n + q] = W[i][n + q];
 }
 
+void build_q_tables(int n, int nq, RefTabQ &t)
+{
+    t.nq = nq;
+    double xl[MAXN], wl[MAXN], v[MAXN], d[MAXN];
+    rule_gauss_lobatto(n, xl, wl);
+    rule_gauss_legendre(nq, t.xq, t.wq);
+    for (int q = 0; q < nq; ++q) {
+        lagrange_eval(n, xl, t.xq[q], v, d);
+        for (int i = 0; i < n; ++i) {
+            t.B[q * n + i] = v[i];
+            t.BD[q * n + i] = d[i];
+        }
+    }
+}
+
 }  // namespace hx
