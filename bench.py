@@ -153,6 +153,45 @@ def time_call(fn, reps, torch):
     return e0.elapsed_time(e1) / reps
 
 
+def consistent_suite(ctx, torch, k, reps=10):
+    """The operator with consistent integration (2k+1 Gauss points): time per
+    application, algorithmic bytes (7 nq^3 + 21 nq^2 numbers per cell, plus x
+    and y), and its difference to the fast operator on a smooth field (the
+    aliasing of the (k+1)-point rule)."""
+    import synth_inputs as si
+    xyz = ctx.dof_coordinates()
+    fa, fb = si.terrain_coefficients()
+    a, b = field_on_device(fa, xyz, torch), field_on_device(fb, xyz, torch)
+    t0 = time.time()
+    ctx.set_consistent(a, b)
+    torch.cuda.synchronize()
+    t_set = time.time() - t0
+    x = field_on_device(si.rhs_terrain(0), xyz, torch)
+    del xyz, a, b
+    y = torch.empty_like(x)
+    ms = time_call(lambda: ctx.apply_consistent(x, y), reps, torch)
+    n = ctx.n_dofs
+    nq, nd = 2 * k + 1, (k + 1) ** 3
+    bpd = (7 * nq ** 3 + 21 * nq ** 2) * 8 / nd + 16
+    yf = ctx.apply_operator(x)
+    alias = float(torch.linalg.norm(yf - y) / torch.linalg.norm(y))
+    # the same for a rough field (seeded normal entries)
+    g = torch.Generator(device=x.device)
+    g.manual_seed(7)
+    xr = torch.randn(n, dtype=torch.float64, device=x.device, generator=g)
+    ctx.apply_consistent(xr, y)
+    yf = ctx.apply_operator(xr)
+    alias_r = float(torch.linalg.norm(yf - y) / torch.linalg.norm(y))
+    del xr
+    out = dict(nq=nq, ms=round(ms, 3), gdofs=round(n / (ms * 1e-3) / 1e9, 3),
+               alg_bytes_per_dof=round(bpd, 1), alg_GBs=round(bpd * n / (ms * 1e-3) / 1e9, 1),
+               set_consistent_s=round(t_set, 2), rel_diff_fast_vs_consistent_smooth=alias,
+               rel_diff_fast_vs_consistent_random=alias_r)
+    log(f"consistent integration: {out}")
+    del x, y, yf
+    return out
+
+
 def pressure_suite(hx, ctx, torch, label, forms, reps=10, fixed_point=False):
     """The pressure system of the IMEX stage (S = D - C A^-1 B) on the
     isothermal background: timing of S and its parts, FGMRES solves of
@@ -302,6 +341,7 @@ def main():
 
     solve = {}
     pressure = {}
+    consistent = None
     if not args.no_solve:
         b = x
         forms = [
@@ -318,6 +358,7 @@ def main():
         del y
         solve[f"terrain{args.nx}x{args.ny}x{args.nz}"] = solve_suite(hx, ctx, b, torch,
                                                                      forms + cg_forms, "C3")
+        consistent = consistent_suite(ctx, torch, k)
         # the pressure system of the stage on the same mesh: FGMRES with the
         # block Jacobi of the Helmholtz-type operator
         pressure[f"terrain{args.nx}x{args.ny}x{args.nz}"] = pressure_suite(
@@ -405,6 +446,7 @@ def main():
         "cpu_baseline": cpu,
         "solve": solve,
         "pressure_system": pressure,
+        "consistent_integration": consistent,
         "setup": setup_times,
         **extra,
     }
