@@ -157,3 +157,62 @@ def ir_solve(apply: Callable, b: np.ndarray, inner: Callable, restart: int = 10,
     """Outer FP64 FGMRES whose (variable) preconditioner is ``inner(r)``."""
     return fgmres(apply, b, precond=inner, restart=restart, rtol=rtol,
                   max_iter=max_iter)
+
+
+# ---------------------------------------------------------------------------
+# Chebyshev polynomial preconditioning with Lanczos eigenvalue estimates
+# (section 3.1 names this technique for the symmetric positive-definite
+# systems: a polynomial damping the eigenvalue range, the range estimated
+# from the Lanczos process)
+# ---------------------------------------------------------------------------
+
+def lanczos_bounds(apply: Callable, precond: Callable, b: np.ndarray, iters: int):
+    """Extreme eigenvalues of M^{-1} A from `iters` steps of preconditioned CG
+    on A x = b: with step lengths a_k and direction ratios g_k the Lanczos
+    matrix is tridiagonal with T[k,k] = 1/a_k + g_{k-1}/a_{k-1} and
+    T[k,k+1] = sqrt(g_k)/a_k; its eigenvalues are Ritz values of M^{-1} A."""
+    r = np.array(b, dtype=np.float64)
+    z = precond(r)
+    p = z.copy()
+    rz = float(r @ z)
+    al, ga = [], []
+    for _ in range(iters):
+        q = apply(p)
+        a = rz / float(p @ q)
+        r = r - a * q
+        z = precond(r)
+        rz_new = float(r @ z)
+        g = rz_new / rz
+        al.append(a)
+        ga.append(g)
+        p = z + g * p
+        rz = rz_new
+    m = len(al)
+    T = np.zeros((m, m))
+    for k in range(m):
+        T[k, k] = 1.0 / al[k] + (ga[k - 1] / al[k - 1] if k > 0 else 0.0)
+        if k + 1 < m:
+            T[k, k + 1] = T[k + 1, k] = math.sqrt(ga[k]) / al[k]
+    ev = np.linalg.eigvalsh(T)
+    return float(ev[0]), float(ev[-1])
+
+
+def chebyshev_apply(apply: Callable, precond: Callable, r: np.ndarray, lo: float, hi: float,
+                    degree: int):
+    """z = p(M^{-1} A) M^{-1} r: `degree` steps of the Chebyshev iteration for
+    A z = r from z = 0 with the interval [lo, hi] of M^{-1} A, so that
+    r - A z = T_m((theta - A M^{-1}) / delta) / T_m(theta / delta) r with
+    theta = (hi + lo)/2, delta = (hi - lo)/2 (the classical three-term
+    recurrence for the scaled Chebyshev polynomials)."""
+    theta, delta = 0.5 * (hi + lo), 0.5 * (hi - lo)
+    sigma = theta / delta
+    rho = 1.0 / sigma
+    d = precond(r) / theta
+    z = d.copy()
+    for _ in range(degree - 1):
+        rho_new = 1.0 / (2.0 * sigma - rho)
+        res = r - apply(z)
+        d = rho_new * rho * d + (2.0 * rho_new / delta) * precond(res)
+        z = z + d
+        rho = rho_new
+    return z
