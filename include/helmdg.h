@@ -71,7 +71,8 @@ typedef enum {
     HX_PC_LEARNED = 2,        /* block Jacobi + per-cell network correction */
     HX_PC_HELMHOLTZ_DIAG = 3, /* inverse diagonal of the volume terms (mass + stiffness) */
     HX_PC_MASS_DIAG = 4,      /* inverse diagonal of the mass term alone */
-    HX_PC_MASS_BLOCK = 5      /* exact inverse of the alpha-weighted cell mass blocks */
+    HX_PC_MASS_BLOCK = 5,     /* exact inverse of the alpha-weighted cell mass blocks */
+    HX_PC_CHEBYSHEV = 6       /* Chebyshev polynomial in M^-1 A, M = block Jacobi (FP64) */
 } hx_pc;
 
 /* Create a context on `device` (HIP ordinal) whose kernels run on
@@ -219,6 +220,22 @@ void hx_default_params(hx_solve_params *p);
  * HX_ERR_NOCONV. */
 hx_status hx_solve(hx_ctx *c, const hx_solve_params *prm, const double *b,
                    double *x, hx_solve_info *info);
+
+/* Chebyshev polynomial preconditioner (section 3.1 names it for the
+ * symmetric positive-definite systems: a polynomial that damps the eigenvalue
+ * range of the preconditioned operator, the range estimated by the Lanczos
+ * process).  HX_PC_CHEBYSHEV applies z = p(M^-1 A) M^-1 r: `degree` steps of
+ * the Chebyshev iteration for A z = r from z = 0 on the interval [lo, hi] of
+ * the eigenvalues of M^-1 A, M the block Jacobi preconditioner; each step
+ * costs one operator and one block-Jacobi application.  The result is a
+ * fixed SPD operator when lo is at most the smallest eigenvalue, so CG may
+ * use it.  hx_set_chebyshev stores degree (1..64) and 0 < lo < hi.
+ * hx_estimate_eigenvalues runs `iters` (1..200) steps of CG with block
+ * Jacobi on A x = b (b DEVICE FP64 [n_dofs], e.g. random) and returns the
+ * extreme Ritz values of M^-1 A (HOST) from the Lanczos tridiagonal matrix of
+ * the CG coefficients: lo from above, hi from below. */
+hx_status hx_set_chebyshev(hx_ctx *c, int degree, double lo, double hi);
+hx_status hx_estimate_eigenvalues(hx_ctx *c, const double *b, int iters, double *lo, double *hi);
 
 /* ---------------------------------------------------------------------- */
 /* consistent integration                                                   */

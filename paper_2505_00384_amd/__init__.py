@@ -22,7 +22,7 @@ HX_OK, HX_ERR_ARG, HX_ERR_STATE, HX_ERR_DEVICE, HX_ERR_OOM, HX_ERR_MESH, \
     HX_ERR_NOCONV, HX_FALLBACK_USED = range(8)
 HX_F64, HX_F32 = 0, 1
 (HX_PC_NONE, HX_PC_BLOCK_JACOBI, HX_PC_LEARNED, HX_PC_HELMHOLTZ_DIAG, HX_PC_MASS_DIAG,
- HX_PC_MASS_BLOCK) = range(6)
+ HX_PC_MASS_BLOCK, HX_PC_CHEBYSHEV) = range(7)
 HX_EXPORT_CELL_DATA, HX_EXPORT_FACE_DATA, HX_EXPORT_SIGMA, HX_EXPORT_VOLUME, \
     HX_EXPORT_BJ_SCALARS, HX_EXPORT_INV_DIAG = range(6)
 HX_PS_GRAD, HX_PS_DIV, HX_PS_VMASS_INV, HX_PS_DMASS, HX_PS_SYSTEM = range(5)
@@ -94,6 +94,8 @@ def load(path: str = LIB_PATH):
                                    C.c_int),
         "hx_apply_pressure_part": ([vp, C.c_int, vp, vp], C.c_int),
         "hx_set_consistent": ([vp, vp, vp, C.c_int], C.c_int),
+        "hx_set_chebyshev": ([vp, C.c_int, C.c_double, C.c_double], C.c_int),
+        "hx_estimate_eigenvalues": ([vp, vp, C.c_int, dp, dp], C.c_int),
         "hx_apply_consistent": ([vp, vp, vp], C.c_int),
         "hx_pressure_rhs": ([vp, vp, vp, vp], C.c_int),
         "hx_pressure_velocity": ([vp, vp, vp, vp], C.c_int),
@@ -191,6 +193,16 @@ class HelmDG:
             a = alpha.contiguous(); b = beta.contiguous()
             st = self.L.hx_set_coefficients(self.h, _ptr(a), _ptr(b), float(penalty), 1)
         self._chk(st, "set_coefficients")
+
+    # -- Chebyshev preconditioner ---------------------------------------------
+    def set_chebyshev(self, degree: int, lo: float, hi: float):
+        self._chk(self.L.hx_set_chebyshev(self.h, int(degree), float(lo), float(hi)), "set_chebyshev")
+
+    def estimate_eigenvalues(self, b, iters: int = 20):
+        lo, hi = C.c_double(), C.c_double()
+        self._chk(self.L.hx_estimate_eigenvalues(self.h, _ptr(b), int(iters), C.byref(lo), C.byref(hi)),
+                  "estimate_eigenvalues")
+        return lo.value, hi.value
 
     # -- consistent integration (2k+1 Gauss points) ----------------------------
     def set_consistent(self, alpha, beta):

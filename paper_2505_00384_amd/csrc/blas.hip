@@ -507,7 +507,8 @@ hipError_t reduce_parts(hx_ctx *c, const double *part, int64_t n, double *dst)
 }
 
 // One fused CG step around the preconditioner pc (none, block Jacobi, the
-// cell mass blocks or a diagonal kind): x += a p, r -= a q, z = M^{-1} r, sc[2] = r.z, sc[3] = r.r.
+// cell mass blocks, a diagonal kind, or the Chebyshev polynomial after the
+// update): x += a p, r -= a q, z = M^{-1} r, sc[2] = r.z, sc[3] = r.r.
 template <typename T>
 hipError_t cg_step_pc(hx_ctx *c, int pc, T *x, T *r, const T *p, const T *q, T *z, double *sc)
 {
@@ -541,10 +542,20 @@ hipError_t cg_step_pc(hx_ctx *c, int pc, T *x, T *r, const T *p, const T *q, T *
     if (nb > 8192) {
         // one partial sum per block of the fused cell-block kernels: two stages
         e = reduce_parts(c, c->cgpart, nb, sc + 2);
-        return e != hipSuccess ? e : reduce_parts(c, c->cgpart + ld, nb, sc + 3);
+        if (e == hipSuccess) e = reduce_parts(c, c->cgpart + ld, nb, sc + 3);
+    } else {
+        hipLaunchKernelGGL(k_red2, dim3(2), dim3(RT), 0, c->stream, c->cgpart, nb, ld, sc + 2);
+        e = hipGetLastError();
     }
-    hipLaunchKernelGGL(k_red2, dim3(2), dim3(RT), 0, c->stream, c->cgpart, nb, ld, sc + 2);
-    return hipGetLastError();
+    if constexpr (sizeof(T) == 8) {
+        // the polynomial preconditioner: z = r above, now z = p(M^-1 A) M^-1 r
+        // and sc[2] = r.z
+        if (e == hipSuccess && pc == HX_PC_CHEBYSHEV) {
+            e = cheb_apply64(c, (const double *)r, (double *)z);
+            if (e == hipSuccess) e = blas_dot(c, n, (const double *)r, (const double *)z, sc + 2);
+        }
+    }
+    return e;
 }
 
 template <typename T>

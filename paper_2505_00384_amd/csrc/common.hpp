@@ -90,6 +90,10 @@ struct hx_ctx {
     double *psFn = nullptr;       // [n_cells][6][3][nf] outward ds n on the own faces
     double *psFh = nullptr;       // [n_cells][6][nf]  h rho on the own faces
     double *psWork = nullptr;     // [7][n_dofs]       velocity temporaries and C A^-1 B x
+    // Chebyshev preconditioner: degree and interval of M^-1 A (M = block Jacobi)
+    int cheb_deg = 0;
+    double cheb_lo = 0.0, cheb_hi = 0.0;
+    double *chebw = nullptr;      // [3][n_dofs]
     // consistent integration: the operator with nq = 2k+1 Gauss points
     bool has_q = false;
     int nq = 0;
@@ -164,6 +168,8 @@ hipError_t press_apply64(hx_ctx *c, const double *x, double *y, const double *b)
 // y = A_q x
 hipError_t launch_q_setup(hx_ctx *c, const double *alpha, const double *beta);
 hipError_t launch_apply_q(hx_ctx *c, const double *x, double *y);
+// z = p(M^-1 A) M^-1 r, the Chebyshev polynomial preconditioner (FP64)
+hipError_t cheb_apply64(hx_ctx *c, const double *r, double *z);
 // h = gamma p / ((gamma - 1) rho) at the nodes
 hipError_t launch_enthalpy(hx_ctx *c, const double *p, const double *rho, double gamma, double *h);
 hipError_t launch_massinv32(hx_ctx *c, const float *r, float *z);

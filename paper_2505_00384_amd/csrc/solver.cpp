@@ -18,6 +18,7 @@
 //    vector is not finite or the residual estimate stalls over stall_window
 //    iterations, the solver restarts from the current x with block Jacobi.
 #include <chrono>
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -142,6 +143,7 @@ hx_status precondition(hx_ctx *c, int pc, int mixed, int inner_iters, const doub
     case HX_PC_HELMHOLTZ_DIAG: HX_HIP(c, launch_diag64(c, 0, v, z)); return HX_OK;
     case HX_PC_MASS_DIAG: HX_HIP(c, launch_diag64(c, 1, v, z)); return HX_OK;
     case HX_PC_MASS_BLOCK: HX_HIP(c, launch_massinv64(c, v, z)); return HX_OK;
+    case HX_PC_CHEBYSHEV: HX_HIP(c, cheb_apply64(c, v, z)); return HX_OK;
     default: return fail(c, HX_ERR_ARG, "unknown preconditioner %d", pc);
     }
 }
@@ -559,6 +561,35 @@ hx_status solve_fgmres(hx_ctx *c, const hx_solve_params *prm, const double *b, d
 }
 
 }  // namespace
+
+// Chebyshev polynomial preconditioner (section 3.1 names it for the SPD
+// systems: a polynomial in M^-1 A that damps the eigenvalue range, the range
+// estimated by the Lanczos process; M = block Jacobi).  degree steps of the
+// Chebyshev iteration for A z = r from z = 0 on [lo, hi]:
+//   d = M^-1 r / theta, z = d; then rho' = 1/(2 sigma - rho),
+//   d = rho' rho d + (2 rho' / delta) M^-1 (r - A z), z += d,
+// theta = (hi + lo)/2, delta = (hi - lo)/2, sigma = theta/delta, rho = 1/sigma.
+hipError_t cheb_apply64(hx_ctx *c, const double *r, double *z)
+{
+    const int64_t n = c->n_dofs;
+    double *res = c->chebw, *d = res + n, *t = d + n;
+    const double theta = 0.5 * (c->cheb_hi + c->cheb_lo), delta = 0.5 * (c->cheb_hi - c->cheb_lo);
+    const double sigma = theta / delta;
+    double rho = 1.0 / sigma;
+    hipError_t e = launch_bj64(c, r, t);
+    if (e == hipSuccess) e = blas_axpby(c, n, 1.0 / theta, t, 0.0, d);
+    if (e == hipSuccess) e = blas_copy(c, n, d, z);
+    for (int k = 1; k < c->cheb_deg && e == hipSuccess; ++k) {
+        const double rn = 1.0 / (2.0 * sigma - rho);
+        e = launch_apply64(c, z, res, r);                       // res = r - A z
+        if (e == hipSuccess) e = launch_bj64(c, res, t);
+        if (e == hipSuccess) e = blas_axpby(c, n, 2.0 * rn / delta, t, rn * rho, d);
+        if (e == hipSuccess) e = blas_axpby(c, n, 1.0, d, 1.0, z);
+        rho = rn;
+    }
+    return e;
+}
+
 }  // namespace hx
 
 using namespace hx;
@@ -601,13 +632,17 @@ hx_status hx_solve(hx_ctx *c, const hx_solve_params *prm, const double *b, doubl
         return fail(c, HX_ERR_ARG, "restart must be in 1..63");
     if (prm->orth != 0 && prm->orth != 1) return fail(c, HX_ERR_ARG, "orth must be 0 or 1");
     if (!(prm->rtol > 0.0) || prm->max_iter < 1) return fail(c, HX_ERR_ARG, "bad rtol/max_iter");
-    if (prm->pc < HX_PC_NONE || prm->pc > HX_PC_MASS_BLOCK) return fail(c, HX_ERR_ARG, "bad pc");
+    if (prm->pc < HX_PC_NONE || prm->pc > HX_PC_CHEBYSHEV) return fail(c, HX_ERR_ARG, "bad pc");
     if (prm->method == 0 && (prm->pc == HX_PC_LEARNED || prm->mixed))
         return fail(c, HX_ERR_ARG, "CG needs a fixed SPD preconditioner; use FGMRES");
     if (prm->mixed && prm->inner_iters < 1) return fail(c, HX_ERR_ARG, "inner_iters must be >= 1");
     if (prm->mixed && prm->pc == HX_PC_LEARNED)
         return fail(c, HX_ERR_ARG, "the learned preconditioner is FP64; it cannot precondition the inner FP32 solve");
     if (prm->pc == HX_PC_LEARNED && !c->mlp) return fail(c, HX_ERR_STATE, "no network loaded");
+    if (prm->pc == HX_PC_CHEBYSHEV && c->cheb_deg < 1)
+        return fail(c, HX_ERR_STATE, "Chebyshev preconditioner not set");
+    if (prm->pc == HX_PC_CHEBYSHEV && prm->mixed)
+        return fail(c, HX_ERR_ARG, "the Chebyshev preconditioner is FP64; it cannot precondition the inner FP32 solve");
     if (prm->system != 0 && prm->system != 1) return fail(c, HX_ERR_ARG, "system must be 0 or 1");
     if (prm->system == 1 && !c->has_press) return fail(c, HX_ERR_STATE, "pressure system not set");
     if (prm->system == 1 && prm->method != 1)
@@ -699,6 +734,78 @@ hx_status hx_solve_pressure_fixed_point(hx_ctx *c, const double *rho, const doub
     if (!conv || !lin_ok)
         return fail(c, HX_ERR_NOCONV, "fixed point: change %.3e after %d iterations%s", change, it,
                     lin_ok ? "" : " (last linear solve not converged)");
+    return HX_OK;
+}
+
+
+hx_status hx_set_chebyshev(hx_ctx *c, int degree, double lo, double hi)
+{
+    if (!c) return HX_ERR_ARG;
+    if (!c->has_coef) return fail(c, HX_ERR_STATE, "set_chebyshev before set_coefficients");
+    if (degree < 1 || degree > 64) return fail(c, HX_ERR_ARG, "degree must be in 1..64");
+    if (!(lo > 0.0) || !(hi > lo) || !std::isfinite(hi)) return fail(c, HX_ERR_ARG, "need 0 < lo < hi");
+    HX_HIP(c, hipSetDevice(c->device));
+    if (!c->chebw) {
+        hx_status s = dalloc(c, (void **)&c->chebw, sizeof(double) * 3 * c->n_dofs);
+        if (s != HX_OK) return s;
+    }
+    c->cheb_deg = degree;
+    c->cheb_lo = lo;
+    c->cheb_hi = hi;
+    return HX_OK;
+}
+
+hx_status hx_estimate_eigenvalues(hx_ctx *c, const double *b, int iters, double *lo, double *hi)
+{
+    if (!c) return HX_ERR_ARG;
+    if (!c->has_coef) return fail(c, HX_ERR_STATE, "estimate before set_coefficients");
+    if (!b || !lo || !hi || iters < 1 || iters > 200) return fail(c, HX_ERR_ARG, "bad arguments");
+    HX_HIP(c, hipSetDevice(c->device));
+    const int64_t n = c->n_dofs;
+    hx_status s = ensure_work(c, 4 * (size_t)n, 0);
+    if (s != HX_OK) return s;
+    double *r = c->work64, *z = r + n, *p = z + n, *q = p + n;
+    double *sc = c->red + SC_OFF + 310;
+    HX_HIP(c, blas_copy(c, n, b, r));
+    HX_HIP(c, launch_bj64(c, r, z));
+    HX_HIP(c, blas_copy(c, n, z, p));
+    HX_HIP(c, blas_dot(c, n, r, z, sc));
+    double rz;
+    if ((s = read_scalars(c, sc, 1, &rz)) != HX_OK) return s;
+    std::vector<double> al, ga;
+    for (int k = 0; k < iters && rz > 0.0; ++k) {
+        double pq, rzn;
+        HX_HIP(c, launch_apply64(c, p, q, nullptr));
+        HX_HIP(c, blas_dot(c, n, p, q, sc + 1));
+        if ((s = read_scalars(c, sc + 1, 1, &pq)) != HX_OK) return s;
+        if (!(pq > 0.0)) break;
+        const double a = rz / pq;
+        HX_HIP(c, blas_axpby(c, n, -a, q, 1.0, r));
+        HX_HIP(c, launch_bj64(c, r, z));
+        HX_HIP(c, blas_dot(c, n, r, z, sc + 2));
+        if ((s = read_scalars(c, sc + 2, 1, &rzn)) != HX_OK) return s;
+        const double g = rzn / rz;
+        al.push_back(a);
+        ga.push_back(g);
+        HX_HIP(c, blas_axpby(c, n, 1.0, z, g, p));
+        rz = rzn;
+    }
+    const int m = (int)al.size();
+    if (m < 1) return fail(c, HX_ERR_ARG, "no Lanczos step possible");
+    // Lanczos tridiagonal matrix from the CG coefficients, dense for sym_eig
+    std::vector<double> T((size_t)m * m, 0.0), w(m), v((size_t)m * m);
+    for (int k = 0; k < m; ++k) {
+        T[(size_t)k * m + k] = 1.0 / al[k] + (k > 0 ? ga[k - 1] / al[k - 1] : 0.0);
+        if (k + 1 < m) T[(size_t)k * m + k + 1] = T[(size_t)(k + 1) * m + k] = std::sqrt(ga[k]) / al[k];
+    }
+    sym_eig(m, T.data(), w.data(), v.data());
+    double mn = w[0], mx = w[0];
+    for (int k = 1; k < m; ++k) {
+        mn = std::min(mn, w[k]);
+        mx = std::max(mx, w[k]);
+    }
+    *lo = mn;
+    *hi = mx;
     return HX_OK;
 }
 
