@@ -358,6 +358,24 @@ def main():
         del y
         solve[f"terrain{args.nx}x{args.ny}x{args.nz}"] = solve_suite(hx, ctx, b, torch,
                                                                      forms + cg_forms, "C3")
+        # CG with the Chebyshev polynomial (degree 4) around block Jacobi, its
+        # interval from 20 Lanczos steps on a random vector (timed apart)
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(3)
+        rv = torch.randn(n, dtype=torch.float64, device=dev, generator=gen)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        lo, hi = ctx.estimate_eigenvalues(rv, 20)
+        torch.cuda.synchronize()
+        t_est = (time.time() - t0) * 1e3
+        del rv
+        ctx.set_chebyshev(4, lo, 1.1 * hi)
+        cheb = solve_suite(hx, ctx, b, torch, [
+            ("fp64_cg_chebyshev4_bj", hx.default_params(method=0, rtol=1e-8,
+                                                        pc=hx.HX_PC_CHEBYSHEV))], "C3")
+        cheb["fp64_cg_chebyshev4_bj"].update(lanczos_ms=round(t_est, 1), lanczos_lo=lo,
+                                             lanczos_hi=hi)
+        solve[f"terrain{args.nx}x{args.ny}x{args.nz}"].update(cheb)
         consistent = consistent_suite(ctx, torch, k)
         # the pressure system of the stage on the same mesh: FGMRES with the
         # block Jacobi of the Helmholtz-type operator
