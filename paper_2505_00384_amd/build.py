@@ -32,8 +32,8 @@ def sources():
 
 
 def generate_tables():
-    """Compile and run the table generator (host only) into _build/optables.inc
-    and _build/optables_binv.inc."""
+    """Compile and run the table generator (host only) into _build/optables.inc,
+    _build/optables_binv.inc and _build/optables_q.inc."""
     exe = os.path.join(BUILD, "gen_tables")
     cmd = [HIPCC, "-O2", "-std=c++17", "-I" + CSRC, os.path.join(CSRC, GEN),
            os.path.join(CSRC, "rules.cpp"), "-o", exe]
@@ -41,7 +41,8 @@ def generate_tables():
     if r.returncode != 0:
         raise RuntimeError(f"table generator failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     subprocess.check_call([exe, os.path.join(BUILD, "optables.inc"),
-                           os.path.join(BUILD, "optables_binv.inc")])
+                           os.path.join(BUILD, "optables_binv.inc"),
+                           os.path.join(BUILD, "optables_q.inc")])
 
 
 def _compile(src: str) -> str:

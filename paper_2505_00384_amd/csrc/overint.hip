@@ -20,6 +20,17 @@
 namespace hx {
 namespace {
 
+// compile-time B and BD at the 2N-1 Gauss points (generated at build time
+// from the library's rules, the same values as the set-up tables)
+template <int N> struct KBQ;
+template <int N> struct KBDQ;
+#include "optables_q.inc"
+
+template <int N>
+__device__ __forceinline__ constexpr double tq(int q, int i) { return KBQ<N>::d[q * N + i]; }
+template <int N>
+__device__ __forceinline__ constexpr double tdq(int q, int i) { return KBDQ<N>::d[q * N + i]; }
+
 template <int N, int Q>
 struct QCfg {
     static constexpr int ND = N * N * N, NF = N * N, Q2 = Q * Q, Q3 = Q * Q * Q;
@@ -68,12 +79,15 @@ k_apply_q(const double *__restrict__ x, double *__restrict__ y, const double *__
     if (t < NF) {
         const int j = t % N, l = t / N;
         double v[N];
+#pragma unroll
         for (int i = 0; i < N; ++i) v[i] = sX[i + N * j + NF * l];
+#pragma unroll
         for (int q = 0; q < Q; ++q) {
             double s0 = 0.0, s1 = 0.0;
+#pragma unroll
             for (int i = 0; i < N; ++i) {
-                s0 += sB[q * N + i] * v[i];
-                s1 += sD[q * N + i] * v[i];
+                s0 += tq<N>(q, i) * v[i];
+                s1 += tdq<N>(q, i) * v[i];
             }
             U0[q + Q * (j + N * l)] = s0;
             U1[q + Q * (j + N * l)] = s1;
@@ -85,16 +99,19 @@ k_apply_q(const double *__restrict__ x, double *__restrict__ y, const double *__
     if (t < C::QN) {
         const int qx = t % Q, l = t / Q;
         double v0[N], v1[N];
+#pragma unroll
         for (int j = 0; j < N; ++j) {
             v0[j] = U0[qx + Q * (j + N * l)];
             v1[j] = U1[qx + Q * (j + N * l)];
         }
+#pragma unroll
         for (int q = 0; q < Q; ++q) {
             double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
             for (int j = 0; j < N; ++j) {
-                s0 += sB[q * N + j] * v0[j];
-                s1 += sD[q * N + j] * v0[j];
-                s2 += sB[q * N + j] * v1[j];
+                s0 += tq<N>(q, j) * v0[j];
+                s1 += tdq<N>(q, j) * v0[j];
+                s2 += tq<N>(q, j) * v1[j];
             }
             V0[qx + Q * (q + Q * l)] = s0;
             V1[qx + Q * (q + Q * l)] = s1;
@@ -107,20 +124,24 @@ k_apply_q(const double *__restrict__ x, double *__restrict__ y, const double *__
     if (t < Q2) {
         const int qx = t % Q, qy = t / Q;
         double a0[N], a1[N], a2[N];
+#pragma unroll
         for (int l = 0; l < N; ++l) {
             a0[l] = V0[qx + Q * (qy + Q * l)];
             a1[l] = V1[qx + Q * (qy + Q * l)];
             a2[l] = V2[qx + Q * (qy + Q * l)];
         }
+#pragma unroll
         for (int l = 0; l < N; ++l) w0[l] = w1[l] = w2[l] = 0.0;
         const double *cp = cell + cid * 7 * Q3 + qx + Q * qy;
+#pragma unroll
         for (int q = 0; q < Q; ++q) {
             double u = 0.0, dz = 0.0, dy = 0.0, dx = 0.0;
+#pragma unroll
             for (int l = 0; l < N; ++l) {
-                u += sB[q * N + l] * a0[l];
-                dz += sD[q * N + l] * a0[l];
-                dy += sB[q * N + l] * a1[l];
-                dx += sB[q * N + l] * a2[l];
+                u += tq<N>(q, l) * a0[l];
+                dz += tdq<N>(q, l) * a0[l];
+                dy += tq<N>(q, l) * a1[l];
+                dx += tq<N>(q, l) * a2[l];
             }
             const double *cq = cp + Q2 * q;
             const double m = cq[0], gxx = cq[Q3], gxy = cq[2 * Q3], gxz = cq[3 * Q3],
@@ -129,10 +150,11 @@ k_apply_q(const double *__restrict__ x, double *__restrict__ y, const double *__
             const double fx = gxx * dx + gxy * dy + gxz * dz;
             const double fy = gxy * dx + gyy * dy + gyz * dz;
             const double fz = gxz * dx + gyz * dy + gzz * dz;
+#pragma unroll
             for (int l = 0; l < N; ++l) {
-                w0[l] += sB[q * N + l] * v + sD[q * N + l] * fz;
-                w1[l] += sB[q * N + l] * fy;
-                w2[l] += sB[q * N + l] * fx;
+                w0[l] += tq<N>(q, l) * v + tdq<N>(q, l) * fz;
+                w1[l] += tq<N>(q, l) * fy;
+                w2[l] += tq<N>(q, l) * fx;
             }
         }
     }
@@ -151,13 +173,16 @@ k_apply_q(const double *__restrict__ x, double *__restrict__ y, const double *__
     if (t < C::QN) {
         const int qx = t % Q, l = t / Q;
         double s0[N], s1[N];
+#pragma unroll
         for (int j = 0; j < N; ++j) s0[j] = s1[j] = 0.0;
+#pragma unroll
         for (int q = 0; q < Q; ++q) {
             const double a0 = V0[qx + Q * (q + Q * l)], a1 = V1[qx + Q * (q + Q * l)],
                          a2 = V2[qx + Q * (q + Q * l)];
+#pragma unroll
             for (int j = 0; j < N; ++j) {
-                s0[j] += sB[q * N + j] * a0 + sD[q * N + j] * a1;
-                s1[j] += sB[q * N + j] * a2;
+                s0[j] += tq<N>(q, j) * a0 + tdq<N>(q, j) * a1;
+                s1[j] += tq<N>(q, j) * a2;
             }
         }
         for (int j = 0; j < N; ++j) {
@@ -170,14 +195,29 @@ k_apply_q(const double *__restrict__ x, double *__restrict__ y, const double *__
     double Y[N];
     if (t < NF) {
         const int j = t % N, l = t / N;
+#pragma unroll
         for (int i = 0; i < N; ++i) Y[i] = 0.0;
+#pragma unroll
         for (int q = 0; q < Q; ++q) {
             const double a0 = U0[q + Q * (j + N * l)], a1 = U1[q + Q * (j + N * l)];
-            for (int i = 0; i < N; ++i) Y[i] += sB[q * N + i] * a0 + sD[q * N + i] * a1;
+#pragma unroll
+            for (int i = 0; i < N; ++i) Y[i] += tq<N>(q, i) * a0 + tdq<N>(q, i) * a1;
         }
     }
 
     // ---------------------------------------------------------------- faces
+    // the face-point lanes (a, b) keep their rows of B and BD
+    double Ra[N], Rda[N], Rb[N], Rdb[N];
+    if (t < Q2) {
+        const int a = t % Q, b = t / Q;
+#pragma unroll
+        for (int e = 0; e < N; ++e) {
+            Ra[e] = sB[a * N + e];
+            Rda[e] = sD[a * N + e];
+            Rb[e] = sB[b * N + e];
+            Rdb[e] = sD[b * N + e];
+        }
+    }
     for (int f = 0; f < 6; ++f) {
         const int d = f >> 1, s = f & 1;
         const int32_t nb = nbr[6 * cid + f];
@@ -203,12 +243,13 @@ k_apply_q(const double *__restrict__ x, double *__restrict__ y, const double *__
         __syncthreads();
         // face points: values, tangential and normal derivatives, flux terms
         if (t < Q2) {
-            const int a = t % Q, b = t / Q;
             double vo = 0, t1o = 0, t2o = 0, dno = 0, vn = 0, t1n = 0, t2n = 0, dnn = 0;
+#pragma unroll
             for (int e2 = 0; e2 < N; ++e2) {
-                const double bb = sB[b * N + e2], db = sD[b * N + e2];
+                const double bb = Rb[e2], db = Rdb[e2];
+#pragma unroll
                 for (int e1 = 0; e1 < N; ++e1) {
-                    const double ba = sB[a * N + e1], da = sD[a * N + e1];
+                    const double ba = Ra[e1], da = Rda[e1];
                     const int k = e1 + N * e2;
                     vo += ba * bb * Lo[k];
                     t1o += da * bb * Lo[k];
