@@ -42,6 +42,14 @@ def test_host_only_calls():
     assert L.hx_setup_mesh(None, 2, 1, 1, None, None) == hx.HX_ERR_ARG
     assert L.hx_apply_operator(None, 0, None, None) == hx.HX_ERR_ARG
     assert L.hx_solve(None, None, None, None, None) == hx.HX_ERR_ARG
+    assert L.hx_set_pressure_system(None, None, None, 1.4, 1.0, 2.0, 0) == hx.HX_ERR_ARG
+    assert L.hx_apply_pressure_part(None, 0, None, None) == hx.HX_ERR_ARG
+    assert L.hx_pressure_rhs(None, None, None, None) == hx.HX_ERR_ARG
+    assert L.hx_pressure_velocity(None, None, None, None) == hx.HX_ERR_ARG
+    assert L.hx_set_consistent(None, None, None, 0) == hx.HX_ERR_ARG
+    assert L.hx_apply_consistent(None, None, None) == hx.HX_ERR_ARG
+    assert L.hx_set_chebyshev(None, 4, 0.1, 1.0) == hx.HX_ERR_ARG
+    assert L.hx_estimate_eigenvalues(None, None, 10, None, None) == hx.HX_ERR_ARG
     assert L.hx_destroy(None) == hx.HX_OK
     assert L.hx_num_dofs(None) == -1
     out = C.c_void_p()
