@@ -152,6 +152,18 @@ def terrain_mesh(nx: int = 32, ny: int = 8, nz: int = 16, g: int = 4) -> Mesh:
     return m
 
 
+def refinement_parents(nx: int, ny: int, nz: int):
+    """Cell map of the box mesh (2nx, 2ny, 2nz) to the box mesh (nx, ny, nz)
+    over the same box: for each fine cell its parent cell and the octant
+    ox + 2 oy + 4 oz it occupies (cells numbered x fastest, then y, then z,
+    both meshes with the same axis orientation)."""
+    f = np.arange(8 * nx * ny * nz, dtype=np.int64)
+    fx, fy, fz = f % (2 * nx), (f // (2 * nx)) % (2 * ny), f // (4 * nx * ny)
+    parent = fx // 2 + nx * (fy // 2 + ny * (fz // 2))
+    octant = (fx & 1) + 2 * (fy & 1) + 4 * (fz & 1)
+    return parent.astype(np.int32), octant.astype(np.int32)
+
+
 def wavy_mapping(eps: float = 0.04):
     """A smooth, fully periodic deformation of the unit cube (curved cells)."""
     tp = 2.0 * math.pi

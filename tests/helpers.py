@@ -89,3 +89,34 @@ def constructed_pressure_state(mesh, k, gamma):
     ref = PressureSystem(mesh, k, rho, gamma * p_star / ((gamma - 1.0) * rho), gamma, tau)
     G = ref.apply(p_star) + ref.div(ref.a_inv(F))
     return rho, F, G, p_bg, p_star, tau
+
+
+def terrain_hierarchy(nx, ny, nz, n_levels, k, g=None):
+    """Terrain channels (nx, ny, nz), (nx/2, ny/2, nz/2), ... with the terrain
+    coefficients at each level's own dofs, and the cell maps between them."""
+    probs, maps = [], []
+    for l in range(n_levels):
+        s = 2 ** l
+        m = si.terrain_mesh(nx // s, ny // s, nz // s, g=k if g is None else g)
+        probs.append(problem(m, k, coef="terrain"))
+        if l + 1 < n_levels:
+            maps.append(si.refinement_parents(nx // (2 * s), ny // (2 * s), nz // (2 * s)))
+    return probs, maps
+
+
+def oracle_levels(probs, maps, smooth_degree=3, smooth_ratio=15.0, coarse_degree=12,
+                  lanczos_iters=20):
+    """Oracle multigrid levels: Chebyshev smoothing on [1.1 hi / ratio, 1.1 hi]
+    of each level's estimated range, the coarsest level's polynomial on
+    [0.9 lo, 1.1 hi]; the estimates come from the oracle's Lanczos process."""
+    from oracle.multigrid import Level
+    from oracle import solvers
+    levels = []
+    for l, p in enumerate(probs):
+        b = si.random_vector(p.n_dofs, 100 + l)
+        lo, hi = solvers.lanczos_bounds(p.apply, p.bj_apply, b, lanczos_iters)
+        if l + 1 < len(probs):
+            levels.append(Level(p, smooth_degree, 1.1 * hi / smooth_ratio, 1.1 * hi, *maps[l]))
+        else:
+            levels.append(Level(p, coarse_degree, 0.9 * lo, 1.1 * hi))
+    return levels
