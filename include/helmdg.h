@@ -72,7 +72,8 @@ typedef enum {
     HX_PC_HELMHOLTZ_DIAG = 3, /* inverse diagonal of the volume terms (mass + stiffness) */
     HX_PC_MASS_DIAG = 4,      /* inverse diagonal of the mass term alone */
     HX_PC_MASS_BLOCK = 5,     /* exact inverse of the alpha-weighted cell mass blocks */
-    HX_PC_CHEBYSHEV = 6       /* Chebyshev polynomial in M^-1 A, M = block Jacobi (FP64) */
+    HX_PC_CHEBYSHEV = 6,      /* Chebyshev polynomial in M^-1 A, M = block Jacobi (FP64) */
+    HX_PC_MULTIGRID = 7       /* one geometric multigrid V-cycle (FP64, hx_set_multigrid) */
 } hx_pc;
 
 /* Create a context on `device` (HIP ordinal) whose kernels run on
@@ -236,6 +237,38 @@ hx_status hx_solve(hx_ctx *c, const hx_solve_params *prm, const double *b,
  * the CG coefficients: lo from above, hi from below. */
 hx_status hx_set_chebyshev(hx_ctx *c, int degree, double lo, double hi);
 hx_status hx_estimate_eigenvalues(hx_ctx *c, const double *b, int iters, double *lo, double *hi);
+
+/* Geometric multigrid (section 3.1: CG preconditioned by geometric multigrid
+ * for the SPD systems, smoothed by Chebyshev polynomials).  Each level is a
+ * context of its own with its mesh, coefficients (the operator is
+ * re-discretised on every level) and Chebyshev polynomial (hx_set_chebyshev:
+ * the smoother, typically on [hi/15, 1.1 hi] of the level's estimated range;
+ * on the coarsest level it replaces the coarse solve, typically over the
+ * whole range with a higher degree).  hx_set_multigrid(c, coarse, ...) makes
+ * `coarse` the next coarser level of c; calling it on every level but the
+ * coarsest builds the hierarchy.  The levels must share the device, the
+ * stream and the degree, and the fine mesh must be a refinement of the
+ * coarse one: parent[f] (HOST int32 [n_cells of c]) is the coarse cell that
+ * holds fine cell f and octant[f] = ox + 2 oy + 4 oz (0..7) the octant of its
+ * reference cube that f fills, with the same axis orientation; no two cells
+ * may fill the same octant of one parent.  Prolongation writes the parent's
+ * polynomial in the child's basis (exact embedding of the spaces), and
+ * restriction is its transpose.  HX_PC_MULTIGRID then applies x = V r, one
+ * V-cycle: the level's Chebyshev polynomial from zero, the restricted
+ * residual handed to the next level's V-cycle and its prolongation added,
+ * and the same polynomial on the updated residual; it is a fixed symmetric
+ * operator, so CG may use it.  coarse = NULL removes the link.  c does not
+ * own `coarse`: keep it alive while linked; set up its mesh again and the
+ * link must be set again.  Errors: HX_ERR_ARG for bad maps, a degree,
+ * device or stream mismatch or a cycle of links; HX_ERR_STATE before
+ * hx_setup_mesh.  Working memory: 4 n_dofs doubles on each linked level.
+ *
+ * hx_mg_transfer applies one transfer of the link (DEVICE FP64 vectors):
+ * dir 0 restricts `in` ([n_dofs of c]) into `out` ([n_dofs of the coarse
+ * level], overwritten); dir 1 adds the prolongation of `in` (coarse) to
+ * `out` (fine).  in and out must not alias. */
+hx_status hx_set_multigrid(hx_ctx *c, hx_ctx *coarse, const int32_t *parent, const int32_t *octant);
+hx_status hx_mg_transfer(hx_ctx *c, int dir, const double *in, double *out);
 
 /* ---------------------------------------------------------------------- */
 /* consistent integration                                                   */

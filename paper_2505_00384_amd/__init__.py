@@ -22,7 +22,7 @@ HX_OK, HX_ERR_ARG, HX_ERR_STATE, HX_ERR_DEVICE, HX_ERR_OOM, HX_ERR_MESH, \
     HX_ERR_NOCONV, HX_FALLBACK_USED = range(8)
 HX_F64, HX_F32 = 0, 1
 (HX_PC_NONE, HX_PC_BLOCK_JACOBI, HX_PC_LEARNED, HX_PC_HELMHOLTZ_DIAG, HX_PC_MASS_DIAG,
- HX_PC_MASS_BLOCK, HX_PC_CHEBYSHEV) = range(7)
+ HX_PC_MASS_BLOCK, HX_PC_CHEBYSHEV, HX_PC_MULTIGRID) = range(8)
 HX_EXPORT_CELL_DATA, HX_EXPORT_FACE_DATA, HX_EXPORT_SIGMA, HX_EXPORT_VOLUME, \
     HX_EXPORT_BJ_SCALARS, HX_EXPORT_INV_DIAG = range(6)
 HX_PS_GRAD, HX_PS_DIV, HX_PS_VMASS_INV, HX_PS_DMASS, HX_PS_SYSTEM = range(5)
@@ -96,6 +96,8 @@ def load(path: str = LIB_PATH):
         "hx_set_consistent": ([vp, vp, vp, C.c_int], C.c_int),
         "hx_set_chebyshev": ([vp, C.c_int, C.c_double, C.c_double], C.c_int),
         "hx_estimate_eigenvalues": ([vp, vp, C.c_int, dp, dp], C.c_int),
+        "hx_set_multigrid": ([vp, vp, vp, vp], C.c_int),
+        "hx_mg_transfer": ([vp, C.c_int, vp, vp], C.c_int),
         "hx_apply_consistent": ([vp, vp, vp], C.c_int),
         "hx_pressure_rhs": ([vp, vp, vp, vp], C.c_int),
         "hx_pressure_velocity": ([vp, vp, vp, vp], C.c_int),
@@ -154,6 +156,11 @@ class HelmDG:
 
     def close(self):
         if getattr(self, "h", None):
+            # finer levels that link this one lose the link first
+            for fine in list(getattr(self, "_mg_finer", [])):
+                f = fine()
+                if f is not None and getattr(f, "h", None) and getattr(f, "_mg_coarse", None) is self:
+                    f.set_multigrid(None)
             self.L.hx_destroy(self.h)
             self.h = None
 
@@ -203,6 +210,29 @@ class HelmDG:
         self._chk(self.L.hx_estimate_eigenvalues(self.h, _ptr(b), int(iters), C.byref(lo), C.byref(hi)),
                   "estimate_eigenvalues")
         return lo.value, hi.value
+
+    # -- geometric multigrid ----------------------------------------------------
+    def set_multigrid(self, coarse, parent=None, octant=None):
+        """Make ``coarse`` (a HelmDG on the same device and stream) the next
+        coarser level: parent[f] and octant[f] per cell of this level.
+        ``coarse=None`` removes the link."""
+        if coarse is None:
+            self._chk(self.L.hx_set_multigrid(self.h, None, None, None), "set_multigrid")
+            self._mg_coarse = None
+            return
+        p = np.ascontiguousarray(parent, dtype=np.int32)
+        o = np.ascontiguousarray(octant, dtype=np.int32)
+        self._chk(self.L.hx_set_multigrid(self.h, coarse.h, p.ctypes.data, o.ctypes.data),
+                  "set_multigrid")
+        self._mg_coarse = coarse   # the library does not own the coarser level
+        import weakref
+        if not hasattr(coarse, "_mg_finer"):
+            coarse._mg_finer = []
+        coarse._mg_finer.append(weakref.ref(self))
+
+    def mg_transfer(self, direction: int, x, out):
+        """direction 0: out = R x (restriction); 1: out += P x (prolongation)."""
+        self._chk(self.L.hx_mg_transfer(self.h, int(direction), _ptr(x), _ptr(out)), "mg_transfer")
 
     # -- consistent integration (2k+1 Gauss points) ----------------------------
     def set_consistent(self, alpha, beta):

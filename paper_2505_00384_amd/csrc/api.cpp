@@ -50,11 +50,14 @@ static void free_mesh(hx_ctx *c)
                      (void **)&c->bjC32, (void **)&c->coef_feat, (void **)&c->work64,
                      (void **)&c->work32, (void **)&c->psW, (void **)&c->psWC, (void **)&c->psMr,
                      (void **)&c->psMd, (void **)&c->psFn, (void **)&c->psFh, (void **)&c->psWork,
-                     (void **)&c->refq, (void **)&c->qcell, (void **)&c->qface, (void **)&c->chebw};
+                     (void **)&c->refq, (void **)&c->qcell, (void **)&c->qface, (void **)&c->chebw,
+                     (void **)&c->mg_cptr, (void **)&c->mg_clist, (void **)&c->mgw};
     for (void **b : bufs) dfree(b);
     c->work64_len = c->work32_len = 0;
     c->has_mesh = c->has_coef = c->has_press = c->has_q = false;
     c->cheb_deg = 0;
+    c->mg_coarse = nullptr;
+    c->mg_nc = 0;
 }
 
 }  // namespace hx
@@ -444,6 +447,13 @@ hx_status hx_apply_preconditioner(hx_ctx *c, hx_pc kind, hx_prec prec, const voi
         if (c->cheb_deg < 1) return fail(c, HX_ERR_STATE, "Chebyshev preconditioner not set");
         HX_HIP(c, cheb_apply64(c, (const double *)r, (double *)z));
         return HX_OK;
+    case HX_PC_MULTIGRID: {
+        if (prec != HX_F64) return fail(c, HX_ERR_ARG, "the multigrid preconditioner is FP64");
+        const hx_status s = mg_check(c);
+        if (s != HX_OK) return s;
+        HX_HIP(c, mg_vcycle64(c, (const double *)r, (double *)z));
+        return HX_OK;
+    }
     case HX_PC_MASS_BLOCK:
         if (prec == HX_F64) HX_HIP(c, launch_massinv64(c, (const double *)r, (double *)z));
         else HX_HIP(c, launch_massinv32(c, (const float *)r, (float *)z));

@@ -26,6 +26,8 @@ struct RefTab64 {
     double L0[MAXN * MAXN];                // 1-D reference stiffness
     double Cinv[MAXN * MAXN];              // inverse Cholesky factor of M (lower)
     double Binv[MAXN * MAXN];              // Binv[i*n+q]: inverse of B (n points = n nodes)
+    double Eh[2][MAXN * MAXN];             // Eh[o][i*n+j] = l_j((o + xl_i)/2): the basis at the
+                                           // nodes of the lower (o = 0) or upper half interval
 };
 
 void sym_eig(int n, double *a, double *w, double *v);
@@ -100,6 +102,13 @@ struct hx_ctx {
     hx::RefTabQ *refq = nullptr;  // device tables
     double *qcell = nullptr;      // [n_cells][7][nq^3]   m, Gxx, Gxy, Gxz, Gyy, Gyz, Gzz
     double *qface = nullptr;      // [n_cells][3][7][nq^2] g-(3), g+(3), s of the +d face
+    // geometric multigrid: the next coarser level (not owned), the children of
+    // each of its cells, and the level vectors
+    hx_ctx *mg_coarse = nullptr;
+    int64_t mg_nc = 0;            // cells of the coarser level when linked
+    int32_t *mg_cptr = nullptr;   // [mg_nc + 1] children of coarse cell j: mg_clist[cptr[j]..cptr[j+1])
+    int32_t *mg_clist = nullptr;  // [n_cells] child cell * 8 + octant, grouped by parent
+    double *mgw = nullptr;        // [4][n_dofs] b, x (as a coarse level), r, t
 
     // separable block-Jacobi data
     double *bjS64 = nullptr;      // [n_cells][3][n][n]  eigenvectors S_d
@@ -170,6 +179,14 @@ hipError_t launch_q_setup(hx_ctx *c, const double *alpha, const double *beta);
 hipError_t launch_apply_q(hx_ctx *c, const double *x, double *y);
 // z = p(M^-1 A) M^-1 r, the Chebyshev polynomial preconditioner (FP64)
 hipError_t cheb_apply64(hx_ctx *c, const double *r, double *z);
+// geometric multigrid: x = V b, one V-cycle from the level c down (FP64);
+// restriction of a fine dual vector to the next coarser level (overwrites
+// b_coarse) and prolongation of a coarse vector added to x_fine
+hipError_t mg_vcycle64(hx_ctx *c, const double *b, double *x);
+hipError_t mg_restrict64(hx_ctx *c, const double *r_fine, double *b_coarse);
+hipError_t mg_prolong_add64(hx_ctx *c, const double *x_coarse, double *x_fine);
+// HX_OK if the chain of levels below c is usable by the V-cycle
+hx_status mg_check(hx_ctx *c);
 // h = gamma p / ((gamma - 1) rho) at the nodes
 hipError_t launch_enthalpy(hx_ctx *c, const double *p, const double *rho, double gamma, double *h);
 hipError_t launch_massinv32(hx_ctx *c, const float *r, float *z);

@@ -1,0 +1,199 @@
+// Geometric multigrid for the SPD Helmholtz-type systems (section 3.1: CG
+// preconditioned by geometric multigrid, with Chebyshev smoothing from
+// Lanczos eigenvalue estimates).
+//
+// Levels are uniform refinements at one polynomial degree: every cell of a
+// finer level fills one octant o = ox + 2 oy + 4 oz of a parent cell of the
+// next coarser level, with the same axis orientation.  Prolongation writes
+// the parent polynomial in the child's basis, x_child = (E_oz (x) E_oy (x)
+// E_ox) x_parent with E_o[i][j] = l_j((o + xl_i)/2); restriction is its
+// transpose.  Both transfers run one workgroup per coarse cell over its
+// list of children, so the restriction sums without atomics; each child is
+// three 1-D sweeps through LDS.  The transfers are HBM bound (8 B per fine
+// dof read, plus 8 B written for the prolongation) and far cheaper than one
+// operator application.
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+
+namespace hx {
+namespace {
+
+constexpr int MG_T = 256;
+
+// children per pass through LDS: two buffers of CH * nd doubles, at most 32 KB
+template <int N>
+constexpr int mg_chunk() { return N * N * N > 125 ? 4 : 8; }
+
+template <int N, bool RESTRICT>
+__global__ __launch_bounds__(MG_T) void k_transfer(const double *__restrict__ in,
+                                                   double *__restrict__ out,
+                                                   const int32_t *__restrict__ cptr,
+                                                   const int32_t *__restrict__ clist,
+                                                   const RefTab64 *__restrict__ T, int64_t n_coarse)
+{
+    constexpr int ND = N * N * N, CH = mg_chunk<N>(), NACC = (ND + MG_T - 1) / MG_T;
+    __shared__ double sE[2][N * N];
+    __shared__ double sA[CH][ND];
+    __shared__ double sB[CH][ND];
+    __shared__ double sC[ND];
+    __shared__ int sChild[CH], sOct[CH];
+    const int t = threadIdx.x;
+    const int64_t cc = blockIdx.x;
+    if (cc >= n_coarse) return;
+    for (int e = t; e < 2 * N * N; e += MG_T) sE[e / (N * N)][e % (N * N)] = T->Eh[e / (N * N)][e % (N * N)];
+    if (!RESTRICT)
+        for (int e = t; e < ND; e += MG_T) sC[e] = in[cc * ND + e];
+    double acc[NACC];
+#pragma unroll
+    for (int a = 0; a < NACC; ++a) acc[a] = 0.0;
+    const int c0 = cptr[cc], c1 = cptr[cc + 1];
+    for (int base = c0; base < c1; base += CH) {
+        const int nch = min(CH, c1 - base);
+        __syncthreads();   // the previous pass is done with sA, sB, sChild
+        if (t < nch) {
+            const int v = clist[base + t];
+            sChild[t] = v >> 3;
+            sOct[t] = v & 7;
+        }
+        __syncthreads();
+        if (!RESTRICT) {
+            // x sweep of the parent values for each child
+            for (int idx = t; idx < nch * ND; idx += MG_T) {
+                const int ch = idx / ND, e = idx % ND;
+                const int i = e % N, bc = e / N;
+                const double *E = sE[sOct[ch] & 1] + i * N;
+                double s = 0.0;
+#pragma unroll
+                for (int a = 0; a < N; ++a) s += E[a] * sC[a + N * bc];
+                sA[ch][e] = s;
+            }
+            __syncthreads();
+            for (int idx = t; idx < nch * ND; idx += MG_T) {
+                const int ch = idx / ND, e = idx % ND;
+                const int i = e % N, j = (e / N) % N, c = e / (N * N);
+                const double *E = sE[(sOct[ch] >> 1) & 1] + j * N;
+                double s = 0.0;
+#pragma unroll
+                for (int b = 0; b < N; ++b) s += E[b] * sA[ch][i + N * (b + N * c)];
+                sB[ch][e] = s;
+            }
+            __syncthreads();
+            for (int idx = t; idx < nch * ND; idx += MG_T) {
+                const int ch = idx / ND, e = idx % ND;
+                const int ij = e % (N * N), l = e / (N * N);
+                const double *E = sE[(sOct[ch] >> 2) & 1] + l * N;
+                double s = 0.0;
+#pragma unroll
+                for (int c = 0; c < N; ++c) s += E[c] * sB[ch][ij + N * N * c];
+                out[(int64_t)sChild[ch] * ND + e] += s;
+            }
+        } else {
+            for (int idx = t; idx < nch * ND; idx += MG_T) {
+                const int ch = idx / ND, e = idx % ND;
+                sA[ch][e] = in[(int64_t)sChild[ch] * ND + e];
+            }
+            __syncthreads();
+            // transposed x sweep: (a, j, l) <- sum_i E[i][a] r(i, j, l)
+            for (int idx = t; idx < nch * ND; idx += MG_T) {
+                const int ch = idx / ND, e = idx % ND;
+                const int a = e % N, jl = e / N;
+                const double *E = sE[sOct[ch] & 1] + a;
+                double s = 0.0;
+#pragma unroll
+                for (int i = 0; i < N; ++i) s += E[i * N] * sA[ch][i + N * jl];
+                sB[ch][e] = s;
+            }
+            __syncthreads();
+            for (int idx = t; idx < nch * ND; idx += MG_T) {
+                const int ch = idx / ND, e = idx % ND;
+                const int a = e % N, b = (e / N) % N, l = e / (N * N);
+                const double *E = sE[(sOct[ch] >> 1) & 1] + b;
+                double s = 0.0;
+#pragma unroll
+                for (int j = 0; j < N; ++j) s += E[j * N] * sB[ch][a + N * (j + N * l)];
+                sA[ch][e] = s;
+            }
+            __syncthreads();
+            // z sweep, summed over the children into the thread's outputs
+#pragma unroll
+            for (int q = 0; q < NACC; ++q) {
+                const int e = t + q * MG_T;
+                if (e < ND) {
+                    const int ab = e % (N * N), c = e / (N * N);
+                    for (int ch = 0; ch < nch; ++ch) {
+                        const double *E = sE[(sOct[ch] >> 2) & 1] + c;
+                        double s = 0.0;
+#pragma unroll
+                        for (int l = 0; l < N; ++l) s += E[l * N] * sA[ch][ab + N * N * l];
+                        acc[q] += s;
+                    }
+                }
+            }
+        }
+    }
+    if (RESTRICT) {
+#pragma unroll
+        for (int q = 0; q < NACC; ++q) {
+            const int e = t + q * MG_T;
+            if (e < ND) out[cc * ND + e] = acc[q];
+        }
+    }
+}
+
+template <bool RESTRICT>
+hipError_t transfer(hx_ctx *c, const double *in, double *out)
+{
+    const int64_t nc = c->mg_nc;
+    if (nc == 0) return hipSuccess;
+    const dim3 g((unsigned)nc), b(MG_T);
+#define HX_MG_CASE(NN)                                                                           \
+    case NN:                                                                                     \
+        hipLaunchKernelGGL((k_transfer<NN, RESTRICT>), g, b, 0, c->stream, in, out, c->mg_cptr,  \
+                           c->mg_clist, c->ref, nc);                                             \
+        break;
+    switch (c->n) {
+        HX_MG_CASE(2) HX_MG_CASE(3) HX_MG_CASE(4) HX_MG_CASE(5) HX_MG_CASE(6) HX_MG_CASE(7)
+        HX_MG_CASE(8)
+    default: return hipErrorInvalidValue;
+    }
+#undef HX_MG_CASE
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t mg_restrict64(hx_ctx *c, const double *r_fine, double *b_coarse)
+{
+    return transfer<true>(c, r_fine, b_coarse);
+}
+
+hipError_t mg_prolong_add64(hx_ctx *c, const double *x_coarse, double *x_fine)
+{
+    return transfer<false>(c, x_coarse, x_fine);
+}
+
+// x = V b: Chebyshev smoothing from zero, the restricted residual solved by
+// the V-cycle of the next coarser level and its prolongation added, then the
+// same Chebyshev polynomial on the updated residual (which keeps V
+// symmetric); the coarsest level applies its own Chebyshev polynomial.  All
+// levels share one stream, so no synchronisation is needed between them.
+hipError_t mg_vcycle64(hx_ctx *c, const double *b, double *x)
+{
+    if (!c->mg_coarse) return cheb_apply64(c, b, x);
+    hx_ctx *C = c->mg_coarse;
+    const int64_t n = c->n_dofs;
+    double *r = c->mgw + 2 * n, *t = c->mgw + 3 * n;
+    double *bc = C->mgw, *xc = C->mgw + C->n_dofs;
+    hipError_t e = cheb_apply64(c, b, x);
+    if (e == hipSuccess) e = launch_apply64(c, x, r, b);      // r = b - A x
+    if (e == hipSuccess) e = mg_restrict64(c, r, bc);
+    if (e == hipSuccess) e = mg_vcycle64(C, bc, xc);
+    if (e == hipSuccess) e = mg_prolong_add64(c, xc, x);
+    if (e == hipSuccess) e = launch_apply64(c, x, r, b);
+    if (e == hipSuccess) e = cheb_apply64(c, r, t);
+    if (e == hipSuccess) e = blas_axpby(c, n, 1.0, t, 1.0, x);
+    return e;
+}
+
+}  // namespace hx

@@ -188,6 +188,13 @@ void build_ref_tables(int n, RefTab64 &t)
         lagrange_eval(n, xl, e ? 1.0 : 0.0, v, d);
         for (int i = 0; i < n; ++i) t.DL[e][i] = d[i];
     }
+    // the basis at the nodes of either half of the interval (the embedding of
+    // a parent cell's polynomial into its children)
+    for (int o = 0; o < 2; ++o)
+        for (int i = 0; i < n; ++i) {
+            lagrange_eval(n, xl, 0.5 * (o + xl[i]), v, d);
+            for (int j = 0; j < n; ++j) t.Eh[o][i * n + j] = v[j];
+        }
     // 1-D reference mass and stiffness with GL quadrature
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j) {

@@ -144,6 +144,7 @@ hx_status precondition(hx_ctx *c, int pc, int mixed, int inner_iters, const doub
     case HX_PC_MASS_DIAG: HX_HIP(c, launch_diag64(c, 1, v, z)); return HX_OK;
     case HX_PC_MASS_BLOCK: HX_HIP(c, launch_massinv64(c, v, z)); return HX_OK;
     case HX_PC_CHEBYSHEV: HX_HIP(c, cheb_apply64(c, v, z)); return HX_OK;
+    case HX_PC_MULTIGRID: HX_HIP(c, mg_vcycle64(c, v, z)); return HX_OK;
     default: return fail(c, HX_ERR_ARG, "unknown preconditioner %d", pc);
     }
 }
@@ -590,6 +591,23 @@ hipError_t cheb_apply64(hx_ctx *c, const double *r, double *z)
     return e;
 }
 
+hx_status mg_check(hx_ctx *c)
+{
+    int depth = 0;
+    for (hx_ctx *L = c; L; L = L->mg_coarse, ++depth) {
+        if (!L->has_coef) return fail(c, HX_ERR_STATE, "multigrid level %d has no coefficients", depth);
+        if (L->cheb_deg < 1)
+            return fail(c, HX_ERR_STATE, "multigrid level %d has no Chebyshev smoother", depth);
+        if (L->mg_coarse) {
+            const hx_ctx *C = L->mg_coarse;
+            if (!L->mgw || !C->mgw || C->n_cells != L->mg_nc || C->k != L->k || C->stream != L->stream)
+                return fail(c, HX_ERR_STATE,
+                            "multigrid level %d changed since hx_set_multigrid; link it again", depth + 1);
+        }
+    }
+    return HX_OK;
+}
+
 }  // namespace hx
 
 using namespace hx;
@@ -632,7 +650,7 @@ hx_status hx_solve(hx_ctx *c, const hx_solve_params *prm, const double *b, doubl
         return fail(c, HX_ERR_ARG, "restart must be in 1..63");
     if (prm->orth != 0 && prm->orth != 1) return fail(c, HX_ERR_ARG, "orth must be 0 or 1");
     if (!(prm->rtol > 0.0) || prm->max_iter < 1) return fail(c, HX_ERR_ARG, "bad rtol/max_iter");
-    if (prm->pc < HX_PC_NONE || prm->pc > HX_PC_CHEBYSHEV) return fail(c, HX_ERR_ARG, "bad pc");
+    if (prm->pc < HX_PC_NONE || prm->pc > HX_PC_MULTIGRID) return fail(c, HX_ERR_ARG, "bad pc");
     if (prm->method == 0 && (prm->pc == HX_PC_LEARNED || prm->mixed))
         return fail(c, HX_ERR_ARG, "CG needs a fixed SPD preconditioner; use FGMRES");
     if (prm->mixed && prm->inner_iters < 1) return fail(c, HX_ERR_ARG, "inner_iters must be >= 1");
@@ -643,6 +661,12 @@ hx_status hx_solve(hx_ctx *c, const hx_solve_params *prm, const double *b, doubl
         return fail(c, HX_ERR_STATE, "Chebyshev preconditioner not set");
     if (prm->pc == HX_PC_CHEBYSHEV && prm->mixed)
         return fail(c, HX_ERR_ARG, "the Chebyshev preconditioner is FP64; it cannot precondition the inner FP32 solve");
+    if (prm->pc == HX_PC_MULTIGRID && prm->mixed)
+        return fail(c, HX_ERR_ARG, "the multigrid preconditioner is FP64; it cannot precondition the inner FP32 solve");
+    if (prm->pc == HX_PC_MULTIGRID) {
+        const hx_status s = mg_check(c);
+        if (s != HX_OK) return s;
+    }
     if (prm->system != 0 && prm->system != 1) return fail(c, HX_ERR_ARG, "system must be 0 or 1");
     if (prm->system == 1 && !c->has_press) return fail(c, HX_ERR_STATE, "pressure system not set");
     if (prm->system == 1 && prm->method != 1)
@@ -752,6 +776,66 @@ hx_status hx_set_chebyshev(hx_ctx *c, int degree, double lo, double hi)
     c->cheb_deg = degree;
     c->cheb_lo = lo;
     c->cheb_hi = hi;
+    return HX_OK;
+}
+
+hx_status hx_set_multigrid(hx_ctx *c, hx_ctx *coarse, const int32_t *parent, const int32_t *octant)
+{
+    if (!c) return HX_ERR_ARG;
+    HX_HIP(c, hipSetDevice(c->device));
+    dfree((void **)&c->mg_cptr);
+    dfree((void **)&c->mg_clist);
+    c->mg_coarse = nullptr;
+    c->mg_nc = 0;
+    if (!coarse) return HX_OK;
+    if (!c->has_mesh || !coarse->has_mesh) return fail(c, HX_ERR_STATE, "set_multigrid before setup_mesh");
+    if (!parent || !octant) return fail(c, HX_ERR_ARG, "parent and octant are required");
+    if (coarse->device != c->device || coarse->stream != c->stream)
+        return fail(c, HX_ERR_ARG, "the levels must share the device and the stream");
+    if (coarse->k != c->k) return fail(c, HX_ERR_ARG, "the levels must have the same degree");
+    for (const hx_ctx *p = coarse; p; p = p->mg_coarse)
+        if (p == c) return fail(c, HX_ERR_ARG, "the levels would form a cycle");
+    const int64_t nf = c->n_cells, nc = coarse->n_cells;
+    if (nf >= (int64_t(1) << 28)) return fail(c, HX_ERR_ARG, "too many cells for the child list");
+    std::vector<int32_t> ptr(nc + 1, 0), list(nf);
+    std::vector<uint8_t> used(nc, 0);
+    for (int64_t f = 0; f < nf; ++f) {
+        const int32_t p = parent[f], o = octant[f];
+        if (p < 0 || p >= nc || o < 0 || o > 7)
+            return fail(c, HX_ERR_ARG, "cell %lld: parent %d or octant %d out of range", (long long)f, p, o);
+        if (used[p] >> o & 1)
+            return fail(c, HX_ERR_ARG, "cell %lld: octant %d of parent %d already taken", (long long)f, o, p);
+        used[p] |= (uint8_t)(1u << o);
+        ++ptr[p + 1];
+    }
+    for (int64_t j = 0; j < nc; ++j) ptr[j + 1] += ptr[j];
+    {
+        std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+        for (int64_t f = 0; f < nf; ++f) list[fill[parent[f]]++] = (int32_t)(f * 8 + octant[f]);
+    }
+    hx_status s = dalloc(c, (void **)&c->mg_cptr, sizeof(int32_t) * (nc + 1));
+    if (s == HX_OK) s = dalloc(c, (void **)&c->mg_clist, sizeof(int32_t) * nf);
+    for (hx_ctx *L : {c, coarse})
+        if (s == HX_OK && !L->mgw) s = dalloc(L, (void **)&L->mgw, sizeof(double) * 4 * L->n_dofs);
+    if (s != HX_OK) return s;
+    HX_HIP(c, hipMemcpy(c->mg_cptr, ptr.data(), sizeof(int32_t) * (nc + 1), hipMemcpyHostToDevice));
+    HX_HIP(c, hipMemcpy(c->mg_clist, list.data(), sizeof(int32_t) * nf, hipMemcpyHostToDevice));
+    c->mg_coarse = coarse;
+    c->mg_nc = nc;
+    return HX_OK;
+}
+
+hx_status hx_mg_transfer(hx_ctx *c, int dir, const double *in, double *out)
+{
+    if (!c) return HX_ERR_ARG;
+    if (!c->mg_coarse) return fail(c, HX_ERR_STATE, "no coarser level set");
+    if (dir != 0 && dir != 1) return fail(c, HX_ERR_ARG, "dir must be 0 (restrict) or 1 (prolong)");
+    if (!in || !out || in == out) return fail(c, HX_ERR_ARG, "bad vectors");
+    if (c->mg_coarse->n_cells != c->mg_nc || !c->mg_coarse->has_mesh)
+        return fail(c, HX_ERR_STATE, "the coarser level changed since hx_set_multigrid");
+    HX_HIP(c, hipSetDevice(c->device));
+    if (dir == 0) HX_HIP(c, mg_restrict64(c, in, out));
+    else HX_HIP(c, mg_prolong_add64(c, in, out));
     return HX_OK;
 }
 

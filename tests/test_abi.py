@@ -50,6 +50,8 @@ def test_host_only_calls():
     assert L.hx_apply_consistent(None, None, None) == hx.HX_ERR_ARG
     assert L.hx_set_chebyshev(None, 4, 0.1, 1.0) == hx.HX_ERR_ARG
     assert L.hx_estimate_eigenvalues(None, None, 10, None, None) == hx.HX_ERR_ARG
+    assert L.hx_set_multigrid(None, None, None, None) == hx.HX_ERR_ARG
+    assert L.hx_mg_transfer(None, 0, None, None) == hx.HX_ERR_ARG
     assert L.hx_destroy(None) == hx.HX_OK
     assert L.hx_num_dofs(None) == -1
     out = C.c_void_p()
