@@ -140,6 +140,61 @@ def solve_suite(hx, ctx, b, torch, forms, label):
     return out
 
 
+def multigrid_suite(hx, ctx, b, torch, dev, dims, k, fine_bounds, levels=5, smooth_degree=2,
+                    smooth_ratio=15.0, coarse_degree=12):
+    """CG with one geometric-multigrid V-cycle per iteration: the terrain
+    channel coarsened by two in every direction down to `levels` levels, each
+    level's operator re-discretised with the coefficients at its own dofs,
+    Chebyshev smoothing of degree 2 on [1.1 hi / 15, 1.1 hi] of each level's
+    Lanczos range (20 steps on a random vector) and a degree-12 polynomial
+    over the whole range on the coarsest level.  The set-up of the coarse
+    levels and their estimates is timed apart from the solve."""
+    import synth_inputs as si
+    nx, ny, nz = dims
+    torch.cuda.synchronize()
+    t0 = time.time()
+    ctxs, maps = [ctx], []
+    for l in range(1, levels):
+        s = 2 ** l
+        if nx % s or ny % s or nz % s:
+            break
+        m = si.terrain_mesh(nx // s, ny // s, nz // s, g=4)
+        c, xyz, _ = setup(hx.HelmDG, m, k, torch, dev)
+        del xyz
+        ctxs.append(c)
+        maps.append(si.refinement_parents(nx // s, ny // s, nz // s))
+    gen = torch.Generator(device=dev)
+    bounds = [fine_bounds]
+    for l, c in enumerate(ctxs[1:], start=1):
+        gen.manual_seed(10 + l)
+        rv = torch.randn(c.n_dofs, dtype=torch.float64, device=dev, generator=gen)
+        bounds.append(c.estimate_eigenvalues(rv, 20))
+        del rv
+    for l, c in enumerate(ctxs):
+        lo, hi = bounds[l]
+        if l + 1 < len(ctxs):
+            c.set_chebyshev(smooth_degree, 1.1 * hi / smooth_ratio, 1.1 * hi)
+            c.set_multigrid(ctxs[l + 1], *maps[l])
+        else:
+            c.set_chebyshev(coarse_degree, 0.9 * lo, 1.1 * hi)
+    torch.cuda.synchronize()
+    t_setup = time.time() - t0
+    out = solve_suite(hx, ctx, b, torch, [
+        ("fp64_cg_multigrid", hx.default_params(method=0, rtol=1e-8, pc=hx.HX_PC_MULTIGRID)),
+        ("fp64_cg_multigrid_fp32_cycle", hx.default_params(method=0, rtol=1e-8,
+                                                           pc=hx.HX_PC_MULTIGRID_MIXED))], "C3")
+    for name in out:
+        out[name].update(
+            levels=[f"{nx // 2 ** l}x{ny // 2 ** l}x{nz // 2 ** l}" for l in range(len(ctxs))],
+            smoother=f"chebyshev{smooth_degree} [hi/{smooth_ratio:g}, 1.1 hi]",
+            coarse=f"chebyshev{coarse_degree} [0.9 lo, 1.1 hi]",
+            coarse_levels_setup_s=round(t_setup, 2))
+    ctx.set_multigrid(None)
+    for c in ctxs[1:]:
+        c.close()
+    return out
+
+
 def time_call(fn, reps, torch):
     fn()
     torch.cuda.synchronize()
@@ -286,8 +341,9 @@ def main():
     ap.add_argument("--ny", type=int, default=64)
     ap.add_argument("--nz", type=int, default=64)
     ap.add_argument("--no-solve", action="store_true")
-    ap.add_argument("--solves", choices=["all", "large"], default="all",
-                    help="'large': only the solves on the timed mesh (for profiling)")
+    ap.add_argument("--solves", choices=["all", "large", "multigrid"], default="all",
+                    help="'large': only the solves on the timed mesh; 'multigrid': only CG "
+                         "with the multigrid V-cycle on it (both for profiling)")
     ap.add_argument("--degree", type=int, default=4,
                     help="polynomial degree (default 4, the benchmark's)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -356,8 +412,8 @@ def main():
                                                          pc=hx.HX_PC_HELMHOLTZ_DIAG)),
         ]
         del y
-        solve[f"terrain{args.nx}x{args.ny}x{args.nz}"] = solve_suite(hx, ctx, b, torch,
-                                                                     forms + cg_forms, "C3")
+        solve[f"terrain{args.nx}x{args.ny}x{args.nz}"] = solve_suite(
+            hx, ctx, b, torch, [] if args.solves == "multigrid" else forms + cg_forms, "C3")
         # CG with the Chebyshev polynomial (degree 4) around block Jacobi, its
         # interval from 20 Lanczos steps on a random vector (timed apart)
         gen = torch.Generator(device=dev)
@@ -369,20 +425,24 @@ def main():
         torch.cuda.synchronize()
         t_est = (time.time() - t0) * 1e3
         del rv
-        ctx.set_chebyshev(4, lo, 1.1 * hi)
-        cheb = solve_suite(hx, ctx, b, torch, [
-            ("fp64_cg_chebyshev4_bj", hx.default_params(method=0, rtol=1e-8,
-                                                        pc=hx.HX_PC_CHEBYSHEV))], "C3")
-        cheb["fp64_cg_chebyshev4_bj"].update(lanczos_ms=round(t_est, 1), lanczos_lo=lo,
-                                             lanczos_hi=hi)
-        solve[f"terrain{args.nx}x{args.ny}x{args.nz}"].update(cheb)
-        consistent = consistent_suite(ctx, torch, k)
-        # the pressure system of the stage on the same mesh: FGMRES with the
-        # block Jacobi of the Helmholtz-type operator
-        pressure[f"terrain{args.nx}x{args.ny}x{args.nz}"] = pressure_suite(
-            hx, ctx, torch, "C3",
-            [("fgmres_bj", hx.default_params(method=1, system=1, restart=30, rtol=1e-8,
-                                             max_iter=5000, pc=hx.HX_PC_BLOCK_JACOBI))])
+        if args.solves != "multigrid":
+            ctx.set_chebyshev(4, lo, 1.1 * hi)
+            cheb = solve_suite(hx, ctx, b, torch, [
+                ("fp64_cg_chebyshev4_bj", hx.default_params(method=0, rtol=1e-8,
+                                                            pc=hx.HX_PC_CHEBYSHEV))], "C3")
+            cheb["fp64_cg_chebyshev4_bj"].update(lanczos_ms=round(t_est, 1), lanczos_lo=lo,
+                                                 lanczos_hi=hi)
+            solve[f"terrain{args.nx}x{args.ny}x{args.nz}"].update(cheb)
+        solve[f"terrain{args.nx}x{args.ny}x{args.nz}"].update(
+            multigrid_suite(hx, ctx, b, torch, dev, (args.nx, args.ny, args.nz), k, (lo, hi)))
+        if args.solves != "multigrid":
+            consistent = consistent_suite(ctx, torch, k)
+            # the pressure system of the stage on the same mesh: FGMRES with
+            # the block Jacobi of the Helmholtz-type operator
+            pressure[f"terrain{args.nx}x{args.ny}x{args.nz}"] = pressure_suite(
+                hx, ctx, torch, "C3",
+                [("fgmres_bj", hx.default_params(method=1, system=1, restart=30, rtol=1e-8,
+                                                 max_iter=5000, pc=hx.HX_PC_BLOCK_JACOBI))])
         ctx.close()
     if not args.no_solve and args.solves == "all":
         del b, x

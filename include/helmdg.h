@@ -73,7 +73,8 @@ typedef enum {
     HX_PC_MASS_DIAG = 4,      /* inverse diagonal of the mass term alone */
     HX_PC_MASS_BLOCK = 5,     /* exact inverse of the alpha-weighted cell mass blocks */
     HX_PC_CHEBYSHEV = 6,      /* Chebyshev polynomial in M^-1 A, M = block Jacobi (FP64) */
-    HX_PC_MULTIGRID = 7       /* one geometric multigrid V-cycle (FP64, hx_set_multigrid) */
+    HX_PC_MULTIGRID = 7,      /* one geometric multigrid V-cycle (FP64, hx_set_multigrid) */
+    HX_PC_MULTIGRID_MIXED = 8 /* the same V-cycle in FP32 for FP64 residuals */
 } hx_pc;
 
 /* Create a context on `device` (HIP ordinal) whose kernels run on
@@ -257,11 +258,17 @@ hx_status hx_estimate_eigenvalues(hx_ctx *c, const double *b, int iters, double 
  * V-cycle: the level's Chebyshev polynomial from zero, the restricted
  * residual handed to the next level's V-cycle and its prolongation added,
  * and the same polynomial on the updated residual; it is a fixed symmetric
- * operator, so CG may use it.  coarse = NULL removes the link.  c does not
+ * operator, so CG may use it.  HX_PC_MULTIGRID_MIXED runs the same cycle in
+ * FP32 throughout (FP32 operator, smoother, transfers and level vectors) on
+ * the FP64 residual rounded to FP32 and returns it widened to FP64: about
+ * half the bytes per cycle, at the price of a preconditioner that is linear
+ * and symmetric only up to FP32 rounding (CG tolerates that in practice,
+ * FGMRES by construction).  coarse = NULL removes the link.  c does not
  * own `coarse`: keep it alive while linked; set up its mesh again and the
  * link must be set again.  Errors: HX_ERR_ARG for bad maps, a degree,
  * device or stream mismatch or a cycle of links; HX_ERR_STATE before
- * hx_setup_mesh.  Working memory: 4 n_dofs doubles on each linked level.
+ * hx_setup_mesh.  Working memory: 3 n_dofs doubles and 3 n_dofs floats on
+ * each linked level (and 2 of each per level for its Chebyshev polynomial).
  *
  * hx_mg_transfer applies one transfer of the link (DEVICE FP64 vectors):
  * dir 0 restricts `in` ([n_dofs of c]) into `out` ([n_dofs of the coarse

@@ -22,7 +22,7 @@ HX_OK, HX_ERR_ARG, HX_ERR_STATE, HX_ERR_DEVICE, HX_ERR_OOM, HX_ERR_MESH, \
     HX_ERR_NOCONV, HX_FALLBACK_USED = range(8)
 HX_F64, HX_F32 = 0, 1
 (HX_PC_NONE, HX_PC_BLOCK_JACOBI, HX_PC_LEARNED, HX_PC_HELMHOLTZ_DIAG, HX_PC_MASS_DIAG,
- HX_PC_MASS_BLOCK, HX_PC_CHEBYSHEV, HX_PC_MULTIGRID) = range(8)
+ HX_PC_MASS_BLOCK, HX_PC_CHEBYSHEV, HX_PC_MULTIGRID, HX_PC_MULTIGRID_MIXED) = range(9)
 HX_EXPORT_CELL_DATA, HX_EXPORT_FACE_DATA, HX_EXPORT_SIGMA, HX_EXPORT_VOLUME, \
     HX_EXPORT_BJ_SCALARS, HX_EXPORT_INV_DIAG = range(6)
 HX_PS_GRAD, HX_PS_DIV, HX_PS_VMASS_INV, HX_PS_DMASS, HX_PS_SYSTEM = range(5)

@@ -51,7 +51,8 @@ static void free_mesh(hx_ctx *c)
                      (void **)&c->work32, (void **)&c->psW, (void **)&c->psWC, (void **)&c->psMr,
                      (void **)&c->psMd, (void **)&c->psFn, (void **)&c->psFh, (void **)&c->psWork,
                      (void **)&c->refq, (void **)&c->qcell, (void **)&c->qface, (void **)&c->chebw,
-                     (void **)&c->mg_cptr, (void **)&c->mg_clist, (void **)&c->mgw};
+                     (void **)&c->mg_cptr, (void **)&c->mg_clist, (void **)&c->mgw,
+                     (void **)&c->mgw32, (void **)&c->chebw32};
     for (void **b : bufs) dfree(b);
     c->work64_len = c->work32_len = 0;
     c->has_mesh = c->has_coef = c->has_press = c->has_q = false;
@@ -447,11 +448,14 @@ hx_status hx_apply_preconditioner(hx_ctx *c, hx_pc kind, hx_prec prec, const voi
         if (c->cheb_deg < 1) return fail(c, HX_ERR_STATE, "Chebyshev preconditioner not set");
         HX_HIP(c, cheb_apply64(c, (const double *)r, (double *)z));
         return HX_OK;
-    case HX_PC_MULTIGRID: {
-        if (prec != HX_F64) return fail(c, HX_ERR_ARG, "the multigrid preconditioner is FP64");
+    case HX_PC_MULTIGRID:
+    case HX_PC_MULTIGRID_MIXED: {
+        if (prec != HX_F64)
+            return fail(c, HX_ERR_ARG, "the multigrid preconditioner takes FP64 vectors");
         const hx_status s = mg_check(c);
         if (s != HX_OK) return s;
-        HX_HIP(c, mg_vcycle64(c, (const double *)r, (double *)z));
+        if (kind == HX_PC_MULTIGRID) HX_HIP(c, mg_vcycle64(c, (const double *)r, (double *)z));
+        else HX_HIP(c, mg_vcycle_mixed(c, (const double *)r, (double *)z));
         return HX_OK;
     }
     case HX_PC_MASS_BLOCK:

@@ -58,12 +58,19 @@ __device__ __forceinline__ void block_sum2(double &u, double &v, double *sh)
 // when p.q is exactly 0: a step in flight after exact convergence):
 //   x += a p,  r -= a q,  z = M^{-1} r,
 // and per-block partial sums of r.z and r.r written to part[blk] and
-// part[ld + blk].  Without FUSE, plain z = M^{-1} r.
-template <int N, typename T, bool FUSE>
+// part[ld + blk].  CHEB: one step of the Chebyshev iteration around the
+// preconditioner, z holding the step direction d and x the iterate:
+//   d = ca M^{-1} r + cb d  (cb read only with CHEB_READ_D),
+//   x = x + d  (CHEB_ACCUM)  or  x = d.
+// Otherwise plain z = M^{-1} r.
+constexpr int CHEB_READ_D = 1, CHEB_ACCUM = 2;
+
+template <int N, typename T, bool FUSE, bool CHEB = false>
 __global__ void __launch_bounds__(Cfg<N>::NT)
 k_bj(const T *__restrict__ rin, T *__restrict__ z, const T *__restrict__ S, const T *__restrict__ L,
      const T *__restrict__ C, int n_cells, int nwg, T *x, T *rw, const T *__restrict__ p,
-     const T *__restrict__ q, const double *__restrict__ sc, double *part, int ld)
+     const T *__restrict__ q, const double *__restrict__ sc, double *part, int ld, T ca = 0,
+     T cb = 0, int flags = 0)
 {
     const T *r = FUSE ? rw : rin;
     constexpr int NF = Cfg<N>::NF, ND = Cfg<N>::ND, CPB = Cfg<N>::CPB;
@@ -207,8 +214,19 @@ k_bj(const T *__restrict__ rin, T *__restrict__ z, const T *__restrict__ S, cons
         for (int i = 0; i < N; ++i) sR[lc][i + N * a + NF * b] = w[i];
     }
     __syncthreads();
-    if (active)
-        for (int e = tt; e < ND; e += NF) z[cid * ND + e] = sR[lc][e];
+    if (active) {
+        if (CHEB) {
+            for (int e = tt; e < ND; e += NF) {
+                const int64_t gi = cid * ND + e;
+                T dn = ca * sR[lc][e];
+                if (flags & CHEB_READ_D) dn += cb * z[gi];
+                z[gi] = dn;
+                x[gi] = (flags & CHEB_ACCUM) ? x[gi] + dn : dn;
+            }
+        } else {
+            for (int e = tt; e < ND; e += NF) z[cid * ND + e] = sR[lc][e];
+        }
+    }
     if (FUSE) {
         __shared__ double sh2[2 * (Cfg<N>::NT / 64)];
         block_sum2<Cfg<N>::NT>(acc_rz, acc_rr, sh2);
@@ -226,6 +244,39 @@ struct CgArgs {
     const T *p = nullptr, *q = nullptr;
     const double *sc = nullptr;
 };
+
+template <int N, typename T>
+hipError_t bj_cheb_n(hx_ctx *c, const T *r, T *d, T *x, double ca, double cb, int flags)
+{
+    const int cpb = Cfg<N>::CPB;
+    const int nwg = (int)((c->n_cells + cpb - 1) / cpb);
+    const bool dbl = std::is_same<T, double>::value;
+    const T *S = dbl ? (const T *)c->bjS64 : (const T *)c->bjS32;
+    const T *L = dbl ? (const T *)c->bjL64 : (const T *)c->bjL32;
+    const T *C = dbl ? (const T *)c->bjC64 : (const T *)c->bjC32;
+    hipLaunchKernelGGL((k_bj<N, T, false, true>), dim3(nwg), dim3(Cfg<N>::NT), 0, c->stream, r, d,
+                       S, L, C, (int)c->n_cells, nwg, x, (T *)nullptr, (const T *)nullptr,
+                       (const T *)nullptr, (const double *)nullptr, (double *)nullptr, 0, (T)ca,
+                       (T)cb, flags);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t bj_cheb_dispatch(hx_ctx *c, const T *r, T *d, T *x, double ca, double cb, int read_d,
+                            int accum)
+{
+    const int flags = (read_d ? CHEB_READ_D : 0) | (accum ? CHEB_ACCUM : 0);
+    switch (c->n) {
+    case 2: return bj_cheb_n<2, T>(c, r, d, x, ca, cb, flags);
+    case 3: return bj_cheb_n<3, T>(c, r, d, x, ca, cb, flags);
+    case 4: return bj_cheb_n<4, T>(c, r, d, x, ca, cb, flags);
+    case 5: return bj_cheb_n<5, T>(c, r, d, x, ca, cb, flags);
+    case 6: return bj_cheb_n<6, T>(c, r, d, x, ca, cb, flags);
+    case 7: return bj_cheb_n<7, T>(c, r, d, x, ca, cb, flags);
+    case 8: return bj_cheb_n<8, T>(c, r, d, x, ca, cb, flags);
+    default: return hipErrorInvalidValue;
+    }
+}
 
 template <int N, typename T>
 hipError_t bj_n(hx_ctx *c, const T *r, T *z, const CgArgs<T> *cg, int *nblk)
@@ -268,6 +319,18 @@ hipError_t bj_dispatch(hx_ctx *c, const T *r, T *z, const CgArgs<T> *cg = nullpt
 }  // namespace
 
 hipError_t launch_bj64(hx_ctx *c, const double *r, double *z) { return bj_dispatch<double>(c, r, z); }
+
+hipError_t launch_bj_cheb64(hx_ctx *c, const double *r, double *d, double *x, double ca, double cb,
+                            int read_d, int accum)
+{
+    return bj_cheb_dispatch<double>(c, r, d, x, ca, cb, read_d, accum);
+}
+
+hipError_t launch_bj_cheb32(hx_ctx *c, const float *r, float *d, float *x, double ca, double cb,
+                            int read_d, int accum)
+{
+    return bj_cheb_dispatch<float>(c, r, d, x, ca, cb, read_d, accum);
+}
 hipError_t launch_bj32(hx_ctx *c, const float *r, float *z) { return bj_dispatch<float>(c, r, z); }
 
 hipError_t launch_cg_bj64(hx_ctx *c, double *x, double *r, const double *p, const double *q,

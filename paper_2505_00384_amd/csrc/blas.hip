@@ -550,9 +550,11 @@ hipError_t cg_step_pc(hx_ctx *c, int pc, T *x, T *r, const T *p, const T *q, T *
     if constexpr (sizeof(T) == 8) {
         // the polynomial and multigrid preconditioners: z = r above, now
         // z = p(M^-1 A) M^-1 r or one V-cycle, and sc[2] = r.z
-        if (e == hipSuccess && (pc == HX_PC_CHEBYSHEV || pc == HX_PC_MULTIGRID)) {
-            e = pc == HX_PC_CHEBYSHEV ? cheb_apply64(c, (const double *)r, (double *)z)
-                                      : mg_vcycle64(c, (const double *)r, (double *)z);
+        if (e == hipSuccess &&
+            (pc == HX_PC_CHEBYSHEV || pc == HX_PC_MULTIGRID || pc == HX_PC_MULTIGRID_MIXED)) {
+            e = pc == HX_PC_CHEBYSHEV   ? cheb_apply64(c, (const double *)r, (double *)z)
+                : pc == HX_PC_MULTIGRID ? mg_vcycle64(c, (const double *)r, (double *)z)
+                                        : mg_vcycle_mixed(c, (const double *)r, (double *)z);
             if (e == hipSuccess) e = blas_dot(c, n, (const double *)r, (const double *)z, sc + 2);
         }
     }

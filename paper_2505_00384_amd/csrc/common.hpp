@@ -95,7 +95,8 @@ struct hx_ctx {
     // Chebyshev preconditioner: degree and interval of M^-1 A (M = block Jacobi)
     int cheb_deg = 0;
     double cheb_lo = 0.0, cheb_hi = 0.0;
-    double *chebw = nullptr;      // [3][n_dofs]
+    double *chebw = nullptr;      // [2][n_dofs] residual and step direction
+    float *chebw32 = nullptr;     // [2][n_dofs] the same in FP32
     // consistent integration: the operator with nq = 2k+1 Gauss points
     bool has_q = false;
     int nq = 0;
@@ -108,7 +109,8 @@ struct hx_ctx {
     int64_t mg_nc = 0;            // cells of the coarser level when linked
     int32_t *mg_cptr = nullptr;   // [mg_nc + 1] children of coarse cell j: mg_clist[cptr[j]..cptr[j+1])
     int32_t *mg_clist = nullptr;  // [n_cells] child cell * 8 + octant, grouped by parent
-    double *mgw = nullptr;        // [4][n_dofs] b, x (as a coarse level), r, t
+    double *mgw = nullptr;        // [3][n_dofs] b, x (as a coarse level), r
+    float *mgw32 = nullptr;       // [3][n_dofs] the same in FP32 (the mixed-precision V-cycle)
 
     // separable block-Jacobi data
     double *bjS64 = nullptr;      // [n_cells][3][n][n]  eigenvectors S_d
@@ -177,14 +179,27 @@ hipError_t press_apply64(hx_ctx *c, const double *x, double *y, const double *b)
 // y = A_q x
 hipError_t launch_q_setup(hx_ctx *c, const double *alpha, const double *beta);
 hipError_t launch_apply_q(hx_ctx *c, const double *x, double *y);
+// one Chebyshev step around block Jacobi (FP64): d = ca M^-1 r + cb d
+// (cb used if read_d), then x += d (accum) or x = d
+hipError_t launch_bj_cheb64(hx_ctx *c, const double *r, double *d, double *x, double ca, double cb,
+                            int read_d, int accum);
+hipError_t launch_bj_cheb32(hx_ctx *c, const float *r, float *d, float *x, double ca, double cb,
+                            int read_d, int accum);
 // z = p(M^-1 A) M^-1 r, the Chebyshev polynomial preconditioner (FP64)
 hipError_t cheb_apply64(hx_ctx *c, const double *r, double *z);
+// the same Chebyshev iteration for A x = b from the given x (x_zero: from
+// zero, x is then only written): x <- x + p(M^-1 A) M^-1 (b - A x)
+hipError_t cheb_iterate64(hx_ctx *c, const double *b, double *x, bool x_zero);
+hipError_t cheb_iterate32(hx_ctx *c, const float *b, float *x, bool x_zero);
 // geometric multigrid: x = V b, one V-cycle from the level c down (FP64);
 // restriction of a fine dual vector to the next coarser level (overwrites
 // b_coarse) and prolongation of a coarse vector added to x_fine
 hipError_t mg_vcycle64(hx_ctx *c, const double *b, double *x);
 hipError_t mg_restrict64(hx_ctx *c, const double *r_fine, double *b_coarse);
 hipError_t mg_prolong_add64(hx_ctx *c, const double *x_coarse, double *x_fine);
+// the same V-cycle in FP32 throughout (FP32 operator, smoother, transfers and
+// level vectors) for an FP64 residual r: z = (double) V32 (float) r
+hipError_t mg_vcycle_mixed(hx_ctx *c, const double *r, double *z);
 // HX_OK if the chain of levels below c is usable by the V-cycle
 hx_status mg_check(hx_ctx *c);
 // h = gamma p / ((gamma - 1) rho) at the nodes

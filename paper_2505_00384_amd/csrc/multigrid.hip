@@ -25,28 +25,28 @@ constexpr int MG_T = 256;
 template <int N>
 constexpr int mg_chunk() { return N * N * N > 125 ? 4 : 8; }
 
-template <int N, bool RESTRICT>
-__global__ __launch_bounds__(MG_T) void k_transfer(const double *__restrict__ in,
-                                                   double *__restrict__ out,
+template <int N, bool RESTRICT, typename T>
+__global__ __launch_bounds__(MG_T) void k_transfer(const T *__restrict__ in,
+                                                   T *__restrict__ out,
                                                    const int32_t *__restrict__ cptr,
                                                    const int32_t *__restrict__ clist,
-                                                   const RefTab64 *__restrict__ T, int64_t n_coarse)
+                                                   const RefTab64 *__restrict__ tab, int64_t n_coarse)
 {
     constexpr int ND = N * N * N, CH = mg_chunk<N>(), NACC = (ND + MG_T - 1) / MG_T;
-    __shared__ double sE[2][N * N];
-    __shared__ double sA[CH][ND];
-    __shared__ double sB[CH][ND];
-    __shared__ double sC[ND];
+    __shared__ T sE[2][N * N];
+    __shared__ T sA[CH][ND];
+    __shared__ T sB[CH][ND];
+    __shared__ T sC[ND];
     __shared__ int sChild[CH], sOct[CH];
     const int t = threadIdx.x;
     const int64_t cc = blockIdx.x;
     if (cc >= n_coarse) return;
-    for (int e = t; e < 2 * N * N; e += MG_T) sE[e / (N * N)][e % (N * N)] = T->Eh[e / (N * N)][e % (N * N)];
+    for (int e = t; e < 2 * N * N; e += MG_T) sE[e / (N * N)][e % (N * N)] = (T)tab->Eh[e / (N * N)][e % (N * N)];
     if (!RESTRICT)
         for (int e = t; e < ND; e += MG_T) sC[e] = in[cc * ND + e];
-    double acc[NACC];
+    T acc[NACC];
 #pragma unroll
-    for (int a = 0; a < NACC; ++a) acc[a] = 0.0;
+    for (int a = 0; a < NACC; ++a) acc[a] = 0;
     const int c0 = cptr[cc], c1 = cptr[cc + 1];
     for (int base = c0; base < c1; base += CH) {
         const int nch = min(CH, c1 - base);
@@ -62,8 +62,8 @@ __global__ __launch_bounds__(MG_T) void k_transfer(const double *__restrict__ in
             for (int idx = t; idx < nch * ND; idx += MG_T) {
                 const int ch = idx / ND, e = idx % ND;
                 const int i = e % N, bc = e / N;
-                const double *E = sE[sOct[ch] & 1] + i * N;
-                double s = 0.0;
+                const T *E = sE[sOct[ch] & 1] + i * N;
+                T s = 0;
 #pragma unroll
                 for (int a = 0; a < N; ++a) s += E[a] * sC[a + N * bc];
                 sA[ch][e] = s;
@@ -72,8 +72,8 @@ __global__ __launch_bounds__(MG_T) void k_transfer(const double *__restrict__ in
             for (int idx = t; idx < nch * ND; idx += MG_T) {
                 const int ch = idx / ND, e = idx % ND;
                 const int i = e % N, j = (e / N) % N, c = e / (N * N);
-                const double *E = sE[(sOct[ch] >> 1) & 1] + j * N;
-                double s = 0.0;
+                const T *E = sE[(sOct[ch] >> 1) & 1] + j * N;
+                T s = 0;
 #pragma unroll
                 for (int b = 0; b < N; ++b) s += E[b] * sA[ch][i + N * (b + N * c)];
                 sB[ch][e] = s;
@@ -82,8 +82,8 @@ __global__ __launch_bounds__(MG_T) void k_transfer(const double *__restrict__ in
             for (int idx = t; idx < nch * ND; idx += MG_T) {
                 const int ch = idx / ND, e = idx % ND;
                 const int ij = e % (N * N), l = e / (N * N);
-                const double *E = sE[(sOct[ch] >> 2) & 1] + l * N;
-                double s = 0.0;
+                const T *E = sE[(sOct[ch] >> 2) & 1] + l * N;
+                T s = 0;
 #pragma unroll
                 for (int c = 0; c < N; ++c) s += E[c] * sB[ch][ij + N * N * c];
                 out[(int64_t)sChild[ch] * ND + e] += s;
@@ -98,8 +98,8 @@ __global__ __launch_bounds__(MG_T) void k_transfer(const double *__restrict__ in
             for (int idx = t; idx < nch * ND; idx += MG_T) {
                 const int ch = idx / ND, e = idx % ND;
                 const int a = e % N, jl = e / N;
-                const double *E = sE[sOct[ch] & 1] + a;
-                double s = 0.0;
+                const T *E = sE[sOct[ch] & 1] + a;
+                T s = 0;
 #pragma unroll
                 for (int i = 0; i < N; ++i) s += E[i * N] * sA[ch][i + N * jl];
                 sB[ch][e] = s;
@@ -108,8 +108,8 @@ __global__ __launch_bounds__(MG_T) void k_transfer(const double *__restrict__ in
             for (int idx = t; idx < nch * ND; idx += MG_T) {
                 const int ch = idx / ND, e = idx % ND;
                 const int a = e % N, b = (e / N) % N, l = e / (N * N);
-                const double *E = sE[(sOct[ch] >> 1) & 1] + b;
-                double s = 0.0;
+                const T *E = sE[(sOct[ch] >> 1) & 1] + b;
+                T s = 0;
 #pragma unroll
                 for (int j = 0; j < N; ++j) s += E[j * N] * sB[ch][a + N * (j + N * l)];
                 sA[ch][e] = s;
@@ -122,8 +122,8 @@ __global__ __launch_bounds__(MG_T) void k_transfer(const double *__restrict__ in
                 if (e < ND) {
                     const int ab = e % (N * N), c = e / (N * N);
                     for (int ch = 0; ch < nch; ++ch) {
-                        const double *E = sE[(sOct[ch] >> 2) & 1] + c;
-                        double s = 0.0;
+                        const T *E = sE[(sOct[ch] >> 2) & 1] + c;
+                        T s = 0;
 #pragma unroll
                         for (int l = 0; l < N; ++l) s += E[l * N] * sA[ch][ab + N * N * l];
                         acc[q] += s;
@@ -141,15 +141,15 @@ __global__ __launch_bounds__(MG_T) void k_transfer(const double *__restrict__ in
     }
 }
 
-template <bool RESTRICT>
-hipError_t transfer(hx_ctx *c, const double *in, double *out)
+template <bool RESTRICT, typename T>
+hipError_t transfer(hx_ctx *c, const T *in, T *out)
 {
     const int64_t nc = c->mg_nc;
     if (nc == 0) return hipSuccess;
     const dim3 g((unsigned)nc), b(MG_T);
 #define HX_MG_CASE(NN)                                                                           \
     case NN:                                                                                     \
-        hipLaunchKernelGGL((k_transfer<NN, RESTRICT>), g, b, 0, c->stream, in, out, c->mg_cptr,  \
+        hipLaunchKernelGGL((k_transfer<NN, RESTRICT, T>), g, b, 0, c->stream, in, out, c->mg_cptr, \
                            c->mg_clist, c->ref, nc);                                             \
         break;
     switch (c->n) {
@@ -165,34 +165,66 @@ hipError_t transfer(hx_ctx *c, const double *in, double *out)
 
 hipError_t mg_restrict64(hx_ctx *c, const double *r_fine, double *b_coarse)
 {
-    return transfer<true>(c, r_fine, b_coarse);
+    return transfer<true, double>(c, r_fine, b_coarse);
 }
 
 hipError_t mg_prolong_add64(hx_ctx *c, const double *x_coarse, double *x_fine)
 {
-    return transfer<false>(c, x_coarse, x_fine);
+    return transfer<false, double>(c, x_coarse, x_fine);
 }
 
 // x = V b: Chebyshev smoothing from zero, the restricted residual solved by
 // the V-cycle of the next coarser level and its prolongation added, then the
-// same Chebyshev polynomial on the updated residual (which keeps V
-// symmetric); the coarsest level applies its own Chebyshev polynomial.  All
-// levels share one stream, so no synchronisation is needed between them.
+// same Chebyshev iteration continued from the corrected x (which applies the
+// same polynomial to the updated residual and keeps V symmetric); the
+// coarsest level applies its own Chebyshev polynomial.  All levels share one
+// stream, so no synchronisation is needed between them.
 hipError_t mg_vcycle64(hx_ctx *c, const double *b, double *x)
 {
-    if (!c->mg_coarse) return cheb_apply64(c, b, x);
+    if (!c->mg_coarse) return cheb_iterate64(c, b, x, true);
     hx_ctx *C = c->mg_coarse;
     const int64_t n = c->n_dofs;
-    double *r = c->mgw + 2 * n, *t = c->mgw + 3 * n;
+    double *r = c->mgw + 2 * n;
     double *bc = C->mgw, *xc = C->mgw + C->n_dofs;
-    hipError_t e = cheb_apply64(c, b, x);
+    hipError_t e = cheb_iterate64(c, b, x, true);
     if (e == hipSuccess) e = launch_apply64(c, x, r, b);      // r = b - A x
-    if (e == hipSuccess) e = mg_restrict64(c, r, bc);
+    if (e == hipSuccess) e = transfer<true, double>(c, r, bc);
     if (e == hipSuccess) e = mg_vcycle64(C, bc, xc);
-    if (e == hipSuccess) e = mg_prolong_add64(c, xc, x);
-    if (e == hipSuccess) e = launch_apply64(c, x, r, b);
-    if (e == hipSuccess) e = cheb_apply64(c, r, t);
-    if (e == hipSuccess) e = blas_axpby(c, n, 1.0, t, 1.0, x);
+    if (e == hipSuccess) e = transfer<false, double>(c, xc, x);
+    if (e == hipSuccess) e = cheb_iterate64(c, b, x, false);
+    return e;
+}
+
+namespace {
+hipError_t vcycle32(hx_ctx *c, const float *b, float *x)
+{
+    if (!c->mg_coarse) return cheb_iterate32(c, b, x, true);
+    hx_ctx *C = c->mg_coarse;
+    const int64_t n = c->n_dofs;
+    float *r = c->mgw32 + 2 * n;
+    float *bc = C->mgw32, *xc = C->mgw32 + C->n_dofs;
+    hipError_t e = cheb_iterate32(c, b, x, true);
+    if (e == hipSuccess) e = launch_apply32(c, x, r, b);
+    if (e == hipSuccess) e = transfer<true, float>(c, r, bc);
+    if (e == hipSuccess) e = vcycle32(C, bc, xc);
+    if (e == hipSuccess) e = transfer<false, float>(c, xc, x);
+    if (e == hipSuccess) e = cheb_iterate32(c, b, x, false);
+    return e;
+}
+}  // namespace
+
+// The FP32 V-cycle as the preconditioner of an FP64 Krylov method: the FP64
+// residual is rounded to FP32, the cycle runs on the FP32 operator data, and
+// its result is widened again.  The rounding makes the preconditioner
+// slightly non-linear (relative perturbations of order 1e-7); CG tolerates
+// that in practice and FGMRES by construction.
+hipError_t mg_vcycle_mixed(hx_ctx *c, const double *r, double *z)
+{
+    const int64_t n = c->n_dofs;
+    float *b32 = c->mgw32, *x32 = c->mgw32 + n;
+    hipError_t e = blas_cast64to32(c, n, r, b32, nullptr);
+    if (e == hipSuccess) e = vcycle32(c, b32, x32);
+    if (e == hipSuccess) e = blas_cast32to64(c, n, x32, z, nullptr);
     return e;
 }
 

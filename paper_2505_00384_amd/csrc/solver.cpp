@@ -145,6 +145,7 @@ hx_status precondition(hx_ctx *c, int pc, int mixed, int inner_iters, const doub
     case HX_PC_MASS_BLOCK: HX_HIP(c, launch_massinv64(c, v, z)); return HX_OK;
     case HX_PC_CHEBYSHEV: HX_HIP(c, cheb_apply64(c, v, z)); return HX_OK;
     case HX_PC_MULTIGRID: HX_HIP(c, mg_vcycle64(c, v, z)); return HX_OK;
+    case HX_PC_MULTIGRID_MIXED: HX_HIP(c, mg_vcycle_mixed(c, v, z)); return HX_OK;
     default: return fail(c, HX_ERR_ARG, "unknown preconditioner %d", pc);
     }
 }
@@ -566,26 +567,55 @@ hx_status solve_fgmres(hx_ctx *c, const hx_solve_params *prm, const double *b, d
 // Chebyshev polynomial preconditioner (section 3.1 names it for the SPD
 // systems: a polynomial in M^-1 A that damps the eigenvalue range, the range
 // estimated by the Lanczos process; M = block Jacobi).  degree steps of the
-// Chebyshev iteration for A z = r from z = 0 on [lo, hi]:
-//   d = M^-1 r / theta, z = d; then rho' = 1/(2 sigma - rho),
+// Chebyshev iteration for A z = r from z = 0 (or from a given z, the same
+// polynomial acting on the error) on [lo, hi]:
+//   d = M^-1 (r - A z) / theta, z += d; then rho' = 1/(2 sigma - rho),
 //   d = rho' rho d + (2 rho' / delta) M^-1 (r - A z), z += d,
 // theta = (hi + lo)/2, delta = (hi - lo)/2, sigma = theta/delta, rho = 1/sigma.
-hipError_t cheb_apply64(hx_ctx *c, const double *r, double *z)
+hipError_t cheb_iterate64(hx_ctx *c, const double *b, double *x, bool x_zero)
 {
     const int64_t n = c->n_dofs;
-    double *res = c->chebw, *d = res + n, *t = d + n;
+    double *res = c->chebw, *d = res + n;
     const double theta = 0.5 * (c->cheb_hi + c->cheb_lo), delta = 0.5 * (c->cheb_hi - c->cheb_lo);
     const double sigma = theta / delta;
     double rho = 1.0 / sigma;
-    hipError_t e = launch_bj64(c, r, t);
-    if (e == hipSuccess) e = blas_axpby(c, n, 1.0 / theta, t, 0.0, d);
-    if (e == hipSuccess) e = blas_copy(c, n, d, z);
+    hipError_t e = hipSuccess;
+    const double *v = b;
+    if (!x_zero) {
+        e = launch_apply64(c, x, res, b);                       // res = b - A x
+        v = res;
+    }
+    // d = M^-1 v / theta; x = d or x += d (the block-Jacobi kernel's epilogue)
+    if (e == hipSuccess) e = launch_bj_cheb64(c, v, d, x, 1.0 / theta, 0.0, 0, !x_zero);
     for (int k = 1; k < c->cheb_deg && e == hipSuccess; ++k) {
         const double rn = 1.0 / (2.0 * sigma - rho);
-        e = launch_apply64(c, z, res, r);                       // res = r - A z
-        if (e == hipSuccess) e = launch_bj64(c, res, t);
-        if (e == hipSuccess) e = blas_axpby(c, n, 2.0 * rn / delta, t, rn * rho, d);
-        if (e == hipSuccess) e = blas_axpby(c, n, 1.0, d, 1.0, z);
+        e = launch_apply64(c, x, res, b);                       // res = b - A x
+        if (e == hipSuccess) e = launch_bj_cheb64(c, res, d, x, 2.0 * rn / delta, rn * rho, 1, 1);
+        rho = rn;
+    }
+    return e;
+}
+
+hipError_t cheb_apply64(hx_ctx *c, const double *r, double *z) { return cheb_iterate64(c, r, z, true); }
+
+hipError_t cheb_iterate32(hx_ctx *c, const float *b, float *x, bool x_zero)
+{
+    const int64_t n = c->n_dofs;
+    float *res = c->chebw32, *d = res + n;
+    const double theta = 0.5 * (c->cheb_hi + c->cheb_lo), delta = 0.5 * (c->cheb_hi - c->cheb_lo);
+    const double sigma = theta / delta;
+    double rho = 1.0 / sigma;
+    hipError_t e = hipSuccess;
+    const float *v = b;
+    if (!x_zero) {
+        e = launch_apply32(c, x, res, b);
+        v = res;
+    }
+    if (e == hipSuccess) e = launch_bj_cheb32(c, v, d, x, 1.0 / theta, 0.0, 0, !x_zero);
+    for (int k = 1; k < c->cheb_deg && e == hipSuccess; ++k) {
+        const double rn = 1.0 / (2.0 * sigma - rho);
+        e = launch_apply32(c, x, res, b);
+        if (e == hipSuccess) e = launch_bj_cheb32(c, res, d, x, 2.0 * rn / delta, rn * rho, 1, 1);
         rho = rn;
     }
     return e;
@@ -600,7 +630,8 @@ hx_status mg_check(hx_ctx *c)
             return fail(c, HX_ERR_STATE, "multigrid level %d has no Chebyshev smoother", depth);
         if (L->mg_coarse) {
             const hx_ctx *C = L->mg_coarse;
-            if (!L->mgw || !C->mgw || C->n_cells != L->mg_nc || C->k != L->k || C->stream != L->stream)
+            if (!L->mgw || !C->mgw || !L->mgw32 || !C->mgw32 || C->n_cells != L->mg_nc ||
+                C->k != L->k || C->stream != L->stream)
                 return fail(c, HX_ERR_STATE,
                             "multigrid level %d changed since hx_set_multigrid; link it again", depth + 1);
         }
@@ -650,7 +681,7 @@ hx_status hx_solve(hx_ctx *c, const hx_solve_params *prm, const double *b, doubl
         return fail(c, HX_ERR_ARG, "restart must be in 1..63");
     if (prm->orth != 0 && prm->orth != 1) return fail(c, HX_ERR_ARG, "orth must be 0 or 1");
     if (!(prm->rtol > 0.0) || prm->max_iter < 1) return fail(c, HX_ERR_ARG, "bad rtol/max_iter");
-    if (prm->pc < HX_PC_NONE || prm->pc > HX_PC_MULTIGRID) return fail(c, HX_ERR_ARG, "bad pc");
+    if (prm->pc < HX_PC_NONE || prm->pc > HX_PC_MULTIGRID_MIXED) return fail(c, HX_ERR_ARG, "bad pc");
     if (prm->method == 0 && (prm->pc == HX_PC_LEARNED || prm->mixed))
         return fail(c, HX_ERR_ARG, "CG needs a fixed SPD preconditioner; use FGMRES");
     if (prm->mixed && prm->inner_iters < 1) return fail(c, HX_ERR_ARG, "inner_iters must be >= 1");
@@ -661,9 +692,10 @@ hx_status hx_solve(hx_ctx *c, const hx_solve_params *prm, const double *b, doubl
         return fail(c, HX_ERR_STATE, "Chebyshev preconditioner not set");
     if (prm->pc == HX_PC_CHEBYSHEV && prm->mixed)
         return fail(c, HX_ERR_ARG, "the Chebyshev preconditioner is FP64; it cannot precondition the inner FP32 solve");
-    if (prm->pc == HX_PC_MULTIGRID && prm->mixed)
-        return fail(c, HX_ERR_ARG, "the multigrid preconditioner is FP64; it cannot precondition the inner FP32 solve");
-    if (prm->pc == HX_PC_MULTIGRID) {
+    const bool mgpc = prm->pc == HX_PC_MULTIGRID || prm->pc == HX_PC_MULTIGRID_MIXED;
+    if (mgpc && prm->mixed)
+        return fail(c, HX_ERR_ARG, "the multigrid preconditioner works on FP64 residuals; it cannot precondition the inner FP32 solve");
+    if (mgpc) {
         const hx_status s = mg_check(c);
         if (s != HX_OK) return s;
     }
@@ -770,7 +802,8 @@ hx_status hx_set_chebyshev(hx_ctx *c, int degree, double lo, double hi)
     if (!(lo > 0.0) || !(hi > lo) || !std::isfinite(hi)) return fail(c, HX_ERR_ARG, "need 0 < lo < hi");
     HX_HIP(c, hipSetDevice(c->device));
     if (!c->chebw) {
-        hx_status s = dalloc(c, (void **)&c->chebw, sizeof(double) * 3 * c->n_dofs);
+        hx_status s = dalloc(c, (void **)&c->chebw, sizeof(double) * 2 * c->n_dofs);
+        if (s == HX_OK) s = dalloc(c, (void **)&c->chebw32, sizeof(float) * 2 * c->n_dofs);
         if (s != HX_OK) return s;
     }
     c->cheb_deg = degree;
@@ -816,7 +849,10 @@ hx_status hx_set_multigrid(hx_ctx *c, hx_ctx *coarse, const int32_t *parent, con
     hx_status s = dalloc(c, (void **)&c->mg_cptr, sizeof(int32_t) * (nc + 1));
     if (s == HX_OK) s = dalloc(c, (void **)&c->mg_clist, sizeof(int32_t) * nf);
     for (hx_ctx *L : {c, coarse})
-        if (s == HX_OK && !L->mgw) s = dalloc(L, (void **)&L->mgw, sizeof(double) * 4 * L->n_dofs);
+        if (s == HX_OK && !L->mgw) {
+            s = dalloc(L, (void **)&L->mgw, sizeof(double) * 3 * L->n_dofs);
+            if (s == HX_OK) s = dalloc(L, (void **)&L->mgw32, sizeof(float) * 3 * L->n_dofs);
+        }
     if (s != HX_OK) return s;
     HX_HIP(c, hipMemcpy(c->mg_cptr, ptr.data(), sizeof(int32_t) * (nc + 1), hipMemcpyHostToDevice));
     HX_HIP(c, hipMemcpy(c->mg_clist, list.data(), sizeof(int32_t) * nf, hipMemcpyHostToDevice));

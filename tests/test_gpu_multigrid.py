@@ -102,6 +102,13 @@ def test_vcycle_matches_oracle(hierarchy):
         err = np.abs(z - ref).max() / np.abs(ref).max()
         print(f"[mg] V-cycle seed {seed}: {err:.2e}", flush=True)
         assert err <= 1e-11
+    # the FP32 cycle: the same V up to FP32 rounding
+    b = si.random_vector(levels[0].prob.n_dofs, 5)
+    z = ctxs[0].apply_preconditioner(to_dev(b), kind=hx.HX_PC_MULTIGRID_MIXED).cpu().numpy()
+    ref = mg.vcycle(levels, b)
+    err = np.abs(z - ref).max() / np.abs(ref).max()
+    print(f"[mg] FP32 V-cycle: {err:.2e}", flush=True)
+    assert err <= 2e-5
     # the middle level's own V-cycle (two levels) too
     b = si.random_vector(levels[1].prob.n_dofs, 7)
     z = ctxs[1].apply_preconditioner(to_dev(b), kind=hx.HX_PC_MULTIGRID).cpu().numpy()
@@ -158,6 +165,14 @@ def test_mg_cg_terrain_32x8x16_gpu_estimates():
     assert info["iters"] <= 15 and info["iters"] * 4 <= i_bj["iters"]
     _, fi = ctxs[0].solve(b, params=hx.default_params(method=1, rtol=1e-8, pc=hx.HX_PC_MULTIGRID))
     assert fi["status"] == hx.HX_OK and fi["true_rel_res"] <= 1e-8
+    # the FP32 cycle inside FP64 CG: the same iteration count within two
+    xm, im = ctxs[0].solve(b, params=hx.default_params(method=0, rtol=1e-8,
+                                                       pc=hx.HX_PC_MULTIGRID_MIXED))
+    print(f"[mg] 32x8x16: CG + FP32 V-cycle {im['iters']} iterations {im['ms_total']:.1f} ms",
+          flush=True)
+    assert im["status"] == hx.HX_OK and im["true_rel_res"] <= 1e-8
+    assert abs(im["iters"] - info["iters"]) <= 2
+    assert float((xm - x).norm() / x.norm()) <= 1e-7
     _close(ctxs)
 
 
@@ -193,6 +208,10 @@ def test_multigrid_errors():
     assert status(lambda: cf.solve(b, params=hx.default_params(method=1, mixed=1,
                                                               pc=hx.HX_PC_MULTIGRID))) == hx.HX_ERR_ARG
     assert status(lambda: cf.apply_preconditioner(b.float(), kind=hx.HX_PC_MULTIGRID)) == hx.HX_ERR_ARG
+    assert status(lambda: cf.apply_preconditioner(b.float(), kind=hx.HX_PC_MULTIGRID_MIXED)
+                  ) == hx.HX_ERR_ARG
+    zm = cf.apply_preconditioner(b, kind=hx.HX_PC_MULTIGRID_MIXED)
+    assert float((zm - z).norm() / z.norm()) <= 1e-5
     # the coarse level set up again: the link must be set again
     cc.setup_mesh(coarse.k, coarse.nodes, coarse.nbr, coarse.g)
     cc.set_coefficients(coarse.alpha, coarse.beta, coarse.P)
