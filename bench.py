@@ -141,14 +141,16 @@ def solve_suite(hx, ctx, b, torch, forms, label):
 
 
 def multigrid_suite(hx, ctx, b, torch, dev, dims, k, fine_bounds, levels=5, smooth_degree=2,
-                    smooth_ratio=15.0, coarse_degree=12):
+                    smooth_ratio=15.0, coarse_degree=12, consistent=False):
     """CG with one geometric-multigrid V-cycle per iteration: the terrain
     channel coarsened by two in every direction down to `levels` levels, each
     level's operator re-discretised with the coefficients at its own dofs,
     Chebyshev smoothing of degree 2 on [1.1 hi / 15, 1.1 hi] of each level's
     Lanczos range (20 steps on a random vector) and a degree-12 polynomial
     over the whole range on the coarsest level.  The set-up of the coarse
-    levels and their estimates is timed apart from the solve."""
+    levels and their estimates is timed apart from the solve.  With
+    ``consistent`` the system with consistent integration (set on ctx) is
+    solved too, preconditioned by the same cycle of the fast operator."""
     import synth_inputs as si
     nx, ny, nz = dims
     torch.cuda.synchronize()
@@ -182,7 +184,10 @@ def multigrid_suite(hx, ctx, b, torch, dev, dims, k, fine_bounds, levels=5, smoo
     out = solve_suite(hx, ctx, b, torch, [
         ("fp64_cg_multigrid", hx.default_params(method=0, rtol=1e-8, pc=hx.HX_PC_MULTIGRID)),
         ("fp64_cg_multigrid_fp32_cycle", hx.default_params(method=0, rtol=1e-8,
-                                                           pc=hx.HX_PC_MULTIGRID_MIXED))], "C3")
+                                                           pc=hx.HX_PC_MULTIGRID_MIXED))]
+        + ([("consistent_cg_multigrid_fp32_cycle", hx.default_params(
+            method=0, rtol=1e-8, system=2, pc=hx.HX_PC_MULTIGRID_MIXED))] if consistent else []),
+        "C3")
     for name in out:
         out[name].update(
             levels=[f"{nx // 2 ** l}x{ny // 2 ** l}x{nz // 2 ** l}" for l in range(len(ctxs))],
@@ -245,6 +250,36 @@ def consistent_suite(ctx, torch, k, reps=10):
     log(f"consistent integration: {out}")
     del x, y, yf
     return out
+
+
+def consistent_mass_suite(hx, ctx, b, torch, reps=10):
+    """The alpha-weighted mass with consistent integration (2k+1 points,
+    beta = 0) solved by CG with the fast (k+1)-point mass-block inverse as
+    preconditioner, against that fast inverse alone: the paper's two
+    treatments of its modified mass matrix (an iterative solve with
+    over-integration, or the direct tensor-product inverse with aliasing).
+    Replaces the consistent data of the context."""
+    import synth_inputs as si
+    xyz = ctx.dof_coordinates()
+    fa, _ = si.terrain_coefficients()
+    a = field_on_device(fa, xyz, torch)
+    del xyz
+    ctx.set_consistent(a, torch.zeros_like(a))
+    del a
+    res = solve_suite(hx, ctx, b, torch, [
+        ("consistent_mass_cg_fast_inverse", hx.default_params(
+            method=0, rtol=1e-8, system=2, pc=hx.HX_PC_MASS_BLOCK))], "C3")
+    z = torch.empty_like(b)
+    ms_fast = time_call(lambda: ctx.apply_preconditioner(b, z, kind=hx.HX_PC_MASS_BLOCK), reps,
+                        torch)
+    x, _ = ctx.solve(b, params=hx.default_params(method=0, rtol=1e-12, system=2,
+                                                 pc=hx.HX_PC_MASS_BLOCK))
+    res["fast_inverse_ms"] = round(ms_fast, 3)
+    res["rel_diff_fast_inverse_vs_consistent"] = float(torch.linalg.norm(z - x) /
+                                                       torch.linalg.norm(x))
+    log(f"C3 consistent mass: {res}")
+    del x, z
+    return res
 
 
 def pressure_suite(hx, ctx, torch, label, forms, reps=10, fixed_point=False):
@@ -433,10 +468,13 @@ def main():
             cheb["fp64_cg_chebyshev4_bj"].update(lanczos_ms=round(t_est, 1), lanczos_lo=lo,
                                                  lanczos_hi=hi)
             solve[f"terrain{args.nx}x{args.ny}x{args.nz}"].update(cheb)
-        solve[f"terrain{args.nx}x{args.ny}x{args.nz}"].update(
-            multigrid_suite(hx, ctx, b, torch, dev, (args.nx, args.ny, args.nz), k, (lo, hi)))
         if args.solves != "multigrid":
             consistent = consistent_suite(ctx, torch, k)
+        solve[f"terrain{args.nx}x{args.ny}x{args.nz}"].update(
+            multigrid_suite(hx, ctx, b, torch, dev, (args.nx, args.ny, args.nz), k, (lo, hi),
+                            consistent=consistent is not None))
+        if args.solves != "multigrid":
+            consistent["weighted_mass"] = consistent_mass_suite(hx, ctx, b, torch)
             # the pressure system of the stage on the same mesh: FGMRES with
             # the block Jacobi of the Helmholtz-type operator
             pressure[f"terrain{args.nx}x{args.ny}x{args.nz}"] = pressure_suite(

@@ -193,7 +193,12 @@ typedef struct {
                             system S = D - C A^-1 B of hx_set_pressure_system (FGMRES
                             only: S is not symmetric); the preconditioners, the inner
                             FP32 CG of the mixed form included, act with the
-                            Helmholtz-type operator set by hx_set_pressure_system */
+                            Helmholtz-type operator set by hx_set_pressure_system;
+                            2 = the operator with consistent integration of
+                            hx_set_consistent (CG or FGMRES), preconditioned by the
+                            preconditioners of the (k+1)-point operator (block
+                            Jacobi, the mass-block inverse, Chebyshev, multigrid,
+                            the inner FP32 CG) */
 } hx_solve_params;
 
 typedef struct {

@@ -170,6 +170,31 @@ hx_status read_scalars(hx_ctx *c, const double *dev, int m, double *host)
 // preconditioner, r.z and r.r) and the update of p.  The host reads |r|^2
 // of step k while step k+1 runs, so the stream never waits for the host; the
 // solve stops one step after the test first passes.
+// y = M x or y = b - M x for the system being solved: the Helmholtz-type
+// operator, the pressure system S = D - C A^-1 B, or the Helmholtz-type
+// operator with consistent integration (2k+1 points)
+hipError_t sys_apply(hx_ctx *c, const hx_solve_params *prm, const double *x, double *y,
+                     const double *b)
+{
+    if (prm->system == 1) return press_apply64(c, x, y, b);
+    if (prm->system == 2) {
+        hipError_t e = launch_apply_q(c, x, y);
+        if (e == hipSuccess && b) e = blas_axpby(c, c->n_dofs, 1.0, b, -1.0, y);
+        return e;
+    }
+    return launch_apply64(c, x, y, b);
+}
+
+// q = M p and dst = p.q (the operator kernel sums p.q itself for system 0)
+hipError_t sys_apply_dot(hx_ctx *c, const hx_solve_params *prm, const double *p, double *q,
+                         double *dst)
+{
+    if (prm->system == 0) return launch_apply64_dot(c, p, q, dst);
+    hipError_t e = sys_apply(c, prm, p, q, nullptr);
+    if (e == hipSuccess) e = blas_dot(c, c->n_dofs, p, q, dst);
+    return e;
+}
+
 hx_status solve_cg(hx_ctx *c, const hx_solve_params *prm, const double *b, double *x,
                    hx_solve_info *info, Timer &tm)
 {
@@ -181,7 +206,7 @@ hx_status solve_cg(hx_ctx *c, const hx_solve_params *prm, const double *b, doubl
     double h[2];
     HX_HIP(c, blas_dot(c, n, b, b, sc + 4));
     if (prm->x0_mode == 1) {
-        HX_HIP(c, launch_apply64(c, x, r, b));
+        HX_HIP(c, sys_apply(c, prm, x, r, b));
     } else {
         HX_HIP(c, blas_fill(c, n, 0.0, x));
         HX_HIP(c, blas_copy(c, n, b, r));
@@ -234,7 +259,7 @@ hx_status solve_cg(hx_ctx *c, const hx_solve_params *prm, const double *b, doubl
     while (it < prm->max_iter && !stop) {
         Timer &t = *tms[it % 2];
         t.rec(1, c->stream);
-        if (hipSuccess != launch_apply64_dot(c, p, q, sc + 1)) { err = fail(c, HX_ERR_DEVICE, "CG: apply"); break; }
+        if (hipSuccess != sys_apply_dot(c, prm, p, q, sc + 1)) { err = fail(c, HX_ERR_DEVICE, "CG: apply"); break; }
         t.rec(2, c->stream);
         t.rec(0, c->stream);
         if (hipSuccess != cg_step_pc64(c, prm->pc, x, r, p, q, z, sc)) { err = fail(c, HX_ERR_DEVICE, "CG: step"); break; }
@@ -328,13 +353,6 @@ struct Hess {
 //    block dot that finalises its last column.  Convergence is tested on the
 //    provisional column (the correction is of the order of the loss of
 //    orthogonality) and confirmed after finalising it.
-// y = M x or y = b - M x for the system being solved: the Helmholtz-type
-// operator, or the pressure system S = D - C A^-1 B
-static hipError_t sys_apply(hx_ctx *c, const hx_solve_params *prm, const double *x, double *y,
-                            const double *b)
-{
-    return prm->system == 1 ? press_apply64(c, x, y, b) : launch_apply64(c, x, y, b);
-}
 
 hx_status solve_fgmres(hx_ctx *c, const hx_solve_params *prm, const double *b, double *x,
                        hx_solve_info *info, Timer &tm)
@@ -699,7 +717,8 @@ hx_status hx_solve(hx_ctx *c, const hx_solve_params *prm, const double *b, doubl
         const hx_status s = mg_check(c);
         if (s != HX_OK) return s;
     }
-    if (prm->system != 0 && prm->system != 1) return fail(c, HX_ERR_ARG, "system must be 0 or 1");
+    if (prm->system < 0 || prm->system > 2) return fail(c, HX_ERR_ARG, "system must be 0, 1 or 2");
+    if (prm->system == 2 && !c->has_q) return fail(c, HX_ERR_STATE, "consistent integration not set");
     if (prm->system == 1 && !c->has_press) return fail(c, HX_ERR_STATE, "pressure system not set");
     if (prm->system == 1 && prm->method != 1)
         return fail(c, HX_ERR_ARG, "the pressure system is not symmetric; use FGMRES");
