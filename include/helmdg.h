@@ -272,8 +272,9 @@ hx_status hx_estimate_eigenvalues(hx_ctx *c, const double *b, int iters, double 
  * own `coarse`: keep it alive while linked; set up its mesh again and the
  * link must be set again.  Errors: HX_ERR_ARG for bad maps, a degree,
  * device or stream mismatch or a cycle of links; HX_ERR_STATE before
- * hx_setup_mesh.  Working memory: 3 n_dofs doubles and 3 n_dofs floats on
- * each linked level (and 2 of each per level for its Chebyshev polynomial).
+ * hx_setup_mesh; a failed call leaves c without a coarser level.  Working
+ * memory: 3 n_dofs doubles and 3 n_dofs floats on each linked level (and 2
+ * of each per level for its Chebyshev polynomial).
  *
  * hx_mg_transfer applies one transfer of the link (DEVICE FP64 vectors):
  * dir 0 restricts `in` ([n_dofs of c]) into `out` ([n_dofs of the coarse
