@@ -415,23 +415,21 @@ __device__ __forceinline__ void interp_t(double *F, bool act, int a, int b, cons
 
 // add face-layer contributions A[f][e1 + N e2] of the six faces to the x
 // pencil (i, j=a, l=b) of the lane
+// add the contribution of face f, computed on its face layer (e1, e2), to
+// the pencil y of lane (a, b): x faces hold nodes (0 or N-1, a, b) with
+// (e1, e2) = (j, l); y faces j = a with (e1, e2) = (i, l); z faces l = b with
+// (e1, e2) = (i, j)
 template <int N>
-__device__ __forceinline__ void add_faces(const double *A, int a, int b, double (&y)[N])
+__device__ __forceinline__ void add_face(const double *A, int f, int a, int b, double (&y)[N])
 {
-    constexpr int NF = N * N;
-    // x faces: nodes (0 or N-1, a, b), (e1, e2) = (j, l)
-    y[0] += A[0 * NF + a + N * b];
-    y[N - 1] += A[1 * NF + a + N * b];
-    // y faces: j = a on the layer, (e1, e2) = (i, l)
-    if (a == 0)
-        for (int i = 0; i < N; ++i) y[i] += A[2 * NF + i + N * b];
-    if (a == N - 1)
-        for (int i = 0; i < N; ++i) y[i] += A[3 * NF + i + N * b];
-    // z faces: l = b on the layer, (e1, e2) = (i, j)
-    if (b == 0)
-        for (int i = 0; i < N; ++i) y[i] += A[4 * NF + i + N * a];
-    if (b == N - 1)
-        for (int i = 0; i < N; ++i) y[i] += A[5 * NF + i + N * a];
+    switch (f) {
+    case 0: y[0] += A[a + N * b]; break;
+    case 1: y[N - 1] += A[a + N * b]; break;
+    case 2: if (a == 0) for (int i = 0; i < N; ++i) y[i] += A[i + N * b]; break;
+    case 3: if (a == N - 1) for (int i = 0; i < N; ++i) y[i] += A[i + N * b]; break;
+    case 4: if (b == 0) for (int i = 0; i < N; ++i) y[i] += A[i + N * a]; break;
+    default: if (b == N - 1) for (int i = 0; i < N; ++i) y[i] += A[i + N * a]; break;
+    }
 }
 
 // MINV: the output is A^-1 B p (the rho-weighted mass inverse of each
@@ -448,7 +446,7 @@ k_grad(const double *__restrict__ p, double *__restrict__ u3, int64_t nt,
     __shared__ double sP[CPB][ND];
     __shared__ double sF[CPB][3][ND];
     __shared__ double sG[CPB][3][NF];
-    __shared__ double sA[CPB][3][6 * NF];
+    __shared__ double sA[CPB][3][NF];
     __shared__ double sL[CPB][NF];
     const int t = threadIdx.x;
     const int lc0 = t / NF;
@@ -469,6 +467,14 @@ k_grad(const double *__restrict__ p, double *__restrict__ u3, int64_t nt,
     for (int e = t; e < NF; e += blockDim.x) sB[e] = T->B[e];
     if (act)
         for (int e = tt; e < ND; e += NF) sP[lc][e] = p[cid * ND + e];
+    // the neighbours' face layers (one value per lane and face), requested
+    // before the cell part so that their latency overlaps it
+    double nbv[6];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        const int32_t nb = act ? rec[1 + f] : -1;
+        nbv[f] = nb >= 0 ? p[(int64_t)nb * ND + lay<N>(f >> 1, (f & 1) ? 0 : N - 1, a, b)] : 0.0;
+    }
     __syncthreads();
     const LaneB<N> LB(sB, a, b);
     double pq[N];
@@ -489,10 +495,11 @@ k_grad(const double *__restrict__ p, double *__restrict__ u3, int64_t nt,
     }
     // faces: tau ds n_e p^ at the Gauss points, back to the face-layer nodes;
     // the neighbour's face layer is gathered into LDS first (one value per lane)
+#pragma unroll
     for (int f = 0; f < 6; ++f) {
         const int d = f >> 1, s = f & 1;
         const int32_t nb = act ? rec[1 + f] : -1;
-        if (nb >= 0) sL[lc][tt] = p[(int64_t)nb * ND + lay<N>(d, s ? 0 : N - 1, a, b)];
+        if (nb >= 0) sL[lc][tt] = nbv[f];
         __syncthreads();
         if (act) {
             const double po = trace_at<N>(LB, sP[lc], d, s ? N - 1 : 0);
@@ -503,12 +510,12 @@ k_grad(const double *__restrict__ p, double *__restrict__ u3, int64_t nt,
         }
         __syncthreads();
         if (act)
-            for (int ec = 0; ec < 3; ++ec) sA[lc][ec][f * NF + tt] = trace_t<N>(LB, sG[lc][ec]);
+            for (int ec = 0; ec < 3; ++ec) sA[lc][ec][tt] = trace_t<N>(LB, sG[lc][ec]);
         __syncthreads();
-    }
-    if (act)
+        if (act)
 #pragma unroll
-        for (int ec = 0; ec < 3; ++ec) add_faces<N>(sA[lc][ec], a, b, Y[ec]);
+            for (int ec = 0; ec < 3; ++ec) add_face<N>(sA[lc][ec], f, a, b, Y[ec]);
+    }
     if (MINV)
         mass_inv3<N>(sF[lc][0], sF[lc][1], sF[lc][2], act, a, b, mr + cid * ND + a + N * b, Y);
     if (act)
@@ -533,7 +540,7 @@ k_div(const double *__restrict__ u3, double *__restrict__ qv, int64_t nt,
     __shared__ double sU[CPB][3][ND];
     __shared__ double sF[CPB][3][ND];
     __shared__ double sG[CPB][NF];
-    __shared__ double sA[CPB][6 * NF];
+    __shared__ double sA[CPB][NF];
     __shared__ double sL[CPB][3][NF];
     const int t = threadIdx.x;
     const int lc0 = t / NF;
@@ -578,6 +585,7 @@ k_div(const double *__restrict__ u3, double *__restrict__ qv, int64_t nt,
     grad_t<N>(sF[lc][0], sF[lc][1], sF[lc][2], act, a, b, t0, t1, t2, tau, Y);
     // interior faces: tau ds {hr u . n_K} at the Gauss points, back to the
     // nodes; the neighbour's face layers are gathered into LDS first
+#pragma unroll
     for (int f = 0; f < 6; ++f) {
         const int d = f >> 1, s = f & 1;
         const int32_t nb = act ? rec[1 + f] : -1;
@@ -604,10 +612,10 @@ k_div(const double *__restrict__ u3, double *__restrict__ qv, int64_t nt,
             sG[lc][tt] = g;
         }
         __syncthreads();
-        if (act) sA[lc][f * NF + tt] = trace_t<N>(LB, sG[lc]);
+        if (act) sA[lc][tt] = trace_t<N>(LB, sG[lc]);
         __syncthreads();
+        if (act) add_face<N>(sA[lc], f, a, b, Y);
     }
-    if (act) add_faces<N>(sA[lc], a, b, Y);
     if (DP) {
         // D x: x at the Gauss points, times md, back to the nodes
         if (act)
