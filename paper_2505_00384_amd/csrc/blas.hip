@@ -294,7 +294,8 @@ template <typename T>
 __global__ void __launch_bounds__(RT) k_cg_elem(int64_t n, T *x, T *r, const T *__restrict__ p,
                                                 const T *__restrict__ q, T *z,
                                                 const T *__restrict__ dinv,
-                                                const double *__restrict__ sc, double *part, int ld)
+                                                const double *__restrict__ sc, double *part, int ld,
+                                                float *r32)
 {
     __shared__ double sh[RT / 64];
     const T al = (T)(sc[1] != 0.0 ? sc[0] / sc[1] : 0.0);
@@ -305,7 +306,8 @@ __global__ void __launch_bounds__(RT) k_cg_elem(int64_t n, T *x, T *r, const T *
         x[i] += al * p[i];
         r[i] = rv;
         const T zv = dinv ? dinv[i] * rv : rv;
-        z[i] = zv;
+        if (r32) r32[i] = (float)rv;   // the FP32 V-cycle's input in place of z
+        else z[i] = zv;
         rz += (double)rv * (double)zv;
         rr += (double)rv * (double)rv;
     }
@@ -315,6 +317,24 @@ __global__ void __launch_bounds__(RT) k_cg_elem(int64_t n, T *x, T *r, const T *
         part[blockIdx.x] = rz;
         part[ld + blockIdx.x] = rr;
     }
+}
+
+// z = (double) x32 and per-block partial sums of r.z (the FP32 V-cycle's
+// output widened and dotted in one pass)
+__global__ void __launch_bounds__(RT) k_widen_dot(int64_t n, const float *__restrict__ x32,
+                                                  const double *__restrict__ r, double *z,
+                                                  double *part)
+{
+    __shared__ double sh[RT / 64];
+    double s = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * RT;
+    for (int64_t i = blockIdx.x * (int64_t)RT + threadIdx.x; i < n; i += stride) {
+        const double zv = (double)x32[i];
+        z[i] = zv;
+        s += r[i] * zv;
+    }
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
 // p = z + (sc[2] / sc[0]) p
@@ -534,8 +554,12 @@ hipError_t cg_step_pc(hx_ctx *c, int pc, T *x, T *r, const T *p, const T *q, T *
             dinv = dbl ? (const T *)(c->dg64 + (int64_t)w * n) : (const T *)(c->dg32 + (int64_t)w * n);
         }
         nb = red_blocks(n);
+        // the FP32 V-cycle reads r rounded to FP32 from its level vector
+        float *r32 = nullptr;
+        if constexpr (sizeof(T) == 8)
+            if (pc == HX_PC_MULTIGRID_MIXED) r32 = c->mgw32;
         hipLaunchKernelGGL(k_cg_elem<T>, dim3(nb), dim3(RT), 0, c->stream, n, x, r, p, q, z, dinv,
-                           sc, c->cgpart, ld);
+                           sc, c->cgpart, ld, r32);
         e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
@@ -550,12 +574,23 @@ hipError_t cg_step_pc(hx_ctx *c, int pc, T *x, T *r, const T *p, const T *q, T *
     if constexpr (sizeof(T) == 8) {
         // the polynomial and multigrid preconditioners: z = r above, now
         // z = p(M^-1 A) M^-1 r or one V-cycle, and sc[2] = r.z
-        if (e == hipSuccess &&
-            (pc == HX_PC_CHEBYSHEV || pc == HX_PC_MULTIGRID || pc == HX_PC_MULTIGRID_MIXED)) {
-            e = pc == HX_PC_CHEBYSHEV   ? cheb_apply64(c, (const double *)r, (double *)z)
-                : pc == HX_PC_MULTIGRID ? mg_vcycle64(c, (const double *)r, (double *)z)
-                                        : mg_vcycle_mixed(c, (const double *)r, (double *)z);
+        if (e == hipSuccess && (pc == HX_PC_CHEBYSHEV || pc == HX_PC_MULTIGRID)) {
+            e = pc == HX_PC_CHEBYSHEV ? cheb_apply64(c, (const double *)r, (double *)z)
+                                      : mg_vcycle64(c, (const double *)r, (double *)z);
             if (e == hipSuccess) e = blas_dot(c, n, (const double *)r, (const double *)z, sc + 2);
+        }
+        if (e == hipSuccess && pc == HX_PC_MULTIGRID_MIXED) {
+            // r in FP32 is already in place: the cycle, then z and r.z in one pass
+            e = mg_vcycle32_resident(c);
+            if (e == hipSuccess) {
+                const int nbd = red_blocks(n);
+                hipLaunchKernelGGL(k_widen_dot, dim3(nbd), dim3(RT), 0, c->stream, n,
+                                   (const float *)(c->mgw32 + n), (const double *)r, (double *)z,
+                                   c->red);
+                hipLaunchKernelGGL(k_red2, dim3(1), dim3(RT), 0, c->stream, c->red, nbd, RED_MAX,
+                                   sc + 2);
+                e = hipGetLastError();
+            }
         }
     }
     return e;

@@ -200,6 +200,9 @@ hipError_t mg_prolong_add64(hx_ctx *c, const double *x_coarse, double *x_fine);
 // the same V-cycle in FP32 throughout (FP32 operator, smoother, transfers and
 // level vectors) for an FP64 residual r: z = (double) V32 (float) r
 hipError_t mg_vcycle_mixed(hx_ctx *c, const double *r, double *z);
+// the same FP32 cycle from the finest level's FP32 input vector mgw32[0, n)
+// to its output mgw32[n, 2n)
+hipError_t mg_vcycle32_resident(hx_ctx *c);
 // HX_OK if the chain of levels below c is usable by the V-cycle
 hx_status mg_check(hx_ctx *c);
 // h = gamma p / ((gamma - 1) rho) at the nodes

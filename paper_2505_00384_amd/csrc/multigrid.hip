@@ -228,4 +228,12 @@ hipError_t mg_vcycle_mixed(hx_ctx *c, const double *r, double *z)
     return e;
 }
 
+// the FP32 cycle on the finest level's own vectors: input in mgw32[0, n),
+// output in mgw32[n, 2n) (the fused CG step writes the input itself)
+hipError_t mg_vcycle32_resident(hx_ctx *c)
+{
+    const int64_t n = c->n_dofs;
+    return vcycle32(c, c->mgw32, c->mgw32 + n);
+}
+
 }  // namespace hx
