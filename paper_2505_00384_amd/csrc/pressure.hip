@@ -538,7 +538,7 @@ k_div(const double *__restrict__ u3, double *__restrict__ qv, int64_t nt,
     constexpr int NF = PCfg<N, DIV_T>::NF, ND = PCfg<N, DIV_T>::ND, CPB = PCfg<N, DIV_T>::CPB;
     __shared__ double sB[NF];
     __shared__ double sU[CPB][3][ND];
-    __shared__ double sF[CPB][3][ND];
+    __shared__ double sF[CPB][ND];
     __shared__ double sG[CPB][NF];
     __shared__ double sA[CPB][NF];
     __shared__ double sL[CPB][3][NF];
@@ -564,27 +564,12 @@ k_div(const double *__restrict__ u3, double *__restrict__ qv, int64_t nt,
             for (int e = tt; e < ND; e += NF) sU[lc][ec][e] = u3[ec * nt + cid * ND + e];
     __syncthreads();
     const LaneB<N> LB(sB, a, b);
-    double uq[3][N];
+    // interior faces first, while all three velocity layers are in LDS:
+    // tau ds {hr u . n_K} at the Gauss points, back to the nodes; the
+    // neighbour's face layers are gathered into LDS first
+    double Yf[N];
 #pragma unroll
-    for (int ec = 0; ec < 3; ++ec) to_gauss<N>(sU[lc][ec], sF[lc][0], act, a, b, uq[ec]);
-    double t0[N], t1[N], t2[N], Y[N];
-    if (act) {
-        const double *Wc = WC + cid * 9 * ND + a + N * b;
-        for (int q = 0; q < N; ++q) {
-            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-            for (int ec = 0; ec < 3; ++ec) {
-                s0 += Wc[(0 + ec) * ND + NF * q] * uq[ec][q];
-                s1 += Wc[(3 + ec) * ND + NF * q] * uq[ec][q];
-                s2 += Wc[(6 + ec) * ND + NF * q] * uq[ec][q];
-            }
-            t0[q] = s0;
-            t1[q] = s1;
-            t2[q] = s2;
-        }
-    }
-    grad_t<N>(sF[lc][0], sF[lc][1], sF[lc][2], act, a, b, t0, t1, t2, tau, Y);
-    // interior faces: tau ds {hr u . n_K} at the Gauss points, back to the
-    // nodes; the neighbour's face layers are gathered into LDS first
+    for (int i = 0; i < N; ++i) Yf[i] = 0.0;
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
         const int d = f >> 1, s = f & 1;
@@ -614,19 +599,44 @@ k_div(const double *__restrict__ u3, double *__restrict__ qv, int64_t nt,
         __syncthreads();
         if (act) sA[lc][tt] = trace_t<N>(LB, sG[lc]);
         __syncthreads();
-        if (act) add_face<N>(sA[lc], f, a, b, Y);
+        if (act) add_face<N>(sA[lc], f, a, b, Yf);
     }
+    // cell terms: the velocity at the Gauss points, the weighted metric
+    // terms, the transposed gradient; once at the Gauss points the second
+    // and third velocity layers serve as its scratch
+    double uq[3][N];
+#pragma unroll
+    for (int ec = 0; ec < 3; ++ec) to_gauss<N>(sU[lc][ec], sF[lc], act, a, b, uq[ec]);
+    double t0[N], t1[N], t2[N], Y[N];
+    if (act) {
+        const double *Wc = WC + cid * 9 * ND + a + N * b;
+        for (int q = 0; q < N; ++q) {
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+            for (int ec = 0; ec < 3; ++ec) {
+                s0 += Wc[(0 + ec) * ND + NF * q] * uq[ec][q];
+                s1 += Wc[(3 + ec) * ND + NF * q] * uq[ec][q];
+                s2 += Wc[(6 + ec) * ND + NF * q] * uq[ec][q];
+            }
+            t0[q] = s0;
+            t1[q] = s1;
+            t2[q] = s2;
+        }
+    }
+    grad_t<N>(sF[lc], sU[lc][1], sU[lc][2], act, a, b, t0, t1, t2, tau, Y);
+    if (act)
+#pragma unroll
+        for (int i = 0; i < N; ++i) Y[i] += Yf[i];
     if (DP) {
         // D x: x at the Gauss points, times md, back to the nodes
         if (act)
-            for (int e = tt; e < ND; e += NF) sF[lc][1][e] = xv[cid * ND + e];
+            for (int e = tt; e < ND; e += NF) sU[lc][0][e] = xv[cid * ND + e];
         __syncthreads();
         double xq[N], dx[N];
-        to_gauss<N>(sF[lc][1], sF[lc][0], act, a, b, xq);
+        to_gauss<N>(sU[lc][0], sF[lc], act, a, b, xq);
         if (act)
 #pragma unroll
             for (int q = 0; q < N; ++q) xq[q] *= md[cid * ND + a + N * b + NF * q];
-        interp_t<N>(sF[lc][0], act, a, b, xq, dx);
+        interp_t<N>(sF[lc], act, a, b, xq, dx);
         if (act)
 #pragma unroll
             for (int i = 0; i < N; ++i) Y[i] = dx[i] - Y[i];
