@@ -110,3 +110,38 @@ def test_mg_cg_beats_block_jacobi():
     assert info_mg.converged and info_mg.true_rel_res <= 1.1e-8
     assert info_mg.iters <= 10 and info_mg.iters * 3 <= info_bj.iters, (info_mg.iters, info_bj.iters)
     assert np.linalg.norm(x_mg - x_bj) <= 1e-6 * np.linalg.norm(x_bj)
+
+
+def test_pins_catch_planted_mistakes(monkeypatch):
+    """Plausible mistakes planted in the oracle (on the CPU) fail the pins
+    above: the two halves of the embedding swapped, the x and z octant bits
+    exchanged, and a cycle without post-smoothing (not symmetric)."""
+    k = 2
+    fine, coarse, (parent, octant) = _nested(3, 2, 1, k, seed=2)
+    f = _poly(k, seed=5)
+    xc = f(*coarse.dof_coords())
+    ref = f(*fine.dof_coords())
+    scale = np.abs(ref).max()
+    assert np.abs(mg.prolong(k, parent, octant, xc) - ref).max() <= 1e-12 * scale
+    good = mg.octant_embeddings
+    monkeypatch.setattr(mg, "octant_embeddings", lambda kk: good(kk)[::-1].copy())
+    assert np.abs(mg.prolong(k, parent, octant, xc) - ref).max() > 1e-3 * scale
+    monkeypatch.setattr(mg, "octant_embeddings", good)
+    swapped = ((octant & 1) << 2) | (octant & 2) | ((octant >> 2) & 1)
+    assert np.abs(mg.prolong(k, parent, swapped, xc) - ref).max() > 1e-3 * scale
+    # a V-cycle that skips the post-smoothing is not symmetric
+    probs, maps = terrain_hierarchy(8, 4, 4, 2, 2)
+    levels = oracle_levels(probs, maps)
+
+    def pre_only(b):
+        L, C = levels
+        x = L.smooth(b)
+        r = b - L.prob.apply(x)
+        bc = mg.restrict(k, L.parent, L.octant, r, C.prob.n_cells)
+        return x + mg.prolong(k, L.parent, L.octant, C.smooth(bc))
+    n = probs[0].n_dofs
+    a, b = si.random_vector(n, 1), si.random_vector(n, 2)
+    Va, Vb = mg.vcycle(levels, a), mg.vcycle(levels, b)
+    assert abs(Va @ b - a @ Vb) <= 1e-12 * np.linalg.norm(Va) * np.linalg.norm(b)
+    Pa, Pb = pre_only(a), pre_only(b)
+    assert abs(Pa @ b - a @ Pb) > 1e-6 * np.linalg.norm(Pa) * np.linalg.norm(b)
