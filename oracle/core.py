@@ -43,37 +43,42 @@ def lib():
     global _lib
     if _lib is None:
         build()
-        L = C.CDLL(LIB)
-        dp = C.POINTER(C.c_double)
-        pp = C.POINTER(_Prob)
-        L.or_gauss_legendre.argtypes = [C.c_int, dp, dp]
-        L.or_gauss_lobatto.argtypes = [C.c_int, dp, dp]
-        L.or_lagrange.argtypes = [C.c_int, dp, C.c_double, dp, dp]
-        L.or_mesh_check.argtypes = [pp]
-        L.or_mesh_check.restype = C.c_int
-        for name in ("or_dof_coords", "or_cell_volumes", "or_face_sigma"):
-            getattr(L, name).argtypes = [pp, dp]
-        L.or_quad_data.argtypes = [pp, dp, dp]
-        L.or_load_vector.argtypes = [pp, dp, dp]
-        L.or_apply.argtypes = [pp, C.c_int, dp, dp]
-        L.or_assemble_dense.argtypes = [pp, C.c_int, dp]
-        L.or_cell_diagonal.argtypes = [pp, C.c_int, dp]
-        L.or_mass_block.argtypes = [pp, C.c_long, dp]
-        L.or_mass_block_apply.argtypes = [pp, dp, dp]
-        L.or_mass_block_apply.restype = C.c_int
-        L.or_grad_apply.argtypes = [pp, C.c_double, dp, dp]
-        L.or_apply_q.argtypes = [pp, C.c_int, C.c_int, dp, dp]
-        L.or_apply_q_cells.argtypes = [pp, C.c_int, C.c_int, C.c_void_p, C.c_long, dp, dp]
-        L.or_div_apply.argtypes = [pp, C.c_double, dp, dp, dp]
-        L.or_grad_apply_cells.argtypes = [pp, C.c_double, C.c_void_p, C.c_long, dp, dp]
-        L.or_div_apply_cells.argtypes = [pp, C.c_double, dp, C.c_void_p, C.c_long, dp, dp]
-        L.or_apply_cells.argtypes = [pp, C.c_int, C.c_void_p, C.c_long, dp, dp]
-        L.or_bj_cell_data.argtypes = [pp, C.c_long, dp, dp, dp, dp]
-        L.or_bj_sep_block.argtypes = [pp, C.c_long, dp]
-        L.or_bj_sep_apply.argtypes = [pp, dp, dp]
-        L.or_bj_sep_apply.restype = C.c_int
-        _lib = L
+        _lib = bind(C.CDLL(LIB))
     return _lib
+
+
+def bind(L):
+    """Declare the argument types of the oracle's entry points on a loaded
+    copy of the library (the oracle itself, or a variant a test compiled)."""
+    dp = C.POINTER(C.c_double)
+    pp = C.POINTER(_Prob)
+    L.or_gauss_legendre.argtypes = [C.c_int, dp, dp]
+    L.or_gauss_lobatto.argtypes = [C.c_int, dp, dp]
+    L.or_lagrange.argtypes = [C.c_int, dp, C.c_double, dp, dp]
+    L.or_mesh_check.argtypes = [pp]
+    L.or_mesh_check.restype = C.c_int
+    for name in ("or_dof_coords", "or_cell_volumes", "or_face_sigma"):
+        getattr(L, name).argtypes = [pp, dp]
+    L.or_quad_data.argtypes = [pp, dp, dp]
+    L.or_load_vector.argtypes = [pp, dp, dp]
+    L.or_apply.argtypes = [pp, C.c_int, dp, dp]
+    L.or_assemble_dense.argtypes = [pp, C.c_int, dp]
+    L.or_cell_diagonal.argtypes = [pp, C.c_int, dp]
+    L.or_mass_block.argtypes = [pp, C.c_long, dp]
+    L.or_mass_block_apply.argtypes = [pp, dp, dp]
+    L.or_mass_block_apply.restype = C.c_int
+    L.or_grad_apply.argtypes = [pp, C.c_double, dp, dp]
+    L.or_apply_q.argtypes = [pp, C.c_int, C.c_int, dp, dp]
+    L.or_apply_q_cells.argtypes = [pp, C.c_int, C.c_int, C.c_void_p, C.c_long, dp, dp]
+    L.or_div_apply.argtypes = [pp, C.c_double, dp, dp, dp]
+    L.or_grad_apply_cells.argtypes = [pp, C.c_double, C.c_void_p, C.c_long, dp, dp]
+    L.or_div_apply_cells.argtypes = [pp, C.c_double, dp, C.c_void_p, C.c_long, dp, dp]
+    L.or_apply_cells.argtypes = [pp, C.c_int, C.c_void_p, C.c_long, dp, dp]
+    L.or_bj_cell_data.argtypes = [pp, C.c_long, dp, dp, dp, dp]
+    L.or_bj_sep_block.argtypes = [pp, C.c_long, dp]
+    L.or_bj_sep_apply.argtypes = [pp, dp, dp]
+    L.or_bj_sep_apply.restype = C.c_int
+    return L
 
 
 def _dp(a: np.ndarray):
