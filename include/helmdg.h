@@ -403,6 +403,22 @@ hx_status hx_training_pair(hx_ctx *c, const double *b, const double *x_star, con
 /* out DEVICE float [batch][n_out] = network(feats DEVICE float [batch][n_in]). */
 hx_status hx_network_forward(hx_ctx *c, const float *feats, int64_t batch, float *out);
 
+/* The same forward pass for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): it calls no hipMalloc, hipFree or allocating library routine.
+ * Its work buffers (packed BF16 inputs and both hidden layers, 2 (ldx + 512)
+ * bytes per row, ldx = n_in rounded up to 32) live in one 16 MiB static
+ * device array per GPU, held until the process ends; batch may not exceed
+ * hx_network_noalloc_max_batch (10,485 rows at Q4), else HX_ERR_ARG and no
+ * launch.  Arguments and layout as hx_network_forward; the result is the
+ * same bit for bit.  All calls on one GPU share the array: calls that
+ * overlap on one GPU (several streams or threads) race.  Asynchronous on the
+ * context's stream. */
+hx_status hx_network_forward_noalloc(hx_ctx *c, const float *feats, int64_t batch, float *out);
+/* Largest batch of hx_network_forward_noalloc for this context's degree
+ * (-1 before hx_setup_mesh). */
+int64_t hx_network_noalloc_max_batch(const hx_ctx *c);
+
 /* One Adam step on the MSE loss mean((net(feats) - targets)^2): forward,
  * backward and update on the GPU.  feats DEVICE float [batch][n_in], targets
  * DEVICE float [batch][n_out]; *loss_out (HOST, may be NULL) = loss before

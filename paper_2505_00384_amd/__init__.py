@@ -87,6 +87,8 @@ def load(path: str = LIB_PATH):
         "hx_get_network": ([vp, vp, i64], C.c_int),
         "hx_gather_features": ([vp, vp, vp, vp], C.c_int),
         "hx_network_forward": ([vp, vp, i64, vp], C.c_int),
+        "hx_network_forward_noalloc": ([vp, vp, i64, vp], C.c_int),
+        "hx_network_noalloc_max_batch": ([vp], i64),
         "hx_training_pair": ([vp, vp, vp, vp, vp, vp], C.c_int),
         "hx_train_step": ([vp, vp, vp, i64, C.c_float, C.POINTER(C.c_float), vp], C.c_int),
         "hx_debug_export": ([vp, C.c_int, vp, i64], C.c_int),
@@ -390,6 +392,20 @@ class HelmDG:
                   "network_forward")
         return out
 
+
+    def network_forward_noalloc(self, feats, out=None):
+        """The same forward pass with the library's static work buffers (no
+        device allocation inside the call); ``out`` may be given."""
+        n_out = (self.k + 1) ** 3
+        if out is None:
+            out = self.torch.empty(feats.shape[0], n_out, dtype=self.torch.float32,
+                                   device=feats.device)
+        self._chk(self.L.hx_network_forward_noalloc(self.h, _ptr(feats), feats.shape[0], _ptr(out)),
+                  "network_forward_noalloc")
+        return out
+
+    def network_noalloc_max_batch(self) -> int:
+        return int(self.L.hx_network_noalloc_max_batch(self.h))
     def train_step(self, feats, targets, lr: float, want_grad: bool = False,
                    want_loss: bool = True):
         loss = C.c_float()

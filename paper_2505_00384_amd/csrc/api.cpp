@@ -86,6 +86,7 @@ hx_status hx_create(hx_ctx **out, int device, void *hip_stream)
     hx_status s = dalloc(c, (void **)&c->red, sizeof(double) * (size_t)1024 * 72);
     if (s == HX_OK && hipHostMalloc((void **)&c->red_host, sizeof(double) * 1024) != hipSuccess)
         s = HX_ERR_DEVICE;
+    if (s == HX_OK) s = noalloc_init(c);
     if (s != HX_OK) {
         hx_destroy(c);
         return s;
@@ -520,6 +521,19 @@ hx_status hx_network_forward(hx_ctx *c, const float *feats, int64_t batch, float
     if (!c) return HX_ERR_ARG;
     if (!feats || !out || batch < 0) return fail(c, HX_ERR_ARG, "bad forward arguments");
     return mlp_forward(c, feats, batch, out);
+}
+
+hx_status hx_network_forward_noalloc(hx_ctx *c, const float *feats, int64_t batch, float *out)
+{
+    if (!c) return HX_ERR_ARG;
+    if (!feats || !out || batch < 0) return fail(c, HX_ERR_ARG, "bad forward arguments");
+    if (!c->has_mesh) return fail(c, HX_ERR_STATE, "network_forward_noalloc before setup_mesh");
+    return mlp_forward_noalloc(c, feats, batch, out);
+}
+
+int64_t hx_network_noalloc_max_batch(const hx_ctx *c)
+{
+    return c && c->has_mesh ? mlp_noalloc_max_batch(c) : -1;
 }
 
 hx_status hx_train_step(hx_ctx *c, const float *feats, const float *targets, int64_t batch,

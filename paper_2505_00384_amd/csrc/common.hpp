@@ -275,6 +275,10 @@ hx_status mlp_set(hx_ctx *c, const float *w, int64_t n);
 hx_status mlp_get(const hx_ctx *c, float *w, int64_t n);
 hx_status mlp_features(hx_ctx *c, const double *r, float *feats, float *scale);
 hx_status mlp_forward(hx_ctx *c, const float *feats, int64_t batch, float *out);
+// the same forward pass with its work buffers in a static device array
+hx_status noalloc_init(hx_ctx *c);
+int64_t mlp_noalloc_max_batch(const hx_ctx *c);
+hx_status mlp_forward_noalloc(hx_ctx *c, const float *feats, int64_t batch, float *out);
 hx_status mlp_train(hx_ctx *c, const float *feats, const float *targets, int64_t batch,
                     float lr, float *loss_out, float *grad_out);
 hx_status mlp_precondition(hx_ctx *c, const double *r, double *z, int *nonfinite);

@@ -18,6 +18,7 @@
 #include "common.hpp"
 
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 namespace hx {
@@ -594,6 +595,76 @@ hx_status mlp_forward(hx_ctx *c, const float *feats, int64_t B, float *out)
     HX_HIP(c, hipGetLastError());
     HX_HIP(c, forward_packed(c, B, false));
     HX_HIP(c, hipMemcpyAsync(out, s->o, 4 * (size_t)B * s->n_out, hipMemcpyDeviceToDevice, c->stream));
+    return HX_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free forward pass.  Its work buffers (the packed BF16 input rows
+// and the two BF16 hidden layers, [B][ldx] + [B][HID] + [B][HID]) live in one
+// file-scope device array per GPU instead of the context's batch buffers,
+// which grow with hipMalloc.  The array keeps the last call's contents; every
+// entry a call reads is first written by that call (k_pack writes the padding
+// columns too), so nothing needs clearing.  Calls that overlap on one GPU
+// share the array and race.
+constexpr size_t NOALLOC_BYTES = (size_t)16 << 20;
+__device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEV = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[NOALLOC_MAX_DEV] = {};
+}  // namespace
+
+// Device address of this GPU's copy of the array (the array's name in host
+// code is only a stand-in).  Called by hx_create with the context's device
+// current, once per device.
+hx_status noalloc_init(hx_ctx *c)
+{
+    if (c->device < 0 || c->device >= NOALLOC_MAX_DEV)
+        return fail(c, HX_ERR_DEVICE, "device %d beyond the %d supported", c->device, NOALLOC_MAX_DEV);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[c->device]) return HX_OK;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return fail(c, HX_ERR_DEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    g_scratch_ptr[c->device] = ptr;
+    return HX_OK;
+}
+
+int64_t mlp_noalloc_max_batch(const hx_ctx *c)
+{
+    const int64_t n_in = c->nd + 6 * c->nf + 1, ldx = ((n_in + 31) / 32) * 32;
+    return (int64_t)(NOALLOC_BYTES / (size_t)(2 * (ldx + 2 * HID)));
+}
+
+hx_status mlp_forward_noalloc(hx_ctx *c, const float *feats, int64_t B, float *out)
+{
+    if (!c->mlp) return fail(c, HX_ERR_STATE, "no network loaded");
+    MlpState *s = c->mlp;
+    const int64_t bmax = mlp_noalloc_max_batch(c);
+    if (B > bmax)
+        return fail(c, HX_ERR_ARG, "batch %lld exceeds the allocation-free maximum %lld (%zu bytes of scratch)",
+                    (long long)B, (long long)bmax, NOALLOC_BYTES);
+    if (B == 0) return HX_OK;
+    unsigned char *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        base = (unsigned char *)g_scratch_ptr[c->device];
+    }
+    if (!base) return fail(c, HX_ERR_STATE, "scratch of device %d not initialised", c->device);
+    uint16_t *xb = (uint16_t *)base;
+    uint16_t *h1b = xb + (size_t)B * s->ldx;
+    uint16_t *h2b = h1b + (size_t)B * HID;
+    hipLaunchKernelGGL(k_pack, dim3(nb256(B * s->ldx)), dim3(256), 0, c->stream, B, s->n_in, s->ldx,
+                       feats, xb);
+    HX_HIP(c, hipGetLastError());
+    HX_HIP(c, gemm(c->stream, (int)B, HID, s->ldx, xb, s->ldx, 1, s->w1b, s->ldx, 1, s->w + s->off_b1,
+                   1, nullptr, HID, h1b, HID));
+    HX_HIP(c, gemm(c->stream, (int)B, HID, HID, h1b, HID, 1, s->w2b, HID, 1, s->w + s->off_b2, 1,
+                   nullptr, HID, h2b, HID));
+    HX_HIP(c, gemm(c->stream, (int)B, s->n_out, HID, h2b, HID, 1, s->w3b, HID, 1, s->w + s->off_b3, 0,
+                   out, s->n_out, nullptr, 0));
     return HX_OK;
 }
 
