@@ -123,7 +123,9 @@ def time_matvec(ctx, x, y, steps, warmup, torch):
     return e0.elapsed_time(e1) / steps        # ms per application
 
 
-def solve_suite(hx, ctx, b, torch, forms, label):
+def solve_suite(hx, ctx, b, torch, forms, label, keep=None):
+    """Time each solve form; with ``keep`` (a dict) the solutions are kept on
+    the host, by form name, for the oracle comparison of the CPU leg."""
     out = {}
     for name, params in forms:
         x = torch.zeros_like(b)
@@ -132,6 +134,8 @@ def solve_suite(hx, ctx, b, torch, forms, label):
         x, info = ctx.solve(b, x, params)
         torch.cuda.synchronize()
         wall = (time.time() - t0) * 1e3
+        if keep is not None:
+            keep[name] = x.cpu().numpy()
         out[name] = dict(ms=round(wall, 3), iters=info["iters"], inner_iters=info["inner_iters"],
                          true_rel_res=info["true_rel_res"], status=hx.STATUS_NAMES[info["status"]],
                          ms_op=round(info["ms_op"], 3), ms_pc=round(info["ms_pc"], 3),
@@ -345,26 +349,131 @@ def pressure_suite(hx, ctx, torch, label, forms, reps=10, fixed_point=False):
     return out
 
 
-def cpu_baseline(layers: int):
-    """Oracle matvec on the bottom `layers` cell layers of the 256x64x64 terrain
-    channel (same cells, same fields), all host cores."""
-    import oracle
+def _omp_threads(n=None):
+    """Set (n given) or read the OpenMP thread count of the calling thread,
+    which runs the oracle's parallel regions."""
+    import ctypes
+    try:
+        gomp = ctypes.CDLL("libgomp.so.1")
+    except OSError:
+        return None
+    if n is not None:
+        gomp.omp_set_num_threads(int(n))
+    return int(gomp.omp_get_max_threads())
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _terrain_sample(nx, ny, layers):
+    """The first nx x ny columns and bottom `layers` cell layers of the
+    256x64x64 terrain channel (same cell sizes, map and fields)."""
     import synth_inputs as si
     T = si.TERRAIN
-    hz = T["Lz"] / 64
-    m = si.box_mesh(256, 64, layers, lo=(-T["Lx"] / 2, 0.0, 0.0),
-                    hi=(T["Lx"] / 2, T["Ly"], layers * hz), periodic=(True, True, False), g=4,
-                    mapping=si.terrain_mapping)
+    hx_, hy, hz = T["Lx"] / 256, T["Ly"] / 64, T["Lz"] / 64
+    return si.box_mesh(nx, ny, layers, lo=(-T["Lx"] / 2, 0.0, 0.0),
+                       hi=(-T["Lx"] / 2 + nx * hx_, ny * hy, layers * hz),
+                       periodic=(nx == 256, ny == 64, False), g=4, mapping=si.terrain_mapping)
+
+
+def cpu_baseline(layers: int, solutions):
+    """The FP64 oracle on the host cores (a baseline, not a target), and the
+    error of each kept GPU solution against the oracle's solution.
+
+    * value: oracle matvec GDoF/s on the bottom `layers` cell layers of the
+      256x64x64 channel, all cores; the same on a 1,024-cell sample with one
+      thread;
+    * the periodic unit cube (4^3, Q2) and the 32x8x16 channel: oracle
+      matvec, and CG with the separable block to 1e-10 (cube, run to the end)
+      and to 1e-8 (channel: time per iteration measured over 3 iterations,
+      times the 72 iterations the oracle's own solve takes, from the stored
+      reference solve);
+    * err_vs_oracle per kept solution: ||x - x*|| / ||x*|| against a dense
+      solve (cube Q2), the oracle's CG to 1e-13 (cube Q4) or the stored
+      oracle solution of the 32x8x16 channel (1e-13)."""
+    import oracle
+    import synth_inputs as si
+    threads = _omp_threads()
+    rec = dict(unit="GDoF/s", kind="oracle", cpu_model=_cpu_model(),
+               nproc=len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count())
+    # all-core matvec on the large sample
+    m = _terrain_sample(256, 64, layers)
     p = oracle.Problem(m, 4)
     p.set_coefficient_functions(*si.terrain_coefficients())
     x = si.rhs_terrain(0)(*p.dof_coords())
     t0 = time.time()
     p.apply(x)
     dt = time.time() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return dict(value=p.n_dofs / dt / 1e9, unit="GDoF/s", cores=cores, kind="oracle",
-                sample=f"FP64 oracle matvec on the bottom {layers} cell layers of the 256x64x64 "
-                       f"Q4 terrain channel ({m.n_cells} cells, {p.n_dofs} dofs), {dt:.2f} s")
+    rec.update(value=p.n_dofs / dt / 1e9, cores=threads,
+               sample=f"FP64 oracle matvec on the bottom {layers} cell layers of the 256x64x64 "
+                      f"Q4 terrain channel ({m.n_cells} cells, {p.n_dofs} dofs), {dt:.2f} s")
+    # one thread, 1,024 cells of the same channel
+    m1 = _terrain_sample(256, 4, 1)
+    p1 = oracle.Problem(m1, 4)
+    p1.set_coefficient_functions(*si.terrain_coefficients())
+    x1 = si.rhs_terrain(0)(*p1.dof_coords())
+    _omp_threads(1)
+    t0 = time.time()
+    p1.apply(x1)
+    dt1 = time.time() - t0
+    used1 = _omp_threads()
+    _omp_threads(threads)
+    rec["one_thread"] = dict(value=p1.n_dofs / dt1 / 1e9, cores=used1,
+                             sample=f"oracle matvec, {m1.n_cells} cells of the same channel, {dt1:.2f} s")
+    # the periodic unit cube, Q2: matvec and CG to 1e-10
+    errs = {}
+    pc = oracle.Problem(si.cube_mesh(4), 2)
+    pc.set_coefficient_functions(*si.const_coefficients(1.0, 0.01))
+    bc = si.rhs_cube(0)(*pc.dof_coords())
+    t0 = time.time()
+    pc.apply(bc)
+    t_mv = time.time() - t0
+    t0 = time.time()
+    xc, ic = oracle.solvers.cg(pc.apply, bc, precond=pc.bj_apply, rtol=1e-10)
+    t_cg = time.time() - t0
+    rec["cube4_q2"] = {"matvec_ms": round(t_mv * 1e3, 2), "cg_bj_1e-10_ms": round(t_cg * 1e3, 1),
+                        "cg_iters": ic.iters}
+    xd = np.linalg.solve(pc.assemble_dense(), bc)
+    for name, xg in solutions.get("cube4_q2", {}).items():
+        errs.setdefault("cube4_q2", {})[name] = float(np.linalg.norm(xg - xd) / np.linalg.norm(xd))
+    # the periodic unit cube, Q4 (the learned form's mesh)
+    p5 = oracle.Problem(si.cube_mesh(4), 4)
+    p5.set_coefficient_functions(*si.const_coefficients(1.0, 0.01))
+    b5 = si.rhs_cube(101)(*p5.dof_coords())
+    x5, i5 = oracle.solvers.cg(p5.apply, b5, precond=p5.bj_apply, rtol=1e-13)
+    for name, xg in solutions.get("cube4_q4", {}).items():
+        errs.setdefault("cube4_q4", {})[name] = float(np.linalg.norm(xg - x5) / np.linalg.norm(x5))
+    # the 32x8x16 channel: matvec, CG per iteration, stored 1e-13 solution
+    p2 = oracle.Problem(si.terrain_mesh(32, 8, 16, g=4), 4)
+    p2.set_coefficient_functions(*si.terrain_coefficients())
+    b2 = si.rhs_terrain(0)(*p2.dof_coords())
+    t0 = time.time()
+    p2.apply(b2)
+    t_mv2 = time.time() - t0
+    t0 = time.time()
+    oracle.solvers.cg(p2.apply, b2, precond=p2.bj_apply, rtol=1e-30, max_iter=3)
+    t_it = (time.time() - t0) / 3.0
+    ref = os.path.join(ROOT, "tests", "golden", "terrain32x8x16_k4_rhs0_solution")
+    meta = {}
+    for line in open(ref + ".txt"):
+        if not line.startswith("#"):
+            kk, vv = line.split()
+            meta[kk] = float(vv)
+    rec["terrain32x8x16"] = {"matvec_ms": round(t_mv2 * 1e3, 1),
+                             "cg_bj_ms_per_iter": round(t_it * 1e3, 1),
+                             "cg_bj_1e-8_ms_projected": round(t_it * 1e3 * meta["iterations_to_1e-8"], 0),
+                             "oracle_iters_to_1e-8": int(meta["iterations_to_1e-8"])}
+    xs = np.load(ref + ".npy")
+    for name, xg in solutions.get("terrain32x8x16", {}).items():
+        errs.setdefault("terrain32x8x16", {})[name] = float(np.linalg.norm(xg - xs) / np.linalg.norm(xs))
+    return rec, errs
 
 
 def main():
@@ -382,7 +491,7 @@ def main():
     ap.add_argument("--degree", type=int, default=4,
                     help="polynomial degree (default 4, the benchmark's)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-layers", type=int, default=6)
+    ap.add_argument("--cpu-layers", type=int, default=4)
     ap.add_argument("--fp32", action="store_true", help="also time the FP32 operator")
     ap.add_argument("--copy-calibrate", action="store_true",
                     help="also run a plain device copy of the x vector (for counter scaling)")
@@ -431,6 +540,7 @@ def main():
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic)
 
     solve = {}
+    kept = {}      # GPU solutions kept for the oracle comparison
     pressure = {}
     consistent = None
     if not args.no_solve:
@@ -504,7 +614,8 @@ def main():
         del F, T
         forms2.append(("learned_fgmres", hx.default_params(method=1, restart=30, rtol=1e-8,
                                                            pc=hx.HX_PC_LEARNED)))
-        solve["terrain32x8x16"] = solve_suite(hx, ctx2, b2, torch, forms2, "C2")
+        solve["terrain32x8x16"] = solve_suite(hx, ctx2, b2, torch, forms2, "C2",
+                                              keep=kept.setdefault("terrain32x8x16", {}))
         solve["learned_training_s"] = round(t_train, 2)
         w = ctx2.get_network()
         pressure["terrain32x8x16"] = pressure_suite(hx, ctx2, torch, "C2", [
@@ -527,7 +638,8 @@ def main():
         c1.set_coefficients(ones, 0.01 * ones, 2.0)
         b1 = field_on_device(si.rhs_cube(0), x1, torch)
         solve["cube4_q2"] = solve_suite(hx, c1, b1, torch, [
-            ("fp64_cg_bj_1e-10", hx.default_params(method=0, rtol=1e-10))], "C1")
+            ("fp64_cg_bj_1e-10", hx.default_params(method=0, rtol=1e-10))], "C1",
+            keep=kept.setdefault("cube4_q2", {}))
         c1.close()
         c5 = hx.HelmDG(0)
         c5.setup_mesh(4, m1.nodes, m1.nbr, 1)
@@ -539,7 +651,7 @@ def main():
         solve["cube4_q4"] = solve_suite(hx, c5, b5, torch, [
             ("fp64_fgmres_bj", hx.default_params(method=1, restart=30, rtol=1e-8)),
             ("learned_fgmres", hx.default_params(method=1, restart=30, rtol=1e-8, pc=hx.HX_PC_LEARNED))],
-            "C5")
+            "C5", keep=kept.setdefault("cube4_q4", {}))
         c5.close()
     else:
         ctx.close()
@@ -547,7 +659,10 @@ def main():
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle)")
-        cpu = cpu_baseline(args.cpu_layers)
+        cpu, errs = cpu_baseline(args.cpu_layers, kept)
+        for wl, d in errs.items():
+            for name, e in d.items():
+                solve[wl][name]["err_vs_oracle"] = e
         log(f"cpu baseline {cpu}")
 
     rec = {
