@@ -33,9 +33,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 def alg_bytes_per_dof(k: int) -> float:
-    """FP64 bytes per dof one application must move: x and y (16), the merged
+    """FP64 bytes per dof of the general data layout: x and y (16), the merged
     cell data (7 values per Gauss point = per dof, 56) and the merged face data
-    (3 faces x 7 values x (k+1)^2 points per cell, 168/(k+1)); 105.6 at k = 4."""
+    (3 faces x 7 values x (k+1)^2 points per cell, 168/(k+1)); 105.6 at k = 4.
+    The library's own byte model (hx_operator_info) counts interior faces
+    only and the compressed data of affine cells."""
     return 16.0 + 56.0 + 3 * 7 * 8.0 / (k + 1)
 HBM_PEAK_GBS = 8000.0
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "op_apply_f64_terrain256x64x64_k4_traffic.txt")
@@ -109,18 +111,49 @@ def field_on_device(f, xyz, torch):
     return torch.from_numpy(out).to(xyz.device)
 
 
-def time_matvec(ctx, x, y, steps, warmup, torch):
+def time_matvec(ctx, x, y, steps, warmup, torch, part=0):
+    """Event-timed average of `steps` back-to-back applications on the
+    context's stream (torch's current stream), after `warmup` untimed ones."""
+    def launch():
+        if part:
+            ctx.apply_operator_part(part, x, y)
+        else:
+            ctx.apply_operator(x, y)
     for _ in range(warmup):
-        ctx.apply_operator(x, y)
+        launch()
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(steps):
-        ctx.apply_operator(x, y)
+        launch()
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / steps        # ms per application
+
+
+def median_windows(ctx, x, y, torch, windows=5, launches=100, part=0):
+    """Median over `windows` timing windows of `launches` applications each."""
+    t = sorted(time_matvec(ctx, x, y, launches, 2, torch, part) for _ in range(windows))
+    return t[len(t) // 2], t
+
+
+def operator_windows(hx, ctx, x, y, torch, n, op_bytes, counts):
+    """Median of 5 windows of 100 applications, the cell and face parts
+    alone, and the general data layout (compression off) for comparison."""
+    med, wins = median_windows(ctx, x, y, torch)
+    t_cell, _ = median_windows(ctx, x, y, torch, windows=3, launches=50, part=hx.HX_PART_CELL)
+    t_face, _ = median_windows(ctx, x, y, torch, windows=3, launches=50, part=hx.HX_PART_FACE)
+    ctx.set_cell_compression(False)
+    _, gen_bytes = ctx.operator_info(hx.HX_F64)
+    t_gen, _ = median_windows(ctx, x, y, torch, windows=3, launches=50)
+    ctx.set_cell_compression(True)
+    return dict(
+        bytes_per_dof=round(op_bytes / n, 2), counts=counts,
+        median_of_5x100_ms=round(med, 4), windows_ms=[round(v, 4) for v in wins],
+        cell_part_ms=round(t_cell, 4), face_part_ms=round(t_face, 4),
+        general_data_ms=round(t_gen, 4), general_bytes_per_dof=round(gen_bytes / n, 2),
+        general_data_frac=round(gen_bytes / (t_gen * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
 
 
 def solve_suite(hx, ctx, b, torch, forms, label, keep=None):
@@ -493,6 +526,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-layers", type=int, default=4)
     ap.add_argument("--fp32", action="store_true", help="also time the FP32 operator")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="only the timed applications (no extra timing windows), for profilers")
     ap.add_argument("--copy-calibrate", action="store_true",
                     help="also run a plain device copy of the x vector (for counter scaling)")
     args = ap.parse_args()
@@ -519,15 +554,22 @@ def main():
     y = torch.empty_like(x)
     ms = time_matvec(ctx, x, y, args.steps, args.warmup, torch)
     gdofs = n / (ms * 1e-3) / 1e9
-    achieved = alg_bytes_per_dof(k) * n / (ms * 1e-3) / 1e9
-    log(f"FP64 matvec {ms:.4f} ms, {gdofs:.2f} GDoF/s, {achieved:.0f} GB/s algorithmic")
+    counts, op_bytes = ctx.operator_info(hx.HX_F64)
+    achieved = op_bytes / (ms * 1e-3) / 1e9
+    log(f"FP64 matvec {ms:.4f} ms, {gdofs:.2f} GDoF/s, {achieved:.0f} GB/s algorithmic "
+        f"({op_bytes / n:.1f} B/dof; {counts})")
     extra = {}
+    if not args.profile_run:
+        extra["operator"] = operator_windows(hx, ctx, x, y, torch, n, op_bytes, counts)
+        log(f"operator: {extra['operator']}")
     if args.fp32:
         x32 = x.float()
         y32 = torch.empty_like(x32)
         ms32 = time_matvec(ctx, x32, y32, args.steps, args.warmup, torch)
+        _, b32 = ctx.operator_info(hx.HX_F32)
         extra["fp32_matvec"] = dict(ms=round(ms32, 4), gdofs=round(n / (ms32 * 1e-3) / 1e9, 3),
-                                    alg_GBs=round(alg_bytes_per_dof(k) / 2 * n / (ms32 * 1e-3) / 1e9, 1))
+                                    alg_GBs=round(b32 / (ms32 * 1e-3) / 1e9, 1),
+                                    frac=round(b32 / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
         log(f"FP32 matvec {ms32:.4f} ms")
         del x32, y32
     if args.copy_calibrate:

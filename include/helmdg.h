@@ -88,7 +88,8 @@ const char *hx_last_error(const hx_ctx *c);
 int hx_max_degree(void);
 
 /* ---------------------------------------------------------------------- */
-/* setup (geometry: step a1)                                               */
+/* setup: geometry of the mapped hexahedra (section 2, the DG space on the  */
+/* mesh; section 3.3, J = detJ x quadrature weight at the Gauss points)    */
 /* ---------------------------------------------------------------------- */
 
 /* Upload a conforming hexahedral mesh and compute its geometry data.
@@ -115,7 +116,8 @@ hx_status hx_dof_coordinates(hx_ctx *c, double *xyz);
 int64_t hx_num_dofs(const hx_ctx *c);
 
 /* ---------------------------------------------------------------------- */
-/* coefficients (step a2)                                                  */
+/* coefficients (section 3.1: the entries of S~, rebuilt each fixed-point */
+/* iteration from the previous pressure)                                  */
 /* ---------------------------------------------------------------------- */
 
 /* Set the mass coefficient alpha and the stiffness coefficient beta (the
@@ -129,7 +131,8 @@ hx_status hx_set_coefficients(hx_ctx *c, const double *alpha, const double *beta
                               double penalty_factor, int on_device);
 
 /* ---------------------------------------------------------------------- */
-/* operator (steps a3, a4, a7)                                             */
+/* operator action (section 2: the Helmholtz-type equation for the       */
+/* pressure; section 3.1: matrix-free evaluation)                          */
 /* ---------------------------------------------------------------------- */
 
 /* y = A x (y overwritten).  prec selects FP64 (double*) or FP32 (float*)
@@ -140,8 +143,33 @@ hx_status hx_apply_operator(hx_ctx *c, hx_prec prec, const void *x, void *y);
 /* r = b - A x in FP64.  r must not alias b or x. */
 hx_status hx_residual(hx_ctx *c, const double *b, const double *x, double *r);
 
+/* One part of y = A x (y overwritten): HX_PART_CELL the cell integrals
+ * (mass and stiffness volume terms), HX_PART_FACE the interior-penalty face
+ * terms; their sum is hx_apply_operator.  For measurement and checks. */
+#define HX_PART_CELL 1
+#define HX_PART_FACE 2
+hx_status hx_apply_operator_part(hx_ctx *c, hx_prec prec, int part, const void *x, void *y);
+
+/* Affine cells (geometry nodes an affine image of the reference nodes, to
+ * 1e-14 of the cell size) have a constant Jacobian; the operator then reads
+ * J^-1 J^-T once per cell and alpha w detJ, beta w detJ at the points (2
+ * values per point instead of 7), and on faces between two affine cells
+ * beta- w, beta+ w per point plus 7 constants per face (instead of 7 values
+ * per point).  on = 1 (the default after hx_setup_mesh) uses this compressed
+ * data; on = 0 makes every cell and face read the general data.  The results
+ * agree to rounding. */
+hx_status hx_set_cell_compression(hx_ctx *c, int on);
+
+/* Counts of the mesh as the operator sees it, counts[4] (HOST, may be NULL)
+ * = {cells, affine cells, interior faces, interior faces between two affine
+ * cells}, and *bytes (HOST, may be NULL) = the bytes one application in the
+ * precision prec must move at the least: x and y, and each cell's and each
+ * interior face's data once, compressed where it applies. */
+hx_status hx_operator_info(const hx_ctx *c, int prec, int64_t *counts, double *bytes);
+
 /* ---------------------------------------------------------------------- */
-/* preconditioners (steps a5, a9)                                          */
+/* preconditioners (section 3.1: the Helmholtz and internal-energy        */
+/* diagonals; section 3.3: tensor-product inverses of cell blocks)        */
 /* ---------------------------------------------------------------------- */
 
 /* z = M^{-1} r.  HX_PC_BLOCK_JACOBI: inverse of the separable approximation
@@ -169,7 +197,8 @@ hx_status hx_apply_preconditioner(hx_ctx *c, hx_pc kind, hx_prec prec,
                                   const void *r, void *z);
 
 /* ---------------------------------------------------------------------- */
-/* solve (steps a6, a8)                                                    */
+/* solve (section 3.1: preconditioned CG for the SPD systems, GMRES with  */
+/* a Jacobi-type preconditioner for the pressure system)                  */
 /* ---------------------------------------------------------------------- */
 
 typedef struct {
@@ -364,14 +393,15 @@ hx_status hx_solve_pressure_fixed_point(hx_ctx *c, const double *rho, const doub
                                         double *fp_change, hx_solve_info *info);
 
 /* ---------------------------------------------------------------------- */
-/* BLAS-1 helpers on the context stream (step a6), FP64 device vectors      */
+/* BLAS-1 helpers on the context stream (Krylov scalars), FP64 vectors    */
 /* ---------------------------------------------------------------------- */
 
 /* *out (HOST) = x . y, deterministic two-stage reduction. */
 hx_status hx_dot(hx_ctx *c, int64_t n, const double *x, const double *y, double *out);
 
 /* ---------------------------------------------------------------------- */
-/* learned preconditioner (steps a9, a10)                                  */
+/* learned preconditioner (not in the paper: a per-cell network added to  */
+/* block Jacobi inside flexible GMRES)                                    */
 /* ---------------------------------------------------------------------- */
 
 /* Network: n_in = (k+1)^3 + 6 (k+1)^2 + 1 -> 256 -> 256 -> (k+1)^3, ReLU,

@@ -26,6 +26,7 @@ HX_F64, HX_F32 = 0, 1
 HX_EXPORT_CELL_DATA, HX_EXPORT_FACE_DATA, HX_EXPORT_SIGMA, HX_EXPORT_VOLUME, \
     HX_EXPORT_BJ_SCALARS, HX_EXPORT_INV_DIAG = range(6)
 HX_PS_GRAD, HX_PS_DIV, HX_PS_VMASS_INV, HX_PS_DMASS, HX_PS_SYSTEM = range(5)
+HX_PART_CELL, HX_PART_FACE = 1, 2
 
 STATUS_NAMES = {0: "HX_OK", 1: "HX_ERR_ARG", 2: "HX_ERR_STATE", 3: "HX_ERR_DEVICE",
                 4: "HX_ERR_OOM", 5: "HX_ERR_MESH", 6: "HX_ERR_NOCONV",
@@ -78,6 +79,9 @@ def load(path: str = LIB_PATH):
         "hx_set_coefficients": ([vp, vp, vp, C.c_double, C.c_int], C.c_int),
         "hx_apply_operator": ([vp, C.c_int, vp, vp], C.c_int),
         "hx_residual": ([vp, vp, vp, vp], C.c_int),
+        "hx_apply_operator_part": ([vp, C.c_int, C.c_int, vp, vp], C.c_int),
+        "hx_set_cell_compression": ([vp, C.c_int], C.c_int),
+        "hx_operator_info": ([vp, C.c_int, vp, vp], C.c_int),
         "hx_apply_preconditioner": ([vp, C.c_int, C.c_int, vp, vp], C.c_int),
         "hx_default_params": ([C.POINTER(SolveParams)], None),
         "hx_solve": ([vp, C.POINTER(SolveParams), vp, vp, C.POINTER(SolveInfo)], C.c_int),
@@ -308,6 +312,27 @@ class HelmDG:
             y = self.torch.empty_like(x)
         self._chk(self.L.hx_apply_operator(self.h, prec, _ptr(x), _ptr(y)), "apply_operator")
         return y
+
+    def apply_operator_part(self, part: int, x, y=None):
+        """One part of A x: HX_PART_CELL (cell integrals) or HX_PART_FACE
+        (face terms)."""
+        prec = HX_F64 if x.dtype == self.torch.float64 else HX_F32
+        if y is None:
+            y = self.torch.empty_like(x)
+        self._chk(self.L.hx_apply_operator_part(self.h, prec, int(part), _ptr(x), _ptr(y)),
+                  "apply_operator_part")
+        return y
+
+    def set_cell_compression(self, on: bool):
+        self._chk(self.L.hx_set_cell_compression(self.h, int(bool(on))), "set_cell_compression")
+
+    def operator_info(self, prec: int = HX_F64):
+        """(counts dict, algorithmic bytes of one application)."""
+        counts = (C.c_int64 * 4)()
+        b = C.c_double()
+        self._chk(self.L.hx_operator_info(self.h, int(prec), counts, C.byref(b)), "operator_info")
+        keys = ("cells", "affine_cells", "interior_faces", "affine_faces")
+        return dict(zip(keys, [int(v) for v in counts])), float(b.value)
 
     def residual(self, b, x, r=None):
         if r is None:

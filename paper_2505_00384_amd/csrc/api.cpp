@@ -52,13 +52,61 @@ static void free_mesh(hx_ctx *c)
                      (void **)&c->psMd, (void **)&c->psFn, (void **)&c->psFh, (void **)&c->psWork,
                      (void **)&c->refq, (void **)&c->qcell, (void **)&c->qface, (void **)&c->chebw,
                      (void **)&c->mg_cptr, (void **)&c->mg_clist, (void **)&c->mgw,
-                     (void **)&c->mgw32, (void **)&c->chebw32};
+                     (void **)&c->mgw32, (void **)&c->chebw32, (void **)&c->ctype,
+                     (void **)&c->acell64, (void **)&c->acell32, (void **)&c->kk64,
+                     (void **)&c->kk32, (void **)&c->aface64, (void **)&c->aface32,
+                     (void **)&c->fc64, (void **)&c->fc32};
     for (void **b : bufs) dfree(b);
+    delete c->order_h;
+    delete c->nbr_h;
+    delete c->ctype_h;
+    c->order_h = nullptr;
+    c->nbr_h = nullptr;
+    c->ctype_h = nullptr;
+    c->n_vis[0] = c->n_vis[1] = 0;
+    c->n_affine = c->n_iface = c->n_cface = 0;
     c->work64_len = c->work32_len = 0;
     c->has_mesh = c->has_coef = c->has_press = c->has_q = false;
     c->cheb_deg = 0;
     c->mg_coarse = nullptr;
     c->mg_nc = 0;
+}
+
+// Traversal records {cell, neighbours -x, +x, -y, +y, -z, +z, mask} in the
+// traversal order.  With the compression on, the general cells come first and
+// the affine cells after them (each group in the traversal order), so that the
+// operator runs one specialised launch per group; the mask (last word) of an
+// affine cell has bit 1 + f set if face f (-x, +x, -y, +y, -z, +z) lies
+// between two affine cells and is read compressed.  With the compression off
+// there is one group of general cells and every mask is zero.
+static hx_status update_visit_masks(hx_ctx *c)
+{
+    const std::vector<int32_t> &order = *c->order_h, &nb = *c->nbr_h;
+    const std::vector<uint8_t> &ct = *c->ctype_h;
+    const size_t nc = (size_t)c->n_cells;
+    std::vector<int32_t> v(nc * 8);
+    size_t o = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        for (size_t i = 0; i < nc; ++i) {
+            const int32_t cell = order[i];
+            const int aff = c->compress && ct[cell];
+            if (aff != pass) continue;
+            int32_t mask = aff;
+            for (int f = 0; f < 6; ++f) {
+                const int32_t n2 = nb[6 * (size_t)cell + f];
+                v[8 * o + 1 + f] = n2;
+                if (aff && n2 >= 0 && ct[n2]) mask |= 2 << f;
+            }
+            v[8 * o] = cell;
+            v[8 * o + 7] = mask;
+            ++o;
+        }
+        c->n_vis[pass] = (int64_t)o - (pass ? c->n_vis[0] : 0);
+    }
+    HX_HIP(c, hipMemcpyAsync(c->visit, v.data(), sizeof(int32_t) * nc * 8, hipMemcpyHostToDevice,
+                             c->stream));
+    HX_HIP(c, hipStreamSynchronize(c->stream));
+    return HX_OK;
 }
 
 }  // namespace hx
@@ -177,6 +225,15 @@ hx_status hx_setup_mesh(hx_ctx *c, int degree, int64_t n_cells, int geo_degree,
     ALLOC(c->bjC64, sizeof(double) * nc * 4);
     ALLOC(c->bjC32, sizeof(float) * nc * 4);
     ALLOC(c->coef_feat, sizeof(double) * nc);
+    ALLOC(c->ctype, nc);
+    ALLOC(c->acell64, sizeof(double) * nc * 2 * c->nd);
+    ALLOC(c->acell32, sizeof(float) * nc * 2 * c->nd);
+    ALLOC(c->kk64, sizeof(double) * nc * 8);
+    ALLOC(c->kk32, sizeof(float) * nc * 8);
+    ALLOC(c->aface64, sizeof(double) * nc * 3 * 2 * c->nf);
+    ALLOC(c->aface32, sizeof(float) * nc * 3 * 2 * c->nf);
+    ALLOC(c->fc64, sizeof(double) * nc * 3 * 8);
+    ALLOC(c->fc32, sizeof(float) * nc * 3 * 8);
 #undef ALLOC
     if (s != HX_OK) {
         free_mesh(c);
@@ -186,20 +243,9 @@ hx_status hx_setup_mesh(hx_ctx *c, int degree, int64_t n_cells, int geo_degree,
                              hipMemcpyHostToDevice, c->stream));
     HX_HIP(c, hipMemcpyAsync(c->nbr, nb32.data(), sizeof(int32_t) * nc * 6, hipMemcpyHostToDevice,
                              c->stream));
-    {
-        // traversal records of the operator kernel: {cell, neighbours, 0}
-        std::vector<int32_t> order(nc), visit(nc * 8);
-        build_traversal(nb32.data(), n_cells, order.data());
-        for (size_t o = 0; o < nc; ++o) {
-            const int32_t cell = order[o];
-            visit[8 * o] = cell;
-            for (int f = 0; f < 6; ++f) visit[8 * o + 1 + f] = nb32[6 * (size_t)cell + f];
-            visit[8 * o + 7] = 0;
-        }
-        HX_HIP(c, hipMemcpyAsync(c->visit, visit.data(), sizeof(int32_t) * nc * 8,
-                                 hipMemcpyHostToDevice, c->stream));
-        HX_HIP(c, hipStreamSynchronize(c->stream));
-    }
+    c->order_h = new std::vector<int32_t>(nc);
+    build_traversal(nb32.data(), n_cells, c->order_h->data());
+    c->nbr_h = new std::vector<int32_t>(nb32);
     HX_HIP(c, hipMemcpyAsync(c->ref, &c->ref_host, sizeof(RefTab64), hipMemcpyHostToDevice,
                              c->stream));
     HX_HIP(c, launch_cell_geometry(c));
@@ -215,8 +261,57 @@ hx_status hx_setup_mesh(hx_ctx *c, int degree, int64_t n_cells, int geo_degree,
     HX_HIP(c, launch_face_sigma(c));
     HX_HIP(c, launch_bj_eigen(c));
     HX_HIP(c, launch_geofac(c));
+    HX_HIP(c, launch_affine_detect(c));
+    c->ctype_h = new std::vector<uint8_t>(nc);
+    HX_HIP(c, hipMemcpyAsync(c->ctype_h->data(), c->ctype, nc, hipMemcpyDeviceToHost, c->stream));
     HX_HIP(c, hipStreamSynchronize(c->stream));
+    {
+        const std::vector<uint8_t> &ct = *c->ctype_h;
+        for (size_t i = 0; i < nc; ++i) {
+            c->n_affine += ct[i];
+            for (int d = 0; d < 3; ++d) {
+                const int32_t nb = nb32[6 * i + 2 * d + 1];
+                if (nb < 0) continue;
+                ++c->n_iface;
+                if (ct[i] && ct[nb]) ++c->n_cface;
+            }
+        }
+    }
+    hx_status sm = update_visit_masks(c);
+    if (sm != HX_OK) return sm;
     c->has_mesh = true;
+    return HX_OK;
+}
+
+hx_status hx_set_cell_compression(hx_ctx *c, int on)
+{
+    if (!c) return HX_ERR_ARG;
+    if (!c->has_mesh) return fail(c, HX_ERR_STATE, "set_cell_compression before setup_mesh");
+    c->compress = on ? 1 : 0;
+    return update_visit_masks(c);
+}
+
+hx_status hx_operator_info(const hx_ctx *cc, int prec, int64_t *counts, double *bytes)
+{
+    if (!cc) return HX_ERR_ARG;
+    hx_ctx *c = const_cast<hx_ctx *>(cc);
+    if (!c->has_mesh) return fail(c, HX_ERR_STATE, "no mesh");
+    if (prec != HX_F64 && prec != HX_F32) return fail(c, HX_ERR_ARG, "bad precision %d", prec);
+    if (counts) {
+        counts[0] = c->n_cells;
+        counts[1] = c->n_affine;
+        counts[2] = c->n_iface;
+        counts[3] = c->n_cface;
+    }
+    if (bytes) {
+        const double T = prec == HX_F64 ? 8.0 : 4.0;
+        const double na = c->compress ? (double)c->n_affine : 0.0;
+        const double nfc = c->compress ? (double)c->n_cface : 0.0;
+        const double nd = c->nd, nf = c->nf;
+        *bytes = T * (2.0 * (double)c->n_dofs + ((double)c->n_cells - na) * 7.0 * nd +
+                      na * (2.0 * nd + 6.0) + ((double)c->n_iface - nfc) * 7.0 * nf +
+                      nfc * (2.0 * nf + 7.0));
+    }
     return HX_OK;
 }
 
@@ -418,6 +513,21 @@ hx_status hx_residual(hx_ctx *c, const double *b, const double *x, double *r)
     if (!b || !x || !r) return fail(c, HX_ERR_ARG, "null vector");
     if (x == r || b == r) return fail(c, HX_ERR_ARG, "r aliases x or b");
     HX_HIP(c, launch_apply64(c, x, r, b));
+    return HX_OK;
+}
+
+hx_status hx_apply_operator_part(hx_ctx *c, hx_prec prec, int part, const void *x, void *y)
+{
+    if (!c) return HX_ERR_ARG;
+    if (!c->has_coef) return fail(c, HX_ERR_STATE, "apply before set_coefficients");
+    if (!x || !y) return fail(c, HX_ERR_ARG, "null vector");
+    if (part != HX_PART_CELL && part != HX_PART_FACE) return fail(c, HX_ERR_ARG, "bad part %d", part);
+    if (prec == HX_F64)
+        HX_HIP(c, launch_apply_part64(c, part, (const double *)x, (double *)y));
+    else if (prec == HX_F32)
+        HX_HIP(c, launch_apply_part32(c, part, (const float *)x, (float *)y));
+    else
+        return fail(c, HX_ERR_ARG, "bad precision %d", (int)prec);
     return HX_OK;
 }
 

@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <vector>
 
 #include "../../include/helmdg.h"
 
@@ -79,6 +80,26 @@ struct hx_ctx {
     double *facegeo = nullptr;    // [n_cells][3][7][nf] geometric factors of the face data
     double *face64 = nullptr;     // [n_cells][3][7][N (1st tangential)][N (2nd)]
     float *face32 = nullptr;
+    // compressed data of affine cells (one Jacobian per cell): the operator
+    // reads these instead of cell64/face64 for affine cells and for faces
+    // between two affine cells (bits of the traversal record's last word)
+    int compress = 1;             // 1: use the compressed data where it applies
+    int64_t n_affine = 0;         // affine cells
+    int64_t n_iface = 0;          // interior faces (each once)
+    int64_t n_cface = 0;          // interior faces between two affine cells
+    uint8_t *ctype = nullptr;     // [n_cells] 1 = affine
+    std::vector<int32_t> *order_h = nullptr;   // host: the traversal order of all cells
+    std::vector<int32_t> *nbr_h = nullptr;     // host copy of the neighbour table
+    int64_t n_vis[2] = {0, 0};    // records of general cells, then of affine cells, in visit
+    std::vector<uint8_t> *ctype_h = nullptr;   // host copy of ctype
+    double *acell64 = nullptr;    // [n_cells][2][nd]  alpha w detJ, beta w detJ (affine cells)
+    float *acell32 = nullptr;
+    double *kk64 = nullptr;       // [n_cells][8]      J^-1 J^-T (6 unique entries), detJ, 0
+    float *kk32 = nullptr;
+    double *aface64 = nullptr;    // [n_cells][3][2][nf] beta- w, beta+ w on the +d face (affine pair)
+    float *aface32 = nullptr;
+    double *fc64 = nullptr;       // [n_cells][3][8]   v- (3), v+ (3), sigma ds0 / 2, 0 of the +d face
+    float *fc32 = nullptr;
     double *dg64 = nullptr;       // [2][n_dofs] inverse volume diagonals: mass + stiffness, mass
     float *dg32 = nullptr;
     double *cgpart = nullptr;     // [2][n_cells + 1] per-block partial sums of the fused CG steps
@@ -159,6 +180,9 @@ hipError_t launch_bj_eigen(hx_ctx *c);                      // bjS, bjL
 hipError_t launch_set_coefficients(hx_ctx *c, const double *alpha, const double *beta);
 hipError_t launch_dof_coords(hx_ctx *c, double *xyz);
 hipError_t launch_geofac(hx_ctx *c);
+// affine cells (geometry nodes an affine image of the reference nodes) and
+// their per-cell constants J^-1 J^-T, detJ
+hipError_t launch_affine_detect(hx_ctx *c);
 hipError_t launch_cell_diag(hx_ctx *c);
 hipError_t launch_diag64(hx_ctx *c, int which, const double *r, double *z);
 hipError_t launch_diag32(hx_ctx *c, int which, const float *r, float *z);
@@ -216,6 +240,9 @@ hipError_t launch_cg_massinv32(hx_ctx *c, float *x, float *r, const float *p, co
 // operator: y = A x, or y = b - A x when b != nullptr
 hipError_t launch_apply64(hx_ctx *c, const double *x, double *y, const double *b);
 hipError_t launch_apply32(hx_ctx *c, const float *x, float *y, const float *b);
+// one part of A x: part 1 the cell integrals only, part 2 the face terms only
+hipError_t launch_apply_part64(hx_ctx *c, int part, const double *x, double *y);
+hipError_t launch_apply_part32(hx_ctx *c, int part, const float *x, float *y);
 // y = A x and dst = x.(A x) in FP64 (CG's p.q), summed in a fixed order
 hipError_t launch_apply64_dot(hx_ctx *c, const double *x, double *y, double *dst);
 hipError_t launch_apply32_dot(hx_ctx *c, const float *x, float *y, double *dst);

@@ -349,6 +349,59 @@ __global__ void k_face_geofac(const double *__restrict__ nodes, int ng, int n, i
 }
 
 // -------------------------------------------------------------------------
+// Affine cells (thread per cell): the geometry nodes are the image of the
+// reference nodes under x0 + A xi, A from the three edges at the first corner,
+// to 1e-14 of the longest edge.  Their Jacobian is constant, so the operator
+// may read one J^-1 J^-T per cell and the coefficients at the points instead
+// of the seven merged values per point.  The per-cell constants are taken
+// from the general geometric factors of the first Gauss point:
+// kk = (w detJ J^-1 J^-T) / (w detJ), and detJ.
+// -------------------------------------------------------------------------
+__global__ void k_affine_detect(const double *__restrict__ nodes, int ng, int nd, int64_t n_cells,
+                                const RefTab64 *__restrict__ T, const double *__restrict__ cellgeo,
+                                uint8_t *ctype, double *kk64, float *kk32)
+{
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= n_cells) return;
+    const double *X = nodes + c * (int64_t)ng * ng * ng * 3;
+    const int g = ng - 1;
+    const int corner[3] = {g, g * ng, g * ng * ng};
+    double A[3][3], diam = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        double s = 0.0;
+        for (int r = 0; r < 3; ++r) {
+            A[r][d] = X[3 * corner[d] + r] - X[r];
+            s += A[r][d] * A[r][d];
+        }
+        diam = fmax(diam, sqrt(s));
+    }
+    double dev = 0.0;
+    for (int az = 0; az < ng; ++az)
+        for (int ay = 0; ay < ng; ++ay)
+            for (int ax = 0; ax < ng; ++ax) {
+                const double xi[3] = {(double)ax / g, (double)ay / g, (double)az / g};
+                const double *P = X + 3 * (ax + ng * (ay + ng * az));
+                for (int r = 0; r < 3; ++r) {
+                    const double pr = X[r] + A[r][0] * xi[0] + A[r][1] * xi[1] + A[r][2] * xi[2];
+                    dev = fmax(dev, fabs(P[r] - pr));
+                }
+            }
+    ctype[c] = dev <= 1e-14 * diam ? 1 : 0;
+    const double *geo = cellgeo + c * 7 * nd;
+    const double w0 = geo[0];
+    for (int s = 0; s < 6; ++s) {
+        const double v = geo[(1 + s) * nd] / w0;
+        kk64[8 * c + s] = v;
+        kk32[8 * c + s] = (float)v;
+    }
+    const double det = w0 / (T->wq[0] * T->wq[0] * T->wq[0]);
+    kk64[8 * c + 6] = det;
+    kk32[8 * c + 6] = (float)det;
+    kk64[8 * c + 7] = 0.0;
+    kk32[8 * c + 7] = 0.0f;
+}
+
+// -------------------------------------------------------------------------
 // merged cell data from the coefficients (block per cell, thread per point):
 //   m = alpha_q w detJ,  G = beta_q w detJ J^-1 J^-T  (alpha_q, beta_q: the
 // nodal fields at the Gauss point), plus the cell means of the separable
@@ -357,7 +410,8 @@ __global__ void k_face_geofac(const double *__restrict__ nodes, int ng, int n, i
 __global__ void k_set_cell(int n, const RefTab64 *__restrict__ T, const double *__restrict__ alpha,
                            const double *__restrict__ beta, const double *__restrict__ ell,
                            const double *__restrict__ cellgeo, double *cell64, float *cell32,
-                           double *bjC64, float *bjC32, double *coef_feat)
+                           double *bjC64, float *bjC32, double *coef_feat,
+                           const uint8_t *__restrict__ ctype, double *acell64, float *acell32)
 {
     const int64_t c = blockIdx.x;
     const int nd = n * n * n;
@@ -387,6 +441,14 @@ __global__ void k_set_cell(int n, const RefTab64 *__restrict__ T, const double *
             const double v = bq * g[s * nd];
             dst[s * nd] = v;
             dstf[s * nd] = (float)v;
+        }
+        if (ctype[c]) {
+            // affine cell: alpha w detJ and beta w detJ (G = beta w detJ J^-1 J^-T)
+            const double am = aq * w, bm = bq * w;
+            acell64[c * 2 * nd + q] = am;
+            acell64[c * 2 * nd + nd + q] = bm;
+            acell32[c * 2 * nd + q] = (float)am;
+            acell32[c * 2 * nd + nd + q] = (float)bm;
         }
         sw = w;
         sa = w * aq;
@@ -428,7 +490,8 @@ __global__ void k_set_cell(int n, const RefTab64 *__restrict__ T, const double *
 __global__ void k_set_face(int n, int64_t n_cells, const int32_t *__restrict__ nbr,
                            const RefTab64 *__restrict__ T, const double *__restrict__ beta,
                            const double *__restrict__ sigma, const double *__restrict__ facegeo,
-                           double *face64, float *face32)
+                           double *face64, float *face32, const uint8_t *__restrict__ ctype,
+                           double *aface64, float *aface32, double *fc64, float *fc32)
 {
     const int nf = n * n, nd = nf * n;
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -465,6 +528,26 @@ __global__ void k_set_face(int n, int64_t n_cells, const int32_t *__restrict__ n
     for (int s = 0; s < 7; ++s) {
         dst[s * nf] = out[s];
         dstf[s * nf] = (float)out[s];
+    }
+    if (ctype[c] && ctype[nb]) {
+        // face between two affine cells: g- = (beta- w) v-, g+ = (beta+ w) v+,
+        // s = sd ((beta- w) + (beta+ w)) with w the face weight, v = ds0 J^-1 n
+        // and sd = sigma ds0 / 2 constant over the face (ds = w ds0)
+        const double wab = T->wq[a] * T->wq[b];
+        aface64[cd * 2 * nf + pt] = bm * wab;
+        aface64[cd * 2 * nf + nf + pt] = bp * wab;
+        aface32[cd * 2 * nf + pt] = (float)(bm * wab);
+        aface32[cd * 2 * nf + nf + pt] = (float)(bp * wab);
+        if (pt == 0) {
+            double v[8];
+            for (int k = 0; k < 6; ++k) v[k] = g[k * nf] / wab;
+            v[6] = sigma[3 * c + d] * g[6 * nf] / wab;
+            v[7] = 0.0;
+            for (int k = 0; k < 8; ++k) {
+                fc64[cd * 8 + k] = v[k];
+                fc32[cd * 8 + k] = (float)v[k];
+            }
+        }
     }
 }
 
@@ -540,18 +623,26 @@ hipError_t launch_geofac(hx_ctx *c)
     return hipGetLastError();
 }
 
+hipError_t launch_affine_detect(hx_ctx *c)
+{
+    hipLaunchKernelGGL(k_affine_detect, dim3(nblk(c->n_cells, 128)), dim3(128), 0, c->stream, c->nodes,
+                       c->g + 1, c->nd, c->n_cells, c->ref, c->cellgeo, c->ctype, c->kk64, c->kk32);
+    return hipGetLastError();
+}
+
 hipError_t launch_set_coefficients(hx_ctx *c, const double *alpha, const double *beta)
 {
     int threads = 64;                     // power of two for the tree reduction
     while (threads < c->nd) threads *= 2;
     hipLaunchKernelGGL(k_set_cell, dim3((unsigned)c->n_cells), dim3(threads), 0, c->stream, c->n,
                        c->ref, alpha, beta, c->ell, c->cellgeo, c->cell64, c->cell32, c->bjC64,
-                       c->bjC32, c->coef_feat);
+                       c->bjC32, c->coef_feat, c->ctype, c->acell64, c->acell32);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t nt = 3 * c->n_cells * c->nf;
     hipLaunchKernelGGL(k_set_face, dim3(nblk(nt, 128)), dim3(128), 0, c->stream, c->n, c->n_cells,
-                       c->nbr, c->ref, beta, c->sigma, c->facegeo, c->face64, c->face32);
+                       c->nbr, c->ref, beta, c->sigma, c->facegeo, c->face64, c->face32, c->ctype,
+                       c->aface64, c->aface32, c->fc64, c->fc32);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_cell_diag(c);

@@ -30,6 +30,14 @@
 //  * cell data [cell][7][N^3] is streamed once with non-temporal loads; x and
 //    the face data [cell][3][7][N][N] are read by neighbours too and stay
 //    cacheable.
+//  * affine cells (constant Jacobian) read compressed data instead: alpha w
+//    detJ and beta w detJ at the points [cell][2][N^3] plus J^-1 J^-T once per
+//    cell, and faces between two affine cells read beta- w, beta+ w per point
+//    [cell][3][2][N][N] plus seven constants per face; the last word of the
+//    traversal record says which cell and faces are compressed (one bit each),
+//    so no extra round trip decides it.  The merged values are rebuilt in
+//    registers where they are used (m = a, G = b J^-1 J^-T; g = (beta w) v,
+//    s = sd ((beta- w) + (beta+ w))).
 //  * cells are visited in the order of a host-built permutation (one 32-byte
 //    record per slot holds the cell and its six neighbours): tiles of
 //    columns swept layer by layer, in one contiguous range per XCD, so the
@@ -179,6 +187,11 @@ template <int N, typename T>
 struct Occ {
     static constexpr int W = sizeof(T) == 8 ? (N <= 3 ? 4 : (N <= 4 ? 3 : 2))
                                             : (N <= 4 ? 4 : (N <= 6 ? 3 : 2));
+    // the launch of affine cells keeps fewer values in registers (2 instead
+    // of 7 per point), so it fits one more wave per SIMD without spilling
+    // (measured at N = 5 FP64: 2.98 -> 2.83 ms for the whole operator on the
+    // 256x64x64 channel, 45 % of its cells affine)
+    static constexpr int WA = sizeof(T) == 8 ? (N <= 3 ? 4 : (N <= 5 ? 3 : 2)) : (N <= 7 ? 4 : 3);
     // request the quadrature-point data before the y sweep (register cost 7 N)
     static constexpr bool PREFETCH_CELL = N <= 5;
 };
@@ -189,12 +202,18 @@ __device__ __forceinline__ T ld_stream(const T *p)
     return __builtin_nontemporal_load(p);
 }
 
-template <int N, typename T, bool DOT>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(Occ<N, T>::W, Occ<N, T>::W)))
+// PART: 0 the whole operator, 1 the cell integrals only, 2 the face terms only;
+// AFF: the launch serves affine cells (compressed cell data; faces compressed
+// where the record's mask says so) or general cells (general data only)
+template <int N, typename T, bool DOT, int PART, bool AFF>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(AFF ? Occ<N, T>::WA : Occ<N, T>::W,
+                                                                         AFF ? Occ<N, T>::WA : Occ<N, T>::W)))
 k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
-        const T *__restrict__ cell, const T *__restrict__ face, const int32_t *__restrict__ visit,
-        int n_cells, int nwg, double *__restrict__ dpart)
+        const T *__restrict__ cell, const T *__restrict__ face, const T *__restrict__ acell,
+        const T *__restrict__ kk, const T *__restrict__ aface, const T *__restrict__ fcon,
+        const int32_t *__restrict__ visit, int n_cells, int nwg, double *__restrict__ dpart)
 {
+    constexpr bool DO_CELL = PART != 2, DO_FACE = PART != 1;
     constexpr int NF = Cfg<N>::NF, ND = Cfg<N>::ND, LPC = Cfg<N>::LPC, CPW = Cfg<N>::CPW,
                   GS = Cfg<N>::GS;
     __shared__ T sU[CPW][ND];
@@ -215,6 +234,9 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
     // line gives every index this wave needs
     const int32_t *rec = visit + (int64_t)(valid ? slot : 0) * 8;
     const int64_t cid = valid ? rec[0] : 0;
+    // bit 1 + f of the record's last word: face f is read compressed
+    const int32_t cmask = (AFF && valid) ? rec[7] : 0;
+    constexpr bool caff = AFF;
     T *G = &sG[cs][0];
     T *U = &sU[cs][0];
 
@@ -225,8 +247,9 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
     const bool fl0 = valid && ln < 6 * N;
     const int f = fl0 ? ln / N : 0, rr = ln % N;
     const int d = f >> 1, s = f & 1;
-    const int32_t nb = fl0 ? rec[1 + f] : -1;
+    const int32_t nb = (DO_FACE && fl0) ? rec[1 + f] : -1;
     const bool fl = nb >= 0;
+    const bool fcmp = AFF && ((cmask >> (1 + f)) & 1);
     // strides of the normal index m, the column index p and the row index r
     // of the face's direction in a cell's lexicographic numbering
     const int sm = d == 0 ? 1 : (d == 1 ? N : NF);
@@ -270,8 +293,15 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
         if (valid && e < ND) U[e] = xv[k];
     }
 
-    // quadrature-point data of this lane's z pencil, streamed once
-    const T *cp = cell + cid * 7 * ND + a + N * b;
+    // quadrature-point data of this lane's z pencil, streamed once: the
+    // seven merged values, or for an affine cell alpha w detJ and beta w detJ
+    // (in cdat[0] and cdat[1]) and J^-1 J^-T of the cell
+    const T *cp = caff ? acell + cid * 2 * ND + a + N * b : cell + cid * 7 * ND + a + N * b;
+    T kq[6];
+    if (DO_CELL && cl && caff) {
+#pragma unroll
+        for (int s2 = 0; s2 < 6; ++s2) kq[s2] = kk[cid * 8 + s2];
+    }
     __syncthreads();
 
     T Y[N];
@@ -279,6 +309,11 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
     // x sweep: lane (j=a, l=b): B u and BD u along x; the lane's own input
     // pencil is kept when the caller wants x.(A x)
     T xp[N];
+    if constexpr (!DO_CELL) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) Y[i] = T(0);
+    }
+    if constexpr (DO_CELL) {
     if (cl) {
         T r[N], s0[N], s1[N];
 #pragma unroll
@@ -299,11 +334,18 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
     // quadrature-point data, requested before the y sweep so that the
     // stream is in flight while it runs
     T cdat[7][N];
-    if (Occ<N, T>::PREFETCH_CELL && cl) {
+    if (DO_CELL && Occ<N, T>::PREFETCH_CELL && cl) {
+        if (caff) {
 #pragma unroll
-        for (int q = 0; q < N; ++q)
+            for (int q = 0; q < N; ++q)
 #pragma unroll
-            for (int k = 0; k < 7; ++k) cdat[k][q] = ld_stream(cp + NF * q + k * ND);
+                for (int k = 0; k < 2; ++k) cdat[k][q] = ld_stream(cp + NF * q + k * ND);
+        } else {
+#pragma unroll
+            for (int q = 0; q < N; ++q)
+#pragma unroll
+                for (int k = 0; k < 7; ++k) cdat[k][q] = ld_stream(cp + NF * q + k * ND);
+        }
     }
     // y sweep: lane (qx=a, l=b)
     {
@@ -355,9 +397,21 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
             for (int q = 0; q < N; ++q) {
                 const T u = uq[q], dz = dzq[q], dy = dyq[q], dx = dxq[q];
                 T cq[7];
+                if (Occ<N, T>::PREFETCH_CELL) {
 #pragma unroll
-                for (int k = 0; k < 7; ++k)
-                    cq[k] = Occ<N, T>::PREFETCH_CELL ? cdat[k][q] : ld_stream(cp + NF * q + k * ND);
+                    for (int k = 0; k < 7; ++k) cq[k] = cdat[k][q];
+                } else if (caff) {
+#pragma unroll
+                    for (int k = 0; k < 2; ++k) cq[k] = ld_stream(cp + NF * q + k * ND);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 7; ++k) cq[k] = ld_stream(cp + NF * q + k * ND);
+                }
+                if (caff) {
+                    const T bw = cq[1];
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) cq[1 + k] = bw * kq[k];
+                }
                 const T m = cq[0], gxx = cq[1], gxy = cq[2], gxz = cq[3], gyy = cq[4], gyz = cq[5],
                         gzz = cq[6];
                 vq[q] = m * u;
@@ -415,8 +469,10 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
         contract_t2<T, N>(p0, p1, Y);
     }
     __syncthreads();
+    }   // DO_CELL
 
     // =========================================================== face part
+    if constexpr (DO_FACE) {
     // The work area of a face holds three N x N fields at a time, laid out
     // [field][q2 or r][p].  Layer values and normal derivatives of a side are
     // interpolated along the second tangential direction by the column lanes
@@ -448,17 +504,32 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
     const int gn_off = s ? 3 : 0, go_off = s ? 0 : 3;
 
     // face data of this row, all requested at once: g of the neighbour side,
-    // g of the own side and the penalty factor at the row's N points
-    T gnb[3][N], gow[3][N], pn[N];
+    // g of the own side and the penalty factor at the row's N points; on a
+    // compressed face beta w of the neighbour side (in gnb[0]) and of the own
+    // side (in gow[0]) and the face's constants v-, v+, sd (in fcv)
+    T gnb[3][N], gow[3][N], pn[N], fcv[7];
     if (fl) {
+        if (fcmp) {
+            const T *af = aface + (fid * 3 + d) * 2 * NF + rr;
+            const int bn_off = s ? NF : 0, bo_off = s ? 0 : NF;
 #pragma unroll
-        for (int q1 = 0; q1 < N; ++q1) {
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                gnb[k][q1] = fd[(gn_off + k) * NF + N * q1];
-                gow[k][q1] = fd[(go_off + k) * NF + N * q1];
+            for (int q1 = 0; q1 < N; ++q1) {
+                gnb[0][q1] = af[bn_off + N * q1];
+                gow[0][q1] = af[bo_off + N * q1];
             }
-            pn[q1] = fd[6 * NF + N * q1];
+            const T *fp = fcon + (fid * 3 + d) * 8;
+#pragma unroll
+            for (int k = 0; k < 7; ++k) fcv[k] = fp[k];
+        } else {
+#pragma unroll
+            for (int q1 = 0; q1 < N; ++q1) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    gnb[k][q1] = fd[(gn_off + k) * NF + N * q1];
+                    gow[k][q1] = fd[(go_off + k) * NF + N * q1];
+                }
+                pn[q1] = fd[6 * NF + N * q1];
+            }
         }
     }
     if (fl) interp_t2(Ln, Nn);
@@ -481,9 +552,17 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
             contract<T, N, 0, false>(EvenOdd<T, N>(h1), t2n);
             contract<T, N, 0, false>(EvenOdd<T, N>(h2), dnn);
         }
+        if (fcmp) {
+            // v of the neighbour side: v+ if the own cell is the minus cell
+            const T v0 = s ? fcv[3] : fcv[0], v1 = s ? fcv[4] : fcv[1], v2 = s ? fcv[5] : fcv[2];
 #pragma unroll
-        for (int q1 = 0; q1 < N; ++q1)
-            fnb[q1] = gnb[0][q1] * dnn[q1] + gnb[1][q1] * t1n[q1] + gnb[2][q1] * t2n[q1];
+            for (int q1 = 0; q1 < N; ++q1)
+                fnb[q1] = gnb[0][q1] * (v0 * dnn[q1] + v1 * t1n[q1] + v2 * t2n[q1]);
+        } else {
+#pragma unroll
+            for (int q1 = 0; q1 < N; ++q1)
+                fnb[q1] = gnb[0][q1] * dnn[q1] + gnb[1][q1] * t1n[q1] + gnb[2][q1] * t2n[q1];
+        }
     }
     __syncthreads();
     // step 1, own side, lane (f, p): layer and normal derivative from the
@@ -529,11 +608,29 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
             contract<T, N, 0, false>(EvenOdd<T, N>(h2), dnq);
         }
         T cvq[N], ct1q[N], ct2q[N], cnq[N];
+        // v of the own side (compressed face)
+        T w0 = T(0), w1 = T(0), w2 = T(0);
+        if (fcmp) {
+            w0 = s ? fcv[0] : fcv[3];
+            w1 = s ? fcv[1] : fcv[4];
+            w2 = s ? fcv[2] : fcv[5];
+        }
 #pragma unroll
         for (int q1 = 0; q1 < N; ++q1) {
             const T vo = voq[q1], t1o = t1q[q1], t2o = t2q[q1], dno = dnq[q1];
-            const T g0 = gow[0][q1], g1 = gow[1][q1], g2 = gow[2][q1];
-            const T pen = pn[q1];
+            T g0, g1, g2, pen;
+            if (fcmp) {
+                const T bo = gow[0][q1];
+                g0 = bo * w0;
+                g1 = bo * w1;
+                g2 = bo * w2;
+                pen = fcv[6] * (bo + gnb[0][q1]);
+            } else {
+                g0 = gow[0][q1];
+                g1 = gow[1][q1];
+                g2 = gow[2][q1];
+                pen = pn[q1];
+            }
             const T flux = g0 * dno + g1 * t1o + g2 * t2o + fnb[q1];
             const T jump = s ? (vo - vnb[q1]) : (vnb[q1] - vo);
             const T sg = s ? T(1) : T(-1);
@@ -581,8 +678,10 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
         }
     }
     __syncthreads();
+    }   // DO_FACE
     // pencil owners (j=a, l=b) add the six faces' contributions
     if (cl) {
+        if constexpr (DO_FACE) {
 #pragma unroll
         for (int i = 0; i < N; ++i) Y[i] = sU[cs][i + N * a + NF * b];
         const T *F = G;
@@ -619,6 +718,7 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
 #pragma unroll
             for (int i = 0; i < N; ++i) Y[i] += e1 * F1[i] + (on ? F0[i] : T(0));
         }
+        }   // DO_FACE
         const int64_t o = cid * ND + N * a + NF * b;
 #pragma unroll
         for (int i = 0; i < N; ++i) y[o + i] = bvec ? bvec[o + i] - Y[i] : Y[i];
@@ -637,34 +737,57 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
 }
 
 template <int N, typename T>
-hipError_t apply_n(hx_ctx *c, const T *x, T *y, const T *b, double *dpart, int *nwg_out)
+hipError_t apply_n(hx_ctx *c, const T *x, T *y, const T *b, double *dpart, int *nwg_out, int part)
 {
     const int cpw = Cfg<N>::CPW;
-    const int nwg = (int)((c->n_cells + cpw - 1) / cpw);
-    const T *cell = std::is_same<T, double>::value ? (const T *)c->cell64 : (const T *)c->cell32;
-    const T *face = std::is_same<T, double>::value ? (const T *)c->face64 : (const T *)c->face32;
-    if (nwg_out) *nwg_out = nwg;
-    if (dpart)
-        hipLaunchKernelGGL((k_apply<N, T, true>), dim3(nwg), dim3(64), 0, c->stream, x, y, b, cell,
-                           face, c->visit, (int)c->n_cells, nwg, dpart);
-    else
-        hipLaunchKernelGGL((k_apply<N, T, false>), dim3(nwg), dim3(64), 0, c->stream, x, y, b, cell,
-                           face, c->visit, (int)c->n_cells, nwg, dpart);
+    constexpr bool F64 = std::is_same<T, double>::value;
+    const T *cell = F64 ? (const T *)c->cell64 : (const T *)c->cell32;
+    const T *face = F64 ? (const T *)c->face64 : (const T *)c->face32;
+    const T *acell = F64 ? (const T *)c->acell64 : (const T *)c->acell32;
+    const T *kk = F64 ? (const T *)c->kk64 : (const T *)c->kk32;
+    const T *aface = F64 ? (const T *)c->aface64 : (const T *)c->aface32;
+    const T *fcon = F64 ? (const T *)c->fc64 : (const T *)c->fc32;
+    // one launch per group of records: general cells, then affine cells
+    int nwg_all = 0;
+    for (int grp = 0; grp < 2; ++grp) {
+        const int64_t nrec = c->n_vis[grp];
+        if (nrec == 0) continue;
+        const int nwg = (int)((nrec + cpw - 1) / cpw);
+        const int32_t *vis = c->visit + 8 * (grp ? c->n_vis[0] : 0);
+        double *dp = dpart ? dpart + nwg_all : nullptr;
+#define HX_APPLY(DOT, PART, AFF)                                                                 \
+    hipLaunchKernelGGL((k_apply<N, T, DOT, PART, AFF>), dim3(nwg), dim3(64), 0, c->stream, x, y, b,  \
+                       cell, face, acell, kk, aface, fcon, vis, (int)nrec, nwg, dp)
+        if (grp == 0) {
+            if (dpart) HX_APPLY(true, 0, false);
+            else if (part == 1) HX_APPLY(false, 1, false);
+            else if (part == 2) HX_APPLY(false, 2, false);
+            else HX_APPLY(false, 0, false);
+        } else {
+            if (dpart) HX_APPLY(true, 0, true);
+            else if (part == 1) HX_APPLY(false, 1, true);
+            else if (part == 2) HX_APPLY(false, 2, true);
+            else HX_APPLY(false, 0, true);
+        }
+#undef HX_APPLY
+        nwg_all += nwg;
+    }
+    if (nwg_out) *nwg_out = nwg_all;
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t apply_dispatch(hx_ctx *c, const T *x, T *y, const T *b, double *dpart = nullptr,
-                          int *nwg = nullptr)
+                          int *nwg = nullptr, int part = 0)
 {
     switch (c->n) {
-    case 2: return apply_n<2, T>(c, x, y, b, dpart, nwg);
-    case 3: return apply_n<3, T>(c, x, y, b, dpart, nwg);
-    case 4: return apply_n<4, T>(c, x, y, b, dpart, nwg);
-    case 5: return apply_n<5, T>(c, x, y, b, dpart, nwg);
-    case 6: return apply_n<6, T>(c, x, y, b, dpart, nwg);
-    case 7: return apply_n<7, T>(c, x, y, b, dpart, nwg);
-    case 8: return apply_n<8, T>(c, x, y, b, dpart, nwg);
+    case 2: return apply_n<2, T>(c, x, y, b, dpart, nwg, part);
+    case 3: return apply_n<3, T>(c, x, y, b, dpart, nwg, part);
+    case 4: return apply_n<4, T>(c, x, y, b, dpart, nwg, part);
+    case 5: return apply_n<5, T>(c, x, y, b, dpart, nwg, part);
+    case 6: return apply_n<6, T>(c, x, y, b, dpart, nwg, part);
+    case 7: return apply_n<7, T>(c, x, y, b, dpart, nwg, part);
+    case 8: return apply_n<8, T>(c, x, y, b, dpart, nwg, part);
     default: return hipErrorInvalidValue;
     }
 }
@@ -679,6 +802,16 @@ hipError_t launch_apply64(hx_ctx *c, const double *x, double *y, const double *b
 hipError_t launch_apply32(hx_ctx *c, const float *x, float *y, const float *b)
 {
     return apply_dispatch<float>(c, x, y, b);
+}
+
+hipError_t launch_apply_part64(hx_ctx *c, int part, const double *x, double *y)
+{
+    return apply_dispatch<double>(c, x, y, nullptr, nullptr, nullptr, part);
+}
+
+hipError_t launch_apply_part32(hx_ctx *c, int part, const float *x, float *y)
+{
+    return apply_dispatch<float>(c, x, y, nullptr, nullptr, nullptr, part);
 }
 
 // y = A x and dst = x.y (summed in a fixed order)

@@ -191,3 +191,72 @@ def test_block_jacobi_terrain_and_fp32():
     z32 = ctx.apply_preconditioner(to_dev(r, torch.float32)).double().cpu().numpy()
     assert normwise(z32, zr)[0] <= 1e-5
     ctx.close()
+
+
+@pytest.mark.parametrize("k", [1, 2, 4])
+def test_operator_parts_match_oracle(k):
+    """The cell integrals alone and the face terms alone against the oracle's
+    cell-only and face-only forms; their sum is the operator."""
+    import paper_2505_00384_amd as hx
+    for name, mk in TINY[:4] + [("terrain-8x2x4-g4", lambda: si.terrain_mesh(8, 2, 4, g=4))]:
+        m = mk()
+        print(f"[parts] k={k} mesh={name}", flush=True)
+        p = problem(m, k, coef="terrain" if name.startswith("terrain") else "random", seed=k)
+        ctx = gpu_context(p)
+        x = si.random_vector(p.n_dofs, 300 + k)
+        xd = to_dev(x)
+        yc = ctx.apply_operator_part(hx.HX_PART_CELL, xd).cpu().numpy()
+        _check(yc, p.apply(x, oracle.OR_CELL))
+        if m.n_cells > 1 or (m.nbr >= 0).any():
+            yf = ctx.apply_operator_part(hx.HX_PART_FACE, xd).cpu().numpy()
+            rf = p.apply(x, oracle.OR_FACE)
+            if np.abs(rf).max() > 0:
+                _check(yf, rf)
+            y = ctx.apply_operator(xd).cpu().numpy()
+            assert np.linalg.norm(yc + yf - y) <= 1e-13 * np.linalg.norm(y)
+        ctx.close()
+
+
+def test_affine_compression_on_a_mixed_mesh():
+    """The terrain channel has affine cells (far from the ridge) and curved
+    ones: the compressed data of the affine cells and of the faces between
+    two of them give the same operator as the general data, and both match
+    the oracle; the counts and the byte model follow the mesh."""
+    import paper_2505_00384_amd as hx
+    import torch
+    p = problem(si.terrain_mesh(16, 4, 8, g=4), 4, coef="terrain")
+    ctx = gpu_context(p)
+    counts, bytes_c = ctx.operator_info()
+    print(f"[affine] {counts}", flush=True)
+    assert 0 < counts["affine_cells"] < counts["cells"]
+    assert 0 < counts["affine_faces"] < counts["interior_faces"]
+    # x periodic, y periodic, z walls: 3 faces per cell minus the top layer
+    assert counts["interior_faces"] == 3 * 16 * 4 * 8 - 16 * 4
+    x = si.random_vector(p.n_dofs, 7)
+    xd = to_dev(x)
+    ref = p.apply(x)
+    y1 = ctx.apply_operator(xd).cpu().numpy()
+    y32 = ctx.apply_operator(xd.float()).cpu().numpy()
+    ctx.set_cell_compression(False)
+    _, bytes_g = ctx.operator_info()
+    y0 = ctx.apply_operator(xd).cpu().numpy()
+    y32g = ctx.apply_operator(xd.float()).cpu().numpy()
+    ctx.set_cell_compression(True)
+    _check(y1, ref)
+    _check(y0, ref)
+    assert np.linalg.norm(y1 - y0) <= 1e-13 * np.linalg.norm(y0)
+    assert np.linalg.norm(y32 - y32g) <= 2e-6 * np.linalg.norm(y32g)
+    assert np.linalg.norm(y32 - ref) <= 2e-6 * np.linalg.norm(ref)
+    # general byte model: x, y, 7 values per point, 7 per face point per interior face
+    n = p.n_dofs
+    assert bytes_g == 8 * (2 * n + 7 * n + 7 * 25 * counts["interior_faces"])
+    na, nfc = counts["affine_cells"], counts["affine_faces"]
+    assert bytes_c == 8 * (2 * n + 7 * 125 * (counts["cells"] - na) + (2 * 125 + 6) * na
+                           + 7 * 25 * (counts["interior_faces"] - nfc) + (2 * 25 + 7) * nfc)
+    # the CG variant with x.(A x) sees the same operator
+    b = to_dev(si.rhs_terrain(2)(*p.dof_coords()))
+    xs, info = ctx.solve(b, params=hx.default_params(method=0, rtol=1e-10))
+    assert info["status"] == hx.HX_OK
+    r = si.rhs_terrain(2)(*p.dof_coords()) - p.apply(xs.cpu().numpy())
+    assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(si.rhs_terrain(2)(*p.dof_coords()))
+    ctx.close()
