@@ -41,7 +41,7 @@ void dfree(void **p)
 
 static void free_mesh(hx_ctx *c)
 {
-    void **bufs[] = {(void **)&c->nodes, (void **)&c->nbr, (void **)&c->visit, (void **)&c->ref, (void **)&c->vol,
+    void **bufs[] = {(void **)&c->nodes, (void **)&c->nbr, (void **)&c->visit, (void **)&c->visitp, (void **)&c->ref, (void **)&c->vol,
                      (void **)&c->ell, (void **)&c->mindet, (void **)&c->sigma,
                      (void **)&c->cell64, (void **)&c->cell32, (void **)&c->face64,
                      (void **)&c->face32, (void **)&c->cellgeo, (void **)&c->facegeo, (void **)&c->dg64, (void **)&c->dg32, (void **)&c->cgpart,
@@ -63,7 +63,8 @@ static void free_mesh(hx_ctx *c)
     c->order_h = nullptr;
     c->nbr_h = nullptr;
     c->ctype_h = nullptr;
-    c->n_vis[0] = c->n_vis[1] = 0;
+    c->n_vis_op = 0;
+    c->vis_mode = 0;
     c->n_affine = c->n_iface = c->n_cface = 0;
     c->work64_len = c->work32_len = 0;
     c->has_mesh = c->has_coef = c->has_press = c->has_q = false;
@@ -72,38 +73,54 @@ static void free_mesh(hx_ctx *c)
     c->mg_nc = 0;
 }
 
-// Traversal records {cell, neighbours -x, +x, -y, +y, -z, +z, mask} in the
-// traversal order.  With the compression on, the general cells come first and
-// the affine cells after them (each group in the traversal order), so that the
-// operator runs one specialised launch per group; the mask (last word) of an
-// affine cell has bit 1 + f set if face f (-x, +x, -y, +y, -z, +z) lies
-// between two affine cells and is read compressed.  With the compression off
-// there is one group of general cells and every mask is zero.
+// Traversal records {cell, neighbours -x, +x, -y, +y, -z, +z, mask}.
+// visitp: every cell once in the traversal order, mask 0 (kernels that read
+// no compressed data).  visit (the operator): with the compression on and
+// both kinds of cells present, the general cells and the affine cells form
+// two groups, each in the traversal order and padded with records of cell -1
+// to whole waves; the waves of the two groups are interleaved in proportion
+// (so both groups advance together and every CU runs both kinds), and every
+// wave's records are of one kind.  Mask bit 0: affine cell (also set on the
+// padding of the affine group); bit 1 + f: face f (-x, +x, -y, +y, -z, +z)
+// lies between two affine cells and is read compressed.
 static hx_status update_visit_masks(hx_ctx *c)
 {
     const std::vector<int32_t> &order = *c->order_h, &nb = *c->nbr_h;
     const std::vector<uint8_t> &ct = *c->ctype_h;
     const size_t nc = (size_t)c->n_cells;
-    std::vector<int32_t> v(nc * 8);
-    size_t o = 0;
-    for (int pass = 0; pass < 2; ++pass) {
-        for (size_t i = 0; i < nc; ++i) {
-            const int32_t cell = order[i];
-            const int aff = c->compress && ct[cell];
-            if (aff != pass) continue;
-            int32_t mask = aff;
-            for (int f = 0; f < 6; ++f) {
-                const int32_t n2 = nb[6 * (size_t)cell + f];
-                v[8 * o + 1 + f] = n2;
-                if (aff && n2 >= 0 && ct[n2]) mask |= 2 << f;
-            }
-            v[8 * o] = cell;
-            v[8 * o + 7] = mask;
-            ++o;
+    const int cpw = op_cells_per_wave(c->n);
+    auto record = [&](int32_t *r, int32_t cell, int aff) {
+        int32_t mask = aff;
+        for (int f = 0; f < 6; ++f) {
+            const int32_t n2 = cell >= 0 ? nb[6 * (size_t)cell + f] : -1;
+            r[1 + f] = n2;
+            if (aff && cell >= 0 && n2 >= 0 && ct[n2]) mask |= 2 << f;
         }
-        c->n_vis[pass] = (int64_t)o - (pass ? c->n_vis[0] : 0);
+        r[0] = cell;
+        r[7] = mask;
+    };
+    std::vector<int32_t> plain(nc * 8);
+    for (size_t i = 0; i < nc; ++i) record(&plain[8 * i], order[i], 0);
+    // the two groups, padded to whole waves
+    std::vector<int32_t> grp[2];
+    for (size_t i = 0; i < nc; ++i) grp[c->compress && ct[order[i]] ? 1 : 0].push_back(order[i]);
+    for (auto &g : grp)
+        while (g.size() % cpw) g.push_back(-1);
+    const size_t w0 = grp[0].size() / cpw, w1 = grp[1].size() / cpw;
+    c->vis_mode = (w0 && w1) ? 2 : (w1 ? 1 : 0);
+    std::vector<int32_t> v((w0 + w1) * cpw * 8);
+    size_t t0 = 0, t1 = 0, o = 0;
+    while (t0 < w0 || t1 < w1) {
+        // next wave from the group that is behind in proportion
+        const int g = (t1 < w1 && (t0 >= w0 || t1 * w0 <= t0 * w1)) ? 1 : 0;
+        size_t &t = g ? t1 : t0;
+        for (int k = 0; k < cpw; ++k, ++o) record(&v[8 * o], grp[g][t * cpw + k], g);
+        ++t;
     }
-    HX_HIP(c, hipMemcpyAsync(c->visit, v.data(), sizeof(int32_t) * nc * 8, hipMemcpyHostToDevice,
+    c->n_vis_op = (int64_t)o;
+    HX_HIP(c, hipMemcpyAsync(c->visit, v.data(), sizeof(int32_t) * v.size(), hipMemcpyHostToDevice,
+                             c->stream));
+    HX_HIP(c, hipMemcpyAsync(c->visitp, plain.data(), sizeof(int32_t) * nc * 8, hipMemcpyHostToDevice,
                              c->stream));
     HX_HIP(c, hipStreamSynchronize(c->stream));
     return HX_OK;
@@ -203,7 +220,8 @@ hx_status hx_setup_mesh(hx_ctx *c, int degree, int64_t n_cells, int geo_degree,
     if (s == HX_OK) s = dalloc(c, (void **)&(ptr), (bytes));
     ALLOC(c->nodes, sizeof(double) * nc * ng3 * 3);
     ALLOC(c->nbr, sizeof(int32_t) * nc * 6);
-    ALLOC(c->visit, sizeof(int32_t) * nc * 8);
+    ALLOC(c->visit, sizeof(int32_t) * (nc + 2 * 64) * 8);
+    ALLOC(c->visitp, sizeof(int32_t) * nc * 8);
     ALLOC(c->ref, sizeof(RefTab64));
     ALLOC(c->vol, sizeof(double) * nc);
     ALLOC(c->ell, sizeof(double) * nc * 3);

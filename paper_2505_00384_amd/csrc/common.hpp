@@ -90,7 +90,9 @@ struct hx_ctx {
     uint8_t *ctype = nullptr;     // [n_cells] 1 = affine
     std::vector<int32_t> *order_h = nullptr;   // host: the traversal order of all cells
     std::vector<int32_t> *nbr_h = nullptr;     // host copy of the neighbour table
-    int64_t n_vis[2] = {0, 0};    // records of general cells, then of affine cells, in visit
+    int64_t n_vis_op = 0;         // records in visit (with padding)
+    int vis_mode = 0;             // 0 general cells only, 1 affine only, 2 both, interleaved by wave
+    int32_t *visitp = nullptr;    // [n_cells][8] plain traversal records (no padding, mask 0)
     std::vector<uint8_t> *ctype_h = nullptr;   // host copy of ctype
     double *acell64 = nullptr;    // [n_cells][2][nd]  alpha w detJ, beta w detJ (affine cells)
     float *acell32 = nullptr;
@@ -240,6 +242,8 @@ hipError_t launch_cg_massinv32(hx_ctx *c, float *x, float *r, const float *p, co
 // operator: y = A x, or y = b - A x when b != nullptr
 hipError_t launch_apply64(hx_ctx *c, const double *x, double *y, const double *b);
 hipError_t launch_apply32(hx_ctx *c, const float *x, float *y, const float *b);
+// cells per wave of the operator kernel at n points per direction
+int op_cells_per_wave(int n);
 // one part of A x: part 1 the cell integrals only, part 2 the face terms only
 hipError_t launch_apply_part64(hx_ctx *c, int part, const double *x, double *y);
 hipError_t launch_apply_part32(hx_ctx *c, int part, const float *x, float *y);

@@ -203,37 +203,30 @@ __device__ __forceinline__ T ld_stream(const T *p)
 }
 
 // PART: 0 the whole operator, 1 the cell integrals only, 2 the face terms only;
-// AFF: the launch serves affine cells (compressed cell data; faces compressed
+// AFF: the wave serves affine cells (compressed cell data; faces compressed
 // where the record's mask says so) or general cells (general data only)
 template <int N, typename T, bool DOT, int PART, bool AFF>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(AFF ? Occ<N, T>::WA : Occ<N, T>::W,
-                                                                         AFF ? Occ<N, T>::WA : Occ<N, T>::W)))
-k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
-        const T *__restrict__ cell, const T *__restrict__ face, const T *__restrict__ acell,
-        const T *__restrict__ kk, const T *__restrict__ aface, const T *__restrict__ fcon,
-        const int32_t *__restrict__ visit, int n_cells, int nwg, double *__restrict__ dpart)
+__device__ __forceinline__ void apply_body(
+    const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
+    const T *__restrict__ cell, const T *__restrict__ face, const T *__restrict__ acell,
+    const T *__restrict__ kk, const T *__restrict__ aface, const T *__restrict__ fcon,
+    const int32_t *__restrict__ visit, int n_cells, int wg, int bid, double *__restrict__ dpart,
+    T (&sU)[Cfg<N>::CPW][Cfg<N>::ND], T (&sG)[Cfg<N>::CPW][Cfg<N>::GS])
 {
     constexpr bool DO_CELL = PART != 2, DO_FACE = PART != 1;
-    constexpr int NF = Cfg<N>::NF, ND = Cfg<N>::ND, LPC = Cfg<N>::LPC, CPW = Cfg<N>::CPW,
-                  GS = Cfg<N>::GS;
-    __shared__ T sU[CPW][ND];
-    __shared__ T sG[CPW][GS];
-
-    // contiguous ranges of the traversal per XCD (workgroups are dealt
-    // round-robin to the XCDs)
-    const int bid = blockIdx.x;
-    const int q8 = nwg / NXCD, r8 = nwg % NXCD, xcd = bid % NXCD;
-    const int wg = xcd * q8 + (xcd < r8 ? xcd : r8) + bid / NXCD;
+    constexpr int NF = Cfg<N>::NF, ND = Cfg<N>::ND, LPC = Cfg<N>::LPC, CPW = Cfg<N>::CPW;
 
     const int lane = threadIdx.x;
     const int cs = lane / LPC;             // cell slot in the wave
     const int ln = lane - cs * LPC;        // lane within the cell
     const int slot = wg * CPW + cs;
-    const bool valid = slot < n_cells;
-    // the slot's record {cell, neighbours -x,+x,-y,+y,-z,+z}: one 32-byte
-    // line gives every index this wave needs
-    const int32_t *rec = visit + (int64_t)(valid ? slot : 0) * 8;
-    const int64_t cid = valid ? rec[0] : 0;
+    // the slot's record {cell, neighbours -x,+x,-y,+y,-z,+z, mask}: one
+    // 32-byte line gives every index this wave needs; a record whose cell is
+    // -1 pads a group of records to whole waves
+    const int32_t *rec = visit + (int64_t)(slot < n_cells ? slot : 0) * 8;
+    const int32_t rc = rec[0];
+    const bool valid = slot < n_cells && rc >= 0;
+    const int64_t cid = valid ? rc : 0;
     // bit 1 + f of the record's last word: face f is read compressed
     const int32_t cmask = (AFF && valid) ? rec[7] : 0;
     constexpr bool caff = AFF;
@@ -736,6 +729,41 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
     }
 }
 
+// MODE 0: every record is a general cell; 1: every record an affine cell;
+// 2: both kinds, each wave's records of one kind (groups padded to whole
+// waves and interleaved), the first record's mask telling which, so that
+// memory-bound waves of general cells and arithmetic-bound waves of affine
+// cells share every CU
+template <int N, typename T, bool DOT, int PART, int MODE>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MODE ? Occ<N, T>::WA : Occ<N, T>::W,
+                                                                         MODE ? Occ<N, T>::WA : Occ<N, T>::W)))
+k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
+        const T *__restrict__ cell, const T *__restrict__ face, const T *__restrict__ acell,
+        const T *__restrict__ kk, const T *__restrict__ aface, const T *__restrict__ fcon,
+        const int32_t *__restrict__ visit, int n_cells, int nwg, double *__restrict__ dpart)
+{
+    constexpr int ND = Cfg<N>::ND, CPW = Cfg<N>::CPW, GS = Cfg<N>::GS;
+    __shared__ T sU[CPW][ND];
+    __shared__ T sG[CPW][GS];
+    // contiguous ranges of the traversal per XCD (workgroups are dealt
+    // round-robin to the XCDs)
+    const int bid = blockIdx.x;
+    const int q8 = nwg / NXCD, r8 = nwg % NXCD, xcd = bid % NXCD;
+    const int wg = xcd * q8 + (xcd < r8 ? xcd : r8) + bid / NXCD;
+    if constexpr (MODE == 2) {
+        const bool waff = visit[(int64_t)wg * CPW * 8 + 7] & 1;
+        if (waff)
+            apply_body<N, T, DOT, PART, true>(x, y, bvec, cell, face, acell, kk, aface, fcon, visit,
+                                              n_cells, wg, bid, dpart, sU, sG);
+        else
+            apply_body<N, T, DOT, PART, false>(x, y, bvec, cell, face, acell, kk, aface, fcon, visit,
+                                               n_cells, wg, bid, dpart, sU, sG);
+    } else {
+        apply_body<N, T, DOT, PART, MODE == 1>(x, y, bvec, cell, face, acell, kk, aface, fcon, visit,
+                                               n_cells, wg, bid, dpart, sU, sG);
+    }
+}
+
 template <int N, typename T>
 hipError_t apply_n(hx_ctx *c, const T *x, T *y, const T *b, double *dpart, int *nwg_out, int part)
 {
@@ -747,32 +775,26 @@ hipError_t apply_n(hx_ctx *c, const T *x, T *y, const T *b, double *dpart, int *
     const T *kk = F64 ? (const T *)c->kk64 : (const T *)c->kk32;
     const T *aface = F64 ? (const T *)c->aface64 : (const T *)c->aface32;
     const T *fcon = F64 ? (const T *)c->fc64 : (const T *)c->fc32;
-    // one launch per group of records: general cells, then affine cells
-    int nwg_all = 0;
-    for (int grp = 0; grp < 2; ++grp) {
-        const int64_t nrec = c->n_vis[grp];
-        if (nrec == 0) continue;
-        const int nwg = (int)((nrec + cpw - 1) / cpw);
-        const int32_t *vis = c->visit + 8 * (grp ? c->n_vis[0] : 0);
-        double *dp = dpart ? dpart + nwg_all : nullptr;
-#define HX_APPLY(DOT, PART, AFF)                                                                 \
-    hipLaunchKernelGGL((k_apply<N, T, DOT, PART, AFF>), dim3(nwg), dim3(64), 0, c->stream, x, y, b,  \
-                       cell, face, acell, kk, aface, fcon, vis, (int)nrec, nwg, dp)
-        if (grp == 0) {
-            if (dpart) HX_APPLY(true, 0, false);
-            else if (part == 1) HX_APPLY(false, 1, false);
-            else if (part == 2) HX_APPLY(false, 2, false);
-            else HX_APPLY(false, 0, false);
-        } else {
-            if (dpart) HX_APPLY(true, 0, true);
-            else if (part == 1) HX_APPLY(false, 1, true);
-            else if (part == 2) HX_APPLY(false, 2, true);
-            else HX_APPLY(false, 0, true);
-        }
-#undef HX_APPLY
-        nwg_all += nwg;
+    const int64_t nrec = c->n_vis_op;
+    const int nwg = (int)((nrec + cpw - 1) / cpw);
+    if (nwg_out) *nwg_out = nwg;
+#define HX_APPLY(DOT, PART, MODE)                                                                \
+    hipLaunchKernelGGL((k_apply<N, T, DOT, PART, MODE>), dim3(nwg), dim3(64), 0, c->stream, x, y, b, \
+                       cell, face, acell, kk, aface, fcon, c->visit, (int)nrec, nwg, dpart)
+#define HX_APPLY_MODE(MODE)                       \
+    if (dpart) HX_APPLY(true, 0, MODE);          \
+    else if (part == 1) HX_APPLY(false, 1, MODE); \
+    else if (part == 2) HX_APPLY(false, 2, MODE); \
+    else HX_APPLY(false, 0, MODE)
+    if (c->vis_mode == 2) {
+        HX_APPLY_MODE(2);
+    } else if (c->vis_mode == 1) {
+        HX_APPLY_MODE(1);
+    } else {
+        HX_APPLY_MODE(0);
     }
-    if (nwg_out) *nwg_out = nwg_all;
+#undef HX_APPLY_MODE
+#undef HX_APPLY
     return hipGetLastError();
 }
 
@@ -812,6 +834,20 @@ hipError_t launch_apply_part64(hx_ctx *c, int part, const double *x, double *y)
 hipError_t launch_apply_part32(hx_ctx *c, int part, const float *x, float *y)
 {
     return apply_dispatch<float>(c, x, y, nullptr, nullptr, nullptr, part);
+}
+
+// cells per wave of the operator kernel at n = k + 1 points per direction
+int op_cells_per_wave(int n)
+{
+    switch (n) {
+    case 2: return Cfg<2>::CPW;
+    case 3: return Cfg<3>::CPW;
+    case 4: return Cfg<4>::CPW;
+    case 5: return Cfg<5>::CPW;
+    case 6: return Cfg<6>::CPW;
+    case 7: return Cfg<7>::CPW;
+    default: return Cfg<8>::CPW;
+    }
 }
 
 // y = A x and dst = x.y (summed in a fixed order)

@@ -657,11 +657,11 @@ hipError_t grad_n(hx_ctx *c, const double *p, double *u3, bool minv)
     const int nb = (int)((c->n_cells + cpb - 1) / cpb);
     if (minv)
         hipLaunchKernelGGL((k_grad<N, true>), dim3(nb), dim3(PCfg<N, GRAD_T>::NT), 0, c->stream, p, u3,
-                           c->n_dofs, c->psW, c->psFn, c->visit, c->ref, c->ps_tau, (int)c->n_cells,
+                           c->n_dofs, c->psW, c->psFn, c->visitp, c->ref, c->ps_tau, (int)c->n_cells,
                            nb, c->psMr);
     else
         hipLaunchKernelGGL((k_grad<N, false>), dim3(nb), dim3(PCfg<N, GRAD_T>::NT), 0, c->stream, p,
-                           u3, c->n_dofs, c->psW, c->psFn, c->visit, c->ref, c->ps_tau,
+                           u3, c->n_dofs, c->psW, c->psFn, c->visitp, c->ref, c->ps_tau,
                            (int)c->n_cells, nb, (const double *)nullptr);
     return hipGetLastError();
 }
@@ -673,11 +673,11 @@ hipError_t div_n(hx_ctx *c, const double *u3, double *q, const double *x, const 
     const int nb = (int)((c->n_cells + cpb - 1) / cpb);
     if (x)
         hipLaunchKernelGGL((k_div<N, true>), dim3(nb), dim3(PCfg<N, DIV_T>::NT), 0, c->stream, u3, q,
-                           c->n_dofs, c->psWC, c->psFn, c->psFh, c->visit, c->ref, c->ps_tau,
+                           c->n_dofs, c->psWC, c->psFn, c->psFh, c->visitp, c->ref, c->ps_tau,
                            (int)c->n_cells, nb, x, c->psMd, b);
     else
         hipLaunchKernelGGL((k_div<N, false>), dim3(nb), dim3(PCfg<N, DIV_T>::NT), 0, c->stream, u3, q,
-                           c->n_dofs, c->psWC, c->psFn, c->psFh, c->visit, c->ref, c->ps_tau,
+                           c->n_dofs, c->psWC, c->psFn, c->psFh, c->visitp, c->ref, c->ps_tau,
                            (int)c->n_cells, nb, (const double *)nullptr, (const double *)nullptr,
                            (const double *)nullptr);
     return hipGetLastError();
