@@ -33,7 +33,8 @@ def build(force: bool = False) -> str:
 class _Prob(C.Structure):
     _fields_ = [("k", C.c_int), ("g", C.c_int), ("n_cells", C.c_long),
                 ("nodes", C.c_void_p), ("nbr", C.c_void_p),
-                ("alpha", C.c_void_p), ("beta", C.c_void_p), ("P", C.c_double)]
+                ("alpha", C.c_void_p), ("beta", C.c_void_p), ("P", C.c_double),
+                ("n_hang", C.c_long), ("hang", C.c_void_p)]
 
 
 _lib = None
@@ -57,7 +58,7 @@ def bind(L):
     L.or_lagrange.argtypes = [C.c_int, dp, C.c_double, dp, dp]
     L.or_mesh_check.argtypes = [pp]
     L.or_mesh_check.restype = C.c_int
-    for name in ("or_dof_coords", "or_cell_volumes", "or_face_sigma"):
+    for name in ("or_dof_coords", "or_cell_volumes", "or_face_sigma", "or_hang_sigma"):
         getattr(L, name).argtypes = [pp, dp]
     L.or_quad_data.argtypes = [pp, dp, dp]
     L.or_load_vector.argtypes = [pp, dp, dp]
@@ -129,6 +130,9 @@ class Problem:
         self.n_dofs = self.n_cells * self.nd
         self.nodes = np.ascontiguousarray(mesh.nodes, dtype=np.float64)
         self.nbr = np.ascontiguousarray(mesh.nbr, dtype=np.int64)
+        hang = getattr(mesh, "hang", None)
+        self.hang = np.ascontiguousarray(np.zeros((0, 4)) if hang is None else hang,
+                                         dtype=np.int64).reshape(-1, 4)
         self.P = float(P)
         self.alpha = None
         self.beta = None
@@ -150,7 +154,7 @@ class Problem:
                   self.nodes.ctypes.data, self.nbr.ctypes.data,
                   self.alpha.ctypes.data if self.alpha is not None else zero,
                   self.beta.ctypes.data if self.beta is not None else zero,
-                  self.P)
+                  self.P, self.hang.shape[0], self.hang.ctypes.data)
         return C.byref(s)
 
     # geometry ------------------------------------------------------------
@@ -175,6 +179,13 @@ class Problem:
         b = np.zeros(self.n_dofs)
         lib().or_load_vector(self._s(), _dp(fq), _dp(b))
         return b
+
+    def hang_sigma(self):
+        """Penalty of every non-conforming quarter face (hanging record)."""
+        s = np.zeros(self.hang.shape[0])
+        if s.size:
+            lib().or_hang_sigma(self._s(), _dp(s))
+        return s
 
     def cell_volumes(self):
         v = np.zeros(self.n_cells)

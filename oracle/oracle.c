@@ -29,6 +29,15 @@
  *   sigma_F = P (k+1)^2 max(|F|/|K-|, |F|/|K+|);
  * boundary faces (neighbour -1) contribute nothing (natural Neumann).
  *
+ * Non-conforming meshes (section 3: the paper's second mesh refines part of
+ * the domain, so faces between a coarse cell and four finer ones appear):
+ * each quarter of a coarse face that meets a fine cell is a face of the same
+ * form, integrated with the fine face's Gauss rule; the coarse side is
+ * evaluated at the images of those points on its face, ds and n come from
+ * the fine side, the minus cell is the one whose +d face it is, and
+ * sigma = P (k+1)^2 max(|S|/|K_fine|, |S|/|K_coarse|) with |S| the quarter's
+ * area.
+ *
  * The separable cell-block preconditioner Ahat_K (the tensor-product
  * structure used for the fast inverse of block-diagonal operators, section
  * 3.3) is built here by explicit Kronecker sums and solved densely.
@@ -314,7 +323,7 @@ int or_mesh_check(const or_prob *p)
     for (long c = 0; c < p->n_cells; ++c) {
         for (int f = 0; f < 6; ++f) {
             long nb = p->nbr[6 * c + f];
-            if (nb < -1 || nb >= p->n_cells) return 2;
+            if (nb < (p->n_hang > 0 ? -2 : -1) || nb >= p->n_cells) return 2;
             if (nb >= 0 && p->nbr[6 * nb + (f ^ 1)] != c) return 2;
         }
     }
@@ -418,6 +427,8 @@ typedef struct {
     double (*dphi)[3];      /* [nd][3] */
 } scratch_t;
 
+static void hang_apply_cell(const or_prob *p, const ref_t *r, long c, const double *xv, double *yc);
+
 /* (A x) restricted to the test functions of cell c, written to yc[nd] */
 static void apply_one_cell(const or_prob *p, int flags, long c, const double *xv, double *yc)
 {
@@ -517,8 +528,155 @@ static void apply_one_cell(const or_prob *p, int flags, long c, const double *xv
                         }
                     }
             }
+        hang_apply_cell(p, &r, c, xv, yc);
     }
     free(phi); free(phiB); free(dphi); free(dphiB);
+}
+
+/* ------------------------------------------------------------------------ */
+/* non-conforming faces                                                      */
+/* ------------------------------------------------------------------------ */
+
+/* reference points of the fine face's Gauss point (a, b) on the fine cell
+ * (xiF) and on the coarse cell (xiC) for the hanging record h */
+static void hang_points(const ref_t *r, const long *h, int a, int b, double xiF[3], double xiC[3])
+{
+    const int fc = (int)h[1], d = fc >> 1, s = (int)h[3];
+    const int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+    face_point(r, d, (fc ^ 1) & 1, a, b, xiF);
+    xiC[d] = (fc & 1) ? 1.0 : 0.0;
+    xiC[t1] = 0.5 * ((s & 1) + r->xq[a]);
+    xiC[t2] = 0.5 * ((s >> 1) + r->xq[b]);
+}
+
+/* unit normal n (the +d direction, i.e. the minus cell's outward normal) and
+ * surface element at the fine face's point (a, b), from the fine side */
+static void hang_normal(const or_prob *p, const ref_t *r, const long *h, int a, int b,
+                        double nrm[3], double *ds)
+{
+    double xiF[3], xiC[3], x[3], J[3][3], K[3][3];
+    const int d = (int)(h[1] >> 1);
+    hang_points(r, h, a, b, xiF, xiC);
+    geom_at(r, cell_nodes(p, r, h[2]), xiF, x, J);
+    double det = det3(J);
+    inv_transpose(J, det, K);
+    double e[3] = {0, 0, 0}, m[3];
+    e[d] = 1.0;
+    matvec3(K, e, m);
+    double len = sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
+    for (int q = 0; q < 3; ++q) nrm[q] = m[q] / len;
+    *ds = r->wq[a] * r->wq[b] * det * len;
+}
+
+/* penalty of the quarter face of record h */
+static double hang_sigma(const or_prob *p, const ref_t *r, const long *h)
+{
+    double area = 0.0, nrm[3], ds;
+    for (int b = 0; b < r->n; ++b)
+        for (int a = 0; a < r->n; ++a) {
+            hang_normal(p, r, h, a, b, nrm, &ds);
+            area += ds;
+        }
+    double vf = cell_volume(p, r, h[2]), vc = cell_volume(p, r, h[0]);
+    double s = area / vf > area / vc ? area / vf : area / vc;
+    return p->P * (double)(r->n * r->n) * s;
+}
+
+void or_hang_sigma(const or_prob *p, double *sigma)
+{
+    ref_t r; ref_init(&r, p->k, p->g);
+#pragma omp parallel for schedule(static)
+    for (long h = 0; h < p->n_hang; ++h) sigma[h] = hang_sigma(p, &r, p->hang + 4 * h);
+}
+
+/* values, physical gradients and beta of both sides at the fine face's point
+ * (a, b) of record h; side 0 = coarse, 1 = fine */
+typedef struct {
+    double *phi[2];
+    double (*dphi[2])[3];
+    double K[2][3][3];
+    double beta[2];
+} hang_pt;
+
+static void hang_eval(const or_prob *p, const ref_t *r, const long *h, int a, int b, hang_pt *hp)
+{
+    double xi[2][3], x[3], J[3][3];
+    const int nd = r->nd;
+    hang_points(r, h, a, b, xi[1], xi[0]);
+    for (int side = 0; side < 2; ++side) {
+        const long c = side ? h[2] : h[0];
+        geom_at(r, cell_nodes(p, r, c), xi[side], x, J);
+        inv_transpose(J, det3(J), hp->K[side]);
+        basis_at(r, xi[side], hp->phi[side], hp->dphi[side]);
+        hp->beta[side] = field_at(hp->phi[side], p->beta + c * nd, nd);
+    }
+}
+
+/* contributions of the quarter face of record h to the test functions of its
+ * coarse (own = 0) or fine (own = 1) cell, added to yc[nd] */
+static void hang_apply(const or_prob *p, const ref_t *r, const long *h, int own, const double *xv,
+                       double *yc, hang_pt *hp)
+{
+    const int nd = r->nd, n = r->n;
+    const int minus = (h[1] & 1) ? 0 : 1;   /* the coarse cell is minus on its own +d face */
+    const double sigma = hang_sigma(p, r, h);
+    const double *xs[2] = {xv + h[0] * nd, xv + h[2] * nd};
+    for (int b = 0; b < n; ++b)
+        for (int a = 0; a < n; ++a) {
+            double nrm[3], ds;
+            hang_normal(p, r, h, a, b, nrm, &ds);
+            hang_eval(p, r, h, a, b, hp);
+            double u[2], dn[2];
+            for (int side = 0; side < 2; ++side) {
+                double gr[3] = {0, 0, 0}, g[3];
+                u[side] = 0.0;
+                for (int e = 0; e < nd; ++e) {
+                    u[side] += hp->phi[side][e] * xs[side][e];
+                    for (int q = 0; q < 3; ++q) gr[q] += hp->dphi[side][e][q] * xs[side][e];
+                }
+                matvec3(hp->K[side], gr, g);
+                dn[side] = nrm[0] * g[0] + nrm[1] * g[1] + nrm[2] * g[2];
+            }
+            const int plus = 1 - minus;
+            double flux = hp->beta[minus] * dn[minus] + hp->beta[plus] * dn[plus];
+            double jump = u[minus] - u[plus];
+            double pen = sigma * 0.5 * (hp->beta[minus] + hp->beta[plus]);
+            double sgn = own == minus ? 1.0 : -1.0;
+            for (int e = 0; e < nd; ++e) {
+                double gv[3];
+                matvec3(hp->K[own], hp->dphi[own][e], gv);
+                double dnv = nrm[0] * gv[0] + nrm[1] * gv[1] + nrm[2] * gv[2];
+                double jv = sgn * hp->phi[own][e];
+                yc[e] += ds * (-0.5 * flux * jv - 0.5 * hp->beta[own] * dnv * jump + pen * jump * jv);
+            }
+        }
+}
+
+static void hang_alloc(hang_pt *hp, int nd)
+{
+    for (int s = 0; s < 2; ++s) {
+        hp->phi[s] = malloc(sizeof(double) * nd);
+        hp->dphi[s] = malloc(sizeof(double) * 3 * nd);
+    }
+}
+
+static void hang_free(hang_pt *hp)
+{
+    for (int s = 0; s < 2; ++s) { free(hp->phi[s]); free(hp->dphi[s]); }
+}
+
+/* the non-conforming face terms on the test functions of cell c */
+static void hang_apply_cell(const or_prob *p, const ref_t *r, long c, const double *xv, double *yc)
+{
+    if (p->n_hang <= 0) return;
+    hang_pt hp;
+    hang_alloc(&hp, r->nd);
+    for (long h = 0; h < p->n_hang; ++h) {
+        const long *rec = p->hang + 4 * h;
+        if (rec[0] == c) hang_apply(p, r, rec, 0, xv, yc, &hp);
+        if (rec[2] == c) hang_apply(p, r, rec, 1, xv, yc, &hp);
+    }
+    hang_free(&hp);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -845,6 +1003,44 @@ void or_assemble_dense(const or_prob *p, int flags, double *A)
                     }
             }
     }
+    /* non-conforming quarter faces, each once, all four blocks */
+    if ((flags & OR_FACE) && p->n_hang > 0) {
+        hang_pt hp;
+        hang_alloc(&hp, nd);
+        for (long h = 0; h < p->n_hang; ++h) {
+            const long *rec = p->hang + 4 * h;
+            const long cells[2] = {rec[0], rec[2]};
+            const int minus = (rec[1] & 1) ? 0 : 1;
+            const double sigma = hang_sigma(p, &r, rec);
+            for (int b = 0; b < n; ++b)
+                for (int a = 0; a < n; ++a) {
+                    double nrm[3], ds;
+                    hang_normal(p, &r, rec, a, b, nrm, &ds);
+                    hang_eval(p, &r, rec, a, b, &hp);
+                    for (int side = 0; side < 2; ++side)
+                        for (int e = 0; e < nd; ++e)
+                            matvec3(hp.K[side], hp.dphi[side][e], side ? gphys2[e] : gphys[e]);
+                    double pen = sigma * 0.5 * (hp.beta[0] + hp.beta[1]);
+                    for (int st = 0; st < 2; ++st)
+                        for (int su = 0; su < 2; ++su) {
+                            double (*gt)[3] = st ? gphys2 : gphys, (*gu)[3] = su ? gphys2 : gphys;
+                            const double *vt = hp.phi[st], *vu = hp.phi[su];
+                            double zt = st == minus ? 1.0 : -1.0, zu = su == minus ? 1.0 : -1.0;
+                            for (int ti = 0; ti < nd; ++ti) {
+                                double dnt = nrm[0] * gt[ti][0] + nrm[1] * gt[ti][1] + nrm[2] * gt[ti][2];
+                                for (int tj = 0; tj < nd; ++tj) {
+                                    double dnu = nrm[0] * gu[tj][0] + nrm[1] * gu[tj][1] + nrm[2] * gu[tj][2];
+                                    double s = -0.5 * hp.beta[su] * dnu * zt * vt[ti]
+                                               - 0.5 * hp.beta[st] * dnt * zu * vu[tj]
+                                               + pen * zu * vu[tj] * zt * vt[ti];
+                                    A[(size_t)(cells[st] * nd + ti) * N + cells[su] * nd + tj] += ds * s;
+                                }
+                            }
+                        }
+                }
+        }
+        hang_free(&hp);
+    }
     free(phi); free(phi2); free(dphi); free(dphi2); free(gphys); free(gphys2);
 }
 
@@ -883,6 +1079,26 @@ void or_bj_cell_data(const or_prob *p, long c, double ell[3], double *abar,
         long lo = p->nbr[6 * c + 2 * d];
         sig[d][0] = lo >= 0 ? face_sigma(p, &r, lo, d) : -1.0;
         sig[d][1] = face_sigma(p, &r, c, d);
+        /* a non-conforming end: the penalty of the fine cell's quarter face,
+           or the area-weighted mean over the four quarters of a coarse face */
+        for (int e = 0; e < 2; ++e) {
+            if (p->nbr[6 * c + 2 * d + e] != -2) continue;
+            double ssum = 0.0, asum = 0.0;
+            for (long h = 0; h < p->n_hang; ++h) {
+                const long *rec = p->hang + 4 * h;
+                int f = rec[0] == c ? (int)rec[1] : (rec[2] == c ? (int)(rec[1] ^ 1) : -1);
+                if (f != 2 * d + e) continue;
+                double area = 0.0, nrm[3], ds;
+                for (int b = 0; b < n; ++b)
+                    for (int a = 0; a < n; ++a) {
+                        hang_normal(p, &r, rec, a, b, nrm, &ds);
+                        area += ds;
+                    }
+                ssum += area * hang_sigma(p, &r, rec);
+                asum += area;
+            }
+            sig[d][e] = asum > 0.0 ? ssum / asum : -1.0;
+        }
     }
     *abar = sa / vol;
     *bbar = sb / vol;

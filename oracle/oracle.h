@@ -16,6 +16,11 @@ typedef struct {
     const double *alpha;   /* [n_cells*(k+1)^3] DG nodal field */
     const double *beta;    /* [n_cells*(k+1)^3] DG nodal field */
     double P;              /* penalty factor */
+    long n_hang;           /* non-conforming (2:1) subfaces, 0 on a conforming mesh */
+    const long *hang;      /* [n_hang][4] = {coarse cell C, its face fc, fine cell F, quarter s}:
+                              face fc^1 of F is quarter s = s1 + 2 s2 of face fc of C
+                              (s1, s2: halves along the first, second tangential
+                              direction); both faces are marked -2 in nbr */
 } or_prob;
 
 void or_gauss_legendre(int n, double *x, double *w);
@@ -28,6 +33,7 @@ void or_quad_data(const or_prob *p, double *xyz, double *wdet);
 void or_load_vector(const or_prob *p, const double *fq, double *b);
 void or_cell_volumes(const or_prob *p, double *vol);
 void or_face_sigma(const or_prob *p, double *sigma);
+void or_hang_sigma(const or_prob *p, double *sigma);
 void or_eval_quad(const or_prob *p, const double *u, double *uq);
 void or_apply(const or_prob *p, int flags, const double *x, double *y);
 void or_apply_cells(const or_prob *p, int flags, const long *cells, long m,

@@ -46,6 +46,7 @@ class Mesh:
     periodic: Tuple[bool, bool, bool]
     name: str = ""
     meta: dict = field(default_factory=dict)
+    hang: Optional[np.ndarray] = None   # [n, 4] non-conforming quarter faces (see refined_mesh)
 
     @property
     def n_cells(self) -> int:
@@ -116,6 +117,104 @@ def box_mesh(nx: int, ny: int, nz: int,
     nbr = box_neighbours(nx, ny, nz, periodic)
     return Mesh(nodes=nodes, nbr=nbr, g=g, dims=(nx, ny, nz), lo=lo, hi=hi,
                 periodic=tuple(bool(p) for p in periodic), name=name)
+
+
+def refined_mesh(nx: int, ny: int, nz: int, region, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0),
+                 periodic=(True, True, True), g: int = 1, mapping: Optional[Callable] = None,
+                 name: str = "refined") -> Mesh:
+    """A structured nx*ny*nz mesh whose coarse cells with indices in
+    ``region`` = ((i0, i1), (j0, j1), (l0, l1)) (half-open) are split into
+    2x2x2 children: a non-conforming mesh with 2:1 faces.
+
+    Cells: the unrefined coarse cells (x fastest), then the children in the
+    order of the fine grid (x fastest).  Every cell's geometry nodes are the
+    (mapped) images of its own equispaced reference nodes.  Faces between two
+    cells of the same size are conforming; a face between a child and an
+    unrefined coarse cell is marked -2 in ``nbr`` on both sides and listed in
+    ``hang`` as {coarse cell, its face, fine cell, quarter s}: face (f ^ 1) of
+    the fine cell is quarter s = s1 + 2 s2 of face f of the coarse cell, s1
+    (s2) the half along the first (second) of the two tangential directions."""
+    if g < 1:
+        raise ValueError("geometry degree must be >= 1")
+    dims = (nx, ny, nz)
+    ref = np.zeros(dims, dtype=bool)
+    (i0, i1), (j0, j1), (l0, l1) = region
+    ref[i0:i1, j0:j1, l0:l1] = True
+    h = [(hi[d] - lo[d]) / dims[d] for d in range(3)]
+    cid = -np.ones(dims, dtype=np.int64)
+    cells = []                         # (origin, size, level, position)
+    for cz in range(nz):
+        for cy in range(ny):
+            for cx in range(nx):
+                if not ref[cx, cy, cz]:
+                    cid[cx, cy, cz] = len(cells)
+                    cells.append(((lo[0] + cx * h[0], lo[1] + cy * h[1], lo[2] + cz * h[2]),
+                                  tuple(h), 0, (cx, cy, cz)))
+    fdims = tuple(2 * v for v in dims)
+    fid = -np.ones(fdims, dtype=np.int64)
+    for fz in range(fdims[2]):
+        for fy in range(fdims[1]):
+            for fx in range(fdims[0]):
+                if ref[fx // 2, fy // 2, fz // 2]:
+                    fid[fx, fy, fz] = len(cells)
+                    cells.append(((lo[0] + fx * h[0] / 2, lo[1] + fy * h[1] / 2, lo[2] + fz * h[2] / 2),
+                                  tuple(v / 2 for v in h), 1, (fx, fy, fz)))
+    n_cells = len(cells)
+    t = np.arange(g + 1, dtype=np.float64) / g
+    ta = np.tile(t, (g + 1) ** 2)
+    tb = np.tile(np.repeat(t, g + 1), g + 1)
+    tc = np.repeat(t, (g + 1) ** 2)
+    org = np.array([c[0] for c in cells])
+    siz = np.array([c[1] for c in cells])
+    X = org[:, 0:1] + ta[None, :] * siz[:, 0:1]
+    Y = org[:, 1:2] + tb[None, :] * siz[:, 1:2]
+    Z = org[:, 2:3] + tc[None, :] * siz[:, 2:3]
+    if mapping is not None:
+        X, Y, Z = mapping(X, Y, Z)
+    nodes = np.stack([X, Y, Z], axis=-1)
+    nbr = np.empty((n_cells, 6), dtype=np.int64)
+    hang = []
+    for c, (_, _, level, pos) in enumerate(cells):
+        gdims = dims if level == 0 else fdims
+        for d in range(3):
+            t1, t2 = (1, 2) if d == 0 else ((0, 2) if d == 1 else (0, 1))
+            for s, step in enumerate((-1, 1)):
+                f = 2 * d + s
+                q = list(pos)
+                q[d] += step
+                if q[d] < 0 or q[d] >= gdims[d]:
+                    if not periodic[d]:
+                        nbr[c, f] = -1
+                        continue
+                    q[d] %= gdims[d]
+                if level == 0:
+                    if ref[tuple(q)]:
+                        nbr[c, f] = -2          # four fine cells: recorded from their side
+                    else:
+                        nbr[c, f] = cid[tuple(q)]
+                else:
+                    parent = tuple(v // 2 for v in q)
+                    if ref[parent]:
+                        nbr[c, f] = fid[tuple(q)]
+                    else:
+                        nbr[c, f] = -2
+                        quarter = (pos[t1] % 2) + 2 * (pos[t2] % 2)
+                        hang.append((cid[parent], f ^ 1, c, quarter))
+    return Mesh(nodes=nodes, nbr=nbr, g=g, dims=dims, lo=tuple(lo), hi=tuple(hi),
+                periodic=tuple(bool(p) for p in periodic), name=name,
+                hang=np.array(hang, dtype=np.int64).reshape(-1, 4))
+
+
+def refined_terrain_mesh(nx: int = 16, ny: int = 4, nz: int = 8, g: int = 4, region=None) -> Mesh:
+    """The terrain channel with the cells above the ridge refined once (a
+    non-conforming mesh: the paper's second mesh refines around the hill).
+    Default region: the middle half in x, all of y, the bottom half in z."""
+    T = TERRAIN
+    if region is None:
+        region = ((nx // 4, 3 * nx // 4), (0, ny), (0, max(1, nz // 2)))
+    return refined_mesh(nx, ny, nz, region, lo=(-T["Lx"] / 2, 0.0, 0.0),
+                        hi=(T["Lx"] / 2, T["Ly"], T["Lz"]), periodic=(True, True, False), g=g,
+                        mapping=terrain_mapping, name=f"terrain-refined-{nx}x{ny}x{nz}")
 
 
 # --- the workloads -------------------------------------------------------
