@@ -108,6 +108,27 @@ int hx_max_degree(void);
 hx_status hx_setup_mesh(hx_ctx *c, int degree, int64_t n_cells, int geo_degree,
                         const double *geo_nodes, const int64_t *neighbours);
 
+/* The same for a non-conforming mesh with 2:1 faces (section 3: the paper's
+ * second mesh refines part of its domain).  A face of a coarse cell C that
+ * meets four finer cells is marked -2 in neighbours, on C and on each fine
+ * cell, and described by n_hang records hang (HOST [n_hang][4]) =
+ * {C, fc, F, s}: face fc (0..5 = -x, +x, -y, +y, -z, +z) of C, of which the
+ * face fc ^ 1 of the fine cell F is quarter s = s1 + 2 s2 (s1, s2 the half
+ * along the first and second of the two tangential directions, in the
+ * direction order x, y, z; the fine cell's tangential axes run parallel to
+ * the coarse cell's).  Each quarter carries the interior-penalty terms
+ * integrated with the fine face's Gauss rule, the coarse side evaluated at
+ * the images of those points, ds and n from the fine side, penalty
+ * P (k+1)^2 max(|S|/|K_fine|, |S|/|K_coarse|).  Fails with HX_ERR_MESH unless
+ * every face marked -2 is listed once (fine side) or with its four quarters
+ * (coarse side).  The separable block Jacobi, the volume diagonals, the mass
+ * blocks, Chebyshev and every solve accept such meshes; the geometric
+ * multigrid, the pressure system and consistent integration return
+ * HX_ERR_STATE on them. */
+hx_status hx_setup_mesh_hanging(hx_ctx *c, int degree, int64_t n_cells, int geo_degree,
+                                const double *geo_nodes, const int64_t *neighbours,
+                                int64_t n_hang, const int64_t *hang);
+
 /* Physical coordinates of every dof (Gauss-Lobatto node images), written to
  * the DEVICE array xyz [3][n_dofs] (all x, then all y, then all z). */
 hx_status hx_dof_coordinates(hx_ctx *c, double *xyz);

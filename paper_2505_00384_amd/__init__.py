@@ -74,6 +74,7 @@ def load(path: str = LIB_PATH):
         "hx_last_error": ([vp], C.c_char_p),
         "hx_max_degree": ([], C.c_int),
         "hx_setup_mesh": ([vp, C.c_int, i64, C.c_int, vp, vp], C.c_int),
+        "hx_setup_mesh_hanging": ([vp, C.c_int, i64, C.c_int, vp, vp, i64, vp], C.c_int),
         "hx_dof_coordinates": ([vp, vp], C.c_int),
         "hx_num_dofs": ([vp], i64),
         "hx_set_coefficients": ([vp, vp, vp, C.c_double, C.c_int], C.c_int),
@@ -180,12 +181,21 @@ class HelmDG:
         return self.L.hx_last_error(self.h).decode()
 
     # -- setup --------------------------------------------------------------
-    def setup_mesh(self, degree: int, nodes: np.ndarray, nbr: np.ndarray, geo_degree: int):
+    def setup_mesh(self, degree: int, nodes: np.ndarray, nbr: np.ndarray, geo_degree: int,
+                   hang: Optional[np.ndarray] = None):
+        """Mesh upload; ``hang`` ([n, 4] int: coarse cell, its face, fine
+        cell, quarter) describes non-conforming 2:1 faces marked -2 in nbr."""
         nodes = np.ascontiguousarray(nodes, dtype=np.float64)
         nbr = np.ascontiguousarray(nbr, dtype=np.int64)
         n_cells = nbr.shape[0]
-        st = self.L.hx_setup_mesh(self.h, int(degree), n_cells, int(geo_degree),
-                                  nodes.ctypes.data, nbr.ctypes.data)
+        if hang is not None and len(hang):
+            hang = np.ascontiguousarray(hang, dtype=np.int64).reshape(-1, 4)
+            st = self.L.hx_setup_mesh_hanging(self.h, int(degree), n_cells, int(geo_degree),
+                                              nodes.ctypes.data, nbr.ctypes.data, hang.shape[0],
+                                              hang.ctypes.data)
+        else:
+            st = self.L.hx_setup_mesh(self.h, int(degree), n_cells, int(geo_degree),
+                                      nodes.ctypes.data, nbr.ctypes.data)
         self._chk(st, "setup_mesh")
         self.k = int(degree)
         self.n_dofs = int(self.L.hx_num_dofs(self.h))

@@ -55,7 +55,11 @@ static void free_mesh(hx_ctx *c)
                      (void **)&c->mgw32, (void **)&c->chebw32, (void **)&c->ctype,
                      (void **)&c->acell64, (void **)&c->acell32, (void **)&c->kk64,
                      (void **)&c->kk32, (void **)&c->aface64, (void **)&c->aface32,
-                     (void **)&c->fc64, (void **)&c->fc32};
+                     (void **)&c->fc64, (void **)&c->fc32, (void **)&c->hang, (void **)&c->hgeo,
+                     (void **)&c->hsig, (void **)&c->harea, (void **)&c->hdata64,
+                     (void **)&c->hdata32, (void **)&c->hcontrib64, (void **)&c->hcontrib32,
+                     (void **)&c->hcells, (void **)&c->hptr, (void **)&c->hlist,
+                     (void **)&c->endsig};
     for (void **b : bufs) dfree(b);
     delete c->order_h;
     delete c->nbr_h;
@@ -65,6 +69,7 @@ static void free_mesh(hx_ctx *c)
     c->ctype_h = nullptr;
     c->n_vis_op = 0;
     c->vis_mode = 0;
+    c->n_hang = c->n_hcell = 0;
     c->n_affine = c->n_iface = c->n_cface = 0;
     c->work64_len = c->work32_len = 0;
     c->has_mesh = c->has_coef = c->has_press = c->has_q = false;
@@ -126,6 +131,70 @@ static hx_status update_visit_masks(hx_ctx *c)
     return HX_OK;
 }
 
+// Block-Jacobi penalty of each non-conforming cell end: the fine cell's
+// quarter penalty, or the area-weighted mean over the four quarters of a
+// coarse face (the end term of the separable block stands for the whole face).
+static hx_status update_hang_sigma(hx_ctx *c)
+{
+    if (c->n_hang == 0) return HX_OK;
+    HX_HIP(c, launch_hang_geometry(c));
+    std::vector<double> sig((size_t)c->n_hang), area((size_t)c->n_hang);
+    std::vector<int32_t> rec((size_t)c->n_hang * 4);
+    HX_HIP(c, hipMemcpyAsync(sig.data(), c->hsig, sizeof(double) * sig.size(), hipMemcpyDeviceToHost, c->stream));
+    HX_HIP(c, hipMemcpyAsync(area.data(), c->harea, sizeof(double) * area.size(), hipMemcpyDeviceToHost,
+                             c->stream));
+    HX_HIP(c, hipMemcpyAsync(rec.data(), c->hang, sizeof(int32_t) * rec.size(), hipMemcpyDeviceToHost,
+                             c->stream));
+    HX_HIP(c, hipStreamSynchronize(c->stream));
+    const size_t nc = (size_t)c->n_cells;
+    std::vector<double> num(nc * 6, 0.0), den(nc * 6, 0.0), es(nc * 6, -1.0);
+    for (size_t h = 0; h < sig.size(); ++h) {
+        const int32_t C = rec[4 * h], fc = rec[4 * h + 1], F = rec[4 * h + 2];
+        num[6 * (size_t)C + fc] += area[h] * sig[h];
+        den[6 * (size_t)C + fc] += area[h];
+        num[6 * (size_t)F + (fc ^ 1)] += area[h] * sig[h];
+        den[6 * (size_t)F + (fc ^ 1)] += area[h];
+    }
+    for (size_t i = 0; i < nc * 6; ++i)
+        if (den[i] > 0.0) es[i] = num[i] / den[i];
+    HX_HIP(c, hipMemcpyAsync(c->endsig, es.data(), sizeof(double) * es.size(), hipMemcpyHostToDevice,
+                             c->stream));
+    HX_HIP(c, hipStreamSynchronize(c->stream));
+    return HX_OK;
+}
+
+// Check the quarter-face records against the neighbour table (host arrays):
+// every face marked -2 is a coarse face listed with its four quarters once
+// each, or a fine face listed once; records name cells, faces and quarters
+// in range.
+static hx_status check_hanging(hx_ctx *c, int64_t n_cells, const int64_t *nbr, int64_t n_hang,
+                               const int64_t *hang)
+{
+    std::vector<int> cover((size_t)n_cells * 6, 0), qmask((size_t)n_cells * 6, 0);
+    for (int64_t h = 0; h < n_hang; ++h) {
+        const int64_t C = hang[4 * h], fc = hang[4 * h + 1], F = hang[4 * h + 2], s = hang[4 * h + 3];
+        if (C < 0 || C >= n_cells || F < 0 || F >= n_cells || C == F || fc < 0 || fc > 5 || s < 0 || s > 3)
+            return fail(c, HX_ERR_MESH, "hanging record %lld out of range", (long long)h);
+        if (nbr[6 * C + fc] != -2 || nbr[6 * F + (fc ^ 1)] != -2)
+            return fail(c, HX_ERR_MESH, "hanging record %lld: its faces are not marked -2", (long long)h);
+        int &q = qmask[6 * (size_t)C + fc];
+        if (q & (1 << s)) return fail(c, HX_ERR_MESH, "hanging record %lld: quarter %lld twice", (long long)h, (long long)s);
+        q |= 1 << s;
+        cover[6 * (size_t)C + fc] += 1;
+        if (cover[6 * (size_t)F + (fc ^ 1)]++ != 0)
+            return fail(c, HX_ERR_MESH, "hanging record %lld: fine face listed twice", (long long)h);
+    }
+    for (int64_t i = 0; i < n_cells; ++i)
+        for (int f = 0; f < 6; ++f) {
+            if (nbr[6 * i + f] != -2) continue;
+            const int k = cover[6 * (size_t)i + f];
+            if (k != 1 && !(k == 4 && qmask[6 * (size_t)i + f] == 15))
+                return fail(c, HX_ERR_MESH, "cell %lld face %d marked -2 without its quarter records",
+                            (long long)i, f);
+        }
+    return HX_OK;
+}
+
 }  // namespace hx
 
 using namespace hx;
@@ -181,6 +250,13 @@ int64_t hx_num_dofs(const hx_ctx *c) { return (c && c->has_mesh) ? c->n_dofs : -
 hx_status hx_setup_mesh(hx_ctx *c, int degree, int64_t n_cells, int geo_degree,
                         const double *geo_nodes, const int64_t *neighbours)
 {
+    return hx_setup_mesh_hanging(c, degree, n_cells, geo_degree, geo_nodes, neighbours, 0, nullptr);
+}
+
+hx_status hx_setup_mesh_hanging(hx_ctx *c, int degree, int64_t n_cells, int geo_degree,
+                                const double *geo_nodes, const int64_t *neighbours, int64_t n_hang,
+                                const int64_t *hang)
+{
     if (!c) return HX_ERR_ARG;
     c->err.clear();
     if (degree < 1 || degree > MAXK)
@@ -195,7 +271,7 @@ hx_status hx_setup_mesh(hx_ctx *c, int degree, int64_t n_cells, int geo_degree,
     for (int64_t i = 0; i < n_cells; ++i)
         for (int f = 0; f < 6; ++f) {
             const int64_t v = neighbours[6 * i + f];
-            if (v < -1 || v >= n_cells)
+            if (v < (n_hang > 0 ? -2 : -1) || v >= n_cells)
                 return fail(c, HX_ERR_MESH, "neighbour %lld of cell %lld face %d out of range",
                             (long long)v, (long long)i, f);
             if (v >= 0 && neighbours[6 * v + (f ^ 1)] != i)
@@ -203,6 +279,11 @@ hx_status hx_setup_mesh(hx_ctx *c, int degree, int64_t n_cells, int geo_degree,
                             (long long)i, f, (long long)v);
             nb32[6 * i + f] = (int32_t)v;
         }
+    if (n_hang < 0 || (n_hang > 0 && !hang)) return fail(c, HX_ERR_ARG, "bad hanging-face table");
+    if (n_hang > 0) {
+        hx_status sh = check_hanging(c, n_cells, neighbours, n_hang, hang);
+        if (sh != HX_OK) return sh;
+    }
     HX_HIP(c, hipSetDevice(c->device));
     free_mesh(c);
     c->k = degree;
@@ -252,6 +333,37 @@ hx_status hx_setup_mesh(hx_ctx *c, int degree, int64_t n_cells, int geo_degree,
     ALLOC(c->aface32, sizeof(float) * nc * 3 * 2 * c->nf);
     ALLOC(c->fc64, sizeof(double) * nc * 3 * 8);
     ALLOC(c->fc32, sizeof(float) * nc * 3 * 8);
+    c->n_hang = n_hang;
+    std::vector<int32_t> hcells, hptr, hlist;
+    if (n_hang > 0) {
+        const size_t nh = (size_t)n_hang;
+        ALLOC(c->hang, sizeof(int32_t) * nh * 4);
+        ALLOC(c->hgeo, sizeof(double) * nh * 7 * c->nf);
+        ALLOC(c->hsig, sizeof(double) * nh);
+        ALLOC(c->harea, sizeof(double) * nh);
+        ALLOC(c->hdata64, sizeof(double) * nh * 7 * c->nf);
+        ALLOC(c->hdata32, sizeof(float) * nh * 7 * c->nf);
+        ALLOC(c->hcontrib64, sizeof(double) * nh * 2 * c->nd);
+        ALLOC(c->hcontrib32, sizeof(float) * nh * 2 * c->nd);
+        ALLOC(c->endsig, sizeof(double) * nc * 6);
+        // the quarter contributions of each cell, in record order
+        std::vector<std::vector<int32_t>> by((size_t)n_cells);
+        for (size_t h = 0; h < nh; ++h) {
+            by[(size_t)hang[4 * h]].push_back((int32_t)(2 * h));
+            by[(size_t)hang[4 * h + 2]].push_back((int32_t)(2 * h + 1));
+        }
+        hptr.push_back(0);
+        for (size_t i = 0; i < nc; ++i) {
+            if (by[i].empty()) continue;
+            hcells.push_back((int32_t)i);
+            hlist.insert(hlist.end(), by[i].begin(), by[i].end());
+            hptr.push_back((int32_t)hlist.size());
+        }
+        c->n_hcell = (int64_t)hcells.size();
+        ALLOC(c->hcells, sizeof(int32_t) * hcells.size());
+        ALLOC(c->hptr, sizeof(int32_t) * hptr.size());
+        ALLOC(c->hlist, sizeof(int32_t) * hlist.size());
+    }
 #undef ALLOC
     if (s != HX_OK) {
         free_mesh(c);
@@ -261,6 +373,19 @@ hx_status hx_setup_mesh(hx_ctx *c, int degree, int64_t n_cells, int geo_degree,
                              hipMemcpyHostToDevice, c->stream));
     HX_HIP(c, hipMemcpyAsync(c->nbr, nb32.data(), sizeof(int32_t) * nc * 6, hipMemcpyHostToDevice,
                              c->stream));
+    if (n_hang > 0) {
+        std::vector<int32_t> h32((size_t)n_hang * 4);
+        for (size_t i = 0; i < h32.size(); ++i) h32[i] = (int32_t)hang[i];
+        HX_HIP(c, hipMemcpyAsync(c->hang, h32.data(), sizeof(int32_t) * h32.size(), hipMemcpyHostToDevice,
+                                 c->stream));
+        HX_HIP(c, hipMemcpyAsync(c->hcells, hcells.data(), sizeof(int32_t) * hcells.size(),
+                                 hipMemcpyHostToDevice, c->stream));
+        HX_HIP(c, hipMemcpyAsync(c->hptr, hptr.data(), sizeof(int32_t) * hptr.size(), hipMemcpyHostToDevice,
+                                 c->stream));
+        HX_HIP(c, hipMemcpyAsync(c->hlist, hlist.data(), sizeof(int32_t) * hlist.size(),
+                                 hipMemcpyHostToDevice, c->stream));
+        HX_HIP(c, hipStreamSynchronize(c->stream));
+    }
     c->order_h = new std::vector<int32_t>(nc);
     build_traversal(nb32.data(), n_cells, c->order_h->data());
     c->nbr_h = new std::vector<int32_t>(nb32);
@@ -277,6 +402,10 @@ hx_status hx_setup_mesh(hx_ctx *c, int degree, int64_t n_cells, int geo_degree,
             return fail(c, HX_ERR_MESH, "cell %zu: detJ = %g <= 0 at a quadrature point", i, md[i]);
         }
     HX_HIP(c, launch_face_sigma(c));
+    {
+        hx_status sh = update_hang_sigma(c);
+        if (sh != HX_OK) return sh;
+    }
     HX_HIP(c, launch_bj_eigen(c));
     HX_HIP(c, launch_geofac(c));
     HX_HIP(c, launch_affine_detect(c));
@@ -328,7 +457,7 @@ hx_status hx_operator_info(const hx_ctx *cc, int prec, int64_t *counts, double *
         const double nd = c->nd, nf = c->nf;
         *bytes = T * (2.0 * (double)c->n_dofs + ((double)c->n_cells - na) * 7.0 * nd +
                       na * (2.0 * nd + 6.0) + ((double)c->n_iface - nfc) * 7.0 * nf +
-                      nfc * (2.0 * nf + 7.0));
+                      nfc * (2.0 * nf + 7.0) + (double)c->n_hang * 7.0 * nf);
     }
     return HX_OK;
 }
@@ -365,6 +494,8 @@ hx_status hx_set_coefficients(hx_ctx *c, const double *alpha, const double *beta
     if (penalty_factor != c->P) {
         c->P = penalty_factor;
         HX_HIP(c, launch_face_sigma(c));
+        hx_status sh = update_hang_sigma(c);
+        if (sh != HX_OK) return sh;
         HX_HIP(c, launch_bj_eigen(c));
     }
     hipError_t e = launch_set_coefficients(c, da, db);
@@ -380,6 +511,7 @@ hx_status hx_set_pressure_system(hx_ctx *c, const double *rho, const double *h, 
 {
     if (!c) return HX_ERR_ARG;
     if (!c->has_mesh) return fail(c, HX_ERR_STATE, "set_pressure_system before setup_mesh");
+    if (c->n_hang) return fail(c, HX_ERR_STATE, "the pressure system is not built on meshes with hanging faces");
     if (!rho || !h) return fail(c, HX_ERR_ARG, "null field");
     if (!(gamma > 1.0) || !std::isfinite(gamma)) return fail(c, HX_ERR_ARG, "gamma must exceed 1");
     if (!(tau > 0.0) || !std::isfinite(tau)) return fail(c, HX_ERR_ARG, "tau must be positive");
@@ -428,6 +560,7 @@ hx_status hx_set_consistent(hx_ctx *c, const double *alpha, const double *beta, 
 {
     if (!c) return HX_ERR_ARG;
     if (!c->has_coef) return fail(c, HX_ERR_STATE, "set_consistent before set_coefficients");
+    if (c->n_hang) return fail(c, HX_ERR_STATE, "consistent integration is not built on meshes with hanging faces");
     if (!alpha || !beta) return fail(c, HX_ERR_ARG, "null coefficient array");
     HX_HIP(c, hipSetDevice(c->device));
     const int64_t n = c->n_dofs, nc = c->n_cells;

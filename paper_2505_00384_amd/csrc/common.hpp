@@ -102,6 +102,22 @@ struct hx_ctx {
     float *aface32 = nullptr;
     double *fc64 = nullptr;       // [n_cells][3][8]   v- (3), v+ (3), sigma ds0 / 2, 0 of the +d face
     float *fc32 = nullptr;
+    // non-conforming (2:1) quarter faces: records {C, fc, F, s} (face fc of
+    // the coarse cell C, face fc ^ 1 of the fine cell F, quarter s)
+    int64_t n_hang = 0;
+    int32_t *hang = nullptr;      // [n_hang][4]
+    double *hgeo = nullptr;       // [n_hang][7][nf] ds J_C^-1 n, ds J_F^-1 n, ds / 2
+    double *hsig = nullptr;       // [n_hang] penalty
+    double *harea = nullptr;      // [n_hang] area
+    double *hdata64 = nullptr;    // [n_hang][7][nf] beta_C ds J_C^-1 n, beta_F ds J_F^-1 n, s
+    float *hdata32 = nullptr;
+    double *hcontrib64 = nullptr; // [n_hang][2][nd] staged contributions (coarse, fine side)
+    float *hcontrib32 = nullptr;
+    int64_t n_hcell = 0;          // cells with quarter faces
+    int32_t *hcells = nullptr;    // [n_hcell]
+    int32_t *hptr = nullptr;      // [n_hcell + 1]
+    int32_t *hlist = nullptr;     // [2 n_hang] record * 2 + side, by cell
+    double *endsig = nullptr;     // [n_cells][6] block-Jacobi penalty of non-conforming ends
     double *dg64 = nullptr;       // [2][n_dofs] inverse volume diagonals: mass + stiffness, mass
     float *dg32 = nullptr;
     double *cgpart = nullptr;     // [2][n_cells + 1] per-block partial sums of the fused CG steps
@@ -242,6 +258,12 @@ hipError_t launch_cg_massinv32(hx_ctx *c, float *x, float *r, const float *p, co
 // operator: y = A x, or y = b - A x when b != nullptr
 hipError_t launch_apply64(hx_ctx *c, const double *x, double *y, const double *b);
 hipError_t launch_apply32(hx_ctx *c, const float *x, float *y, const float *b);
+// non-conforming faces: geometry and penalties, merged data from nodal
+// beta, and y += (y -= with residual) the quarter faces' terms of A x
+hipError_t launch_hang_geometry(hx_ctx *c);
+hipError_t launch_hang_coefficients(hx_ctx *c, const double *beta);
+hipError_t launch_hang_apply64(hx_ctx *c, const double *x, double *y, bool residual);
+hipError_t launch_hang_apply32(hx_ctx *c, const float *x, float *y, bool residual);
 // cells per wave of the operator kernel at n points per direction
 int op_cells_per_wave(int n);
 // one part of A x: part 1 the cell integrals only, part 2 the face terms only

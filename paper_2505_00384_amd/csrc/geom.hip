@@ -211,8 +211,8 @@ __device__ void jacobi_eig(double (&A)[N][N], double (&V)[N][N])
 template <int N>
 __global__ void k_bj_eigen(int64_t n_cells, const int32_t *__restrict__ nbr,
                            const RefTab64 *__restrict__ T, const double *__restrict__ ell,
-                           const double *__restrict__ sigma, double *S64, float *S32, double *L64,
-                           float *L32)
+                           const double *__restrict__ sigma, const double *__restrict__ endsig,
+                           double *S64, float *S32, double *L64, float *L32)
 {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= 3 * n_cells) return;
@@ -220,8 +220,9 @@ __global__ void k_bj_eigen(int64_t n_cells, const int32_t *__restrict__ nbr,
     const int d = (int)(t % 3);
     const double l = ell[3 * c + d];
     const int32_t lo = nbr[6 * c + 2 * d], hi = nbr[6 * c + 2 * d + 1];
-    const double sig_lo = lo >= 0 ? sigma[3 * (int64_t)lo + d] : -1.0;
-    const double sig_hi = hi >= 0 ? sigma[3 * c + d] : -1.0;
+    // a non-conforming end (neighbour -2) takes its penalty from endsig
+    const double sig_lo = lo >= 0 ? sigma[3 * (int64_t)lo + d] : (lo == -2 ? endsig[6 * c + 2 * d] : -1.0);
+    const double sig_hi = hi >= 0 ? sigma[3 * c + d] : (hi == -2 ? endsig[6 * c + 2 * d + 1] : -1.0);
     double L[N][N];
     for (int i = 0; i < N; ++i)
         for (int j = 0; j < N; ++j) L[i][j] = T->L0[i * N + j];
@@ -592,8 +593,8 @@ template <int N>
 static hipError_t bj_eigen_n(hx_ctx *c)
 {
     hipLaunchKernelGGL(k_bj_eigen<N>, dim3(nblk(3 * c->n_cells, 64)), dim3(64), 0, c->stream,
-                       c->n_cells, c->nbr, c->ref, c->ell, c->sigma, c->bjS64, c->bjS32, c->bjL64,
-                       c->bjL32);
+                       c->n_cells, c->nbr, c->ref, c->ell, c->sigma, c->endsig, c->bjS64, c->bjS32,
+                       c->bjL64, c->bjL32);
     return hipGetLastError();
 }
 
@@ -645,6 +646,10 @@ hipError_t launch_set_coefficients(hx_ctx *c, const double *alpha, const double 
                        c->aface64, c->aface32, c->fc64, c->fc32);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (c->n_hang) {
+        e = launch_hang_coefficients(c, beta);
+        if (e != hipSuccess) return e;
+    }
     return launch_cell_diag(c);
 }
 

@@ -799,8 +799,8 @@ hipError_t apply_n(hx_ctx *c, const T *x, T *y, const T *b, double *dpart, int *
 }
 
 template <typename T>
-hipError_t apply_dispatch(hx_ctx *c, const T *x, T *y, const T *b, double *dpart = nullptr,
-                          int *nwg = nullptr, int part = 0)
+hipError_t apply_conforming(hx_ctx *c, const T *x, T *y, const T *b, double *dpart, int *nwg,
+                            int part)
 {
     switch (c->n) {
     case 2: return apply_n<2, T>(c, x, y, b, dpart, nwg, part);
@@ -812,6 +812,21 @@ hipError_t apply_dispatch(hx_ctx *c, const T *x, T *y, const T *b, double *dpart
     case 8: return apply_n<8, T>(c, x, y, b, dpart, nwg, part);
     default: return hipErrorInvalidValue;
     }
+}
+
+// the operator, then the terms of the non-conforming quarter faces (face
+// part); with quarter faces the fused x.(A x) of the CG variant is not used
+// (the callers take the dot product after the whole operator)
+template <typename T>
+hipError_t apply_dispatch(hx_ctx *c, const T *x, T *y, const T *b, double *dpart = nullptr,
+                          int *nwg = nullptr, int part = 0)
+{
+    hipError_t e = apply_conforming<T>(c, x, y, b, dpart, nwg, part);
+    if (e != hipSuccess || c->n_hang == 0 || part == 1) return e;
+    if constexpr (sizeof(T) == 8)
+        return launch_hang_apply64(c, (const double *)x, (double *)y, b != nullptr);
+    else
+        return launch_hang_apply32(c, (const float *)x, (float *)y, b != nullptr);
 }
 
 }  // namespace
@@ -853,6 +868,10 @@ int op_cells_per_wave(int n)
 // y = A x and dst = x.y (summed in a fixed order)
 hipError_t launch_apply64_dot(hx_ctx *c, const double *x, double *y, double *dst)
 {
+    if (c->n_hang) {
+        hipError_t e = apply_dispatch<double>(c, x, y, nullptr);
+        return e != hipSuccess ? e : blas_dot(c, c->n_dofs, x, y, dst);
+    }
     int nwg = 0;
     hipError_t e = apply_dispatch<double>(c, x, y, nullptr, c->cgpart, &nwg);
     return e != hipSuccess ? e : reduce_parts(c, c->cgpart, nwg, dst);
@@ -860,6 +879,10 @@ hipError_t launch_apply64_dot(hx_ctx *c, const double *x, double *y, double *dst
 
 hipError_t launch_apply32_dot(hx_ctx *c, const float *x, float *y, double *dst)
 {
+    if (c->n_hang) {
+        hipError_t e = apply_dispatch<float>(c, x, y, nullptr);
+        return e != hipSuccess ? e : blas_dot32(c, c->n_dofs, x, y, dst);
+    }
     int nwg = 0;
     hipError_t e = apply_dispatch<float>(c, x, y, nullptr, c->cgpart, &nwg);
     return e != hipSuccess ? e : reduce_parts(c, c->cgpart, nwg, dst);

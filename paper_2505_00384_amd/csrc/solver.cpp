@@ -840,6 +840,8 @@ hx_status hx_set_multigrid(hx_ctx *c, hx_ctx *coarse, const int32_t *parent, con
     c->mg_coarse = nullptr;
     c->mg_nc = 0;
     if (!coarse) return HX_OK;
+    if (c->n_hang || coarse->n_hang)
+        return fail(c, HX_ERR_STATE, "multigrid levels are uniform refinements; this mesh has hanging faces");
     if (!c->has_mesh || !coarse->has_mesh) return fail(c, HX_ERR_STATE, "set_multigrid before setup_mesh");
     if (!parent || !octant) return fail(c, HX_ERR_ARG, "parent and octant are required");
     if (coarse->device != c->device || coarse->stream != c->stream)

@@ -23,7 +23,7 @@ def problem(mesh, k, coef="random", seed=0, P=2.0):
 def gpu_context(p):
     import paper_2505_00384_amd as hx
     ctx = hx.HelmDG(0)
-    ctx.setup_mesh(p.k, p.nodes, p.nbr, p.g)
+    ctx.setup_mesh(p.k, p.nodes, p.nbr, p.g, hang=p.hang if p.hang.shape[0] else None)
     ctx.set_coefficients(p.alpha, p.beta, p.P)
     return ctx
 
