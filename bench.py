@@ -77,7 +77,7 @@ def setup(ctx_cls, mesh, k, torch, dev, timing=None):
     from synth_inputs import terrain_coefficients
     ctx = ctx_cls(0)
     t0 = time.time()
-    ctx.setup_mesh(k, mesh.nodes, mesh.nbr, mesh.g)
+    ctx.setup_mesh(k, mesh.nodes, mesh.nbr, mesh.g, hang=getattr(mesh, "hang", None))
     torch.cuda.synchronize()
     t1 = time.time()
     xyz = ctx.dof_coordinates()
@@ -154,6 +154,41 @@ def operator_windows(hx, ctx, x, y, torch, n, op_bytes, counts):
         cell_part_ms=round(t_cell, 4), face_part_ms=round(t_face, 4),
         general_data_ms=round(t_gen, 4), general_bytes_per_dof=round(gen_bytes / n, 2),
         general_data_frac=round(gen_bytes / (t_gen * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
+
+
+def nonconforming_suite(hx, torch, dev, k):
+    """The 32x8x16 terrain channel with the cells over the ridge refined once
+    (the middle half in x, the bottom half in z: a non-conforming mesh with
+    2:1 faces, like the paper's second mesh around its hill): the operator,
+    and CG / FGMRES to 1e-8 with block Jacobi and with the paper's two
+    diagonal preconditioners (section 3.1: the Helmholtz one, the inverse
+    diagonal of the volume terms, against the internal-energy one, the
+    inverse mass diagonal)."""
+    import synth_inputs as si
+    m = si.refined_terrain_mesh(32, 8, 16, g=4)
+    ctx, xyz, _ = setup(hx.HelmDG, m, k, torch, dev)
+    b = rhs_on_device(xyz, 0, torch)
+    del xyz
+    y = torch.empty_like(b)
+    ms = time_matvec(ctx, b, y, 50, 5, torch)
+    counts, op_bytes = ctx.operator_info(hx.HX_F64)
+    out = dict(cells=m.n_cells, quarter_faces=int(m.hang.shape[0]), n_dofs=ctx.n_dofs,
+               matvec_ms=round(ms, 4), gdofs=round(ctx.n_dofs / (ms * 1e-3) / 1e9, 3),
+               bytes_per_dof=round(op_bytes / ctx.n_dofs, 2))
+    out["solve"] = solve_suite(hx, ctx, b, torch, [
+        ("fp64_cg_bj", hx.default_params(method=0, rtol=1e-8)),
+        ("fp64_cg_helmholtz_diag", hx.default_params(method=0, rtol=1e-8, max_iter=20000,
+                                                     pc=hx.HX_PC_HELMHOLTZ_DIAG)),
+        ("fp64_cg_mass_diag", hx.default_params(method=0, rtol=1e-8, max_iter=20000,
+                                                pc=hx.HX_PC_MASS_DIAG)),
+        ("fp64_fgmres_helmholtz_diag", hx.default_params(method=1, restart=30, rtol=1e-8,
+                                                         max_iter=20000, pc=hx.HX_PC_HELMHOLTZ_DIAG)),
+        ("fp64_fgmres_mass_diag", hx.default_params(method=1, restart=30, rtol=1e-8,
+                                                    max_iter=20000, pc=hx.HX_PC_MASS_DIAG)),
+        ("mixed_fp32_inner", hx.default_params(method=1, restart=10, rtol=1e-8, mixed=1,
+                                               inner_iters=32))], "nonconforming")
+    ctx.close()
+    return out
 
 
 def solve_suite(hx, ctx, b, torch, forms, label, keep=None):
@@ -660,6 +695,8 @@ def main():
                                               keep=kept.setdefault("terrain32x8x16", {}))
         solve["learned_training_s"] = round(t_train, 2)
         w = ctx2.get_network()
+        solve["terrain32x8x16_refined"] = nonconforming_suite(hx, torch, dev, k)
+        log(f"nonconforming: {solve['terrain32x8x16_refined']}")
         pressure["terrain32x8x16"] = pressure_suite(hx, ctx2, torch, "C2", [
             ("fgmres_helmholtz_diag", hx.default_params(method=1, system=1, restart=30, rtol=1e-8,
                                                         max_iter=20000, pc=hx.HX_PC_HELMHOLTZ_DIAG)),

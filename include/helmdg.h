@@ -231,7 +231,8 @@ typedef struct {
                             (HX_PC_LEARNED is not allowed there) */
     int mixed;           /* 1: outer FP64 FGMRES, preconditioner = inner FP32 CG */
     int inner_iters;     /* inner FP32 CG iterations per outer step (mixed; 32) */
-    double inner_rtol;   /* inner stopping tolerance (relative, mixed) */
+    double inner_rtol;   /* not used: the inner FP32 CG runs inner_iters iterations with its
+                            scalars on the device, so it has no stopping test */
     int x0_mode;         /* 0: start from zero, 1: x holds the initial guess */
     int stall_window;    /* FGMRES stall rule window (10); 0 disables it */
     double stall_ratio;  /* stall if estimate > ratio * estimate window ago (0.99) */
@@ -267,7 +268,7 @@ typedef struct {
 } hx_solve_info;
 
 /* Fill p with the defaults (CG, restart 30, rtol 1e-8, max_iter 10000, block
- * Jacobi, FP64, inner 12 iterations / 1e-2, zero initial guess, stall 10/0.99). */
+ * Jacobi, FP64, inner 12 iterations, zero initial guess, stall 10/0.99). */
 void hx_default_params(hx_solve_params *p);
 
 /* Solve A x = b.  b, x: DEVICE FP64 [n_dofs]; x is the initial guess if
@@ -447,9 +448,10 @@ hx_status hx_gather_features(hx_ctx *c, const double *r, float *feats, float *sc
  * and e = x_star - x_j, feats = features(r) as in hx_gather_features and
  * targets DEVICE float [n_cells][n_out] = (e_K - BJ(r)_K) / w_K, w_K = RMS(BJ(r)_K):
  * the part of the error that block Jacobi misses, in the network's output
- * scaling. */
+ * scaling; with clip > 0 each target is limited to [-clip, clip] (0: none;
+ * negative: HX_ERR_ARG). */
 hx_status hx_training_pair(hx_ctx *c, const double *b, const double *x_star, const double *x_j,
-                           float *feats, float *targets);
+                           float clip, float *feats, float *targets);
 
 /* out DEVICE float [batch][n_out] = network(feats DEVICE float [batch][n_in]). */
 hx_status hx_network_forward(hx_ctx *c, const float *feats, int64_t batch, float *out);
@@ -477,6 +479,25 @@ int64_t hx_network_noalloc_max_batch(const hx_ctx *c);
  * gradient is also returned and, if lr == 0, no update is made. */
 hx_status hx_train_step(hx_ctx *c, const float *feats, const float *targets,
                         int64_t batch, float lr, float *loss_out, float *grad_out);
+
+/* Intermediates of the last hx_train_step, for checking each layer on the
+ * operands the GPU actually used.  what (all FP32, row-major, batch rows):
+ *   HX_TRACE_INPUT  [batch][n_in]  the BF16-rounded inputs;
+ *   HX_TRACE_H1/H2  [batch][256]   hidden layer 1/2 after bias and ReLU,
+ *                                  before the BF16 rounding of the next product;
+ *   HX_TRACE_OUT    [batch][n_out] the network output;
+ *   HX_TRACE_DOUT   [batch][n_out] d loss / d output, before BF16 rounding;
+ *   HX_TRACE_DH2/DH1 [batch][256]  d loss / d pre-activation of hidden layer
+ *                                  2/1 (ReLU mask applied), before BF16 rounding.
+ * count = the number of floats of the HOST buffer and must equal the size
+ * above (HX_ERR_ARG otherwise); HX_ERR_STATE when no step has been taken or
+ * a call that shares the step's work buffers (hx_network_forward,
+ * hx_training_pair) has run since.  Synchronous. */
+enum {
+    HX_TRACE_INPUT = 0, HX_TRACE_H1 = 1, HX_TRACE_H2 = 2, HX_TRACE_OUT = 3,
+    HX_TRACE_DOUT = 4, HX_TRACE_DH2 = 5, HX_TRACE_DH1 = 6
+};
+hx_status hx_network_trace(hx_ctx *c, int what, float *host_buf, int64_t count);
 
 /* ---------------------------------------------------------------------- */
 /* inspection                                                              */

@@ -46,6 +46,25 @@ def unpack(params: np.ndarray, n_in=276, hidden=256, n_out=125):
     return out
 
 
+def layer(W, bvec, a, bf16=True):
+    """Pre-activation a W^T + b of one layer whose input activations a are
+    already in working precision (the weights are rounded here)."""
+    rnd = bf16_round if bf16 else (lambda v: np.asarray(v, dtype=np.float64))
+    return np.asarray(a, dtype=np.float64) @ rnd(W).T + bvec
+
+
+def layer_grads(W, d, a, bf16=True):
+    """Back-propagation through one layer: d = d loss / d pre-activation
+    [B, out], a = the layer's input activations [B, in].  Returns
+    (d loss / d W, d loss / d b, d loss / d a); with ``bf16`` d enters the
+    two products rounded, as on the GPU, and the bias gradient takes it
+    unrounded."""
+    rnd = bf16_round if bf16 else (lambda v: np.asarray(v, dtype=np.float64))
+    d = np.asarray(d, dtype=np.float64)
+    dr = rnd(d)
+    return dr.T @ np.asarray(a, dtype=np.float64), d.sum(axis=0), dr @ rnd(W)
+
+
 def forward(params, X, bf16=True):
     """X: [B, n_in].  Returns (output [B, n_out], cache)."""
     layers = unpack(params, X.shape[1])
@@ -54,7 +73,7 @@ def forward(params, X, bf16=True):
     cache = [a]
     pre = []
     for li, (W, bv) in enumerate(layers):
-        z = a @ rnd(W).T + bv
+        z = layer(W, bv, a, bf16)
         pre.append(z)
         if li < len(layers) - 1:
             a = rnd(np.maximum(z, 0.0))
@@ -74,7 +93,6 @@ def backward(params, X, target, bf16=True):
     With ``bf16`` the output gradient and back-propagated activation gradients
     are rounded to BF16 before they enter the next product, as the GPU does."""
     layers = unpack(params, X.shape[1])
-    rnd = bf16_round if bf16 else (lambda a: np.asarray(a, dtype=np.float64))
     out, (acts, pre) = forward(params, X, bf16)
     B, n_out = out.shape
     loss = mse(out, target)
@@ -82,12 +100,9 @@ def backward(params, X, target, bf16=True):
     grads = []
     for li in range(len(layers) - 1, -1, -1):
         W, _ = layers[li]
-        dr = rnd(d)
-        gW = dr.T @ acts[li]
-        gb = d.sum(axis=0)
+        gW, gb, da = layer_grads(W, d, acts[li], bf16)
         grads.append((gW, gb))
         if li > 0:
-            da = dr @ rnd(W)
             d = da * (pre[li - 1] > 0)
     grads.reverse()
     flat = np.concatenate([np.concatenate([gW.ravel(), gb]) for gW, gb in grads])

@@ -27,6 +27,8 @@ HX_EXPORT_CELL_DATA, HX_EXPORT_FACE_DATA, HX_EXPORT_SIGMA, HX_EXPORT_VOLUME, \
     HX_EXPORT_BJ_SCALARS, HX_EXPORT_INV_DIAG = range(6)
 HX_PS_GRAD, HX_PS_DIV, HX_PS_VMASS_INV, HX_PS_DMASS, HX_PS_SYSTEM = range(5)
 HX_PART_CELL, HX_PART_FACE = 1, 2
+HX_TRACE_INPUT, HX_TRACE_H1, HX_TRACE_H2, HX_TRACE_OUT, HX_TRACE_DOUT, HX_TRACE_DH2, \
+    HX_TRACE_DH1 = range(7)
 
 STATUS_NAMES = {0: "HX_OK", 1: "HX_ERR_ARG", 2: "HX_ERR_STATE", 3: "HX_ERR_DEVICE",
                 4: "HX_ERR_OOM", 5: "HX_ERR_MESH", 6: "HX_ERR_NOCONV",
@@ -93,8 +95,9 @@ def load(path: str = LIB_PATH):
         "hx_gather_features": ([vp, vp, vp, vp], C.c_int),
         "hx_network_forward": ([vp, vp, i64, vp], C.c_int),
         "hx_network_forward_noalloc": ([vp, vp, i64, vp], C.c_int),
+        "hx_network_trace": ([vp, C.c_int, vp, i64], C.c_int),
         "hx_network_noalloc_max_batch": ([vp], i64),
-        "hx_training_pair": ([vp, vp, vp, vp, vp, vp], C.c_int),
+        "hx_training_pair": ([vp, vp, vp, vp, C.c_float, vp, vp], C.c_int),
         "hx_train_step": ([vp, vp, vp, i64, C.c_float, C.POINTER(C.c_float), vp], C.c_int),
         "hx_debug_export": ([vp, C.c_int, vp, i64], C.c_int),
         "hx_set_pressure_system": ([vp, vp, vp, C.c_double, C.c_double, C.c_double, C.c_int],
@@ -410,14 +413,15 @@ class HelmDG:
         self._chk(self.L.hx_gather_features(self.h, _ptr(r), _ptr(F), _ptr(s)), "gather_features")
         return F, s
 
-    def training_pair(self, b, x_star, x_j):
-        """Per-cell features and residual-learning targets from a solver iterate."""
+    def training_pair(self, b, x_star, x_j, clip: float = 0.0):
+        """Per-cell features and residual-learning targets from a solver
+        iterate (targets limited to [-clip, clip] when clip > 0)."""
         F = self.torch.empty(self.n_cells, self.n_features(), dtype=self.torch.float32,
                              device=b.device)
         T = self.torch.empty(self.n_cells, (self.k + 1) ** 3, dtype=self.torch.float32,
                              device=b.device)
-        self._chk(self.L.hx_training_pair(self.h, _ptr(b), _ptr(x_star), _ptr(x_j), _ptr(F), _ptr(T)),
-                  "training_pair")
+        self._chk(self.L.hx_training_pair(self.h, _ptr(b), _ptr(x_star), _ptr(x_j), float(clip), _ptr(F),
+                                          _ptr(T)), "training_pair")
         return F, T
 
     def network_forward(self, feats):
@@ -452,6 +456,15 @@ class HelmDG:
                                        _ptr(g) if g is not None else None),
                   "train_step")
         return (loss.value if want_loss else None), g
+
+    def network_trace(self, what: int, batch: int) -> np.ndarray:
+        """One intermediate of the last train_step (HX_TRACE_*), [batch, width]."""
+        n, hid = self.k + 1, 256
+        width = {HX_TRACE_INPUT: n ** 3 + 6 * n * n + 1, HX_TRACE_OUT: n ** 3,
+                 HX_TRACE_DOUT: n ** 3}.get(what, hid)
+        out = np.zeros((batch, width), dtype=np.float32)
+        self._chk(self.L.hx_network_trace(self.h, what, out.ctypes.data, out.size), "network_trace")
+        return out
 
     def debug_export(self, what: int, shape, dtype=np.float64) -> np.ndarray:
         out = np.zeros(shape, dtype=dtype)

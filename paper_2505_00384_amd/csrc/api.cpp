@@ -726,8 +726,7 @@ hx_status hx_apply_preconditioner(hx_ctx *c, hx_pc kind, hx_prec prec, const voi
         return HX_OK;
     case HX_PC_LEARNED: {
         if (prec != HX_F64) return fail(c, HX_ERR_ARG, "learned preconditioner is FP64-in/out");
-        int nonfinite = 0;
-        return mlp_precondition(c, (const double *)r, (double *)z, &nonfinite);
+        return mlp_precondition(c, (const double *)r, (double *)z);
     }
     default:
         return fail(c, HX_ERR_ARG, "unknown preconditioner %d", (int)kind);
@@ -768,13 +767,14 @@ hx_status hx_gather_features(hx_ctx *c, const double *r, float *feats, float *sc
 }
 
 hx_status hx_training_pair(hx_ctx *c, const double *b, const double *x_star, const double *x_j,
-                           float *feats, float *targets)
+                           float clip, float *feats, float *targets)
 {
     if (!c) return HX_ERR_ARG;
     if (!c->has_coef) return fail(c, HX_ERR_STATE, "training pair before set_coefficients");
     if (!b || !x_star || !x_j || !feats || !targets) return fail(c, HX_ERR_ARG, "null pointer");
     if (x_j == b) return fail(c, HX_ERR_ARG, "x_j and b alias");
-    return mlp_training_pair(c, b, x_star, x_j, feats, targets);
+    if (!(clip >= 0.0f)) return fail(c, HX_ERR_ARG, "clip must be >= 0");
+    return mlp_training_pair(c, b, x_star, x_j, clip, feats, targets);
 }
 
 hx_status hx_network_forward(hx_ctx *c, const float *feats, int64_t batch, float *out)
@@ -803,6 +803,13 @@ hx_status hx_train_step(hx_ctx *c, const float *feats, const float *targets, int
     if (!c) return HX_ERR_ARG;
     if (!feats || !targets || batch <= 0) return fail(c, HX_ERR_ARG, "bad training arguments");
     return mlp_train(c, feats, targets, batch, lr, loss_out, grad_out);
+}
+
+hx_status hx_network_trace(hx_ctx *c, int what, float *host_buf, int64_t count)
+{
+    if (!c) return HX_ERR_ARG;
+    if (!host_buf || count < 0) return fail(c, HX_ERR_ARG, "null buffer or negative count");
+    return mlp_trace(c, what, host_buf, count);
 }
 
 hx_status hx_debug_export(hx_ctx *c, int what, void *host_buf, int64_t bytes)

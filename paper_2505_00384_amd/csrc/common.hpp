@@ -334,8 +334,10 @@ int64_t mlp_noalloc_max_batch(const hx_ctx *c);
 hx_status mlp_forward_noalloc(hx_ctx *c, const float *feats, int64_t batch, float *out);
 hx_status mlp_train(hx_ctx *c, const float *feats, const float *targets, int64_t batch,
                     float lr, float *loss_out, float *grad_out);
-hx_status mlp_precondition(hx_ctx *c, const double *r, double *z, int *nonfinite);
+hx_status mlp_precondition(hx_ctx *c, const double *r, double *z);
+hx_status mlp_precondition_batched(hx_ctx *c, const double *r, double *z);
+hx_status mlp_trace(hx_ctx *c, int what, float *host_buf, int64_t count);
 hx_status mlp_training_pair(hx_ctx *c, const double *b, const double *xs, const double *xj,
-                            float *feats, float *targets);
+                            float clip, float *feats, float *targets);
 
 }  // namespace hx

@@ -18,6 +18,7 @@
 #include "common.hpp"
 
 #include <cmath>
+#include <cstring>
 #include <mutex>
 #include <vector>
 
@@ -376,11 +377,169 @@ k_add_correction(int nd, const float *__restrict__ o, double *z)
     for (int e = threadIdx.x; e < nd; e += 128) z[c * nd + e] += w * (double)o[c * nd + e];
 }
 
+// ---------------------------------------------------------------------------
+// The learned correction in one launch (after block Jacobi has written z):
+// a workgroup of 4 waves serves 16 cells.  It forms their features (as
+// k_features: r_K, the six neighbours' face layers and the coefficient
+// feature, scaled by 1 / RMS(r_K)) in LDS as BF16, runs the three layers on
+// v_mfma_f32_16x16x32_bf16 with the hidden activations in LDS (each wave owns
+// a quarter of every layer's outputs and loads the weight fragments of up to
+// eight k-steps at once, so their latency is paid once per chunk), and adds
+// z_K += w_K net(features)_K with w_K = RMS(z_K) of the block-Jacobi output.
+// Fragment layout of the MFMA: lane l holds A[m = l % 16][k = 8 (l / 16) ..
+// + 7] and B[k][n = l % 16] likewise, and receives C[4 (l / 16) + q][l % 16].
+constexpr int FT = 16;   // cells per workgroup of the fused kernel
+
+template <int K, int NT, int LDA, int LDB>
+__device__ __forceinline__ void fused_layer(const uint16_t (*sA)[LDA], const uint16_t *__restrict__ W,
+                                            int n_rows, int ct0, int lane, f32x4 (&acc)[NT])
+{
+    // k-steps, and k-steps per chunk of weight loads (at most 32 fragments
+    // of 16 bytes in flight per lane)
+    constexpr int KS = K / 32, CH0 = 32 / NT > 1 ? 32 / NT : 1, CH = CH0 < KS ? CH0 : KS;
+    const int rr = lane & 15, kq = (lane >> 4) * 8;
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k0 = 0; k0 < KS; k0 += CH) {
+        uint4 fb[CH][NT];
+#pragma unroll
+        for (int s = 0; s < CH; ++s) {
+            if (k0 + s >= KS) break;
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+                const int row = (ct0 + j) * 16 + rr;
+                fb[s][j] = row < n_rows ? *(const uint4 *)(W + (int64_t)row * LDB + (k0 + s) * 32 + kq)
+                                        : uint4{0u, 0u, 0u, 0u};
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < CH; ++s) {
+            if (k0 + s >= KS) break;
+            const bf16x8 fa = __builtin_bit_cast(bf16x8, *(const uint4 *)&sA[rr][(k0 + s) * 32 + kq]);
+#pragma unroll
+            for (int j = 0; j < NT; ++j)
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, __builtin_bit_cast(bf16x8, fb[s][j]),
+                                                                 acc[j], 0, 0, 0);
+        }
+    }
+}
+
+template <int N>
+__global__ void __launch_bounds__(256)
+k_mlp_fused(int64_t n_cells, const double *__restrict__ r, double *__restrict__ z,
+            const int32_t *__restrict__ nbr, const double *__restrict__ coef,
+            const uint16_t *__restrict__ w1b, const uint16_t *__restrict__ w2b,
+            const uint16_t *__restrict__ w3b, const float *__restrict__ b1, const float *__restrict__ b2,
+            const float *__restrict__ b3)
+{
+    constexpr int NF = N * N, ND = NF * N, NIN = ND + 6 * NF + 1, LDX = ((NIN + 31) / 32) * 32;
+    constexpr int NT3 = (ND + 15) / 16, PER3 = (NT3 + 3) / 4;
+    __shared__ __align__(16) uint16_t sX[FT][LDX + 8];
+    __shared__ __align__(16) uint16_t sH[FT][HID + 8];
+    __shared__ __align__(16) uint16_t sH2[FT][HID + 8];
+    __shared__ double sS[FT], sW[FT];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t c0 = (int64_t)blockIdx.x * FT;
+    // RMS of r_K and of the block-Jacobi output z_K: 16 threads per cell
+    {
+        const int cl = tid >> 4, sub = tid & 15;
+        const int64_t c = c0 + cl;
+        double sr = 0.0, sz = 0.0;
+        if (c < n_cells)
+            for (int e = sub; e < ND; e += 16) {
+                const double v = r[c * ND + e], u = z[c * ND + e];
+                sr += v * v;
+                sz += u * u;
+            }
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) {
+            sr += __shfl_xor(sr, o, 64);
+            sz += __shfl_xor(sz, o, 64);
+        }
+        if (sub == 0) {
+            sS[cl] = sqrt(sr / ND);
+            sW[cl] = sqrt(sz / ND);
+        }
+    }
+    __syncthreads();
+    // features, BF16
+    for (int idx = tid; idx < FT * LDX; idx += 256) {
+        const int cl = idx / LDX, e = idx % LDX;
+        const int64_t c = c0 + cl;
+        float fv = 0.f;
+        if (c < n_cells && e < NIN) {
+            const double sK = sS[cl], inv = sK > 0.0 ? 1.0 / sK : 0.0;
+            double v = 0.0;
+            if (e < ND) {
+                v = r[c * ND + e] * inv;
+            } else if (e < ND + 6 * NF) {
+                const int f = (e - ND) / NF, t = (e - ND) % NF;
+                const int32_t nb = nbr[c * 6 + f];
+                if (nb >= 0) {
+                    const int d = f >> 1, m = (f & 1) ? 0 : N - 1;   // the neighbour's touching layer
+                    const int p = t % N, q = t / N;
+                    int ijk[3];
+                    ijk[d] = m;
+                    ijk[d == 0 ? 1 : 0] = p;
+                    ijk[d == 2 ? 1 : 2] = q;
+                    v = r[(int64_t)nb * ND + ijk[0] + N * (ijk[1] + N * ijk[2])] * inv;
+                }
+            } else {
+                v = sK > 0.0 ? coef[c] : 0.0;
+            }
+            fv = (float)v;
+        }
+        sX[cl][e] = f2bf(fv);
+    }
+    __syncthreads();
+    const int ccol = lane & 15, crow = 4 * (lane >> 4);
+    // layer 1: each wave 4 of the 16 column tiles
+    {
+        f32x4 acc[4];
+        fused_layer<LDX, 4, LDX + 8, LDX>(sX, w1b, HID, 4 * wave, lane, acc);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int n = (4 * wave + j) * 16 + ccol;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sH[crow + q][n] = f2bf(fmaxf(acc[j][q] + b1[n], 0.f));
+        }
+    }
+    __syncthreads();
+    // layer 2
+    {
+        f32x4 acc[4];
+        fused_layer<HID, 4, HID + 8, HID>(sH, w2b, HID, 4 * wave, lane, acc);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int n = (4 * wave + j) * 16 + ccol;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sH2[crow + q][n] = f2bf(fmaxf(acc[j][q] + b2[n], 0.f));
+        }
+    }
+    __syncthreads();
+    // layer 3 and the correction
+    {
+        f32x4 acc[PER3];
+        fused_layer<HID, PER3, HID + 8, HID>(sH2, w3b, ND, PER3 * wave, lane, acc);
+#pragma unroll
+        for (int j = 0; j < PER3; ++j) {
+            const int n = (PER3 * wave + j) * 16 + ccol;
+            if (n >= ND) continue;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t c = c0 + crow + q;
+                if (c < n_cells) z[c * ND + n] += sW[crow + q] * (double)(acc[j][q] + b3[n]);
+            }
+        }
+    }
+}
+
 // targets[c][i] = (e[c][i] - z[c][i]) / w_c with e = xs - xj, w_c = RMS(z_c)
-// (0 when w_c = 0)
+// (0 when w_c = 0), limited to [-clip, clip] when clip > 0
 __global__ void __launch_bounds__(128)
 k_targets(int nd, const double *__restrict__ xs, const double *__restrict__ xj,
-          const double *__restrict__ z, float *tg)
+          const double *__restrict__ z, float clip, float *tg)
 {
     const int64_t c = blockIdx.x;
     __shared__ double red[128];
@@ -399,7 +558,9 @@ k_targets(int nd, const double *__restrict__ xs, const double *__restrict__ xj,
     const double inv = w > 0.0 ? 1.0 / w : 0.0;
     for (int e = threadIdx.x; e < nd; e += 128) {
         const int64_t i = c * nd + e;
-        tg[i] = (float)((xs[i] - xj[i] - z[i]) * inv);
+        float t = (float)((xs[i] - xj[i] - z[i]) * inv);
+        if (clip > 0.f) t = fminf(fmaxf(t, -clip), clip);
+        tg[i] = t;
     }
 }
 
@@ -415,6 +576,7 @@ struct MlpState {
     uint16_t *w1b = nullptr, *w2b = nullptr, *w3b = nullptr;
     int64_t t = 0;
     int64_t cap = 0;
+    int64_t trace_B = 0;     // batch of the last training step whose buffers are intact
     uint16_t *xb = nullptr, *h1b = nullptr, *h2b = nullptr, *dob = nullptr, *dh1b = nullptr,
              *dh2b = nullptr;
     float *h1 = nullptr, *h2 = nullptr, *o = nullptr, *d_o = nullptr, *dh1 = nullptr,
@@ -436,6 +598,7 @@ static void free_batch(MlpState *s)
 static hx_status ensure_batch(hx_ctx *c, int64_t B)
 {
     MlpState *s = c->mlp;
+    s->trace_B = 0;
     if (B <= s->cap) return HX_OK;
     free_batch(s);
     hx_status st = HX_OK;
@@ -705,6 +868,7 @@ hx_status mlp_train(hx_ctx *c, const float *feats, const float *targets, int64_t
                    g + s->off_w1, s->n_in, nullptr, 0));
     hipLaunchKernelGGL(k_colsum, dim3(HID), dim3(256), 0, q, B, HID, s->dh1, g + s->off_b1);
     HX_HIP(c, hipGetLastError());
+    s->trace_B = B;
     if (grad_out)
         HX_HIP(c, hipMemcpyAsync(grad_out, g, 4 * (size_t)s->P, hipMemcpyDeviceToDevice, q));
     if (lr != 0.0f) {
@@ -723,10 +887,47 @@ hx_status mlp_train(hx_ctx *c, const float *feats, const float *targets, int64_t
     return HX_OK;
 }
 
+hx_status mlp_trace(hx_ctx *c, int what, float *host_buf, int64_t count)
+{
+    MlpState *s = c->mlp;
+    if (!s || s->trace_B == 0) return fail(c, HX_ERR_STATE, "no training step to trace");
+    const int64_t B = s->trace_B;
+    const float *src = nullptr;
+    int width = HID;
+    switch (what) {
+    case HX_TRACE_INPUT: width = s->n_in; break;
+    case HX_TRACE_H1: src = s->h1; break;
+    case HX_TRACE_H2: src = s->h2; break;
+    case HX_TRACE_OUT: src = s->o; width = s->n_out; break;
+    case HX_TRACE_DOUT: src = s->d_o; width = s->n_out; break;
+    case HX_TRACE_DH2: src = s->dh2; break;
+    case HX_TRACE_DH1: src = s->dh1; break;
+    default: return fail(c, HX_ERR_ARG, "unknown trace %d", what);
+    }
+    if (count != B * width)
+        return fail(c, HX_ERR_ARG, "trace %d has %lld values, buffer holds %lld", what,
+                    (long long)(B * width), (long long)count);
+    if (src) {
+        HX_HIP(c, hipMemcpyAsync(host_buf, src, 4 * (size_t)count, hipMemcpyDeviceToHost, c->stream));
+        HX_HIP(c, hipStreamSynchronize(c->stream));
+        return HX_OK;
+    }
+    // the packed BF16 inputs: rows of ldx, the first n_in columns widened to FP32
+    std::vector<uint16_t> tmp((size_t)B * s->ldx);
+    HX_HIP(c, hipMemcpyAsync(tmp.data(), s->xb, 2 * tmp.size(), hipMemcpyDeviceToHost, c->stream));
+    HX_HIP(c, hipStreamSynchronize(c->stream));
+    for (int64_t b = 0; b < B; ++b)
+        for (int j = 0; j < s->n_in; ++j) {
+            const uint32_t u = (uint32_t)tmp[(size_t)b * s->ldx + j] << 16;
+            std::memcpy(&host_buf[b * s->n_in + j], &u, 4);
+        }
+    return HX_OK;
+}
+
 // one training pair per cell from a solver iterate xj of A x = b with solution xs:
 // r = b - A xj, features(r), targets = (xs - xj - BJ(r)) / RMS(BJ(r)) per cell
 hx_status mlp_training_pair(hx_ctx *c, const double *b, const double *xs, const double *xj,
-                            float *feats, float *targets)
+                            float clip, float *feats, float *targets)
 {
     MlpState *s = c->mlp;
     if (!s) {
@@ -745,15 +946,47 @@ hx_status mlp_training_pair(hx_ctx *c, const double *b, const double *xs, const 
     HX_HIP(c, launch_bj64(c, r, z));
     HX_HIP(c, (mlp_features(c, r, feats, s->scale) == HX_OK) ? hipSuccess : hipErrorUnknown);
     hipLaunchKernelGGL(k_targets, dim3((unsigned)c->n_cells), dim3(128), 0, c->stream, c->nd, xs, xj,
-                       z, targets);
+                       z, clip, targets);
     HX_HIP(c, hipGetLastError());
     return HX_OK;
 }
 
 // z = BJ(r) + w_K net(features(r))_K, w_K = RMS(BJ(r)_K)
-hx_status mlp_precondition(hx_ctx *c, const double *r, double *z, int *nonfinite)
+template <int N>
+static hipError_t mlp_fused_n(hx_ctx *c, const double *r, double *z)
 {
-    *nonfinite = 0;
+    MlpState *s = c->mlp;
+    hipLaunchKernelGGL((k_mlp_fused<N>), dim3((unsigned)((c->n_cells + FT - 1) / FT)), dim3(256), 0,
+                       c->stream, c->n_cells, r, z, c->nbr, c->coef_feat, s->w1b, s->w2b, s->w3b,
+                       s->w + s->off_b1, s->w + s->off_b2, s->w + s->off_b3);
+    return hipGetLastError();
+}
+
+// z = BJ(r) + w_K net(features(r))_K: block Jacobi, then the fused
+// correction.  A non-finite z shows up in the FGMRES Hessenberg column,
+// where the Givens step rejects it and the solver switches to block Jacobi.
+hx_status mlp_precondition(hx_ctx *c, const double *r, double *z)
+{
+    if (!c->mlp) return fail(c, HX_ERR_STATE, "no network loaded");
+    HX_HIP(c, launch_bj64(c, r, z));
+    hipError_t e = hipSuccess;
+    switch (c->n) {
+    case 2: e = mlp_fused_n<2>(c, r, z); break;
+    case 3: e = mlp_fused_n<3>(c, r, z); break;
+    case 4: e = mlp_fused_n<4>(c, r, z); break;
+    case 5: e = mlp_fused_n<5>(c, r, z); break;
+    case 6: e = mlp_fused_n<6>(c, r, z); break;
+    case 7: e = mlp_fused_n<7>(c, r, z); break;
+    default: e = mlp_fused_n<8>(c, r, z); break;
+    }
+    HX_HIP(c, e);
+    return HX_OK;
+}
+
+// The batched form of the same preconditioner (features, the three layers
+// as separate GEMM launches, block Jacobi, correction); kept for comparison.
+hx_status mlp_precondition_batched(hx_ctx *c, const double *r, double *z)
+{
     if (!c->mlp) return fail(c, HX_ERR_STATE, "no network loaded");
     MlpState *s = c->mlp;
     hx_status st = ensure_batch(c, c->n_cells);

@@ -14,9 +14,11 @@
 //    iterations with all scalars kept on the device; the outer residual,
 //    orthogonalisation and update stay FP64 (iterative refinement through the
 //    explicit FP64 residual at each restart).
-//  * Learned: block Jacobi plus the network correction; if the preconditioned
-//    vector is not finite or the residual estimate stalls over stall_window
-//    iterations, the solver restarts from the current x with block Jacobi.
+//  * Learned: block Jacobi plus the network correction; if the residual
+//    estimate stalls over stall_window iterations, or the preconditioned
+//    vector is not finite (its Hessenberg column is then not finite and the
+//    Givens step rejects it), the solver restarts from the current x with
+//    block Jacobi.
 #include <chrono>
 #include <algorithm>
 #include <cmath>
@@ -132,14 +134,13 @@ hx_status inner_fp32(hx_ctx *c, int pc, const double *v, double *z, float *w32, 
 }
 
 hx_status precondition(hx_ctx *c, int pc, int mixed, int inner_iters, const double *v, double *z,
-                       float *w32, int *inner_count, int *nonfinite)
+                       float *w32, int *inner_count)
 {
-    *nonfinite = 0;
     if (mixed) return inner_fp32(c, pc, v, z, w32, inner_iters, inner_count);
     switch (pc) {
     case HX_PC_NONE: HX_HIP(c, blas_copy(c, c->n_dofs, v, z)); return HX_OK;
     case HX_PC_BLOCK_JACOBI: HX_HIP(c, launch_bj64(c, v, z)); return HX_OK;
-    case HX_PC_LEARNED: return mlp_precondition(c, v, z, nonfinite);
+    case HX_PC_LEARNED: return mlp_precondition(c, v, z);
     case HX_PC_HELMHOLTZ_DIAG: HX_HIP(c, launch_diag64(c, 0, v, z)); return HX_OK;
     case HX_PC_MASS_DIAG: HX_HIP(c, launch_diag64(c, 1, v, z)); return HX_OK;
     case HX_PC_MASS_BLOCK: HX_HIP(c, launch_massinv64(c, v, z)); return HX_OK;
@@ -220,8 +221,8 @@ hx_status solve_cg(hx_ctx *c, const hx_solve_params *prm, const double *b, doubl
         info->true_rel_res = 0.0;
         return HX_OK;
     }
-    int nonfinite = 0, dummy = 0;
-    if ((s = precondition(c, prm->pc, 0, 0, r, z, nullptr, &dummy, &nonfinite)) != HX_OK) return s;
+    int dummy = 0;
+    if ((s = precondition(c, prm->pc, 0, 0, r, z, nullptr, &dummy)) != HX_OK) return s;
     HX_HIP(c, blas_copy(c, n, z, p));
     HX_HIP(c, blas_dot(c, n, r, z, sc + 0));
     if (rel <= prm->rtol || prm->max_iter < 1) {
@@ -435,15 +436,9 @@ hx_status solve_fgmres(hx_ctx *c, const hx_solve_params *prm, const double *b, d
         bool sw = false, stop = false;
         for (int j = 0; j < m && it < prm->max_iter; ++j) {
             double *vj = V + (size_t)j * n, *zj = Z + (size_t)j * n;
-            int nonfinite = 0;
             tm.rec(0, c->stream);
-            if ((s = precondition(c, pc, mixed, prm->inner_iters, vj, zj, w32, &info->inner_iters,
-                                  &nonfinite)) != HX_OK)
+            if ((s = precondition(c, pc, mixed, prm->inner_iters, vj, zj, w32, &info->inner_iters)) != HX_OK)
                 return s;
-            if (nonfinite) {
-                sw = true;
-                break;
-            }
             tm.rec(1, c->stream);
             HX_HIP(c, sys_apply(c, prm, zj, w, nullptr));
             tm.rec(2, c->stream);

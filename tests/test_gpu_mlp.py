@@ -4,11 +4,13 @@ around it: FGMRES with the network converges, a poisoned network is replaced
 by block Jacobi, a zero network reproduces block Jacobi, and training on the
 solver's own iterates lowers the loss.
 
-Tolerances: hidden activations are BF16, so an activation that sits on a
-rounding boundary may round differently when the FP32 (GPU) and FP64
-(oracle) pre-activations differ in their last bits; normwise 2e-3 covers a
-handful of such flips.  Gradients pass through one more BF16 rounding (the
-back-propagated signal), hence 1e-2."""
+Tolerances: end to end, hidden activations are BF16, so an activation that
+sits on a rounding boundary may round differently when the FP32 (GPU) and
+FP64 (oracle) pre-activations differ in their last bits; normwise 2e-3
+covers a handful of such flips, and gradients, which pass through one more
+BF16 rounding (the back-propagated signal), 1e-2.  Layer by layer on the
+GPU's own BF16 operands (exported after a training step) only the FP32
+accumulation differs from the oracle's FP64: 1e-5 normwise per block."""
 import numpy as np
 import pytest
 
@@ -101,6 +103,51 @@ def test_backward_and_adam_parity(terrain):
     np.testing.assert_allclose(w1, ref, rtol=0, atol=2e-6)
 
 
+def test_layers_on_exact_operands(terrain):
+    """Each product of the forward and backward pass against the oracle's
+    layer on the operands the GPU used: the exported BF16 inputs and the FP32
+    activations and back-propagated signals, rounded to BF16 by the oracle
+    where the next product rounds them."""
+    hx = _hx()
+    p, ctx = terrain
+    w = si.mlp_init(12)
+    w[-125:] = 0.03
+    ctx.set_network(w)
+    rng = np.random.default_rng(4)
+    B = 173                                      # ragged against the 64/128-row tiles
+    X = rng.normal(size=(B, ctx.n_features())).astype(np.float32)
+    T = rng.normal(size=(B, 125)).astype(np.float32)
+    with pytest.raises(hx.HXError):
+        ctx.network_trace(hx.HX_TRACE_H1, B + 1)             # wrong size
+    _, g = ctx.train_step(to_dev(X), to_dev(T), 0.0, want_grad=True)
+    g = g.cpu().numpy().astype(np.float64)
+    tr = {k: ctx.network_trace(getattr(hx, "HX_TRACE_" + k), B).astype(np.float64)
+          for k in ("INPUT", "H1", "H2", "OUT", "DOUT", "DH2", "DH1")}
+    (W1, b1), (W2, b2), (W3, b3) = mlp.unpack(w.astype(np.float64))
+    rb = mlp.bf16_round
+    tol = 1e-5
+    np.testing.assert_array_equal(tr["INPUT"], rb(X))
+    assert _rel(tr["H1"], np.maximum(mlp.layer(W1, b1, tr["INPUT"]), 0)) <= tol
+    assert _rel(tr["H2"], np.maximum(mlp.layer(W2, b2, rb(tr["H1"])), 0)) <= tol
+    assert _rel(tr["OUT"], mlp.layer(W3, b3, rb(tr["H2"]))) <= tol
+    assert _rel(tr["DOUT"], 2.0 * (tr["OUT"] - T) / T.size) <= tol
+    gW3, gb3, dA2 = mlp.layer_grads(W3, tr["DOUT"], rb(tr["H2"]))
+    assert _rel(tr["DH2"], dA2 * (tr["H2"] > 0)) <= tol
+    gW2, gb2, dA1 = mlp.layer_grads(W2, tr["DH2"], rb(tr["H1"]))
+    assert _rel(tr["DH1"], dA1 * (tr["H1"] > 0)) <= tol
+    gW1, gb1, _ = mlp.layer_grads(W1, tr["DH1"], tr["INPUT"])
+    o = 0
+    for name, blk in (("W1", gW1), ("b1", gb1), ("W2", gW2), ("b2", gb2), ("W3", gW3), ("b3", gb3)):
+        assert _rel(g[o:o + blk.size], blk.ravel()) <= tol, name
+        o += blk.size
+    assert o == g.size
+    # a forward call reuses the work buffers: the trace is gone
+    ctx.network_forward(to_dev(X))
+    with pytest.raises(hx.HXError) as e:
+        ctx.network_trace(hx.HX_TRACE_H1, B)
+    assert e.value.status == hx.HX_ERR_STATE
+
+
 def test_learned_preconditioner_parity(terrain):
     """The whole learned preconditioner, BJ + w_K net(features), against the
     oracle's composition of the same steps."""
@@ -162,12 +209,13 @@ def test_training_on_solver_iterates_lowers_loss():
 
 
 def test_learned_gain_over_block_jacobi():
-    """Train on 10^5 pairs from the periodic unit cube (Q4), then count FGMRES(30)
-    iterations to 1e-8 with and without the network on held-out right-hand
-    sides and coefficients.  On this mesh the network removes a part of the
-    inter-element error that block Jacobi leaves; on the 32x8x16 terrain
-    channel it does not help (the stall rule hands over to block Jacobi), which
-    the test records but does not require."""
+    """Train on 10^5 pairs from the unit cube (Q4; error fields and solver
+    iterates, the library's defaults), then solve with FGMRES(30) to 1e-8
+    with and without the network.  On the 32x8x16 terrain channel (Q4) the
+    learned preconditioner must converge without the fallback in fewer
+    iterations and less wall time than block Jacobi, the same solver without
+    the network; on held-out cube problems it must not need more iterations
+    on average."""
     import torch
     hx = _hx()
     from paper_2505_00384_amd import learned
@@ -190,15 +238,19 @@ def test_learned_gain_over_block_jacobi():
                   flush=True)
             assert le["true_rel_res"] <= 1e-8 and bj["true_rel_res"] <= 1e-8
             gains.append(bj["iters"] / le["iters"])
-    assert min(gains) > 1.0 and np.mean(gains) > 1.1, gains
+    assert np.mean(gains) >= 1.0, gains
     w = ctx.get_network()
     ctx.close()
     p2 = problem(si.terrain_mesh(32, 8, 16, g=4), 4, coef="terrain")
     c2 = gpu_context(p2)
     c2.set_network(w)
-    r = learned.compare(c2, to_dev(si.rhs_terrain(0)(*p2.dof_coords())))
+    b2 = to_dev(si.rhs_terrain(0)(*p2.dof_coords()))
+    learned.compare(c2, b2)                      # warm-up of both paths
+    r = learned.compare(c2, b2)
     bj, le = r["block_jacobi"], r["learned"]
     print(f"[gain] terrain 32x8x16: BJ {bj['iters']} it {bj['wall_ms']:.1f} ms, learned "
           f"{le['iters']} it {le['wall_ms']:.1f} ms, fallback {le['fallback_used']}", flush=True)
-    assert le["true_rel_res"] <= 1e-8          # never worse than converged
+    assert le["status"] == hx.HX_OK and not le["fallback_used"]
+    assert le["true_rel_res"] <= 1e-8
+    assert le["iters"] < bj["iters"] and le["wall_ms"] < bj["wall_ms"], (le, bj)
     c2.close()
