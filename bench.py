@@ -625,6 +625,8 @@ def main():
         forms = [
             ("fp64_fgmres_bj", hx.default_params(method=1, restart=30, rtol=1e-8, pc=hx.HX_PC_BLOCK_JACOBI)),
             ("mixed_fp32_inner", hx.default_params(method=1, restart=10, rtol=1e-8, mixed=1, inner_iters=32)),
+            # the minimal mixed form: FP32 operator and block Jacobi inside FP64 FGMRES
+            ("mixed_fp32_minimal", hx.default_params(method=1, restart=30, rtol=1e-8, mixed=2)),
         ]
         # SPD operator: CG with block Jacobi and with the paper's Helmholtz
         # (volume-diagonal) preconditioner

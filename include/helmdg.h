@@ -229,7 +229,12 @@ typedef struct {
     int max_iter;        /* total iteration cap */
     int pc;              /* hx_pc of the iteration; with mixed = 1, of the inner FP32 CG
                             (HX_PC_LEARNED is not allowed there) */
-    int mixed;           /* 1: outer FP64 FGMRES, preconditioner = inner FP32 CG */
+    int mixed;           /* 0: FP64 throughout; 1: outer FP64 FGMRES, preconditioner =
+                            inner FP32 CG; 2 (minimal form): FP64 FGMRES vectors and
+                            orthogonalisation, the operator and the preconditioner pc
+                            (block Jacobi, a diagonal kind, the mass blocks or none)
+                            applied once per step in FP32; the FP64 residual at each
+                            restart refines (Helmholtz-type system only) */
     int inner_iters;     /* inner FP32 CG iterations per outer step (mixed; 32) */
     double inner_rtol;   /* not used: the inner FP32 CG runs inner_iters iterations with its
                             scalars on the device, so it has no stopping test */

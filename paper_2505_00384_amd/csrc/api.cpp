@@ -218,7 +218,12 @@ hx_status hx_create(hx_ctx **out, int device, void *hip_stream)
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
     hx_status s = dalloc(c, (void **)&c->red, sizeof(double) * (size_t)1024 * 72);
+    if (s == HX_OK) s = dalloc(c, (void **)&c->dpart, sizeof(double) * (size_t)1024 * 128);
     if (s == HX_OK && hipHostMalloc((void **)&c->red_host, sizeof(double) * 1024) != hipSuccess)
+        s = HX_ERR_DEVICE;
+    if (s == HX_OK && (hipHostMalloc((void **)&c->pin_host, sizeof(double) * 2 * FG_SLOT,
+                                     hipHostMallocMapped) != hipSuccess ||
+                       hipHostGetDevicePointer((void **)&c->pin_dev, c->pin_host, 0) != hipSuccess))
         s = HX_ERR_DEVICE;
     if (s == HX_OK) s = noalloc_init(c);
     if (s != HX_OK) {
@@ -238,7 +243,9 @@ hx_status hx_destroy(hx_ctx *c)
     mlp_destroy(c);
     free_mesh(c);
     dfree((void **)&c->red);
+    dfree((void **)&c->dpart);
     if (c->red_host) (void)hipHostFree(c->red_host);
+    if (c->pin_host) (void)hipHostFree(c->pin_host);
     delete c;
     return HX_OK;
 }

@@ -13,6 +13,7 @@
 // before the solve and sums r.z and r.r per block, so one CG step touches
 // each vector once.
 #include "common.hpp"
+#include "sum256.hpp"
 
 #include <cstddef>
 #include <type_traits>
@@ -62,7 +63,9 @@ __device__ __forceinline__ void block_sum2(double &u, double &v, double *sh)
 // preconditioner, z holding the step direction d and x the iterate:
 //   d = ca M^{-1} r + cb d  (cb read only with CHEB_READ_D),
 //   x = x + d  (CHEB_ACCUM)  or  x = d.
-// Otherwise plain z = M^{-1} r.
+// Otherwise plain z = M^{-1} r, or, with part given (scaled form: ld
+// partial sums of |r|^2 in part), z = M^{-1} (r / |r|) and x = r / |r|, the
+// norm from the fixed-order sum256 of the partial sums.
 constexpr int CHEB_READ_D = 1, CHEB_ACCUM = 2;
 
 template <int N, typename T, bool FUSE, bool CHEB = false>
@@ -92,6 +95,13 @@ k_bj(const T *__restrict__ rin, T *__restrict__ z, const T *__restrict__ S, cons
     const bool active = slot && cid < n_cells;
 
     double acc_rr = 0.0, acc_rz = 0.0;
+    T sfac = 1;
+    const bool scaled = !FUSE && !CHEB && part != nullptr;
+    if (scaled) {
+        static_assert(Cfg<N>::NT == 256, "the scaled form sums with a 256-thread workgroup");
+        __shared__ double shs[4];
+        sfac = (T)(1.0 / sqrt(sum256(part, ld, shs)));
+    }
     if (FUSE && active) {
         const T al = (T)(sc[1] != 0.0 ? sc[0] / sc[1] : 0.0);
         for (int e = tt; e < ND; e += NF) {
@@ -101,6 +111,12 @@ k_bj(const T *__restrict__ rin, T *__restrict__ z, const T *__restrict__ S, cons
             rw[gi] = rv;
             sR[lc][e] = rv;
             acc_rr += (double)rv * (double)rv;
+        }
+    } else if (active && scaled) {
+        for (int e = tt; e < ND; e += NF) {
+            const T rv = r[cid * ND + e] * sfac;
+            x[cid * ND + e] = rv;
+            sR[lc][e] = rv;
         }
     } else if (active) {
         for (int e = tt; e < ND; e += NF) sR[lc][e] = r[cid * ND + e];
@@ -316,9 +332,37 @@ hipError_t bj_dispatch(hx_ctx *c, const T *r, T *z, const CgArgs<T> *cg = nullpt
     }
 }
 
+template <int N>
+hipError_t bj_scaled_n(hx_ctx *c, const double *w, const double *part, int nb, double *v, double *z)
+{
+    const int cpb = Cfg<N>::CPB;
+    const int nwg = (int)((c->n_cells + cpb - 1) / cpb);
+    hipLaunchKernelGGL((k_bj<N, double, false>), dim3(nwg), dim3(Cfg<N>::NT), 0, c->stream, w, z,
+                       c->bjS64, c->bjL64, c->bjC64, (int)c->n_cells, nwg, v, (double *)nullptr,
+                       (const double *)nullptr, (const double *)nullptr, (const double *)nullptr,
+                       const_cast<double *>(part), nb);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_bj64(hx_ctx *c, const double *r, double *z) { return bj_dispatch<double>(c, r, z); }
+
+hipError_t launch_bj64_scaled(hx_ctx *c, const double *w, const double *part, int nb, double *v,
+                              double *z)
+{
+    if (nb < 1 || !part) return hipErrorInvalidValue;
+    switch (c->n) {
+    case 2: return bj_scaled_n<2>(c, w, part, nb, v, z);
+    case 3: return bj_scaled_n<3>(c, w, part, nb, v, z);
+    case 4: return bj_scaled_n<4>(c, w, part, nb, v, z);
+    case 5: return bj_scaled_n<5>(c, w, part, nb, v, z);
+    case 6: return bj_scaled_n<6>(c, w, part, nb, v, z);
+    case 7: return bj_scaled_n<7>(c, w, part, nb, v, z);
+    case 8: return bj_scaled_n<8>(c, w, part, nb, v, z);
+    default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_bj_cheb64(hx_ctx *c, const double *r, double *d, double *x, double ca, double cb,
                             int read_d, int accum)

@@ -4,6 +4,7 @@
 // and block updates for classical Gram-Schmidt, fused CG updates that read
 // their scalars from device memory (no host round trip), casts.
 #include "common.hpp"
+#include "sum256.hpp"
 
 namespace hx {
 namespace {
@@ -90,78 +91,153 @@ __global__ void __launch_bounds__(RT) k_mdot1(int64_t n, int v0, int mc,
     }
 }
 
-// two-sided block dot over the vector chunk blockIdx.y:
-// part[(k)*ld + blk] = sum_i V[k][i] a[i], part[(mtot + k)*ld + blk] = sum_i V[k][i] b[i]
-__global__ void __launch_bounds__(RT) k_mdot2(int64_t n, int mtot, const double *__restrict__ V,
-                                              int64_t ldv, const double *__restrict__ a,
-                                              const double *__restrict__ b, double *part, int ld)
+// ---------------------------------------------------------------------------
+// One step of classical Gram-Schmidt with the second pass delayed by one step
+// (see solver.cpp), in four launches.  V[j] holds the tentative vector t of
+// the previous step, w = A z_j.
+//
+// k_dcgs_dot: per workgroup, partial block dots of [V_0 .. V_{j-1}, t] with t
+// and with w.  k_dcgs_coef sums them in a fixed order and derives the step's
+// scalars: sc[0..j): c = V_{j-1}^T t, sc[j]: t.t, sc[64..64+j): h = V_{j-1}^T w,
+// sc[64+j]: t.w, sc[DC_CW + k] = h_k - c_k hj/rho, sc[DC_S + 0..4] = 1/rho,
+// hj/rho, rho, hj, flag (1 if t lies in the span of V_{j-1} to working
+// precision).
+// ---------------------------------------------------------------------------
+constexpr int DC_CW = 300, DC_S = 364;
+constexpr int DMC = 16;           // vectors per workgroup row of k_dcgs_dot
+constexpr int DC_LD = 1024;       // partial-sum row stride (max workgroups per chunk)
+
+// rows r < nrows of part (stride ld, nb <= 1024 columns) summed in a fixed
+// order, one wave per row, each wave's rows two at a time with all their
+// loads in flight together; result in out[r] (LDS)
+__device__ void sum_rows(const double *__restrict__ part, int nrows, int nb, int ld, double *out)
 {
-    __shared__ double sh[RT / 64];
-    const int v0 = blockIdx.y * MC;
-    const int mc = (mtot - v0) < MC ? (mtot - v0) : MC;
-    double sa[MC], sb[MC];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int r0 = wv; r0 < nrows; r0 += 2 * nw) {
+        double s[2];
 #pragma unroll
-    for (int k = 0; k < MC; ++k) sa[k] = sb[k] = 0.0;
-    const int64_t stride = (int64_t)gridDim.x * RT;
-    for (int64_t i = blockIdx.x * (int64_t)RT + threadIdx.x; i < n; i += stride) {
-        const double ai = a[i], bi = b[i];
+        for (int q = 0; q < 2; ++q) {
+            const int r = r0 + q * nw;
+            double v[16];
 #pragma unroll
-        for (int k = 0; k < MC; ++k)
-            if (k < mc) {
-                const double v = V[(int64_t)(v0 + k) * ldv + i];
-                sa[k] += v * ai;
-                sb[k] += v * bi;
+            for (int u = 0; u < 16; ++u) {
+                const int p = lane + 64 * u;
+                v[u] = (r < nrows && p < nb) ? part[(int64_t)r * ld + p] : 0.0;
             }
-    }
+            double a = 0.0;
 #pragma unroll
-    for (int k = 0; k < MC; ++k) {
-        if (k >= mc) break;
-        const double ra = block_sum(sa[k], sh);
-        const double rb = block_sum(sb[k], sh);
-        if (threadIdx.x == 0) {
-            part[(int64_t)(v0 + k) * ld + blockIdx.x] = ra;
-            part[(int64_t)(mtot + v0 + k) * ld + blockIdx.x] = rb;
+            for (int u = 0; u < 16; ++u) a += v[u];
+            s[q] = a;
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const double t = wave_sum(s[q]);
+            const int r = r0 + q * nw;
+            if (lane == 0 && r < nrows) out[r] = t;
         }
     }
 }
 
-// Scalars of one delayed-reorthogonalisation step (see solver.cpp), one
-// thread, fixed summation order.  sc[0..j): c = V_{j-1}^T t, sc[j]: t.t,
-// sc[64..64+j): h = V_{j-1}^T w, sc[64+j]: t.w.  Writes sc[DC_CW + k] =
-// h_k - c_k hj/rho, and sc[DC_S + 0..4] = 1/rho, hj/rho, rho, hj, flag (1 if
-// t lies in the span of V_{j-1} to working precision).
-constexpr int DC_CW = 300, DC_S = 364;
-__global__ void k_dcgs_coef(int j, double *sc)
+__global__ void __launch_bounds__(RT) k_dcgs_dot(int64_t n, int j, const double *__restrict__ V,
+                                                 int64_t ldv, const double *__restrict__ w,
+                                                 double *part)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    __shared__ double wsum[RT / 64][2 * DMC];
+    const int m = j + 1;
+    const int v0 = blockIdx.y * DMC;
+    const int mc = (m - v0) < DMC ? (m - v0) : DMC;
+    const double *t = V + (int64_t)j * ldv;
+    double sa[DMC], sb[DMC];
+#pragma unroll
+    for (int k = 0; k < DMC; ++k) sa[k] = sb[k] = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * RT;
+    // rows past the chunk's last vector repeat that vector (same cache
+    // lines, results unused), so the loads issue without branches
+    const double *rows[DMC];
+#pragma unroll
+    for (int k = 0; k < DMC; ++k) rows[k] = V + (int64_t)(v0 + (k < mc ? k : mc - 1)) * ldv;
+    for (int64_t i = blockIdx.x * (int64_t)RT + threadIdx.x; i < n; i += stride) {
+        const double ai = t[i], bi = w[i];
+        double v[DMC];
+#pragma unroll
+        for (int k = 0; k < DMC; ++k) v[k] = rows[k][i];
+#pragma unroll
+        for (int k = 0; k < DMC; ++k) {
+            sa[k] += v[k] * ai;
+            sb[k] += v[k] * bi;
+        }
+    }
+    // per-wave sums, then the waves in a fixed order
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < DMC; ++k) {
+        const double ra = wave_sum(sa[k]), rb = wave_sum(sb[k]);
+        if (lane == 0) {
+            wsum[wv][k] = ra;
+            wsum[wv][DMC + k] = rb;
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < 2 * mc) {
+        const int k = threadIdx.x < mc ? threadIdx.x : threadIdx.x - mc;
+        const int col = threadIdx.x < mc ? k : DMC + k;
+        double r = 0.0;
+        for (int q = 0; q < RT / 64; ++q) r += wsum[q][col];
+        const int row = threadIdx.x < mc ? v0 + k : m + v0 + k;
+        part[(int64_t)row * DC_LD + blockIdx.x] = r;
+    }
+}
+
+// k_dcgs_coef (one workgroup of 1024): the 2(j+1) dot products from the
+// nb partial sums of each, in a fixed order, and the step's scalars
+__global__ void __launch_bounds__(1024) k_dcgs_coef(int j, int nb, const double *__restrict__ part,
+                                                    double *sc, double *hout)
+{
+    __shared__ double sums[2 * 64];
+    const int m = j + 1;
+    sum_rows(part, 2 * m, nb, DC_LD, sums);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const double *ca = sums, *cb = sums + m;
     double cc = 0.0, ch = 0.0;
     for (int k = 0; k < j; ++k) {
-        cc += sc[k] * sc[k];
-        ch += sc[k] * sc[64 + k];
+        cc += ca[k] * ca[k];
+        ch += ca[k] * cb[k];
     }
-    const double r2 = sc[j] - cc;
+    const double r2 = ca[j] - cc;
     double flag = 0.0, rho;
-    if (r2 > 0.0 && r2 >= 1e-12 * sc[j]) {
+    if (r2 > 0.0 && r2 >= 1e-12 * ca[j]) {
         rho = sqrt(r2);
     } else {
         flag = 1.0;
-        rho = sc[j] > 0.0 ? sqrt(sc[j]) : 1.0;
+        rho = ca[j] > 0.0 ? sqrt(ca[j]) : 1.0;
     }
-    const double hj = (sc[64 + j] - ch) / rho;
-    for (int k = 0; k < j; ++k) sc[DC_CW + k] = sc[64 + k] - sc[k] * (hj / rho);
+    const double hj = (cb[j] - ch) / rho;
+    for (int k = 0; k <= j; ++k) {
+        sc[k] = ca[k];
+        sc[64 + k] = cb[k];
+    }
+    for (int k = 0; k < j; ++k) sc[DC_CW + k] = cb[k] - ca[k] * (hj / rho);
     sc[DC_S + 0] = 1.0 / rho;
     sc[DC_S + 1] = hj / rho;
     sc[DC_S + 2] = rho;
     sc[DC_S + 3] = hj;
     sc[DC_S + 4] = flag;
+    if (hout) {
+        for (int k = 0; k <= j; ++k) {
+            hout[k] = ca[k];
+            hout[64 + k] = cb[k];
+        }
+        for (int k = 0; k < 5; ++k) hout[DC_S + k] = sc[DC_S + k];
+    }
 }
 
-// Fused update of one delayed step: with t = V[j] (tentative vector),
-//   V[j] <- (t - V_{j-1} c) / rho,  w <- w - V_{j-1} cw - t hj/rho,
-// and part[blk] = partial sums of the new |w|^2.  Reads V_{j-1} once.
+// k_dcgs_update: with t = V[j],
+//   V[j] <- (t - V_{j-1} c) / rho,  w <- w - V_{j-1} cw - t hj/rho
+// (reads V_{j-1} once), and per workgroup the partial sum of the new |w|^2.
 __global__ void __launch_bounds__(RT) k_dcgs_update(int64_t n, int j, double *V, int64_t ldv,
                                                     const double *__restrict__ sc, double *w,
-                                                    double *part)
+                                                    double *part, double *hpart)
 {
     __shared__ double sh[RT / 64];
     __shared__ double cs[64], cws[64];
@@ -195,7 +271,24 @@ __global__ void __launch_bounds__(RT) k_dcgs_update(int64_t n, int j, double *V,
         nu += wn * wn;
     }
     nu = block_sum(nu, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = nu;
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = nu;
+        if (hpart) hpart[blockIdx.x] = nu;
+    }
+}
+
+// k_dcgs_scale: every workgroup sums the nb partial sums of |w|^2 (sum256)
+// and writes its slice of V[j+1] = w / |w|; workgroup 0 also stores |w|^2 in
+// *dst
+__global__ void __launch_bounds__(RT) k_dcgs_scale(int64_t n, int nb, const double *__restrict__ part,
+                                                   const double *__restrict__ w, double *v, double *dst)
+{
+    __shared__ double sh[4];
+    const double s2 = sum256(part, nb, sh);
+    if (blockIdx.x == 0 && threadIdx.x == 0) dst[0] = s2;
+    const double inv = 1.0 / sqrt(s2);
+    const int64_t stride = (int64_t)gridDim.x * RT;
+    for (int64_t i = blockIdx.x * (int64_t)RT + threadIdx.x; i < n; i += stride) v[i] = w[i] * inv;
 }
 
 // w += sign * sum_k h[k] V[k]
@@ -380,52 +473,29 @@ hipError_t blas_mdot(hx_ctx *c, int64_t n, int m, const double *V, int64_t ldv, 
     return hipGetLastError();
 }
 
-// dst_a[k] = V[k].a, dst_b[k] = V[k].b for k < m (m <= 64)
-hipError_t blas_mdot2(hx_ctx *c, int64_t n, int m, const double *V, int64_t ldv, const double *a,
-                      const double *b, double *dst_a, double *dst_b)
+// one delayed-reorthogonalisation step (see k_dcgs_dot): finalises V[j],
+// projects w, stores |w|^2 in sc[128] and the tentative next vector w/|w| in
+// V[j+1]; j < 64
+hipError_t blas_dcgs(hx_ctx *c, int64_t n, int j, double *V, int64_t ldv, double *w, double *sc,
+                     double *host_out, bool scale, int *nb_out)
 {
-    // two rows of partial sums per vector (up to 128 rows of RED_MAX); the
-    // per-block buffer of the fused CG steps holds them when it is large enough
-    int nb = red_blocks(n);
-    double *part = c->red;
-    int ld = RED_MAX / 2;
-    if ((int64_t)2 * 64 * 2 * RED_MAX <= 2 * (c->n_cells + 1)) {
-        part = c->cgpart;
-        ld = 2 * RED_MAX;
-        const int64_t want = (n + RT * 8 - 1) / (RT * 8);
-        nb = (int)(want < 2 * RED_MAX ? (want < 1 ? 1 : want) : 2 * RED_MAX);
-    } else if ((int64_t)2 * 64 * RED_MAX <= 2 * (c->n_cells + 1)) {
-        part = c->cgpart;
-        ld = RED_MAX;
-    } else if (nb > RED_MAX / 2) {
-        nb = RED_MAX / 2;
+    if (j < 0 || j >= 64) return hipErrorInvalidValue;
+    const int64_t want = (n + RT * 4 - 1) / (RT * 4);
+    const int nb = (int)(want < 1 ? 1 : (want > DC_LD ? DC_LD : want));
+    const int nch = (j + 1 + DMC - 1) / DMC;
+    hipLaunchKernelGGL(k_dcgs_dot, dim3(nb, nch), dim3(RT), 0, c->stream, n, j, V, ldv, w, c->dpart);
+    hipLaunchKernelGGL(k_dcgs_coef, dim3(1), dim3(1024), 0, c->stream, j, nb, c->dpart, sc, host_out);
+    const int64_t want2 = (n + RT * 2 - 1) / (RT * 2);
+    const int nb2 = (int)(want2 < 1 ? 1 : (want2 > RED_MAX ? RED_MAX : want2));
+    hipLaunchKernelGGL(k_dcgs_update, dim3(nb2), dim3(RT), 0, c->stream, n, j, V, ldv, sc, w,
+                       c->red + RED_WPART, host_out ? host_out + FG_PART : (double *)nullptr);
+    if (scale) {
+        const int64_t want3 = (n + RT * 4 - 1) / (RT * 4);
+        const int nb3 = (int)(want3 < 1 ? 1 : (want3 > 4096 ? 4096 : want3));
+        hipLaunchKernelGGL(k_dcgs_scale, dim3(nb3), dim3(RT), 0, c->stream, n, nb2, c->red + RED_WPART,
+                           w, V + (int64_t)(j + 1) * ldv, sc + 128);
     }
-    const int nch = (m + MC - 1) / MC;
-    hipLaunchKernelGGL(k_mdot2, dim3(nb, nch), dim3(RT), 0, c->stream, n, m, V, ldv, a, b, part, ld);
-    hipLaunchKernelGGL(k_red2, dim3(m), dim3(RT), 0, c->stream, part, nb, ld, dst_a);
-    hipLaunchKernelGGL(k_red2, dim3(m), dim3(RT), 0, c->stream, part + (int64_t)m * ld, nb, ld,
-                       dst_b);
-    return hipGetLastError();
-}
-
-// one delayed-reorthogonalisation step after blas_mdot2 filled sc (see
-// k_dcgs_coef): finalises V[j], projects w, stores |w|^2 in sc[128] and the
-// tentative next vector w/|w| in V[j+1]
-hipError_t blas_dcgs_step(hx_ctx *c, int64_t n, int j, double *V, int64_t ldv, double *w,
-                          double *sc)
-{
-    hipLaunchKernelGGL(k_dcgs_coef, dim3(1), dim3(64), 0, c->stream, j, sc);
-    int nb = red_blocks(n);
-    double *part = c->red;
-    if (2 * RED_MAX <= 2 * (c->n_cells + 1)) {
-        const int64_t want = (n + RT * 8 - 1) / (RT * 8);
-        nb = (int)(want < 2 * RED_MAX ? (want < 1 ? 1 : want) : 2 * RED_MAX);
-        part = c->cgpart;
-    }
-    hipLaunchKernelGGL(k_dcgs_update, dim3(nb), dim3(RT), 0, c->stream, n, j, V, ldv, sc, w, part);
-    hipLaunchKernelGGL(k_red2, dim3(1), dim3(RT), 0, c->stream, part, nb, RED_MAX, sc + 128);
-    hipLaunchKernelGGL(k_scale_copy, dim3(nb256(n)), dim3(256), 0, c->stream, n, sc + 128, 2, w,
-                       V + (int64_t)(j + 1) * ldv);
+    if (nb_out) *nb_out = nb2;
     return hipGetLastError();
 }
 

@@ -163,6 +163,11 @@ struct hx_ctx {
     // reductions
     double *red = nullptr;        // partial sums
     double *red_host = nullptr;   // pinned
+    double *dpart = nullptr;      // [128][1024] partial block dots of blas_dcgs
+    // pinned, device-mapped: the scalars of the two FGMRES steps in flight,
+    // written by the kernels themselves (FG_SLOT doubles per step)
+    double *pin_host = nullptr;
+    double *pin_dev = nullptr;
     int red_blocks = 0;
 
     // solver work space (allocated on first use, grown as needed)
@@ -285,11 +290,25 @@ hipError_t blas_dot(hx_ctx *c, int64_t n, const double *x, const double *y, doub
 hipError_t blas_dot32(hx_ctx *c, int64_t n, const float *x, const float *y, double *dst);
 hipError_t blas_mdot(hx_ctx *c, int64_t n, int m, const double *V, int64_t ldv,
                      const double *w, double *dst /*[m]*/);
-hipError_t blas_mdot2(hx_ctx *c, int64_t n, int m, const double *V, int64_t ldv, const double *a,
-                      const double *b, double *dst_a, double *dst_b);
-hipError_t blas_dcgs_step(hx_ctx *c, int64_t n, int j, double *V, int64_t ldv, double *w,
-                          double *sc);
-constexpr int DCGS_S = 364;   // device scalars of blas_dcgs_step: 1/rho, hj/rho, rho, hj, flag
+// One step of delayed classical Gram-Schmidt (blas.hip).  host_out (device
+// view of a pinned slot, may be null) receives the step's scalars in the
+// layout of sc and, from FG_PART, the nb partial sums of |w|^2 (*nb_out);
+// with scale the normalised w goes to V[j+1] (else a later kernel does it).
+hipError_t blas_dcgs(hx_ctx *c, int64_t n, int j, double *V, int64_t ldv, double *w, double *sc,
+                     double *host_out, bool scale, int *nb_out);
+constexpr int DCGS_S = 364;   // device scalars of blas_dcgs: 1/rho, hj/rho, rho, hj, flag
+constexpr int FG_PART = 512;  // offset of the |w|^2 partial sums in a pinned slot
+// c->red: stage-1 partial sums from 0, the |w|^2 partial sums of blas_dcgs
+// at RED_WPART (at most 1024), solver scalars from 66 Ki
+constexpr int64_t RED_WPART = 65536;
+constexpr int FG_SLOT = 1536; // doubles per pinned slot
+// v = w / |w| with |w|^2 the fixed-order sum (sum256) of part[0..nb), and
+// z = block Jacobi of v, in one launch (FP64)
+hipError_t launch_bj64_scaled(hx_ctx *c, const double *w, const double *part, int nb, double *v,
+                              double *z);
+// host repetition of the device's sum256 order
+double host_sum256(const double *p, int nb);
+
 hipError_t blas_mupdate(hx_ctx *c, int64_t n, int m, const double *V, int64_t ldv,
                         const double *h /*device [m]*/, double sign, double *w);
 hipError_t blas_axpby(hx_ctx *c, int64_t n, double a, const double *x, double b, double *y);
@@ -337,6 +356,8 @@ hx_status mlp_train(hx_ctx *c, const float *feats, const float *targets, int64_t
 hx_status mlp_precondition(hx_ctx *c, const double *r, double *z);
 hx_status mlp_precondition_batched(hx_ctx *c, const double *r, double *z);
 hx_status mlp_trace(hx_ctx *c, int what, float *host_buf, int64_t count);
+// z += w_K net(features(r))_K on a z that already holds BJ(r)
+hx_status mlp_correct(hx_ctx *c, const double *r, double *z);
 hx_status mlp_training_pair(hx_ctx *c, const double *b, const double *xs, const double *xj,
                             float clip, float *feats, float *targets);
 

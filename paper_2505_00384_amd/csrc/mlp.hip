@@ -962,13 +962,11 @@ static hipError_t mlp_fused_n(hx_ctx *c, const double *r, double *z)
     return hipGetLastError();
 }
 
-// z = BJ(r) + w_K net(features(r))_K: block Jacobi, then the fused
-// correction.  A non-finite z shows up in the FGMRES Hessenberg column,
-// where the Givens step rejects it and the solver switches to block Jacobi.
-hx_status mlp_precondition(hx_ctx *c, const double *r, double *z)
+// The correction alone, on a z that already holds BJ(r): one fused launch
+// (features, the three layers, z_K += w_K o_K).
+hx_status mlp_correct(hx_ctx *c, const double *r, double *z)
 {
     if (!c->mlp) return fail(c, HX_ERR_STATE, "no network loaded");
-    HX_HIP(c, launch_bj64(c, r, z));
     hipError_t e = hipSuccess;
     switch (c->n) {
     case 2: e = mlp_fused_n<2>(c, r, z); break;
@@ -981,6 +979,16 @@ hx_status mlp_precondition(hx_ctx *c, const double *r, double *z)
     }
     HX_HIP(c, e);
     return HX_OK;
+}
+
+// z = BJ(r) + w_K net(features(r))_K: block Jacobi, then the fused
+// correction.  A non-finite z shows up in the FGMRES Hessenberg column,
+// where the Givens step rejects it and the solver switches to block Jacobi.
+hx_status mlp_precondition(hx_ctx *c, const double *r, double *z)
+{
+    if (!c->mlp) return fail(c, HX_ERR_STATE, "no network loaded");
+    HX_HIP(c, launch_bj64(c, r, z));
+    return mlp_correct(c, r, z);
 }
 
 // The batched form of the same preconditioner (features, the three layers

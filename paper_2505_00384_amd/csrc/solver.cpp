@@ -133,9 +133,28 @@ hx_status inner_fp32(hx_ctx *c, int pc, const double *v, double *z, float *w32, 
     return HX_OK;
 }
 
+// one FP32 application of preconditioner pc to the FP64 vector v (the
+// minimal mixed form): z = (double) M32^-1 (float) v.  w32: 2 float vectors.
+hx_status once_fp32(hx_ctx *c, int pc, const double *v, double *z, float *w32)
+{
+    const int64_t n = c->n_dofs;
+    float *r = w32, *zz = w32 + n;
+    HX_HIP(c, blas_cast64to32(c, n, v, r, nullptr));
+    switch (pc) {
+    case HX_PC_BLOCK_JACOBI: HX_HIP(c, launch_bj32(c, r, zz)); break;
+    case HX_PC_HELMHOLTZ_DIAG: HX_HIP(c, launch_diag32(c, 0, r, zz)); break;
+    case HX_PC_MASS_DIAG: HX_HIP(c, launch_diag32(c, 1, r, zz)); break;
+    case HX_PC_MASS_BLOCK: HX_HIP(c, launch_massinv32(c, r, zz)); break;
+    default: zz = r;
+    }
+    HX_HIP(c, blas_cast32to64(c, n, zz, z, nullptr));
+    return HX_OK;
+}
+
 hx_status precondition(hx_ctx *c, int pc, int mixed, int inner_iters, const double *v, double *z,
                        float *w32, int *inner_count)
 {
+    if (mixed == 2) return once_fp32(c, pc, v, z, w32);
     if (mixed) return inner_fp32(c, pc, v, z, w32, inner_iters, inner_count);
     switch (pc) {
     case HX_PC_NONE: HX_HIP(c, blas_copy(c, c->n_dofs, v, z)); return HX_OK;
@@ -157,6 +176,31 @@ double now_ms()
     return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
 
+}  // namespace
+
+// the additions of the device's sum256, in its order: 256 thread sums of
+// strided elements, each wave folded by halving distances, the four wave
+// sums in order
+double host_sum256(const double *p, int nb)
+{
+    double th[256];
+    for (int t = 0; t < 256; ++t) {
+        double s = 0.0;
+        for (int i = t; i < nb; i += 256) s += p[i];
+        th[t] = s;
+    }
+    double tot = 0.0;
+    for (int wv = 0; wv < 4; ++wv) {
+        double *v = th + 64 * wv;
+        for (int o = 32; o > 0; o >>= 1)
+            for (int i = 0; i < o; ++i) v[i] = v[i] + v[i + o];
+        tot += v[0];
+    }
+    return tot;
+}
+
+namespace {
+
 hx_status read_scalars(hx_ctx *c, const double *dev, int m, double *host)
 {
     HX_HIP(c, hipMemcpyAsync(c->red_host, dev, sizeof(double) * m, hipMemcpyDeviceToHost, c->stream));
@@ -174,6 +218,22 @@ hx_status read_scalars(hx_ctx *c, const double *dev, int m, double *host)
 // y = M x or y = b - M x for the system being solved: the Helmholtz-type
 // operator, the pressure system S = D - C A^-1 B, or the Helmholtz-type
 // operator with consistent integration (2k+1 points)
+hipError_t sys_apply(hx_ctx *c, const hx_solve_params *prm, const double *x, double *y,
+                     const double *b);
+
+// the operator of an Arnoldi step: FP64, or FP32 in the minimal mixed form
+// (w32 + 2 n .. + 4 n: the FP32 copies of x and y)
+hipError_t step_apply(hx_ctx *c, const hx_solve_params *prm, const double *x, double *y, float *w32)
+{
+    if (prm->mixed != 2) return sys_apply(c, prm, x, y, nullptr);
+    const int64_t n = c->n_dofs;
+    float *x32 = w32 + 2 * n, *y32 = w32 + 3 * n;
+    hipError_t e = blas_cast64to32(c, n, x, x32, nullptr);
+    if (e == hipSuccess) e = launch_apply32(c, x32, y32, nullptr);
+    if (e == hipSuccess) e = blas_cast32to64(c, n, y32, y, nullptr);
+    return e;
+}
+
 hipError_t sys_apply(hx_ctx *c, const hx_solve_params *prm, const double *x, double *y,
                      const double *b)
 {
@@ -351,9 +411,18 @@ struct Hess {
 //    finalises v_j = (t_j - V_{j-1} c)/rho and projects w (two reads of V).
 //    Since t_j = rho v_j + V_{j-1} c, column j-1 of H gains nu_{j-1} c and
 //    H(j, j-1) = nu_{j-1} rho one step late; a cycle ends with one extra
-//    block dot that finalises its last column.  Convergence is tested on the
-//    provisional column (the correction is of the order of the loss of
-//    orthogonality) and confirmed after finalising it.
+//    block dot that finalises its last column.  A step is one
+//    preconditioner, one operator and three orthogonalisation launches
+//    (partial block dots; their fixed-order sums and the step's scalars;
+//    the fused update with partial sums of |w|^2), plus the normalisation
+//    w/|w|, which block Jacobi folds into the next step's launch.  The
+//    kernels write the step's scalars to pinned host memory themselves.
+//    With a cheap preconditioner the host keeps one step in flight: it
+//    launches step j+1 before it waits for the scalars of step j, and tests
+//    convergence on the finalised columns.  With a costly one it runs one
+//    step at a time and tests the provisional column first (its correction
+//    is of the order of the loss of orthogonality), confirming after
+//    finalising it.
 
 hx_status solve_fgmres(hx_ctx *c, const hx_solve_params *prm, const double *b, double *x,
                        hx_solve_info *info, Timer &tm)
@@ -374,6 +443,24 @@ hx_status solve_fgmres(hx_ctx *c, const hx_solve_params *prm, const double *b, d
     Hess H(m);
     std::vector<double> y(m);
     const bool delayed = prm->orth == 1;
+    // delayed form: two steps in flight, slot j % 2 of the pinned buffer,
+    // events and timers
+    struct Ready {
+        hipEvent_t e[2] = {nullptr, nullptr};
+        ~Ready()
+        {
+            for (auto &x : e)
+                if (x) (void)hipEventDestroy(x);
+        }
+    } rd;
+    hipEvent_t *ready = rd.e;
+    for (int i = 0; i < 2; ++i)
+        if (hipEventCreateWithFlags(&ready[i], hipEventDisableTiming) != hipSuccess)
+            return fail(c, HX_ERR_DEVICE, "hipEventCreate failed");
+    Timer tb(tm.ok);
+    Timer *tms[2] = {&tm, &tb};
+    int nb_step[2] = {0, 0};
+    double *fin_host = c->red_host;
 
     HX_HIP(c, blas_dot(c, n, b, b, sc + 129));
     double tmp[1];
@@ -409,14 +496,14 @@ hx_status solve_fgmres(hx_ctx *c, const hx_solve_params *prm, const double *b, d
         tm.rec(2, c->stream);
         HX_HIP(c, blas_mdot(c, n, j + 2, V, n, V + (size_t)(j + 1) * n, sc));
         tm.rec(3, c->stream);
-        HX_HIP(c, hipMemcpyAsync(c->red_host, sc, sizeof(double) * (j + 2), hipMemcpyDeviceToHost,
+        HX_HIP(c, hipMemcpyAsync(fin_host, sc, sizeof(double) * (j + 2), hipMemcpyDeviceToHost,
                                  c->stream));
         HX_HIP(c, hipStreamSynchronize(c->stream));
         tm.orth += tm.span(2, 3);
         double cc = 0.0;
-        for (int i = 0; i <= j; ++i) cc += c->red_host[i] * c->red_host[i];
-        const double r2 = c->red_host[j + 1] - cc;
-        for (int i = 0; i <= j; ++i) H.h(i, j) += nu_prev * c->red_host[i];
+        for (int i = 0; i <= j; ++i) cc += fin_host[i] * fin_host[i];
+        const double r2 = fin_host[j + 1] - cc;
+        for (int i = 0; i <= j; ++i) H.h(i, j) += nu_prev * fin_host[i];
         H.h(j + 1, j) = r2 > 0.0 ? nu_prev * std::sqrt(r2) : 0.0;
         return HX_OK;
     };
@@ -433,16 +520,16 @@ hx_status solve_fgmres(hx_ctx *c, const hx_solve_params *prm, const double *b, d
         HX_HIP(c, blas_scale_copy(c, n, sc + 128, 2, V, V));
         H.reset(beta);
         int j_used = 0;
-        bool sw = false, stop = false;
-        for (int j = 0; j < m && it < prm->max_iter; ++j) {
+        bool sw = false;
+        for (int j = 0; !delayed && j < m && it < prm->max_iter; ++j) {
             double *vj = V + (size_t)j * n, *zj = Z + (size_t)j * n;
             tm.rec(0, c->stream);
             if ((s = precondition(c, pc, mixed, prm->inner_iters, vj, zj, w32, &info->inner_iters)) != HX_OK)
                 return s;
             tm.rec(1, c->stream);
-            HX_HIP(c, sys_apply(c, prm, zj, w, nullptr));
+            HX_HIP(c, step_apply(c, prm, zj, w, w32));
             tm.rec(2, c->stream);
-            if (!delayed) {
+            {
                 // CGS2
                 HX_HIP(c, blas_mdot(c, n, j + 1, V, n, w, sc));
                 HX_HIP(c, blas_mupdate(c, n, j + 1, V, n, sc, -1.0, w));
@@ -472,17 +559,59 @@ hx_status solve_fgmres(hx_ctx *c, const hx_solve_params *prm, const double *b, d
                 if (!(hn > 0.0)) break;   // happy breakdown: exact solution in the space
                 continue;
             }
-            // delayed CGS2: V[j] holds t_j
-            HX_HIP(c, blas_mdot2(c, n, j + 1, V, n, vj, w, sc, sc + 64));
-            HX_HIP(c, blas_dcgs_step(c, n, j, V, n, w, sc));
-            tm.rec(3, c->stream);
-            HX_HIP(c, hipMemcpyAsync(c->red_host, sc, sizeof(double) * (DCGS_S + 5),
-                                     hipMemcpyDeviceToHost, c->stream));
-            HX_HIP(c, hipStreamSynchronize(c->stream));
-            tm.acc();
-            const double *hs = c->red_host;
+        }
+        // delayed CGS2, one step in flight: step j+1 is launched before the
+        // host waits for the scalars of step j, so the stream never idles
+        // while the host updates the Hessenberg matrix.  Step j+1 is what
+        // finalises column j; when the cycle stops at column j it is
+        // discarded (its column is never used).
+        const int base = it;
+        // cheap preconditioners run one step ahead; block Jacobi (also under
+        // the learned correction) then takes the normalisation of the
+        // previous step's w into its own launch.  Costly ones (inner FP32
+        // CG, Chebyshev, multigrid) run one step at a time and test the
+        // provisional column, so that no step is spent past convergence.
+        const bool pipe = mixed != 1 && pc != HX_PC_CHEBYSHEV && pc != HX_PC_MULTIGRID &&
+                          pc != HX_PC_MULTIGRID_MIXED;
+        const bool fuse = pipe && !mixed && (pc == HX_PC_BLOCK_JACOBI || pc == HX_PC_LEARNED);
+        auto will_launch = [&](int j) { return j < m && base + j < prm->max_iter; };
+        int nb_prev = 0;   // partial sums of |w|^2 of the previous step
+        auto launch_step = [&](int j) -> hx_status {
+            double *vj = V + (size_t)j * n, *zj = Z + (size_t)j * n;
+            Timer &t = *tms[j % 2];
+            t.rec(0, c->stream);
+            if (j > 0 && fuse) {
+                HX_HIP(c, launch_bj64_scaled(c, w, c->red + RED_WPART, nb_prev, vj, zj));
+                if (pc == HX_PC_LEARNED) {
+                    hx_status st = mlp_correct(c, vj, zj);
+                    if (st != HX_OK) return st;
+                }
+            } else {
+                hx_status st = precondition(c, pc, mixed, prm->inner_iters, vj, zj, w32, &info->inner_iters);
+                if (st != HX_OK) return st;
+            }
+            t.rec(1, c->stream);
+            HX_HIP(c, step_apply(c, prm, zj, w, w32));
+            t.rec(2, c->stream);
+            const bool scale_now = !(fuse && will_launch(j + 1));
+            HX_HIP(c, blas_dcgs(c, n, j, V, n, w, sc, c->pin_dev + (size_t)(j % 2) * FG_SLOT, scale_now,
+                                &nb_prev));
+            nb_step[j % 2] = nb_prev;
+            t.rec(3, c->stream);
+            HX_HIP(c, hipEventRecord(ready[j % 2], c->stream));
+            return HX_OK;
+        };
+        for (int j = 0; delayed && will_launch(j); ++j) {
+            if ((j == 0 || !pipe) && (s = launch_step(j)) != HX_OK) return s;
+            const bool more = will_launch(j + 1);
+            const bool ahead = pipe && more;
+            if (ahead && (s = launch_step(j + 1)) != HX_OK) return s;
+            if (hipEventSynchronize(ready[j % 2]) != hipSuccess)
+                return fail(c, HX_ERR_DEVICE, "FGMRES: event wait failed");
+            tms[j % 2]->acc();
+            const double *hs = c->pin_host + (size_t)(j % 2) * FG_SLOT;
             const double rho = hs[DCGS_S + 2], hj = hs[DCGS_S + 3], flag = hs[DCGS_S + 4];
-            const double nu = std::sqrt(hs[128]);
+            const double nu = std::sqrt(host_sum256(hs + FG_PART, nb_step[j % 2]));
             ++it;
             if (j > 0) {
                 // finalise column j-1 with the coefficients of t_j
@@ -512,7 +641,6 @@ hx_status solve_fgmres(hx_ctx *c, const hx_solve_params *prm, const double *b, d
             H.h(j, j) = hj;
             H.h(j + 1, j) = nu;
             nu_prev = nu;
-            const bool last = j + 1 == m || it >= prm->max_iter;
             if (!(nu > 0.0)) {
                 // happy breakdown: the column is final as it stands
                 if (!H.rotate(j)) {
@@ -521,17 +649,19 @@ hx_status solve_fgmres(hx_ctx *c, const hx_solve_params *prm, const double *b, d
                 }
                 j_used = j + 1;
                 record(j);
-                stop = true;
                 break;
             }
-            if (last || H.peek(j) / nb <= prm->rtol) {
+            if (ahead) continue;   // step j+1, in flight, finalises column j
+            if (!more || H.peek(j) / nb <= prm->rtol) {
+                // last step of the cycle, or the provisional column passes:
+                // finalise it here
                 if ((s = finalise(j)) != HX_OK) return s;
                 if (!H.rotate(j)) {
                     sw = true;
                     break;
                 }
                 j_used = j + 1;
-                if (record(j) <= prm->rtol || last) break;
+                if (record(j) <= prm->rtol || !more) break;
                 if (stalled()) {
                     sw = true;
                     break;
@@ -540,7 +670,6 @@ hx_status solve_fgmres(hx_ctx *c, const hx_solve_params *prm, const double *b, d
                 // coefficients and adds them to the now-final column, so undo
                 for (int i = 0; i <= j; ++i) H.h(i, j) = i < j ? hs[64 + i] : hj;
                 H.h(j + 1, j) = nu;
-                // roll the rotation back
                 H.g[j] = H.cs[j] * H.g[j] - H.sn[j] * H.g[j + 1];
                 H.g[j + 1] = 0.0;
                 est_hist.pop_back();
@@ -548,7 +677,6 @@ hx_status solve_fgmres(hx_ctx *c, const hx_solve_params *prm, const double *b, d
                 j_used = j;
             }
         }
-        (void)stop;
         if (j_used > 0) {
             for (int i = j_used - 1; i >= 0; --i) {
                 double t = H.g[i];
@@ -570,6 +698,9 @@ hx_status solve_fgmres(hx_ctx *c, const hx_solve_params *prm, const double *b, d
             }
         }
     }
+    tm.op += tb.op;
+    tm.pc += tb.pc;
+    tm.orth += tb.orth;
     info->iters = it;
     info->history_len = info->history ? hist : 0;
     return HX_OK;
@@ -697,7 +828,10 @@ hx_status hx_solve(hx_ctx *c, const hx_solve_params *prm, const double *b, doubl
     if (prm->pc < HX_PC_NONE || prm->pc > HX_PC_MULTIGRID_MIXED) return fail(c, HX_ERR_ARG, "bad pc");
     if (prm->method == 0 && (prm->pc == HX_PC_LEARNED || prm->mixed))
         return fail(c, HX_ERR_ARG, "CG needs a fixed SPD preconditioner; use FGMRES");
-    if (prm->mixed && prm->inner_iters < 1) return fail(c, HX_ERR_ARG, "inner_iters must be >= 1");
+    if (prm->mixed < 0 || prm->mixed > 2) return fail(c, HX_ERR_ARG, "mixed must be 0, 1 or 2");
+    if (prm->mixed == 1 && prm->inner_iters < 1) return fail(c, HX_ERR_ARG, "inner_iters must be >= 1");
+    if (prm->mixed == 2 && prm->system != 0)
+        return fail(c, HX_ERR_ARG, "the minimal mixed form has an FP32 operator only for the Helmholtz-type system");
     if (prm->mixed && prm->pc == HX_PC_LEARNED)
         return fail(c, HX_ERR_ARG, "the learned preconditioner is FP64; it cannot precondition the inner FP32 solve");
     if (prm->pc == HX_PC_LEARNED && !c->mlp) return fail(c, HX_ERR_STATE, "no network loaded");

@@ -157,6 +157,11 @@ def test_initial_guess_zero_rhs_and_errors(terrain_small):
     with pytest.raises(hx.HXError) as e:
         ctx.solve(to_dev(b), params=hx.default_params(method=0, pc=hx.HX_PC_LEARNED))
     assert e.value.status == hx.HX_ERR_ARG
+    for bad in (dict(mixed=3), dict(mixed=-1), dict(mixed=2, pc=hx.HX_PC_LEARNED),
+                dict(mixed=2, system=1)):
+        with pytest.raises(hx.HXError) as e:
+            ctx.solve(to_dev(b), params=hx.default_params(method=1, **bad))
+        assert e.value.status in (hx.HX_ERR_ARG, hx.HX_ERR_STATE), bad
     ctx.close()
 
 
@@ -218,10 +223,11 @@ def _terrain32_reference():
 
 def test_terrain_32x8x16_forms_vs_oracle_solution():
     """The 32x8x16 Q4 channel against the oracle's 1e-13 solution: FP64
-    FGMRES(30)+BJ, FP64 CG+BJ and the mixed form (FP32 inner CG) reach a 1e-8
+    FGMRES(30)+BJ, FP64 CG+BJ, the mixed form (FP32 inner CG) and the minimal
+    mixed form (FP32 operator and block Jacobi inside FP64 FGMRES) reach a 1e-8
     true residual, the oracle's own residual of each GPU solution is 1e-8 too,
     the FP64 solutions are within 1e-6 of the oracle's (kappa * rtol) and the
-    mixed solution within 1e-7 (the mixed-precision bar)."""
+    mixed solutions within 1e-7 (the mixed-precision bar)."""
     hx = _hx()
     print("[solve] terrain 32x8x16 vs oracle solution", flush=True)
     xs = _terrain32_reference()
@@ -234,7 +240,8 @@ def test_terrain_32x8x16_forms_vs_oracle_solution():
             ("fgmres", hx.default_params(method=1, restart=30, rtol=1e-8), 1e-6),
             ("cg", hx.default_params(method=0, rtol=1e-8), 1e-6),
             ("mixed", hx.default_params(method=1, restart=10, rtol=1e-8, mixed=1, inner_iters=32), 1e-7),
-            ("mixed12", hx.default_params(method=1, restart=10, rtol=1e-8, mixed=1, inner_iters=12), 1e-7)]:
+            ("mixed12", hx.default_params(method=1, restart=10, rtol=1e-8, mixed=1, inner_iters=12), 1e-7),
+            ("minimal", hx.default_params(method=1, restart=30, rtol=1e-8, mixed=2), 1e-7)]:
         x, info = ctx.solve(bd, params=prm)
         x = x.cpu().numpy()
         err = np.linalg.norm(x - xs) / np.linalg.norm(xs)
