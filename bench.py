@@ -417,6 +417,84 @@ def pressure_suite(hx, ctx, torch, label, forms, reps=10, fixed_point=False):
     return out
 
 
+def kernels_suite(hx, ctx, torch, dev, dims, k, reps):
+    """Every hot kernel of the path launched ``reps`` times on the timed mesh
+    (for kernel traces and counters), with its mean time per launch from HIP
+    events on the context's stream and its algorithmic bytes per dof:
+    FP64 and FP32 operator, block Jacobi in both precisions, the learned
+    correction (seeded random network), the consistent-integration operator,
+    the multigrid restriction and prolongation to the 2x coarser channel, and
+    the pressure parts B (gradient) and C (divergence)."""
+    import synth_inputs as si
+    n = ctx.n_dofs
+    nd = (k + 1) ** 3
+    xyz = ctx.dof_coordinates()
+    x = field_on_device(si.rhs_terrain(0), xyz, torch)
+    y = torch.empty_like(x)
+    out = {}
+    # a plain copy of known size (8 n bytes read, 8 n written): the scale of
+    # the HBM byte counters
+    y.copy_(x)
+    torch.cuda.synchronize()
+    log(f"copy calibration: {8 * n} bytes read, {8 * n} bytes written")
+
+    def rec(name, fn, bpd, flops_per_dof=None):
+        ms = time_call(fn, reps, torch)
+        d = dict(ms=round(ms, 4), alg_bytes_per_dof=round(bpd, 2),
+                 alg_GBs=round(bpd * n / (ms * 1e-3) / 1e9, 1))
+        d["frac"] = round(d["alg_GBs"] / HBM_PEAK_GBS, 4)
+        if flops_per_dof:
+            d["TFLOPs"] = round(flops_per_dof * n / (ms * 1e-3) / 1e12, 2)
+        out[name] = d
+        log(f"kernels {name}: {d}")
+
+    _, b64 = ctx.operator_info(hx.HX_F64)
+    _, b32 = ctx.operator_info(hx.HX_F32)
+    rec("operator_f64", lambda: ctx.apply_operator(x, y), b64 / n)
+    x32, y32 = x.float(), torch.empty(n, dtype=torch.float32, device=dev)
+    rec("operator_f32", lambda: ctx.apply_operator(x32, y32), b32 / n)
+    nf = (k + 1) ** 2
+    bj = (3 * nf + 3 * (k + 1) + 4) / nd       # S, l, c per cell, per dof
+    rec("block_jacobi_f64", lambda: ctx.apply_preconditioner(x, y), 16 + 8 * bj)
+    rec("block_jacobi_f32", lambda: ctx.apply_preconditioner(x32, y32), 8 + 4 * bj)
+    del x32, y32
+    # learned: block Jacobi, then the fused correction (reads r_K and the six
+    # neighbour face layers, reads and writes z)
+    n_in = nd + 6 * nf + 1
+    ctx.set_network(si.mlp_init(5, n_in=n_in, n_out=nd))
+    mlp_flops = 2 * (n_in * 256 + 256 * 256 + 256 * nd) / nd
+    rec("learned_pc", lambda: ctx.apply_preconditioner(x, y, kind=hx.HX_PC_LEARNED),
+        16 + 8 * bj + 8 * (nd + 6 * nf) / nd + 16, mlp_flops)
+    # consistent integration
+    fa, fb = si.terrain_coefficients()
+    ctx.set_consistent(field_on_device(fa, xyz, torch), field_on_device(fb, xyz, torch))
+    nq = 2 * k + 1
+    rec("operator_consistent", lambda: ctx.apply_consistent(x, y),
+        (7 * nq ** 3 + 21 * nq ** 2) * 8 / nd + 16)
+    # multigrid transfers to the 2x coarser channel
+    nx, ny, nz = dims
+    mc = si.terrain_mesh(nx // 2, ny // 2, nz // 2, g=4)
+    cc, xc, _ = setup(hx.HelmDG, mc, k, torch, dev)
+    del mc, xc
+    ctx.set_multigrid(cc, *si.refinement_parents(nx // 2, ny // 2, nz // 2))
+    yc = torch.empty(cc.n_dofs, dtype=torch.float64, device=dev)
+    rec("mg_restrict", lambda: ctx.mg_transfer(0, x, yc), 8 + 8 / 8)
+    rec("mg_prolong", lambda: ctx.mg_transfer(1, yc, y), 16 + 8 / 8)
+    ctx.set_multigrid(None)
+    cc.close()
+    del yc
+    # pressure parts
+    gamma, T = 1.4, si.TERRAIN
+    frho, fh = si.terrain_pressure_fields(gamma)
+    ctx.set_pressure_system(field_on_device(frho, xyz, torch), field_on_device(fh, xyz, torch),
+                            gamma, T["dt"])
+    u3 = torch.stack([field_on_device(si.rhs_terrain(s_), xyz, torch) for s_ in (6, 7, 8)])
+    rec("pressure_B", lambda: ctx.apply_pressure_part(hx.HX_PS_GRAD, x), 132.8)
+    rec("pressure_C", lambda: ctx.apply_pressure_part(hx.HX_PS_DIV, u3), 142.4)
+    del u3, xyz, x, y
+    return out
+
+
 def _omp_threads(n=None):
     """Set (n given) or read the OpenMP thread count of the calling thread,
     which runs the oracle's parallel regions."""
@@ -565,6 +643,9 @@ def main():
                     help="only the timed applications (no extra timing windows), for profilers")
     ap.add_argument("--copy-calibrate", action="store_true",
                     help="also run a plain device copy of the x vector (for counter scaling)")
+    ap.add_argument("--kernels", action="store_true",
+                    help="only launch every hot kernel --steps times on the mesh and report "
+                         "each one's time and algorithmic bandwidth (for profilers)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
@@ -584,6 +665,12 @@ def main():
     n = ctx.n_dofs
     log(f"setup {t_setup:.2f} s, {n} dofs")
     del mesh
+    if args.kernels:
+        res = kernels_suite(hx, ctx, torch, dev, (args.nx, args.ny, args.nz), k, args.steps)
+        ctx.close()
+        print(json.dumps({"kernels": res, "config": {"mesh": f"{args.nx}x{args.ny}x{args.nz}",
+                                                     "degree": k, "n_dofs": n}}), flush=True)
+        return
     x = rhs_on_device(xyz, 0, torch)
     del xyz
     y = torch.empty_like(x)

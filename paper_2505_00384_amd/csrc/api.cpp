@@ -51,7 +51,7 @@ static void free_mesh(hx_ctx *c)
                      (void **)&c->work32, (void **)&c->psW, (void **)&c->psWC, (void **)&c->psMr,
                      (void **)&c->psMd, (void **)&c->psFn, (void **)&c->psFh, (void **)&c->psWork,
                      (void **)&c->refq, (void **)&c->qcell, (void **)&c->qface, (void **)&c->chebw,
-                     (void **)&c->mg_cptr, (void **)&c->mg_clist, (void **)&c->mgw,
+                     (void **)&c->mg_cptr, (void **)&c->mg_clist, (void **)&c->mg_child8, (void **)&c->mgw,
                      (void **)&c->mgw32, (void **)&c->chebw32, (void **)&c->ctype,
                      (void **)&c->acell64, (void **)&c->acell32, (void **)&c->kk64,
                      (void **)&c->kk32, (void **)&c->aface64, (void **)&c->aface32,

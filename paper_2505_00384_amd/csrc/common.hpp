@@ -148,6 +148,7 @@ struct hx_ctx {
     int64_t mg_nc = 0;            // cells of the coarser level when linked
     int32_t *mg_cptr = nullptr;   // [mg_nc + 1] children of coarse cell j: mg_clist[cptr[j]..cptr[j+1])
     int32_t *mg_clist = nullptr;  // [n_cells] child cell * 8 + octant, grouped by parent
+    int32_t *mg_child8 = nullptr; // [mg_nc][8] child in octant o, when every coarse cell has all eight
     double *mgw = nullptr;        // [3][n_dofs] b, x (as a coarse level), r
     float *mgw32 = nullptr;       // [3][n_dofs] the same in FP32 (the mixed-precision V-cycle)
 

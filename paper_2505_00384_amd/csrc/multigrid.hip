@@ -141,6 +141,117 @@ __global__ __launch_bounds__(MG_T) void k_transfer(const T *__restrict__ in,
     }
 }
 
+// The same transfers when every coarse cell has all eight children (the
+// uniform hierarchy): child8[8 j + o] is the child in octant o of coarse cell
+// j.  The tensor-product sweeps are ordered so that the children of one pair
+// of octants are combined as early as possible: the restriction sweeps x on
+// all eight children and adds the two x-neighbours (four results), then y
+// (two), then z (one); the prolongation expands z (two), y (four), then x
+// (eight).  Every thread reads its child indices itself, so the loads start
+// without a barrier.  One workgroup per coarse cell.
+template <int N, typename T>
+__global__ __launch_bounds__(MG_T) void k_restrict8(const T *__restrict__ in, T *__restrict__ out,
+                                                    const int32_t *__restrict__ child8,
+                                                    const RefTab64 *__restrict__ tab, int64_t n_coarse)
+{
+    constexpr int ND = N * N * N, NF = N * N;
+    __shared__ T sE[2][NF];
+    __shared__ T sA[8][ND];
+    __shared__ T sB[4][ND];
+    const int t = threadIdx.x;
+    const int64_t cc = blockIdx.x;
+    if (cc >= n_coarse) return;
+    for (int e = t; e < 2 * NF; e += MG_T) sE[e / NF][e % NF] = (T)tab->Eh[e / NF][e % NF];
+    for (int idx = t; idx < 8 * ND; idx += MG_T) {
+        const int o = idx / ND, e = idx - o * ND;
+        sA[o][e] = in[(int64_t)child8[cc * 8 + o] * ND + e];
+    }
+    __syncthreads();
+    // x: (a, j, l) of pair p = oy + 2 oz, summed over ox
+    for (int idx = t; idx < 4 * ND; idx += MG_T) {
+        const int p = idx / ND, e = idx - p * ND;
+        const int a = e % N, jl = e / N;
+        T s = 0;
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+            s += sE[0][i * N + a] * sA[2 * p][i + N * jl] + sE[1][i * N + a] * sA[2 * p + 1][i + N * jl];
+        sB[p][e] = s;
+    }
+    __syncthreads();
+    // y: (a, b, l) of oz, summed over oy
+    for (int idx = t; idx < 2 * ND; idx += MG_T) {
+        const int q = idx / ND, e = idx - q * ND;
+        const int a = e % N, b = (e / N) % N, l = e / NF;
+        T s = 0;
+#pragma unroll
+        for (int j = 0; j < N; ++j)
+            s += sE[0][j * N + b] * sB[2 * q][a + N * (j + N * l)] +
+                 sE[1][j * N + b] * sB[2 * q + 1][a + N * (j + N * l)];
+        sA[q][e] = s;
+    }
+    __syncthreads();
+    // z: summed over oz
+    for (int e = t; e < ND; e += MG_T) {
+        const int ab = e % NF, c = e / NF;
+        T s = 0;
+#pragma unroll
+        for (int l = 0; l < N; ++l)
+            s += sE[0][l * N + c] * sA[0][ab + NF * l] + sE[1][l * N + c] * sA[1][ab + NF * l];
+        out[cc * ND + e] = s;
+    }
+}
+
+template <int N, typename T>
+__global__ __launch_bounds__(MG_T) void k_prolong8(const T *__restrict__ in, T *__restrict__ out,
+                                                   const int32_t *__restrict__ child8,
+                                                   const RefTab64 *__restrict__ tab, int64_t n_coarse)
+{
+    constexpr int ND = N * N * N, NF = N * N;
+    __shared__ T sE[2][NF];
+    __shared__ T sC[ND];
+    __shared__ T sZ[2][ND];
+    __shared__ T sY[4][ND];
+    const int t = threadIdx.x;
+    const int64_t cc = blockIdx.x;
+    if (cc >= n_coarse) return;
+    for (int e = t; e < 2 * NF; e += MG_T) sE[e / NF][e % NF] = (T)tab->Eh[e / NF][e % NF];
+    for (int e = t; e < ND; e += MG_T) sC[e] = in[cc * ND + e];
+    __syncthreads();
+    // z: (a, b, l) for oz = 0, 1
+    for (int idx = t; idx < 2 * ND; idx += MG_T) {
+        const int q = idx / ND, e = idx - q * ND;
+        const int ab = e % NF, l = e / NF;
+        T s = 0;
+#pragma unroll
+        for (int c = 0; c < N; ++c) s += sE[q][l * N + c] * sC[ab + NF * c];
+        sZ[q][e] = s;
+    }
+    __syncthreads();
+    // y: (a, j, l) for p = oy + 2 oz
+    for (int idx = t; idx < 4 * ND; idx += MG_T) {
+        const int p = idx / ND, e = idx - p * ND;
+        const int a = e % N, j = (e / N) % N, l = e / NF;
+        const T *E = sE[p & 1] + j * N;
+        const T *src = sZ[p >> 1];
+        T s = 0;
+#pragma unroll
+        for (int b = 0; b < N; ++b) s += E[b] * src[a + N * (b + N * l)];
+        sY[p][e] = s;
+    }
+    __syncthreads();
+    // x: (i, j, l) of octant o = ox + 2 p, added to the child
+    for (int idx = t; idx < 8 * ND; idx += MG_T) {
+        const int o = idx / ND, e = idx - o * ND;
+        const int i = e % N, jl = e / N;
+        const T *E = sE[o & 1] + i * N;
+        const T *src = sY[o >> 1];
+        T s = 0;
+#pragma unroll
+        for (int a = 0; a < N; ++a) s += E[a] * src[a + N * jl];
+        out[(int64_t)child8[cc * 8 + o] * ND + e] += s;
+    }
+}
+
 template <bool RESTRICT, typename T>
 hipError_t transfer(hx_ctx *c, const T *in, T *out)
 {
@@ -149,8 +260,15 @@ hipError_t transfer(hx_ctx *c, const T *in, T *out)
     const dim3 g((unsigned)nc), b(MG_T);
 #define HX_MG_CASE(NN)                                                                           \
     case NN:                                                                                     \
-        hipLaunchKernelGGL((k_transfer<NN, RESTRICT, T>), g, b, 0, c->stream, in, out, c->mg_cptr, \
-                           c->mg_clist, c->ref, nc);                                             \
+        if (c->mg_child8 && RESTRICT)                                                            \
+            hipLaunchKernelGGL((k_restrict8<NN, T>), g, b, 0, c->stream, in, out, c->mg_child8,  \
+                               c->ref, nc);                                                      \
+        else if (c->mg_child8)                                                                   \
+            hipLaunchKernelGGL((k_prolong8<NN, T>), g, b, 0, c->stream, in, out, c->mg_child8,   \
+                               c->ref, nc);                                                      \
+        else                                                                                     \
+            hipLaunchKernelGGL((k_transfer<NN, RESTRICT, T>), g, b, 0, c->stream, in, out,       \
+                               c->mg_cptr, c->mg_clist, c->ref, nc);                             \
         break;
     switch (c->n) {
         HX_MG_CASE(2) HX_MG_CASE(3) HX_MG_CASE(4) HX_MG_CASE(5) HX_MG_CASE(6) HX_MG_CASE(7)

@@ -966,6 +966,7 @@ hx_status hx_set_multigrid(hx_ctx *c, hx_ctx *coarse, const int32_t *parent, con
     HX_HIP(c, hipSetDevice(c->device));
     dfree((void **)&c->mg_cptr);
     dfree((void **)&c->mg_clist);
+    dfree((void **)&c->mg_child8);
     c->mg_coarse = nullptr;
     c->mg_nc = 0;
     if (!coarse) return HX_OK;
@@ -1006,6 +1007,16 @@ hx_status hx_set_multigrid(hx_ctx *c, hx_ctx *coarse, const int32_t *parent, con
     if (s != HX_OK) return s;
     HX_HIP(c, hipMemcpy(c->mg_cptr, ptr.data(), sizeof(int32_t) * (nc + 1), hipMemcpyHostToDevice));
     HX_HIP(c, hipMemcpy(c->mg_clist, list.data(), sizeof(int32_t) * nf, hipMemcpyHostToDevice));
+    // every coarse cell with all eight children: the octant table of the
+    // dense transfer kernels
+    bool full = nf == 8 * nc;
+    for (int64_t j = 0; full && j < nc; ++j) full = used[j] == 0xFF;
+    if (full) {
+        std::vector<int32_t> c8((size_t)8 * nc);
+        for (int64_t f = 0; f < nf; ++f) c8[(size_t)8 * parent[f] + octant[f]] = (int32_t)f;
+        if ((s = dalloc(c, (void **)&c->mg_child8, sizeof(int32_t) * 8 * nc)) != HX_OK) return s;
+        HX_HIP(c, hipMemcpy(c->mg_child8, c8.data(), sizeof(int32_t) * 8 * nc, hipMemcpyHostToDevice));
+    }
     c->mg_coarse = coarse;
     c->mg_nc = nc;
     return HX_OK;
