@@ -317,6 +317,7 @@ def consistent_suite(ctx, torch, k, reps=10):
     del xr
     out = dict(nq=nq, ms=round(ms, 3), gdofs=round(n / (ms * 1e-3) / 1e9, 3),
                alg_bytes_per_dof=round(bpd, 1), alg_GBs=round(bpd * n / (ms * 1e-3) / 1e9, 1),
+               frac=round(bpd * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                set_consistent_s=round(t_set, 2), rel_diff_fast_vs_consistent_smooth=alias,
                rel_diff_fast_vs_consistent_random=alias_r)
     log(f"consistent integration: {out}")
@@ -638,7 +639,7 @@ def main():
                     help="polynomial degree (default 4, the benchmark's)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-layers", type=int, default=4)
-    ap.add_argument("--fp32", action="store_true", help="also time the FP32 operator")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the timing of the FP32 operator")
     ap.add_argument("--profile-run", action="store_true",
                     help="only the timed applications (no extra timing windows), for profilers")
     ap.add_argument("--copy-calibrate", action="store_true",
@@ -684,7 +685,7 @@ def main():
     if not args.profile_run:
         extra["operator"] = operator_windows(hx, ctx, x, y, torch, n, op_bytes, counts)
         log(f"operator: {extra['operator']}")
-    if args.fp32:
+    if not args.no_fp32:
         x32 = x.float()
         y32 = torch.empty_like(x32)
         ms32 = time_matvec(ctx, x32, y32, args.steps, args.warmup, torch)

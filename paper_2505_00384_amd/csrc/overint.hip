@@ -50,7 +50,7 @@ __device__ __forceinline__ int qlay(int d, int m, int e1, int e2)
 }
 
 template <int N>
-__global__ void __launch_bounds__(q_nt<N>())
+__global__ void __launch_bounds__(q_nt<N>(), 4)
 k_apply_q(const double *__restrict__ x, double *__restrict__ y, const double *__restrict__ cell,
           const double *__restrict__ face, const int32_t *__restrict__ nbr,
           const RefTabQ *__restrict__ TQ, const RefTab64 *__restrict__ T, int n_cells)
@@ -60,11 +60,18 @@ k_apply_q(const double *__restrict__ x, double *__restrict__ y, const double *__
     constexpr int ND = C::ND, NF = C::NF, Q2 = C::Q2, Q3 = C::Q3, QNN = C::QNN, QQN = C::QQN;
     __shared__ double sB[Q * N], sD[Q * N], sDL[2][N];
     __shared__ double sX[ND];
-    __shared__ double U0[QNN], U1[QNN];
-    __shared__ double V0[QQN], V1[QQN], V2[QQN];
-    __shared__ double Lo[NF], Do[NF], Ln[NF], Dn[NF];
-    __shared__ double Pv[Q2], P1[Q2], P2[Q2], Pn[Q2];
     __shared__ double FA[6][2][NF];
+    // one pool for the sweep buffers of the cell part (U0, U1, V0, V1, V2)
+    // and, once those are free, the face stage: U0 keeps the output pencils
+    // and the face arrays overlay U1 .. V2
+    constexpr int CELLW = QNN + 3 * QQN, FACEW = 4 * NF + 9 * C::QN + 4 * Q2;
+    __shared__ double pool[QNN + (CELLW > FACEW ? CELLW : FACEW)];
+    double *const U0 = pool, *const U1 = pool + QNN, *const V0 = U1 + QNN, *const V1 = V0 + QQN,
+                 *const V2 = V1 + QQN;
+    double *const Lo = U1, *const Do = Lo + NF, *const Ln = Do + NF, *const Dn = Ln + NF;
+    double *const Tf = Dn + NF;                 // [6][Q N]: e1-contractions, lane a + Q e2
+    double *const Pv = Tf + 6 * C::QN, *const P1 = Pv + Q2, *const P2 = P1 + Q2, *const Pn = P2 + Q2;
+    double *const Gf = Pn + Q2;                 // [3][N Q]: a-contractions back, lane e1 + N b
     const int t = threadIdx.x;
     const int64_t cid = blockIdx.x;
     for (int e = t; e < Q * N; e += blockDim.x) {
@@ -206,17 +213,19 @@ k_apply_q(const double *__restrict__ x, double *__restrict__ y, const double *__
     }
 
     // ---------------------------------------------------------------- faces
-    // the face-point lanes (a, b) keep their rows of B and BD
-    double Ra[N], Rda[N], Rb[N], Rdb[N];
-    if (t < Q2) {
-        const int a = t % Q, b = t / Q;
+    // The output pencils wait in LDS (U0, free after the transposed x
+    // sweep) while the faces run.  Per face, sum-factorised in two 1-D
+    // steps each way: lanes (e1, e2) form the own and the neighbour's face
+    // layer and normal-derivative column; lanes (a, e2) contract along e1
+    // (value and e1-derivative of both layers, value of both derivative
+    // columns); lanes (a, b) contract along e2 and form the flux terms at the
+    // face points; lanes (e1, b) and then (e1, e2) contract back.
+    __syncthreads();
+    double *sY = U0;
+    if (t < NF) {
+        const int j = t % N, l = t / N;
 #pragma unroll
-        for (int e = 0; e < N; ++e) {
-            Ra[e] = sB[a * N + e];
-            Rda[e] = sD[a * N + e];
-            Rb[e] = sB[b * N + e];
-            Rdb[e] = sD[b * N + e];
-        }
+        for (int i = 0; i < N; ++i) sY[i + N * j + NF * l] = Y[i];
     }
     for (int f = 0; f < 6; ++f) {
         const int d = f >> 1, s = f & 1;
@@ -241,25 +250,45 @@ k_apply_q(const double *__restrict__ x, double *__restrict__ y, const double *__
             Dn[t] = dnv;
         }
         __syncthreads();
-        // face points: values, tangential and normal derivatives, flux terms
+        // along e1: lane (a, e2)
+        if (t < C::QN) {
+            const int a = t % Q, e2 = t / Q;
+            double c0 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0, c5 = 0;
+#pragma unroll
+            for (int e1 = 0; e1 < N; ++e1) {
+                const double ba = sB[a * N + e1], da = sD[a * N + e1];
+                const int k = e1 + N * e2;
+                c0 += ba * Lo[k];
+                c1 += da * Lo[k];
+                c2 += ba * Do[k];
+                c3 += ba * Ln[k];
+                c4 += da * Ln[k];
+                c5 += ba * Dn[k];
+            }
+            Tf[0 * C::QN + t] = c0;
+            Tf[1 * C::QN + t] = c1;
+            Tf[2 * C::QN + t] = c2;
+            Tf[3 * C::QN + t] = c3;
+            Tf[4 * C::QN + t] = c4;
+            Tf[5 * C::QN + t] = c5;
+        }
+        __syncthreads();
+        // along e2 and the flux terms: lane (a, b)
         if (t < Q2) {
+            const int a = t % Q, b = t / Q;
             double vo = 0, t1o = 0, t2o = 0, dno = 0, vn = 0, t1n = 0, t2n = 0, dnn = 0;
 #pragma unroll
             for (int e2 = 0; e2 < N; ++e2) {
-                const double bb = Rb[e2], db = Rdb[e2];
-#pragma unroll
-                for (int e1 = 0; e1 < N; ++e1) {
-                    const double ba = Ra[e1], da = Rda[e1];
-                    const int k = e1 + N * e2;
-                    vo += ba * bb * Lo[k];
-                    t1o += da * bb * Lo[k];
-                    t2o += ba * db * Lo[k];
-                    dno += ba * bb * Do[k];
-                    vn += ba * bb * Ln[k];
-                    t1n += da * bb * Ln[k];
-                    t2n += ba * db * Ln[k];
-                    dnn += ba * bb * Dn[k];
-                }
+                const double bb = sB[b * N + e2], db = sD[b * N + e2];
+                const int k = a + Q * e2;
+                vo += bb * Tf[0 * C::QN + k];
+                t1o += bb * Tf[1 * C::QN + k];
+                t2o += db * Tf[0 * C::QN + k];
+                dno += bb * Tf[2 * C::QN + k];
+                vn += bb * Tf[3 * C::QN + k];
+                t1n += bb * Tf[4 * C::QN + k];
+                t2n += db * Tf[3 * C::QN + k];
+                dnn += bb * Tf[5 * C::QN + k];
             }
             const int64_t fid = s ? cid : (int64_t)nb;
             const double *fd = face + (fid * 3 + d) * 7 * Q2 + t;
@@ -275,43 +304,60 @@ k_apply_q(const double *__restrict__ x, double *__restrict__ y, const double *__
             P2[t] = hj * fd[(go + 2) * Q2];
         }
         __syncthreads();
-        // back to layer weights (value test) and normal-derivative weights
+        // back along a: lane (e1, b)
+        if (t < C::QN) {
+            const int e1 = t % N, b = t / N;
+            double g = 0, h = 0, kk = 0;
+#pragma unroll
+            for (int a = 0; a < Q; ++a) {
+                const double ba = sB[a * N + e1], da = sD[a * N + e1];
+                const int k = a + Q * b;
+                g += ba * Pv[k] + da * P1[k];
+                h += ba * P2[k];
+                kk += ba * Pn[k];
+            }
+            Gf[0 * C::QN + t] = g;
+            Gf[1 * C::QN + t] = h;
+            Gf[2 * C::QN + t] = kk;
+        }
+        __syncthreads();
+        // back along b: lane (e1, e2)
         if (t < NF) {
             const int e1 = t % N, e2 = t / N;
             double f0 = 0.0, f1 = 0.0;
+#pragma unroll
             for (int b = 0; b < Q; ++b) {
                 const double bb = sB[b * N + e2], db = sD[b * N + e2];
-                for (int a = 0; a < Q; ++a) {
-                    const double ba = sB[a * N + e1], da = sD[a * N + e1];
-                    const int k = a + Q * b;
-                    f0 += ba * bb * Pv[k] + da * bb * P1[k] + ba * db * P2[k];
-                    f1 += ba * bb * Pn[k];
-                }
+                const int k = e1 + N * b;
+                f0 += bb * Gf[0 * C::QN + k] + db * Gf[1 * C::QN + k];
+                f1 += bb * Gf[2 * C::QN + k];
             }
             FA[f][0][t] = f0;
             FA[f][1][t] = f1;
         }
-        __syncthreads();
     }
     __syncthreads();
     // pencil owners (j, l) add the six faces
     if (t < NF) {
         const int j = t % N, l = t / N;
+        double Yp[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) Yp[i] = sY[i + N * j + NF * l];
         for (int s = 0; s < 2; ++s) {
             const int layer = s ? N - 1 : 0;
             // x faces: normal coordinate i, (e1, e2) = (j, l)
             {
                 const double f0 = FA[s][0][j + N * l], f1 = FA[s][1][j + N * l];
-                for (int i = 0; i < N; ++i) Y[i] += sDL[s][i] * f1 + (i == layer ? f0 : 0.0);
+                for (int i = 0; i < N; ++i) Yp[i] += sDL[s][i] * f1 + (i == layer ? f0 : 0.0);
             }
             // y faces: normal coordinate j, (e1, e2) = (i, l)
             for (int i = 0; i < N; ++i)
-                Y[i] += sDL[s][j] * FA[2 + s][1][i + N * l] + (j == layer ? FA[2 + s][0][i + N * l] : 0.0);
+                Yp[i] += sDL[s][j] * FA[2 + s][1][i + N * l] + (j == layer ? FA[2 + s][0][i + N * l] : 0.0);
             // z faces: normal coordinate l, (e1, e2) = (i, j)
             for (int i = 0; i < N; ++i)
-                Y[i] += sDL[s][l] * FA[4 + s][1][i + N * j] + (l == layer ? FA[4 + s][0][i + N * j] : 0.0);
+                Yp[i] += sDL[s][l] * FA[4 + s][1][i + N * j] + (l == layer ? FA[4 + s][0][i + N * j] : 0.0);
         }
-        for (int i = 0; i < N; ++i) y[cid * ND + i + N * j + NF * l] = Y[i];
+        for (int i = 0; i < N; ++i) y[cid * ND + i + N * j + NF * l] = Yp[i];
     }
 }
 
