@@ -299,9 +299,7 @@ __device__ __forceinline__ void apply_body(
 
     T Y[N];
     // =========================================================== cell part
-    // x sweep: lane (j=a, l=b): B u and BD u along x; the lane's own input
-    // pencil is kept when the caller wants x.(A x)
-    T xp[N];
+    // x sweep: lane (j=a, l=b): B u and BD u along x
     if constexpr (!DO_CELL) {
 #pragma unroll
         for (int i = 0; i < N; ++i) Y[i] = T(0);
@@ -310,10 +308,7 @@ __device__ __forceinline__ void apply_body(
     if (cl) {
         T r[N], s0[N], s1[N];
 #pragma unroll
-        for (int i = 0; i < N; ++i) {
-            r[i] = U[i + N * a + NF * b];
-            if (DOT) xp[i] = r[i];
-        }
+        for (int i = 0; i < N; ++i) r[i] = U[i + N * a + NF * b];
         const EvenOdd<T, N> xr(r);
         contract<T, N, 0, false>(xr, s0);
         contract<T, N, 1, false>(xr, s1);
@@ -716,12 +711,15 @@ __device__ __forceinline__ void apply_body(
 #pragma unroll
         for (int i = 0; i < N; ++i) y[o + i] = bvec ? bvec[o + i] - Y[i] : Y[i];
     }
-    // x.(A x) of the wave's cells (fixed-order wave sum), for CG's p.q
+    // x.(A x) of the wave's cells (fixed-order wave sum), for CG's p.q; the
+    // lane's input pencil is read again (it was read at the start, so it is
+    // likely in L2) rather than kept in registers through the kernel
     if (DOT) {
         double acc = 0.0;
         if (cl) {
+            const T *xo = x + cid * ND + N * a + NF * b;
 #pragma unroll
-            for (int i = 0; i < N; ++i) acc += (double)xp[i] * (double)Y[i];
+            for (int i = 0; i < N; ++i) acc += (double)xo[i] * (double)Y[i];
         }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
