@@ -12,9 +12,9 @@
 // k_hang_apply computes each quarter's contributions to the test functions
 // of both cells (one workgroup per quarter, no atomics) into a staging
 // buffer, and k_hang_gather adds them to y cell by cell in a fixed order, so
-// results stay bitwise reproducible.  Quarter faces are a small fraction of
-// all faces, so these kernels favour simplicity: basis values at the points
-// come from Lagrange evaluation and the contractions run over all dofs.
+// results stay bitwise reproducible.  The set-up kernels evaluate the basis
+// and the map at the points directly (Lagrange evaluation); the apply kernel
+// sum-factorises on the face.
 //
 // Records: {C, fc, F, s}: face fc (0..5 = -x, +x, -y, +y, -z, +z) of the
 // coarse cell C, face fc ^ 1 of the fine cell F, quarter s.  Point (a, b) of
@@ -201,67 +201,159 @@ __global__ void k_hang_coef(int n, int64_t n_hang, const int32_t *__restrict__ h
     }
 }
 
-// contributions of one quarter to the test functions of both cells (block of
-// 64 threads per quarter): contrib[h][side][nd], side 0 coarse, 1 fine
+// contributions of one quarter to the test functions of both cells (one
+// wave per quarter): contrib[h][side][nd], side 0 coarse, 1 fine.  Both
+// sides' traces are sum-factorised on the face: items (side, i1, i2) take the
+// face layer and the normal-derivative column (GLL nodes lie on the face, so
+// the normal direction needs the end node and the derivative weights only),
+// items (side, a, i2) contract along the first tangential direction with the
+// side's 1-D tables at the quarter's points (the coarse side's at
+// ((s + xi)/2)), items (a, b) along the second and form the flux terms of
+// both sides, and the same steps run backwards to the face layer and the
+// normal lines, which each item (side, i1, i2) writes whole.
 template <int N, typename T>
 __global__ void __launch_bounds__(64)
 k_hang_apply(int64_t n_hang, const int32_t *__restrict__ hang, const RefTab64 *__restrict__ TB,
              const T *__restrict__ hd, const T *__restrict__ x, T *__restrict__ contrib)
 {
     constexpr int NF = N * N, ND = NF * N;
-    __shared__ T sv[2][NF][3][N], sd[2][NF][3][N];   // 1-D values and derivatives per point
-    __shared__ T cv[2][NF], cg[2][NF][3];              // test coefficients per point
+    __shared__ T tb[2][2][2][NF];          // [side][tangential axis][value, derivative][a * N + i]
+    __shared__ T sDL[2][N];                // l_m'(0), l_m'(1)
+    __shared__ T Lv[2][NF], Ld[2][NF];     // face layer and normal derivative, [side][i1 + N i2]
+    __shared__ T T0[2][NF], T1[2][NF], T2[2][NF];   // along t1, [side][a + N i2]
+    __shared__ T Wv[2][NF], Wa[2][NF], Wb[2][NF], Wn[2][NF];   // weights per point a + N b
+    __shared__ T Gv[2][NF], Gb[2][NF], Gn[2][NF];   // back along t1, [side][i1 + N b]
     const int64_t h = blockIdx.x;
     const int32_t *rec = hang + 4 * h;
-    const int minus = (rec[1] & 1) ? 0 : 1;
+    const int fc = rec[1], d = fc >> 1, sq = rec[3];
+    const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+    const int st[3] = {1, N, NF};
+    const int s1 = st[t1], s2 = st[t2], sn = st[d];
+    // end node along the normal: the coarse cell's face fc, the fine cell's fc ^ 1
+    const int eside[2] = {(fc & 1) ? 1 : 0, ((fc ^ 1) & 1) ? 1 : 0};
+    const int minus = (fc & 1) ? 0 : 1;
     const T *xs[2] = {x + (int64_t)rec[0] * ND, x + (int64_t)rec[2] * ND};
     const int tid = threadIdx.x;
+    // 1-D tables: fine side from the set-up tables, coarse side at the
+    // quarter's points
+    if (tid < 2 * N) {
+        const int ax = tid / N, a = tid % N;
+        const int half = ax == 0 ? (sq & 1) : (sq >> 1);
+        T v[N], dv[N];
+        lag_nodes<T>(N, TB->xl, 0.5 * (half + TB->xq[a]), v, dv);
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            tb[0][ax][0][a * N + i] = v[i];
+            tb[0][ax][1][a * N + i] = dv[i];
+        }
+    }
+    for (int e = tid; e < 2 * NF; e += 64) {
+        const int ax = e / NF, k = e % NF;
+        tb[1][ax][0][k] = (T)TB->B[k];
+        tb[1][ax][1][k] = (T)TB->BD[k];
+    }
+    if (tid < 2 * N) sDL[tid / N][tid % N] = (T)TB->DL[tid / N][tid % N];
+    __syncthreads();
+    // face layer and normal derivative: item (side, i1, i2)
+    for (int it = tid; it < 2 * NF; it += 64) {
+        const int side = it / NF, k = it % NF;
+        const int i1 = k % N, i2 = k / N;
+        const T *xp = xs[side] + i1 * s1 + i2 * s2;
+        const int e = eside[side];
+        T dn = 0;
+#pragma unroll
+        for (int m = 0; m < N; ++m) dn += sDL[e][m] * xp[m * sn];
+        Lv[side][k] = xp[(e ? N - 1 : 0) * sn];
+        Ld[side][k] = dn;
+    }
+    __syncthreads();
+    // along t1: item (side, a, i2)
+    for (int it = tid; it < 2 * NF; it += 64) {
+        const int side = it / NF, k = it % NF;
+        const int a = k % N, i2 = k / N;
+        const T *B1 = tb[side][0][0] + a * N, *D1 = tb[side][0][1] + a * N;
+        T c0 = 0, c1 = 0, c2 = 0;
+#pragma unroll
+        for (int i1 = 0; i1 < N; ++i1) {
+            c0 += B1[i1] * Lv[side][i1 + N * i2];
+            c1 += D1[i1] * Lv[side][i1 + N * i2];
+            c2 += B1[i1] * Ld[side][i1 + N * i2];
+        }
+        T0[side][k] = c0;
+        T1[side][k] = c1;
+        T2[side][k] = c2;
+    }
+    __syncthreads();
+    // along t2 and the flux terms at point (a, b): both sides in one item
     for (int pt = tid; pt < NF; pt += 64) {
         const int a = pt % N, b = pt / N;
-        double xi[2][3];
-        quarter_points(TB, rec, a, b, xi[1], xi[0]);
         T u[2], gr[2][3];
-        for (int side = 0; side < 2; ++side) {
-            for (int c = 0; c < 3; ++c) lag_nodes<T>(N, TB->xl, xi[side][c], sv[side][pt][c], sd[side][pt][c]);
-            T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-            for (int l = 0; l < N; ++l)
-                for (int j = 0; j < N; ++j)
-                    for (int i = 0; i < N; ++i) {
-                        const T xv = xs[side][i + N * (j + N * l)];
-                        const T v0 = sv[side][pt][0][i], v1 = sv[side][pt][1][j], v2 = sv[side][pt][2][l];
-                        s0 += v0 * v1 * v2 * xv;
-                        s1 += sd[side][pt][0][i] * v1 * v2 * xv;
-                        s2 += v0 * sd[side][pt][1][j] * v2 * xv;
-                        s3 += v0 * v1 * sd[side][pt][2][l] * xv;
-                    }
-            u[side] = s0;
-            gr[side][0] = s1;
-            gr[side][1] = s2;
-            gr[side][2] = s3;
+#pragma unroll
+        for (int sd = 0; sd < 2; ++sd) {
+            const T *B2 = tb[sd][1][0] + b * N, *D2 = tb[sd][1][1] + b * N;
+            T v = 0, ga = 0, gb = 0, gn = 0;
+#pragma unroll
+            for (int i2 = 0; i2 < N; ++i2) {
+                v += B2[i2] * T0[sd][a + N * i2];
+                ga += B2[i2] * T1[sd][a + N * i2];
+                gb += D2[i2] * T0[sd][a + N * i2];
+                gn += B2[i2] * T2[sd][a + N * i2];
+            }
+            u[sd] = v;
+            gr[sd][t1] = ga;
+            gr[sd][t2] = gb;
+            gr[sd][d] = gn;
         }
         const T *g = hd + h * 7 * NF + pt;
         T flux = 0;
+#pragma unroll
         for (int r = 0; r < 3; ++r) flux += g[r * NF] * gr[0][r] + g[(3 + r) * NF] * gr[1][r];
         const T jump = u[minus] - u[1 - minus];
         const T pen = g[6 * NF];
-        for (int side = 0; side < 2; ++side) {
-            const T z = side == minus ? T(1) : T(-1);
-            cv[side][pt] = z * (T(-0.5) * flux + pen * jump);
-            for (int r = 0; r < 3; ++r) cg[side][pt][r] = T(-0.5) * jump * g[(3 * side + r) * NF];
+#pragma unroll
+        for (int sd = 0; sd < 2; ++sd) {
+            const T z = sd == minus ? T(1) : T(-1);
+            const T hj = T(-0.5) * jump;
+            Wv[sd][pt] = z * (T(-0.5) * flux + pen * jump);
+            Wa[sd][pt] = hj * g[(3 * sd + t1) * NF];
+            Wb[sd][pt] = hj * g[(3 * sd + t2) * NF];
+            Wn[sd][pt] = hj * g[(3 * sd + d) * NF];
         }
     }
     __syncthreads();
-    for (int e = tid; e < 2 * ND; e += 64) {
-        const int side = e / ND, i = e % ND;
-        const int ia = i % N, ja = (i / N) % N, la = i / NF;
-        T acc = 0;
-        for (int pt = 0; pt < NF; ++pt) {
-            const T v0 = sv[side][pt][0][ia], v1 = sv[side][pt][1][ja], v2 = sv[side][pt][2][la];
-            acc += cv[side][pt] * v0 * v1 * v2 + cg[side][pt][0] * sd[side][pt][0][ia] * v1 * v2 +
-                   cg[side][pt][1] * v0 * sd[side][pt][1][ja] * v2 +
-                   cg[side][pt][2] * v0 * v1 * sd[side][pt][2][la];
+    // back along t1: item (side, i1, b)
+    for (int it = tid; it < 2 * NF; it += 64) {
+        const int side = it / NF, k = it % NF;
+        const int i1 = k % N, b = k / N;
+        const T *B1 = tb[side][0][0], *D1 = tb[side][0][1];
+        T gv = 0, gb = 0, gn = 0;
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+            const int pt = a + N * b;
+            gv += B1[a * N + i1] * Wv[side][pt] + D1[a * N + i1] * Wa[side][pt];
+            gb += B1[a * N + i1] * Wb[side][pt];
+            gn += B1[a * N + i1] * Wn[side][pt];
         }
-        contrib[(h * 2 + side) * ND + i] = acc;
+        Gv[side][k] = gv;
+        Gb[side][k] = gb;
+        Gn[side][k] = gn;
+    }
+    __syncthreads();
+    // back along t2 and out: item (side, i1, i2) writes its normal line
+    for (int it = tid; it < 2 * NF; it += 64) {
+        const int side = it / NF, k = it % NF;
+        const int i1 = k % N, i2 = k / N;
+        const T *B2 = tb[side][1][0], *D2 = tb[side][1][1];
+        T f0 = 0, f1 = 0;
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+            f0 += B2[b * N + i2] * Gv[side][i1 + N * b] + D2[b * N + i2] * Gb[side][i1 + N * b];
+            f1 += B2[b * N + i2] * Gn[side][i1 + N * b];
+        }
+        const int e = eside[side];
+        T *out = contrib + (h * 2 + side) * ND + i1 * s1 + i2 * s2;
+#pragma unroll
+        for (int m = 0; m < N; ++m) out[m * sn] = sDL[e][m] * f1 + (m == (e ? N - 1 : 0) ? f0 : T(0));
     }
 }
 

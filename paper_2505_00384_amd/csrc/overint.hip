@@ -64,14 +64,13 @@ k_apply_q(const double *__restrict__ x, double *__restrict__ y, const double *__
     // one pool for the sweep buffers of the cell part (U0, U1, V0, V1, V2)
     // and, once those are free, the face stage: U0 keeps the output pencils
     // and the face arrays overlay U1 .. V2
-    constexpr int CELLW = QNN + 3 * QQN, FACEW = 4 * NF + 9 * C::QN + 4 * Q2;
+    // the face stage handles the two faces of one direction together: per
+    // face 4 NF (layers), 6 QN (along e1), 4 Q2 (face points), 3 QN (back)
+    constexpr int FACE1 = 4 * NF + 9 * C::QN + 4 * Q2;
+    constexpr int CELLW = QNN + 3 * QQN, FACEW = 2 * FACE1;
     __shared__ double pool[QNN + (CELLW > FACEW ? CELLW : FACEW)];
     double *const U0 = pool, *const U1 = pool + QNN, *const V0 = U1 + QNN, *const V1 = V0 + QQN,
                  *const V2 = V1 + QQN;
-    double *const Lo = U1, *const Do = Lo + NF, *const Ln = Do + NF, *const Dn = Ln + NF;
-    double *const Tf = Dn + NF;                 // [6][Q N]: e1-contractions, lane a + Q e2
-    double *const Pv = Tf + 6 * C::QN, *const P1 = Pv + Q2, *const P2 = P1 + Q2, *const Pn = P2 + Q2;
-    double *const Gf = Pn + Q2;                 // [3][N Q]: a-contractions back, lane e1 + N b
     const int t = threadIdx.x;
     const int64_t cid = blockIdx.x;
     for (int e = t; e < Q * N; e += blockDim.x) {
@@ -214,12 +213,13 @@ k_apply_q(const double *__restrict__ x, double *__restrict__ y, const double *__
 
     // ---------------------------------------------------------------- faces
     // The output pencils wait in LDS (U0, free after the transposed x
-    // sweep) while the faces run.  Per face, sum-factorised in two 1-D
-    // steps each way: lanes (e1, e2) form the own and the neighbour's face
-    // layer and normal-derivative column; lanes (a, e2) contract along e1
-    // (value and e1-derivative of both layers, value of both derivative
-    // columns); lanes (a, b) contract along e2 and form the flux terms at the
-    // face points; lanes (e1, b) and then (e1, e2) contract back.
+    // sweep) while the faces run, the two faces of each direction together.
+    // Per face, sum-factorised in two 1-D steps each way: items (e1, e2)
+    // form the own and the neighbour's face layer and normal-derivative
+    // column; items (a, e2) contract along e1 (value and e1-derivative of
+    // both layers, value of both derivative columns); items (a, b) contract
+    // along e2 and form the flux terms at the face points; items (e1, b) and
+    // then (e1, e2) contract back.
     __syncthreads();
     double *sY = U0;
     if (t < NF) {
@@ -227,16 +227,19 @@ k_apply_q(const double *__restrict__ x, double *__restrict__ y, const double *__
 #pragma unroll
         for (int i = 0; i < N; ++i) sY[i + N * j + NF * l] = Y[i];
     }
-    for (int f = 0; f < 6; ++f) {
-        const int d = f >> 1, s = f & 1;
-        const int32_t nb = nbr[6 * cid + f];
-        if (nb < 0) {
-            if (t < NF) FA[f][0][t] = FA[f][1][t] = 0.0;
-            continue;               // uniform across the block: no barrier skipped unevenly
-        }
-        // layers and normal-derivative columns, own and neighbour side
-        if (t < NF) {
-            const int e1 = t % N, e2 = t / N;
+    for (int d = 0; d < 3; ++d) {
+        const int32_t nbs[2] = {nbr[6 * cid + 2 * d], nbr[6 * cid + 2 * d + 1]};
+        // layers and normal-derivative columns of face (d, s), own and
+        // neighbour side: item (s, e1, e2)
+        for (int it = t; it < 2 * NF; it += blockDim.x) {
+            const int s = it / NF, k = it - s * NF;
+            const int32_t nb = nbs[s];
+            if (nb < 0) {
+                FA[2 * d + s][0][k] = FA[2 * d + s][1][k] = 0.0;
+                continue;
+            }
+            double *F = U1 + s * FACE1;
+            const int e1 = k % N, e2 = k / N;
             const int mo = s ? N - 1 : 0, mn = s ? 0 : N - 1;
             const double *xn = x + (int64_t)nb * ND;
             double dov = 0.0, dnv = 0.0;
@@ -244,97 +247,114 @@ k_apply_q(const double *__restrict__ x, double *__restrict__ y, const double *__
                 dov += sDL[s][m] * sX[qlay<N>(d, m, e1, e2)];
                 dnv += sDL[1 - s][m] * xn[qlay<N>(d, m, e1, e2)];
             }
-            Lo[t] = sX[qlay<N>(d, mo, e1, e2)];
-            Do[t] = dov;
-            Ln[t] = xn[qlay<N>(d, mn, e1, e2)];
-            Dn[t] = dnv;
+            F[k] = sX[qlay<N>(d, mo, e1, e2)];
+            F[NF + k] = dov;
+            F[2 * NF + k] = xn[qlay<N>(d, mn, e1, e2)];
+            F[3 * NF + k] = dnv;
         }
         __syncthreads();
-        // along e1: lane (a, e2)
-        if (t < C::QN) {
-            const int a = t % Q, e2 = t / Q;
+        // along e1: item (s, a, e2)
+        for (int it = t; it < 2 * C::QN; it += blockDim.x) {
+            const int s = it / C::QN, k = it - s * C::QN;
+            if (nbs[s] < 0) continue;
+            const double *F = U1 + s * FACE1;
+            double *Tf = U1 + s * FACE1 + 4 * NF;
+            const int a = k % Q, e2 = k / Q;
             double c0 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0, c5 = 0;
 #pragma unroll
             for (int e1 = 0; e1 < N; ++e1) {
                 const double ba = sB[a * N + e1], da = sD[a * N + e1];
-                const int k = e1 + N * e2;
-                c0 += ba * Lo[k];
-                c1 += da * Lo[k];
-                c2 += ba * Do[k];
-                c3 += ba * Ln[k];
-                c4 += da * Ln[k];
-                c5 += ba * Dn[k];
+                const int kk = e1 + N * e2;
+                c0 += ba * F[kk];
+                c1 += da * F[kk];
+                c2 += ba * F[NF + kk];
+                c3 += ba * F[2 * NF + kk];
+                c4 += da * F[2 * NF + kk];
+                c5 += ba * F[3 * NF + kk];
             }
-            Tf[0 * C::QN + t] = c0;
-            Tf[1 * C::QN + t] = c1;
-            Tf[2 * C::QN + t] = c2;
-            Tf[3 * C::QN + t] = c3;
-            Tf[4 * C::QN + t] = c4;
-            Tf[5 * C::QN + t] = c5;
+            Tf[0 * C::QN + k] = c0;
+            Tf[1 * C::QN + k] = c1;
+            Tf[2 * C::QN + k] = c2;
+            Tf[3 * C::QN + k] = c3;
+            Tf[4 * C::QN + k] = c4;
+            Tf[5 * C::QN + k] = c5;
         }
         __syncthreads();
-        // along e2 and the flux terms: lane (a, b)
-        if (t < Q2) {
-            const int a = t % Q, b = t / Q;
+        // along e2 and the flux terms: item (s, a, b)
+        for (int it = t; it < 2 * Q2; it += blockDim.x) {
+            const int s = it / Q2, k = it - s * Q2;
+            const int32_t nb = nbs[s];
+            if (nb < 0) continue;
+            const double *Tf = U1 + s * FACE1 + 4 * NF;
+            double *P = U1 + s * FACE1 + 4 * NF + 6 * C::QN;
+            const int a = k % Q, b = k / Q;
             double vo = 0, t1o = 0, t2o = 0, dno = 0, vn = 0, t1n = 0, t2n = 0, dnn = 0;
 #pragma unroll
             for (int e2 = 0; e2 < N; ++e2) {
                 const double bb = sB[b * N + e2], db = sD[b * N + e2];
-                const int k = a + Q * e2;
-                vo += bb * Tf[0 * C::QN + k];
-                t1o += bb * Tf[1 * C::QN + k];
-                t2o += db * Tf[0 * C::QN + k];
-                dno += bb * Tf[2 * C::QN + k];
-                vn += bb * Tf[3 * C::QN + k];
-                t1n += bb * Tf[4 * C::QN + k];
-                t2n += db * Tf[3 * C::QN + k];
-                dnn += bb * Tf[5 * C::QN + k];
+                const int kk = a + Q * e2;
+                vo += bb * Tf[0 * C::QN + kk];
+                t1o += bb * Tf[1 * C::QN + kk];
+                t2o += db * Tf[0 * C::QN + kk];
+                dno += bb * Tf[2 * C::QN + kk];
+                vn += bb * Tf[3 * C::QN + kk];
+                t1n += bb * Tf[4 * C::QN + kk];
+                t2n += db * Tf[3 * C::QN + kk];
+                dnn += bb * Tf[5 * C::QN + kk];
             }
             const int64_t fid = s ? cid : (int64_t)nb;
-            const double *fd = face + (fid * 3 + d) * 7 * Q2 + t;
+            const double *fd = face + (fid * 3 + d) * 7 * Q2 + k;
             const int go = s ? 0 : 3, gn = s ? 3 : 0;
             const double flux = fd[go * Q2] * dno + fd[(go + 1) * Q2] * t1o + fd[(go + 2) * Q2] * t2o +
                                 fd[gn * Q2] * dnn + fd[(gn + 1) * Q2] * t1n + fd[(gn + 2) * Q2] * t2n;
             const double jump = s ? (vo - vn) : (vn - vo);
             const double sg = s ? 1.0 : -1.0;
             const double hj = -0.5 * jump;
-            Pv[t] = sg * (-0.5 * flux + fd[6 * Q2] * jump);
-            Pn[t] = hj * fd[go * Q2];
-            P1[t] = hj * fd[(go + 1) * Q2];
-            P2[t] = hj * fd[(go + 2) * Q2];
+            P[k] = sg * (-0.5 * flux + fd[6 * Q2] * jump);            // value weight
+            P[Q2 + k] = hj * fd[(go + 1) * Q2];                       // e1-derivative weight
+            P[2 * Q2 + k] = hj * fd[(go + 2) * Q2];                   // e2-derivative weight
+            P[3 * Q2 + k] = hj * fd[go * Q2];                         // normal-derivative weight
         }
         __syncthreads();
-        // back along a: lane (e1, b)
-        if (t < C::QN) {
-            const int e1 = t % N, b = t / N;
+        // back along a: item (s, e1, b)
+        for (int it = t; it < 2 * C::QN; it += blockDim.x) {
+            const int s = it / C::QN, k = it - s * C::QN;
+            if (nbs[s] < 0) continue;
+            const double *P = U1 + s * FACE1 + 4 * NF + 6 * C::QN;
+            double *Gf = U1 + s * FACE1 + 4 * NF + 6 * C::QN + 4 * Q2;
+            const int e1 = k % N, b = k / N;
             double g = 0, h = 0, kk = 0;
 #pragma unroll
             for (int a = 0; a < Q; ++a) {
                 const double ba = sB[a * N + e1], da = sD[a * N + e1];
-                const int k = a + Q * b;
-                g += ba * Pv[k] + da * P1[k];
-                h += ba * P2[k];
-                kk += ba * Pn[k];
+                const int pk = a + Q * b;
+                g += ba * P[pk] + da * P[Q2 + pk];
+                h += ba * P[2 * Q2 + pk];
+                kk += ba * P[3 * Q2 + pk];
             }
-            Gf[0 * C::QN + t] = g;
-            Gf[1 * C::QN + t] = h;
-            Gf[2 * C::QN + t] = kk;
+            Gf[0 * C::QN + k] = g;
+            Gf[1 * C::QN + k] = h;
+            Gf[2 * C::QN + k] = kk;
         }
         __syncthreads();
-        // back along b: lane (e1, e2)
-        if (t < NF) {
-            const int e1 = t % N, e2 = t / N;
+        // back along b: item (s, e1, e2)
+        for (int it = t; it < 2 * NF; it += blockDim.x) {
+            const int s = it / NF, k = it - s * NF;
+            if (nbs[s] < 0) continue;
+            const double *Gf = U1 + s * FACE1 + 4 * NF + 6 * C::QN + 4 * Q2;
+            const int e1 = k % N, e2 = k / N;
             double f0 = 0.0, f1 = 0.0;
 #pragma unroll
             for (int b = 0; b < Q; ++b) {
                 const double bb = sB[b * N + e2], db = sD[b * N + e2];
-                const int k = e1 + N * b;
-                f0 += bb * Gf[0 * C::QN + k] + db * Gf[1 * C::QN + k];
-                f1 += bb * Gf[2 * C::QN + k];
+                const int gk = e1 + N * b;
+                f0 += bb * Gf[0 * C::QN + gk] + db * Gf[1 * C::QN + gk];
+                f1 += bb * Gf[2 * C::QN + gk];
             }
-            FA[f][0][t] = f0;
-            FA[f][1][t] = f1;
+            FA[2 * d + s][0][k] = f0;
+            FA[2 * d + s][1][k] = f1;
         }
+        __syncthreads();
     }
     __syncthreads();
     // pencil owners (j, l) add the six faces
