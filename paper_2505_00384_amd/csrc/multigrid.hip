@@ -148,55 +148,79 @@ __global__ __launch_bounds__(MG_T) void k_transfer(const T *__restrict__ in,
 // all eight children and adds the two x-neighbours (four results), then y
 // (two), then z (one); the prolongation expands z (two), y (four), then x
 // (eight).  Every thread reads its child indices itself, so the loads start
-// without a barrier.  One workgroup per coarse cell.
+// without a barrier.  The restriction's first sweep takes one pencil pair
+// per thread straight from memory, two coarse cells per workgroup while
+// they fit; the prolongation runs one coarse cell per workgroup.
+
+// coarse cells per workgroup of the dense restriction: two while one item
+// per thread covers both cells' x sweep
+template <int N>
+constexpr int rcpb() { return 8 * N * N <= MG_T ? 2 : 1; }
+
 template <int N, typename T>
-__global__ __launch_bounds__(MG_T) void k_restrict8(const T *__restrict__ in, T *__restrict__ out,
+__global__ __launch_bounds__(MG_T) __attribute__((amdgpu_waves_per_eu(N <= 5 ? 8 : 4, 8)))
+void k_restrict8(const T *__restrict__ in, T *__restrict__ out,
                                                     const int32_t *__restrict__ child8,
                                                     const RefTab64 *__restrict__ tab, int64_t n_coarse)
 {
-    constexpr int ND = N * N * N, NF = N * N;
+    constexpr int ND = N * N * N, NF = N * N, CPB = rcpb<N>();
     __shared__ T sE[2][NF];
-    __shared__ T sA[8][ND];
-    __shared__ T sB[4][ND];
+    __shared__ T sB[CPB][4][ND];
+    __shared__ T sA[CPB][2][ND];
     const int t = threadIdx.x;
-    const int64_t cc = blockIdx.x;
-    if (cc >= n_coarse) return;
+    const int64_t c0 = (int64_t)blockIdx.x * CPB;
     for (int e = t; e < 2 * NF; e += MG_T) sE[e / NF][e % NF] = (T)tab->Eh[e / NF][e % NF];
-    for (int idx = t; idx < 8 * ND; idx += MG_T) {
-        const int o = idx / ND, e = idx - o * ND;
-        sA[o][e] = in[(int64_t)child8[cc * 8 + o] * ND + e];
+    // x: item (cell lc, pair p = oy + 2 oz, pencil jl), one per thread; the
+    // two children's pencils are requested before the barrier
+    const int lc = t / (4 * NF), r = t - lc * 4 * NF, p = r / NF, jl = r - p * NF;
+    const bool act = lc < CPB && c0 + lc < n_coarse;
+    T v0[N], v1[N];
+    if (act) {
+        const int64_t cc = c0 + lc;
+        const T *x0 = in + (int64_t)child8[cc * 8 + 2 * p] * ND + N * jl;
+        const T *x1 = in + (int64_t)child8[cc * 8 + 2 * p + 1] * ND + N * jl;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            v0[i] = x0[i];
+            v1[i] = x1[i];
+        }
     }
     __syncthreads();
-    // x: (a, j, l) of pair p = oy + 2 oz, summed over ox
-    for (int idx = t; idx < 4 * ND; idx += MG_T) {
-        const int p = idx / ND, e = idx - p * ND;
-        const int a = e % N, jl = e / N;
-        T s = 0;
+    if (act) {
+#pragma unroll 1
+        for (int a = 0; a < N; ++a) {
+            T s = 0;
 #pragma unroll
-        for (int i = 0; i < N; ++i)
-            s += sE[0][i * N + a] * sA[2 * p][i + N * jl] + sE[1][i * N + a] * sA[2 * p + 1][i + N * jl];
-        sB[p][e] = s;
+            for (int i = 0; i < N; ++i) s += sE[0][i * N + a] * v0[i] + sE[1][i * N + a] * v1[i];
+            sB[lc][p][a + N * jl] = s;
+        }
     }
     __syncthreads();
     // y: (a, b, l) of oz, summed over oy
-    for (int idx = t; idx < 2 * ND; idx += MG_T) {
-        const int q = idx / ND, e = idx - q * ND;
+#pragma unroll 1
+    for (int it = t; it < CPB * 2 * ND; it += MG_T) {
+        const int lc2 = it / (2 * ND), r2 = it - lc2 * 2 * ND, q = r2 / ND, e = r2 - q * ND;
+        if (c0 + lc2 >= n_coarse) continue;
         const int a = e % N, b = (e / N) % N, l = e / NF;
         T s = 0;
 #pragma unroll
         for (int j = 0; j < N; ++j)
-            s += sE[0][j * N + b] * sB[2 * q][a + N * (j + N * l)] +
-                 sE[1][j * N + b] * sB[2 * q + 1][a + N * (j + N * l)];
-        sA[q][e] = s;
+            s += sE[0][j * N + b] * sB[lc2][2 * q][a + N * (j + N * l)] +
+                 sE[1][j * N + b] * sB[lc2][2 * q + 1][a + N * (j + N * l)];
+        sA[lc2][q][e] = s;
     }
     __syncthreads();
     // z: summed over oz
-    for (int e = t; e < ND; e += MG_T) {
+#pragma unroll 1
+    for (int it = t; it < CPB * ND; it += MG_T) {
+        const int lc2 = it / ND, e = it - lc2 * ND;
+        const int64_t cc = c0 + lc2;
+        if (cc >= n_coarse) continue;
         const int ab = e % NF, c = e / NF;
         T s = 0;
 #pragma unroll
         for (int l = 0; l < N; ++l)
-            s += sE[0][l * N + c] * sA[0][ab + NF * l] + sE[1][l * N + c] * sA[1][ab + NF * l];
+            s += sE[0][l * N + c] * sA[lc2][0][ab + NF * l] + sE[1][l * N + c] * sA[lc2][1][ab + NF * l];
         out[cc * ND + e] = s;
     }
 }
@@ -261,8 +285,9 @@ hipError_t transfer(hx_ctx *c, const T *in, T *out)
 #define HX_MG_CASE(NN)                                                                           \
     case NN:                                                                                     \
         if (c->mg_child8 && RESTRICT)                                                            \
-            hipLaunchKernelGGL((k_restrict8<NN, T>), g, b, 0, c->stream, in, out, c->mg_child8,  \
-                               c->ref, nc);                                                      \
+            hipLaunchKernelGGL((k_restrict8<NN, T>), dim3((unsigned)((nc + rcpb<NN>() - 1) /      \
+                                                                   rcpb<NN>())),                 \
+                               b, 0, c->stream, in, out, c->mg_child8, c->ref, nc);              \
         else if (c->mg_child8)                                                                   \
             hipLaunchKernelGGL((k_prolong8<NN, T>), g, b, 0, c->stream, in, out, c->mg_child8,   \
                                c->ref, nc);                                                      \
