@@ -425,8 +425,10 @@ __device__ __forceinline__ void fused_layer(const uint16_t (*sA)[LDA], const uin
     }
 }
 
+constexpr int FW = 16;   // waves per workgroup of the fused kernel
+
 template <int N>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(64 * FW)
 k_mlp_fused(int64_t n_cells, const double *__restrict__ r, double *__restrict__ z,
             const int32_t *__restrict__ nbr, const double *__restrict__ coef,
             const uint16_t *__restrict__ w1b, const uint16_t *__restrict__ w2b,
@@ -434,26 +436,29 @@ k_mlp_fused(int64_t n_cells, const double *__restrict__ r, double *__restrict__ 
             const float *__restrict__ b3)
 {
     constexpr int NF = N * N, ND = NF * N, NIN = ND + 6 * NF + 1, LDX = ((NIN + 31) / 32) * 32;
-    constexpr int NT3 = (ND + 15) / 16, PER3 = (NT3 + 3) / 4;
+    constexpr int NTH = 64 * FW, PER = (HID / 16) / FW;   // column tiles of 16 per wave, hidden layers
+    constexpr int NT3 = (ND + 15) / 16, PER3 = (NT3 + FW - 1) / FW;
+    constexpr int SUB = NTH / FT;                         // threads per cell in the norms
+    static_assert(PER * FW * 16 == HID && SUB >= 16 && (SUB & (SUB - 1)) == 0, "layout");
     __shared__ __align__(16) uint16_t sX[FT][LDX + 8];
     __shared__ __align__(16) uint16_t sH[FT][HID + 8];
     __shared__ __align__(16) uint16_t sH2[FT][HID + 8];
     __shared__ double sS[FT], sW[FT];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t c0 = (int64_t)blockIdx.x * FT;
-    // RMS of r_K and of the block-Jacobi output z_K: 16 threads per cell
+    // RMS of r_K and of the block-Jacobi output z_K: SUB threads per cell
     {
-        const int cl = tid >> 4, sub = tid & 15;
+        const int cl = tid / SUB, sub = tid % SUB;
         const int64_t c = c0 + cl;
         double sr = 0.0, sz = 0.0;
         if (c < n_cells)
-            for (int e = sub; e < ND; e += 16) {
+            for (int e = sub; e < ND; e += SUB) {
                 const double v = r[c * ND + e], u = z[c * ND + e];
                 sr += v * v;
                 sz += u * u;
             }
 #pragma unroll
-        for (int o = 8; o > 0; o >>= 1) {
+        for (int o = SUB / 2; o > 0; o >>= 1) {
             sr += __shfl_xor(sr, o, 64);
             sz += __shfl_xor(sz, o, 64);
         }
@@ -464,7 +469,7 @@ k_mlp_fused(int64_t n_cells, const double *__restrict__ r, double *__restrict__ 
     }
     __syncthreads();
     // features, BF16
-    for (int idx = tid; idx < FT * LDX; idx += 256) {
+    for (int idx = tid; idx < FT * LDX; idx += NTH) {
         const int cl = idx / LDX, e = idx % LDX;
         const int64_t c = c0 + cl;
         float fv = 0.f;
@@ -494,13 +499,13 @@ k_mlp_fused(int64_t n_cells, const double *__restrict__ r, double *__restrict__ 
     }
     __syncthreads();
     const int ccol = lane & 15, crow = 4 * (lane >> 4);
-    // layer 1: each wave 4 of the 16 column tiles
+    // layer 1: each wave PER of the 16 column tiles
     {
-        f32x4 acc[4];
-        fused_layer<LDX, 4, LDX + 8, LDX>(sX, w1b, HID, 4 * wave, lane, acc);
+        f32x4 acc[PER];
+        fused_layer<LDX, PER, LDX + 8, LDX>(sX, w1b, HID, PER * wave, lane, acc);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int n = (4 * wave + j) * 16 + ccol;
+        for (int j = 0; j < PER; ++j) {
+            const int n = (PER * wave + j) * 16 + ccol;
 #pragma unroll
             for (int q = 0; q < 4; ++q) sH[crow + q][n] = f2bf(fmaxf(acc[j][q] + b1[n], 0.f));
         }
@@ -508,11 +513,11 @@ k_mlp_fused(int64_t n_cells, const double *__restrict__ r, double *__restrict__ 
     __syncthreads();
     // layer 2
     {
-        f32x4 acc[4];
-        fused_layer<HID, 4, HID + 8, HID>(sH, w2b, HID, 4 * wave, lane, acc);
+        f32x4 acc[PER];
+        fused_layer<HID, PER, HID + 8, HID>(sH, w2b, HID, PER * wave, lane, acc);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int n = (4 * wave + j) * 16 + ccol;
+        for (int j = 0; j < PER; ++j) {
+            const int n = (PER * wave + j) * 16 + ccol;
 #pragma unroll
             for (int q = 0; q < 4; ++q) sH2[crow + q][n] = f2bf(fmaxf(acc[j][q] + b2[n], 0.f));
         }
@@ -956,7 +961,7 @@ template <int N>
 static hipError_t mlp_fused_n(hx_ctx *c, const double *r, double *z)
 {
     MlpState *s = c->mlp;
-    hipLaunchKernelGGL((k_mlp_fused<N>), dim3((unsigned)((c->n_cells + FT - 1) / FT)), dim3(256), 0,
+    hipLaunchKernelGGL((k_mlp_fused<N>), dim3((unsigned)((c->n_cells + FT - 1) / FT)), dim3(64 * FW), 0,
                        c->stream, c->n_cells, r, z, c->nbr, c->coef_feat, s->w1b, s->w2b, s->w3b,
                        s->w + s->off_b1, s->w + s->off_b2, s->w + s->off_b3);
     return hipGetLastError();
