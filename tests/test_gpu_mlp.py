@@ -1,5 +1,5 @@
-"""GPU parity of the learned preconditioner's kernels (steps a9, a10) with
-the network oracle on the same BF16-rounded weights, plus the solver policy
+"""GPU parity of the learned preconditioner's inference and training kernels
+with the network oracle on the same BF16-rounded weights, plus the solver policy
 around it: FGMRES with the network converges, a poisoned network is replaced
 by block Jacobi, a zero network reproduces block Jacobi, and training on the
 solver's own iterates lowers the loss.

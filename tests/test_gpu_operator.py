@@ -1,6 +1,6 @@
-"""GPU parity of geometry (step a1), coefficient merge (a2), the fused
-cell + face operator (a3, a4), the residual (a7) and the separable block
-Jacobi (a5) against the FP64 oracle, on the same seeded inputs.
+"""GPU parity of the geometry, the coefficient merge, the fused cell + face
+operator, the residual and the separable block Jacobi against the FP64
+oracle, on the same seeded inputs.
 
 Tolerances: FP64 normwise ||y - y_or|| <= 1e-12 ||y_or|| and
 max|y - y_or| <= 1e-12 max|y_or| (both sides sum in different orders and the
