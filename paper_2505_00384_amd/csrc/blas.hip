@@ -432,12 +432,38 @@ __global__ void __launch_bounds__(RT) k_widen_dot(int64_t n, const float *__rest
 
 // p = z + (sc[2] / sc[0]) p
 template <typename T>
-__global__ void k_cg_pt(int64_t n, const T *__restrict__ z, T *p, const double *__restrict__ sc)
+__global__ void k_cg_pt(int64_t n, const T *__restrict__ z, T *p, const double *__restrict__ sc,
+                        int beta_ready)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const T bt = (T)(sc[0] != 0.0 ? sc[2] / sc[0] : 0.0);
+    const T bt = (T)(beta_ready ? sc[5] : (sc[0] != 0.0 ? sc[2] / sc[0] : 0.0));
     p[i] = z[i] + bt * p[i];
+}
+
+// stage 2 of a fused CG step whose z is final: workgroup 0 sums r.z (row 0
+// of part), workgroup 1 r.r (row 1); then beta = new r.z / old r.z goes to
+// sc[5] and the new r.z to sc[2] and sc[0] (so no separate shift is needed),
+// r.r to sc[3] and, when host is given (device view of pinned memory), to
+// *host.  The sums take k_red2's order.
+__global__ void __launch_bounds__(RT) k_red_cg(const double *__restrict__ part, int nb, int ld,
+                                               double *sc, double *host)
+{
+    __shared__ double sh[RT / 64];
+    double s = 0.0;
+    const double *p = part + (int64_t)blockIdx.x * ld;
+    for (int i = threadIdx.x; i < nb; i += RT) s += p[i];
+    s = block_sum(s, sh);
+    if (threadIdx.x != 0) return;
+    if (blockIdx.x == 0) {
+        const double old = sc[0];
+        sc[5] = old != 0.0 ? s / old : 0.0;
+        sc[2] = s;
+        sc[0] = s;
+    } else {
+        sc[3] = s;
+        if (host) *host = s;
+    }
 }
 
 inline unsigned nb256(int64_t n) { return (unsigned)((n + 255) / 256); }
@@ -600,8 +626,10 @@ hipError_t reduce_parts(hx_ctx *c, const double *part, int64_t n, double *dst)
 // cell mass blocks, a diagonal kind, or the Chebyshev polynomial after the
 // update): x += a p, r -= a q, z = M^{-1} r, sc[2] = r.z, sc[3] = r.r.
 template <typename T>
-hipError_t cg_step_pc(hx_ctx *c, int pc, T *x, T *r, const T *p, const T *q, T *z, double *sc)
+hipError_t cg_step_pc(hx_ctx *c, int pc, T *x, T *r, const T *p, const T *q, T *z, double *sc,
+                      double *host_rr, int *flags)
 {
+    *flags = 0;
     const int64_t n = c->n_dofs;
     const int ld = (int)c->n_cells + 1;
     const bool dbl = sizeof(T) == 8;
@@ -633,10 +661,16 @@ hipError_t cg_step_pc(hx_ctx *c, int pc, T *x, T *r, const T *p, const T *q, T *
         e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
+    const bool z_final = pc != HX_PC_CHEBYSHEV && pc != HX_PC_MULTIGRID && pc != HX_PC_MULTIGRID_MIXED;
     if (nb > 8192) {
         // one partial sum per block of the fused cell-block kernels: two stages
         e = reduce_parts(c, c->cgpart, nb, sc + 2);
         if (e == hipSuccess) e = reduce_parts(c, c->cgpart + ld, nb, sc + 3);
+    } else if (z_final) {
+        // the sums, the direction coefficient and r.r for the host in one launch
+        hipLaunchKernelGGL(k_red_cg, dim3(2), dim3(RT), 0, c->stream, c->cgpart, nb, ld, sc, host_rr);
+        e = hipGetLastError();
+        *flags = CG_BETA_READY | (host_rr ? CG_RR_ON_HOST : 0);
     } else {
         hipLaunchKernelGGL(k_red2, dim3(2), dim3(RT), 0, c->stream, c->cgpart, nb, ld, sc + 2);
         e = hipGetLastError();
@@ -667,31 +701,32 @@ hipError_t cg_step_pc(hx_ctx *c, int pc, T *x, T *r, const T *p, const T *q, T *
 }
 
 template <typename T>
-hipError_t cg_step_p(hx_ctx *c, const T *z, T *p, double *sc)
+hipError_t cg_step_p(hx_ctx *c, const T *z, T *p, double *sc, int flags)
 {
     const int64_t n = c->n_dofs;
-    hipLaunchKernelGGL(k_cg_pt<T>, dim3(nb256(n)), dim3(256), 0, c->stream, n, z, p, sc);
-    hipLaunchKernelGGL(k_shift, dim3(1), dim3(64), 0, c->stream, sc);
+    const int ready = (flags & CG_BETA_READY) ? 1 : 0;
+    hipLaunchKernelGGL(k_cg_pt<T>, dim3(nb256(n)), dim3(256), 0, c->stream, n, z, p, sc, ready);
+    if (!ready) hipLaunchKernelGGL(k_shift, dim3(1), dim3(64), 0, c->stream, sc);
     return hipGetLastError();
 }
 
 hipError_t cg_step_pc64(hx_ctx *c, int pc, double *x, double *r, const double *p, const double *q,
-                        double *z, double *sc)
+                        double *z, double *sc, double *host_rr, int *flags)
 {
-    return cg_step_pc<double>(c, pc, x, r, p, q, z, sc);
+    return cg_step_pc<double>(c, pc, x, r, p, q, z, sc, host_rr, flags);
 }
 hipError_t cg_step_pc32(hx_ctx *c, int pc, float *x, float *r, const float *p, const float *q,
-                        float *z, double *sc)
+                        float *z, double *sc, int *flags)
 {
-    return cg_step_pc<float>(c, pc, x, r, p, q, z, sc);
+    return cg_step_pc<float>(c, pc, x, r, p, q, z, sc, nullptr, flags);
 }
-hipError_t cg_step_p64(hx_ctx *c, const double *z, double *p, double *sc)
+hipError_t cg_step_p64(hx_ctx *c, const double *z, double *p, double *sc, int flags)
 {
-    return cg_step_p<double>(c, z, p, sc);
+    return cg_step_p<double>(c, z, p, sc, flags);
 }
-hipError_t cg_step_p32(hx_ctx *c, const float *z, float *p, double *sc)
+hipError_t cg_step_p32(hx_ctx *c, const float *z, float *p, double *sc, int flags)
 {
-    return cg_step_p<float>(c, z, p, sc);
+    return cg_step_p<float>(c, z, p, sc, flags);
 }
 
 }  // namespace hx

@@ -330,12 +330,15 @@ hipError_t launch_cg_bj64(hx_ctx *c, double *x, double *r, const double *p, cons
                           double *z, const double *sc, int *nblk);
 hipError_t launch_cg_bj32(hx_ctx *c, float *x, float *r, const float *p, const float *q, float *z,
                           const double *sc, int *nblk);
+// flags of a fused CG step: the direction coefficient is in sc[5] and the
+// new r.z already in sc[0] (no shift needed); r.r was written to host_rr
+constexpr int CG_BETA_READY = 1, CG_RR_ON_HOST = 2;
 hipError_t cg_step_pc64(hx_ctx *c, int pc, double *x, double *r, const double *p, const double *q,
-                        double *z, double *sc);
+                        double *z, double *sc, double *host_rr, int *flags);
 hipError_t cg_step_pc32(hx_ctx *c, int pc, float *x, float *r, const float *p, const float *q,
-                        float *z, double *sc);
-hipError_t cg_step_p64(hx_ctx *c, const double *z, double *p, double *sc);
-hipError_t cg_step_p32(hx_ctx *c, const float *z, float *p, double *sc);
+                        float *z, double *sc, int *flags);
+hipError_t cg_step_p64(hx_ctx *c, const double *z, double *p, double *sc, int flags);
+hipError_t cg_step_p32(hx_ctx *c, const float *z, float *p, double *sc, int flags);
 hipError_t cg32_step_p_dot(hx_ctx *c, int64_t n, const float *r, const float *z, double *sc);
 hipError_t blas_lincomb(hx_ctx *c, int64_t n, int m, const double *Z, int64_t ldz,
                         const double *y_dev, double *x);

@@ -125,8 +125,9 @@ hx_status inner_fp32(hx_ctx *c, int pc, const double *v, double *z, float *w32, 
             HX_HIP(c, cg32_step_x(c, n, x, r, p, q, sc));
             break;
         }
-        HX_HIP(c, cg_step_pc32(c, pc, x, r, p, q, zz, sc));
-        HX_HIP(c, cg_step_p32(c, zz, p, sc));
+        int fl = 0;
+        HX_HIP(c, cg_step_pc32(c, pc, x, r, p, q, zz, sc, &fl));
+        HX_HIP(c, cg_step_p32(c, zz, p, sc, fl));
     }
     HX_HIP(c, blas_cast32to64(c, n, x, z, nullptr));
     *count += iters;
@@ -297,7 +298,7 @@ hx_status solve_cg(hx_ctx *c, const hx_solve_params *prm, const double *b, doubl
             return fail(c, HX_ERR_DEVICE, "hipEventCreate failed");
     Timer tb(true);
     Timer *tms[2] = {&tm, &tb};
-    double *hr = c->red_host + 1000;
+    double *hr = c->pin_host;   // slots 0, 1 (device-mapped: the reduction may write them)
     auto cleanup = [&]() {
         for (auto &e : done)
             if (e) (void)hipEventDestroy(e);
@@ -323,11 +324,14 @@ hx_status solve_cg(hx_ctx *c, const hx_solve_params *prm, const double *b, doubl
         if (hipSuccess != sys_apply_dot(c, prm, p, q, sc + 1)) { err = fail(c, HX_ERR_DEVICE, "CG: apply"); break; }
         t.rec(2, c->stream);
         t.rec(0, c->stream);
-        if (hipSuccess != cg_step_pc64(c, prm->pc, x, r, p, q, z, sc)) { err = fail(c, HX_ERR_DEVICE, "CG: step"); break; }
+        int fl = 0;
+        if (hipSuccess != cg_step_pc64(c, prm->pc, x, r, p, q, z, sc, c->pin_dev + it % 2, &fl)) { err = fail(c, HX_ERR_DEVICE, "CG: step"); break; }
         t.rec(3, c->stream);
-        if (hipSuccess != cg_step_p64(c, z, p, sc)) { err = fail(c, HX_ERR_DEVICE, "CG: p update"); break; }
-        if (hipSuccess != hipMemcpyAsync(hr + it % 2, sc + 3, sizeof(double), hipMemcpyDeviceToHost,
-                                         c->stream) ||
+        if (hipSuccess != cg_step_p64(c, z, p, sc, fl)) { err = fail(c, HX_ERR_DEVICE, "CG: p update"); break; }
+        // |r|^2 for the host: written by the reduction itself, else copied
+        if ((!(fl & CG_RR_ON_HOST) &&
+             hipSuccess != hipMemcpyAsync(hr + it % 2, sc + 3, sizeof(double), hipMemcpyDeviceToHost,
+                                          c->stream)) ||
             hipSuccess != hipEventRecord(done[it % 2], c->stream)) {
             err = fail(c, HX_ERR_DEVICE, "CG: copy");
             break;
