@@ -613,6 +613,11 @@ __global__ void __launch_bounds__(RT) k_chunk_sum(const double *__restrict__ par
 
 hipError_t reduce_parts(hx_ctx *c, const double *part, int64_t n, double *dst)
 {
+    if (n <= 8192) {
+        // few partial sums: one workgroup, one launch
+        hipLaunchKernelGGL(k_red2, dim3(1), dim3(RT), 0, c->stream, part, (int)n, 0, dst);
+        return hipGetLastError();
+    }
     const int64_t chunk = 4096;
     int64_t nb = (n + chunk - 1) / chunk;
     if (nb < 1) nb = 1;
