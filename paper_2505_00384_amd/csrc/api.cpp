@@ -44,7 +44,7 @@ static void free_mesh(hx_ctx *c)
     void **bufs[] = {(void **)&c->nodes, (void **)&c->nbr, (void **)&c->visit, (void **)&c->visitp, (void **)&c->ref, (void **)&c->vol,
                      (void **)&c->ell, (void **)&c->mindet, (void **)&c->sigma,
                      (void **)&c->cell64, (void **)&c->cell32, (void **)&c->face64,
-                     (void **)&c->face32, (void **)&c->cellgeo, (void **)&c->facegeo, (void **)&c->dg64, (void **)&c->dg32, (void **)&c->cgpart,
+                     (void **)&c->face32, (void **)&c->cellgeo, (void **)&c->facegeo, (void **)&c->dg64, (void **)&c->dg32, (void **)&c->cgpart, (void **)&c->pqpart,
                      (void **)&c->bjS64, (void **)&c->bjS32,
                      (void **)&c->bjL64, (void **)&c->bjL32, (void **)&c->bjC64,
                      (void **)&c->bjC32, (void **)&c->coef_feat, (void **)&c->work64,
@@ -324,6 +324,7 @@ hx_status hx_setup_mesh_hanging(hx_ctx *c, int degree, int64_t n_cells, int geo_
     ALLOC(c->dg64, sizeof(double) * 2 * nc * c->nd);
     ALLOC(c->dg32, sizeof(float) * 2 * nc * c->nd);
     ALLOC(c->cgpart, sizeof(double) * 2 * (nc + 1));
+    ALLOC(c->pqpart, sizeof(double) * 2 * (nc + 1));
     ALLOC(c->bjS64, sizeof(double) * nc * 3 * c->nf);
     ALLOC(c->bjS32, sizeof(float) * nc * 3 * c->nf);
     ALLOC(c->bjL64, sizeof(double) * nc * 3 * c->n);

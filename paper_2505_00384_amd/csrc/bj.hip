@@ -73,7 +73,7 @@ __global__ void __launch_bounds__(Cfg<N>::NT)
 k_bj(const T *__restrict__ rin, T *__restrict__ z, const T *__restrict__ S, const T *__restrict__ L,
      const T *__restrict__ C, int n_cells, int nwg, T *x, T *rw, const T *__restrict__ p,
      const T *__restrict__ q, const double *__restrict__ sc, double *part, int ld, T ca = 0,
-     T cb = 0, int flags = 0)
+     T cb = 0, int flags = 0, const double *__restrict__ pqp = nullptr, int npq = 0)
 {
     const T *r = FUSE ? rw : rin;
     constexpr int NF = Cfg<N>::NF, ND = Cfg<N>::ND, CPB = Cfg<N>::CPB;
@@ -102,8 +102,19 @@ k_bj(const T *__restrict__ rin, T *__restrict__ z, const T *__restrict__ S, cons
         __shared__ double shs[4];
         sfac = (T)(1.0 / sqrt(sum256(part, ld, shs)));
     }
+    // p.q: the operator's partial sums summed here (every workgroup the same
+    // fixed order), or the value in sc[1]
+    double pq = 0.0;
+    if (FUSE) {
+        if (pqp) {
+            __shared__ double shq[4];
+            pq = sum256(pqp, npq, shq);
+        } else {
+            pq = sc[1];
+        }
+    }
     if (FUSE && active) {
-        const T al = (T)(sc[1] != 0.0 ? sc[0] / sc[1] : 0.0);
+        const T al = (T)(pq != 0.0 ? sc[0] / pq : 0.0);
         for (int e = tt; e < ND; e += NF) {
             const int64_t gi = cid * ND + e;
             const T rv = rw[gi] - al * q[gi];
@@ -259,6 +270,8 @@ struct CgArgs {
     T *x = nullptr, *r = nullptr;
     const T *p = nullptr, *q = nullptr;
     const double *sc = nullptr;
+    const double *pqp = nullptr;   // partial sums of p.q (null: p.q in sc[1])
+    int npq = 0;
 };
 
 template <int N, typename T>
@@ -307,7 +320,7 @@ hipError_t bj_n(hx_ctx *c, const T *r, T *z, const CgArgs<T> *cg, int *nblk)
     if (cg)
         hipLaunchKernelGGL((k_bj<N, T, true>), dim3(nwg), dim3(Cfg<N>::NT), 0, c->stream, r, z, S,
                            L, C, (int)c->n_cells, nwg, cg->x, cg->r, cg->p, cg->q, cg->sc,
-                           c->cgpart, (int)c->n_cells + 1);
+                           c->cgpart, (int)c->n_cells + 1, (T)0, (T)0, 0, cg->pqp, cg->npq);
     else
         hipLaunchKernelGGL((k_bj<N, T, false>), dim3(nwg), dim3(Cfg<N>::NT), 0, c->stream, r, z, S,
                            L, C, (int)c->n_cells, nwg, (T *)nullptr, (T *)nullptr,
@@ -378,18 +391,18 @@ hipError_t launch_bj_cheb32(hx_ctx *c, const float *r, float *d, float *x, doubl
 hipError_t launch_bj32(hx_ctx *c, const float *r, float *z) { return bj_dispatch<float>(c, r, z); }
 
 hipError_t launch_cg_bj64(hx_ctx *c, double *x, double *r, const double *p, const double *q,
-                          double *z, const double *sc, int *nblk)
+                          double *z, const double *sc, int *nblk, const double *pqp, int npq)
 {
     CgArgs<double> a;
-    a.x = x; a.r = r; a.p = p; a.q = q; a.sc = sc;
+    a.x = x; a.r = r; a.p = p; a.q = q; a.sc = sc; a.pqp = pqp; a.npq = npq;
     return bj_dispatch<double>(c, r, z, &a, nblk);
 }
 
 hipError_t launch_cg_bj32(hx_ctx *c, float *x, float *r, const float *p, const float *q, float *z,
-                          const double *sc, int *nblk)
+                          const double *sc, int *nblk, const double *pqp, int npq)
 {
     CgArgs<float> a;
-    a.x = x; a.r = r; a.p = p; a.q = q; a.sc = sc;
+    a.x = x; a.r = r; a.p = p; a.q = q; a.sc = sc; a.pqp = pqp; a.npq = npq;
     return bj_dispatch<float>(c, r, z, &a, nblk);
 }
 
@@ -437,7 +450,7 @@ __global__ void __launch_bounds__(Cfg<N>::NT)
 k_massinv(const T *__restrict__ rin, T *__restrict__ z, const T *__restrict__ wgt, int64_t wstride,
           const double *__restrict__ Fm, int n_cells, int nwg, T *x, T *rw,
           const T *__restrict__ p, const T *__restrict__ q, const double *__restrict__ sc,
-          double *part, int ld)
+          double *part, int ld, const double *__restrict__ pqp = nullptr, int npq = 0)
 {
     const T *r = FUSE ? rw : rin;
     constexpr int NF = Cfg<N>::NF, ND = Cfg<N>::ND, CPB = Cfg<N>::CPB;
@@ -459,8 +472,18 @@ k_massinv(const T *__restrict__ rin, T *__restrict__ z, const T *__restrict__ wg
     for (int e = t; e < NF; e += blockDim.x) sB[e] = (T)(INV ? Fm[e] : Fm[(e % N) * N + e / N]);
     T mq[N], v[N], w[N], rp[N];
     double acc_rr = 0.0, acc_rz = 0.0;
+    double pq = 0.0;
+    if (FUSE) {
+        static_assert(!FUSE || Cfg<N>::NT == 256, "the fused step sums with a 256-thread workgroup");
+        if (pqp) {
+            __shared__ double shq[4];
+            pq = sum256(pqp, npq, shq);
+        } else {
+            pq = sc[1];
+        }
+    }
     if (FUSE && active) {
-        const T al = (T)(sc[1] != 0.0 ? sc[0] / sc[1] : 0.0);
+        const T al = (T)(pq != 0.0 ? sc[0] / pq : 0.0);
         for (int e = tt; e < ND; e += NF) {
             const int64_t gi = cid * ND + e;
             const T rv = rw[gi] - al * q[gi];
@@ -602,7 +625,7 @@ hipError_t massinv_n(hx_ctx *c, const T *wgt, int64_t wstride, bool inv, const T
     if (cg)
         hipLaunchKernelGGL((k_massinv<N, T, true, true>), dim3(nwg), dim3(Cfg<N>::NT), 0, c->stream,
                            r, z, wgt, wstride, Fm, (int)c->n_cells, nwg, cg->x, cg->r, cg->p, cg->q,
-                           cg->sc, c->cgpart, (int)c->n_cells + 1);
+                           cg->sc, c->cgpart, (int)c->n_cells + 1, cg->pqp, cg->npq);
     else if (inv)
         hipLaunchKernelGGL((k_massinv<N, T, false, true>), dim3(nwg), dim3(Cfg<N>::NT), 0, c->stream,
                            r, z, wgt, wstride, Fm, (int)c->n_cells, nwg, (T *)nullptr, (T *)nullptr,
@@ -649,18 +672,18 @@ hipError_t launch_mass64(hx_ctx *c, const double *wgt, int64_t wstride, int inv,
 }
 
 hipError_t launch_cg_massinv64(hx_ctx *c, double *x, double *r, const double *p, const double *q,
-                               double *z, const double *sc, int *nblk)
+                               double *z, const double *sc, int *nblk, const double *pqp, int npq)
 {
     CgArgs<double> a;
-    a.x = x; a.r = r; a.p = p; a.q = q; a.sc = sc;
+    a.x = x; a.r = r; a.p = p; a.q = q; a.sc = sc; a.pqp = pqp; a.npq = npq;
     return massinv_dispatch<double>(c, r, z, &a, nblk);
 }
 
 hipError_t launch_cg_massinv32(hx_ctx *c, float *x, float *r, const float *p, const float *q,
-                               float *z, const double *sc, int *nblk)
+                               float *z, const double *sc, int *nblk, const double *pqp, int npq)
 {
     CgArgs<float> a;
-    a.x = x; a.r = r; a.p = p; a.q = q; a.sc = sc;
+    a.x = x; a.r = r; a.p = p; a.q = q; a.sc = sc; a.pqp = pqp; a.npq = npq;
     return massinv_dispatch<float>(c, r, z, &a, nblk);
 }
 

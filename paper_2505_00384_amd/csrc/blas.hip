@@ -352,13 +352,20 @@ __global__ void k_copy(int64_t n, const double *__restrict__ x, double *y)
 }
 
 // ---- FP32 CG with device scalars: sc[0] = rz (current), sc[1] = p.q,
-// sc[2] = new rz.  x += a p, r -= a q with a = sc[0]/sc[1].
-__global__ void k_cg_x(int64_t n, float *x, float *r, const float *__restrict__ p,
-                       const float *__restrict__ q, const double *__restrict__ sc)
+// sc[2] = new rz.  x += a p, r -= a q with a = sc[0]/p.q; p.q is the
+// fixed-order sum of pqp[0..npq) when pqp is given, else sc[1].
+// 256 threads per block.
+__global__ void __launch_bounds__(256) k_cg_x(int64_t n, float *x, float *r,
+                                              const float *__restrict__ p,
+                                              const float *__restrict__ q,
+                                              const double *__restrict__ sc,
+                                              const double *__restrict__ pqp, int npq)
 {
+    __shared__ double shq[4];
+    const double pq = pqp ? sum256(pqp, npq, shq) : sc[1];
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const float a = (float)(sc[1] != 0.0 ? sc[0] / sc[1] : 0.0);
+    const float a = (float)(pq != 0.0 ? sc[0] / pq : 0.0);
     x[i] += a * p[i];
     r[i] -= a * q[i];
 }
@@ -380,18 +387,22 @@ __global__ void k_shift(double *sc)
 
 // ---- fused CG steps, FP64 or FP32 vectors, scalars on the device:
 // sc[0] = r.z (current), sc[1] = p.q, sc[2] = new r.z, sc[3] = new r.r.
-// x += a p, r -= a q with a = sc[0] / sc[1] (0 when p.q is exactly 0: the
+// x += a p, r -= a q with a = sc[0] / p.q (0 when p.q is exactly 0: the
 // step in flight after exact convergence), z = dinv r (or z = r), and the
 // per-block partial sums of r.z and r.r in part[blk], part[ld + blk].
+// p.q is the fixed-order sum of pqp[0..npq) when pqp is given, else sc[1].
 template <typename T>
 __global__ void __launch_bounds__(RT) k_cg_elem(int64_t n, T *x, T *r, const T *__restrict__ p,
                                                 const T *__restrict__ q, T *z,
                                                 const T *__restrict__ dinv,
                                                 const double *__restrict__ sc, double *part, int ld,
-                                                float *r32)
+                                                float *r32, const double *__restrict__ pqp, int npq)
 {
+    static_assert(RT == 256, "sum256 needs 256 threads");
     __shared__ double sh[RT / 64];
-    const T al = (T)(sc[1] != 0.0 ? sc[0] / sc[1] : 0.0);
+    __shared__ double shq[4];
+    const double pq = pqp ? sum256(pqp, npq, shq) : sc[1];
+    const T al = (T)(pq != 0.0 ? sc[0] / pq : 0.0);
     double rz = 0.0, rr = 0.0;
     const int64_t stride = (int64_t)gridDim.x * RT;
     for (int64_t i = blockIdx.x * (int64_t)RT + threadIdx.x; i < n; i += stride) {
@@ -582,9 +593,10 @@ hipError_t blas_fill32(hx_ctx *c, int64_t n, float v, float *y)
 }
 
 hipError_t cg32_step_x(hx_ctx *c, int64_t n, float *x, float *r, const float *p, const float *q,
-                       double *sc)
+                       double *sc, const double *pqp, int npq)
 {
-    hipLaunchKernelGGL(k_cg_x, dim3(nb256(n)), dim3(256), 0, c->stream, n, x, r, p, q, sc);
+    hipLaunchKernelGGL(k_cg_x, dim3(nb256(n)), dim3(256), 0, c->stream, n, x, r, p, q, sc, pqp,
+                       npq);
     return hipGetLastError();
 }
 
@@ -630,11 +642,13 @@ hipError_t reduce_parts(hx_ctx *c, const double *part, int64_t n, double *dst)
 // One fused CG step around the preconditioner pc (none, block Jacobi, the
 // cell mass blocks, a diagonal kind, or the Chebyshev polynomial after the
 // update): x += a p, r -= a q, z = M^{-1} r, sc[2] = r.z, sc[3] = r.r.
+// npq > 0: p.q is the sum of the operator's npq partial sums in c->pqpart.
 template <typename T>
 hipError_t cg_step_pc(hx_ctx *c, int pc, T *x, T *r, const T *p, const T *q, T *z, double *sc,
-                      double *host_rr, int *flags)
+                      double *host_rr, int *flags, int npq)
 {
     *flags = 0;
+    const double *pqp = npq > 0 ? c->pqpart : nullptr;
     const int64_t n = c->n_dofs;
     const int ld = (int)c->n_cells + 1;
     const bool dbl = sizeof(T) == 8;
@@ -642,14 +656,14 @@ hipError_t cg_step_pc(hx_ctx *c, int pc, T *x, T *r, const T *p, const T *q, T *
     hipError_t e;
     if (pc == HX_PC_BLOCK_JACOBI) {
         e = dbl ? launch_cg_bj64(c, (double *)x, (double *)r, (const double *)p, (const double *)q,
-                                 (double *)z, sc, &nb)
+                                 (double *)z, sc, &nb, pqp, npq)
                 : launch_cg_bj32(c, (float *)x, (float *)r, (const float *)p, (const float *)q,
-                                 (float *)z, sc, &nb);
+                                 (float *)z, sc, &nb, pqp, npq);
     } else if (pc == HX_PC_MASS_BLOCK) {
         e = dbl ? launch_cg_massinv64(c, (double *)x, (double *)r, (const double *)p,
-                                      (const double *)q, (double *)z, sc, &nb)
+                                      (const double *)q, (double *)z, sc, &nb, pqp, npq)
                 : launch_cg_massinv32(c, (float *)x, (float *)r, (const float *)p, (const float *)q,
-                                      (float *)z, sc, &nb);
+                                      (float *)z, sc, &nb, pqp, npq);
     } else {
         const T *dinv = nullptr;
         if (pc == HX_PC_HELMHOLTZ_DIAG || pc == HX_PC_MASS_DIAG) {
@@ -662,7 +676,7 @@ hipError_t cg_step_pc(hx_ctx *c, int pc, T *x, T *r, const T *p, const T *q, T *
         if constexpr (sizeof(T) == 8)
             if (pc == HX_PC_MULTIGRID_MIXED) r32 = c->mgw32;
         hipLaunchKernelGGL(k_cg_elem<T>, dim3(nb), dim3(RT), 0, c->stream, n, x, r, p, q, z, dinv,
-                           sc, c->cgpart, ld, r32);
+                           sc, c->cgpart, ld, r32, pqp, npq);
         e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
@@ -716,14 +730,14 @@ hipError_t cg_step_p(hx_ctx *c, const T *z, T *p, double *sc, int flags)
 }
 
 hipError_t cg_step_pc64(hx_ctx *c, int pc, double *x, double *r, const double *p, const double *q,
-                        double *z, double *sc, double *host_rr, int *flags)
+                        double *z, double *sc, double *host_rr, int *flags, int npq)
 {
-    return cg_step_pc<double>(c, pc, x, r, p, q, z, sc, host_rr, flags);
+    return cg_step_pc<double>(c, pc, x, r, p, q, z, sc, host_rr, flags, npq);
 }
 hipError_t cg_step_pc32(hx_ctx *c, int pc, float *x, float *r, const float *p, const float *q,
-                        float *z, double *sc, int *flags)
+                        float *z, double *sc, int *flags, int npq)
 {
-    return cg_step_pc<float>(c, pc, x, r, p, q, z, sc, nullptr, flags);
+    return cg_step_pc<float>(c, pc, x, r, p, q, z, sc, nullptr, flags, npq);
 }
 hipError_t cg_step_p64(hx_ctx *c, const double *z, double *p, double *sc, int flags)
 {

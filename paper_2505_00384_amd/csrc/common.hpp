@@ -121,6 +121,7 @@ struct hx_ctx {
     double *dg64 = nullptr;       // [2][n_dofs] inverse volume diagonals: mass + stiffness, mass
     float *dg32 = nullptr;
     double *cgpart = nullptr;     // [2][n_cells + 1] per-block partial sums of the fused CG steps
+    double *pqpart = nullptr;     // [2 (n_cells + 1)] the operator's per-workgroup partial sums of p.q
     // pressure system of the IMEX stage (A U + B P = F, C U + D P = G)
     bool has_press = false;
     double ps_tau = 0.0;
@@ -257,9 +258,9 @@ hx_status mg_check(hx_ctx *c);
 hipError_t launch_enthalpy(hx_ctx *c, const double *p, const double *rho, double gamma, double *h);
 hipError_t launch_massinv32(hx_ctx *c, const float *r, float *z);
 hipError_t launch_cg_massinv64(hx_ctx *c, double *x, double *r, const double *p, const double *q,
-                               double *z, const double *sc, int *nblk);
+                               double *z, const double *sc, int *nblk, const double *pqp, int npq);
 hipError_t launch_cg_massinv32(hx_ctx *c, float *x, float *r, const float *p, const float *q,
-                               float *z, const double *sc, int *nblk);
+                               float *z, const double *sc, int *nblk, const double *pqp, int npq);
 
 // operator: y = A x, or y = b - A x when b != nullptr
 hipError_t launch_apply64(hx_ctx *c, const double *x, double *y, const double *b);
@@ -275,9 +276,15 @@ int op_cells_per_wave(int n);
 // one part of A x: part 1 the cell integrals only, part 2 the face terms only
 hipError_t launch_apply_part64(hx_ctx *c, int part, const double *x, double *y);
 hipError_t launch_apply_part32(hx_ctx *c, int part, const float *x, float *y);
-// y = A x and dst = x.(A x) in FP64 (CG's p.q), summed in a fixed order
-hipError_t launch_apply64_dot(hx_ctx *c, const double *x, double *y, double *dst);
-hipError_t launch_apply32_dot(hx_ctx *c, const float *x, float *y, double *dst);
+// y = A x and x.(A x) in FP64 (CG's p.q), summed in a fixed order.  With
+// npq given and at most PQ_MAX per-workgroup partial sums, the partial sums
+// stay in c->pqpart for the next fused CG step to sum (*npq = their count);
+// otherwise dst = their sum (*npq = 0).
+constexpr int PQ_MAX = 8192;
+hipError_t launch_apply64_dot(hx_ctx *c, const double *x, double *y, double *dst,
+                              int *npq = nullptr);
+hipError_t launch_apply32_dot(hx_ctx *c, const float *x, float *y, double *dst,
+                              int *npq = nullptr);
 // dst = sum of part[0..n) in a fixed order (two stages)
 hipError_t reduce_parts(hx_ctx *c, const double *part, int64_t n, double *dst);
 
@@ -323,20 +330,21 @@ hipError_t blas_fill32(hx_ctx *c, int64_t n, float v, float *y);
 // fused CG steps on device scalars (no host round trip)
 hipError_t cg32_init(hx_ctx *c, int64_t n, float *r, float *z, float *p, double *sc);
 hipError_t cg32_step_x(hx_ctx *c, int64_t n, float *x, float *r, const float *p,
-                       const float *q, double *sc);
+                       const float *q, double *sc, const double *pqp, int npq);
 hipError_t cg32_step_p(hx_ctx *c, int64_t n, const float *z, float *p, double *sc);
-// fused CG steps (scalars in sc[0..3], see blas.hip)
+// fused CG steps (scalars in sc[0..3], see blas.hip); p.q is the sum256 of
+// pqp[0..npq) when pqp is given, else sc[1]
 hipError_t launch_cg_bj64(hx_ctx *c, double *x, double *r, const double *p, const double *q,
-                          double *z, const double *sc, int *nblk);
+                          double *z, const double *sc, int *nblk, const double *pqp, int npq);
 hipError_t launch_cg_bj32(hx_ctx *c, float *x, float *r, const float *p, const float *q, float *z,
-                          const double *sc, int *nblk);
+                          const double *sc, int *nblk, const double *pqp, int npq);
 // flags of a fused CG step: the direction coefficient is in sc[5] and the
 // new r.z already in sc[0] (no shift needed); r.r was written to host_rr
 constexpr int CG_BETA_READY = 1, CG_RR_ON_HOST = 2;
 hipError_t cg_step_pc64(hx_ctx *c, int pc, double *x, double *r, const double *p, const double *q,
-                        double *z, double *sc, double *host_rr, int *flags);
+                        double *z, double *sc, double *host_rr, int *flags, int npq);
 hipError_t cg_step_pc32(hx_ctx *c, int pc, float *x, float *r, const float *p, const float *q,
-                        float *z, double *sc, int *flags);
+                        float *z, double *sc, int *flags, int npq);
 hipError_t cg_step_p64(hx_ctx *c, const double *z, double *p, double *sc, int flags);
 hipError_t cg_step_p32(hx_ctx *c, const float *z, float *p, double *sc, int flags);
 hipError_t cg32_step_p_dot(hx_ctx *c, int64_t n, const float *r, const float *z, double *sc);

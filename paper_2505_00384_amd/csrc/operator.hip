@@ -863,27 +863,37 @@ int op_cells_per_wave(int n)
     }
 }
 
-// y = A x and dst = x.y (summed in a fixed order)
-hipError_t launch_apply64_dot(hx_ctx *c, const double *x, double *y, double *dst)
+// y = A x and x.y (summed in a fixed order): the per-workgroup partial sums
+// in c->pqpart are left there when npq is given and there are at most
+// PQ_MAX of them (*npq = their count), else dst = their sum (*npq = 0)
+template <typename T>
+hipError_t apply_dot(hx_ctx *c, const T *x, T *y, double *dst, int *npq)
 {
+    if (npq) *npq = 0;
     if (c->n_hang) {
-        hipError_t e = apply_dispatch<double>(c, x, y, nullptr);
-        return e != hipSuccess ? e : blas_dot(c, c->n_dofs, x, y, dst);
+        hipError_t e = apply_dispatch<T>(c, x, y, nullptr);
+        if (e != hipSuccess) return e;
+        if constexpr (sizeof(T) == 8) return blas_dot(c, c->n_dofs, x, y, dst);
+        else return blas_dot32(c, c->n_dofs, x, y, dst);
     }
     int nwg = 0;
-    hipError_t e = apply_dispatch<double>(c, x, y, nullptr, c->cgpart, &nwg);
-    return e != hipSuccess ? e : reduce_parts(c, c->cgpart, nwg, dst);
+    hipError_t e = apply_dispatch<T>(c, x, y, nullptr, c->pqpart, &nwg);
+    if (e != hipSuccess) return e;
+    if (npq && nwg <= PQ_MAX) {
+        *npq = nwg;
+        return hipSuccess;
+    }
+    return reduce_parts(c, c->pqpart, nwg, dst);
 }
 
-hipError_t launch_apply32_dot(hx_ctx *c, const float *x, float *y, double *dst)
+hipError_t launch_apply64_dot(hx_ctx *c, const double *x, double *y, double *dst, int *npq)
 {
-    if (c->n_hang) {
-        hipError_t e = apply_dispatch<float>(c, x, y, nullptr);
-        return e != hipSuccess ? e : blas_dot32(c, c->n_dofs, x, y, dst);
-    }
-    int nwg = 0;
-    hipError_t e = apply_dispatch<float>(c, x, y, nullptr, c->cgpart, &nwg);
-    return e != hipSuccess ? e : reduce_parts(c, c->cgpart, nwg, dst);
+    return apply_dot<double>(c, x, y, dst, npq);
+}
+
+hipError_t launch_apply32_dot(hx_ctx *c, const float *x, float *y, double *dst, int *npq)
+{
+    return apply_dot<float>(c, x, y, dst, npq);
 }
 
 }  // namespace hx

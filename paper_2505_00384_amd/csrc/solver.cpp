@@ -120,13 +120,15 @@ hx_status inner_fp32(hx_ctx *c, int pc, const double *v, double *z, float *w32, 
     HX_HIP(c, hipMemcpyAsync(p, zz, sizeof(float) * n, hipMemcpyDeviceToDevice, c->stream));
     HX_HIP(c, blas_dot32(c, n, r, zz, sc + 0));
     for (int it = 0; it < iters; ++it) {
-        HX_HIP(c, launch_apply32_dot(c, p, q, sc + 1));
+        // p.q: partial sums left for the step kernel, or summed into sc[1]
+        int npq = 0;
+        HX_HIP(c, launch_apply32_dot(c, p, q, sc + 1, &npq));
         if (it + 1 == iters) {
-            HX_HIP(c, cg32_step_x(c, n, x, r, p, q, sc));
+            HX_HIP(c, cg32_step_x(c, n, x, r, p, q, sc, npq > 0 ? c->pqpart : nullptr, npq));
             break;
         }
         int fl = 0;
-        HX_HIP(c, cg_step_pc32(c, pc, x, r, p, q, zz, sc, &fl));
+        HX_HIP(c, cg_step_pc32(c, pc, x, r, p, q, zz, sc, &fl, npq));
         HX_HIP(c, cg_step_p32(c, zz, p, sc, fl));
     }
     HX_HIP(c, blas_cast32to64(c, n, x, z, nullptr));
@@ -247,11 +249,13 @@ hipError_t sys_apply(hx_ctx *c, const hx_solve_params *prm, const double *x, dou
     return launch_apply64(c, x, y, b);
 }
 
-// q = M p and dst = p.q (the operator kernel sums p.q itself for system 0)
+// q = M p and dst = p.q (the operator kernel sums p.q itself for system 0
+// and, when *npq > 0 on return, leaves its partial sums for the step kernel)
 hipError_t sys_apply_dot(hx_ctx *c, const hx_solve_params *prm, const double *p, double *q,
-                         double *dst)
+                         double *dst, int *npq)
 {
-    if (prm->system == 0) return launch_apply64_dot(c, p, q, dst);
+    *npq = 0;
+    if (prm->system == 0) return launch_apply64_dot(c, p, q, dst, npq);
     hipError_t e = sys_apply(c, prm, p, q, nullptr);
     if (e == hipSuccess) e = blas_dot(c, c->n_dofs, p, q, dst);
     return e;
@@ -321,11 +325,12 @@ hx_status solve_cg(hx_ctx *c, const hx_solve_params *prm, const double *b, doubl
     while (it < prm->max_iter && !stop) {
         Timer &t = *tms[it % 2];
         t.rec(1, c->stream);
-        if (hipSuccess != sys_apply_dot(c, prm, p, q, sc + 1)) { err = fail(c, HX_ERR_DEVICE, "CG: apply"); break; }
+        int npq = 0;
+        if (hipSuccess != sys_apply_dot(c, prm, p, q, sc + 1, &npq)) { err = fail(c, HX_ERR_DEVICE, "CG: apply"); break; }
         t.rec(2, c->stream);
         t.rec(0, c->stream);
         int fl = 0;
-        if (hipSuccess != cg_step_pc64(c, prm->pc, x, r, p, q, z, sc, c->pin_dev + it % 2, &fl)) { err = fail(c, HX_ERR_DEVICE, "CG: step"); break; }
+        if (hipSuccess != cg_step_pc64(c, prm->pc, x, r, p, q, z, sc, c->pin_dev + it % 2, &fl, npq)) { err = fail(c, HX_ERR_DEVICE, "CG: step"); break; }
         t.rec(3, c->stream);
         if (hipSuccess != cg_step_p64(c, z, p, sc, fl)) { err = fail(c, HX_ERR_DEVICE, "CG: p update"); break; }
         // |r|^2 for the host: written by the reduction itself, else copied
