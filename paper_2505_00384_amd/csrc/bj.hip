@@ -13,6 +13,7 @@
 // before the solve and sums r.z and r.r per block, so one CG step touches
 // each vector once.
 #include "common.hpp"
+#include "bj_cell.hpp"
 #include "sum256.hpp"
 
 #include <cstddef>
@@ -138,109 +139,7 @@ k_bj(const T *__restrict__ rin, T *__restrict__ z, const T *__restrict__ S, cons
         for (int e = tt; e < 4; e += NF) sC[lc][e] = C[cid * 4 + e];
     }
     __syncthreads();
-    T v[N], w[N], rp[N];
-    // S_x^T along x: thread (j=a, l=b); rp keeps the residual pencil, whose
-    // positions are those of the output pencil written at the end
-    if (active) {
-#pragma unroll
-        for (int i = 0; i < N; ++i) v[i] = rp[i] = sR[lc][i + N * a + NF * b];
-#pragma unroll
-        for (int m = 0; m < N; ++m) {
-            T s = 0;
-#pragma unroll
-            for (int i = 0; i < N; ++i) s += sS[lc][0][i * N + m] * v[i];
-            w[m] = s;
-        }
-    }
-    __syncthreads();
-    if (active) {
-#pragma unroll
-        for (int m = 0; m < N; ++m) sR[lc][m + N * a + NF * b] = w[m];
-    }
-    __syncthreads();
-    // S_y^T along y: thread (mx=a, l=b)
-    if (active) {
-#pragma unroll
-        for (int j = 0; j < N; ++j) v[j] = sR[lc][a + N * j + NF * b];
-#pragma unroll
-        for (int m = 0; m < N; ++m) {
-            T s = 0;
-#pragma unroll
-            for (int j = 0; j < N; ++j) s += sS[lc][1][j * N + m] * v[j];
-            w[m] = s;
-        }
-    }
-    __syncthreads();
-    if (active) {
-#pragma unroll
-        for (int m = 0; m < N; ++m) sR[lc][a + N * m + NF * b] = w[m];
-    }
-    __syncthreads();
-    // S_z^T along z, diagonal scaling, S_z along z: thread (mx=a, my=b)
-    if (active) {
-#pragma unroll
-        for (int l = 0; l < N; ++l) v[l] = sR[lc][a + N * b + NF * l];
-        const T c0 = sC[lc][0], cx = sC[lc][1], cy = sC[lc][2], cz = sC[lc][3];
-        const T base = c0 + cx * sL[lc][0][a] + cy * sL[lc][1][b];
-#pragma unroll
-        for (int m = 0; m < N; ++m) {
-            T s = 0;
-#pragma unroll
-            for (int l = 0; l < N; ++l) s += sS[lc][2][l * N + m] * v[l];
-            w[m] = s / (base + cz * sL[lc][2][m]);
-        }
-#pragma unroll
-        for (int l = 0; l < N; ++l) {
-            T s = 0;
-#pragma unroll
-            for (int m = 0; m < N; ++m) s += sS[lc][2][l * N + m] * w[m];
-            v[l] = s;
-        }
-    }
-    __syncthreads();
-    if (active) {
-#pragma unroll
-        for (int l = 0; l < N; ++l) sR[lc][a + N * b + NF * l] = v[l];
-    }
-    __syncthreads();
-    // S_y along y: thread (mx=a, l=b)
-    if (active) {
-#pragma unroll
-        for (int m = 0; m < N; ++m) v[m] = sR[lc][a + N * m + NF * b];
-#pragma unroll
-        for (int j = 0; j < N; ++j) {
-            T s = 0;
-#pragma unroll
-            for (int m = 0; m < N; ++m) s += sS[lc][1][j * N + m] * v[m];
-            w[j] = s;
-        }
-    }
-    __syncthreads();
-    if (active) {
-#pragma unroll
-        for (int j = 0; j < N; ++j) sR[lc][a + N * j + NF * b] = w[j];
-    }
-    __syncthreads();
-    // S_x along x: thread (j=a, l=b); the output goes back through LDS so
-    // that the stores are contiguous across threads
-    if (active) {
-#pragma unroll
-        for (int m = 0; m < N; ++m) v[m] = sR[lc][m + N * a + NF * b];
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-            T s = 0;
-#pragma unroll
-            for (int m = 0; m < N; ++m) s += sS[lc][0][i * N + m] * v[m];
-            w[i] = s;
-            acc_rz += (double)rp[i] * (double)s;
-        }
-    }
-    __syncthreads();
-    if (active) {
-#pragma unroll
-        for (int i = 0; i < N; ++i) sR[lc][i + N * a + NF * b] = w[i];
-    }
-    __syncthreads();
+    bj_cell_solve<N, T>(sR[lc], sS[lc], sL[lc], sC[lc], a, b, active, acc_rz);
     if (active) {
         if (CHEB) {
             for (int e = tt; e < ND; e += NF) {

@@ -368,8 +368,10 @@ hx_status mlp_train(hx_ctx *c, const float *feats, const float *targets, int64_t
 hx_status mlp_precondition(hx_ctx *c, const double *r, double *z);
 hx_status mlp_precondition_batched(hx_ctx *c, const double *r, double *z);
 hx_status mlp_trace(hx_ctx *c, int what, float *host_buf, int64_t count);
-// z += w_K net(features(r))_K on a z that already holds BJ(r)
-hx_status mlp_correct(hx_ctx *c, const double *r, double *z);
+// z = BJ(v) + w_K net(features(v))_K with v = w / |w| (|w|^2 the sum256 of
+// part[0..nbp); v written to vout) or v = w when part is null, in one launch
+hx_status mlp_apply_fused(hx_ctx *c, const double *w, const double *part, int nbp, double *vout,
+                          double *z);
 hx_status mlp_training_pair(hx_ctx *c, const double *b, const double *xs, const double *xj,
                             float clip, float *feats, float *targets);
 

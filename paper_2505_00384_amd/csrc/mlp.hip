@@ -16,6 +16,8 @@
 // The correction added to block Jacobi is w_K net(features)_K with w_K the RMS
 // of the block-Jacobi output on the cell, so the network works in O(1) units.
 #include "common.hpp"
+#include "bj_cell.hpp"
+#include "sum256.hpp"
 
 #include <cmath>
 #include <cstring>
@@ -378,14 +380,19 @@ k_add_correction(int nd, const float *__restrict__ o, double *z)
 }
 
 // ---------------------------------------------------------------------------
-// The learned correction in one launch (after block Jacobi has written z):
-// a workgroup of 4 waves serves 16 cells.  It forms their features (as
-// k_features: r_K, the six neighbours' face layers and the coefficient
-// feature, scaled by 1 / RMS(r_K)) in LDS as BF16, runs the three layers on
-// v_mfma_f32_16x16x32_bf16 with the hidden activations in LDS (each wave owns
-// a quarter of every layer's outputs and loads the weight fragments of up to
-// eight k-steps at once, so their latency is paid once per chunk), and adds
-// z_K += w_K net(features)_K with w_K = RMS(z_K) of the block-Jacobi output.
+// The learned preconditioner, a workgroup of FW waves serving 16 cells.  It
+// reads r_K (WBJ: scaled by s = 1/|w| when the partial sums of |w|^2 are
+// given, the normalisation of the Krylov vector, whose result it also
+// writes), forms the features (as k_features: r_K, the six neighbours' face
+// layers and the coefficient feature, scaled by 1 / RMS(r_K)) in LDS as BF16,
+// obtains BJ(r)_K (WBJ: solves the cells' block-Jacobi systems in LDS with
+// the sweeps of the block-Jacobi kernels, so the whole preconditioner is one
+// launch; otherwise reads it from z, written by the block-Jacobi kernel),
+// runs the three layers on v_mfma_f32_16x16x32_bf16 with the hidden
+// activations in LDS (each wave owns a share of every layer's outputs and
+// loads the weight fragments of several k-steps at once, so their latency
+// is paid once per chunk), and writes z_K = BJ(r)_K + w_K net(features)_K
+// with w_K = RMS(BJ(r)_K).
 // Fragment layout of the MFMA: lane l holds A[m = l % 16][k = 8 (l / 16) ..
 // + 7] and B[k][n = l % 16] likewise, and receives C[4 (l / 16) + q][l % 16].
 constexpr int FT = 16;   // cells per workgroup of the fused kernel
@@ -427,45 +434,61 @@ __device__ __forceinline__ void fused_layer(const uint16_t (*sA)[LDA], const uin
 
 constexpr int FW = 16;   // waves per workgroup of the fused kernel
 
-template <int N>
+template <int N, bool WBJ>
 __global__ void __launch_bounds__(64 * FW)
-k_mlp_fused(int64_t n_cells, const double *__restrict__ r, double *__restrict__ z,
+k_mlp_fused(int64_t n_cells, const double *__restrict__ w, double *__restrict__ z,
             const int32_t *__restrict__ nbr, const double *__restrict__ coef,
             const uint16_t *__restrict__ w1b, const uint16_t *__restrict__ w2b,
             const uint16_t *__restrict__ w3b, const float *__restrict__ b1, const float *__restrict__ b2,
-            const float *__restrict__ b3)
+            const float *__restrict__ b3, const double *__restrict__ bjS,
+            const double *__restrict__ bjL, const double *__restrict__ bjC,
+            const double *__restrict__ part, int nbp, double *__restrict__ vout)
 {
     constexpr int NF = N * N, ND = NF * N, NIN = ND + 6 * NF + 1, LDX = ((NIN + 31) / 32) * 32;
     constexpr int NTH = 64 * FW, PER = (HID / 16) / FW;   // column tiles of 16 per wave, hidden layers
     constexpr int NT3 = (ND + 15) / 16, PER3 = (NT3 + FW - 1) / FW;
     constexpr int SUB = NTH / FT;                         // threads per cell in the norms
     static_assert(PER * FW * 16 == HID && SUB >= 16 && (SUB & (SUB - 1)) == 0, "layout");
+    static_assert(FT * NF <= NTH && NTH >= 256, "block-Jacobi threads");
+    constexpr int FB = WBJ ? FT : 1;
     __shared__ __align__(16) uint16_t sX[FT][LDX + 8];
     __shared__ __align__(16) uint16_t sH[FT][HID + 8];
     __shared__ __align__(16) uint16_t sH2[FT][HID + 8];
-    __shared__ double sS[FT], sW[FT];
+    __shared__ double sR[FT][ND];          // r_K, then BJ(r)_K
+    __shared__ double sBS[FB][3][NF], sBL[FB][3][N], sBC[FB][4];
+    __shared__ double sS[FT], sW[FT], sh4[4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t c0 = (int64_t)blockIdx.x * FT;
-    // RMS of r_K and of the block-Jacobi output z_K: SUB threads per cell
+    // the Krylov vector's scale (the fixed-order sum the host repeats)
+    const double sc = part ? 1.0 / sqrt(sum256(part, nbp, sh4)) : 1.0;
+    // r_K = sc w_K into LDS (and to vout), its RMS: SUB threads per cell
     {
         const int cl = tid / SUB, sub = tid % SUB;
         const int64_t c = c0 + cl;
-        double sr = 0.0, sz = 0.0;
+        double sr = 0.0;
         if (c < n_cells)
             for (int e = sub; e < ND; e += SUB) {
-                const double v = r[c * ND + e], u = z[c * ND + e];
+                const double v = w[c * ND + e] * sc;
+                sR[cl][e] = v;
+                if (vout) vout[c * ND + e] = v;
                 sr += v * v;
-                sz += u * u;
             }
 #pragma unroll
-        for (int o = SUB / 2; o > 0; o >>= 1) {
-            sr += __shfl_xor(sr, o, 64);
-            sz += __shfl_xor(sz, o, 64);
+        for (int o = SUB / 2; o > 0; o >>= 1) sr += __shfl_xor(sr, o, 64);
+        if (sub == 0) sS[cl] = sqrt(sr / ND);
+    }
+    // block-Jacobi tables of the workgroup's cells
+    if constexpr (WBJ) {
+        for (int idx = tid; idx < FT * 3 * NF; idx += NTH) {
+            const int cl = idx / (3 * NF), e = idx % (3 * NF);
+            if (c0 + cl < n_cells) sBS[cl][e / NF][e % NF] = bjS[(c0 + cl) * 3 * NF + e];
         }
-        if (sub == 0) {
-            sS[cl] = sqrt(sr / ND);
-            sW[cl] = sqrt(sz / ND);
+        for (int idx = tid; idx < FT * 3 * N; idx += NTH) {
+            const int cl = idx / (3 * N), e = idx % (3 * N);
+            if (c0 + cl < n_cells) sBL[cl][e / N][e % N] = bjL[(c0 + cl) * 3 * N + e];
         }
+        if (tid < FT * 4 && c0 + tid / 4 < n_cells)
+            sBC[tid / 4][tid % 4] = bjC[(c0 + tid / 4) * 4 + tid % 4];
     }
     __syncthreads();
     // features, BF16
@@ -477,7 +500,7 @@ k_mlp_fused(int64_t n_cells, const double *__restrict__ r, double *__restrict__ 
             const double sK = sS[cl], inv = sK > 0.0 ? 1.0 / sK : 0.0;
             double v = 0.0;
             if (e < ND) {
-                v = r[c * ND + e] * inv;
+                v = sR[cl][e] * inv;
             } else if (e < ND + 6 * NF) {
                 const int f = (e - ND) / NF, t = (e - ND) % NF;
                 const int32_t nb = nbr[c * 6 + f];
@@ -488,7 +511,7 @@ k_mlp_fused(int64_t n_cells, const double *__restrict__ r, double *__restrict__ 
                     ijk[d] = m;
                     ijk[d == 0 ? 1 : 0] = p;
                     ijk[d == 2 ? 1 : 2] = q;
-                    v = r[(int64_t)nb * ND + ijk[0] + N * (ijk[1] + N * ijk[2])] * inv;
+                    v = (w[(int64_t)nb * ND + ijk[0] + N * (ijk[1] + N * ijk[2])] * sc) * inv;
                 }
             } else {
                 v = sK > 0.0 ? coef[c] : 0.0;
@@ -497,9 +520,34 @@ k_mlp_fused(int64_t n_cells, const double *__restrict__ r, double *__restrict__ 
         }
         sX[cl][e] = f2bf(fv);
     }
-    __syncthreads();
+    if constexpr (WBJ) {
+        // block Jacobi in place: NF threads per cell
+        const int lc0 = tid / NF, lc = lc0 < FT ? lc0 : 0, tt = tid - lc0 * NF;
+        const bool active = lc0 < FT && c0 + lc0 < n_cells;
+        double unused = 0.0;
+        bj_cell_solve<N, double>(sR[lc], sBS[lc], sBL[lc], sBC[lc], tt % N, tt / N, active, unused);
+    } else {
+        // BJ(r) from z, once the features have read r
+        __syncthreads();
+        for (int idx = tid; idx < FT * ND; idx += NTH) {
+            const int cl = idx / ND, e = idx % ND;
+            if (c0 + cl < n_cells) sR[cl][e] = z[(c0 + cl) * ND + e];
+        }
+        __syncthreads();
+    }
+    // w_K = RMS(BJ(r)_K)
+    {
+        const int cl = tid / SUB, sub = tid % SUB;
+        double sz = 0.0;
+        if (c0 + cl < n_cells)
+            for (int e = sub; e < ND; e += SUB) sz += sR[cl][e] * sR[cl][e];
+#pragma unroll
+        for (int o = SUB / 2; o > 0; o >>= 1) sz += __shfl_xor(sz, o, 64);
+        if (sub == 0) sW[cl] = sqrt(sz / ND);
+    }
     const int ccol = lane & 15, crow = 4 * (lane >> 4);
-    // layer 1: each wave PER of the 16 column tiles
+    // layer 1: each wave PER of the 16 column tiles (sX is complete: a
+    // barrier follows the block-Jacobi step)
     {
         f32x4 acc[PER];
         fused_layer<LDX, PER, LDX + 8, LDX>(sX, w1b, HID, PER * wave, lane, acc);
@@ -523,7 +571,7 @@ k_mlp_fused(int64_t n_cells, const double *__restrict__ r, double *__restrict__ 
         }
     }
     __syncthreads();
-    // layer 3 and the correction
+    // layer 3 and z = BJ(r) + w_K o_K
     {
         f32x4 acc[PER3];
         fused_layer<HID, PER3, HID + 8, HID>(sH2, w3b, ND, PER3 * wave, lane, acc);
@@ -534,7 +582,8 @@ k_mlp_fused(int64_t n_cells, const double *__restrict__ r, double *__restrict__ 
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int64_t c = c0 + crow + q;
-                if (c < n_cells) z[c * ND + n] += sW[crow + q] * (double)(acc[j][q] + b3[n]);
+                if (c < n_cells)
+                    z[c * ND + n] = sR[crow + q][n] + sW[crow + q] * (double)(acc[j][q] + b3[n]);
             }
         }
     }
@@ -588,6 +637,7 @@ struct MlpState {
           *dh2 = nullptr, *scale = nullptr, *loss = nullptr;
     double *part = nullptr, *zt = nullptr;
     float *loss_host = nullptr;
+    int n_cu = 0;            // compute units of the device
 };
 
 static void free_batch(MlpState *s)
@@ -666,6 +716,9 @@ hx_status mlp_create(hx_ctx *c)
     A(s->loss, 16);
 #undef A
     if (st == HX_OK && hipHostMalloc((void **)&s->loss_host, 16) != hipSuccess) st = HX_ERR_DEVICE;
+    if (st == HX_OK &&
+        hipDeviceGetAttribute(&s->n_cu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess)
+        st = HX_ERR_DEVICE;
     if (st != HX_OK) {
         mlp_destroy(c);
         return st;
@@ -956,44 +1009,61 @@ hx_status mlp_training_pair(hx_ctx *c, const double *b, const double *xs, const 
     return HX_OK;
 }
 
-// z = BJ(r) + w_K net(features(r))_K, w_K = RMS(BJ(r)_K)
+// z = BJ(v) + w_K net(features(v))_K, w_K = RMS(BJ(v)_K), with v = w / |w|
+// (|w|^2 the fixed-order sum of part[0..nbp), v written to vout) or v = w
+// (part null).  With at most one workgroup per compute unit the whole
+// preconditioner is one launch (the grid is too small for occupancy to
+// matter, and the launch it saves does); on larger meshes the block-Jacobi
+// kernel (with the normalisation) runs first and the network kernel, at
+// half the registers and twice the occupancy, reads its output.
 template <int N>
-static hipError_t mlp_fused_n(hx_ctx *c, const double *r, double *z)
+static hipError_t mlp_fused_n(hx_ctx *c, const double *w, const double *part, int nbp,
+                              double *vout, double *z)
 {
     MlpState *s = c->mlp;
-    hipLaunchKernelGGL((k_mlp_fused<N>), dim3((unsigned)((c->n_cells + FT - 1) / FT)), dim3(64 * FW), 0,
-                       c->stream, c->n_cells, r, z, c->nbr, c->coef_feat, s->w1b, s->w2b, s->w3b,
-                       s->w + s->off_b1, s->w + s->off_b2, s->w + s->off_b3);
+    const int64_t nwg = (c->n_cells + FT - 1) / FT;
+    if (nwg <= s->n_cu) {
+        hipLaunchKernelGGL((k_mlp_fused<N, true>), dim3((unsigned)nwg), dim3(64 * FW), 0, c->stream,
+                           c->n_cells, w, z, c->nbr, c->coef_feat, s->w1b, s->w2b, s->w3b,
+                           s->w + s->off_b1, s->w + s->off_b2, s->w + s->off_b3, c->bjS64, c->bjL64,
+                           c->bjC64, part, nbp, vout);
+        return hipGetLastError();
+    }
+    hipError_t e = part ? launch_bj64_scaled(c, w, part, nbp, vout, z) : launch_bj64(c, w, z);
+    if (e != hipSuccess) return e;
+    const double *v = part ? vout : w;
+    hipLaunchKernelGGL((k_mlp_fused<N, false>), dim3((unsigned)nwg), dim3(64 * FW), 0, c->stream,
+                       c->n_cells, v, z, c->nbr, c->coef_feat, s->w1b, s->w2b, s->w3b,
+                       s->w + s->off_b1, s->w + s->off_b2, s->w + s->off_b3, (const double *)nullptr,
+                       (const double *)nullptr, (const double *)nullptr, (const double *)nullptr, 0,
+                       (double *)nullptr);
     return hipGetLastError();
 }
 
-// The correction alone, on a z that already holds BJ(r): one fused launch
-// (features, the three layers, z_K += w_K o_K).
-hx_status mlp_correct(hx_ctx *c, const double *r, double *z)
+hx_status mlp_apply_fused(hx_ctx *c, const double *w, const double *part, int nbp, double *vout,
+                          double *z)
 {
     if (!c->mlp) return fail(c, HX_ERR_STATE, "no network loaded");
     hipError_t e = hipSuccess;
     switch (c->n) {
-    case 2: e = mlp_fused_n<2>(c, r, z); break;
-    case 3: e = mlp_fused_n<3>(c, r, z); break;
-    case 4: e = mlp_fused_n<4>(c, r, z); break;
-    case 5: e = mlp_fused_n<5>(c, r, z); break;
-    case 6: e = mlp_fused_n<6>(c, r, z); break;
-    case 7: e = mlp_fused_n<7>(c, r, z); break;
-    default: e = mlp_fused_n<8>(c, r, z); break;
+    case 2: e = mlp_fused_n<2>(c, w, part, nbp, vout, z); break;
+    case 3: e = mlp_fused_n<3>(c, w, part, nbp, vout, z); break;
+    case 4: e = mlp_fused_n<4>(c, w, part, nbp, vout, z); break;
+    case 5: e = mlp_fused_n<5>(c, w, part, nbp, vout, z); break;
+    case 6: e = mlp_fused_n<6>(c, w, part, nbp, vout, z); break;
+    case 7: e = mlp_fused_n<7>(c, w, part, nbp, vout, z); break;
+    default: e = mlp_fused_n<8>(c, w, part, nbp, vout, z); break;
     }
     HX_HIP(c, e);
     return HX_OK;
 }
 
-// z = BJ(r) + w_K net(features(r))_K: block Jacobi, then the fused
-// correction.  A non-finite z shows up in the FGMRES Hessenberg column,
-// where the Givens step rejects it and the solver switches to block Jacobi.
+// z = BJ(r) + w_K net(features(r))_K in one launch.  A non-finite z shows up
+// in the FGMRES Hessenberg column, where the Givens step rejects it and the
+// solver switches to block Jacobi.
 hx_status mlp_precondition(hx_ctx *c, const double *r, double *z)
 {
-    if (!c->mlp) return fail(c, HX_ERR_STATE, "no network loaded");
-    HX_HIP(c, launch_bj64(c, r, z));
-    return mlp_correct(c, r, z);
+    return mlp_apply_fused(c, r, nullptr, 0, nullptr, z);
 }
 
 // The batched form of the same preconditioner (features, the three layers

@@ -590,10 +590,11 @@ hx_status solve_fgmres(hx_ctx *c, const hx_solve_params *prm, const double *b, d
             Timer &t = *tms[j % 2];
             t.rec(0, c->stream);
             if (j > 0 && fuse) {
-                HX_HIP(c, launch_bj64_scaled(c, w, c->red + RED_WPART, nb_prev, vj, zj));
                 if (pc == HX_PC_LEARNED) {
-                    hx_status st = mlp_correct(c, vj, zj);
+                    hx_status st = mlp_apply_fused(c, w, c->red + RED_WPART, nb_prev, vj, zj);
                     if (st != HX_OK) return st;
+                } else {
+                    HX_HIP(c, launch_bj64_scaled(c, w, c->red + RED_WPART, nb_prev, vj, zj));
                 }
             } else {
                 hx_status st = precondition(c, pc, mixed, prm->inner_iters, vj, zj, w32, &info->inner_iters);

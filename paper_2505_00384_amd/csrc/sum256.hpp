@@ -7,20 +7,22 @@
 
 namespace hx {
 
-// Sum of p[0..nb) by a workgroup of exactly 256 threads: thread t adds p[t],
-// p[t + 256], ... starting from 0; each wave folds its lanes with
-// shuffle-down distances 32, 16, ..., 1; the four wave sums are added in wave
-// order starting from 0.  Every thread returns the result.  The host function
-// host_sum256 (solver.cpp) performs the same additions in the same order.
+// Sum of p[0..nb) by the first 256 threads of a workgroup of at least 256
+// (every thread calls it): thread t < 256 adds p[t], p[t + 256], ...
+// starting from 0; each wave folds its lanes with shuffle-down distances 32,
+// 16, ..., 1; the four wave sums are added in wave order starting from 0.
+// Every thread returns the result.  The host function host_sum256
+// (solver.cpp) performs the same additions in the same order.
 __device__ inline double sum256(const double *__restrict__ p, int nb, double *sh /* LDS [4] */)
 {
     double s = 0.0;
-    for (int i = threadIdx.x; i < nb; i += 256) s += p[i];
+    if (threadIdx.x < 256)
+        for (int i = threadIdx.x; i < nb; i += 256) s += p[i];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     __syncthreads();
-    if (lane == 0) sh[wv] = s;
+    if (lane == 0 && wv < 4) sh[wv] = s;
     __syncthreads();
     double t = 0.0;
 #pragma unroll

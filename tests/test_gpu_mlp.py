@@ -164,6 +164,46 @@ def test_learned_preconditioner_parity(terrain):
     assert np.linalg.norm(zr - zb) > 0.01 * np.linalg.norm(zb)      # the correction is not trivial
 
 
+def test_learned_preconditioner_two_launch_form():
+    """On 4,352 cells (272 workgroups of 16 cells, more than one per compute
+    unit of a 256-CU device) block Jacobi and the network kernel run as two
+    launches instead of one.  Parity with the oracle on sampled cells (a
+    cell's output depends only on its own and its neighbours' residual values
+    and on its own coefficient feature), and a zero network reproduces block
+    Jacobi bit for bit, also inside FGMRES, where the preconditioner launch
+    also normalises the Krylov vector."""
+    import torch
+    hx = _hx()
+    p = problem(si.terrain_mesh(34, 8, 16, g=4), 4, coef="terrain")
+    ctx = gpu_context(p)
+    try:
+        w = si.mlp_init(11, out_scale=0.5)
+        ctx.set_network(w)
+        r = si.rhs_terrain(3)(*p.dof_coords()) + 0.2 * si.random_vector(p.n_dofs, 8)
+        z = ctx.apply_preconditioner(to_dev(r), kind=hx.HX_PC_LEARNED).cpu().numpy()
+        cells = np.random.default_rng(5).choice(p.n_cells, 256, replace=False)
+        coef = np.zeros(p.n_cells)
+        for i in cells:
+            ell, ab, bb, _ = p.bj_cell_data(int(i))
+            coef[i] = np.log(bb / (ab * np.cbrt(ell.prod()) ** 2))
+        zr = mlp.precondition(p, w.astype(np.float64), r, coef).reshape(p.n_cells, -1)[cells]
+        zb = p.bj_apply(r).reshape(p.n_cells, -1)[cells]
+        zg = z.reshape(p.n_cells, -1)[cells]
+        assert np.linalg.norm(zg - zr) <= 2e-3 * np.linalg.norm(zr - zb) + 1e-11 * np.linalg.norm(zb)
+        assert np.linalg.norm(zr - zb) > 0.01 * np.linalg.norm(zb)
+        ctx.set_network(si.mlp_init(9, out_scale=0.0))
+        rd = to_dev(si.random_vector(p.n_dofs, 6))
+        assert torch.equal(ctx.apply_preconditioner(rd, kind=hx.HX_PC_LEARNED),
+                           ctx.apply_preconditioner(rd, kind=hx.HX_PC_BLOCK_JACOBI))
+        b = to_dev(si.rhs_terrain(4)(*p.dof_coords()))
+        x_l, i_l = ctx.solve(b, params=hx.default_params(method=1, pc=hx.HX_PC_LEARNED))
+        x_b, i_b = ctx.solve(b, params=hx.default_params(method=1, pc=hx.HX_PC_BLOCK_JACOBI))
+        assert i_l["status"] == hx.HX_OK and i_l["iters"] == i_b["iters"]
+        assert torch.equal(x_l, x_b)
+    finally:
+        ctx.close()
+
+
 def test_zero_network_is_block_jacobi_and_poisoned_network_falls_back(terrain):
     import torch
     hx = _hx()
