@@ -104,7 +104,7 @@ __global__ void __launch_bounds__(RT) k_mdot1(int64_t n, int v0, int mc,
 // precision).
 // ---------------------------------------------------------------------------
 constexpr int DC_CW = 300, DC_S = 364;
-constexpr int DMC = 16;           // vectors per workgroup row of k_dcgs_dot
+constexpr int DMC = 32;           // most basis vectors per pass of the block kernels
 constexpr int DC_LD = 1024;       // partial-sum row stride (max workgroups per chunk)
 
 // rows r < nrows of part (stride ld, nb <= 1024 columns) summed in a fixed
@@ -138,31 +138,39 @@ __device__ void sum_rows(const double *__restrict__ part, int nrows, int nb, int
     }
 }
 
+// MC: vectors per workgroup row (a multiple of 4 at least the chunk's
+// count, so few loads are wasted on padding); NT: streaming loads of the
+// basis (vectors far larger than the caches; on small systems the basis is
+// read again from the caches at the next step)
+template <int MC, bool NT>
 __global__ void __launch_bounds__(RT) k_dcgs_dot(int64_t n, int j, const double *__restrict__ V,
                                                  int64_t ldv, const double *__restrict__ w,
                                                  double *part)
 {
-    __shared__ double wsum[RT / 64][2 * DMC];
+    __shared__ double wsum[RT / 64][2 * MC];
     const int m = j + 1;
-    const int v0 = blockIdx.y * DMC;
-    const int mc = (m - v0) < DMC ? (m - v0) : DMC;
+    const int v0 = blockIdx.y * MC;
+    const int mc = (m - v0) < MC ? (m - v0) : MC;
     const double *t = V + (int64_t)j * ldv;
-    double sa[DMC], sb[DMC];
+    double sa[MC], sb[MC];
 #pragma unroll
-    for (int k = 0; k < DMC; ++k) sa[k] = sb[k] = 0.0;
+    for (int k = 0; k < MC; ++k) sa[k] = sb[k] = 0.0;
     const int64_t stride = (int64_t)gridDim.x * RT;
     // rows past the chunk's last vector repeat that vector (same cache
     // lines, results unused), so the loads issue without branches
-    const double *rows[DMC];
+    const double *rows[MC];
 #pragma unroll
-    for (int k = 0; k < DMC; ++k) rows[k] = V + (int64_t)(v0 + (k < mc ? k : mc - 1)) * ldv;
+    for (int k = 0; k < MC; ++k) rows[k] = V + (int64_t)(v0 + (k < mc ? k : mc - 1)) * ldv;
     for (int64_t i = blockIdx.x * (int64_t)RT + threadIdx.x; i < n; i += stride) {
         const double ai = t[i], bi = w[i];
-        double v[DMC];
+        double v[MC];
 #pragma unroll
-        for (int k = 0; k < DMC; ++k) v[k] = rows[k][i];
+        for (int k = 0; k < MC; ++k) v[k] = NT ? __builtin_nontemporal_load(rows[k] + i) : rows[k][i];
+        // every load in flight before the arithmetic (the scheduler would
+        // interleave them with the multiply-adds to save registers)
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int k = 0; k < DMC; ++k) {
+        for (int k = 0; k < MC; ++k) {
             sa[k] += v[k] * ai;
             sb[k] += v[k] * bi;
         }
@@ -170,17 +178,17 @@ __global__ void __launch_bounds__(RT) k_dcgs_dot(int64_t n, int j, const double 
     // per-wave sums, then the waves in a fixed order
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-    for (int k = 0; k < DMC; ++k) {
+    for (int k = 0; k < MC; ++k) {
         const double ra = wave_sum(sa[k]), rb = wave_sum(sb[k]);
         if (lane == 0) {
             wsum[wv][k] = ra;
-            wsum[wv][DMC + k] = rb;
+            wsum[wv][MC + k] = rb;
         }
     }
     __syncthreads();
     if ((int)threadIdx.x < 2 * mc) {
         const int k = threadIdx.x < mc ? threadIdx.x : threadIdx.x - mc;
-        const int col = threadIdx.x < mc ? k : DMC + k;
+        const int col = threadIdx.x < mc ? k : MC + k;
         double r = 0.0;
         for (int q = 0; q < RT / 64; ++q) r += wsum[q][col];
         const int row = threadIdx.x < mc ? v0 + k : m + v0 + k;
@@ -234,39 +242,47 @@ __global__ void __launch_bounds__(1024) k_dcgs_coef(int j, int nb, const double 
 
 // k_dcgs_update: with t = V[j],
 //   V[j] <- (t - V_{j-1} c) / rho,  w <- w - V_{j-1} cw - t hj/rho
-// (reads V_{j-1} once), and per workgroup the partial sum of the new |w|^2.
-__global__ void __launch_bounds__(RT) k_dcgs_update(int64_t n, int j, double *V, int64_t ldv,
-                                                    const double *__restrict__ sc, double *w,
-                                                    double *part, double *hpart)
+// (reads V_{j-1} once, MC vectors at a time with all their loads in flight;
+// rows past V_{j-1} repeat its last vector with coefficient 0), and per
+// workgroup the partial sum of the new |w|^2.  Vr: V_0 .. V_{j-1} (read
+// only), t: V_j; the two do not overlap.
+template <int MC>
+__global__ void __launch_bounds__(RT) k_dcgs_update(int64_t n, int j, const double *__restrict__ Vr,
+                                                    int64_t ldv, double *__restrict__ t,
+                                                    const double *__restrict__ sc,
+                                                    double *__restrict__ w, double *part,
+                                                    double *hpart)
 {
     __shared__ double sh[RT / 64];
     __shared__ double cs[64], cws[64];
-    for (int k = threadIdx.x; k < j; k += RT) {
-        cs[k] = sc[k];
-        cws[k] = sc[DC_CW + k];
+    const int jp = (j + MC - 1) / MC * MC;
+    for (int k = threadIdx.x; k < jp; k += RT) {
+        cs[k] = k < j ? sc[k] : 0.0;
+        cws[k] = k < j ? sc[DC_CW + k] : 0.0;
     }
     __syncthreads();
     const double irho = sc[DC_S + 0], hr = sc[DC_S + 1];
     double nu = 0.0;
     const int64_t stride = (int64_t)gridDim.x * RT;
-    double *t = V + (int64_t)j * ldv;
     for (int64_t i = blockIdx.x * (int64_t)RT + threadIdx.x; i < n; i += stride) {
+        const double ti = t[i], wi = w[i];
         double sv = 0.0, sw = 0.0;
-        int k = 0;
-        for (; k + 4 <= j; k += 4) {
-            const double v0 = V[(int64_t)k * ldv + i], v1 = V[(int64_t)(k + 1) * ldv + i],
-                         v2 = V[(int64_t)(k + 2) * ldv + i], v3 = V[(int64_t)(k + 3) * ldv + i];
-            sv += v0 * cs[k] + v1 * cs[k + 1] + v2 * cs[k + 2] + v3 * cs[k + 3];
-            sw += v0 * cws[k] + v1 * cws[k + 1] + v2 * cws[k + 2] + v3 * cws[k + 3];
+        for (int k0 = 0; k0 < j; k0 += MC) {
+            double v[MC];
+#pragma unroll
+            for (int k = 0; k < MC; ++k) {
+                const int r = k0 + k < j ? k0 + k : j - 1;
+                v[k] = Vr[(int64_t)r * ldv + i];
+            }
+            __builtin_amdgcn_sched_barrier(0);   // every load in flight first
+#pragma unroll
+            for (int k = 0; k < MC; ++k) {
+                sv += v[k] * cs[k0 + k];
+                sw += v[k] * cws[k0 + k];
+            }
         }
-        for (; k < j; ++k) {
-            const double v = V[(int64_t)k * ldv + i];
-            sv += v * cs[k];
-            sw += v * cws[k];
-        }
-        const double ti = t[i];
         t[i] = (ti - sv) * irho;
-        const double wn = w[i] - sw - ti * hr;
+        const double wn = wi - sw - ti * hr;
         w[i] = wn;
         nu += wn * wn;
     }
@@ -519,13 +535,40 @@ hipError_t blas_dcgs(hx_ctx *c, int64_t n, int j, double *V, int64_t ldv, double
     if (j < 0 || j >= 64) return hipErrorInvalidValue;
     const int64_t want = (n + RT * 4 - 1) / (RT * 4);
     const int nb = (int)(want < 1 ? 1 : (want > DC_LD ? DC_LD : want));
+    // the dot's vectors in as few chunks of at most DMC as possible, each
+    // padded to a multiple of 4
     const int nch = (j + 1 + DMC - 1) / DMC;
-    hipLaunchKernelGGL(k_dcgs_dot, dim3(nb, nch), dim3(RT), 0, c->stream, n, j, V, ldv, w, c->dpart);
-    hipLaunchKernelGGL(k_dcgs_coef, dim3(1), dim3(1024), 0, c->stream, j, nb, c->dpart, sc, host_out);
+    const int per = (j + 1 + nch - 1) / nch;
     const int64_t want2 = (n + RT * 2 - 1) / (RT * 2);
     const int nb2 = (int)(want2 < 1 ? 1 : (want2 > RED_MAX ? RED_MAX : want2));
-    hipLaunchKernelGGL(k_dcgs_update, dim3(nb2), dim3(RT), 0, c->stream, n, j, V, ldv, sc, w,
-                       c->red + RED_WPART, host_out ? host_out + FG_PART : (double *)nullptr);
+    double *hp = host_out ? host_out + FG_PART : nullptr;
+    double *t = V + (int64_t)j * ldv;
+    const bool nt = n >= ((int64_t)1 << 23);   // 64 MB vectors and up
+#define HX_DCGS(MC)                                                                                \
+    case MC:                                                                                       \
+        if (nt)                                                                                    \
+            hipLaunchKernelGGL((k_dcgs_dot<MC, true>), dim3(nb, nch), dim3(RT), 0, c->stream, n, j, \
+                               V, ldv, w, c->dpart);                                               \
+        else                                                                                       \
+            hipLaunchKernelGGL((k_dcgs_dot<MC, false>), dim3(nb, nch), dim3(RT), 0, c->stream, n,   \
+                               j, V, ldv, w, c->dpart);                                            \
+        hipLaunchKernelGGL(k_dcgs_coef, dim3(1), dim3(1024), 0, c->stream, j, nb, c->dpart, sc,     \
+                           host_out);                                                              \
+        hipLaunchKernelGGL(k_dcgs_update<MC>, dim3(nb2), dim3(RT), 0, c->stream, n, j, V, ldv, t,   \
+                           sc, w, c->red + RED_WPART, hp);                                         \
+        break
+    switch ((per + 3) / 4 * 4) {
+        HX_DCGS(4);
+        HX_DCGS(8);
+        HX_DCGS(12);
+        HX_DCGS(16);
+        HX_DCGS(20);
+        HX_DCGS(24);
+        HX_DCGS(28);
+        HX_DCGS(32);
+    default: return hipErrorInvalidValue;
+    }
+#undef HX_DCGS
     if (scale) {
         const int64_t want3 = (n + RT * 4 - 1) / (RT * 4);
         const int nb3 = (int)(want3 < 1 ? 1 : (want3 > 4096 ? 4096 : want3));
