@@ -114,43 +114,91 @@ k_bj(const T *__restrict__ rin, T *__restrict__ z, const T *__restrict__ S, cons
             pq = sc[1];
         }
     }
+    // every global load of the cell at once (one memory round trip): the
+    // residual (and for the CG step x, p and q), the eigenvector matrices,
+    // the eigenvalues and the constants; each thread's values lie NF apart
+    constexpr int NLS = (3 * N + NF - 1) / NF;   // eigenvalue loads per thread
+    T rv[N], xv[N], pv[N], qv[N], tS[3], tL[NLS], tC = 0;
+    if (active) {
+        const T *rs = FUSE ? rw : r;
+#pragma unroll
+        for (int u = 0; u < N; ++u) {
+            const int64_t gi = cid * ND + tt + u * NF;
+            rv[u] = rs[gi];
+            if (FUSE) {
+                xv[u] = x[gi];
+                pv[u] = p[gi];
+                qv[u] = q[gi];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 3; ++u) tS[u] = S[cid * 3 * NF + tt + u * NF];
+#pragma unroll
+        for (int u = 0; u < NLS; ++u) {
+            const int e = tt + u * NF;
+            tL[u] = e < 3 * N ? L[cid * 3 * N + e] : T(0);
+        }
+        if (tt < 4) tC = C[cid * 4 + tt];
+    }
+    // (the scheduler would otherwise wait for each load before the next)
+    __builtin_amdgcn_sched_barrier(0);
     if (FUSE && active) {
         const T al = (T)(pq != 0.0 ? sc[0] / pq : 0.0);
-        for (int e = tt; e < ND; e += NF) {
+#pragma unroll
+        for (int u = 0; u < N; ++u) {
+            const int e = tt + u * NF;
             const int64_t gi = cid * ND + e;
-            const T rv = rw[gi] - al * q[gi];
-            x[gi] += al * p[gi];
-            rw[gi] = rv;
-            sR[lc][e] = rv;
-            acc_rr += (double)rv * (double)rv;
+            const T rn = rv[u] - al * qv[u];
+            x[gi] = xv[u] + al * pv[u];
+            rw[gi] = rn;
+            sR[lc][e] = rn;
+            acc_rr += (double)rn * (double)rn;
         }
     } else if (active && scaled) {
-        for (int e = tt; e < ND; e += NF) {
-            const T rv = r[cid * ND + e] * sfac;
-            x[cid * ND + e] = rv;
-            sR[lc][e] = rv;
+#pragma unroll
+        for (int u = 0; u < N; ++u) {
+            const int e = tt + u * NF;
+            const T rn = rv[u] * sfac;
+            x[cid * ND + e] = rn;
+            sR[lc][e] = rn;
         }
     } else if (active) {
-        for (int e = tt; e < ND; e += NF) sR[lc][e] = r[cid * ND + e];
+#pragma unroll
+        for (int u = 0; u < N; ++u) sR[lc][tt + u * NF] = rv[u];
     }
     if (active) {
-        for (int e = tt; e < 3 * NF; e += NF) sS[lc][e / NF][e % NF] = S[cid * 3 * NF + e];
-        for (int e = tt; e < 3 * N; e += NF) sL[lc][e / N][e % N] = L[cid * 3 * N + e];
-        for (int e = tt; e < 4; e += NF) sC[lc][e] = C[cid * 4 + e];
+#pragma unroll
+        for (int u = 0; u < 3; ++u) sS[lc][u][tt] = tS[u];
+#pragma unroll
+        for (int u = 0; u < NLS; ++u) {
+            const int e = tt + u * NF;
+            if (e < 3 * N) sL[lc][e / N][e % N] = tL[u];
+        }
+        if (tt < 4) sC[lc][tt] = tC;
     }
     __syncthreads();
     bj_cell_solve<N, T>(sR[lc], sS[lc], sL[lc], sC[lc], a, b, active, acc_rz);
     if (active) {
         if (CHEB) {
-            for (int e = tt; e < ND; e += NF) {
+            T zo[N], xo[N];
+#pragma unroll
+            for (int u = 0; u < N; ++u) {
+                const int64_t gi = cid * ND + tt + u * NF;
+                zo[u] = (flags & CHEB_READ_D) ? z[gi] : T(0);
+                xo[u] = (flags & CHEB_ACCUM) ? x[gi] : T(0);
+            }
+#pragma unroll
+            for (int u = 0; u < N; ++u) {
+                const int e = tt + u * NF;
                 const int64_t gi = cid * ND + e;
                 T dn = ca * sR[lc][e];
-                if (flags & CHEB_READ_D) dn += cb * z[gi];
+                if (flags & CHEB_READ_D) dn += cb * zo[u];
                 z[gi] = dn;
-                x[gi] = (flags & CHEB_ACCUM) ? x[gi] + dn : dn;
+                x[gi] = (flags & CHEB_ACCUM) ? xo[u] + dn : dn;
             }
         } else {
-            for (int e = tt; e < ND; e += NF) z[cid * ND + e] = sR[lc][e];
+#pragma unroll
+            for (int u = 0; u < N; ++u) z[cid * ND + tt + u * NF] = sR[lc][tt + u * NF];
         }
     }
     if (FUSE) {
@@ -368,7 +416,8 @@ k_massinv(const T *__restrict__ rin, T *__restrict__ z, const T *__restrict__ wg
     const int64_t cid = (int64_t)wg * CPB + lc;
     const bool active = slot && cid < n_cells;
 
-    for (int e = t; e < NF; e += blockDim.x) sB[e] = (T)(INV ? Fm[e] : Fm[(e % N) * N + e / N]);
+    static_assert(NF <= Cfg<N>::NT, "one table entry per thread");
+    const T fb = t < NF ? (T)(INV ? Fm[t] : Fm[(t % N) * N + t / N]) : T(0);
     T mq[N], v[N], w[N], rp[N];
     double acc_rr = 0.0, acc_rz = 0.0;
     double pq = 0.0;
@@ -381,22 +430,40 @@ k_massinv(const T *__restrict__ rin, T *__restrict__ z, const T *__restrict__ wg
             pq = sc[1];
         }
     }
-    if (FUSE && active) {
-        const T al = (T)(pq != 0.0 ? sc[0] / pq : 0.0);
-        for (int e = tt; e < ND; e += NF) {
-            const int64_t gi = cid * ND + e;
-            const T rv = rw[gi] - al * q[gi];
-            x[gi] += al * p[gi];
-            rw[gi] = rv;
-            sR[lc][e] = rv;
-            acc_rr += (double)rv * (double)rv;
-        }
-    } else if (active) {
-        for (int e = tt; e < ND; e += NF) sR[lc][e] = r[cid * ND + e];
-    }
+    // every global load of the cell at once: the residual (and for the CG
+    // step x, p and q) and the pencil's weights
+    T rv[N], xv[N], pv[N], qv[N];
     if (active) {
 #pragma unroll
+        for (int u = 0; u < N; ++u) {
+            const int64_t gi = cid * ND + tt + u * NF;
+            rv[u] = r[gi];
+            if (FUSE) {
+                xv[u] = x[gi];
+                pv[u] = p[gi];
+                qv[u] = q[gi];
+            }
+        }
+#pragma unroll
         for (int m = 0; m < N; ++m) mq[m] = wgt[cid * wstride + a + N * b + NF * m];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if (t < NF) sB[t] = fb;
+    if (FUSE && active) {
+        const T al = (T)(pq != 0.0 ? sc[0] / pq : 0.0);
+#pragma unroll
+        for (int u = 0; u < N; ++u) {
+            const int e = tt + u * NF;
+            const int64_t gi = cid * ND + e;
+            const T rn = rv[u] - al * qv[u];
+            x[gi] = xv[u] + al * pv[u];
+            rw[gi] = rn;
+            sR[lc][e] = rn;
+            acc_rr += (double)rn * (double)rn;
+        }
+    } else if (active) {
+#pragma unroll
+        for (int u = 0; u < N; ++u) sR[lc][tt + u * NF] = rv[u];
     }
     __syncthreads();
     // B^{-T} along x: thread (j=a, l=b); rp keeps the residual pencil, at the
@@ -499,8 +566,10 @@ k_massinv(const T *__restrict__ rin, T *__restrict__ z, const T *__restrict__ wg
         for (int i = 0; i < N; ++i) sR[lc][i + N * a + NF * b] = w[i];
     }
     __syncthreads();
-    if (active)
-        for (int e = tt; e < ND; e += NF) z[cid * ND + e] = sR[lc][e];
+    if (active) {
+#pragma unroll
+        for (int u = 0; u < N; ++u) z[cid * ND + tt + u * NF] = sR[lc][tt + u * NF];
+    }
     if (FUSE) {
         __shared__ double sh2[2 * (Cfg<N>::NT / 64)];
         block_sum2<Cfg<N>::NT>(acc_rz, acc_rr, sh2);
