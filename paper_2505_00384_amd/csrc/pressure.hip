@@ -461,19 +461,36 @@ k_grad(const double *__restrict__ p, double *__restrict__ u3, int64_t nt,
     const int wg = xcd * q8 + (xcd < r8 ? xcd : r8) + bid / NXCD;
     const int64_t sl = (int64_t)wg * CPB + lc;
     const bool act = slot && sl < n_cells;
-    const int32_t *rec = visit + (act ? sl : 0) * 8;
-    const int64_t cid = act ? rec[0] : 0;
+    // the 32-byte record in two 16-byte loads (slot 0's for idle threads)
+    const int4 *rec4 = reinterpret_cast<const int4 *>(visit + (act ? sl : 0) * 8);
+    const int4 r0 = rec4[0], r1 = rec4[1];
+    const int32_t nbr6[6] = {r0.y, r0.z, r0.w, r1.x, r1.y, r1.z};
+    const int64_t cid = act ? r0.x : 0;
 
-    for (int e = t; e < NF; e += blockDim.x) sB[e] = T->B[e];
-    if (act)
-        for (int e = tt; e < ND; e += NF) sP[lc][e] = p[cid * ND + e];
-    // the neighbours' face layers (one value per lane and face), requested
-    // before the cell part so that their latency overlaps it
-    double nbv[6];
+    // one batch of loads (one memory round trip): the 1-D table, the cell's
+    // values, the neighbours' face layers (one value per lane and face; a
+    // missing neighbour reads the own cell and is dropped) and the first
+    // face's outward ds n; they are requested before the cell part so that
+    // their latency overlaps it
+    static_assert(NF <= PCfg<N, GRAD_T>::NT, "one table entry per thread");
+    const double fbv = t < NF ? T->B[t] : 0.0;
+    double pv[N], nbv[6], fnx[3];
+#pragma unroll
+    for (int u = 0; u < N; ++u) pv[u] = p[cid * ND + tt + u * NF];
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
-        const int32_t nb = act ? rec[1 + f] : -1;
-        nbv[f] = nb >= 0 ? p[(int64_t)nb * ND + lay<N>(f >> 1, (f & 1) ? 0 : N - 1, a, b)] : 0.0;
+        const int32_t nb = act ? nbr6[f] : -1;
+        const int64_t src = nb >= 0 ? (int64_t)nb : cid;
+        const double v = p[src * ND + lay<N>(f >> 1, (f & 1) ? 0 : N - 1, a, b)];
+        nbv[f] = nb >= 0 ? v : 0.0;
+    }
+#pragma unroll
+    for (int ec = 0; ec < 3; ++ec) fnx[ec] = fn[(cid * 6 + 0) * 3 * NF + tt + ec * NF];
+    __builtin_amdgcn_sched_barrier(0);
+    if (t < NF) sB[t] = fbv;
+    if (act) {
+#pragma unroll
+        for (int u = 0; u < N; ++u) sP[lc][tt + u * NF] = pv[u];
     }
     __syncthreads();
     const LaneB<N> LB(sB, a, b);
@@ -498,15 +515,22 @@ k_grad(const double *__restrict__ p, double *__restrict__ u3, int64_t nt,
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
         const int d = f >> 1, s = f & 1;
-        const int32_t nb = act ? rec[1 + f] : -1;
+        const int32_t nb = act ? nbr6[f] : -1;
+        // this face's ds n, and the next face's requested now
+        double fcur[3];
+#pragma unroll
+        for (int ec = 0; ec < 3; ++ec) fcur[ec] = fnx[ec];
+        if (f < 5) {
+#pragma unroll
+            for (int ec = 0; ec < 3; ++ec) fnx[ec] = fn[(cid * 6 + f + 1) * 3 * NF + tt + ec * NF];
+        }
         if (nb >= 0) sL[lc][tt] = nbv[f];
         __syncthreads();
         if (act) {
             const double po = trace_at<N>(LB, sP[lc], d, s ? N - 1 : 0);
             double ph = po;
             if (nb >= 0) ph = 0.5 * (po + trace_at2<N>(LB, sL[lc]));
-            const double *fnc = fn + (cid * 6 + f) * 3 * NF + tt;
-            for (int ec = 0; ec < 3; ++ec) sG[lc][ec][tt] = tau * ph * fnc[ec * NF];
+            for (int ec = 0; ec < 3; ++ec) sG[lc][ec][tt] = tau * ph * fcur[ec];
         }
         __syncthreads();
         if (act)
@@ -555,13 +579,50 @@ k_div(const double *__restrict__ u3, double *__restrict__ qv, int64_t nt,
     const int wg = xcd * q8 + (xcd < r8 ? xcd : r8) + bid / NXCD;
     const int64_t sl = (int64_t)wg * CPB + lc;
     const bool act = slot && sl < n_cells;
-    const int32_t *rec = visit + (act ? sl : 0) * 8;
-    const int64_t cid = act ? rec[0] : 0;
+    // the 32-byte record in two 16-byte loads (slot 0's for idle threads)
+    const int4 *rec4 = reinterpret_cast<const int4 *>(visit + (act ? sl : 0) * 8);
+    const int4 r0 = rec4[0], r1 = rec4[1];
+    const int32_t nbr6[6] = {r0.y, r0.z, r0.w, r1.x, r1.y, r1.z};
+    const int64_t cid = act ? r0.x : 0;
 
-    for (int e = t; e < NF; e += blockDim.x) sB[e] = T->B[e];
-    if (act)
+    // one batch of loads (one memory round trip): the 1-D table, the cell's
+    // three velocity components, the neighbours' face layers of the three
+    // (a missing neighbour reads the own cell and is dropped) and the first
+    // face's ds n and h rho factors
+    static_assert(NF <= PCfg<N, DIV_T>::NT, "one table entry per thread");
+    const double fbv = t < NF ? T->B[t] : 0.0;
+    double uv[3][N], nbu[6][3], fnx[3], fhx[2];
+#pragma unroll
+    for (int ec = 0; ec < 3; ++ec)
+#pragma unroll
+        for (int u = 0; u < N; ++u) uv[ec][u] = u3[ec * nt + cid * ND + tt + u * NF];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        const int32_t nb = act ? nbr6[f] : -1;
+        const int64_t src = nb >= 0 ? (int64_t)nb : cid;
+        const int64_t o = src * ND + lay<N>(f >> 1, (f & 1) ? 0 : N - 1, a, b);
+#pragma unroll
+        for (int ec = 0; ec < 3; ++ec) nbu[f][ec] = u3[ec * nt + o];
+    }
+    // ds n and the two h rho factors of face f (the neighbour's entry of a
+    // missing neighbour reads the own cell's and is not used)
+    auto face_data = [&](int f, double (&fo)[3], double (&ho)[2]) {
+        const int32_t nb = act ? nbr6[f] : -1;
+        const int64_t src = nb >= 0 ? (int64_t)nb : cid;
+#pragma unroll
+        for (int ec = 0; ec < 3; ++ec) fo[ec] = fn[(cid * 6 + f) * 3 * NF + tt + ec * NF];
+        ho[0] = fh[(cid * 6 + f) * NF + tt];
+        ho[1] = fh[(src * 6 + (nb >= 0 ? (f ^ 1) : f)) * NF + tt];
+    };
+    face_data(0, fnx, fhx);
+    __builtin_amdgcn_sched_barrier(0);
+    if (t < NF) sB[t] = fbv;
+    if (act) {
+#pragma unroll
         for (int ec = 0; ec < 3; ++ec)
-            for (int e = tt; e < ND; e += NF) sU[lc][ec][e] = u3[ec * nt + cid * ND + e];
+#pragma unroll
+            for (int u = 0; u < N; ++u) sU[lc][ec][tt + u * NF] = uv[ec][u];
+    }
     __syncthreads();
     const LaneB<N> LB(sB, a, b);
     // interior faces first, while all three velocity layers are in LDS:
@@ -573,25 +634,31 @@ k_div(const double *__restrict__ u3, double *__restrict__ qv, int64_t nt,
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
         const int d = f >> 1, s = f & 1;
-        const int32_t nb = act ? rec[1 + f] : -1;
+        const int32_t nb = act ? nbr6[f] : -1;
+        // this face's data, and the next face's requested now
+        double fcur[3], hcur[2];
+#pragma unroll
+        for (int ec = 0; ec < 3; ++ec) fcur[ec] = fnx[ec];
+        hcur[0] = fhx[0];
+        hcur[1] = fhx[1];
+        if (f < 5) face_data(f + 1, fnx, fhx);
         if (nb >= 0) {
-            const int64_t o = (int64_t)nb * ND + lay<N>(d, s ? 0 : N - 1, a, b);
-            for (int ec = 0; ec < 3; ++ec) sL[lc][ec][tt] = u3[ec * nt + o];
+#pragma unroll
+            for (int ec = 0; ec < 3; ++ec) sL[lc][ec][tt] = nbu[f][ec];
         }
         __syncthreads();
         if (act) {
             double g = 0.0;
             if (nb >= 0) {
-                const double *fnc = fn + (cid * 6 + f) * 3 * NF + tt;
                 double fo = 0.0, fnb = 0.0;
                 for (int ec = 0; ec < 3; ++ec) {
                     const double uo = trace_at<N>(LB, sU[lc][ec], d, s ? N - 1 : 0);
                     const double un = trace_at2<N>(LB, sL[lc][ec]);
-                    fo += uo * fnc[ec * NF];
-                    fnb += un * fnc[ec * NF];
+                    fo += uo * fcur[ec];
+                    fnb += un * fcur[ec];
                 }
-                fo *= fh[(cid * 6 + f) * NF + tt];
-                fnb *= fh[((int64_t)nb * 6 + (f ^ 1)) * NF + tt];
+                fo *= hcur[0];
+                fnb *= hcur[1];
                 g = tau * 0.5 * (fo + fnb);
             }
             sG[lc][tt] = g;
@@ -627,15 +694,25 @@ k_div(const double *__restrict__ u3, double *__restrict__ qv, int64_t nt,
 #pragma unroll
         for (int i = 0; i < N; ++i) Y[i] += Yf[i];
     if (DP) {
-        // D x: x at the Gauss points, times md, back to the nodes
-        if (act)
-            for (int e = tt; e < ND; e += NF) sU[lc][0][e] = xv[cid * ND + e];
+        // D x: x at the Gauss points, times md, back to the nodes (x and md
+        // requested together)
+        double xl[N], mdq[N];
+#pragma unroll
+        for (int u = 0; u < N; ++u) {
+            xl[u] = xv[cid * ND + tt + u * NF];
+            mdq[u] = md[cid * ND + a + N * b + NF * u];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        if (act) {
+#pragma unroll
+            for (int u = 0; u < N; ++u) sU[lc][0][tt + u * NF] = xl[u];
+        }
         __syncthreads();
         double xq[N], dx[N];
         to_gauss<N>(sU[lc][0], sF[lc], act, a, b, xq);
         if (act)
 #pragma unroll
-            for (int q = 0; q < N; ++q) xq[q] *= md[cid * ND + a + N * b + NF * q];
+            for (int q = 0; q < N; ++q) xq[q] *= mdq[q];
         interp_t<N>(sF[lc], act, a, b, xq, dx);
         if (act)
 #pragma unroll
