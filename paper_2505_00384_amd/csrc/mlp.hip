@@ -456,43 +456,122 @@ k_mlp_fused(int64_t n_cells, const double *__restrict__ w, double *__restrict__ 
     __shared__ __align__(16) uint16_t sH2[FT][HID + 8];
     __shared__ double sR[FT][ND];          // r_K, then BJ(r)_K
     __shared__ double sBS[FB][3][NF], sBL[FB][3][N], sBC[FB][4];
-    __shared__ double sS[FT], sW[FT], sh4[4];
+    __shared__ double sS[FT], sW[FT], sCf[FT], sh4[4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t c0 = (int64_t)blockIdx.x * FT;
+    constexpr int RPT = (ND + SUB - 1) / SUB;            // own values per thread
+    constexpr int FPT = (FT * LDX + NTH - 1) / NTH;      // feature slots per thread
+    constexpr int SPT = (FT * 3 * NF + NTH - 1) / NTH;   // eigenvector entries per thread
+    constexpr int LPT = (FT * 3 * N + NTH - 1) / NTH;    // eigenvalues per thread
+    constexpr int ZPT = (FT * ND + NTH - 1) / NTH;       // block-Jacobi outputs per thread
+    const int cl_r = tid / SUB, sub = tid % SUB;
+    const bool own_ok = c0 + cl_r < n_cells;
+    // First batch of loads, all in flight together with the partial sums of
+    // the scale below (every address valid; an unused entry reads element
+    // 0): the own values, the neighbour index and the coefficient feature of
+    // each of this thread's feature slots, the block-Jacobi tables.
+    double wv[RPT];
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+        const int e = sub + u * SUB;
+        wv[u] = w[(own_ok && e < ND) ? (c0 + cl_r) * ND + e : 0];
+    }
+    int32_t fnb[FPT];
+#pragma unroll
+    for (int u = 0; u < FPT; ++u) {
+        const int idx = tid + u * NTH, cl = idx / LDX, e = idx % LDX;
+        const int64_t c = c0 + cl;
+        const bool isn = idx < FT * LDX && c < n_cells && e >= ND && e < ND + 6 * NF;
+        const int32_t nbv = nbr[isn ? c * 6 + (e - ND) / NF : 0];
+        fnb[u] = isn ? nbv : -1;
+    }
+    const double cfv = coef[(tid < FT && c0 + tid < n_cells) ? c0 + tid : 0];
+    double tS[SPT], tL[LPT], tC = 0.0;
+    if constexpr (WBJ) {
+#pragma unroll
+        for (int u = 0; u < SPT; ++u) {
+            const int idx = tid + u * NTH, cl = idx / (3 * NF);
+            const bool ok = idx < FT * 3 * NF && c0 + cl < n_cells;
+            tS[u] = bjS[ok ? (c0 + cl) * 3 * NF + idx % (3 * NF) : 0];
+        }
+#pragma unroll
+        for (int u = 0; u < LPT; ++u) {
+            const int idx = tid + u * NTH, cl = idx / (3 * N);
+            const bool ok = idx < FT * 3 * N && c0 + cl < n_cells;
+            tL[u] = bjL[ok ? (c0 + cl) * 3 * N + idx % (3 * N) : 0];
+        }
+        tC = bjC[(tid < FT * 4 && c0 + tid / 4 < n_cells) ? (c0 + tid / 4) * 4 + tid % 4 : 0];
+    }
     // the Krylov vector's scale (the fixed-order sum the host repeats)
     const double sc = part ? 1.0 / sqrt(sum256(part, nbp, sh4)) : 1.0;
+    // second batch: the neighbours' face-layer values of the feature slots
+    // and, without the block-Jacobi solve here, the block-Jacobi output
+    double fval[FPT];
+#pragma unroll
+    for (int u = 0; u < FPT; ++u) {
+        const int idx = tid + u * NTH, e = idx % LDX;
+        const int f = (e - ND) / NF, t = (e - ND) % NF;
+        const int32_t nb = fnb[u];
+        int64_t a = 0;
+        if (nb >= 0) {
+            const int d = f >> 1, m = (f & 1) ? 0 : N - 1;   // the neighbour's touching layer
+            const int p = t % N, q = t / N;
+            int ijk[3];
+            ijk[d] = m;
+            ijk[d == 0 ? 1 : 0] = p;
+            ijk[d == 2 ? 1 : 2] = q;
+            a = (int64_t)nb * ND + ijk[0] + N * (ijk[1] + N * ijk[2]);
+        }
+        fval[u] = w[a];
+    }
+    double zv[ZPT];
+    if constexpr (!WBJ) {
+#pragma unroll
+        for (int u = 0; u < ZPT; ++u) {
+            const int idx = tid + u * NTH, cl = idx / ND;
+            zv[u] = z[(idx < FT * ND && c0 + cl < n_cells) ? (c0 + cl) * ND + idx % ND : 0];
+        }
+    }
     // r_K = sc w_K into LDS (and to vout), its RMS: SUB threads per cell
     {
-        const int cl = tid / SUB, sub = tid % SUB;
-        const int64_t c = c0 + cl;
         double sr = 0.0;
-        if (c < n_cells)
-            for (int e = sub; e < ND; e += SUB) {
-                const double v = w[c * ND + e] * sc;
-                sR[cl][e] = v;
-                if (vout) vout[c * ND + e] = v;
-                sr += v * v;
+        if (own_ok) {
+#pragma unroll
+            for (int u = 0; u < RPT; ++u) {
+                const int e = sub + u * SUB;
+                if (e < ND) {
+                    const double v = wv[u] * sc;
+                    sR[cl_r][e] = v;
+                    if (vout) vout[(c0 + cl_r) * ND + e] = v;
+                    sr += v * v;
+                }
             }
+        }
 #pragma unroll
         for (int o = SUB / 2; o > 0; o >>= 1) sr += __shfl_xor(sr, o, 64);
-        if (sub == 0) sS[cl] = sqrt(sr / ND);
+        if (sub == 0) sS[cl_r] = sqrt(sr / ND);
     }
+    if (tid < FT) sCf[tid] = cfv;
     // block-Jacobi tables of the workgroup's cells
     if constexpr (WBJ) {
-        for (int idx = tid; idx < FT * 3 * NF; idx += NTH) {
-            const int cl = idx / (3 * NF), e = idx % (3 * NF);
-            if (c0 + cl < n_cells) sBS[cl][e / NF][e % NF] = bjS[(c0 + cl) * 3 * NF + e];
+#pragma unroll
+        for (int u = 0; u < SPT; ++u) {
+            const int idx = tid + u * NTH, cl = idx / (3 * NF), e = idx % (3 * NF);
+            if (idx < FT * 3 * NF && c0 + cl < n_cells) sBS[cl][e / NF][e % NF] = tS[u];
         }
-        for (int idx = tid; idx < FT * 3 * N; idx += NTH) {
-            const int cl = idx / (3 * N), e = idx % (3 * N);
-            if (c0 + cl < n_cells) sBL[cl][e / N][e % N] = bjL[(c0 + cl) * 3 * N + e];
+#pragma unroll
+        for (int u = 0; u < LPT; ++u) {
+            const int idx = tid + u * NTH, cl = idx / (3 * N), e = idx % (3 * N);
+            if (idx < FT * 3 * N && c0 + cl < n_cells) sBL[cl][e / N][e % N] = tL[u];
         }
-        if (tid < FT * 4 && c0 + tid / 4 < n_cells)
-            sBC[tid / 4][tid % 4] = bjC[(c0 + tid / 4) * 4 + tid % 4];
+        if (tid < FT * 4 && c0 + tid / 4 < n_cells) sBC[tid / 4][tid % 4] = tC;
     }
     __syncthreads();
     // features, BF16
-    for (int idx = tid; idx < FT * LDX; idx += NTH) {
+#pragma unroll
+    for (int u = 0; u < FPT; ++u) {
+        const int idx = tid + u * NTH;
+        if (idx >= FT * LDX) break;
         const int cl = idx / LDX, e = idx % LDX;
         const int64_t c = c0 + cl;
         float fv = 0.f;
@@ -502,19 +581,9 @@ k_mlp_fused(int64_t n_cells, const double *__restrict__ w, double *__restrict__ 
             if (e < ND) {
                 v = sR[cl][e] * inv;
             } else if (e < ND + 6 * NF) {
-                const int f = (e - ND) / NF, t = (e - ND) % NF;
-                const int32_t nb = nbr[c * 6 + f];
-                if (nb >= 0) {
-                    const int d = f >> 1, m = (f & 1) ? 0 : N - 1;   // the neighbour's touching layer
-                    const int p = t % N, q = t / N;
-                    int ijk[3];
-                    ijk[d] = m;
-                    ijk[d == 0 ? 1 : 0] = p;
-                    ijk[d == 2 ? 1 : 2] = q;
-                    v = (w[(int64_t)nb * ND + ijk[0] + N * (ijk[1] + N * ijk[2])] * sc) * inv;
-                }
+                if (fnb[u] >= 0) v = (fval[u] * sc) * inv;
             } else {
-                v = sK > 0.0 ? coef[c] : 0.0;
+                v = sK > 0.0 ? sCf[cl] : 0.0;
             }
             fv = (float)v;
         }
@@ -527,11 +596,12 @@ k_mlp_fused(int64_t n_cells, const double *__restrict__ w, double *__restrict__ 
         double unused = 0.0;
         bj_cell_solve<N, double>(sR[lc], sBS[lc], sBL[lc], sBC[lc], tt % N, tt / N, active, unused);
     } else {
-        // BJ(r) from z, once the features have read r
+        // BJ(r) from z (loaded above), once the features have read r
         __syncthreads();
-        for (int idx = tid; idx < FT * ND; idx += NTH) {
-            const int cl = idx / ND, e = idx % ND;
-            if (c0 + cl < n_cells) sR[cl][e] = z[(c0 + cl) * ND + e];
+#pragma unroll
+        for (int u = 0; u < ZPT; ++u) {
+            const int idx = tid + u * NTH, cl = idx / ND;
+            if (idx < FT * ND && c0 + cl < n_cells) sR[cl][idx % ND] = zv[u];
         }
         __syncthreads();
     }
@@ -1022,12 +1092,15 @@ static hipError_t mlp_fused_n(hx_ctx *c, const double *w, const double *part, in
 {
     MlpState *s = c->mlp;
     const int64_t nwg = (c->n_cells + FT - 1) / FT;
-    if (nwg <= s->n_cu) {
-        hipLaunchKernelGGL((k_mlp_fused<N, true>), dim3((unsigned)nwg), dim3(64 * FW), 0, c->stream,
-                           c->n_cells, w, z, c->nbr, c->coef_feat, s->w1b, s->w2b, s->w3b,
-                           s->w + s->off_b1, s->w + s->off_b2, s->w + s->off_b3, c->bjS64, c->bjL64,
-                           c->bjC64, part, nbp, vout);
-        return hipGetLastError();
+    // (degrees 6 and 7 would spill registers in the one-launch form)
+    if constexpr (N <= 6) {
+        if (nwg <= s->n_cu) {
+            hipLaunchKernelGGL((k_mlp_fused<N, true>), dim3((unsigned)nwg), dim3(64 * FW), 0,
+                               c->stream, c->n_cells, w, z, c->nbr, c->coef_feat, s->w1b, s->w2b,
+                               s->w3b, s->w + s->off_b1, s->w + s->off_b2, s->w + s->off_b3,
+                               c->bjS64, c->bjL64, c->bjC64, part, nbp, vout);
+            return hipGetLastError();
+        }
     }
     hipError_t e = part ? launch_bj64_scaled(c, w, part, nbp, vout, z) : launch_bj64(c, w, z);
     if (e != hipSuccess) return e;
