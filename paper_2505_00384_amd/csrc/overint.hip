@@ -139,8 +139,20 @@ k_apply_q(const double *__restrict__ x, double *__restrict__ y, const double *__
 #pragma unroll
         for (int l = 0; l < N; ++l) w0[l] = w1[l] = w2[l] = 0.0;
         const double *cp = cell + cid * 7 * Q3 + qx + Q * qy;
+        // the point data of plane q + 1 are requested before plane q's
+        // arithmetic, so one plane's loads are always in flight
+        double nx[7];
+#pragma unroll
+        for (int k = 0; k < 7; ++k) nx[k] = cp[k * Q3];
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
+            double cd[7];
+#pragma unroll
+            for (int k = 0; k < 7; ++k) cd[k] = nx[k];
+            if (q + 1 < Q) {
+#pragma unroll
+                for (int k = 0; k < 7; ++k) nx[k] = cp[Q2 * (q + 1) + k * Q3];
+            }
             double u = 0.0, dz = 0.0, dy = 0.0, dx = 0.0;
 #pragma unroll
             for (int l = 0; l < N; ++l) {
@@ -149,9 +161,8 @@ k_apply_q(const double *__restrict__ x, double *__restrict__ y, const double *__
                 dy += tq<N>(q, l) * a1[l];
                 dx += tq<N>(q, l) * a2[l];
             }
-            const double *cq = cp + Q2 * q;
-            const double m = cq[0], gxx = cq[Q3], gxy = cq[2 * Q3], gxz = cq[3 * Q3],
-                         gyy = cq[4 * Q3], gyz = cq[5 * Q3], gzz = cq[6 * Q3];
+            const double m = cd[0], gxx = cd[1], gxy = cd[2], gxz = cd[3], gyy = cd[4], gyz = cd[5],
+                         gzz = cd[6];
             const double v = m * u;
             const double fx = gxx * dx + gxy * dy + gxz * dz;
             const double fy = gxy * dx + gyy * dy + gyz * dz;
