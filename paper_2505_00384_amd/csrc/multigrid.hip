@@ -169,7 +169,14 @@ void k_restrict8(const T *__restrict__ in, T *__restrict__ out,
     __shared__ T sA[CPB][2][ND];
     const int t = threadIdx.x;
     const int64_t c0 = (int64_t)blockIdx.x * CPB;
-    for (int e = t; e < 2 * NF; e += MG_T) sE[e / NF][e % NF] = (T)tab->Eh[e / NF][e % NF];
+    // the table entries requested together with the child indices
+    constexpr int EPT = (2 * NF + MG_T - 1) / MG_T;
+    T te[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+        const int e = t + u * MG_T;
+        te[u] = (T)tab->Eh[e < 2 * NF ? e / NF : 0][e < 2 * NF ? e % NF : 0];
+    }
     // x: item (cell lc, pair p = oy + 2 oz, pencil jl), one per thread; the
     // two children's pencils are requested before the barrier
     const int lc = t / (4 * NF), r = t - lc * 4 * NF, p = r / NF, jl = r - p * NF;
@@ -184,6 +191,11 @@ void k_restrict8(const T *__restrict__ in, T *__restrict__ out,
             v0[i] = x0[i];
             v1[i] = x1[i];
         }
+    }
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+        const int e = t + u * MG_T;
+        if (e < 2 * NF) sE[e / NF][e % NF] = te[u];
     }
     __syncthreads();
     if (act) {
@@ -238,8 +250,42 @@ __global__ __launch_bounds__(MG_T) void k_prolong8(const T *__restrict__ in, T *
     const int t = threadIdx.x;
     const int64_t cc = blockIdx.x;
     if (cc >= n_coarse) return;
-    for (int e = t; e < 2 * NF; e += MG_T) sE[e / NF][e % NF] = (T)tab->Eh[e / NF][e % NF];
-    for (int e = t; e < ND; e += MG_T) sC[e] = in[cc * ND + e];
+    // every load up front: the table, the coarse values, the eight child
+    // indices, then the fine values this thread adds to (their latency
+    // overlaps the z and y sweeps)
+    constexpr int EPT = (2 * NF + MG_T - 1) / MG_T, CPT = (ND + MG_T - 1) / MG_T,
+                  OPT = (8 * ND + MG_T - 1) / MG_T;
+    T te[EPT], tc[CPT];
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+        const int e = t + u * MG_T;
+        te[u] = (T)tab->Eh[e < 2 * NF ? e / NF : 0][e < 2 * NF ? e % NF : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+        const int e = t + u * MG_T;
+        tc[u] = in[cc * ND + (e < ND ? e : 0)];
+    }
+    const int4 *c4 = reinterpret_cast<const int4 *>(child8 + cc * 8);
+    const int4 k0 = c4[0], k1 = c4[1];
+    const int32_t kids[8] = {k0.x, k0.y, k0.z, k0.w, k1.x, k1.y, k1.z, k1.w};
+    T fo[OPT];
+#pragma unroll
+    for (int u = 0; u < OPT; ++u) {
+        const int idx = t + u * MG_T;
+        const int o = idx < 8 * ND ? idx / ND : 0, e = idx < 8 * ND ? idx - o * ND : 0;
+        fo[u] = out[(int64_t)kids[o] * ND + e];
+    }
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+        const int e = t + u * MG_T;
+        if (e < 2 * NF) sE[e / NF][e % NF] = te[u];
+    }
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+        const int e = t + u * MG_T;
+        if (e < ND) sC[e] = tc[u];
+    }
     __syncthreads();
     // z: (a, b, l) for oz = 0, 1
     for (int idx = t; idx < 2 * ND; idx += MG_T) {
@@ -264,7 +310,10 @@ __global__ __launch_bounds__(MG_T) void k_prolong8(const T *__restrict__ in, T *
     }
     __syncthreads();
     // x: (i, j, l) of octant o = ox + 2 p, added to the child
-    for (int idx = t; idx < 8 * ND; idx += MG_T) {
+#pragma unroll
+    for (int u = 0; u < OPT; ++u) {
+        const int idx = t + u * MG_T;
+        if (idx >= 8 * ND) break;
         const int o = idx / ND, e = idx - o * ND;
         const int i = e % N, jl = e / N;
         const T *E = sE[o & 1] + i * N;
@@ -272,7 +321,7 @@ __global__ __launch_bounds__(MG_T) void k_prolong8(const T *__restrict__ in, T *
         T s = 0;
 #pragma unroll
         for (int a = 0; a < N; ++a) s += E[a] * src[a + N * jl];
-        out[(int64_t)child8[cc * 8 + o] * ND + e] += s;
+        out[(int64_t)kids[o] * ND + e] = fo[u] + s;
     }
 }
 
