@@ -211,7 +211,8 @@ __device__ __forceinline__ void apply_body(
     const T *__restrict__ cell, const T *__restrict__ face, const T *__restrict__ acell,
     const T *__restrict__ kk, const T *__restrict__ aface, const T *__restrict__ fcon,
     const int32_t *__restrict__ visit, int n_cells, int wg, int bid, double *__restrict__ dpart,
-    T (&sU)[Cfg<N>::CPW][Cfg<N>::ND], T (&sG)[Cfg<N>::CPW][Cfg<N>::GS])
+    T (&sU)[Cfg<N>::CPW][Cfg<N>::ND], T (&sG)[Cfg<N>::CPW][Cfg<N>::GS],
+    T (&sXd)[DOT ? Cfg<N>::CPW : 1][DOT ? Cfg<N>::ND : 1])
 {
     constexpr bool DO_CELL = PART != 2, DO_FACE = PART != 1;
     constexpr int NF = Cfg<N>::NF, ND = Cfg<N>::ND, LPC = Cfg<N>::LPC, CPW = Cfg<N>::CPW;
@@ -283,7 +284,10 @@ __device__ __forceinline__ void apply_body(
 #pragma unroll
     for (int k = 0; k < XL; ++k) {
         const int e = ln + k * LPC;
-        if (valid && e < ND) U[e] = xv[k];
+        if (valid && e < ND) {
+            U[e] = xv[k];
+            if constexpr (DOT) sXd[cs][e] = xv[k];   // kept for x.(A x)
+        }
     }
 
     // quadrature-point data of this lane's z pencil, streamed once: the
@@ -712,12 +716,13 @@ __device__ __forceinline__ void apply_body(
         for (int i = 0; i < N; ++i) y[o + i] = bvec ? bvec[o + i] - Y[i] : Y[i];
     }
     // x.(A x) of the wave's cells (fixed-order wave sum), for CG's p.q; the
-    // lane's input pencil is read again (it was read at the start, so it is
-    // likely in L2) rather than kept in registers through the kernel
-    if (DOT) {
+    // lane's input pencil comes from the copy of the input cells kept in LDS
+    // (registers through the kernel would spill, and a second read from
+    // memory misses the L2 on large meshes)
+    if constexpr (DOT) {
         double acc = 0.0;
         if (cl) {
-            const T *xo = x + cid * ND + N * a + NF * b;
+            const T *xo = &sXd[cs][N * a + NF * b];
 #pragma unroll
             for (int i = 0; i < N; ++i) acc += (double)xo[i] * (double)Y[i];
         }
@@ -743,6 +748,7 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
     constexpr int ND = Cfg<N>::ND, CPW = Cfg<N>::CPW, GS = Cfg<N>::GS;
     __shared__ T sU[CPW][ND];
     __shared__ T sG[CPW][GS];
+    __shared__ T sXd[DOT ? CPW : 1][DOT ? ND : 1];   // the input cells (CG variant)
     // contiguous ranges of the traversal per XCD (workgroups are dealt
     // round-robin to the XCDs)
     const int bid = blockIdx.x;
@@ -752,13 +758,13 @@ k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ bvec,
         const bool waff = visit[(int64_t)wg * CPW * 8 + 7] & 1;
         if (waff)
             apply_body<N, T, DOT, PART, true>(x, y, bvec, cell, face, acell, kk, aface, fcon, visit,
-                                              n_cells, wg, bid, dpart, sU, sG);
+                                              n_cells, wg, bid, dpart, sU, sG, sXd);
         else
             apply_body<N, T, DOT, PART, false>(x, y, bvec, cell, face, acell, kk, aface, fcon, visit,
-                                               n_cells, wg, bid, dpart, sU, sG);
+                                               n_cells, wg, bid, dpart, sU, sG, sXd);
     } else {
         apply_body<N, T, DOT, PART, MODE == 1>(x, y, bvec, cell, face, acell, kk, aface, fcon, visit,
-                                               n_cells, wg, bid, dpart, sU, sG);
+                                               n_cells, wg, bid, dpart, sU, sG, sXd);
     }
 }
 
