@@ -468,6 +468,32 @@ __global__ void k_cg_pt(int64_t n, const T *__restrict__ z, T *p, const double *
     p[i] = z[i] + bt * p[i];
 }
 
+// p = z + beta p with beta = new r.z / sc[cur]: every workgroup sums the
+// fused step's nb partial sums of r.z (row 0 of part) in the same fixed
+// order; workgroup 0 also sums r.r (row 1) and writes the new r.z to
+// sc[2 - cur] (the slot no workgroup reads here), r.r to sc[3] and, when
+// host is given (device view of pinned memory), to *host.  256 threads.
+template <typename T>
+__global__ void __launch_bounds__(256) k_cg_pt_red(int64_t n, const T *__restrict__ z, T *p,
+                                                   const double *__restrict__ part, int nb, int ld,
+                                                   double *sc, int cur, double *host)
+{
+    __shared__ double sh[4];
+    const double rz = sum256(part, nb, sh);
+    const double old = sc[cur];
+    const T bt = (T)(old != 0.0 ? rz / old : 0.0);
+    if (blockIdx.x == 0) {
+        const double rr = sum256(part + ld, nb, sh);
+        if (threadIdx.x == 0) {
+            sc[2 - cur] = rz;
+            sc[3] = rr;
+            if (host) *host = rr;
+        }
+    }
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = z[i] + bt * p[i];
+}
+
 // stage 2 of a fused CG step whose z is final: workgroup 0 sums r.z (row 0
 // of part), workgroup 1 r.r (row 1); then beta = new r.z / old r.z goes to
 // sc[5] and the new r.z to sc[2] and sc[0] (so no separate shift is needed),
@@ -686,12 +712,19 @@ hipError_t reduce_parts(hx_ctx *c, const double *part, int64_t n, double *dst)
 // cell mass blocks, a diagonal kind, or the Chebyshev polynomial after the
 // update): x += a p, r -= a q, z = M^{-1} r, sc[2] = r.z, sc[3] = r.r.
 // npq > 0: p.q is the sum of the operator's npq partial sums in c->pqpart.
+// lp (may be null): the loop's state; the step kernels read the current r.z
+// from slot lp->cur of sc, and with p.q from the operator's partial sums,
+// at most 8,192 partial sums of the step and a final z the sums are left to
+// the direction update (CG_DEFERRED).
 template <typename T>
-hipError_t cg_step_pc(hx_ctx *c, int pc, T *x, T *r, const T *p, const T *q, T *z, double *sc,
-                      double *host_rr, int *flags, int npq)
+hipError_t cg_step_pc(hx_ctx *c, int pc, T *x, T *r, const T *p, const T *q, T *z, double *sc_base,
+                      double *host_rr, int *flags, int npq, CgLoop *lp)
 {
     *flags = 0;
     const double *pqp = npq > 0 ? c->pqpart : nullptr;
+    // the current r.z in sc[0] for the step kernels (slot 2 only ever with
+    // p.q from partial sums, so the kernels do not read sc[1])
+    double *sc = sc_base + (lp ? lp->cur : 0);
     const int64_t n = c->n_dofs;
     const int ld = (int)c->n_cells + 1;
     const bool dbl = sizeof(T) == 8;
@@ -728,6 +761,11 @@ hipError_t cg_step_pc(hx_ctx *c, int pc, T *x, T *r, const T *p, const T *q, T *
         // one partial sum per block of the fused cell-block kernels: two stages
         e = reduce_parts(c, c->cgpart, nb, sc + 2);
         if (e == hipSuccess) e = reduce_parts(c, c->cgpart + ld, nb, sc + 3);
+    } else if (z_final && lp && pqp) {
+        // the direction update sums r.z and r.r itself
+        lp->nb = nb;
+        lp->host = host_rr;
+        *flags = CG_DEFERRED | (host_rr ? CG_RR_ON_HOST : 0);
     } else if (z_final) {
         // the sums, the direction coefficient and r.r for the host in one launch
         hipLaunchKernelGGL(k_red_cg, dim3(2), dim3(RT), 0, c->stream, c->cgpart, nb, ld, sc, host_rr);
@@ -763,9 +801,16 @@ hipError_t cg_step_pc(hx_ctx *c, int pc, T *x, T *r, const T *p, const T *q, T *
 }
 
 template <typename T>
-hipError_t cg_step_p(hx_ctx *c, const T *z, T *p, double *sc, int flags)
+hipError_t cg_step_p(hx_ctx *c, const T *z, T *p, double *sc, int flags, CgLoop *lp)
 {
     const int64_t n = c->n_dofs;
+    if (flags & CG_DEFERRED) {
+        hipLaunchKernelGGL(k_cg_pt_red<T>, dim3(nb256(n)), dim3(256), 0, c->stream, n, z, p,
+                           (const double *)c->cgpart, lp->nb, (int)c->n_cells + 1, sc, lp->cur,
+                           lp->host);
+        lp->cur = 2 - lp->cur;
+        return hipGetLastError();
+    }
     const int ready = (flags & CG_BETA_READY) ? 1 : 0;
     hipLaunchKernelGGL(k_cg_pt<T>, dim3(nb256(n)), dim3(256), 0, c->stream, n, z, p, sc, ready);
     if (!ready) hipLaunchKernelGGL(k_shift, dim3(1), dim3(64), 0, c->stream, sc);
@@ -773,22 +818,22 @@ hipError_t cg_step_p(hx_ctx *c, const T *z, T *p, double *sc, int flags)
 }
 
 hipError_t cg_step_pc64(hx_ctx *c, int pc, double *x, double *r, const double *p, const double *q,
-                        double *z, double *sc, double *host_rr, int *flags, int npq)
+                        double *z, double *sc, double *host_rr, int *flags, int npq, CgLoop *lp)
 {
-    return cg_step_pc<double>(c, pc, x, r, p, q, z, sc, host_rr, flags, npq);
+    return cg_step_pc<double>(c, pc, x, r, p, q, z, sc, host_rr, flags, npq, lp);
 }
 hipError_t cg_step_pc32(hx_ctx *c, int pc, float *x, float *r, const float *p, const float *q,
-                        float *z, double *sc, int *flags, int npq)
+                        float *z, double *sc, int *flags, int npq, CgLoop *lp)
 {
-    return cg_step_pc<float>(c, pc, x, r, p, q, z, sc, nullptr, flags, npq);
+    return cg_step_pc<float>(c, pc, x, r, p, q, z, sc, nullptr, flags, npq, lp);
 }
-hipError_t cg_step_p64(hx_ctx *c, const double *z, double *p, double *sc, int flags)
+hipError_t cg_step_p64(hx_ctx *c, const double *z, double *p, double *sc, int flags, CgLoop *lp)
 {
-    return cg_step_p<double>(c, z, p, sc, flags);
+    return cg_step_p<double>(c, z, p, sc, flags, lp);
 }
-hipError_t cg_step_p32(hx_ctx *c, const float *z, float *p, double *sc, int flags)
+hipError_t cg_step_p32(hx_ctx *c, const float *z, float *p, double *sc, int flags, CgLoop *lp)
 {
-    return cg_step_p<float>(c, z, p, sc, flags);
+    return cg_step_p<float>(c, z, p, sc, flags, lp);
 }
 
 }  // namespace hx

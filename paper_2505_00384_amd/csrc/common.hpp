@@ -339,14 +339,26 @@ hipError_t launch_cg_bj64(hx_ctx *c, double *x, double *r, const double *p, cons
 hipError_t launch_cg_bj32(hx_ctx *c, float *x, float *r, const float *p, const float *q, float *z,
                           const double *sc, int *nblk, const double *pqp, int npq);
 // flags of a fused CG step: the direction coefficient is in sc[5] and the
-// new r.z already in sc[0] (no shift needed); r.r was written to host_rr
-constexpr int CG_BETA_READY = 1, CG_RR_ON_HOST = 2;
+// new r.z already in sc[0] (no shift needed); r.r was written (or, deferred,
+// will be written by the direction update) to host_rr; deferred: the
+// direction update sums r.z and r.r itself
+constexpr int CG_BETA_READY = 1, CG_RR_ON_HOST = 2, CG_DEFERRED = 4;
+// A CG loop's state between its fused step and its direction update: the
+// slot of sc (0 or 2) that holds the current r.z (with the deferred sums the
+// direction update reads it and writes the new r.z to the other slot, so no
+// workgroup overwrites a value others still read), the step's partial-sum
+// count and the host slot for r.r.
+struct CgLoop {
+    int cur = 0;
+    int nb = 0;
+    double *host = nullptr;
+};
 hipError_t cg_step_pc64(hx_ctx *c, int pc, double *x, double *r, const double *p, const double *q,
-                        double *z, double *sc, double *host_rr, int *flags, int npq);
+                        double *z, double *sc, double *host_rr, int *flags, int npq, CgLoop *lp);
 hipError_t cg_step_pc32(hx_ctx *c, int pc, float *x, float *r, const float *p, const float *q,
-                        float *z, double *sc, int *flags, int npq);
-hipError_t cg_step_p64(hx_ctx *c, const double *z, double *p, double *sc, int flags);
-hipError_t cg_step_p32(hx_ctx *c, const float *z, float *p, double *sc, int flags);
+                        float *z, double *sc, int *flags, int npq, CgLoop *lp);
+hipError_t cg_step_p64(hx_ctx *c, const double *z, double *p, double *sc, int flags, CgLoop *lp);
+hipError_t cg_step_p32(hx_ctx *c, const float *z, float *p, double *sc, int flags, CgLoop *lp);
 hipError_t cg32_step_p_dot(hx_ctx *c, int64_t n, const float *r, const float *z, double *sc);
 hipError_t blas_lincomb(hx_ctx *c, int64_t n, int m, const double *Z, int64_t ldz,
                         const double *y_dev, double *x);

@@ -119,17 +119,18 @@ hx_status inner_fp32(hx_ctx *c, int pc, const double *v, double *z, float *w32, 
     }
     HX_HIP(c, hipMemcpyAsync(p, zz, sizeof(float) * n, hipMemcpyDeviceToDevice, c->stream));
     HX_HIP(c, blas_dot32(c, n, r, zz, sc + 0));
+    CgLoop lp;   // the current r.z in sc[lp.cur]
     for (int it = 0; it < iters; ++it) {
         // p.q: partial sums left for the step kernel, or summed into sc[1]
         int npq = 0;
         HX_HIP(c, launch_apply32_dot(c, p, q, sc + 1, &npq));
         if (it + 1 == iters) {
-            HX_HIP(c, cg32_step_x(c, n, x, r, p, q, sc, npq > 0 ? c->pqpart : nullptr, npq));
+            HX_HIP(c, cg32_step_x(c, n, x, r, p, q, sc + lp.cur, npq > 0 ? c->pqpart : nullptr, npq));
             break;
         }
         int fl = 0;
-        HX_HIP(c, cg_step_pc32(c, pc, x, r, p, q, zz, sc, &fl, npq));
-        HX_HIP(c, cg_step_p32(c, zz, p, sc, fl));
+        HX_HIP(c, cg_step_pc32(c, pc, x, r, p, q, zz, sc, &fl, npq, &lp));
+        HX_HIP(c, cg_step_p32(c, zz, p, sc, fl, &lp));
     }
     HX_HIP(c, blas_cast32to64(c, n, x, z, nullptr));
     *count += iters;
@@ -310,6 +311,7 @@ hx_status solve_cg(hx_ctx *c, const hx_solve_params *prm, const double *b, doubl
     int it = 0, checked = 0;
     bool stop = false;
     hx_status err = HX_OK;
+    CgLoop lp;   // the current r.z in sc[lp.cur]
     // rel of step k, once its copy has landed
     auto check = [&](int k) -> bool {
         if (hipEventSynchronize(done[k % 2]) != hipSuccess) {
@@ -330,9 +332,9 @@ hx_status solve_cg(hx_ctx *c, const hx_solve_params *prm, const double *b, doubl
         t.rec(2, c->stream);
         t.rec(0, c->stream);
         int fl = 0;
-        if (hipSuccess != cg_step_pc64(c, prm->pc, x, r, p, q, z, sc, c->pin_dev + it % 2, &fl, npq)) { err = fail(c, HX_ERR_DEVICE, "CG: step"); break; }
+        if (hipSuccess != cg_step_pc64(c, prm->pc, x, r, p, q, z, sc, c->pin_dev + it % 2, &fl, npq, &lp)) { err = fail(c, HX_ERR_DEVICE, "CG: step"); break; }
         t.rec(3, c->stream);
-        if (hipSuccess != cg_step_p64(c, z, p, sc, fl)) { err = fail(c, HX_ERR_DEVICE, "CG: p update"); break; }
+        if (hipSuccess != cg_step_p64(c, z, p, sc, fl, &lp)) { err = fail(c, HX_ERR_DEVICE, "CG: p update"); break; }
         // |r|^2 for the host: written by the reduction itself, else copied
         if ((!(fl & CG_RR_ON_HOST) &&
              hipSuccess != hipMemcpyAsync(hr + it % 2, sc + 3, sizeof(double), hipMemcpyDeviceToHost,
