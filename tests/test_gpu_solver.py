@@ -77,11 +77,13 @@ def test_delayed_reorthogonalisation_matches_cgs2(terrain_small):
     """FGMRES with the second Gram-Schmidt pass delayed and fused (orth=1)
     against two plain passes per step (orth=0): both are CGS2, so the
     residual estimates agree to rounding, the iteration counts match, and both
-    meet the true-residual bar; across a restart too (restart 7)."""
+    meet the true-residual bar; across a restart too (restart 7), and with
+    more than 32 basis vectors (restart 48: the block dot takes two chunks of
+    vectors)."""
     hx = _hx()
     p, b, xs = terrain_small
     ctx = gpu_context(p)
-    for restart in (7, 30):
+    for restart in (7, 30, 48):
         out = {}
         for orth in (0, 1):
             x, info = ctx.solve(to_dev(b), params=hx.default_params(method=1, restart=restart,
