@@ -658,8 +658,8 @@ def main():
                          "each one's time and algorithmic bandwidth (for profilers)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
-              "decomposition is a design, not part of this build.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the library does "
+              "not shard the mesh across GPUs.", file=sys.stderr)
         sys.exit(2)
 
     import torch

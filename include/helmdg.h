@@ -84,7 +84,7 @@ hx_status hx_create(hx_ctx **out, int device, void *hip_stream);
 hx_status hx_destroy(hx_ctx *c);
 /* Message of the last failed call (never NULL; "" if none). */
 const char *hx_last_error(const hx_ctx *c);
-/* Highest polynomial degree this build supports. */
+/* Highest polynomial degree the library supports. */
 int hx_max_degree(void);
 
 /* ---------------------------------------------------------------------- */
