@@ -733,8 +733,23 @@ def main():
                                                          pc=hx.HX_PC_HELMHOLTZ_DIAG)),
         ]
         del y
+        # learned form: network trained on the periodic unit cube at the same
+        # degree with the library's own kernels, then used on every mesh
+        w_net, t_train, learned_form = None, None, []
+        if args.solves == "all":
+            from paper_2505_00384_amd import learned
+            t0 = time.time()
+            F, T = learned.generate_pairs(100000, seed=0, k=k, log=log)
+            ctx.set_network(learned.init_weights(ctx, seed=0))
+            learned.train(ctx, F, T, steps=3000, batch=2048, lr=1e-3, log=log, log_every=1000)
+            t_train = time.time() - t0
+            del F, T
+            w_net = ctx.get_network()
+            learned_form = [("learned_fgmres", hx.default_params(method=1, restart=30, rtol=1e-8,
+                                                                 pc=hx.HX_PC_LEARNED))]
         solve[f"terrain{args.nx}x{args.ny}x{args.nz}"] = solve_suite(
-            hx, ctx, b, torch, [] if args.solves == "multigrid" else forms + cg_forms, "C3")
+            hx, ctx, b, torch, [] if args.solves == "multigrid" else forms + cg_forms + learned_form,
+            "C3")
         # CG with the Chebyshev polynomial (degree 4) around block Jacobi, its
         # interval from 20 Lanczos steps on a random vector (timed apart)
         gen = torch.Generator(device=dev)
@@ -780,20 +795,13 @@ def main():
             ("fp64_fgmres_helmholtz_diag", hx.default_params(method=1, restart=30, rtol=1e-8,
                                                              max_iter=20000,
                                                              pc=hx.HX_PC_HELMHOLTZ_DIAG))]
-        # learned form: network trained on the periodic unit cube (Q4), then used here
-        from paper_2505_00384_amd import learned
-        t0 = time.time()
-        F, T = learned.generate_pairs(100000, seed=0, log=log)
-        ctx2.set_network(learned.init_weights(ctx2, seed=0))
-        learned.train(ctx2, F, T, steps=3000, batch=2048, lr=1e-3, log=log, log_every=1000)
-        t_train = time.time() - t0
-        del F, T
-        forms2.append(("learned_fgmres", hx.default_params(method=1, restart=30, rtol=1e-8,
-                                                           pc=hx.HX_PC_LEARNED)))
+        # the learned form with the network trained above
+        ctx2.set_network(w_net)
+        forms2 += learned_form
         solve["terrain32x8x16"] = solve_suite(hx, ctx2, b2, torch, forms2, "C2",
                                               keep=kept.setdefault("terrain32x8x16", {}))
         solve["learned_training_s"] = round(t_train, 2)
-        w = ctx2.get_network()
+        w = w_net
         solve["terrain32x8x16_refined"] = nonconforming_suite(hx, torch, dev, k)
         log(f"nonconforming: {solve['terrain32x8x16_refined']}")
         pressure["terrain32x8x16"] = pressure_suite(hx, ctx2, torch, "C2", [
