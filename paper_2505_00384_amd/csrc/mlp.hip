@@ -434,6 +434,28 @@ __device__ __forceinline__ void fused_layer(const uint16_t (*sA)[LDA], const uin
 
 constexpr int FW = 16;   // waves per workgroup of the fused kernel
 
+// offset inside the neighbour cell of face feature t of face f (the
+// neighbour's touching layer, tangential lexicographic order, lower
+// direction fastest), for every f * N^2 + t
+template <int N>
+struct FaceFeat {
+    int off[6 * N * N];
+    constexpr FaceFeat() : off()
+    {
+        for (int f = 0; f < 6; ++f)
+            for (int t = 0; t < N * N; ++t) {
+                const int d = f >> 1, m = (f & 1) ? 0 : N - 1;
+                int ijk[3] = {0, 0, 0};
+                ijk[d] = m;
+                ijk[d == 0 ? 1 : 0] = t % N;
+                ijk[d == 2 ? 1 : 2] = t / N;
+                off[f * N * N + t] = ijk[0] + N * (ijk[1] + N * ijk[2]);
+            }
+    }
+};
+template <int N>
+__device__ constexpr FaceFeat<N> kFaceFeat{};
+
 template <int N, bool WBJ>
 __global__ void __launch_bounds__(64 * FW)
 k_mlp_fused(int64_t n_cells, const double *__restrict__ w, double *__restrict__ z,
@@ -456,7 +478,7 @@ k_mlp_fused(int64_t n_cells, const double *__restrict__ w, double *__restrict__ 
     __shared__ __align__(16) uint16_t sH2[FT][HID + 8];
     __shared__ double sR[FT][ND];          // r_K, then BJ(r)_K
     __shared__ double sBS[FB][3][NF], sBL[FB][3][N], sBC[FB][4];
-    __shared__ double sS[FT], sW[FT], sCf[FT], sh4[4];
+    __shared__ double sS[FT], sInv[FT], sW[FT], sCf[FT], sh4[4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t c0 = (int64_t)blockIdx.x * FT;
     constexpr int RPT = (ND + SUB - 1) / SUB;            // own values per thread
@@ -476,7 +498,7 @@ k_mlp_fused(int64_t n_cells, const double *__restrict__ w, double *__restrict__ 
         const int e = sub + u * SUB;
         wv[u] = w[(own_ok && e < ND) ? (c0 + cl_r) * ND + e : 0];
     }
-    int32_t fnb[FPT];
+    int32_t fnb[FPT], foff[FPT];
 #pragma unroll
     for (int u = 0; u < FPT; ++u) {
         const int idx = tid + u * NTH, cl = idx / LDX, e = idx % LDX;
@@ -484,6 +506,7 @@ k_mlp_fused(int64_t n_cells, const double *__restrict__ w, double *__restrict__ 
         const bool isn = idx < FT * LDX && c < n_cells && e >= ND && e < ND + 6 * NF;
         const int32_t nbv = nbr[isn ? c * 6 + (e - ND) / NF : 0];
         fnb[u] = isn ? nbv : -1;
+        foff[u] = kFaceFeat<N>.off[isn ? e - ND : 0];
     }
     const double cfv = coef[(tid < FT && c0 + tid < n_cells) ? c0 + tid : 0];
     double tS[SPT], tL[LPT], tC = 0.0;
@@ -509,19 +532,9 @@ k_mlp_fused(int64_t n_cells, const double *__restrict__ w, double *__restrict__ 
     double fval[FPT];
 #pragma unroll
     for (int u = 0; u < FPT; ++u) {
-        const int idx = tid + u * NTH, e = idx % LDX;
-        const int f = (e - ND) / NF, t = (e - ND) % NF;
         const int32_t nb = fnb[u];
         int64_t a = 0;
-        if (nb >= 0) {
-            const int d = f >> 1, m = (f & 1) ? 0 : N - 1;   // the neighbour's touching layer
-            const int p = t % N, q = t / N;
-            int ijk[3];
-            ijk[d] = m;
-            ijk[d == 0 ? 1 : 0] = p;
-            ijk[d == 2 ? 1 : 2] = q;
-            a = (int64_t)nb * ND + ijk[0] + N * (ijk[1] + N * ijk[2]);
-        }
+        if (nb >= 0) a = (int64_t)nb * ND + foff[u];
         fval[u] = w[a];
     }
     double zv[ZPT];
@@ -549,7 +562,11 @@ k_mlp_fused(int64_t n_cells, const double *__restrict__ w, double *__restrict__ 
         }
 #pragma unroll
         for (int o = SUB / 2; o > 0; o >>= 1) sr += __shfl_xor(sr, o, 64);
-        if (sub == 0) sS[cl_r] = sqrt(sr / ND);
+        if (sub == 0) {
+            const double sK = sqrt(sr / ND);
+            sS[cl_r] = sK;
+            sInv[cl_r] = sK > 0.0 ? 1.0 / sK : 0.0;
+        }
     }
     if (tid < FT) sCf[tid] = cfv;
     // block-Jacobi tables of the workgroup's cells
@@ -576,7 +593,7 @@ k_mlp_fused(int64_t n_cells, const double *__restrict__ w, double *__restrict__ 
         const int64_t c = c0 + cl;
         float fv = 0.f;
         if (c < n_cells && e < NIN) {
-            const double sK = sS[cl], inv = sK > 0.0 ? 1.0 / sK : 0.0;
+            const double sK = sS[cl], inv = sInv[cl];
             double v = 0.0;
             if (e < ND) {
                 v = sR[cl][e] * inv;
