@@ -58,6 +58,7 @@ def _close(a, b, tol, floor=0.0):
 CASES = [(name, mk, k) for (name, mk) in TINY for k in (1, 2)] + [
     ("terrain-4x2x3-g4", lambda: si.terrain_mesh(4, 2, 3, g=4), 4),
     ("wavy-2-g3", lambda: si.wavy_cube_mesh(2, 3), 3),
+    ("terrain-3x2x2-g4", lambda: si.terrain_mesh(3, 2, 2, g=4), 6),
 ]
 
 
