@@ -34,8 +34,12 @@ def bf16_round(a) -> np.ndarray:
     return out
 
 
-def unpack(params: np.ndarray, n_in=276, hidden=256, n_out=125):
+def unpack(params: np.ndarray, n_in=276, hidden=256, n_out=None):
+    """[(W1, b1), (W2, b2), (W3, b3)] from the flat vector; n_out (the
+    cell's dof count) follows from the vector's length when not given."""
     p = np.asarray(params, dtype=np.float64)
+    if n_out is None:
+        n_out = (p.size - hidden * (n_in + 1) - hidden * (hidden + 1)) // (hidden + 1)
     shapes = [(hidden, n_in), (hidden, hidden), (n_out, hidden)]
     out, o = [], 0
     for (r, c) in shapes:

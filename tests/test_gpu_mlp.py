@@ -164,6 +164,31 @@ def test_learned_preconditioner_parity(terrain):
     assert np.linalg.norm(zr - zb) > 0.01 * np.linalg.norm(zb)      # the correction is not trivial
 
 
+@pytest.mark.parametrize("k", [2, 6])
+def test_learned_preconditioner_parity_other_degrees(k):
+    """The whole learned preconditioner at degree 2 (one launch: block
+    Jacobi inside the network kernel) and at degree 6 (two launches: block
+    Jacobi, then the network kernel) against the oracle's composition, on a
+    terrain channel of 16 cells."""
+    hx = _hx()
+    p = problem(si.terrain_mesh(4, 2, 2, g=4), k, coef="terrain")
+    ctx = gpu_context(p)
+    try:
+        n = k + 1
+        w = si.mlp_init(13, n_in=n ** 3 + 6 * n * n + 1, n_out=n ** 3, out_scale=0.5)
+        ctx.set_network(w)
+        r = si.rhs_terrain(3)(*p.dof_coords()) + 0.2 * si.random_vector(p.n_dofs, 8)
+        z = ctx.apply_preconditioner(to_dev(r), kind=hx.HX_PC_LEARNED).cpu().numpy()
+        zr = mlp.precondition(p, w.astype(np.float64), r, _oracle_coef(p))
+        zb = p.bj_apply(r)
+        print(f"[learned] k={k}: |z - zr| / |zr - zb| = "
+              f"{np.linalg.norm(z - zr) / np.linalg.norm(zr - zb):.2e}", flush=True)
+        assert np.linalg.norm(z - zr) <= 2e-3 * np.linalg.norm(zr - zb) + 1e-11 * np.linalg.norm(zb)
+        assert np.linalg.norm(zr - zb) > 0.01 * np.linalg.norm(zb)
+    finally:
+        ctx.close()
+
+
 def test_learned_preconditioner_two_launch_form():
     """On 4,352 cells (272 workgroups of 16 cells, more than one per compute
     unit of a 256-CU device) block Jacobi and the network kernel run as two
