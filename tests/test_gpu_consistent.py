@@ -15,6 +15,7 @@ pytestmark = pytest.mark.gpu
 CASES = [(name, mk, k) for (name, mk) in TINY for k in (1, 2)] + [
     ("terrain-4x2x3-g4", lambda: si.terrain_mesh(4, 2, 3, g=4), 4),
     ("wavy-2-g3", lambda: si.wavy_cube_mesh(2, 3), 3),
+    ("terrain-2x1x2-g4", lambda: si.terrain_mesh(2, 1, 2, g=4), 6),
 ]
 
 
