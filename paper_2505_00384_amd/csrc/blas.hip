@@ -559,13 +559,17 @@ hipError_t blas_dcgs(hx_ctx *c, int64_t n, int j, double *V, int64_t ldv, double
                      double *host_out, bool scale, int *nb_out)
 {
     if (j < 0 || j >= 64) return hipErrorInvalidValue;
-    const int64_t want = (n + RT * 4 - 1) / (RT * 4);
+    // four elements per thread, or one on small systems (whose few
+    // workgroups would otherwise be latency bound)
+    int64_t want = (n + RT * 4 - 1) / (RT * 4);
+    if (want < 256) want = (n + RT - 1) / RT;
     const int nb = (int)(want < 1 ? 1 : (want > DC_LD ? DC_LD : want));
     // the dot's vectors in as few chunks of at most DMC as possible, each
     // padded to a multiple of 4
     const int nch = (j + 1 + DMC - 1) / DMC;
     const int per = (j + 1 + nch - 1) / nch;
-    const int64_t want2 = (n + RT * 2 - 1) / (RT * 2);
+    int64_t want2 = (n + RT * 2 - 1) / (RT * 2);
+    if (want2 < 256) want2 = (n + RT - 1) / RT;
     const int nb2 = (int)(want2 < 1 ? 1 : (want2 > RED_MAX ? RED_MAX : want2));
     double *hp = host_out ? host_out + FG_PART : nullptr;
     double *t = V + (int64_t)j * ldv;
