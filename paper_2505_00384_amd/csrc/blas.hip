@@ -13,9 +13,12 @@ constexpr int RT = 256;          // threads of a reduction block
 constexpr int RED_MAX = 1024;    // max stage-1 blocks
 constexpr int MC = 8;            // vectors per block-dot pass
 
+// eight elements per thread, or two on small systems (whose few blocks
+// would otherwise be latency bound); at most RED_MAX
 inline int red_blocks(int64_t n)
 {
     int64_t b = (n + RT * 8 - 1) / (RT * 8);
+    if (b < 256) b = (n + RT * 2 - 1) / (RT * 2);
     if (b < 1) b = 1;
     if (b > RED_MAX) b = RED_MAX;
     return (int)b;
@@ -751,6 +754,7 @@ hipError_t cg_step_pc(hx_ctx *c, int pc, T *x, T *r, const T *p, const T *q, T *
             dinv = dbl ? (const T *)(c->dg64 + (int64_t)w * n) : (const T *)(c->dg32 + (int64_t)w * n);
         }
         nb = red_blocks(n);
+        if (nb > ld) nb = ld;   // rows of c->cgpart (n_cells + 1 partial sums)
         // the FP32 V-cycle reads r rounded to FP32 from its level vector
         float *r32 = nullptr;
         if constexpr (sizeof(T) == 8)
