@@ -219,6 +219,23 @@ __global__ void k_weights_to_bf16(int64_t n, const float *__restrict__ w, int ro
     (void)n;
 }
 
+// fp32 [rows][cols] -> bf16 in the fused kernel's fragment order: for
+// column tile ct (16 output columns), k-step s (32 inputs) and lane l the
+// 8 values W[16 ct + l % 16][32 s + 8 (l / 16) .. + 7] sit at
+// ((ct ks + s) 64 + l) 8, so that one wave's fragment load is 1 KB in a
+// row and its whole slice of a layer is contiguous; rows past rows and
+// inputs past cols are zero
+__global__ void k_weights_frag(const float *__restrict__ w, int rows, int cols, int ks, uint16_t *out)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= (int64_t)((rows + 15) / 16) * ks * 512) return;
+    const int e = (int)(i & 7), lane = (int)((i >> 3) & 63);
+    const int64_t blk = i >> 9;
+    const int s = (int)(blk % ks), ct = (int)(blk / ks);
+    const int r = ct * 16 + (lane & 15), k = s * 32 + (lane >> 4) * 8 + e;
+    out[i] = (r < rows && k < cols) ? f2bf(w[(int64_t)r * cols + k]) : (uint16_t)0;
+}
+
 // fp32 [B][n_in] -> bf16 [B][ld]
 __global__ void k_pack(int64_t Bn, int n_in, int ld, const float *__restrict__ x, uint16_t *out)
 {
@@ -397,38 +414,39 @@ k_add_correction(int nd, const float *__restrict__ o, double *z)
 // + 7] and B[k][n = l % 16] likewise, and receives C[4 (l / 16) + q][l % 16].
 constexpr int FT = 16;   // cells per workgroup of the fused kernel
 
-template <int K, int NT, int LDA, int LDB>
-__device__ __forceinline__ void fused_layer(const uint16_t (*sA)[LDA], const uint16_t *__restrict__ W,
-                                            int n_rows, int ct0, int lane, f32x4 (&acc)[NT])
+// One wave's weight fragments of its NT column tiles over all KS k-steps
+// from a layer in fragment order (n_tiles column tiles), issued together
+// without branches: a tile at or past n_tiles reads the last one (its
+// results are never stored)
+template <int KS, int NT>
+__device__ __forceinline__ void layer_weights(const uint16_t *__restrict__ P, int n_tiles, int ct0,
+                                              int lane, uint4 (&fb)[KS][NT])
 {
-    // k-steps, and k-steps per chunk of weight loads (at most 32 fragments
-    // of 16 bytes in flight per lane)
-    constexpr int KS = K / 32, CH0 = 32 / NT > 1 ? 32 / NT : 1, CH = CH0 < KS ? CH0 : KS;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const int ct = min(ct0 + j, n_tiles - 1);
+            fb[s][j] = *(const uint4 *)(P + ((int64_t)(ct * KS + s) * 64 + lane) * 8);
+        }
+    }
+}
+
+// acc[j] = (16 rows of sA) x (column tile j of the weights in fb)
+template <int K, int NT, int LDA>
+__device__ __forceinline__ void layer_mfma(const uint16_t (*sA)[LDA], const uint4 (&fb)[K / 32][NT],
+                                           int lane, f32x4 (&acc)[NT])
+{
     const int rr = lane & 15, kq = (lane >> 4) * 8;
 #pragma unroll
     for (int j = 0; j < NT; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int k0 = 0; k0 < KS; k0 += CH) {
-        uint4 fb[CH][NT];
+    for (int s = 0; s < K / 32; ++s) {
+        const bf16x8 fa = __builtin_bit_cast(bf16x8, *(const uint4 *)&sA[rr][s * 32 + kq]);
 #pragma unroll
-        for (int s = 0; s < CH; ++s) {
-            if (k0 + s >= KS) break;
-#pragma unroll
-            for (int j = 0; j < NT; ++j) {
-                const int row = (ct0 + j) * 16 + rr;
-                fb[s][j] = row < n_rows ? *(const uint4 *)(W + (int64_t)row * LDB + (k0 + s) * 32 + kq)
-                                        : uint4{0u, 0u, 0u, 0u};
-            }
-        }
-#pragma unroll
-        for (int s = 0; s < CH; ++s) {
-            if (k0 + s >= KS) break;
-            const bf16x8 fa = __builtin_bit_cast(bf16x8, *(const uint4 *)&sA[rr][(k0 + s) * 32 + kq]);
-#pragma unroll
-            for (int j = 0; j < NT; ++j)
-                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, __builtin_bit_cast(bf16x8, fb[s][j]),
-                                                                 acc[j], 0, 0, 0);
-        }
+        for (int j = 0; j < NT; ++j)
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, __builtin_bit_cast(bf16x8, fb[s][j]),
+                                                             acc[j], 0, 0, 0);
     }
 }
 
@@ -460,8 +478,7 @@ template <int N, bool WBJ>
 __global__ void __launch_bounds__(64 * FW)
 k_mlp_fused(int64_t n_cells, const double *__restrict__ w, double *__restrict__ z,
             const int32_t *__restrict__ nbr, const double *__restrict__ coef,
-            const uint16_t *__restrict__ w1b, const uint16_t *__restrict__ w2b,
-            const uint16_t *__restrict__ w3b, const float *__restrict__ b1, const float *__restrict__ b2,
+            const uint16_t *__restrict__ wfr, const float *__restrict__ b1, const float *__restrict__ b2,
             const float *__restrict__ b3, const double *__restrict__ bjS,
             const double *__restrict__ bjL, const double *__restrict__ bjC,
             const double *__restrict__ part, int nbp, double *__restrict__ vout)
@@ -622,6 +639,34 @@ k_mlp_fused(int64_t n_cells, const double *__restrict__ w, double *__restrict__ 
         }
         __syncthreads();
     }
+    // Weight fragments.  The one-launch form (at most one workgroup per
+    // compute unit, so its register count costs no occupancy) loads them a
+    // layer ahead: layers 1 and 2 here, in flight during the norms below,
+    // layer 3 once layer 1's products are issued.  The other form loads
+    // each layer's just before its products (two workgroups per compute
+    // unit at the smaller degrees).
+    // The biases of the lane's output columns come first, so that waiting
+    // for them never waits for weights issued later.
+    constexpr int KS1 = LDX / 32, KS2 = HID / 32;
+    const uint16_t *__restrict__ w1f = wfr;
+    const uint16_t *__restrict__ w2f = wfr + (HID / 16) * KS1 * 512;
+    const uint16_t *__restrict__ w3f = w2f + (HID / 16) * KS2 * 512;
+    uint4 f1[KS1][PER], f2[KS2][PER], f3[KS2][PER3];
+    float bv1[PER], bv2[PER], bv3[PER3];
+    const int ccol = lane & 15, crow = 4 * (lane >> 4);
+    auto biases = [&](const float *__restrict__ bsrc, int n_rows, int per, float *bv) {
+        for (int j = 0; j < per; ++j) {
+            const int n = (per * wave + j) * 16 + ccol;
+            bv[j] = bsrc[n < n_rows ? n : 0];
+        }
+    };
+    if constexpr (WBJ) {
+        biases(b1, HID, PER, bv1);
+        biases(b2, HID, PER, bv2);
+        biases(b3, ND, PER3, bv3);
+        layer_weights<KS1, PER>(w1f, HID / 16, PER * wave, lane, f1);
+        layer_weights<KS2, PER>(w2f, HID / 16, PER * wave, lane, f2);
+    }
     // w_K = RMS(BJ(r)_K)
     {
         const int cl = tid / SUB, sub = tid % SUB;
@@ -632,36 +677,48 @@ k_mlp_fused(int64_t n_cells, const double *__restrict__ w, double *__restrict__ 
         for (int o = SUB / 2; o > 0; o >>= 1) sz += __shfl_xor(sz, o, 64);
         if (sub == 0) sW[cl] = sqrt(sz / ND);
     }
-    const int ccol = lane & 15, crow = 4 * (lane >> 4);
     // layer 1: each wave PER of the 16 column tiles (sX is complete: a
     // barrier follows the block-Jacobi step)
     {
         f32x4 acc[PER];
-        fused_layer<LDX, PER, LDX + 8, LDX>(sX, w1b, HID, PER * wave, lane, acc);
+        if constexpr (!WBJ) {
+            biases(b1, HID, PER, bv1);
+            layer_weights<KS1, PER>(w1f, HID / 16, PER * wave, lane, f1);
+        }
+        layer_mfma<LDX, PER, LDX + 8>(sX, f1, lane, acc);
+        if constexpr (WBJ) layer_weights<KS2, PER3>(w3f, NT3, PER3 * wave, lane, f3);
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
             const int n = (PER * wave + j) * 16 + ccol;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) sH[crow + q][n] = f2bf(fmaxf(acc[j][q] + b1[n], 0.f));
+            for (int q = 0; q < 4; ++q) sH[crow + q][n] = f2bf(fmaxf(acc[j][q] + bv1[j], 0.f));
         }
     }
     __syncthreads();
     // layer 2
     {
         f32x4 acc[PER];
-        fused_layer<HID, PER, HID + 8, HID>(sH, w2b, HID, PER * wave, lane, acc);
+        if constexpr (!WBJ) {
+            biases(b2, HID, PER, bv2);
+            layer_weights<KS2, PER>(w2f, HID / 16, PER * wave, lane, f2);
+        }
+        layer_mfma<HID, PER, HID + 8>(sH, f2, lane, acc);
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
             const int n = (PER * wave + j) * 16 + ccol;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) sH2[crow + q][n] = f2bf(fmaxf(acc[j][q] + b2[n], 0.f));
+            for (int q = 0; q < 4; ++q) sH2[crow + q][n] = f2bf(fmaxf(acc[j][q] + bv2[j], 0.f));
         }
     }
     __syncthreads();
     // layer 3 and z = BJ(r) + w_K o_K
     {
         f32x4 acc[PER3];
-        fused_layer<HID, PER3, HID + 8, HID>(sH2, w3b, ND, PER3 * wave, lane, acc);
+        if constexpr (!WBJ) {
+            biases(b3, ND, PER3, bv3);
+            layer_weights<KS2, PER3>(w3f, NT3, PER3 * wave, lane, f3);
+        }
+        layer_mfma<HID, PER3, HID + 8>(sH2, f3, lane, acc);
 #pragma unroll
         for (int j = 0; j < PER3; ++j) {
             const int n = (PER3 * wave + j) * 16 + ccol;
@@ -670,7 +727,7 @@ k_mlp_fused(int64_t n_cells, const double *__restrict__ w, double *__restrict__ 
             for (int q = 0; q < 4; ++q) {
                 const int64_t c = c0 + crow + q;
                 if (c < n_cells)
-                    z[c * ND + n] = sR[crow + q][n] + sW[crow + q] * (double)(acc[j][q] + b3[n]);
+                    z[c * ND + n] = sR[crow + q][n] + sW[crow + q] * (double)(acc[j][q] + bv3[j]);
             }
         }
     }
@@ -715,6 +772,7 @@ struct MlpState {
     int64_t off_w1 = 0, off_b1 = 0, off_w2 = 0, off_b2 = 0, off_w3 = 0, off_b3 = 0;
     float *w = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
     uint16_t *w1b = nullptr, *w2b = nullptr, *w3b = nullptr;
+    uint16_t *wfr = nullptr;   // the three layers in the fused kernel's fragment order
     int64_t t = 0;
     int64_t cap = 0;
     int64_t trace_B = 0;     // batch of the last training step whose buffers are intact
@@ -799,6 +857,8 @@ hx_status mlp_create(hx_ctx *c)
     A(s->w1b, 2 * (size_t)HID * s->ldx);
     A(s->w2b, 2 * (size_t)HID * HID);
     A(s->w3b, 2 * (size_t)s->n_out * HID);
+    A(s->wfr, 2 * (size_t)512 * ((HID / 16) * (s->ldx / 32) + (HID / 16) * (HID / 32) +
+                                 ((s->n_out + 15) / 16) * (HID / 32)));
     A(s->part, 8 * 1024);
     A(s->loss, 16);
 #undef A
@@ -819,7 +879,7 @@ void mlp_destroy(hx_ctx *c)
     if (!s) return;
     free_batch(s);
     void **b[] = {(void **)&s->w, (void **)&s->m, (void **)&s->v, (void **)&s->grad,
-                  (void **)&s->w1b, (void **)&s->w2b, (void **)&s->w3b, (void **)&s->part,
+                  (void **)&s->w1b, (void **)&s->w2b, (void **)&s->w3b, (void **)&s->wfr, (void **)&s->part,
                   (void **)&s->loss, (void **)&s->zt};
     for (void **p : b) dfree(p);
     if (s->loss_host) (void)hipHostFree(s->loss_host);
@@ -836,6 +896,14 @@ static hipError_t refresh_bf16(hx_ctx *c)
                        s->P, s->w + s->off_w2, HID, HID, HID, s->w2b);
     hipLaunchKernelGGL(k_weights_to_bf16, dim3(nb256((int64_t)s->n_out * HID)), dim3(256), 0,
                        c->stream, s->P, s->w + s->off_w3, s->n_out, HID, HID, s->w3b);
+    const int ks1 = s->ldx / 32, ks = HID / 32;
+    uint16_t *f2 = s->wfr + (int64_t)512 * (HID / 16) * ks1, *f3 = f2 + (int64_t)512 * (HID / 16) * ks;
+    hipLaunchKernelGGL(k_weights_frag, dim3(nb256((int64_t)512 * (HID / 16) * ks1)), dim3(256), 0,
+                       c->stream, s->w + s->off_w1, HID, s->n_in, ks1, s->wfr);
+    hipLaunchKernelGGL(k_weights_frag, dim3(nb256((int64_t)512 * (HID / 16) * ks)), dim3(256), 0,
+                       c->stream, s->w + s->off_w2, HID, HID, ks, f2);
+    hipLaunchKernelGGL(k_weights_frag, dim3(nb256((int64_t)512 * ((s->n_out + 15) / 16) * ks)),
+                       dim3(256), 0, c->stream, s->w + s->off_w3, s->n_out, HID, ks, f3);
     return hipGetLastError();
 }
 
@@ -1113,8 +1181,8 @@ static hipError_t mlp_fused_n(hx_ctx *c, const double *w, const double *part, in
     if constexpr (N <= 6) {
         if (nwg <= s->n_cu) {
             hipLaunchKernelGGL((k_mlp_fused<N, true>), dim3((unsigned)nwg), dim3(64 * FW), 0,
-                               c->stream, c->n_cells, w, z, c->nbr, c->coef_feat, s->w1b, s->w2b,
-                               s->w3b, s->w + s->off_b1, s->w + s->off_b2, s->w + s->off_b3,
+                               c->stream, c->n_cells, w, z, c->nbr, c->coef_feat, s->wfr,
+                               s->w + s->off_b1, s->w + s->off_b2, s->w + s->off_b3,
                                c->bjS64, c->bjL64, c->bjC64, part, nbp, vout);
             return hipGetLastError();
         }
@@ -1123,7 +1191,7 @@ static hipError_t mlp_fused_n(hx_ctx *c, const double *w, const double *part, in
     if (e != hipSuccess) return e;
     const double *v = part ? vout : w;
     hipLaunchKernelGGL((k_mlp_fused<N, false>), dim3((unsigned)nwg), dim3(64 * FW), 0, c->stream,
-                       c->n_cells, v, z, c->nbr, c->coef_feat, s->w1b, s->w2b, s->w3b,
+                       c->n_cells, v, z, c->nbr, c->coef_feat, s->wfr,
                        s->w + s->off_b1, s->w + s->off_b2, s->w + s->off_b3, (const double *)nullptr,
                        (const double *)nullptr, (const double *)nullptr, (const double *)nullptr, 0,
                        (double *)nullptr);
